@@ -1,0 +1,255 @@
+"""FP64 CPU oracle for the Gaussian-surface partition/estimation method
+(Liu, Chen & Lu, arXiv:1611.03474).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP implementation in ``paper_1611_03474_amd`` and never imports it.
+
+The numerical work lives in ``tms_oracle.c`` (plain C, double precision,
+OpenMP over independent cubes/points); this module compiles it with gcc when
+needed and wraps it with ctypes.  Each wrapper cites the passage of the paper
+that the C function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tms_oracle.c")
+_LIB = os.path.join(_HERE, "libtms_oracle.so")
+
+OR_MAXLEV = 8
+REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN = 0, 1, 2
+CLS_OUTSIDE, CLS_SURFACE, CLS_INSIDE = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile ``tms_oracle.c`` into ``libtms_oracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+             "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("D", C.c_double), ("c", C.c_double), ("tau", C.c_double),
+                ("h0", C.c_double), ("h_min", C.c_double), ("pad", C.c_double),
+                ("eps_cut", C.c_double), ("uniform", C.c_int32),
+                ("nthreads", C.c_int32), ("conf", C.c_int32), ("gl_nodes", C.c_int32)]
+
+
+_I64A = C.c_int64 * OR_MAXLEV
+
+
+class _Result(C.Structure):
+    _fields_ = [("n_leaves", C.c_int64), ("ijk", C.POINTER(C.c_int32)),
+                ("level", C.POINTER(C.c_uint8)), ("reason", C.POINTER(C.c_uint8)),
+                ("mask", C.POINTER(C.c_uint8)), ("cls", C.POINTER(C.c_uint8)),
+                ("corner_phi", C.POINTER(C.c_double)), ("n_vert", C.c_int64),
+                ("vkey", C.POINTER(C.c_uint64)), ("vt", C.POINTER(C.c_double)),
+                ("vxyz", C.POINTER(C.c_double)), ("origin", C.c_double * 3),
+                ("dims", C.c_int64 * 3), ("K", C.c_int32), ("status", C.c_int32),
+                ("rc2", C.c_double), ("n_est", _I64A), ("n_disc", _I64A),
+                ("n_refine", _I64A), ("n_conv", _I64A), ("n_hmin", _I64A),
+                ("n_pairs", C.c_int64), ("n_corners", C.c_int64),
+                ("tie_cube", C.c_int64), ("tie_corner", C.c_int64)]
+
+
+_lib = None
+_DP = C.POINTER(C.c_double)
+_FUN1 = C.CFUNCTYPE(C.c_double, C.c_double, C.c_void_p)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        L.or_gauss_legendre.argtypes = [C.c_int, _DP, _DP]
+        L.or_project_fn.argtypes = [_FUN1, C.c_void_p, C.c_int, _DP]
+        L.or_project.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _DP]
+        L.or_cutoff2.argtypes = [_DP, C.c_int64, C.c_double, C.c_double]
+        L.or_cutoff2.restype = C.c_double
+        L.or_phi.argtypes = [_DP, C.c_int64, C.c_double, C.c_double, _DP, C.c_int64, _DP, _DP,
+                             C.c_int]
+        L.or_cube_tensor.argtypes = [_DP, C.c_int64, C.c_double, C.c_double, C.c_int, _DP, _DP,
+                                     _DP, C.POINTER(C.c_int64)]
+        L.or_tensor_eval.argtypes = [_DP, C.c_double, C.c_double, C.c_double]
+        L.or_tensor_eval.restype = C.c_double
+        L.or_higher_mass.argtypes = [_DP]
+        L.or_higher_mass.restype = C.c_double
+        L.or_svd.argtypes = [C.c_int, C.c_int, _DP, _DP, _DP, _DP]
+        L.or_cubic_range.argtypes = [_DP, _DP, _DP]
+        L.or_bound.argtypes = [_DP, _DP]
+        L.or_partition.argtypes = [_DP, C.c_int64, C.POINTER(Params)]
+        L.or_partition.restype = C.POINTER(_Result)
+        L.or_free.argtypes = [C.POINTER(_Result)]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _atoms(xyzr) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(xyzr, dtype=np.float64).reshape(-1, 4))
+    return a
+
+
+# --------------------------------------------------------------------------
+# Single-function wrappers (used by the pinning tests)
+# --------------------------------------------------------------------------
+
+def gauss_legendre(n: int):
+    t = np.zeros(n)
+    w = np.zeros(n)
+    lib().or_gauss_legendre(n, _dp(t), _dp(w))
+    return t, w
+
+
+def project(D, lo, hi, xi, nodes=0):
+    """Degree-3 Legendre projection with C0 endpoint correction of the factor
+    exp(-D (x - xi)^2) on [lo, hi] (Section 2.2.1, eqs. poly2_1, poly3,
+    condition1, alpha)."""
+    a = np.zeros(4)
+    lib().or_project(float(D), float(lo), float(hi), float(xi), int(nodes), _dp(a))
+    return a
+
+
+def project_fn(f, nodes=0):
+    """The same projection applied to an arbitrary function f on [-1, 1]."""
+    cb = _FUN1(lambda t, _ctx: float(f(t)))
+    a = np.zeros(4)
+    lib().or_project_fn(cb, None, int(nodes), _dp(a))
+    return a
+
+
+def cutoff2(xyzr, D, eps_cut=1e-10):
+    a = _atoms(xyzr)
+    return lib().or_cutoff2(_dp(a), a.shape[0], float(D), float(eps_cut))
+
+
+def phi(xyzr, D, pts, eps_cut=1e-10, grad=False, nthreads=0):
+    """phi and its gradient at points (Section 1, eq. Gaussian1), truncated to
+    the atoms within R_c of each point."""
+    a = _atoms(xyzr)
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    out = np.zeros(p.shape[0])
+    g = np.zeros((p.shape[0], 3)) if grad else None
+    lib().or_phi(_dp(a), a.shape[0], float(D), float(eps_cut), _dp(p), p.shape[0], _dp(out),
+                 _dp(g) if grad else None, int(nthreads))
+    return (out, g) if grad else out
+
+
+def cube_tensor(xyzr, D, lo, hi, eps_cut=1e-10, nodes=0):
+    """Coefficient tensor A[j,k,l] of a cube (eqs. polynew, tensor1, tensor2)."""
+    a = _atoms(xyzr)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    A = np.zeros(64)
+    nn = C.c_int64(0)
+    lib().or_cube_tensor(_dp(a), a.shape[0], float(D), float(eps_cut), int(nodes), _dp(lo),
+                         _dp(hi), _dp(A), C.byref(nn))
+    return A.reshape(4, 4, 4), nn.value
+
+
+def tensor_eval(A, x, y, z):
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(64)
+    return lib().or_tensor_eval(_dp(A), float(x), float(y), float(z))
+
+
+def higher_mass(A):
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(64)
+    return lib().or_higher_mass(_dp(A))
+
+
+def svd(M):
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    m, n = M.shape
+    s = np.zeros(m)
+    U = np.zeros((m, m))
+    Vt = np.zeros((m, n))
+    lib().or_svd(m, n, _dp(M), _dp(s), _dp(U), _dp(Vt))
+    return U, s, Vt
+
+
+def cubic_range(q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    lo = C.c_double(0)
+    hi = C.c_double(0)
+    lib().or_cubic_range(_dp(q), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
+
+
+def bound(A):
+    """(L, U, rho, r, tie) of the nested-SVD bound (Section 2.2.2)."""
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(64)
+    out = np.zeros(5)
+    lib().or_bound(_dp(A), _dp(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Whole pass
+# --------------------------------------------------------------------------
+
+class Result:
+    """Leaves, corner values, classes and edge vertices of one pass."""
+
+    def __init__(self, r: _Result):
+        n = r.n_leaves
+        nv = r.n_vert
+        self.status = r.status
+        self.n_leaves = n
+        self.ijk = np.ctypeslib.as_array(r.ijk, (max(n, 1), 3))[:n].copy()
+        self.level = np.ctypeslib.as_array(r.level, (max(n, 1),))[:n].copy()
+        self.reason = np.ctypeslib.as_array(r.reason, (max(n, 1),))[:n].copy()
+        self.mask = np.ctypeslib.as_array(r.mask, (max(n, 1),))[:n].copy()
+        self.cls = np.ctypeslib.as_array(r.cls, (max(n, 1),))[:n].copy()
+        self.corner_phi = np.ctypeslib.as_array(r.corner_phi, (max(n, 1), 8))[:n].copy()
+        self.n_vert = nv
+        self.vkey = np.ctypeslib.as_array(r.vkey, (max(nv, 1),))[:nv].copy()
+        self.vt = np.ctypeslib.as_array(r.vt, (max(nv, 1),))[:nv].copy()
+        self.vxyz = np.ctypeslib.as_array(r.vxyz, (max(nv, 1), 3))[:nv].copy()
+        self.origin = np.array(r.origin[:])
+        self.dims = np.array(r.dims[:])
+        self.K = r.K
+        self.rc2 = r.rc2
+        self.n_est = np.array(r.n_est[:])
+        self.n_disc = np.array(r.n_disc[:])
+        self.n_refine = np.array(r.n_refine[:])
+        self.n_conv = np.array(r.n_conv[:])
+        self.n_hmin = np.array(r.n_hmin[:])
+        self.n_pairs = r.n_pairs
+        self.n_corners = r.n_corners
+        self.tie_cube = r.tie_cube
+        self.tie_corner = r.tie_corner
+
+    @property
+    def cubes_estimated(self) -> int:
+        return int(self.n_est.sum())
+
+
+def partition(xyzr, D, c=1.0, tau=1e-3, h0=2.0, h_min=0.25, pad=3.0, eps_cut=1e-10,
+              uniform=False, nthreads=0, conf=0, gl_nodes=0) -> Result:
+    """Adaptive partition and estimation (Section 2.2, Steps 1-3) followed by
+    leaf classification (eq. linear1) and edge intersections (eq. intersection)."""
+    a = _atoms(xyzr)
+    P = Params(D=float(D), c=float(c), tau=float(tau), h0=float(h0), h_min=float(h_min),
+               pad=float(pad), eps_cut=float(eps_cut), uniform=int(bool(uniform)),
+               nthreads=int(nthreads), conf=int(conf), gl_nodes=int(gl_nodes))
+    rp = lib().or_partition(_dp(a), a.shape[0], C.byref(P))
+    try:
+        res = Result(rp.contents)
+    finally:
+        lib().or_free(rp)
+    if res.status != 0:
+        raise ValueError("oracle rejected the input (status %d)" % res.status)
+    return res

@@ -1,0 +1,1073 @@
+/*
+ * tms_oracle.c -- plain FP64 CPU oracle for the Gaussian-surface adaptive
+ * partition-and-estimation method of Liu, Chen & Lu, "Efficient and Qualified
+ * Mesh Generation for Gaussian Molecular Surface Using Piecewise Trilinear
+ * Polynomial Approximation" (arXiv:1611.03474).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP implementation.
+ *
+ * Everything is computed in double precision, step by step, in the order the
+ * paper gives, with no blocking or fusion beyond what the definitions state.
+ * The only acceleration structure is a uniform bin grid used to enumerate a
+ * superset of the atoms that pass the neighbourhood predicate; the predicate
+ * itself decides membership.
+ *
+ * Readings of the paper that this file takes (the paper is silent or garbled
+ * there) are marked "Reading:" in the comments.
+ *
+ * Build: gcc -O2 -fopenmp -fPIC -shared -o libtms_oracle.so tms_oracle.c -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Parameters                                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double D;        /* decay rate of the Gaussian kernel (Section 1, eq. Gaussian1) */
+    double c;        /* isovalue (Section 1) */
+    double tau;      /* bound on the higher-order coefficients (Section 2.2, Step 3) */
+    double h0;       /* edge of the initial coarse grid cubes (Section 2.2) */
+    double h_min;    /* edge of the finest cubes allowed */
+    double pad;      /* padding of the initial grid around the atoms */
+    double eps_cut;  /* truncation level of a single Gaussian term */
+    int32_t uniform; /* 1: plain method, every cube of an h0 grid is a leaf */
+    int32_t nthreads;/* OpenMP threads (0: library default) */
+    int32_t conf;    /* conformation id written into edge keys */
+    int32_t gl_nodes;/* Gauss-Legendre nodes for the 1-D projections (0: 32) */
+} or_params;
+
+enum { OR_REASON_UNIFORM = 0, OR_REASON_CONVERGED = 1, OR_REASON_HMIN = 2 };
+enum { OR_CLS_OUTSIDE = 0, OR_CLS_SURFACE = 1, OR_CLS_INSIDE = 2 };
+
+#define OR_MAXLEV 8
+#define OR_TIE 1e-9
+
+/* ------------------------------------------------------------------------ */
+/* Legendre polynomials L0..L3 and Gauss-Legendre quadrature                  */
+/* ------------------------------------------------------------------------ */
+
+static void legendre4(double t, double L[4])
+{
+    L[0] = 1.0;
+    L[1] = t;
+    L[2] = 0.5 * (3.0 * t * t - 1.0);
+    L[3] = 0.5 * (5.0 * t * t * t - 3.0 * t);
+}
+
+/* n-point Gauss-Legendre nodes and weights on [-1,1]: the nodes are the roots
+ * of the degree-n Legendre polynomial, found by Newton's method from the
+ * asymptotic guess cos(pi (i - 1/4) / (n + 1/2)); the weight of a node t is
+ * 2 / ((1 - t^2) P_n'(t)^2).  P_n and P_n' come from Bonnet's recurrence. */
+void or_gauss_legendre(int n, double *t, double *w)
+{
+    for (int i = 0; i < n; ++i) {
+        double x = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            /* p1 = P_n(x), p0 = P_{n-1}(x) */
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-17)
+                break;
+        }
+        {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+        }
+        t[i] = x;
+        w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-dimensional degree-3 Legendre projection with C0 endpoint correction   */
+/* (Section 2.2.1: eqs. poly2_1..poly2_3, the alpha_j integrals, eqs. poly3,  */
+/* condition1, alpha).                                                        */
+/*                                                                            */
+/* Reading: the alpha_j integral is printed with normalisation 2/(b-a) and   */
+/* integrand "phi(local coordinate)"; it is taken as the standard Legendre    */
+/* projection of the one-dimensional factor f of the Gaussian, i.e.           */
+/*   alpha_j = (2j+1)/2 * int_{-1}^{1} f(t) L_j(t) dt,                        */
+/* the only reading for which the paper's least-squares remark holds.         */
+/* ------------------------------------------------------------------------ */
+
+typedef double (*or_fun1)(double t, void *ctx);
+
+/* Generic projection of a function f on [-1,1] given its values at the ends;
+ * exposed so that the tests can feed polynomials through it. */
+static double gl_t[65][64], gl_w[65][64];
+static volatile int gl_ready[65];
+
+static void gl_nodes(int n, const double **t, const double **w)
+{
+    if (!gl_ready[n]) {
+#ifdef _OPENMP
+#pragma omp critical(or_gl_init)
+#endif
+        {
+            if (!gl_ready[n]) {
+                or_gauss_legendre(n, gl_t[n], gl_w[n]);
+                gl_ready[n] = 1;
+            }
+        }
+    }
+    *t = gl_t[n];
+    *w = gl_w[n];
+}
+
+void or_project_fn(or_fun1 f, void *ctx, int nodes, double alpha[4])
+{
+    const double *t, *w;
+    if (nodes <= 0 || nodes > 64)
+        nodes = 32;
+    gl_nodes(nodes, &t, &w);
+    double a[4] = {0, 0, 0, 0};
+    for (int q = 0; q < nodes; ++q) {
+        double L[4];
+        legendre4(t[q], L);
+        double fq = f(t[q], ctx);
+        for (int j = 0; j < 4; ++j)
+            a[j] += w[q] * fq * L[j];
+    }
+    for (int j = 0; j < 4; ++j)
+        a[j] *= (2.0 * j + 1.0) / 2.0;
+    /* eq. condition1: the corrected polynomial must equal f at both ends.
+     * P(1) = sum_j a_j, P(-1) = sum_j (-1)^j a_j; adding e0 L2 + e1 L3 with
+     * L2(+-1) = 1 and L3(+-1) = +-1 gives e0 + e1 = f(1) - P(1) and
+     * e0 - e1 = f(-1) - P(-1). */
+    double fp = f(1.0, ctx), fm = f(-1.0, ctx);
+    double ep = fp - (a[0] + a[1] + a[2] + a[3]);
+    double em = fm - (a[0] - a[1] + a[2] - a[3]);
+    double e0 = 0.5 * (ep + em), e1 = 0.5 * (ep - em);
+    alpha[0] = a[0];
+    alpha[1] = a[1];
+    alpha[2] = a[2] + e0; /* eq. alpha, j = n-1 */
+    alpha[3] = a[3] + e1; /* eq. alpha, j = n */
+}
+
+typedef struct {
+    double D, s, delta;
+} gauss1_ctx;
+
+/* the one-dimensional factor exp(-D (x - x_i)^2) with x = m + s t and
+ * delta = m - x_i (eq. Gaussian2, written with D carried explicitly). */
+static double gauss1(double t, void *vctx)
+{
+    const gauss1_ctx *g = (const gauss1_ctx *)vctx;
+    double u = g->s * t + g->delta;
+    return exp(-g->D * u * u);
+}
+
+/* Projection of the factor of atom coordinate xi on the interval [lo,hi]. */
+void or_project(double D, double lo, double hi, double xi, int nodes, double alpha[4])
+{
+    gauss1_ctx g;
+    g.D = D;
+    g.s = 0.5 * (hi - lo);
+    g.delta = 0.5 * (lo + hi) - xi;
+    or_project_fn(gauss1, &g, nodes, alpha);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Atom bins: a superset enumerator for the neighbourhood predicates.         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;
+    const double *xyzr; /* [n][4] */
+    double lo[3];       /* bin grid origin */
+    double bs;          /* bin size */
+    int64_t nb[3];
+    int64_t *start;     /* [nbins+1] */
+    int64_t *idx;       /* atom indices, bin-major, ascending inside a bin */
+} or_bins;
+
+static int64_t clampi(int64_t v, int64_t lo, int64_t hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+static void bins_build(or_bins *b, const double *xyzr, int64_t n, double bs)
+{
+    b->n = n;
+    b->xyzr = xyzr;
+    b->bs = bs;
+    double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        mn[a] = n ? xyzr[a] : 0.0;
+        mx[a] = mn[a];
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double v = xyzr[4 * i + a];
+            if (v < mn[a]) mn[a] = v;
+            if (v > mx[a]) mx[a] = v;
+        }
+    int64_t tot = 1;
+    for (int a = 0; a < 3; ++a) {
+        b->lo[a] = mn[a];
+        b->nb[a] = (int64_t)floor((mx[a] - mn[a]) / bs) + 1;
+        tot *= b->nb[a];
+    }
+    b->start = (int64_t *)calloc((size_t)tot + 1, sizeof(int64_t));
+    b->idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a)
+            c[a] = clampi((int64_t)floor((xyzr[4 * i + a] - b->lo[a]) / bs), 0, b->nb[a] - 1);
+        key[i] = (c[2] * b->nb[1] + c[1]) * b->nb[0] + c[0];
+        b->start[key[i] + 1]++;
+    }
+    for (int64_t k = 0; k < tot; ++k)
+        b->start[k + 1] += b->start[k];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)tot);
+    memcpy(fill, b->start, sizeof(int64_t) * (size_t)tot);
+    for (int64_t i = 0; i < n; ++i)
+        b->idx[fill[key[i]]++] = i;
+    free(fill);
+    free(key);
+}
+
+static void bins_free(or_bins *b)
+{
+    free(b->start);
+    free(b->idx);
+}
+
+/* Visit every atom whose bin overlaps the box [lo-R, hi+R]. */
+#define BINS_FOREACH(b, blo, bhi, R, i_var, ...)                                          \
+    do {                                                                                  \
+        int64_t c0_[3], c1_[3];                                                           \
+        for (int a_ = 0; a_ < 3; ++a_) {                                                  \
+            c0_[a_] = clampi((int64_t)floor(((blo)[a_] - (R) - (b)->lo[a_]) / (b)->bs), 0, \
+                             (b)->nb[a_] - 1);                                            \
+            c1_[a_] = clampi((int64_t)floor(((bhi)[a_] + (R) - (b)->lo[a_]) / (b)->bs), 0, \
+                             (b)->nb[a_] - 1);                                            \
+        }                                                                                 \
+        for (int64_t z_ = c0_[2]; z_ <= c1_[2]; ++z_)                                     \
+            for (int64_t y_ = c0_[1]; y_ <= c1_[1]; ++y_)                                 \
+                for (int64_t x_ = c0_[0]; x_ <= c1_[0]; ++x_) {                           \
+                    int64_t k_ = (z_ * (b)->nb[1] + y_) * (b)->nb[0] + x_;                \
+                    for (int64_t p_ = (b)->start[k_]; p_ < (b)->start[k_ + 1]; ++p_) {    \
+                        int64_t i_var = (b)->idx[p_];                                     \
+                        __VA_ARGS__                                                       \
+                    }                                                                     \
+                }                                                                         \
+    } while (0)
+
+/* Reading: the paper only says that the sum is taken over the atoms near the
+ * cube (Section 2.2.1, after eq. polynew).  Here an atom belongs to the
+ * neighbourhood of a closed box iff its squared distance to the box is at
+ * most R_c^2 = r_max^2 + ln(1/eps_cut)/D, so every dropped term of phi is
+ * below eps_cut.  A point is a box with lo = hi. */
+static double box_dist2(const double *x, const double lo[3], const double hi[3])
+{
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = 0.0;
+        if (x[a] < lo[a]) d = lo[a] - x[a];
+        else if (x[a] > hi[a]) d = x[a] - hi[a];
+        d2 += d * d;
+    }
+    return d2;
+}
+
+double or_cutoff2(const double *xyzr, int64_t n, double D, double eps_cut)
+{
+    double rmax = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (xyzr[4 * i + 3] > rmax) rmax = xyzr[4 * i + 3];
+    return rmax * rmax + log(1.0 / eps_cut) / D;
+}
+
+/* ------------------------------------------------------------------------ */
+/* phi and its gradient (Section 1, eq. Gaussian1)                            */
+/*   phi(p)  = sum_i exp(-D(|p-x_i|^2 - r_i^2))                               */
+/*   grad(p) = sum_i -2D (p - x_i) exp(-D(|p-x_i|^2 - r_i^2))                 */
+/* over the atoms with |p - x_i|^2 <= R_c^2.                                  */
+/* ------------------------------------------------------------------------ */
+
+static void phi_point(const or_bins *b, double D, double rc2, const double *p, double *phi,
+                      double *grad)
+{
+    const double *xyzr = b->xyzr;
+    double R = sqrt(rc2);
+    double s = 0.0, g[3] = {0, 0, 0};
+    BINS_FOREACH(b, p, p, R, i, {
+        const double *x = xyzr + 4 * i;
+        double d[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
+        double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (d2 <= rc2) {
+            double term = exp(-D * (d2 - x[3] * x[3]));
+            s += term;
+            for (int a = 0; a < 3; ++a)
+                g[a] += -2.0 * D * d[a] * term;
+        }
+    });
+    *phi = s;
+    if (grad)
+        for (int a = 0; a < 3; ++a)
+            grad[a] = g[a];
+}
+
+void or_phi(const double *xyzr, int64_t n, double D, double eps_cut, const double *pts,
+            int64_t m, double *phi, double *grad, int nthreads)
+{
+    double rc2 = or_cutoff2(xyzr, n, D, eps_cut);
+    or_bins b;
+    bins_build(&b, xyzr, n, sqrt(rc2));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t k = 0; k < m; ++k)
+        phi_point(&b, D, rc2, pts + 3 * k, phi + k, grad ? grad + 3 * k : NULL);
+    bins_free(&b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coefficient tensor of one cube (eqs. polynew, tensor1, tensor2)            */
+/*   A[j][k][l] = sum_{i in N(Q)} exp(D r_i^2) a~x_j a~y_k a~z_l               */
+/* j: x-degree, k: y-degree, l: z-degree; flat index 16 j + 4 k + l.          */
+/* ------------------------------------------------------------------------ */
+
+static int64_t cube_tensor(const or_bins *b, double D, double rc2, int nodes,
+                           const double lo[3], const double hi[3], double A[64])
+{
+    const double *xyzr = b->xyzr;
+    double R = sqrt(rc2);
+    int64_t cnt = 0;
+    for (int e = 0; e < 64; ++e)
+        A[e] = 0.0;
+    BINS_FOREACH(b, lo, hi, R, i, {
+        const double *x = xyzr + 4 * i;
+        if (box_dist2(x, lo, hi) <= rc2) {
+            double ax[4], ay[4], az[4];
+            or_project(D, lo[0], hi[0], x[0], nodes, ax);
+            or_project(D, lo[1], hi[1], x[1], nodes, ay);
+            or_project(D, lo[2], hi[2], x[2], nodes, az);
+            double w = exp(D * x[3] * x[3]);
+            for (int j = 0; j < 4; ++j)
+                for (int k = 0; k < 4; ++k)
+                    for (int l = 0; l < 4; ++l)
+                        A[16 * j + 4 * k + l] += w * ax[j] * ay[k] * az[l];
+            ++cnt;
+        }
+    });
+    return cnt;
+}
+
+void or_cube_tensor(const double *xyzr, int64_t n, double D, double eps_cut, int nodes,
+                    const double lo[3], const double hi[3], double A[64], int64_t *n_nb)
+{
+    double rc2 = or_cutoff2(xyzr, n, D, eps_cut);
+    or_bins b;
+    bins_build(&b, xyzr, n, sqrt(rc2));
+    int64_t c = cube_tensor(&b, D, rc2, nodes, lo, hi, A);
+    if (n_nb) *n_nb = c;
+    bins_free(&b);
+}
+
+/* Value of the tensor polynomial at local coordinates (eq. tensor1). */
+double or_tensor_eval(const double A[64], double x, double y, double z)
+{
+    double Lx[4], Ly[4], Lz[4], s = 0.0;
+    legendre4(x, Lx);
+    legendre4(y, Ly);
+    legendre4(z, Lz);
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l)
+                s += A[16 * j + 4 * k + l] * Lx[j] * Ly[k] * Lz[l];
+    return s;
+}
+
+/* Reading of Step 3's stopping rule ("coefficients of higher order terms
+ * (higher than the linear order) ... under some user-specified bound"): the
+ * absolute l1 mass of the 56 entries with max(j,k,l) >= 2. */
+double or_higher_mass(const double A[64])
+{
+    double e = 0.0;
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l)
+                if (j >= 2 || k >= 2 || l >= 2)
+                    e += fabs(A[16 * j + 4 * k + l]);
+    return e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Singular value decomposition of a small m x n matrix (m <= n <= 16) by     */
+/* one-sided (Hestenes) Jacobi rotations on the columns of M^T.               */
+/*   M = U diag(s) Vt, s descending; U is m x m, Vt is m x n (row-major).     */
+/* ------------------------------------------------------------------------ */
+
+void or_svd(int m, int n, const double *M, double *s, double *U, double *Vt)
+{
+    double B[16][16]; /* B = M^T, n x m: column q of B is row q of M */
+    double W[16][16]; /* accumulated rotations, m x m */
+    for (int i = 0; i < n; ++i)
+        for (int q = 0; q < m; ++q)
+            B[i][q] = M[q * n + i];
+    for (int p = 0; p < m; ++p)
+        for (int q = 0; q < m; ++q)
+            W[p][q] = (p == q) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        int rotated = 0;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    al += B[i][p] * B[i][p];
+                    be += B[i][q] * B[i][q];
+                    ga += B[i][p] * B[i][q];
+                }
+                if (ga == 0.0 || fabs(ga) <= 1e-16 * sqrt(al * be))
+                    continue;
+                rotated = 1;
+                double zeta = (be - al) / (2.0 * ga);
+                double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < n; ++i) {
+                    double bp = B[i][p], bq = B[i][q];
+                    B[i][p] = cs * bp - sn * bq;
+                    B[i][q] = sn * bp + cs * bq;
+                }
+                for (int i = 0; i < m; ++i) {
+                    double wp = W[i][p], wq = W[i][q];
+                    W[i][p] = cs * wp - sn * wq;
+                    W[i][q] = sn * wp + cs * wq;
+                }
+            }
+        if (!rotated)
+            break;
+    }
+    /* M^T W = B has orthogonal columns; with sigma_q = |B_q| and
+     * v_q = B_q / sigma_q this gives M = W diag(sigma) V^T. */
+    double sig[16];
+    int ord[16];
+    for (int q = 0; q < m; ++q) {
+        double nn = 0.0;
+        for (int i = 0; i < n; ++i)
+            nn += B[i][q] * B[i][q];
+        sig[q] = sqrt(nn);
+        ord[q] = q;
+    }
+    for (int a = 0; a < m; ++a) /* selection sort, descending */
+        for (int b2 = a + 1; b2 < m; ++b2)
+            if (sig[ord[b2]] > sig[ord[a]]) {
+                int t = ord[a];
+                ord[a] = ord[b2];
+                ord[b2] = t;
+            }
+    for (int a = 0; a < m; ++a) {
+        int q = ord[a];
+        s[a] = sig[q];
+        for (int i = 0; i < m; ++i)
+            U[i * m + a] = W[i][q];
+        for (int i = 0; i < n; ++i)
+            Vt[a * n + i] = sig[q] > 0.0 ? B[i][q] / sig[q] : 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Range of a one-dimensional degree-3 Legendre series on [-1,1].             */
+/* Reading: the paper asks for the lower and upper bounds of the cubics       */
+/* (Section 2.2.2) without saying how; the exact extremes are taken, over     */
+/* the end points and the real critical points inside the interval.           */
+/* ------------------------------------------------------------------------ */
+
+static double series_eval(const double q[4], double t)
+{
+    double L[4];
+    legendre4(t, L);
+    return q[0] * L[0] + q[1] * L[1] + q[2] * L[2] + q[3] * L[3];
+}
+
+void or_cubic_range(const double q[4], double *lo, double *hi)
+{
+    /* derivative of q0 + q1 t + q2 (3t^2-1)/2 + q3 (5t^3-3t)/2:
+     * (15/2 q3) t^2 + 3 q2 t + (q1 - 3/2 q3) */
+    double a = 7.5 * q[3], b = 3.0 * q[2], c = q[1] - 1.5 * q[3];
+    double cand[4];
+    int nc = 0;
+    cand[nc++] = -1.0;
+    cand[nc++] = 1.0;
+    if (a == 0.0) {
+        if (b != 0.0) cand[nc++] = -c / b;
+    } else {
+        double disc = b * b - 4.0 * a * c;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double qq = -0.5 * (b + (b >= 0.0 ? sq : -sq));
+            if (qq != 0.0) {
+                cand[nc++] = qq / a;
+                cand[nc++] = c / qq;
+            } else {
+                cand[nc++] = 0.0; /* b = 0 and disc = 0: double root at 0 */
+            }
+        }
+    }
+    double mn = series_eval(q, -1.0), mx = mn;
+    for (int i = 0; i < nc; ++i) {
+        double t = cand[i];
+        if (!(t >= -1.0 && t <= 1.0))
+            continue;
+        double v = series_eval(q, t);
+        if (v < mn) mn = v;
+        if (v > mx) mx = v;
+    }
+    *lo = mn;
+    *hi = mx;
+}
+
+static void interval_mul(double a0, double a1, double b0, double b1, double *lo, double *hi)
+{
+    double p[4] = {a1 * b1, a1 * b0, a0 * b1, a0 * b0};
+    double mn = p[0], mx = p[0];
+    for (int i = 1; i < 4; ++i) {
+        if (p[i] < mn) mn = p[i];
+        if (p[i] > mx) mx = p[i];
+    }
+    *lo = mn;
+    *hi = mx;
+}
+
+/* Smallest r with sum_{i<=r} s_i >= 0.99 sum_{i<=4} s_i (eq. SVD3 and its
+ * inner counterpart); 0 when every s_i is zero.  *margin receives the
+ * relative distance of that decision from a tie. */
+static int rank99(const double s[4], double *margin)
+{
+    double tot = s[0] + s[1] + s[2] + s[3];
+    *margin = 1.0;
+    if (!(tot > 0.0))
+        return 0;
+    double target = 0.99 * tot, cum = 0.0;
+    int r = 4;
+    for (int i = 0; i < 4; ++i) {
+        double prev = cum;
+        cum += s[i];
+        if (cum >= target) {
+            r = i + 1;
+            double m1 = (cum - target) / tot;
+            double m0 = (i > 0) ? (target - prev) / tot : 1.0;
+            *margin = m1 < m0 ? m1 : m0;
+            break;
+        }
+    }
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lower and upper bound of the tensor polynomial on its cube                 */
+/* (Section 2.2.2: eqs. matrix1, SVD1..SVD7, poly5..poly7, Sxyz, bound1..3).  */
+/*                                                                            */
+/* Reading (unfolding): the rows of the 4 x 16 unfolding carry the x-degree   */
+/* j and the columns the pair (k,l) as 4k+l, so that u_i multiplies the       */
+/* x-Legendre vector as in eq. Sxyz; V_i[k][l] = v_i[4k+l].                   */
+/* Reading (residual): |T| <= sum |R_ijk| (the form eqs. bound2/3 use).       */
+/*                                                                            */
+/* out[0] = L, out[1] = U, out[2] = rho (residual l1 mass), out[3] = outer    */
+/* rank r, out[4] = smallest decision margin of the rank rules and singular   */
+/* value gaps that shape the main part (a near-tie indicator).                */
+/* ------------------------------------------------------------------------ */
+
+void or_bound(const double A[64], double out[5])
+{
+    double sig[4], U[16], Vt[64];
+    or_svd(4, 16, A, sig, U, Vt);
+    double tie = 1.0, mr;
+    int r = rank99(sig, &mr);
+    if (mr < tie) tie = mr;
+    for (int i = 0; i < r; ++i) {
+        double g = (sig[0] > 0.0) ? (sig[i] - (i + 1 < 4 ? sig[i + 1] : 0.0)) / sig[0] : 1.0;
+        if (i + 1 < 4 && g < tie) tie = g;
+    }
+
+    double At[64];
+    for (int e = 0; e < 64; ++e)
+        At[e] = 0.0;
+    double Msum = 0.0, msum = 0.0;
+    for (int i = 0; i < r; ++i) {
+        double Vi[16], d[4], Wi[16], Zt[16];
+        for (int e = 0; e < 16; ++e)
+            Vi[e] = Vt[i * 16 + e];
+        or_svd(4, 4, Vi, d, Wi, Zt);
+        double mi;
+        int ri = rank99(d, &mi);
+        if (mi < tie) tie = mi;
+        for (int k = 0; k < ri; ++k) {
+            double g = (d[0] > 0.0) ? (d[k] - (k + 1 < 4 ? d[k + 1] : 0.0)) / d[0] : 1.0;
+            if (k + 1 < 4 && g < tie) tie = g;
+        }
+        double u[4];
+        for (int j = 0; j < 4; ++j)
+            u[j] = U[j * 4 + i];
+        double Myz = 0.0, myz = 0.0;
+        for (int k = 0; k < ri; ++k) {
+            double w[4], z[4];
+            for (int a = 0; a < 4; ++a) {
+                w[a] = Wi[a * 4 + k];
+                z[a] = Zt[k * 4 + a];
+            }
+            /* main part: sigma_i u_i (x) d_k w_k (x) z_k  (eq. SVD7) */
+            for (int j = 0; j < 4; ++j)
+                for (int kk = 0; kk < 4; ++kk)
+                    for (int l = 0; l < 4; ++l)
+                        At[16 * j + 4 * kk + l] += sig[i] * u[j] * d[k] * w[kk] * z[l];
+            double wy0, wy1, zz0, zz1, p0, p1;
+            or_cubic_range(w, &wy0, &wy1);
+            or_cubic_range(z, &zz0, &zz1);
+            interval_mul(wy0, wy1, zz0, zz1, &p0, &p1); /* m_k^yz, M_k^yz */
+            Myz += d[k] * p1;
+            myz += d[k] * p0;
+        }
+        double ux0, ux1, q0, q1;
+        or_cubic_range(u, &ux0, &ux1);
+        interval_mul(ux0, ux1, myz, Myz, &q0, &q1); /* m_i, M_i */
+        Msum += sig[i] * q1;
+        msum += sig[i] * q0;
+    }
+    double rho = 0.0;
+    for (int e = 0; e < 64; ++e)
+        rho += fabs(A[e] - At[e]);
+    out[0] = msum - rho; /* eq. bound3 */
+    out[1] = Msum + rho; /* eq. bound2 */
+    out[2] = rho;
+    out[3] = (double)r;
+    out[4] = tie;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive partition and estimation (Section 2.2, Steps 1-3), leaf           */
+/* classification against the trilinear interpolant (eq. linear1) and the    */
+/* edge intersection points (eq. intersection).                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n_leaves;
+    int32_t *ijk;       /* [n_leaves][3] cube index at its level */
+    uint8_t *level;     /* [n_leaves] */
+    uint8_t *reason;    /* [n_leaves] OR_REASON_* */
+    uint8_t *mask;      /* [n_leaves] bit v = dx + 2 dy + 4 dz set iff phi >= c */
+    uint8_t *cls;       /* [n_leaves] OR_CLS_* */
+    double *corner_phi; /* [n_leaves][8] */
+    int64_t n_vert;
+    uint64_t *vkey;     /* [n_vert] */
+    double *vt;         /* [n_vert] */
+    double *vxyz;       /* [n_vert][3] */
+    double origin[3];
+    int64_t dims[3];
+    int32_t K;
+    int32_t status;     /* 0 ok, <0 invalid input */
+    double rc2;
+    int64_t n_est[OR_MAXLEV], n_disc[OR_MAXLEV], n_refine[OR_MAXLEV];
+    int64_t n_conv[OR_MAXLEV], n_hmin[OR_MAXLEV];
+    int64_t n_pairs;      /* cube-atom pairs inside the cut-off */
+    int64_t n_corners;    /* unique leaf corners */
+    int64_t tie_cube;     /* cube decisions with a margin below OR_TIE */
+    int64_t tie_corner;   /* corner signs with |phi-c|/c below OR_TIE */
+} or_result;
+
+static int is_pow2_ratio(double a, double b, int *k)
+{
+    double r = a / b;
+    for (int i = 0; i < OR_MAXLEV; ++i)
+        if (r == (double)(1 << i)) {
+            *k = i;
+            return 1;
+        }
+    return 0;
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int64_t find_u64(const uint64_t *v, int64_t n, uint64_t key)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (v[mid] == key) return mid;
+        if (v[mid] < key) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* lattice point key: finest-lattice coordinates, 16 bits each */
+static uint64_t point_key(int64_t X, int64_t Y, int64_t Z)
+{
+    return ((uint64_t)X << 32) | ((uint64_t)Y << 16) | (uint64_t)Z;
+}
+
+/* edge key: conf(11) | level(3) | axis(2) | X(16) | Y(16) | Z(16), X,Y,Z the
+ * finest-lattice coordinates of the edge's lower end */
+static uint64_t edge_key(int conf, int level, int axis, int64_t X, int64_t Y, int64_t Z)
+{
+    return ((uint64_t)conf << 53) | ((uint64_t)level << 50) | ((uint64_t)axis << 48) |
+           ((uint64_t)X << 32) | ((uint64_t)Y << 16) | (uint64_t)Z;
+}
+
+void or_free(or_result *r)
+{
+    if (!r) return;
+    free(r->ijk);
+    free(r->level);
+    free(r->reason);
+    free(r->mask);
+    free(r->cls);
+    free(r->corner_phi);
+    free(r->vkey);
+    free(r->vt);
+    free(r->vxyz);
+    free(r);
+}
+
+typedef struct {
+    int32_t i[3];
+} cube3;
+
+or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
+{
+    or_result *R = (or_result *)calloc(1, sizeof(or_result));
+    int K = 0;
+    if (!(P->D > 0) || !(P->c > 0) || !(P->h0 > 0) || !(P->h_min > 0) || !(P->eps_cut > 0) ||
+        !(P->eps_cut < 1) || !(P->pad >= 0) || n < 0 ||
+        (!P->uniform && (!(P->tau > 0) || !is_pow2_ratio(P->h0, P->h_min, &K)))) {
+        R->status = -1;
+        return R;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 4; ++a)
+            if (!isfinite(xyzr[4 * i + a]) || (a == 3 && !(xyzr[4 * i + 3] > 0))) {
+                R->status = -1;
+                return R;
+            }
+#ifdef _OPENMP
+    if (P->nthreads > 0) omp_set_num_threads(P->nthreads);
+#endif
+    if (P->uniform) K = 0;
+    R->K = K;
+    const double D = P->D, c = P->c, h0 = P->h0;
+    const int nodes = P->gl_nodes > 0 ? P->gl_nodes : 32;
+
+    /* Initial coarse grid (Section 2.2): reading -- the origin is snapped to
+     * a multiple of h0 below the padded atom box, and the grid covers the
+     * padded box. */
+    double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        mn[a] = n ? xyzr[a] : 0.0;
+        mx[a] = mn[a];
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double v = xyzr[4 * i + a];
+            if (v < mn[a]) mn[a] = v;
+            if (v > mx[a]) mx[a] = v;
+        }
+    for (int a = 0; a < 3; ++a) {
+        R->origin[a] = h0 * floor((mn[a] - P->pad) / h0);
+        R->dims[a] = (int64_t)ceil((mx[a] + P->pad - R->origin[a]) / h0);
+        if (R->dims[a] < 1) R->dims[a] = 1;
+        if ((R->dims[a] << K) > 65535) {
+            R->status = -2;
+            return R;
+        }
+    }
+    double rc2 = or_cutoff2(xyzr, n, D, P->eps_cut);
+    R->rc2 = rc2;
+    double Rc = sqrt(rc2);
+    or_bins bins;
+    bins_build(&bins, xyzr, n, Rc);
+
+    /* ---- leaves --------------------------------------------------------- */
+    int64_t cap = 1024, nl = 0;
+    cube3 *lijk = (cube3 *)malloc(sizeof(cube3) * cap);
+    uint8_t *llev = (uint8_t *)malloc(cap), *lrea = (uint8_t *)malloc(cap);
+#define PUSH_LEAF(I0, I1, I2, LEV, REA)                                   \
+    do {                                                                  \
+        if (nl == cap) {                                                  \
+            cap *= 2;                                                     \
+            lijk = (cube3 *)realloc(lijk, sizeof(cube3) * cap);           \
+            llev = (uint8_t *)realloc(llev, cap);                         \
+            lrea = (uint8_t *)realloc(lrea, cap);                         \
+        }                                                                 \
+        lijk[nl].i[0] = (I0); lijk[nl].i[1] = (I1); lijk[nl].i[2] = (I2); \
+        llev[nl] = (uint8_t)(LEV); lrea[nl] = (uint8_t)(REA);             \
+        ++nl;                                                             \
+    } while (0)
+
+    if (P->uniform) {
+        for (int64_t z = 0; z < R->dims[2]; ++z)
+            for (int64_t y = 0; y < R->dims[1]; ++y)
+                for (int64_t x = 0; x < R->dims[0]; ++x)
+                    PUSH_LEAF((int32_t)x, (int32_t)y, (int32_t)z, 0, OR_REASON_UNIFORM);
+    } else {
+        /* Q_0: the root cubes in raster order (x fastest) whose neighbourhood
+         * holds at least one atom; an empty neighbourhood gives A = 0 and
+         * the bound [0,0], which excludes c > 0, so such a root is dropped
+         * without being estimated. */
+        int64_t nroot = R->dims[0] * R->dims[1] * R->dims[2];
+        uint8_t *occ = (uint8_t *)calloc((size_t)nroot, 1);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+        for (int64_t k = 0; k < nroot; ++k) {
+            int64_t x = k % R->dims[0], y = (k / R->dims[0]) % R->dims[1],
+                    z = k / (R->dims[0] * R->dims[1]);
+            double lo[3] = {R->origin[0] + x * h0, R->origin[1] + y * h0, R->origin[2] + z * h0};
+            double hi[3] = {lo[0] + h0, lo[1] + h0, lo[2] + h0};
+            int hit = 0;
+            BINS_FOREACH(&bins, lo, hi, Rc, i, {
+                if (!hit && box_dist2(xyzr + 4 * i, lo, hi) <= rc2) hit = 1;
+            });
+            occ[k] = (uint8_t)hit;
+        }
+        int64_t nq = 0, qcap = 1024;
+        cube3 *Q = (cube3 *)malloc(sizeof(cube3) * qcap);
+        for (int64_t k = 0; k < nroot; ++k)
+            if (occ[k]) {
+                if (nq == qcap) {
+                    qcap *= 2;
+                    Q = (cube3 *)realloc(Q, sizeof(cube3) * qcap);
+                }
+                Q[nq].i[0] = (int32_t)(k % R->dims[0]);
+                Q[nq].i[1] = (int32_t)((k / R->dims[0]) % R->dims[1]);
+                Q[nq].i[2] = (int32_t)(k / (R->dims[0] * R->dims[1]));
+                ++nq;
+            }
+        free(occ);
+
+        for (int lev = 0; lev <= K; ++lev) {
+            double h = h0 / (double)(1 << lev);
+            R->n_est[lev] = nq;
+            /* decision per cube: 0 discard, 1 refine, 2 converged leaf, 3 h_min leaf */
+            uint8_t *dec = (uint8_t *)malloc((size_t)(nq ? nq : 1));
+            int64_t pairs = 0, ties = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pairs, ties)
+#endif
+            for (int64_t q = 0; q < nq; ++q) {
+                double lo[3], hi[3], A[64];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = R->origin[a] + Q[q].i[a] * h;
+                    hi[a] = lo[a] + h;
+                }
+                /* Step 1: the degree-3 tensor polynomial of the cube */
+                pairs += cube_tensor(&bins, D, rc2, nodes, lo, hi, A);
+                double E = or_higher_mass(A);
+                double tie = 1.0;
+                /* Step 3 for a child cube: higher-order mass under the
+                 * user bound -> trilinear leaf (2E bounds |P - g|). */
+                if (lev >= 1) {
+                    double m = fabs(2.0 * E - P->tau) / P->tau;
+                    if (m < tie) tie = m;
+                }
+                if (lev >= 1 && 2.0 * E <= P->tau) {
+                    dec[q] = 2;
+                } else {
+                    /* Step 2: keep the cube iff L <= c <= U */
+                    double b[5];
+                    or_bound(A, b);
+                    double scale = 0.0;
+                    for (int e = 0; e < 64; ++e)
+                        scale += fabs(A[e]);
+                    if (scale > 0.0) {
+                        double m = fmin(fabs(b[0] - c), fabs(b[1] - c)) / scale;
+                        if (m < tie) tie = m;
+                        if (b[4] < tie) tie = b[4];
+                    }
+                    if (c < b[0] || c > b[1]) dec[q] = 0;
+                    else if (lev == K) dec[q] = 3;
+                    else dec[q] = 1;
+                }
+                if (tie < OR_TIE) ++ties;
+            }
+            R->n_pairs += pairs;
+            R->tie_cube += ties;
+            /* ordered compaction: leaves in queue order, children of each
+             * refined cube in octant order (bit 0: x, bit 1: y, bit 2: z) */
+            int64_t nn = 0;
+            for (int64_t q = 0; q < nq; ++q) {
+                if (dec[q] == 0) R->n_disc[lev]++;
+                else if (dec[q] == 1) { R->n_refine[lev]++; nn += 8; }
+                else if (dec[q] == 2) { R->n_conv[lev]++; PUSH_LEAF(Q[q].i[0], Q[q].i[1], Q[q].i[2], lev, OR_REASON_CONVERGED); }
+                else { R->n_hmin[lev]++; PUSH_LEAF(Q[q].i[0], Q[q].i[1], Q[q].i[2], lev, OR_REASON_HMIN); }
+            }
+            cube3 *Qn = (cube3 *)malloc(sizeof(cube3) * (size_t)(nn ? nn : 1));
+            int64_t w = 0;
+            for (int64_t q = 0; q < nq; ++q)
+                if (dec[q] == 1)
+                    for (int o = 0; o < 8; ++o) {
+                        Qn[w].i[0] = 2 * Q[q].i[0] + (o & 1);
+                        Qn[w].i[1] = 2 * Q[q].i[1] + ((o >> 1) & 1);
+                        Qn[w].i[2] = 2 * Q[q].i[2] + ((o >> 2) & 1);
+                        ++w;
+                    }
+            free(dec);
+            free(Q);
+            Q = Qn;
+            nq = nn;
+        }
+        free(Q);
+    }
+
+    /* ---- corners: phi once per unique finest-lattice point --------------- */
+    R->n_leaves = nl;
+    R->ijk = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(nl ? nl : 1));
+    R->level = llev;
+    R->reason = lrea;
+    for (int64_t q = 0; q < nl; ++q)
+        for (int a = 0; a < 3; ++a)
+            R->ijk[3 * q + a] = lijk[q].i[a];
+    free(lijk);
+    R->mask = (uint8_t *)malloc((size_t)(nl ? nl : 1));
+    R->cls = (uint8_t *)malloc((size_t)(nl ? nl : 1));
+    R->corner_phi = (double *)malloc(sizeof(double) * 8 * (size_t)(nl ? nl : 1));
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * 8 * (size_t)(nl ? nl : 1));
+    for (int64_t q = 0; q < nl; ++q) {
+        int sh = K - R->level[q];
+        for (int v = 0; v < 8; ++v) {
+            int64_t X = ((int64_t)R->ijk[3 * q + 0] + (v & 1)) << sh;
+            int64_t Y = ((int64_t)R->ijk[3 * q + 1] + ((v >> 1) & 1)) << sh;
+            int64_t Z = ((int64_t)R->ijk[3 * q + 2] + ((v >> 2) & 1)) << sh;
+            keys[8 * q + v] = point_key(X, Y, Z);
+        }
+    }
+    int64_t nk = 8 * nl;
+    uint64_t *uk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nk ? nk : 1));
+    memcpy(uk, keys, sizeof(uint64_t) * (size_t)nk);
+    qsort(uk, (size_t)nk, sizeof(uint64_t), cmp_u64);
+    int64_t nu = 0;
+    for (int64_t i = 0; i < nk; ++i)
+        if (i == 0 || uk[i] != uk[i - 1]) uk[nu++] = uk[i];
+    R->n_corners = nu;
+    double *uphi = (double *)malloc(sizeof(double) * (size_t)(nu ? nu : 1));
+    double hmin = P->uniform ? h0 : P->h_min;
+    int64_t cties = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : cties)
+#endif
+    for (int64_t i = 0; i < nu; ++i) {
+        double p[3] = {R->origin[0] + (double)(int64_t)((uk[i] >> 32) & 0xFFFF) * hmin,
+                       R->origin[1] + (double)(int64_t)((uk[i] >> 16) & 0xFFFF) * hmin,
+                       R->origin[2] + (double)(int64_t)(uk[i] & 0xFFFF) * hmin};
+        phi_point(&bins, D, rc2, p, uphi + i, NULL);
+        if (fabs(uphi[i] - c) / c < OR_TIE) ++cties;
+    }
+    R->tie_corner = cties;
+    /* classification against c through the sign pattern of the trilinear
+     * interpolant's corner values (eq. linear1): g is a convex combination
+     * of the corner values, so g = c meets the closed cube iff
+     * min <= c <= max over the corners. */
+    for (int64_t q = 0; q < nl; ++q) {
+        uint8_t m = 0;
+        for (int v = 0; v < 8; ++v) {
+            int64_t u = find_u64(uk, nu, keys[8 * q + v]);
+            double f = uphi[u];
+            R->corner_phi[8 * q + v] = f;
+            if (f >= c) m |= (uint8_t)(1u << v);
+        }
+        R->mask[q] = m;
+        R->cls[q] = (m == 0) ? OR_CLS_OUTSIDE : (m == 0xFF ? OR_CLS_INSIDE : OR_CLS_SURFACE);
+    }
+    free(uphi);
+    free(uk);
+    free(keys);
+
+    /* ---- edge intersections (eq. intersection) ----------------------------
+     * g restricted to a cube edge is linear in the edge coordinate, so the
+     * root of g = c on an edge whose end signs differ is
+     * t = (c - phi0) / (phi1 - phi0), measured from the lower end.  Edges are
+     * visited leaf by leaf (leaf order), edge by edge (axis-major; inside an
+     * axis the two other offsets with the lower axis first); an edge key that
+     * was already emitted is skipped. */
+    int64_t vcap = 1024, nv = 0;
+    R->vkey = (uint64_t *)malloc(sizeof(uint64_t) * vcap);
+    R->vt = (double *)malloc(sizeof(double) * vcap);
+    R->vxyz = (double *)malloc(sizeof(double) * 3 * vcap);
+    /* seen-set: open addressing on the edge key */
+    int64_t hcap = 1024;
+    while (hcap < 24 * (nl + 1)) hcap *= 2;
+    uint64_t *hset = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)hcap);
+    for (int64_t i = 0; i < hcap; ++i)
+        hset[i] = ~(uint64_t)0;
+    for (int64_t q = 0; q < nl; ++q) {
+        if (R->cls[q] != OR_CLS_SURFACE) continue;
+        int lev = R->level[q], sh = K - lev;
+        double h = h0 / (double)(1 << lev);
+        for (int axis = 0; axis < 3; ++axis)
+            for (int ab = 0; ab < 4; ++ab) {
+                int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+                int lowo = o1 < o2 ? o1 : o2, higho = o1 < o2 ? o2 : o1;
+                int off[3] = {0, 0, 0};
+                off[lowo] = ab & 1;
+                off[higho] = (ab >> 1) & 1;
+                int v0 = off[0] + 2 * off[1] + 4 * off[2];
+                int v1 = v0 + (1 << axis);
+                int b0 = (R->mask[q] >> v0) & 1, b1 = (R->mask[q] >> v1) & 1;
+                if (b0 == b1) continue;
+                int64_t X = ((int64_t)R->ijk[3 * q + 0] + off[0]) << sh;
+                int64_t Y = ((int64_t)R->ijk[3 * q + 1] + off[1]) << sh;
+                int64_t Z = ((int64_t)R->ijk[3 * q + 2] + off[2]) << sh;
+                uint64_t key = edge_key(P->conf, lev, axis, X, Y, Z);
+                uint64_t hsh = key * 0x9E3779B97F4A7C15ull;
+                int64_t slot = (int64_t)(hsh >> 17) & (hcap - 1);
+                int found = 0;
+                while (hset[slot] != ~(uint64_t)0) {
+                    if (hset[slot] == key) { found = 1; break; }
+                    slot = (slot + 1) & (hcap - 1);
+                }
+                if (found) continue;
+                hset[slot] = key;
+                double f0 = R->corner_phi[8 * q + v0], f1 = R->corner_phi[8 * q + v1];
+                double t = (c - f0) / (f1 - f0);
+                if (nv == vcap) {
+                    vcap *= 2;
+                    R->vkey = (uint64_t *)realloc(R->vkey, sizeof(uint64_t) * vcap);
+                    R->vt = (double *)realloc(R->vt, sizeof(double) * vcap);
+                    R->vxyz = (double *)realloc(R->vxyz, sizeof(double) * 3 * vcap);
+                }
+                R->vkey[nv] = key;
+                R->vt[nv] = t;
+                double p0[3] = {R->origin[0] + (double)X * hmin, R->origin[1] + (double)Y * hmin,
+                                R->origin[2] + (double)Z * hmin};
+                p0[axis] += t * h;
+                for (int a = 0; a < 3; ++a)
+                    R->vxyz[3 * nv + a] = p0[a];
+                ++nv;
+            }
+    }
+    free(hset);
+    R->n_vert = nv;
+    bins_free(&bins);
+    return R;
+#undef PUSH_LEAF
+}
