@@ -1,0 +1,237 @@
+/*
+ * tms.h -- C ABI of the MI355X (gfx950) implementation of the adaptive
+ * partition-and-estimation stage of the Gaussian molecular surface method of
+ * Liu, Chen & Lu, "Efficient and Qualified Mesh Generation for Gaussian
+ * Molecular Surface Using Piecewise Trilinear Polynomial Approximation"
+ * (arXiv:1611.03474).
+ *
+ * Problem statement (Section 1 and Section 2.1): atoms with centres x_i and
+ * radii r_i define phi(x) = sum_i exp(-D(|x - x_i|^2 - r_i^2)) (eq. Gaussian1);
+ * the surface is phi = c.  Stage one (Section 2.2) covers space with cubes of
+ * several sizes in which phi is replaced by a trilinear interpolant whose error
+ * is controlled by a user tolerance; its output is the list of cubes and the
+ * points where the trilinear surface crosses the cube edges (eq. intersection).
+ *
+ * Conventions for every entry point
+ *  - All functions return an int32 status: TMS_OK (0) or a negative TMS_E_*
+ *    code.  No C++ exception crosses this boundary.  After an error,
+ *    tms_last_error(ctx) returns a NUL-terminated message owned by ctx.
+ *  - Pointers documented as "device" address HIP device memory of the
+ *    context's device (for instance torch tensors on that device); pointers
+ *    documented as "host" address host memory.  The library never keeps a
+ *    pointer that the caller passes in.
+ *  - Work is enqueued on the stream given to tms_create.  Calls return after
+ *    their results are complete on that stream (each call synchronises the
+ *    stream at least once, because output sizes are data dependent).
+ *  - Coordinates are in the caller's length unit (angstrom in the paper).
+ *  - A context is not thread-safe: one host thread at a time per context.
+ */
+#ifndef TMS_H
+#define TMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define TMS_OK 0
+#define TMS_E_INVALID (-1)  /* an argument or the input data is invalid       */
+#define TMS_E_CAPACITY (-2) /* an output buffer is too small; see the call    */
+#define TMS_E_DEVICE (-3)   /* a HIP runtime error (no device, launch, ...)   */
+#define TMS_E_OOM (-4)      /* device memory allocation failed                */
+
+/* ---- precision of the per-pair arithmetic -------------------------------- */
+#define TMS_PREC_FP64 0       /* everything in double precision                 */
+#define TMS_PREC_FP32_GUARD 1 /* sums over atom pairs in single precision; any  */
+                              /* cube or point whose decision margin lies within */
+                              /* the single-precision error band is recomputed  */
+                              /* in double precision, so every discrete result  */
+                              /* equals the double-precision one               */
+
+/* ---- partition mode ---------------------------------------------------- */
+#define TMS_MODE_ADAPTIVE 0 /* Section 2.2 Steps 1-3: estimate, bound, divide   */
+#define TMS_MODE_UNIFORM 1  /* plain method: every cube of the h0 grid is a leaf */
+
+/* ---- leaf reasons and classes ------------------------------------------ */
+#define TMS_REASON_UNIFORM 0   /* uniform mode                                   */
+#define TMS_REASON_CONVERGED 1 /* higher-order mass 2E <= tau (Step 3)          */
+#define TMS_REASON_HMIN 2      /* kept by the bound at the finest level          */
+#define TMS_CLS_OUTSIDE 0      /* every corner value below c                     */
+#define TMS_CLS_SURFACE 1      /* corner values on both sides of c               */
+#define TMS_CLS_INSIDE 2       /* every corner value >= c                        */
+
+#define TMS_MAX_LEVELS 8
+
+typedef struct tms_ctx tms_ctx;
+typedef struct tms_cells tms_cells;
+
+/* Parameters of one surface (Section 1, Section 2.2).
+ *  D       decay rate of the Gaussian kernel (> 0)
+ *  c       isovalue (> 0)
+ *  tau     bound on the higher-order coefficients that turns a child cube
+ *          into a trilinear leaf: the cube is a leaf when 2E <= tau, E the
+ *          l1 mass of the tensor entries of degree above one in some
+ *          variable; 2E bounds |P - g| on the cube (> 0; adaptive mode)
+ *  h0      edge of the initial coarse grid cubes (> 0)
+ *  h_min   edge of the finest cubes; h0/h_min must be 2^K, 0 <= K < 8
+ *  pad     margin added around the atom bounding box (>= 0)
+ *  eps_cut every Gaussian term below eps_cut is dropped: the sums run over
+ *          atoms within R_c, R_c^2 = max r_i^2 + ln(1/eps_cut)/D (0 < eps_cut < 1)
+ *  precision TMS_PREC_*;  mode TMS_MODE_*                                    */
+typedef struct {
+    double D, c, tau, h0, h_min, pad, eps_cut;
+    int32_t precision;
+    int32_t mode;
+} tms_params;
+
+/* One leaf cube: the closed box origin + [i, i+1] * h0 / 2^level per axis.
+ * mask bit v (v = dx + 2 dy + 4 dz, d* in {0,1} the corner offsets) is set
+ * iff phi at that corner is >= c.  20 bytes, 4-byte aligned. */
+typedef struct {
+    int32_t ix, iy, iz;
+    int32_t conf; /* conformation index (0 for a single structure) */
+    uint8_t level, reason, mask, cls;
+} tms_leaf;
+
+/* One edge intersection point (eq. intersection).  edge_key packs
+ * conf(11 bits) | level(3) | axis(2) | X(16) | Y(16) | Z(16), where X, Y, Z
+ * are the finest-lattice coordinates (units of h_min) of the edge's lower
+ * end; t in [0,1] is the position along the edge from that end; x, y, z the
+ * point.  40 bytes. */
+typedef struct {
+    uint64_t edge_key;
+    double t, x, y, z;
+} tms_vertex;
+
+/* Counters of one partition pass (host struct, filled on request). */
+typedef struct {
+    int64_t n_est[TMS_MAX_LEVELS];    /* cubes whose tensor was computed */
+    int64_t n_disc[TMS_MAX_LEVELS];   /* cubes discarded by the bound    */
+    int64_t n_refine[TMS_MAX_LEVELS]; /* cubes divided into 8 children   */
+    int64_t n_conv[TMS_MAX_LEVELS];   /* converged leaves                */
+    int64_t n_hmin[TMS_MAX_LEVELS];   /* leaves kept at the finest level */
+    int64_t n_leaves, n_surface, n_corners;
+    int64_t n_bound;        /* cubes that needed the full nested-SVD bound     */
+    int64_t guard_cubes;    /* cubes recomputed in double precision            */
+    int64_t guard_points;   /* corner points recomputed in double precision    */
+    int64_t n_pairs;        /* cube-atom pairs inside R_c (algorithmic work)   */
+} tms_stats;
+
+/* Create a context on HIP device `device`, enqueueing work on `stream`
+ * (a hipStream_t; NULL means the device's null stream).  The stream is
+ * borrowed: it must outlive the context.  *out receives the context.
+ * Errors: TMS_E_INVALID (out NULL), TMS_E_DEVICE (no such device). */
+int32_t tms_create(tms_ctx **out, int32_t device, void *stream);
+
+/* Free a context and every buffer and cell structure it owns. */
+int32_t tms_destroy(tms_ctx *ctx);
+
+/* Message of the last failing call on ctx ("" if none); valid until the next
+ * call on ctx.  With ctx == NULL: message of the last tms_create failure. */
+const char *tms_last_error(const tms_ctx *ctx);
+
+/* Host-only validation of a parameter set (no device needed).  Returns
+ * TMS_OK or TMS_E_INVALID and writes a message into msg[0..msg_len). */
+int32_t tms_check_params(const tms_params *p, char *msg, int64_t msg_len);
+
+/* Host-only validation of an atom array xyzr (host, [n][4] double: x, y, z,
+ * r) against p: finite values, r > 0, lattice size below 2^16 per axis. */
+int32_t tms_check_atoms_host(const double *xyzr, int64_t n, const tms_params *p,
+                             char *msg, int64_t msg_len);
+
+/* Bin the atoms and build the neighbourhood lists (Section 2.2.1, after eq.
+ * polynew: only atoms near a cube contribute).
+ *  xyzr   device, [n][4] double (x, y, z, r), row-major; read, not kept.
+ *  n      number of atoms (>= 0).
+ *  p      parameters (copied).
+ *  cells  in/out: if *cells is NULL a new structure is created; otherwise
+ *         it is rebuilt in place and its device memory reused.  Owned by ctx;
+ *         free with tms_free_cells or tms_destroy.
+ * The initial grid (Section 2.2) has its origin at h0 * floor((min - pad)/h0)
+ * per axis and ceil((max + pad - origin)/h0) cubes per axis.
+ * Errors: TMS_E_INVALID (NaN/Inf, r <= 0, bad parameters, lattice too large),
+ * TMS_E_OOM, TMS_E_DEVICE. */
+int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_params *p,
+                        tms_cells **cells);
+
+/* Grid of a cell structure (host outputs; any pointer may be NULL). */
+int32_t tms_cells_info(const tms_cells *cells, double origin[3], int64_t dims[3], int32_t *K,
+                       double *rc2, int64_t *n_atoms);
+
+int32_t tms_free_cells(tms_ctx *ctx, tms_cells *cells);
+
+/* phi and its gradient at m points (eq. Gaussian1), summed over the atoms
+ * within R_c of each point.
+ *  pts   device [m][3] double;  phi device [m] double;  grad device [m][3]
+ *  double or NULL.  In TMS_PREC_FP32_GUARD the sums run in single precision
+ *  and every point with |phi - c| inside the single-precision error band is
+ *  recomputed in double precision, so the sign of phi - c is the
+ *  double-precision one; *n_guard (host, may be NULL) receives the count.
+ * Errors: TMS_E_INVALID, TMS_E_DEVICE. */
+int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                     double *phi, double *grad, int64_t *n_guard);
+
+/* The adaptive partition and estimation pass (Section 2.2, Steps 1-3), then
+ * the classification of every leaf by the signs of phi - c at its corners
+ * (the trilinear interpolant of eq. linear1 meets the closed cube iff the
+ * corner values straddle c).
+ *  leaves      device [cap] tms_leaf, or NULL to only count.
+ *  cap         capacity of leaves (and of corner_phi rows).
+ *  n_leaves    host out: number of leaves.
+ *  corner_phi  device [cap][8] double (corner v = dx + 2dy + 4dz) or NULL.
+ *  stats       host out or NULL.
+ * Leaves are ordered by level, then by refinement order: the roots in raster
+ * order (x fastest), and the 8 children of a divided cube in octant order
+ * (bit 0 x, bit 1 y, bit 2 z) at the position of their parent.
+ * The result is kept in ctx until the next partition call; if cap is too
+ * small the call returns TMS_E_CAPACITY with *n_leaves set to the required
+ * count and nothing copied -- then call tms_get_leaves with a larger buffer.
+ * Errors: TMS_E_CAPACITY, TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
+int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves, int64_t cap,
+                               int64_t *n_leaves, double *corner_phi, tms_stats *stats);
+
+/* Copy the leaves (and corner values, if corner_phi is not NULL) of the last
+ * partition pass.  Errors: TMS_E_CAPACITY (*n_leaves = required), TMS_E_INVALID. */
+int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64_t cap,
+                       int64_t *n_leaves);
+
+/* Edge intersection points of the trilinear surface g = c (eq. intersection):
+ * on every edge of a SURFACE leaf whose end signs differ, g is linear, and
+ * the point is at t = (c - phi0)/(phi1 - phi0) from the lower end.  An edge
+ * shared by leaves of the same level is emitted once, by the first leaf (in
+ * input order) that has it.  Vertices come out in (leaf, edge) order, the 12
+ * edges of a leaf ordered by axis, then by the offsets of the two other axes
+ * (lower axis first).
+ *  leaves     device [n] tms_leaf (as produced by tms_partition_estimate).
+ *  corner_phi device [n][8] double, or NULL to evaluate phi at the corners.
+ *  out        device [cap] tms_vertex, or NULL to only count.
+ *  n_out      host out: number of vertices.
+ * The result is kept in ctx until the next extract call (see
+ * tms_get_vertices).  Errors: TMS_E_CAPACITY (*n_out = required),
+ * TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
+int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves,
+                                  int64_t n, const double *corner_phi, tms_vertex *out,
+                                  int64_t cap, int64_t *n_out);
+
+int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_out);
+
+/* Debug: the coefficient tensor A (eqs. polynew, tensor1, tensor2) of given
+ * cubes, computed by the same kernels as the partition pass.
+ *  cubes  device [n][4] int32 (level, ix, iy, iz);  A device [n][64] double,
+ *  A[16 j + 4 k + l], j/k/l the x/y/z Legendre degrees.
+ *  precision TMS_PREC_* (FP32 results are widened to double). */
+int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cubes, int64_t n,
+                         int32_t precision, double *A);
+
+/* Debug: the nested-SVD bound (Section 2.2.2, eqs. SVD1-SVD7, Sxyz,
+ * bound1-bound3) of given tensors.
+ *  A   device [n][64] double;  out device [n][4] double: L, U, rho (l1 mass
+ *  of the residual tensor), r (outer rank kept by the 0.99 rule). */
+int32_t tms_debug_bound(tms_ctx *ctx, const double *A, int64_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMS_H */

@@ -59,7 +59,9 @@ class _Result(C.Structure):
                 ("rc2", C.c_double), ("n_est", _I64A), ("n_disc", _I64A),
                 ("n_refine", _I64A), ("n_conv", _I64A), ("n_hmin", _I64A),
                 ("n_pairs", C.c_int64), ("n_corners", C.c_int64),
-                ("tie_cube", C.c_int64), ("tie_corner", C.c_int64)]
+                ("tie_cube", C.c_int64), ("tie_corner", C.c_int64),
+                ("n_tie_list", C.c_int64), ("tie_list", C.c_int32 * (4 * 1024)),
+                ("tie_corner_keys", C.c_uint64 * 1024)]
 
 
 _lib = None
@@ -231,6 +233,10 @@ class Result:
         self.n_corners = r.n_corners
         self.tie_cube = r.tie_cube
         self.tie_corner = r.tie_corner
+        nt = min(r.n_tie_list, 1024)
+        self.tie_cubes = np.array(r.tie_list[:4 * nt], dtype=np.int64).reshape(nt, 4)
+        self.tie_corner_keys = np.array(r.tie_corner_keys[:min(r.tie_corner, 1024)],
+                                        dtype=np.uint64)
 
     @property
     def cubes_estimated(self) -> int:

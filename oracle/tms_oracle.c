@@ -51,6 +51,7 @@ enum { OR_CLS_OUTSIDE = 0, OR_CLS_SURFACE = 1, OR_CLS_INSIDE = 2 };
 
 #define OR_MAXLEV 8
 #define OR_TIE 1e-9
+#define OR_TIE_LIST 1024
 
 /* ------------------------------------------------------------------------ */
 /* Legendre polynomials L0..L3 and Gauss-Legendre quadrature                  */
@@ -690,6 +691,9 @@ typedef struct {
     int64_t n_corners;    /* unique leaf corners */
     int64_t tie_cube;     /* cube decisions with a margin below OR_TIE */
     int64_t tie_corner;   /* corner signs with |phi-c|/c below OR_TIE */
+    int64_t n_tie_list;   /* entries used in tie_list */
+    int32_t tie_list[4 * OR_TIE_LIST]; /* (level, ix, iy, iz) of near-tie cubes */
+    uint64_t tie_corner_keys[OR_TIE_LIST]; /* finest-lattice keys of near-tie corners */
 } or_result;
 
 static int is_pow2_ratio(double a, double b, int *k)
@@ -908,7 +912,21 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
                     else if (lev == K) dec[q] = 3;
                     else dec[q] = 1;
                 }
-                if (tie < OR_TIE) ++ties;
+                if (tie < OR_TIE) {
+                    ++ties;
+#ifdef _OPENMP
+#pragma omp critical(or_tie)
+#endif
+                    {
+                        if (R->n_tie_list < OR_TIE_LIST) {
+                            int32_t *t4 = R->tie_list + 4 * R->n_tie_list++;
+                            t4[0] = lev;
+                            t4[1] = Q[q].i[0];
+                            t4[2] = Q[q].i[1];
+                            t4[3] = Q[q].i[2];
+                        }
+                    }
+                }
             }
             R->n_pairs += pairs;
             R->tie_cube += ties;
@@ -973,15 +991,19 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
     double hmin = P->uniform ? h0 : P->h_min;
     int64_t cties = 0;
 #ifdef _OPENMP
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : cties)
+#pragma omp parallel for schedule(dynamic, 256)
 #endif
     for (int64_t i = 0; i < nu; ++i) {
         double p[3] = {R->origin[0] + (double)(int64_t)((uk[i] >> 32) & 0xFFFF) * hmin,
                        R->origin[1] + (double)(int64_t)((uk[i] >> 16) & 0xFFFF) * hmin,
                        R->origin[2] + (double)(int64_t)(uk[i] & 0xFFFF) * hmin};
         phi_point(&bins, D, rc2, p, uphi + i, NULL);
-        if (fabs(uphi[i] - c) / c < OR_TIE) ++cties;
     }
+    for (int64_t i = 0; i < nu; ++i)
+        if (fabs(uphi[i] - c) / c < OR_TIE) {
+            if (cties < OR_TIE_LIST) R->tie_corner_keys[cties] = uk[i];
+            ++cties;
+        }
     R->tie_corner = cties;
     /* classification against c through the sign pattern of the trilinear
      * interpolant's corner values (eq. linear1): g is a convex combination

@@ -1,0 +1,345 @@
+// phi / grad phi at points (eq. Gaussian1) and the leaf-corner stage:
+// unique finest-lattice corners, phi once per corner, 8-bit sign masks and
+// classes against c (eq. linear1).  gfx950.
+//
+// Every phi value at a point is a pure function of the point: its cell, the
+// 5x5x5 cell stencil (cells of edge >= R_c/2), atoms in canonical order.  So
+// corners shared by neighbouring leaves get bit-identical values and signs.
+#include "tms_device.h"
+
+namespace tms {
+
+namespace {
+
+constexpr int kBS = 256;
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
+constexpr uint64_t kEmpty = ~0ull;
+
+// Error band of the single-precision sum, relative to phi: per term the
+// exponent -D d^2 (|.| <= ln(1/eps_cut) + D r_max^2 ~ 30) carries a relative
+// error of a few ulp, plus the accumulation; 2^-14 leaves a wide margin.
+constexpr double kGammaPhi32 = 1.0 / 16384.0;
+
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_phi_points(Grid g, const double *__restrict__ pts,
+                                                    int64_t m, const int32_t *__restrict__ cs,
+                                                    const double *__restrict__ ax,
+                                                    const double *__restrict__ ay,
+                                                    const double *__restrict__ az,
+                                                    const double *__restrict__ aw,
+                                                    double *__restrict__ phi,
+                                                    double *__restrict__ grad,
+                                                    uint8_t *__restrict__ guard) {
+    int64_t k = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (k >= m) return;
+    const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
+    T f, gr[3];
+    phi_at<T>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi[k] = (double)f;
+    if (grad) {
+        grad[3 * k] = (double)gr[0];
+        grad[3 * k + 1] = (double)gr[1];
+        grad[3 * k + 2] = (double)gr[2];
+    }
+    if (guard) {
+        const double fd = (double)f;
+        guard[k] = (fabs(fd - g.c) <= kGammaPhi32 * fd + 1e-30) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kBS) void k_phi_subset(Grid g, const double *__restrict__ pts,
+                                                    const int32_t *__restrict__ list, int64_t m,
+                                                    const int32_t *__restrict__ cs,
+                                                    const double *__restrict__ ax,
+                                                    const double *__restrict__ ay,
+                                                    const double *__restrict__ az,
+                                                    const double *__restrict__ aw,
+                                                    double *__restrict__ phi,
+                                                    double *__restrict__ grad) {
+    int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (t >= m) return;
+    const int64_t k = list[t];
+    const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
+    double f, gr[3];
+    phi_at<double>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi[k] = f;
+    if (grad) {
+        grad[3 * k] = gr[0];
+        grad[3 * k + 1] = gr[1];
+        grad[3 * k + 2] = gr[2];
+    }
+}
+
+// finest-lattice key of corner v of a leaf: conf(16) | X(16) | Y(16) | Z(16)
+__device__ __forceinline__ uint64_t corner_key(const tms_leaf &L, int v, int K) {
+    const int sh = K - L.level;
+    const uint64_t X = (uint64_t)((L.ix + (v & 1)) << sh);
+    const uint64_t Y = (uint64_t)((L.iy + ((v >> 1) & 1)) << sh);
+    const uint64_t Z = (uint64_t)((L.iz + ((v >> 2) & 1)) << sh);
+    return ((uint64_t)(uint32_t)L.conf << 48) | (X << 32) | (Y << 16) | Z;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// open addressing with linear probing; returns the slot that holds key
+__device__ __forceinline__ uint32_t hash_insert(uint64_t *__restrict__ hk, uint64_t hmask,
+                                                uint64_t key) {
+    uint64_t s = mix64(key) & hmask;
+    while (true) {
+        uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long *>(hk + s),
+                                  (unsigned long long)kEmpty, (unsigned long long)key);
+        if (prev == kEmpty || prev == key) return (uint32_t)s;
+        s = (s + 1) & hmask;
+    }
+}
+
+__global__ void k_corner_insert(const tms_leaf *__restrict__ leaves, int64_t n, int K,
+                                uint64_t *__restrict__ hk, uint32_t *__restrict__ hown,
+                                uint64_t hmask, uint32_t *__restrict__ slot) {
+    int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= 8 * n) return;
+    const tms_leaf L = leaves[c >> 3];
+    const uint64_t key = corner_key(L, (int)(c & 7), K);
+    const uint32_t s = hash_insert(hk, hmask, key);
+    slot[c] = s;
+    atomicMin(&hown[s], (uint32_t)c);
+}
+
+__global__ void k_owner_flags(const uint32_t *__restrict__ slot, const uint32_t *__restrict__ hown,
+                              int64_t ncand, int32_t *__restrict__ f) {
+    int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= ncand) return;
+    const uint32_t s = slot[c];
+    f[c] = (s != 0xFFFFFFFFu && hown[s] == (uint32_t)c) ? 1 : 0;
+}
+
+__global__ void k_corner_unique(const tms_leaf *__restrict__ leaves, int64_t ncand, int K, Grid g,
+                                const int32_t *__restrict__ f, const int32_t *__restrict__ off,
+                                const uint32_t *__restrict__ slot, double *__restrict__ upts,
+                                uint32_t *__restrict__ slot2u) {
+    int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= ncand || !f[c]) return;
+    const tms_leaf L = leaves[c >> 3];
+    const int v = (int)(c & 7), sh = K - L.level;
+    const int64_t u = off[c];
+    upts[3 * u] = g.o[0] + (double)((L.ix + (v & 1)) << sh) * g.hmin;
+    upts[3 * u + 1] = g.o[1] + (double)((L.iy + ((v >> 1) & 1)) << sh) * g.hmin;
+    upts[3 * u + 2] = g.o[2] + (double)((L.iz + ((v >> 2) & 1)) << sh) * g.hmin;
+    slot2u[slot[c]] = (uint32_t)u;
+}
+
+__device__ __forceinline__ void classify(tms_leaf &L, const double f[8], double c) {
+    uint8_t m = 0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v)
+        if (f[v] >= c) m |= (uint8_t)(1u << v);
+    L.mask = m;
+    L.cls = (m == 0) ? TMS_CLS_OUTSIDE : (m == 0xFF ? TMS_CLS_INSIDE : TMS_CLS_SURFACE);
+}
+
+__global__ void k_corner_gather(const tms_leaf *__restrict__ lin, int64_t n,
+                                const uint32_t *__restrict__ slot, const uint32_t *__restrict__ s2u,
+                                const double *__restrict__ uphi, double c,
+                                tms_leaf *__restrict__ lout, double *__restrict__ cphi) {
+    int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n) return;
+    double f[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) f[v] = uphi[s2u[slot[8 * q + v]]];
+    tms_leaf L = lin[q];
+    classify(L, f, c);
+    lout[q] = L;
+    if (cphi) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) cphi[8 * q + v] = f[v];
+    }
+}
+
+__global__ void k_uniform_leaves(Grid g, tms_leaf *__restrict__ leaves, int64_t n) {
+    int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n) return;
+    tms_leaf L;
+    L.ix = (int32_t)(q % g.nr[0]);
+    L.iy = (int32_t)((q / g.nr[0]) % g.nr[1]);
+    L.iz = (int32_t)(q / ((int64_t)g.nr[0] * g.nr[1]));
+    L.conf = 0;
+    L.level = 0;
+    L.reason = TMS_REASON_UNIFORM;
+    L.mask = 0;
+    L.cls = 0;
+    leaves[q] = L;
+}
+
+__global__ void k_uniform_points(Grid g, double *__restrict__ pts, int64_t m) {
+    int64_t k = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (k >= m) return;
+    const int64_t px = g.nr[0] + 1, py = g.nr[1] + 1;
+    const int64_t x = k % px, y = (k / px) % py, z = k / (px * py);
+    pts[3 * k] = g.o[0] + (double)x * g.h0;
+    pts[3 * k + 1] = g.o[1] + (double)y * g.h0;
+    pts[3 * k + 2] = g.o[2] + (double)z * g.h0;
+}
+
+__global__ void k_uniform_gather(Grid g, const double *__restrict__ uphi, double c,
+                                 tms_leaf *__restrict__ leaves, int64_t n,
+                                 double *__restrict__ cphi) {
+    int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n) return;
+    tms_leaf L = leaves[q];
+    const int64_t px = g.nr[0] + 1, py = g.nr[1] + 1;
+    double f[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int64_t x = L.ix + (v & 1), y = L.iy + ((v >> 1) & 1), z = L.iz + ((v >> 2) & 1);
+        f[v] = uphi[(z * py + y) * px + x];
+    }
+    classify(L, f, c);
+    leaves[q] = L;
+    if (cphi) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) cphi[8 * q + v] = f[v];
+    }
+}
+
+__global__ void k_count_u8(const uint8_t *__restrict__ v, int64_t n, uint8_t value,
+                           unsigned long long *__restrict__ cnt) {
+    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    unsigned long long c = (i < n && v[i] == value) ? 1ull : 0ull;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
+__global__ void k_flags_u8(const uint8_t *__restrict__ gd, int64_t n, int32_t *__restrict__ f) {
+    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i < n) f[i] = gd[i] ? 1 : 0;
+}
+
+__global__ void k_list_emit2(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
+                             int64_t n, int32_t *__restrict__ list) {
+    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i < n && f[i]) list[off[i]] = (int32_t)i;
+}
+
+__global__ void k_count_surface(const tms_leaf *__restrict__ leaves, int64_t n,
+                                unsigned long long *__restrict__ cnt) {
+    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    unsigned long long c = (i < n && leaves[i].cls == TMS_CLS_SURFACE) ? 1ull : 0ull;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+}
+
+}  // namespace
+
+hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
+                             const int32_t *cs, const double *ax, const double *ay, const double *az,
+                             const double *aw, double *phi, double *grad, uint8_t *guard,
+                             hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    if (precision == TMS_PREC_FP32_GUARD)
+        hipLaunchKernelGGL(k_phi_points<float>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
+                           ay, az, aw, phi, grad, guard);
+    else
+        hipLaunchKernelGGL(k_phi_points<double>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
+                           ay, az, aw, phi, grad, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_points_subset(const Grid &g, const double *pts, const int32_t *list, int64_t m,
+                                    const int32_t *cs, const double *ax, const double *ay,
+                                    const double *az, const double *aw, double *phi, double *grad,
+                                    hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, list, m, cs, ax, ay, az,
+                       aw, phi, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
+                                uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_insert, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, hkeys, hown,
+                       (uint64_t)(hcap - 1), slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_t ncand,
+                              int32_t *flags, hipStream_t s) {
+    if (ncand <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_owner_flags, dim3(nblk(ncand)), dim3(kBS), 0, s, slot, hown, ncand, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid &g,
+                                const int32_t *flags, const int32_t *off, const uint32_t *slot,
+                                double *upts, uint32_t *slot2u, hipStream_t s) {
+    if (ncand <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_unique, dim3(nblk(ncand)), dim3(kBS), 0, s, leaves, ncand, K, g,
+                       flags, off, slot, upts, slot2u);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_gather(const tms_leaf *lin, int64_t n, const uint32_t *slot,
+                                const uint32_t *slot2u, const double *uphi, double c,
+                                tms_leaf *lout, double *cphi, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_gather, dim3(nblk(n)), dim3(kBS), 0, s, lin, n, slot, slot2u, uphi, c,
+                       lout, cphi);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform_leaves(const Grid &g, tms_leaf *leaves, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uniform_leaves, dim3(nblk(n)), dim3(kBS), 0, s, g, leaves, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform_points(const Grid &g, double *pts, int64_t m, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uniform_points, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform_gather(const Grid &g, const double *uphi, double c, tms_leaf *leaves,
+                                 int64_t n, double *cphi, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uniform_gather, dim3(nblk(n)), dim3(kBS), 0, s, g, uphi, c, leaves, n, cphi);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_u8(const uint8_t *v, int64_t n, uint8_t value, unsigned long long *count,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_u8, dim3(nblk(n)), dim3(kBS), 0, s, v, n, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_flags_u8(const uint8_t *gd, int64_t n, int32_t *flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flags_u8, dim3(nblk(n)), dim3(kBS), 0, s, gd, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_list_emit2, dim3(nblk(n)), dim3(kBS), 0, s, flags, off, n, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_surface, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, count);
+    return hipGetLastError();
+}
+
+}  // namespace tms

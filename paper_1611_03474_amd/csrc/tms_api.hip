@@ -1,0 +1,834 @@
+// Host side of the C ABI declared in include/tms.h: argument validation, grid
+// set-up, buffer management and the level-by-level orchestration of the
+// partition/estimation kernels (Section 2.2 of Liu, Chen & Lu,
+// arXiv:1611.03474) on one HIP stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tms_internal.h"
+
+using namespace tms;
+
+namespace tms {
+
+hipError_t DevBuf::ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    size_t nb = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) {
+        p = nullptr;
+        cap = 0;
+        (void)hipGetLastError();
+        return e;
+    }
+    cap = nb;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+hipError_t launch_edge_count(const tms_leaf *leaves, int64_t n, unsigned long long *count,
+                             hipStream_t s);
+
+}  // namespace tms
+
+void tms_cells::release() {
+    ax.release();
+    ay.release();
+    az.release();
+    aw.release();
+    aidx.release();
+    ar.release();
+    cell_start.release();
+    root_start.release();
+    root_atoms.release();
+    tmp_key.release();
+    tmp_cnt.release();
+}
+
+namespace {
+
+std::string g_create_err;
+
+int32_t fail(tms_ctx *ctx, int32_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_err = buf;
+    return code;
+}
+
+int32_t hip_fail(tms_ctx *ctx, hipError_t e, const char *what) {
+    (void)hipGetLastError();
+    return fail(ctx, e == hipErrorOutOfMemory ? TMS_E_OOM : TMS_E_DEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIPCK(expr)                                               \
+    do {                                                          \
+        hipError_t e_ = (expr);                                   \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);    \
+    } while (0)
+
+void set_msg(char *msg, int64_t len, const std::string &s) {
+    if (!msg || len <= 0) return;
+    size_t n = std::min<size_t>((size_t)len - 1, s.size());
+    memcpy(msg, s.data(), n);
+    msg[n] = 0;
+}
+
+bool check_params(const tms_params *p, std::string &why, int *Kout) {
+    if (!p) { why = "params is NULL"; return false; }
+    auto pos = [](double v) { return std::isfinite(v) && v > 0; };
+    if (!pos(p->D)) { why = "D must be finite and > 0"; return false; }
+    if (!pos(p->c)) { why = "c must be finite and > 0"; return false; }
+    if (!pos(p->h0)) { why = "h0 must be finite and > 0"; return false; }
+    if (!pos(p->h_min)) { why = "h_min must be finite and > 0"; return false; }
+    if (!(std::isfinite(p->pad) && p->pad >= 0)) { why = "pad must be finite and >= 0"; return false; }
+    if (!(p->eps_cut > 0 && p->eps_cut < 1)) { why = "eps_cut must be in (0,1)"; return false; }
+    if (p->precision != TMS_PREC_FP64 && p->precision != TMS_PREC_FP32_GUARD) {
+        why = "precision must be TMS_PREC_FP64 or TMS_PREC_FP32_GUARD";
+        return false;
+    }
+    if (p->mode != TMS_MODE_ADAPTIVE && p->mode != TMS_MODE_UNIFORM) {
+        why = "mode must be TMS_MODE_ADAPTIVE or TMS_MODE_UNIFORM";
+        return false;
+    }
+    int K = 0;
+    if (p->mode == TMS_MODE_ADAPTIVE) {
+        if (!pos(p->tau)) { why = "tau must be finite and > 0"; return false; }
+        double r = p->h0 / p->h_min;
+        bool ok = false;
+        for (int k = 0; k < TMS_MAX_LEVELS; ++k)
+            if (r == std::ldexp(1.0, k)) { K = k; ok = true; }
+        if (!ok) { why = "h0 / h_min must be 2^K with 0 <= K < 8"; return false; }
+        double beta = 0.5 * p->h0 * std::sqrt(p->D);
+        if (gl_half_nodes(beta, p->precision == TMS_PREC_FP32_GUARD) < 0) {
+            why = "h0 * sqrt(D) too large for the projection quadrature (need h0 sqrt(D) <= 2.5)";
+            return false;
+        }
+    }
+    if (Kout) *Kout = K;
+    return true;
+}
+
+int64_t next_pow2(int64_t v) {
+    int64_t p = 1024;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// grow a buffer keeping its first `used` bytes
+hipError_t grow_keep(DevBuf &b, size_t need, size_t used, hipStream_t s) {
+    if (need <= b.cap && b.p) return hipSuccess;
+    void *np = nullptr;
+    size_t nb = std::max<size_t>(need, b.cap + b.cap / 2);
+    hipError_t e = hipMalloc(&np, nb);
+    if (e != hipSuccess) return e;
+    if (used && b.p) {
+        e = hipMemcpyAsync(np, b.p, used, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+    }
+    b.release();
+    b.p = np;
+    b.cap = nb;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t d2h(T *dst, const void *src, size_t count, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// scan `n` int32 values of `in` into `out` and return the total on the host
+int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int64_t *total) {
+    HIPCK(ctx->scan_c.ensure(scan_tmp_bytes(n) + 512));
+    int32_t *tot = ctx->counters.as<int32_t>() + 60;
+    HIPCK(exclusive_scan(in, out, n, tot, ctx->scan_c.p, ctx->stream));
+    int32_t h = 0;
+    HIPCK(d2h(&h, tot, 1, ctx->stream));
+    *total = h;
+    return TMS_OK;
+}
+
+// phi at m points of `pts` into uphi (with single-precision guard); returns
+// the number of points recomputed in double precision
+int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                       double *phi, double *grad, int64_t *n_guard) {
+    const int prec = cells->p.precision;
+    const Grid &g = cells->g;
+    *n_guard = 0;
+    if (m <= 0) return TMS_OK;
+    uint8_t *gbuf = nullptr;
+    if (prec == TMS_PREC_FP32_GUARD) {
+        HIPCK(ctx->uguard.ensure((size_t)m));
+        gbuf = ctx->uguard.as<uint8_t>();
+    }
+    HIPCK(launch_phi_points(g, prec, pts, m, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
+                            cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
+                            phi, grad, gbuf, ctx->stream));
+    if (prec == TMS_PREC_FP32_GUARD) {
+        HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)m));
+        HIPCK(ctx->scan_a.ensure(sizeof(int32_t) * (size_t)m));
+        HIPCK(launch_guard_flags_u8(gbuf, m, ctx->flags.as<int32_t>(), ctx->stream));
+        int64_t ng = 0;
+        int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), m, &ng);
+        if (rc) return rc;
+        if (ng > 0) {
+            HIPCK(ctx->idx.ensure(sizeof(int32_t) * (size_t)ng));
+            HIPCK(launch_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), m,
+                                   ctx->idx.as<int32_t>(), ctx->stream));
+            HIPCK(launch_phi_points_subset(g, pts, ctx->idx.as<int32_t>(), ng,
+                                           cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
+                                           cells->ay.as<double>(), cells->az.as<double>(),
+                                           cells->aw.as<double>(), phi, grad, ctx->stream));
+        }
+        *n_guard = ng;
+    }
+    return TMS_OK;
+}
+
+// unique corners of `leaves`, phi once per corner, masks and classes;
+// writes leaves_out (may alias leaves) and cphi [n][8]
+int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
+                     tms_leaf *leaves_out, double *cphi, int64_t *n_corners, int64_t *n_guard) {
+    const Grid &g = cells->g;
+    hipStream_t s = ctx->stream;
+    *n_corners = 0;
+    *n_guard = 0;
+    if (n <= 0) return TMS_OK;
+    const int64_t ncand = 8 * n;
+    if (ncand >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves (%lld)", (long long)n);
+    const int64_t hcap = next_pow2(2 * ncand);
+    HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
+    HIPCK(ctx->hown.ensure(sizeof(uint32_t) * (size_t)hcap));
+    HIPCK(ctx->slot.ensure(sizeof(uint32_t) * (size_t)ncand));
+    HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)ncand));
+    HIPCK(ctx->scan_a.ensure(sizeof(int32_t) * (size_t)ncand));
+    HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
+    HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
+    HIPCK(launch_corner_insert(leaves, n, g.K, ctx->hkeys.as<uint64_t>(), ctx->hown.as<uint32_t>(),
+                               hcap, ctx->slot.as<uint32_t>(), s));
+    HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
+                             ctx->flags.as<int32_t>(), s));
+    int64_t nu = 0;
+    int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), ncand, &nu);
+    if (rc) return rc;
+    HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)nu));
+    HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)nu));
+    // slot -> unique index map reuses the owner array (same size, u32)
+    uint32_t *slot2u = ctx->hown.as<uint32_t>();
+    HIPCK(ctx->lc.ensure(sizeof(uint32_t) * (size_t)hcap));
+    slot2u = ctx->lc.as<uint32_t>();
+    HIPCK(launch_corner_unique(leaves, ncand, g.K, g, ctx->flags.as<int32_t>(),
+                               ctx->scan_a.as<int32_t>(), ctx->slot.as<uint32_t>(),
+                               ctx->uniq.as<double>(), slot2u, s));
+    rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nu, ctx->uphi.as<double>(), nullptr,
+                        n_guard);
+    if (rc) return rc;
+    HIPCK(launch_corner_gather(leaves, n, ctx->slot.as<uint32_t>(), slot2u, ctx->uphi.as<double>(),
+                               g.c, leaves_out, cphi, s));
+    *n_corners = nu;
+    return TMS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t tms_create(tms_ctx **out, int32_t device, void *stream) {
+    if (!out) return fail(nullptr, TMS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int cnt = 0;
+    hipError_t e = hipGetDeviceCount(&cnt);
+    if (e != hipSuccess || cnt <= 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, TMS_E_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= cnt)
+        return fail(nullptr, TMS_E_DEVICE, "device %d out of range (%d devices)", device, cnt);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, TMS_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    tms_ctx *ctx = new tms_ctx();
+    ctx->device = device;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    e = ctx->counters.ensure(4096);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, TMS_E_OOM, "counter allocation failed");
+    }
+    *out = ctx;
+    return TMS_OK;
+}
+
+int32_t tms_destroy(tms_ctx *ctx) {
+    if (!ctx) return TMS_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (tms_cells *c : ctx->cells) {
+        c->release();
+        delete c;
+    }
+    tms::DevBuf *bufs[] = {&ctx->leaves, &ctx->corner_phi, &ctx->verts, &ctx->q[0], &ctx->q[1],
+                           &ctx->qmeta, &ctx->abuf, &ctx->ebuf, &ctx->dec, &ctx->scan_a,
+                           &ctx->scan_b, &ctx->scan_c, &ctx->flags, &ctx->idx, &ctx->hkeys,
+                           &ctx->hown, &ctx->slot, &ctx->uniq, &ctx->uphi, &ctx->uguard, &ctx->lc,
+                           &ctx->ctmp, &ctx->counters, &ctx->hostpin};
+    for (auto *b : bufs) b->release();
+    delete ctx;
+    return TMS_OK;
+}
+
+const char *tms_last_error(const tms_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+int32_t tms_check_params(const tms_params *p, char *msg, int64_t msg_len) {
+    std::string why;
+    if (!check_params(p, why, nullptr)) {
+        set_msg(msg, msg_len, why);
+        return TMS_E_INVALID;
+    }
+    set_msg(msg, msg_len, "");
+    return TMS_OK;
+}
+
+int32_t tms_check_atoms_host(const double *xyzr, int64_t n, const tms_params *p, char *msg,
+                             int64_t msg_len) {
+    std::string why;
+    int K = 0;
+    if (!check_params(p, why, &K)) {
+        set_msg(msg, msg_len, why);
+        return TMS_E_INVALID;
+    }
+    if (n < 0 || (n > 0 && !xyzr)) {
+        set_msg(msg, msg_len, "n < 0 or xyzr NULL");
+        return TMS_E_INVALID;
+    }
+    double mn[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 4; ++a)
+            if (!std::isfinite(xyzr[4 * i + a])) {
+                set_msg(msg, msg_len, "non-finite atom value");
+                return TMS_E_INVALID;
+            }
+        if (!(xyzr[4 * i + 3] > 0)) {
+            set_msg(msg, msg_len, "atom radius must be > 0");
+            return TMS_E_INVALID;
+        }
+        for (int a = 0; a < 3; ++a) {
+            double v = xyzr[4 * i + a];
+            if (i == 0 || v < mn[a]) mn[a] = v;
+            if (i == 0 || v > mx[a]) mx[a] = v;
+        }
+    }
+    const double h0 = p->h0;
+    if (p->mode == TMS_MODE_UNIFORM) K = 0;
+    for (int a = 0; a < 3; ++a) {
+        double o = h0 * std::floor((mn[a] - p->pad) / h0);
+        double d = std::ceil((mx[a] + p->pad - o) / h0);
+        if (d * std::ldexp(1.0, K) > 65535.0) {
+            set_msg(msg, msg_len, "finest lattice exceeds 65535 points per axis");
+            return TMS_E_INVALID;
+        }
+    }
+    set_msg(msg, msg_len, "");
+    return TMS_OK;
+}
+
+int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_params *p,
+                        tms_cells **cells_io) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells_io) return fail(ctx, TMS_E_INVALID, "cells is NULL");
+    std::string why;
+    int K = 0;
+    if (!check_params(p, why, &K)) return fail(ctx, TMS_E_INVALID, "%s", why.c_str());
+    if (n < 0 || (n > 0 && !xyzr)) return fail(ctx, TMS_E_INVALID, "n < 0 or xyzr NULL");
+    if (n >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many atoms");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    tms_cells *cells = *cells_io;
+    if (cells && std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    bool fresh = false;
+    if (!cells) {
+        cells = new tms_cells();
+        fresh = true;
+    }
+    auto bail = [&](int32_t rc) {
+        if (fresh) {
+            cells->release();
+            delete cells;
+        }
+        return rc;
+    };
+    cells->p = *p;
+    cells->n = n;
+    if (p->mode == TMS_MODE_UNIFORM) K = 0;
+
+    // bounding box, radii, finiteness
+    double st[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (n > 0) {
+        tms::DevBuf &tb = ctx->ctmp;
+        hipError_t e = tb.ensure(sizeof(double) * (16 + 9 * 1024));
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "stats buffer"));
+        e = launch_atom_stats(xyzr, n, tb.as<double>(), s);
+        if (e == hipSuccess) e = d2h(st, tb.p, 9, s);
+        if (e != hipSuccess) return bail(hip_fail(ctx, e, "atom stats"));
+        if (st[8] > 0) return bail(fail(ctx, TMS_E_INVALID, "atom array holds NaN or Inf"));
+        if (!(st[7] > 0)) return bail(fail(ctx, TMS_E_INVALID, "atom radius must be > 0"));
+    }
+    Grid g{};
+    g.h0 = p->h0;
+    g.hmin = (p->mode == TMS_MODE_UNIFORM) ? p->h0 : p->h_min;
+    g.D = p->D;
+    g.c = p->c;
+    g.tau = p->tau;
+    g.K = K;
+    g.span = 2;
+    cells->rmax = n > 0 ? st[6] : 0.0;
+    g.rc2 = cells->rmax * cells->rmax + std::log(1.0 / p->eps_cut) / p->D;
+    for (int a = 0; a < 3; ++a) {
+        double mn = n > 0 ? st[a] : 0.0, mx = n > 0 ? st[3 + a] : 0.0;
+        g.o[a] = p->h0 * std::floor((mn - p->pad) / p->h0);
+        double d = std::ceil((mx + p->pad - g.o[a]) / p->h0);
+        if (d < 1) d = 1;
+        if (d * std::ldexp(1.0, K) > 65535.0)
+            return bail(fail(ctx, TMS_E_INVALID, "finest lattice exceeds 65535 points per axis"));
+        g.nr[a] = (int32_t)d;
+    }
+    // atom cells: edge h0 * 2^m >= R_c / 2, so a +-2 cell stencil covers R_c
+    const double Rc = std::sqrt(g.rc2);
+    g.cs = p->h0;
+    while (g.cs < 0.5 * Rc) g.cs *= 2.0;
+    int64_t ncells = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.nc[a] = (int32_t)std::max(1.0, std::ceil(g.nr[a] * p->h0 / g.cs));
+        ncells *= g.nc[a];
+    }
+    cells->g = g;
+    cells->ncells = ncells;
+    cells->nroots = (int64_t)g.nr[0] * g.nr[1] * g.nr[2];
+
+    auto ck = [&](hipError_t e, const char *what) -> int32_t {
+        return e == hipSuccess ? TMS_OK : hip_fail(ctx, e, what);
+    };
+#define CK(expr)                                        \
+    do {                                                \
+        int32_t rc_ = ck((expr), #expr);                \
+        if (rc_) return bail(rc_);                      \
+    } while (0)
+    const size_t na = (size_t)std::max<int64_t>(n, 1);
+    CK(cells->ax.ensure(8 * na));
+    CK(cells->ay.ensure(8 * na));
+    CK(cells->az.ensure(8 * na));
+    CK(cells->aw.ensure(8 * na));
+    CK(cells->ar.ensure(8 * na));
+    CK(cells->aidx.ensure(4 * na));
+    CK(cells->tmp_key.ensure(4 * na));
+    CK(cells->cell_start.ensure(4 * (size_t)(ncells + 1)));
+    CK(cells->tmp_cnt.ensure(4 * (size_t)(ncells + 1)));
+    int32_t *cnt = cells->tmp_cnt.as<int32_t>();
+    CK(launch_fill_u32(reinterpret_cast<uint32_t *>(cnt), 0u, ncells + 1, s));
+    CK(launch_bin_atoms(g, xyzr, n, cells->tmp_key.as<int32_t>(), cnt, ncells, s));
+    {
+        int64_t tot = 0;
+        int32_t rc = scan_total(ctx, cnt, cells->cell_start.as<int32_t>(), ncells + 1, &tot);
+        if (rc) return bail(rc);
+    }
+    // scatter positions start from the cell offsets
+    CK(hipMemcpyAsync(cnt, cells->cell_start.p, 4 * (size_t)ncells, hipMemcpyDeviceToDevice, s));
+    CK(launch_scatter_atoms(g, xyzr, n, cells->tmp_key.as<int32_t>(), cnt, cells->ax.as<double>(),
+                            cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
+                            cells->ar.as<double>(), cells->aidx.as<int32_t>(), s));
+    CK(launch_sort_cells(cells->cell_start.as<int32_t>(), ncells, cells->ax.as<double>(),
+                         cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
+                         cells->ar.as<double>(), cells->aidx.as<int32_t>(), s));
+    cells->n_root_entries = 0;
+    if (p->mode == TMS_MODE_ADAPTIVE) {
+        const int64_t nr = cells->nroots;
+        CK(cells->root_start.ensure(4 * (size_t)(nr + 1)));
+        CK(ctx->flags.ensure(4 * (size_t)(nr + 1)));
+        int32_t *rc_cnt = ctx->flags.as<int32_t>();
+        CK(launch_fill_u32(reinterpret_cast<uint32_t *>(rc_cnt), 0u, nr + 1, s));
+        CK(launch_root_count(g, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
+                             cells->ay.as<double>(), cells->az.as<double>(), nr, rc_cnt, s));
+        int64_t tot = 0;
+        int32_t rc = scan_total(ctx, rc_cnt, cells->root_start.as<int32_t>(), nr + 1, &tot);
+        if (rc) return bail(rc);
+        cells->n_root_entries = tot;
+        CK(cells->root_atoms.ensure(4 * (size_t)std::max<int64_t>(tot, 1)));
+        CK(launch_root_fill(g, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
+                            cells->ay.as<double>(), cells->az.as<double>(), nr,
+                            cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(), s));
+    }
+    CK(hipStreamSynchronize(s));
+#undef CK
+    if (fresh) ctx->cells.push_back(cells);
+    *cells_io = cells;
+    return TMS_OK;
+}
+
+int32_t tms_cells_info(const tms_cells *cells, double origin[3], int64_t dims[3], int32_t *K,
+                       double *rc2, int64_t *n_atoms) {
+    if (!cells) return TMS_E_INVALID;
+    for (int a = 0; a < 3; ++a) {
+        if (origin) origin[a] = cells->g.o[a];
+        if (dims) dims[a] = cells->g.nr[a];
+    }
+    if (K) *K = cells->g.K;
+    if (rc2) *rc2 = cells->g.rc2;
+    if (n_atoms) *n_atoms = cells->n;
+    return TMS_OK;
+}
+
+int32_t tms_free_cells(tms_ctx *ctx, tms_cells *cells) {
+    if (!ctx || !cells) return TMS_E_INVALID;
+    auto it = std::find(ctx->cells.begin(), ctx->cells.end(), cells);
+    if (it == ctx->cells.end()) return fail(ctx, TMS_E_INVALID, "unknown cells handle");
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    cells->release();
+    delete cells;
+    ctx->cells.erase(it);
+    return TMS_OK;
+}
+
+int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                     double *phi, double *grad, int64_t *n_guard) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || m < 0 || (m > 0 && (!pts || !phi)))
+        return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_eval_phi");
+    HIPCK(hipSetDevice(ctx->device));
+    int64_t ng = 0;
+    int32_t rc = phi_with_guard(ctx, cells, pts, m, phi, grad, &ng);
+    if (rc) return rc;
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    if (n_guard) *n_guard = ng;
+    return TMS_OK;
+}
+
+int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves_out,
+                               int64_t cap, int64_t *n_leaves, double *corner_phi_out,
+                               tms_stats *stats) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || !n_leaves || cap < 0) return fail(ctx, TMS_E_INVALID, "invalid arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const Grid &g = cells->g;
+    const int prec = cells->p.precision;
+    tms_stats st;
+    memset(&st, 0, sizeof st);
+    unsigned long long *ctr = ctx->counters.as<unsigned long long>();
+    int64_t L = 0;
+
+    if (cells->p.mode == TMS_MODE_UNIFORM) {
+        L = cells->nroots;
+        if (L >= (int64_t)0x7FFFFFFF / 8) return fail(ctx, TMS_E_INVALID, "grid too large");
+        HIPCK(ctx->leaves.ensure(sizeof(tms_leaf) * (size_t)L));
+        HIPCK(ctx->corner_phi.ensure(sizeof(double) * 8 * (size_t)L));
+        HIPCK(launch_uniform_leaves(g, ctx->leaves.as<tms_leaf>(), L, s));
+        const int64_t m = (int64_t)(g.nr[0] + 1) * (g.nr[1] + 1) * (g.nr[2] + 1);
+        HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)m));
+        HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)m));
+        HIPCK(launch_uniform_points(g, ctx->uniq.as<double>(), m, s));
+        int64_t ng = 0;
+        int32_t rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), m, ctx->uphi.as<double>(),
+                                    nullptr, &ng);
+        if (rc) return rc;
+        HIPCK(launch_uniform_gather(g, ctx->uphi.as<double>(), g.c, ctx->leaves.as<tms_leaf>(), L,
+                                    ctx->corner_phi.as<double>(), s));
+        st.n_corners = m;
+        st.guard_points = ng;
+    } else {
+        // Q_0: roots with a non-empty neighbourhood, raster order
+        const int64_t nr = cells->nroots;
+        HIPCK(ctx->flags.ensure(4 * (size_t)nr));
+        HIPCK(ctx->scan_a.ensure(4 * (size_t)nr));
+        HIPCK(launch_roots_flags(cells->root_start.as<int32_t>(), nr, ctx->flags.as<int32_t>(), s));
+        int64_t nq = 0;
+        int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nr, &nq);
+        if (rc) return rc;
+        int cur = 0;
+        HIPCK(ctx->q[0].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nq, 1)));
+        HIPCK(launch_roots_emit(g, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nr,
+                                ctx->q[0].as<int4>(), s));
+        for (int lev = 0; lev <= g.K && nq > 0; ++lev) {
+            if (nq >= (int64_t)0x7FFFFFFF / 8) return fail(ctx, TMS_E_INVALID, "queue too large");
+            st.n_est[lev] = nq;
+            HIPCK(ctx->abuf.ensure(sizeof(double) * 64 * (size_t)nq));
+            HIPCK(ctx->ebuf.ensure(sizeof(double) * (size_t)nq));
+            HIPCK(ctx->dec.ensure((size_t)nq));
+            HIPCK(hipMemsetAsync(ctr, 0, 256, s));
+            const int4 *q = ctx->q[cur].as<int4>();
+            HIPCK(launch_estimate(g, lev, prec, q, nq, nullptr, cells->root_start.as<int32_t>(),
+                                  cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
+                                  cells->ay.as<double>(), cells->az.as<double>(),
+                                  cells->aw.as<double>(), ctx->abuf.as<double>(),
+                                  ctx->ebuf.as<double>(), reinterpret_cast<int64_t *>(ctr + 0), s));
+            HIPCK(launch_decide(g, lev, prec, ctx->abuf.as<double>(), ctx->ebuf.as<double>(), nq,
+                                nullptr, ctx->dec.as<uint8_t>(),
+                                reinterpret_cast<int32_t *>(ctr + 1), s));
+            if (prec == TMS_PREC_FP32_GUARD) {
+                HIPCK(ctx->flags.ensure(4 * (size_t)nq));
+                HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
+                HIPCK(launch_guard_list_flags(ctx->dec.as<uint8_t>(), nq, ctx->flags.as<int32_t>(), s));
+                int64_t ng = 0;
+                rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &ng);
+                if (rc) return rc;
+                if (ng > 0) {
+                    HIPCK(ctx->idx.ensure(4 * (size_t)ng));
+                    HIPCK(launch_guard_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(),
+                                                 nq, ctx->idx.as<int32_t>(), s));
+                    HIPCK(launch_estimate(g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(),
+                                          cells->root_start.as<int32_t>(),
+                                          cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
+                                          cells->ay.as<double>(), cells->az.as<double>(),
+                                          cells->aw.as<double>(), ctx->abuf.as<double>(),
+                                          ctx->ebuf.as<double>(), nullptr, s));
+                    HIPCK(launch_decide(g, lev, TMS_PREC_FP64, ctx->abuf.as<double>(),
+                                        ctx->ebuf.as<double>(), ng, ctx->idx.as<int32_t>(),
+                                        ctx->dec.as<uint8_t>(), reinterpret_cast<int32_t *>(ctr + 1),
+                                        s));
+                }
+                st.guard_cubes += ng;
+            }
+            HIPCK(launch_level_histo(ctx->dec.as<uint8_t>(), nq, ctr + 8, s));
+            HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
+            HIPCK(ctx->scan_b.ensure(4 * (size_t)nq));
+            HIPCK(ctx->flags.ensure(4 * (size_t)nq));
+            HIPCK(ctx->idx.ensure(4 * (size_t)nq));
+            int32_t *lcnt = ctx->flags.as<int32_t>(), *ccnt = ctx->idx.as<int32_t>();
+            HIPCK(launch_level_counts(ctx->dec.as<uint8_t>(), nq, lcnt, ccnt, s));
+            int64_t nl = 0, nc = 0;
+            rc = scan_total(ctx, lcnt, ctx->scan_a.as<int32_t>(), nq, &nl);
+            if (rc) return rc;
+            rc = scan_total(ctx, ccnt, ctx->scan_b.as<int32_t>(), nq, &nc);
+            if (rc) return rc;
+            unsigned long long h[16];
+            HIPCK(d2h(h, ctr, 16, s));
+            st.n_pairs += (int64_t)h[0];
+            st.n_bound += (int64_t)h[1];
+            st.n_disc[lev] = (int64_t)h[8 + DEC_DISCARD];
+            st.n_refine[lev] = (int64_t)h[8 + DEC_REFINE];
+            st.n_conv[lev] = (int64_t)h[8 + DEC_CONV];
+            st.n_hmin[lev] = (int64_t)h[8 + DEC_HMIN];
+            HIPCK(grow_keep(ctx->leaves, sizeof(tms_leaf) * (size_t)(L + nl), sizeof(tms_leaf) * (size_t)L, s));
+            HIPCK(ctx->q[cur ^ 1].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nc, 1)));
+            HIPCK(launch_level_emit(q, ctx->dec.as<uint8_t>(), nq, lev, ctx->scan_a.as<int32_t>(),
+                                    ctx->scan_b.as<int32_t>(), ctx->leaves.as<tms_leaf>(), L,
+                                    ctx->q[cur ^ 1].as<int4>(), s));
+            L += nl;
+            nq = nc;
+            cur ^= 1;
+        }
+        HIPCK(ctx->leaves.ensure(sizeof(tms_leaf) * (size_t)std::max<int64_t>(L, 1)));
+        HIPCK(ctx->corner_phi.ensure(sizeof(double) * 8 * (size_t)std::max<int64_t>(L, 1)));
+        int64_t nu = 0, ng = 0;
+        rc = corner_stage(ctx, cells, ctx->leaves.as<tms_leaf>(), L, ctx->leaves.as<tms_leaf>(),
+                          ctx->corner_phi.as<double>(), &nu, &ng);
+        if (rc) return rc;
+        st.n_corners = nu;
+        st.guard_points = ng;
+    }
+    HIPCK(hipMemsetAsync(ctr, 0, 8, s));
+    HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr, s));
+    unsigned long long ns = 0;
+    HIPCK(d2h(&ns, ctr, 1, s));
+    st.n_leaves = L;
+    st.n_surface = (int64_t)ns;
+    ctx->n_leaves = L;
+    if (stats) *stats = st;
+    *n_leaves = L;
+    if (!leaves_out) return TMS_OK;
+    if (cap < L) return fail(ctx, TMS_E_CAPACITY, "leaf capacity %lld < %lld", (long long)cap, (long long)L);
+    if (L > 0) {
+        HIPCK(hipMemcpyAsync(leaves_out, ctx->leaves.p, sizeof(tms_leaf) * (size_t)L,
+                             hipMemcpyDeviceToDevice, s));
+        if (corner_phi_out)
+            HIPCK(hipMemcpyAsync(corner_phi_out, ctx->corner_phi.p, sizeof(double) * 8 * (size_t)L,
+                                 hipMemcpyDeviceToDevice, s));
+    }
+    HIPCK(hipStreamSynchronize(s));
+    return TMS_OK;
+}
+
+int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64_t cap,
+                       int64_t *n_leaves) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!n_leaves) return fail(ctx, TMS_E_INVALID, "n_leaves is NULL");
+    *n_leaves = ctx->n_leaves;
+    if (!leaves) return TMS_OK;
+    if (cap < ctx->n_leaves) return fail(ctx, TMS_E_CAPACITY, "leaf capacity too small");
+    HIPCK(hipSetDevice(ctx->device));
+    const int64_t L = ctx->n_leaves;
+    if (L > 0) {
+        HIPCK(hipMemcpyAsync(leaves, ctx->leaves.p, sizeof(tms_leaf) * (size_t)L,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+        if (corner_phi)
+            HIPCK(hipMemcpyAsync(corner_phi, ctx->corner_phi.p, sizeof(double) * 8 * (size_t)L,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return TMS_OK;
+}
+
+int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves,
+                                  int64_t n, const double *corner_phi, tms_vertex *out, int64_t cap,
+                                  int64_t *n_out) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || !n_out || n < 0 || cap < 0 || (n > 0 && !leaves))
+        return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_extract_cube_vertices");
+    if (12 * n >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves");
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const Grid &g = cells->g;
+    const tms_leaf *lv = leaves;
+    const double *cphi = corner_phi;
+    if (n > 0 && !cphi) {
+        // evaluate the corners of the given leaves (classes recomputed too)
+        HIPCK(ctx->ctmp.ensure((sizeof(tms_leaf) + 8 * sizeof(double)) * (size_t)n + 256));
+        tms_leaf *lt = ctx->ctmp.as<tms_leaf>();
+        double *ct = reinterpret_cast<double *>(
+            (reinterpret_cast<uintptr_t>(lt + n) + 255) & ~(uintptr_t)255);
+        int64_t nu = 0, ng = 0;
+        int32_t rc = corner_stage(ctx, cells, leaves, n, lt, ct, &nu, &ng);
+        if (rc) return rc;
+        lv = lt;
+        cphi = ct;
+    }
+    int64_t nv = 0;
+    if (n > 0) {
+        unsigned long long *ctr = ctx->counters.as<unsigned long long>();
+        HIPCK(hipMemsetAsync(ctr, 0, 8, s));
+        HIPCK(launch_edge_count(lv, n, ctr, s));
+        unsigned long long ncr = 0;
+        HIPCK(d2h(&ncr, ctr, 1, s));
+        const int64_t ncand = 12 * n;
+        const int64_t hcap = next_pow2(2 * (int64_t)ncr + 2);
+        HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
+        HIPCK(ctx->hown.ensure(sizeof(uint32_t) * (size_t)hcap));
+        HIPCK(ctx->slot.ensure(sizeof(uint32_t) * (size_t)ncand));
+        HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)ncand));
+        HIPCK(ctx->scan_b.ensure(sizeof(int32_t) * (size_t)ncand));
+        HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
+        HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
+        HIPCK(launch_edge_insert(lv, n, g.K, ctx->hkeys.as<uint64_t>(), ctx->hown.as<uint32_t>(),
+                                 hcap, ctx->slot.as<uint32_t>(), s));
+        HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
+                                 ctx->flags.as<int32_t>(), s));
+        int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), ncand, &nv);
+        if (rc) return rc;
+        HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
+        HIPCK(launch_edge_emit(g, cells->p.precision, lv, cphi, ncand, ctx->flags.as<int32_t>(),
+                               ctx->scan_b.as<int32_t>(), cells->cell_start.as<int32_t>(),
+                               cells->ax.as<double>(), cells->ay.as<double>(),
+                               cells->az.as<double>(), cells->aw.as<double>(),
+                               ctx->verts.as<tms_vertex>(), s));
+    }
+    ctx->n_verts = nv;
+    *n_out = nv;
+    if (!out) {
+        HIPCK(hipStreamSynchronize(s));
+        return TMS_OK;
+    }
+    if (cap < nv) {
+        HIPCK(hipStreamSynchronize(s));
+        return fail(ctx, TMS_E_CAPACITY, "vertex capacity %lld < %lld", (long long)cap, (long long)nv);
+    }
+    if (nv > 0)
+        HIPCK(hipMemcpyAsync(out, ctx->verts.p, sizeof(tms_vertex) * (size_t)nv,
+                             hipMemcpyDeviceToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
+    return TMS_OK;
+}
+
+int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_out) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!n_out) return fail(ctx, TMS_E_INVALID, "n_out is NULL");
+    *n_out = ctx->n_verts;
+    if (!out) return TMS_OK;
+    if (cap < ctx->n_verts) return fail(ctx, TMS_E_CAPACITY, "vertex capacity too small");
+    HIPCK(hipSetDevice(ctx->device));
+    if (ctx->n_verts > 0)
+        HIPCK(hipMemcpyAsync(out, ctx->verts.p, sizeof(tms_vertex) * (size_t)ctx->n_verts,
+                             hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return TMS_OK;
+}
+
+int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cubes, int64_t n,
+                         int32_t precision, double *A) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || n < 0 || (n > 0 && (!cubes || !A)) ||
+        (precision != TMS_PREC_FP64 && precision != TMS_PREC_FP32_GUARD))
+        return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_debug_tensor");
+    if (cells->p.mode != TMS_MODE_ADAPTIVE)
+        return fail(ctx, TMS_E_INVALID, "tensors need cells built in adaptive mode");
+    if (n == 0) return TMS_OK;
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const Grid &g = cells->g;
+    std::vector<int32_t> hc(4 * (size_t)n);
+    HIPCK(d2h(hc.data(), cubes, 4 * (size_t)n, s));
+    std::vector<int4> hq((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int lev = hc[4 * i];
+        if (lev < 0 || lev > g.K) return fail(ctx, TMS_E_INVALID, "cube level out of range");
+        for (int a = 0; a < 3; ++a) {
+            int v = hc[4 * i + 1 + a];
+            if (v < 0 || v >= (g.nr[a] << lev)) return fail(ctx, TMS_E_INVALID, "cube index out of range");
+        }
+        hq[(size_t)i] = make_int4(hc[4 * i + 1], hc[4 * i + 2], hc[4 * i + 3], 0);
+    }
+    HIPCK(ctx->q[0].ensure(sizeof(int4) * (size_t)n));
+    HIPCK(ctx->ebuf.ensure(sizeof(double) * (size_t)n));
+    HIPCK(ctx->idx.ensure(sizeof(int32_t) * (size_t)n));
+    HIPCK(hipMemcpyAsync(ctx->q[0].p, hq.data(), sizeof(int4) * (size_t)n, hipMemcpyHostToDevice, s));
+    for (int lev = 0; lev <= g.K; ++lev) {
+        std::vector<int32_t> sub;
+        for (int64_t i = 0; i < n; ++i)
+            if (hc[4 * i] == lev) sub.push_back((int32_t)i);
+        if (sub.empty()) continue;
+        HIPCK(hipMemcpyAsync(ctx->idx.p, sub.data(), sizeof(int32_t) * sub.size(),
+                             hipMemcpyHostToDevice, s));
+        HIPCK(launch_estimate(g, lev, precision, ctx->q[0].as<int4>(), (int64_t)sub.size(),
+                              ctx->idx.as<int32_t>(), cells->root_start.as<int32_t>(),
+                              cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
+                              cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
+                              A, ctx->ebuf.as<double>(), nullptr, s));
+        HIPCK(hipStreamSynchronize(s));
+    }
+    return TMS_OK;
+}
+
+int32_t tms_debug_bound(tms_ctx *ctx, const double *A, int64_t n, double *out) {
+    if (!ctx) return TMS_E_INVALID;
+    if (n < 0 || (n > 0 && (!A || !out))) return fail(ctx, TMS_E_INVALID, "invalid arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    HIPCK(launch_bound_debug(A, n, out, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return TMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,428 @@
+// Device-side building blocks of the partition/estimation kernels (gfx950).
+//
+// Notation follows Section 2.2 of Liu, Chen & Lu (arXiv:1611.03474): a cube's
+// polynomial is P(x,y,z) = sum_{jkl} A[j][k][l] L_j(x) L_k(y) L_l(z) in local
+// coordinates [-1,1]^3 (eq. tensor1), A = sum_i w_i a~x (x) a~y (x) a~z with
+// w_i = exp(D r_i^2) and a~ the endpoint-corrected degree-3 Legendre
+// projections of the one-dimensional Gaussian factors (eqs. poly2_1, poly3,
+// condition1, alpha).  Flat index of A: 16 j + 4 k + l.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "tms_internal.h"
+
+namespace tms {
+
+// ---------------------------------------------------------------------------
+// Exponentials.  Single precision uses the hardware base-2 exponential on a
+// pre-scaled argument; double precision uses the device math library.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float exp_neg(float a_log2e) {  // 2^(a)
+    return __builtin_amdgcn_exp2f(a_log2e);
+}
+
+template <typename T>
+struct Arith;
+
+template <>
+struct Arith<float> {
+    // exp(-D u^2) with Dl = D log2(e)
+    static __device__ __forceinline__ float gauss(float Dl, float u) {
+        return __builtin_amdgcn_exp2f(-Dl * u * u);
+    }
+    static __device__ __forceinline__ float gauss2(float Dl, float u2) {
+        return __builtin_amdgcn_exp2f(-Dl * u2);
+    }
+    static constexpr double kLogScale = 1.4426950408889634074;  // log2(e)
+};
+
+template <>
+struct Arith<double> {
+    static __device__ __forceinline__ double gauss(double D, double u) { return exp(-D * u * u); }
+    static __device__ __forceinline__ double gauss2(double D, double u2) { return exp(-D * u2); }
+    static constexpr double kLogScale = 1.0;
+};
+
+// ---------------------------------------------------------------------------
+// Endpoint-corrected degree-3 Legendre projection of f(t) = exp(-D (s t + d)^2)
+// on t in [-1,1] (x = m + s t, d = m - x_i).  a[0..3] receive the corrected
+// coefficients of eq. alpha.  QH is half the number of quadrature nodes.
+// ---------------------------------------------------------------------------
+template <typename T, int QH>
+__device__ __forceinline__ void project(const GLRule<T> &R, T Dk, T s, T d, T a[4]) {
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+        T fp = Arith<T>::gauss(Dk, s * R.t[q] + d);
+        T fm = Arith<T>::gauss(Dk, d - s * R.t[q]);
+        T ev = fp + fm, od = fp - fm;
+        a0 += R.c0[q] * ev;
+        a2 += R.c2[q] * ev;
+        a1 += R.c1[q] * od;
+        a3 += R.c3[q] * od;
+    }
+    // eq. condition1: match f at t = +-1 by adding e0 L2 + e1 L3
+    T f1 = Arith<T>::gauss(Dk, s + d);
+    T fm1 = Arith<T>::gauss(Dk, d - s);
+    T ep = f1 - (a0 + a1 + a2 + a3);
+    T em = fm1 - (a0 - a1 + a2 - a3);
+    a[0] = a0;
+    a[1] = a1;
+    a[2] = a2 + T(0.5) * (ep + em);
+    a[3] = a3 + T(0.5) * (ep - em);
+}
+
+// ---------------------------------------------------------------------------
+// Range of q0 L0 + q1 L1 + q2 L2 + q3 L3 on [-1,1]: extremes over the ends and
+// the interior critical points (roots of the derivative
+// (15/2) q3 t^2 + 3 q2 t + (q1 - 3/2 q3)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double leg3(const double q[4], double t) {
+    double t2 = t * t;
+    return q[0] + q[1] * t + q[2] * (1.5 * t2 - 0.5) + q[3] * t * (2.5 * t2 - 1.5);
+}
+
+__device__ __forceinline__ void leg3_range(const double q[4], double &lo, double &hi) {
+    double vp = q[0] + q[1] + q[2] + q[3];
+    double vm = q[0] - q[1] + q[2] - q[3];
+    lo = fmin(vp, vm);
+    hi = fmax(vp, vm);
+    double qa = 7.5 * q[3], qb = 3.0 * q[2], qc = q[1] - 1.5 * q[3];
+    double r0 = 2.0, r1 = 2.0;  // outside [-1,1] = absent
+    if (qa != 0.0) {
+        double disc = qb * qb - 4.0 * qa * qc;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double h = -0.5 * (qb + copysign(sq, qb));
+            if (h != 0.0) {
+                r0 = h / qa;
+                r1 = qc / h;
+            } else {
+                r0 = 0.0;
+            }
+        }
+    } else if (qb != 0.0) {
+        r0 = -qc / qb;
+    }
+    if (r0 >= -1.0 && r0 <= 1.0) {
+        double v = leg3(q, r0);
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    if (r1 >= -1.0 && r1 <= 1.0) {
+        double v = leg3(q, r1);
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+}
+
+__device__ __forceinline__ void imul(double a0, double a1, double b0, double b1, double &lo,
+                                     double &hi) {
+    double p0 = a0 * b0, p1 = a0 * b1, p2 = a1 * b0, p3 = a1 * b1;
+    lo = fmin(fmin(p0, p1), fmin(p2, p3));
+    hi = fmax(fmax(p0, p1), fmax(p2, p3));
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric 4x4 eigen-decomposition by cyclic Jacobi rotations.
+// S is overwritten (diagonal = eigenvalues); V receives eigenvectors as
+// columns; lam/vec are returned sorted by descending eigenvalue.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void jacobi_rot(double S[4][4], double V[4][4], int p, int q) {
+    double spq = S[p][q];
+    if (spq == 0.0) return;
+    double theta = (S[q][q] - S[p][p]) / (2.0 * spq);
+    double t;
+    if (fabs(theta) > 1e150)
+        t = 0.5 / theta;
+    else
+        t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double kp = S[k][p], kq = S[k][q];
+        S[k][p] = c * kp - s * kq;
+        S[k][q] = s * kp + c * kq;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double pk = S[p][k], qk = S[q][k];
+        S[p][k] = c * pk - s * qk;
+        S[q][k] = s * pk + c * qk;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double kp = V[k][p], kq = V[k][q];
+        V[k][p] = c * kp - s * kq;
+        V[k][q] = s * kp + c * kq;
+    }
+}
+
+__device__ __forceinline__ void eig4_sorted(double S[4][4], double lam[4], double V[4][4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) V[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[0][3] * S[0][3] +
+                     S[1][2] * S[1][2] + S[1][3] * S[1][3] + S[2][3] * S[2][3];
+        double dg = S[0][0] * S[0][0] + S[1][1] * S[1][1] + S[2][2] * S[2][2] + S[3][3] * S[3][3];
+        if (off <= 1e-34 * dg || off == 0.0) break;
+        jacobi_rot(S, V, 0, 1);
+        jacobi_rot(S, V, 0, 2);
+        jacobi_rot(S, V, 0, 3);
+        jacobi_rot(S, V, 1, 2);
+        jacobi_rot(S, V, 1, 3);
+        jacobi_rot(S, V, 2, 3);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lam[i] = S[i][i];
+    // sorting network on (lam, V columns), descending
+    auto cx = [&](int a, int b) {
+        if (lam[b] > lam[a]) {
+            double t = lam[a];
+            lam[a] = lam[b];
+            lam[b] = t;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double u = V[k][a];
+                V[k][a] = V[k][b];
+                V[k][b] = u;
+            }
+        }
+    };
+    cx(0, 1);
+    cx(2, 3);
+    cx(0, 2);
+    cx(1, 3);
+    cx(1, 2);
+}
+
+// smallest r with cum_r >= 0.99 total (eq. SVD3); 0 for an all-zero set.
+// *m_lo/*m_hi receive |cum_r - target| and |target - cum_{r-1}| (absolute).
+__device__ __forceinline__ int rank99(const double s[4], double &m_hi, double &m_lo) {
+    double tot = (s[0] + s[1]) + (s[2] + s[3]);
+    m_hi = 1e300;
+    m_lo = 1e300;
+    if (!(tot > 0.0)) return 0;
+    double target = 0.99 * tot, cum = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double prev = cum;
+        cum += s[i];
+        if (cum >= target) {
+            m_hi = cum - target;
+            if (i > 0) m_lo = target - prev;
+            return i + 1;
+        }
+    }
+    return 4;
+}
+
+struct BoundResult {
+    double L, U, rho;
+    int r;
+    bool unstable;  // a rank rule or singular gap lies within the guard band
+};
+
+// Nested-SVD bound of Section 2.2.2 (eqs. matrix1, SVD1-SVD7, Sxyz,
+// bound1-bound3) in double precision.  The 4 x 16 unfolding carries the
+// x-degree on its rows and (k,l) as 4k+l on its columns.  The singular
+// triplets come from the eigen-decomposition of the 4x4 Gram matrices
+// (A1 A1^T, then V_i V_i^T), sigma = sqrt(lambda), right vectors by
+// back-substitution.  band > 0 marks results whose discrete choices (ranks,
+// singular subspaces) could flip under an l1 perturbation of A of size band.
+__device__ inline BoundResult nested_bound(const double *A, double band) {
+    BoundResult R;
+    R.unstable = false;
+    double S[4][4], W[4][4], lam[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i; j < 4; ++j) {
+            double g = 0.0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) g += A[16 * i + e] * A[16 * j + e];
+            S[i][j] = g;
+            S[j][i] = g;
+        }
+    eig4_sorted(S, lam, W);
+    double sig[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sig[i] = sqrt(fmax(lam[i], 0.0));
+    double mhi, mlo;
+    int r = rank99(sig, mhi, mlo);
+    R.r = r;
+    const double kb = 4.0 * band;
+    if (band > 0.0) {
+        if (mhi <= kb || mlo <= kb) R.unstable = true;
+        for (int i = 0; i < r && i < 3; ++i)
+            if (sig[i] - sig[i + 1] <= kb + 1e-6 * sig[0]) R.unstable = true;
+    }
+    double At[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) At[e] = 0.0;
+    double Msum = 0.0, msum = 0.0;
+    for (int i = 0; i < r; ++i) {
+        double u[4] = {W[0][i], W[1][i], W[2][i], W[3][i]};
+        double inv = 1.0 / sig[i];
+        double v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            v[e] = (u[0] * A[e] + u[1] * A[16 + e] + u[2] * A[32 + e] + u[3] * A[48 + e]) * inv;
+        // V_i[k][l] = v[4k+l]; H = V_i V_i^T
+        double H[4][4], Z[4][4], mu[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int k2 = k; k2 < 4; ++k2) {
+                double g = v[4 * k] * v[4 * k2] + v[4 * k + 1] * v[4 * k2 + 1] +
+                           v[4 * k + 2] * v[4 * k2 + 2] + v[4 * k + 3] * v[4 * k2 + 3];
+                H[k][k2] = g;
+                H[k2][k] = g;
+            }
+        eig4_sorted(H, mu, Z);
+        double d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = sqrt(fmax(mu[k], 0.0));
+        double nhi, nlo;
+        int ri = rank99(d, nhi, nlo);
+        if (band > 0.0) {
+            double kbi = kb * inv;
+            if (nhi <= kbi || nlo <= kbi) R.unstable = true;
+            for (int k = 0; k < ri && k < 3; ++k)
+                if (d[k] - d[k + 1] <= kbi + 1e-6 * d[0]) R.unstable = true;
+        }
+        double ux0, ux1;
+        leg3_range(u, ux0, ux1);
+        double Myz = 0.0, myz = 0.0;
+        for (int k = 0; k < ri; ++k) {
+            double w[4] = {Z[0][k], Z[1][k], Z[2][k], Z[3][k]};
+            double iz = 1.0 / d[k];
+            double z[4];
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+                z[l] = (w[0] * v[l] + w[1] * v[4 + l] + w[2] * v[8 + l] + w[3] * v[12 + l]) * iz;
+            double coef = sig[i] * d[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    double cjk = coef * u[j] * w[kk];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) At[16 * j + 4 * kk + l] += cjk * z[l];
+                }
+            double w0, w1, z0, z1, p0, p1;
+            leg3_range(w, w0, w1);
+            leg3_range(z, z0, z1);
+            imul(w0, w1, z0, z1, p0, p1);
+            Myz += d[k] * p1;
+            myz += d[k] * p0;
+        }
+        double q0, q1;
+        imul(ux0, ux1, myz, Myz, q0, q1);
+        Msum += sig[i] * q1;
+        msum += sig[i] * q0;
+    }
+    double rho = 0.0;
+#pragma unroll
+    for (int e = 0; e < 64; ++e) rho += fabs(A[e] - At[e]);
+    R.rho = rho;
+    R.L = msum - rho;
+    R.U = Msum + rho;
+    return R;
+}
+
+// Values of P at the 8 corners of its cube and at the centre; returns the
+// range of those samples (a sub-range of P's range on the cube).
+__device__ __forceinline__ void sample_range(const double *A, double &lo, double &hi) {
+    // contract z with L(+-1) = (1, +-1, 1, +-1)
+    double Bp[16], Bm[16];
+#pragma unroll
+    for (int jk = 0; jk < 16; ++jk) {
+        double e = A[4 * jk] + A[4 * jk + 2], o = A[4 * jk + 1] + A[4 * jk + 3];
+        Bp[jk] = e + o;
+        Bm[jk] = e - o;
+    }
+    lo = 1e300;
+    hi = -1e300;
+#pragma unroll
+    for (int zz = 0; zz < 2; ++zz) {
+        const double *B = zz ? Bp : Bm;
+        double Cp[4], Cm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double e = B[4 * j] + B[4 * j + 2], o = B[4 * j + 1] + B[4 * j + 3];
+            Cp[j] = e + o;
+            Cm[j] = e - o;
+        }
+#pragma unroll
+        for (int yy = 0; yy < 2; ++yy) {
+            const double *Cq = yy ? Cp : Cm;
+            double e = Cq[0] + Cq[2], o = Cq[1] + Cq[3];
+            double v0 = e - o, v1 = e + o;
+            lo = fmin(lo, fmin(v0, v1));
+            hi = fmax(hi, fmax(v0, v1));
+        }
+    }
+    // centre: L(0) = (1, 0, -1/2, 0)
+    double ctr = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; j += 2)
+#pragma unroll
+        for (int k = 0; k < 4; k += 2)
+#pragma unroll
+            for (int l = 0; l < 4; l += 2) {
+                double f = ((j == 2) ? -0.5 : 1.0) * ((k == 2) ? -0.5 : 1.0) * ((l == 2) ? -0.5 : 1.0);
+                ctr += f * A[16 * j + 4 * k + l];
+            }
+    lo = fmin(lo, ctr);
+    hi = fmax(hi, ctr);
+}
+
+// ---------------------------------------------------------------------------
+// phi and grad phi at one point (eq. Gaussian1).
+// ---------------------------------------------------------------------------
+// Sum over atoms within R_c of p.  The pair predicate and the differences run
+// in double; the exponentials and sums in T.
+template <typename T>
+__device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
+                                       const int32_t *__restrict__ cs, const double *__restrict__ ax,
+                                       const double *__restrict__ ay, const double *__restrict__ az,
+                                       const double *__restrict__ aw, T &phi, T gr[3]) {
+    const T Dk = (T)(g.D * Arith<T>::kLogScale);
+    const T m2D = (T)(-2.0 * g.D);
+    phi = T(0);
+    gr[0] = gr[1] = gr[2] = T(0);
+    int c0[3], c1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // points far outside the grid (or NaN) get an empty stencil
+        const double fc = floor((p[a] - g.o[a]) / g.cs);
+        const int ci = (fc > -1.0e8 && fc < 1.0e8) ? (int)fc : -1000000;
+        c0[a] = max(ci - g.span, 0);
+        c1[a] = min(ci + g.span, g.nc[a] - 1);
+    }
+    for (int cz = c0[2]; cz <= c1[2]; ++cz)
+        for (int cy = c0[1]; cy <= c1[1]; ++cy) {
+            const int row = (cz * g.nc[1] + cy) * g.nc[0];
+            if (c0[0] > c1[0]) continue;
+            const int b = cs[row + c0[0]], e = cs[row + c1[0] + 1];
+            for (int i = b; i < e; ++i) {
+                const double dx = p[0] - ax[i], dy = p[1] - ay[i], dz = p[2] - az[i];
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 > g.rc2) continue;
+                const T term = (T)aw[i] * Arith<T>::gauss2(Dk, (T)d2);
+                phi += term;
+                const T f = m2D * term;
+                gr[0] += f * (T)dx;
+                gr[1] += f * (T)dy;
+                gr[2] += f * (T)dz;
+            }
+        }
+}
+
+}  // namespace tms

@@ -1,0 +1,203 @@
+// Internal declarations shared by the host orchestration and the HIP kernels
+// of the gfx950 partition/estimation library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tms.h"
+
+namespace tms {
+
+// ---------------------------------------------------------------------------
+// Grid description passed by value to kernels.
+// ---------------------------------------------------------------------------
+struct Grid {
+    double o[3];     // origin of the root grid (multiple of h0)
+    double h0;       // root cube edge
+    double hmin;     // finest cube edge
+    double D, c, tau;
+    double rc2;      // squared cut-off radius
+    double cs;       // atom-cell edge (h0 * 2^m >= R_c / 2)
+    int32_t nr[3];   // root cubes per axis
+    int32_t nc[3];   // atom cells per axis
+    int32_t K;       // finest level
+    int32_t span;    // cell stencil half-width (2)
+};
+
+// Gauss-Legendre rule folded for the even/odd parts of a function on [-1,1]:
+// with f+ = f(t_q) + f(-t_q), f- = f(t_q) - f(-t_q) for the positive nodes t_q,
+//   a0 = sum c0 f+,  a1 = sum c1 f-,  a2 = sum c2 f+,  a3 = sum c3 f-
+// gives the four Legendre projection coefficients (2j+1)/2 int f L_j.
+template <typename T>
+struct GLRule {
+    T t[8], c0[8], c1[8], c2[8], c3[8];
+};
+
+// Number of positive nodes (half the rule) used on a level whose cubes have
+// half-width s: chosen from beta = s sqrt(D) so that the quadrature error of
+// the projection stays below the arithmetic's own rounding.
+int gl_half_nodes(double beta, bool fp32);
+template <typename T>
+GLRule<T> gl_rule(int half);
+
+// Decision codes of the per-cube state machine.
+enum : uint8_t {
+    DEC_DISCARD = 0,
+    DEC_REFINE = 1,
+    DEC_CONV = 2,   // converged leaf
+    DEC_HMIN = 3,   // kept at the finest level
+    DEC_GUARD = 4,  // single-precision margin too small: redo in double
+};
+
+// ---------------------------------------------------------------------------
+// Device buffer that only grows.
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes);
+    void release();
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace tms
+
+// ---------------------------------------------------------------------------
+// Public opaque types.
+// ---------------------------------------------------------------------------
+struct tms_cells {
+    tms::Grid g{};
+    tms_params p{};
+    int64_t n = 0;               // atoms
+    int64_t nroots = 0;          // root cubes (nr[0]*nr[1]*nr[2])
+    int64_t ncells = 0;
+    int64_t n_root_entries = 0;  // sum of root neighbourhood sizes
+    int64_t n_nonempty = 0;      // roots with a non-empty neighbourhood
+    double rmax = 0;
+    // device memory, atoms sorted by cell (ascending original index inside a cell)
+    tms::DevBuf ax, ay, az, aw, aidx, ar;   // double x3, w = exp(D r^2), int32 index, r
+    tms::DevBuf cell_start;                 // int32 [ncells + 1]
+    tms::DevBuf root_start;                 // int32 [nroots + 1]
+    tms::DevBuf root_atoms;                 // int32 [n_root_entries]
+    tms::DevBuf tmp_key, tmp_cnt;           // scratch for binning
+    void release();
+};
+
+struct tms_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<tms_cells *> cells;
+    // last partition result
+    tms::DevBuf leaves, corner_phi;
+    int64_t n_leaves = 0;
+    // last extract result
+    tms::DevBuf verts;
+    int64_t n_verts = 0;
+    // workspace (grow-only)
+    tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
+        slot, uniq, uphi, uguard, lc, ctmp;
+    tms::DevBuf counters;  // small device counters
+    tms::DevBuf hostpin;   // unused
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+namespace tms {
+
+// k_cells.hip
+hipError_t launch_atom_stats(const double *xyzr, int64_t n, double *out8, hipStream_t s);
+hipError_t launch_bin_atoms(const Grid &g, const double *xyzr, int64_t n, int32_t *key,
+                            int32_t *cnt, int64_t ncells, hipStream_t s);
+hipError_t launch_scatter_atoms(const Grid &g, const double *xyzr, int64_t n, const int32_t *key,
+                                int32_t *fill, double *ax, double *ay, double *az, double *aw,
+                                double *ar, int32_t *aidx, hipStream_t s);
+hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *ax, double *ay,
+                             double *az, double *aw, double *ar, int32_t *aidx, hipStream_t s);
+hipError_t launch_root_count(const Grid &g, const int32_t *cell_start, const double *ax,
+                             const double *ay, const double *az, int64_t nroots, int32_t *cnt,
+                             hipStream_t s);
+hipError_t launch_root_fill(const Grid &g, const int32_t *cell_start, const double *ax,
+                            const double *ay, const double *az, int64_t nroots,
+                            const int32_t *start, int32_t *atoms, hipStream_t s);
+
+// k_scan.hip -- exclusive scan of int32 values into int32 offsets; total
+// written to *total_dev (device).  tmp must hold scan_tmp_bytes(n).
+size_t scan_tmp_bytes(int64_t n);
+hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev,
+                          void *tmp, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+// k_partition.hip
+hipError_t launch_roots_flags(const int32_t *root_start, int64_t nroots, int32_t *flags,
+                              hipStream_t s);
+hipError_t launch_roots_emit(const Grid &g, const int32_t *flags, const int32_t *off,
+                             int64_t nroots, int4 *q, hipStream_t s);
+hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+                           const int32_t *subset, const int32_t *root_start,
+                           const int32_t *root_atoms, const double *ax, const double *ay,
+                           const double *az, const double *aw, double *A, double *E,
+                           int64_t *pairs, hipStream_t s);
+hipError_t launch_decide(const Grid &g, int level, int precision, const double *A,
+                         const double *E, int64_t n, const int32_t *subset, uint8_t *dec,
+                         int32_t *nbound, hipStream_t s);
+hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s);
+hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
+                                  int32_t *list, hipStream_t s);
+hipError_t launch_level_counts(const uint8_t *dec, int64_t n, int32_t *leaf_cnt,
+                               int32_t *child_cnt, hipStream_t s);
+hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int level,
+                             const int32_t *leaf_off, const int32_t *child_off, tms_leaf *leaves,
+                             int64_t leaf_base, int4 *qnext, hipStream_t s);
+hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
+                              hipStream_t s);
+hipError_t launch_bound_debug(const double *A, int64_t n, double *out, hipStream_t s);
+
+// k_phi.hip
+hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
+                             const int32_t *cell_start, const double *ax, const double *ay,
+                             const double *az, const double *aw, double *phi, double *grad,
+                             uint8_t *guard, hipStream_t s);
+hipError_t launch_phi_points_subset(const Grid &g, const double *pts, const int32_t *list,
+                                    int64_t m, const int32_t *cell_start, const double *ax,
+                                    const double *ay, const double *az, const double *aw,
+                                    double *phi, double *grad, hipStream_t s);
+hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
+                                uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
+hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_t ncand,
+                              int32_t *flags, hipStream_t s);
+hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid &g,
+                                const int32_t *flags, const int32_t *off, const uint32_t *slot,
+                                double *upts, uint32_t *slot2u, hipStream_t s);
+hipError_t launch_corner_gather(const tms_leaf *leaves_in, int64_t n, const uint32_t *slot,
+                                const uint32_t *slot2u, const double *uphi, double c,
+                                tms_leaf *leaves_out, double *corner_phi, hipStream_t s);
+hipError_t launch_uniform_leaves(const Grid &g, tms_leaf *leaves, int64_t n, hipStream_t s);
+hipError_t launch_uniform_points(const Grid &g, double *pts, int64_t m, hipStream_t s);
+hipError_t launch_uniform_gather(const Grid &g, const double *uphi, double c, tms_leaf *leaves,
+                                 int64_t n, double *corner_phi, hipStream_t s);
+hipError_t launch_count_u8(const uint8_t *v, int64_t n, uint8_t value,
+                           unsigned long long *count, hipStream_t s);
+hipError_t launch_guard_flags_u8(const uint8_t *g, int64_t n, int32_t *flags, hipStream_t s);
+hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
+                            hipStream_t s);
+hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
+                                hipStream_t s);
+
+// k_extract.hip
+hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
+                              uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
+hipError_t launch_edge_emit(const Grid &g, int precision, const tms_leaf *leaves,
+                            const double *corner_phi, int64_t ncand, const int32_t *flags,
+                            const int32_t *off, const int32_t *cs, const double *ax,
+                            const double *ay, const double *az, const double *aw,
+                            tms_vertex *out, hipStream_t s);
+
+}  // namespace tms

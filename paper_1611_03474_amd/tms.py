@@ -1,0 +1,308 @@
+"""Thin ctypes binding over ``libtms.so`` (the C ABI of ``include/tms.h``).
+
+Only argument marshalling lives here: every step of the computation runs in
+the library's HIP kernels.  PyTorch supplies device memory and the stream.
+Importing this module does not touch the GPU; the first ``Context`` loads the
+library and raises ``RuntimeError`` if it is missing (no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtms.so")
+
+TMS_OK, TMS_E_INVALID, TMS_E_CAPACITY, TMS_E_DEVICE, TMS_E_OOM = 0, -1, -2, -3, -4
+PREC_FP64, PREC_FP32_GUARD = 0, 1
+MODE_ADAPTIVE, MODE_UNIFORM = 0, 1
+REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN = 0, 1, 2
+CLS_OUTSIDE, CLS_SURFACE, CLS_INSIDE = 0, 1, 2
+MAX_LEVELS = 8
+
+LEAF_DTYPE = np.dtype([("ix", "<i4"), ("iy", "<i4"), ("iz", "<i4"), ("conf", "<i4"),
+                       ("level", "u1"), ("reason", "u1"), ("mask", "u1"), ("cls", "u1")])
+VERTEX_DTYPE = np.dtype([("edge_key", "<u8"), ("t", "<f8"), ("x", "<f8"), ("y", "<f8"),
+                         ("z", "<f8")])
+assert LEAF_DTYPE.itemsize == 20 and VERTEX_DTYPE.itemsize == 40
+
+
+class TmsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("tms error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("D", C.c_double), ("c", C.c_double), ("tau", C.c_double), ("h0", C.c_double),
+                ("h_min", C.c_double), ("pad", C.c_double), ("eps_cut", C.c_double),
+                ("precision", C.c_int32), ("mode", C.c_int32)]
+
+
+_I64L = C.c_int64 * MAX_LEVELS
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_est", _I64L), ("n_disc", _I64L), ("n_refine", _I64L), ("n_conv", _I64L),
+                ("n_hmin", _I64L), ("n_leaves", C.c_int64), ("n_surface", C.c_int64),
+                ("n_corners", C.c_int64), ("n_bound", C.c_int64), ("guard_cubes", C.c_int64),
+                ("guard_points", C.c_int64), ("n_pairs", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if isinstance(v, C.Array) else int(v)
+        d["cubes_estimated"] = int(sum(self.n_est))
+        return d
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtms.so; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libtms.so not found at %s: build it with "
+                           "`python -m paper_1611_03474_amd.build`" % path)
+    L = C.CDLL(path)
+    i32, i64, dp = C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.tms_create.argtypes = [C.POINTER(_VP), i32, _VP]
+    L.tms_destroy.argtypes = [_VP]
+    L.tms_last_error.argtypes = [_VP]
+    L.tms_last_error.restype = C.c_char_p
+    L.tms_check_params.argtypes = [C.POINTER(Params), C.c_char_p, i64]
+    L.tms_check_atoms_host.argtypes = [dp, i64, C.POINTER(Params), C.c_char_p, i64]
+    L.tms_build_cells.argtypes = [_VP, _VP, i64, C.POINTER(Params), C.POINTER(_VP)]
+    L.tms_cells_info.argtypes = [_VP, dp, C.POINTER(i64), C.POINTER(i32), dp, C.POINTER(i64)]
+    L.tms_free_cells.argtypes = [_VP, _VP]
+    L.tms_eval_phi.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, C.POINTER(i64)]
+    L.tms_partition_estimate.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64), _VP,
+                                         C.POINTER(Stats)]
+    L.tms_get_leaves.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
+    L.tms_extract_cube_vertices.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(i64)]
+    L.tms_get_vertices.argtypes = [_VP, _VP, i64, C.POINTER(i64)]
+    L.tms_debug_tensor.argtypes = [_VP, _VP, _VP, i64, i32, _VP]
+    L.tms_debug_bound.argtypes = [_VP, _VP, i64, _VP]
+    for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
+              "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
+              "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
+              "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+def make_params(D=0.9, c=1.0, tau=1e-3, h0=2.0, h_min=0.25, pad=3.0, eps_cut=1e-10,
+                precision=PREC_FP64, mode=MODE_ADAPTIVE) -> Params:
+    return Params(D=float(D), c=float(c), tau=float(tau), h0=float(h0), h_min=float(h_min),
+                  pad=float(pad), eps_cut=float(eps_cut), precision=int(precision),
+                  mode=int(mode))
+
+
+def check_params(p: Params):
+    buf = C.create_string_buffer(256)
+    rc = load_library().tms_check_params(C.byref(p), buf, 256)
+    return rc, buf.value.decode()
+
+
+def check_atoms_host(xyzr: np.ndarray, p: Params):
+    a = np.ascontiguousarray(xyzr, dtype=np.float64).reshape(-1, 4)
+    buf = C.create_string_buffer(256)
+    rc = load_library().tms_check_atoms_host(a.ctypes.data_as(C.POINTER(C.c_double)),
+                                             a.shape[0], C.byref(p), buf, 256)
+    return rc, buf.value.decode()
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class Cells:
+    handle: C.c_void_p
+    params: Params
+    n_atoms: int
+    origin: np.ndarray
+    dims: np.ndarray
+    K: int
+    rc2: float
+
+
+class Context:
+    """A library context on one device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = _VP()
+        rc = self.lib.tms_create(C.byref(h), int(device), _VP(stream.cuda_stream))
+        if rc != TMS_OK:
+            raise TmsError(rc, self.lib.tms_last_error(None).decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tms_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != TMS_OK:
+            raise TmsError(rc, self.lib.tms_last_error(self.h).decode())
+
+    # ---------------------------------------------------------------- cells
+    def build_cells(self, xyzr, params: Params, cells: Cells | None = None) -> Cells:
+        t = self._torch
+        a = xyzr if isinstance(xyzr, t.Tensor) else t.as_tensor(np.asarray(xyzr))
+        a = a.to(device=self.device, dtype=t.float64).contiguous()
+        assert a.dim() == 2 and a.shape[1] == 4
+        h = cells.handle if cells is not None else _VP()
+        self._check(self.lib.tms_build_cells(self.h, _VP(_ptr(a)), a.shape[0], C.byref(params),
+                                             C.byref(h)))
+        o = (C.c_double * 3)()
+        d = (C.c_int64 * 3)()
+        K = C.c_int32()
+        rc2 = C.c_double()
+        na = C.c_int64()
+        self.lib.tms_cells_info(h, o, d, C.byref(K), C.byref(rc2), C.byref(na))
+        return Cells(h, params, int(na.value), np.array(o[:]), np.array(d[:]), int(K.value),
+                     float(rc2.value))
+
+    def free_cells(self, cells: Cells):
+        self._check(self.lib.tms_free_cells(self.h, cells.handle))
+
+    # ------------------------------------------------------------------ phi
+    def eval_phi(self, cells: Cells, pts, grad: bool = False):
+        t = self._torch
+        p = pts if isinstance(pts, t.Tensor) else t.as_tensor(np.asarray(pts))
+        p = p.to(device=self.device, dtype=t.float64).contiguous()
+        m = p.shape[0]
+        phi = t.empty(m, dtype=t.float64, device=self.device)
+        g = t.empty((m, 3), dtype=t.float64, device=self.device) if grad else None
+        ng = C.c_int64()
+        self._check(self.lib.tms_eval_phi(self.h, cells.handle, _VP(_ptr(p)), m, _VP(_ptr(phi)),
+                                          _VP(_ptr(g)), C.byref(ng)))
+        return phi, g, int(ng.value)
+
+    # ------------------------------------------------------------ partition
+    def partition_estimate(self, cells: Cells, cap: int | None = None):
+        """Returns (leaves uint8 tensor [L, 20], corner_phi [L, 8], stats dict)."""
+        t = self._torch
+        st = Stats()
+        n = C.c_int64()
+        if cap is None:
+            self._check(self.lib.tms_partition_estimate(self.h, cells.handle, None, 0,
+                                                         C.byref(n), None, C.byref(st)))
+            cap = n.value
+            leaves = t.empty((max(cap, 1), 20), dtype=t.uint8, device=self.device)
+            cphi = t.empty((max(cap, 1), 8), dtype=t.float64, device=self.device)
+            self._check(self.lib.tms_get_leaves(self.h, _VP(_ptr(leaves)), _VP(_ptr(cphi)), cap,
+                                                C.byref(n)))
+        else:
+            leaves = t.empty((max(cap, 1), 20), dtype=t.uint8, device=self.device)
+            cphi = t.empty((max(cap, 1), 8), dtype=t.float64, device=self.device)
+            rc = self.lib.tms_partition_estimate(self.h, cells.handle, _VP(_ptr(leaves)), cap,
+                                                 C.byref(n), _VP(_ptr(cphi)), C.byref(st))
+            if rc == TMS_E_CAPACITY:
+                cap = n.value
+                leaves = t.empty((max(cap, 1), 20), dtype=t.uint8, device=self.device)
+                cphi = t.empty((max(cap, 1), 8), dtype=t.float64, device=self.device)
+                rc = self.lib.tms_get_leaves(self.h, _VP(_ptr(leaves)), _VP(_ptr(cphi)), cap,
+                                             C.byref(n))
+            self._check(rc)
+        L = n.value
+        return leaves[:L], cphi[:L], st.as_dict()
+
+    def partition_into(self, cells: Cells, leaves, cphi):
+        """Partition into preallocated buffers; returns (L, stats) or raises
+        TmsError(TMS_E_CAPACITY) with the required size in .required."""
+        st = Stats()
+        n = C.c_int64()
+        rc = self.lib.tms_partition_estimate(self.h, cells.handle, _VP(_ptr(leaves)),
+                                             leaves.shape[0], C.byref(n), _VP(_ptr(cphi)),
+                                             C.byref(st))
+        if rc == TMS_E_CAPACITY:
+            e = TmsError(rc, self.lib.tms_last_error(self.h).decode())
+            e.required = n.value
+            raise e
+        self._check(rc)
+        return n.value, st
+
+    def extract(self, cells: Cells, leaves, corner_phi=None, cap: int | None = None):
+        """Returns vertex uint8 tensor [V, 40]."""
+        t = self._torch
+        n = C.c_int64()
+        nl = leaves.shape[0]
+        if cap is None:
+            self._check(self.lib.tms_extract_cube_vertices(
+                self.h, cells.handle, _VP(_ptr(leaves)), nl, _VP(_ptr(corner_phi)), None, 0,
+                C.byref(n)))
+            cap = n.value
+            out = t.empty((max(cap, 1), 40), dtype=t.uint8, device=self.device)
+            self._check(self.lib.tms_get_vertices(self.h, _VP(_ptr(out)), cap, C.byref(n)))
+        else:
+            out = t.empty((max(cap, 1), 40), dtype=t.uint8, device=self.device)
+            rc = self.lib.tms_extract_cube_vertices(self.h, cells.handle, _VP(_ptr(leaves)), nl,
+                                                    _VP(_ptr(corner_phi)), _VP(_ptr(out)), cap,
+                                                    C.byref(n))
+            if rc == TMS_E_CAPACITY:
+                cap = n.value
+                out = t.empty((max(cap, 1), 40), dtype=t.uint8, device=self.device)
+                rc = self.lib.tms_get_vertices(self.h, _VP(_ptr(out)), cap, C.byref(n))
+            self._check(rc)
+        return out[:n.value]
+
+    def extract_into(self, cells: Cells, leaves, nl: int, corner_phi, out):
+        n = C.c_int64()
+        rc = self.lib.tms_extract_cube_vertices(self.h, cells.handle, _VP(_ptr(leaves)), nl,
+                                                _VP(_ptr(corner_phi)), _VP(_ptr(out)),
+                                                out.shape[0], C.byref(n))
+        if rc == TMS_E_CAPACITY:
+            e = TmsError(rc, self.lib.tms_last_error(self.h).decode())
+            e.required = n.value
+            raise e
+        self._check(rc)
+        return n.value
+
+    # ----------------------------------------------------------------- debug
+    def debug_tensor(self, cells: Cells, cubes, precision=PREC_FP64):
+        t = self._torch
+        cb = t.as_tensor(np.asarray(cubes, dtype=np.int32)).to(self.device).contiguous()
+        A = t.zeros((cb.shape[0], 64), dtype=t.float64, device=self.device)
+        self._check(self.lib.tms_debug_tensor(self.h, cells.handle, _VP(_ptr(cb)), cb.shape[0],
+                                              int(precision), _VP(_ptr(A))))
+        return A
+
+    def debug_bound(self, A):
+        t = self._torch
+        a = t.as_tensor(np.asarray(A, dtype=np.float64)).reshape(-1, 64).to(self.device)
+        a = a.contiguous()
+        out = t.zeros((a.shape[0], 4), dtype=t.float64, device=self.device)
+        self._check(self.lib.tms_debug_bound(self.h, _VP(_ptr(a)), a.shape[0], _VP(_ptr(out))))
+        return out
+
+
+def leaves_to_numpy(leaves) -> np.ndarray:
+    return leaves.cpu().numpy().reshape(-1).view(LEAF_DTYPE)
+
+
+def vertices_to_numpy(verts) -> np.ndarray:
+    return verts.cpu().numpy().reshape(-1).view(VERTEX_DTYPE)
