@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of the partition/estimation hot path on one MI355X.
+
+One step = one whole pass over a 110,000-atom synthetic assembly already
+resident in HBM: atom binning and neighbourhood lists, the adaptive partition
+and estimation (Section 2.2, Steps 1-3, h0 = 2 -> h_min = 0.25, tau = 1e-3,
+D = 0.9, c = 1), corner classification, and the edge intersection points.
+
+Printed: one JSON line.  ``value`` is cubes estimated per second (cubes
+whose coefficient tensor was computed, summed over levels, divided by the
+step time) for the FP32+guard path; the FP64 path, phi evaluations per
+second, the dominant kernel's roofline position and the FP64 CPU oracle's
+rate on a bounded sample ride along in the same line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+# MI355X published peaks (per GPU)
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# algorithmic work per unit ("Measurement")
+FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
+FLOP_PER_PHI_PAIR = 14   # phi + grad per in-range (point, atom) pair, excl. exp
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
+    import torch
+    p = w.params(precision)
+    cells = ctx.build_cells(atoms_dev, p)
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    cap_l = int(len(leaves) * 1.05) + 1024
+    cap_v = int(len(verts) * 1.05) + 1024
+    lb = torch.empty((cap_l, 20), dtype=torch.uint8, device=ctx.device)
+    cb = torch.empty((cap_l, 8), dtype=torch.float64, device=ctx.device)
+    vb = torch.empty((cap_v, 40), dtype=torch.uint8, device=ctx.device)
+
+    def step():
+        ctx.build_cells(atoms_dev, p, cells)
+        nl, s = ctx.partition_into(cells, lb, cb)
+        nv = ctx.extract_into(cells, lb, nl, cb, vb)
+        return nl, nv, s
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.get_timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        nl, nv, s = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = ctx.get_timing(reset=True)
+    ctx.set_timing(False)
+    sd = s.as_dict()
+    ctx.free_cells(cells)
+    ms = (t1 - t0) * 1e3 / steps
+    per_step = {k: {"ms": v["ms"] / steps, "launches": v["launches"] / steps}
+                for k, v in tm.items()}
+    return dict(ms_per_step=ms, stats=sd, n_leaves=nl, n_vertices=nv, timing=per_step)
+
+
+def cpu_baseline(atoms, w):
+    """FP64 oracle on a bounded sample: the first globule of the assembly and
+    its hydrogens (about 1/20 of the workload)."""
+    import numpy as np
+    import oracle
+    heavy = atoms[:5000]
+    cen = heavy[:, :3].mean(axis=0)
+    rho = np.max(np.linalg.norm(heavy[:, :3] - cen, axis=1))
+    sel = np.linalg.norm(atoms[:, :3] - cen, axis=1) <= rho + 1.05
+    sample = atoms[sel]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    r = oracle.partition(sample, w.D, c=w.c, tau=w.tau, h0=w.h0, h_min=w.h_min, pad=w.pad,
+                         eps_cut=w.eps_cut, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": r.cubes_estimated / dt, "unit": "cubes/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "globule 0 of the assembly with its hydrogens (%d atoms, %d cubes "
+                      "estimated, %.1f s wall)" % (len(sample), r.cubes_estimated, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="assembly110k")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1611_03474_amd import tms, workloads
+
+    w = workloads.ALL[args.workload]
+    log("generating workload", w.name)
+    t0 = time.perf_counter()
+    atoms = workloads.atoms(w)
+    log("  %d atoms in %.1f s" % (len(atoms), time.perf_counter() - t0))
+    atoms_dev = torch.as_tensor(atoms, dtype=torch.float64, device="cuda:0").contiguous()
+    ctx = tms.Context(0)
+
+    log("FP32+guard run")
+    f32 = run_mode(ctx, tms, atoms_dev, w, tms.PREC_FP32_GUARD, args.steps, args.warmup)
+    log("  %.2f ms/step" % f32["ms_per_step"])
+    f64 = None
+    if not args.no_fp64:
+        log("FP64 run")
+        f64 = run_mode(ctx, tms, atoms_dev, w, tms.PREC_FP64, args.steps, args.warmup)
+        log("  %.2f ms/step" % f64["ms_per_step"])
+
+    def rates(r):
+        st = r["stats"]
+        return {"cubes_per_s": st["cubes_estimated"] / (r["ms_per_step"] * 1e-3),
+                "phi_evals_per_s": st["n_corners"] / (r["timing"]["phi"]["ms"] * 1e-3)
+                if r["timing"]["phi"]["ms"] > 0 else None}
+
+    r32 = rates(f32)
+    st = f32["stats"]
+    # dominant kernel by device time
+    tm = f32["timing"]
+    dom = max(("estimate", "decide", "phi"), key=lambda k: tm[k]["ms"])
+    if dom == "estimate":
+        work = st["n_pairs"] * FLOP_PER_PAIR
+        peak = PEAK_FP32_TFLOPS
+    elif dom == "phi":
+        work = None
+        peak = PEAK_FP32_TFLOPS
+    else:
+        work = None
+        peak = PEAK_FP64_TFLOPS
+    achieved = (work / (tm[dom]["ms"] * 1e-3) / 1e12) if work else None
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
+                "traffic": None}
+
+    out = {
+        "metric": "cubes estimated/sec and phi evals/sec at 100k atoms, FP32+guard vs FP64",
+        "value": r32["cubes_per_s"],
+        "unit": "cubes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "description": w.description, "atoms": int(len(atoms)),
+                   "D": w.D, "c": w.c, "tau": w.tau, "h0": w.h0, "h_min": w.h_min,
+                   "precision": "fp32+fp64 guard"},
+        "phi_evals_per_s": r32["phi_evals_per_s"],
+        "cubes_estimated": st["cubes_estimated"],
+        "per_level_estimated": st["n_est"][:4],
+        "leaves": f32["n_leaves"], "surface_leaves": st["n_surface"],
+        "unique_corners": st["n_corners"], "vertices": f32["n_vertices"],
+        "pairs": st["n_pairs"], "bound_cubes": st["n_bound"],
+        "guard_cubes": st["guard_cubes"], "guard_points": st["guard_points"],
+        "guard_cube_fraction": st["guard_cubes"] / max(1, st["cubes_estimated"]),
+        "device_ms_per_step": {k: round(v["ms"], 4) for k, v in tm.items()},
+        "roofline": roofline,
+    }
+    if f64 is not None:
+        r64 = rates(f64)
+        out["fp64"] = {"value": r64["cubes_per_s"], "ms_per_step": f64["ms_per_step"],
+                       "phi_evals_per_s": r64["phi_evals_per_s"],
+                       "device_ms_per_step": {k: round(v["ms"], 4)
+                                              for k, v in f64["timing"].items()},
+                       "same_leaf_count": f64["n_leaves"] == f32["n_leaves"]}
+        out["speedup_fp32guard_vs_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(atoms, w)
+        log("  %s" % out["cpu_baseline"])
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -217,19 +217,60 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
 
 int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_out);
 
+/* ---- device-time instrumentation ----------------------------------------
+ * When enabled, the library brackets its kernel launches with HIP events on
+ * the context's stream and accumulates the elapsed device time per phase
+ * (TMS_T_* slots).  Off by default; costs two event records per launch. */
+#define TMS_T_BUILD 0    /* binning and neighbourhood lists           */
+#define TMS_T_ESTIMATE 1 /* tensor estimate kernels (all levels)       */
+#define TMS_T_DECIDE 2   /* decision / nested-SVD bound kernels        */
+#define TMS_T_GUARD 3    /* double-precision recomputation of guards   */
+#define TMS_T_COMPACT 4  /* scans, queue and leaf compaction           */
+#define TMS_T_CORNER 5   /* corner de-duplication and gathering        */
+#define TMS_T_PHI 6      /* phi kernels (corner values, tms_eval_phi)   */
+#define TMS_T_EXTRACT 7  /* edge de-duplication and vertex emission    */
+#define TMS_T_SLOTS 8
+
+typedef struct {
+    double ms[TMS_T_SLOTS];       /* accumulated device milliseconds */
+    int64_t launches[TMS_T_SLOTS];/* kernel launches timed           */
+} tms_timing;
+
+/* Enable (1) or disable (0) per-phase device timing on ctx. */
+int32_t tms_set_timing(tms_ctx *ctx, int32_t enable);
+
+/* Copy the accumulated timings into *out (host); reset them if reset != 0. */
+int32_t tms_get_timing(tms_ctx *ctx, tms_timing *out, int32_t reset);
+
 /* Debug: the coefficient tensor A (eqs. polynew, tensor1, tensor2) of given
  * cubes, computed by the same kernels as the partition pass.
  *  cubes  device [n][4] int32 (level, ix, iy, iz);  A device [n][64] double,
  *  A[16 j + 4 k + l], j/k/l the x/y/z Legendre degrees.
+ *  S      device [n] double or NULL: the l1 scale sum_i w_i |a~x|_1 |a~y|_1
+ *         |a~z|_1 that sizes the single-precision error band.
  *  precision TMS_PREC_* (FP32 results are widened to double). */
 int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cubes, int64_t n,
-                         int32_t precision, double *A);
+                         int32_t precision, double *A, double *S);
 
 /* Debug: the nested-SVD bound (Section 2.2.2, eqs. SVD1-SVD7, Sxyz,
  * bound1-bound3) of given tensors.
- *  A   device [n][64] double;  out device [n][4] double: L, U, rho (l1 mass
- *  of the residual tensor), r (outer rank kept by the 0.99 rule). */
-int32_t tms_debug_bound(tms_ctx *ctx, const double *A, int64_t n, double *out);
+ *  A     device [n][64] double;
+ *  band  device [n] double or NULL (zeros): l1 perturbation size for the
+ *        stability flag;
+ *  out   device [n][6] double: L, U, rho (l1 mass of the residual tensor),
+ *        r (outer rank kept by the 0.99 rule), jump (1 if a 0.99 rank rule
+ *        lies within the perturbation band, else 0), amp (first-order factor
+ *        by which an l1 perturbation of A of size band can move L and U). */
+int32_t tms_debug_bound(tms_ctx *ctx, const double *A, const double *band, int64_t n,
+                        double *out);
+
+/* Debug: the exponential used by TMS_PREC_FP32_GUARD, y[i] = exp(x[i]) for
+ * x[i] <= 0, computed as 2^n 2^f with n, f split in double precision and 2^f
+ * from the single-precision hardware exponential.  Its relative error is
+ * bounded by 1.5e-7 (one unit in the last place of the single-precision
+ * result plus the rounding of f); the guard band of the FP32+guard path
+ * rests on that bound.  x, y device [n] double. */
+int32_t tms_debug_fast_exp(tms_ctx *ctx, const double *x, int64_t n, double *y);
 
 #ifdef __cplusplus
 }

@@ -74,38 +74,22 @@ __global__ void k_edge_insert(const tms_leaf *__restrict__ leaves, int64_t n, in
     atomicMin(&hown[s], (uint32_t)c);
 }
 
-// With single-precision corner values (relative error below kPhiErr32), the
-// root t = (c - phi0)/(phi1 - phi0) carries an error up to
-// kPhiErr32 (phi0 + phi1) / |phi1 - phi0|; edges where that could exceed
-// kTErr get both corner values again in double precision.
-constexpr double kPhiErr32 = 1.0e-6;
-constexpr double kTErr = 5.0e-6;
-
-__global__ void k_edge_emit(Grid g, int precision, const tms_leaf *__restrict__ leaves,
+__global__ void k_edge_emit(Grid g, const tms_leaf *__restrict__ leaves,
                             const double *__restrict__ cphi, int64_t ncand,
                             const int32_t *__restrict__ f, const int32_t *__restrict__ off_,
-                            const int32_t *__restrict__ cs, const double *__restrict__ ax,
-                            const double *__restrict__ ay, const double *__restrict__ az,
-                            const double *__restrict__ aw, tms_vertex *__restrict__ out) {
+                            tms_vertex *__restrict__ out) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (c >= ncand || !f[c]) return;
     const int64_t q = c / 12;
     const tms_leaf L = leaves[q];
     int axis, off[3], v0, v1;
     edge_corners((int)(c % 12), axis, off, v0, v1);
-    double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
+    const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
     const int sh = g.K - L.level;
     const double h = ldexp(g.h0, -(int)L.level);
     double p[3] = {g.o[0] + (double)((L.ix + off[0]) << sh) * g.hmin,
                    g.o[1] + (double)((L.iy + off[1]) << sh) * g.hmin,
                    g.o[2] + (double)((L.iz + off[2]) << sh) * g.hmin};
-    if (precision == TMS_PREC_FP32_GUARD &&
-        kPhiErr32 * (fabs(f0) + fabs(f1)) > kTErr * fabs(f1 - f0)) {
-        double gr[3], q1[3] = {p[0], p[1], p[2]};
-        q1[axis] = g.o[axis] + (double)(((axis == 0 ? L.ix : axis == 1 ? L.iy : L.iz) + 1) << sh) * g.hmin;
-        phi_at<double>(g, p, cs, ax, ay, az, aw, f0, gr);
-        phi_at<double>(g, q1, cs, ax, ay, az, aw, f1, gr);
-    }
     const double t = (g.c - f0) / (f1 - f0);
     p[axis] += t * h;
     tms_vertex V;
@@ -152,14 +136,12 @@ hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t
     return hipGetLastError();
 }
 
-hipError_t launch_edge_emit(const Grid &g, int precision, const tms_leaf *leaves,
-                            const double *corner_phi, int64_t ncand, const int32_t *flags,
-                            const int32_t *off, const int32_t *cs, const double *ax,
-                            const double *ay, const double *az, const double *aw,
+hipError_t launch_edge_emit(const Grid &g, const tms_leaf *leaves, const double *corner_phi,
+                            int64_t ncand, const int32_t *flags, const int32_t *off,
                             tms_vertex *out, hipStream_t s) {
     if (ncand <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_emit, dim3(nblk(ncand)), dim3(kBS), 0, s, g, precision, leaves,
-                       corner_phi, ncand, flags, off, cs, ax, ay, az, aw, out);
+    hipLaunchKernelGGL(k_edge_emit, dim3(nblk(ncand)), dim3(kBS), 0, s, g, leaves, corner_phi, ncand,
+                       flags, off, out);
     return hipGetLastError();
 }
 

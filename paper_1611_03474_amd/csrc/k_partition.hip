@@ -43,14 +43,17 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long 
 // One thread per cube.  The thread walks its root's neighbourhood list (all
 // threads of a wavefront usually share a root, so the list loads are
 // uniform), keeps the atoms within R_c of its own cube, projects the three
-// Gaussian factors and accumulates the 4x4x4 rank-one update.
-template <typename T, int QH>
+// Gaussian factors and accumulates the 4x4x4 rank-one update in double
+// precision.  With FAST exponentials it also accumulates the l1 error bound
+// E of the tensor: a perturbation da of a factor moves w a (x) b (x) c by at
+// most w (|da| |b| |c| + |a| |db| |c| + |a| |b| |dc|) in l1.
+template <bool FAST, int QH>
 __global__ __launch_bounds__(kBS) void k_estimate(
-    Grid g, int level, GLRule<T> R, const int4 *__restrict__ q, int64_t n,
+    Grid g, int level, GLRule<double> R, const int4 *__restrict__ q, int64_t n,
     const int32_t *__restrict__ subset, const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
-    double *__restrict__ Aout, double *__restrict__ Sout, unsigned long long *__restrict__ pairs) {
+    double *__restrict__ Aout, double *__restrict__ Eout, unsigned long long *__restrict__ pairs) {
     int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     unsigned long long np = 0;
     if (t < n) {
@@ -60,14 +63,13 @@ __global__ __launch_bounds__(kBS) void k_estimate(
         const double lo[3] = {g.o[0] + c.x * h, g.o[1] + c.y * h, g.o[2] + c.z * h};
         const double hi[3] = {lo[0] + h, lo[1] + h, lo[2] + h};
         const double mid[3] = {lo[0] + 0.5 * h, lo[1] + 0.5 * h, lo[2] + 0.5 * h};
-        const T s = (T)(0.5 * h);
-        const T Dk = (T)(g.D * Arith<T>::kLogScale);
+        const double s = 0.5 * h;
         const int64_t root =
             ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
-        T A[64];
+        double A[64];
 #pragma unroll
-        for (int e = 0; e < 64; ++e) A[e] = T(0);
-        T S = T(0);
+        for (int e = 0; e < 64; ++e) A[e] = 0.0;
+        double EA = 0.0;
         const int b = root_start[root], e_ = root_start[root + 1];
         for (int p = b; p < e_; ++p) {
             const int i = root_atoms[p];
@@ -77,39 +79,48 @@ __global__ __launch_bounds__(kBS) void k_estimate(
             const double dz = fmax(fmax(lo[2] - z, z - hi[2]), 0.0);
             if (dx * dx + dy * dy + dz * dz > g.rc2) continue;
             ++np;
-            T px[4], py[4], pz[4];
-            project<T, QH>(R, Dk, s, (T)(mid[0] - x), px);
-            project<T, QH>(R, Dk, s, (T)(mid[1] - y), py);
-            project<T, QH>(R, Dk, s, (T)(mid[2] - z), pz);
-            const T w = (T)aw[i];
+            double px[4], py[4], pz[4], ex, ey, ez;
+            project<FAST, QH>(R, g.D, s, mid[0] - x, px, ex);
+            project<FAST, QH>(R, g.D, s, mid[1] - y, py, ey);
+            project<FAST, QH>(R, g.D, s, mid[2] - z, pz, ez);
+            const double w = aw[i];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const T wx = w * px[j];
+                const double wx = w * px[j];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const T wxy = wx * py[k];
+                    const double wxy = wx * py[k];
 #pragma unroll
                     for (int l = 0; l < 4; ++l) A[16 * j + 4 * k + l] += wxy * pz[l];
                 }
             }
-            const T nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
-            const T ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
-            const T nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
-            S += w * nx * ny * nz;
+            if (FAST) {
+                const double nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
+                const double ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
+                const double nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
+                EA += w * ((ex * ny + nx * ey) * nz + nx * ny * ez);
+            }
         }
         double *dst = Aout + 64 * qi;
 #pragma unroll
-        for (int e = 0; e < 64; ++e) dst[e] = (double)A[e];
-        Sout[qi] = (double)S;
+        for (int e = 0; e < 64; ++e) dst[e] = A[e];
+        Eout[qi] = EA;
     }
     if (pairs) wave_add(pairs, np);
 }
 
-// Per-cube decision in double precision.  gamma > 0 (single-precision
-// tensors) turns decisions whose margin is within gamma * S into DEC_GUARD.
-__global__ __launch_bounds__(kBS) void k_decide(Grid g, int level, double gamma,
+// Safety factor on the first-order perturbation estimate band * amp of the
+// bound (measured deviations of single-precision bounds stay below
+// 0.25 band * amp; see the calibration notes in the design document).
+constexpr double kKappa = 8.0;
+
+// Per-cube decision in double precision.  For tensors built with FAST
+// exponentials, decisions whose margin lies within the tensor's error band
+// (amplified for the bound by the first-order factor amp) become DEC_GUARD
+// and are redone with exact exponentials.
+__global__ __launch_bounds__(kBS) void k_decide(Grid g, int level, int fast,
                                                 const double *__restrict__ Ain,
-                                                const double *__restrict__ Sin, int64_t n,
+                                                const double *__restrict__ Ein, int64_t n,
                                                 const int32_t *__restrict__ subset,
                                                 uint8_t *__restrict__ dec,
                                                 unsigned long long *__restrict__ nbound) {
@@ -121,7 +132,6 @@ __global__ __launch_bounds__(kBS) void k_decide(Grid g, int level, double gamma,
         const double *src = Ain + 64 * qi;
 #pragma unroll
         for (int e = 0; e < 64; ++e) A[e] = src[e];
-        const double band = gamma * Sin[qi];
         double E = 0.0, asum = 0.0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -133,6 +143,10 @@ __global__ __launch_bounds__(kBS) void k_decide(Grid g, int level, double gamma,
                     asum += v;
                     if (j >= 2 || k >= 2 || l >= 2) E += v;
                 }
+        // l1 error band of A: the accumulated bound of the FAST exponentials
+        // plus a floor for double-precision rounding; zero for exact
+        // exponentials (no guard)
+        const double band = fast ? Ein[qi] + 1e-13 * asum : 0.0;
         uint8_t d = 255;
         if (level >= 1) {
             // Step 3: higher-order mass under the user bound -> trilinear leaf
@@ -151,8 +165,8 @@ __global__ __launch_bounds__(kBS) void k_decide(Grid g, int level, double gamma,
             } else {
                 ++nb;
                 BoundResult B = nested_bound(A, band);
-                if (band > 0.0 && (B.unstable || fabs(B.L - g.c) <= 64.0 * band ||
-                                   fabs(B.U - g.c) <= 64.0 * band)) {
+                if (band > 0.0 && (B.jump || fabs(B.L - g.c) <= kKappa * band * B.amp ||
+                                   fabs(B.U - g.c) <= kKappa * band * B.amp)) {
                     d = DEC_GUARD;
                 }
                 keep = (B.L <= g.c && g.c <= B.U);  // Step 2
@@ -222,41 +236,49 @@ __global__ void k_level_histo(const uint8_t *__restrict__ dec, int64_t n,
     if (threadIdx.x < 5 && sh[threadIdx.x]) atomicAdd(&h[threadIdx.x], sh[threadIdx.x]);
 }
 
-__global__ void k_bound_debug(const double *__restrict__ Ain, int64_t n, double *__restrict__ out) {
+__global__ __launch_bounds__(kBS) void k_bound_debug(const double *__restrict__ Ain,
+                                                     const double *__restrict__ band, int64_t n,
+                                                     double *__restrict__ out) {
     int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= n) return;
     double A[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) A[e] = Ain[64 * t + e];
-    BoundResult B = nested_bound(A, 0.0);
-    out[4 * t + 0] = B.L;
-    out[4 * t + 1] = B.U;
-    out[4 * t + 2] = B.rho;
-    out[4 * t + 3] = (double)B.r;
+    BoundResult B = nested_bound(A, band ? band[t] : 0.0);
+    out[6 * t + 0] = B.L;
+    out[6 * t + 1] = B.U;
+    out[6 * t + 2] = B.rho;
+    out[6 * t + 3] = (double)B.r;
+    out[6 * t + 4] = B.jump ? 1.0 : 0.0;
+    out[6 * t + 5] = B.amp;
 }
 
-template <typename T, int QH>
+__global__ void k_fast_exp_debug(const double *__restrict__ x, int64_t n, double *__restrict__ y) {
+    int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (t < n) y[t] = expn<true>(x[t]);
+}
+
+template <bool FAST, int QH>
 hipError_t estimate_t(const Grid &g, int level, const int4 *q, int64_t n, const int32_t *subset,
                       const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
-                      const double *az, const double *aw, double *A, double *S,
+                      const double *az, const double *aw, double *A, double *E,
                       unsigned long long *pairs, hipStream_t s) {
-    GLRule<T> R = gl_rule<T>(QH);
-    hipLaunchKernelGGL((k_estimate<T, QH>), dim3(nblk(n)), dim3(kBS), 0, s, g, level, R, q, n,
-                       subset, rs, ra, ax, ay, az, aw, A, S, pairs);
+    GLRule<double> R = gl_rule<double>(QH);
+    hipLaunchKernelGGL((k_estimate<FAST, QH>), dim3(nblk(n)), dim3(kBS), 0, s, g, level, R, q, n,
+                       subset, rs, ra, ax, ay, az, aw, A, E, pairs);
     return hipGetLastError();
 }
 
-template <typename T>
+template <bool FAST>
 hipError_t estimate_dispatch(int qh, const Grid &g, int level, const int4 *q, int64_t n,
                              const int32_t *subset, const int32_t *rs, const int32_t *ra,
                              const double *ax, const double *ay, const double *az, const double *aw,
-                             double *A, double *S, unsigned long long *pairs, hipStream_t s) {
+                             double *A, double *E, unsigned long long *pairs, hipStream_t s) {
     switch (qh) {
-    case 3: return estimate_t<T, 3>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, S, pairs, s);
-    case 4: return estimate_t<T, 4>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, S, pairs, s);
-    case 5: return estimate_t<T, 5>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, S, pairs, s);
-    case 6: return estimate_t<T, 6>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, S, pairs, s);
-    case 8: return estimate_t<T, 8>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, S, pairs, s);
+    case 4: return estimate_t<FAST, 4>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
+    case 5: return estimate_t<FAST, 5>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
+    case 6: return estimate_t<FAST, 6>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
+    case 8: return estimate_t<FAST, 8>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -303,6 +325,7 @@ GLRule<T> gl_rule(int half) {
             r.c1[q] = (double)(1.5L * wq * x);
             r.c2[q] = (double)(2.5L * wq * L2);
             r.c3[q] = (double)(3.5L * wq * L3);
+            r.cs[q] = fabs(r.c0[q]) + fabs(r.c1[q]) + fabs(r.c2[q]) + fabs(r.c3[q]);
         }
         cache[half] = r;
         ready[half] = true;
@@ -314,23 +337,17 @@ GLRule<T> gl_rule(int half) {
         o.c1[q] = (T)cache[half].c1[q];
         o.c2[q] = (T)cache[half].c2[q];
         o.c3[q] = (T)cache[half].c3[q];
+        o.cs[q] = (T)cache[half].cs[q];
     }
     return o;
 }
-template GLRule<float> gl_rule<float>(int);
 template GLRule<double> gl_rule<double>(int);
 
-// beta = s sqrt(D).  Double: quadrature error below 2e-15 for the rules
-// chosen (measured against 40-digit quadrature over |d| <= 7); single: below
-// 1e-8, under single-precision rounding.
-int gl_half_nodes(double beta, bool fp32) {
-    if (fp32) {
-        if (beta <= 0.25) return 3;
-        if (beta <= 0.75) return 4;
-        if (beta <= 1.25) return 5;
-        if (beta <= 2.0) return 8;
-        return -1;
-    }
+// beta = s sqrt(D): quadrature error of the projection below 2e-15
+// (measured against 40-digit quadrature over |d| <= 7).  Both exponential
+// policies use the same rule, so they differ only by exponential rounding.
+int gl_half_nodes(double beta, bool fast) {
+    (void)fast;
     if (beta <= 0.25) return 4;
     if (beta <= 0.5) return 5;
     if (beta <= 0.75) return 6;
@@ -357,27 +374,22 @@ hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *
                            int64_t *pairs, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const double beta = 0.5 * ldexp(g.h0, -level) * sqrt(g.D);
-    const bool f32 = precision == TMS_PREC_FP32_GUARD;
-    const int qh = gl_half_nodes(beta, f32);
+    const bool fast = precision == TMS_PREC_FP32_GUARD;
+    const int qh = gl_half_nodes(beta, fast);
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    if (f32)
-        return estimate_dispatch<float>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay,
-                                        az, aw, A, S, pc, s);
-    return estimate_dispatch<double>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
-                                     aw, A, S, pc, s);
+    if (fast)
+        return estimate_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay,
+                                       az, aw, A, S, pc, s);
+    return estimate_dispatch<false>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
+                                    aw, A, S, pc, s);
 }
-
-// Error band of single-precision tensors, relative to S: covers rounding of
-// the projections (a few ulp of the largest factor value per coefficient)
-// and of the accumulation, with a wide safety margin.
-static constexpr double kGammaFP32 = 1.0 / 16384.0;
 
 hipError_t launch_decide(const Grid &g, int level, int precision, const double *A, const double *S,
                          int64_t n, const int32_t *subset, uint8_t *dec, int32_t *nbound,
                          hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const double gamma = (precision == TMS_PREC_FP32_GUARD) ? kGammaFP32 : 0.0;
-    hipLaunchKernelGGL(k_decide, dim3(nblk(n)), dim3(kBS), 0, s, g, level, gamma, A, S, n, subset,
+    const int fast = (precision == TMS_PREC_FP32_GUARD) ? 1 : 0;
+    hipLaunchKernelGGL(k_decide, dim3(nblk(n)), dim3(kBS), 0, s, g, level, fast, A, S, n, subset,
                        dec, reinterpret_cast<unsigned long long *>(nbound));
     return hipGetLastError();
 }
@@ -417,9 +429,16 @@ hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long 
     return hipGetLastError();
 }
 
-hipError_t launch_bound_debug(const double *A, int64_t n, double *out, hipStream_t s) {
+hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bound_debug, dim3(nblk(n)), dim3(kBS), 0, s, A, n, out);
+    hipLaunchKernelGGL(k_fast_exp_debug, dim3(nblk(n)), dim3(kBS), 0, s, x, n, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_bound_debug(const double *A, const double *band, int64_t n, double *out,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bound_debug, dim3(nblk(n)), dim3(kBS), 0, s, A, band, n, out);
     return hipGetLastError();
 }
 

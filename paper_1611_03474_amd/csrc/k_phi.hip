@@ -15,35 +15,34 @@ constexpr int kBS = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
 constexpr uint64_t kEmpty = ~0ull;
 
-// Error band of the single-precision sum, relative to phi: per term the
-// exponent -D d^2 (|.| <= ln(1/eps_cut) + D r_max^2 ~ 30) carries a relative
-// error of a few ulp, plus the accumulation; 2^-14 leaves a wide margin.
-constexpr double kGammaPhi32 = 1.0 / 16384.0;
-
-template <typename T>
+// FAST phi kernel: every term carries a relative error <= kFastExpErr, so
+// |dphi| <= kFastExpErr phi.  guard[k] = 1 when the sign of phi - c is not
+// certain (|phi - c| <= 2 kFastExpErr phi) or when |phi - c| <= band_rel * c;
+// the caller recomputes those points with exact exponentials.
+template <bool FAST>
 __global__ __launch_bounds__(kBS) void k_phi_points(Grid g, const double *__restrict__ pts,
                                                     int64_t m, const int32_t *__restrict__ cs,
                                                     const double *__restrict__ ax,
                                                     const double *__restrict__ ay,
                                                     const double *__restrict__ az,
                                                     const double *__restrict__ aw,
-                                                    double *__restrict__ phi,
+                                                    double band_rel, double *__restrict__ phi,
                                                     double *__restrict__ grad,
                                                     uint8_t *__restrict__ guard) {
     int64_t k = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (k >= m) return;
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
-    T f, gr[3];
-    phi_at<T>(g, p, cs, ax, ay, az, aw, f, gr);
-    phi[k] = (double)f;
+    double f, gr[3];
+    phi_at<FAST>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi[k] = f;
     if (grad) {
-        grad[3 * k] = (double)gr[0];
-        grad[3 * k + 1] = (double)gr[1];
-        grad[3 * k + 2] = (double)gr[2];
+        grad[3 * k] = gr[0];
+        grad[3 * k + 1] = gr[1];
+        grad[3 * k + 2] = gr[2];
     }
     if (guard) {
-        const double fd = (double)f;
-        guard[k] = (fabs(fd - g.c) <= kGammaPhi32 * fd + 1e-30) ? 1 : 0;
+        const double m_ = fabs(f - g.c);
+        guard[k] = (m_ <= 2.0 * kFastExpErr * f + 1e-300 || m_ <= band_rel * g.c) ? 1 : 0;
     }
 }
 
@@ -61,7 +60,7 @@ __global__ __launch_bounds__(kBS) void k_phi_subset(Grid g, const double *__rest
     const int64_t k = list[t];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
-    phi_at<double>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi_at<false>(g, p, cs, ax, ay, az, aw, f, gr);
     phi[k] = f;
     if (grad) {
         grad[3 * k] = gr[0];
@@ -241,15 +240,15 @@ __global__ void k_count_surface(const tms_leaf *__restrict__ leaves, int64_t n,
 
 hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
                              const int32_t *cs, const double *ax, const double *ay, const double *az,
-                             const double *aw, double *phi, double *grad, uint8_t *guard,
-                             hipStream_t s) {
+                             const double *aw, double band_rel, double *phi, double *grad,
+                             uint8_t *guard, hipStream_t s) {
     if (m <= 0) return hipSuccess;
     if (precision == TMS_PREC_FP32_GUARD)
-        hipLaunchKernelGGL(k_phi_points<float>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
-                           ay, az, aw, phi, grad, guard);
+        hipLaunchKernelGGL(k_phi_points<true>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
+                           ay, az, aw, band_rel, phi, grad, guard);
     else
-        hipLaunchKernelGGL(k_phi_points<double>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
-                           ay, az, aw, phi, grad, nullptr);
+        hipLaunchKernelGGL(k_phi_points<false>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
+                           ay, az, aw, 0.0, phi, grad, nullptr);
     return hipGetLastError();
 }
 

@@ -40,6 +40,56 @@ void DevBuf::release() {
 hipError_t launch_edge_count(const tms_leaf *leaves, int64_t n, unsigned long long *count,
                              hipStream_t s);
 
+static hipEvent_t ev_get(tms_ctx *ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+TimedScope::TimedScope(tms_ctx *c, int s) : ctx(c), slot(s) {
+    const bool outer = ctx->tdepth++ == 0;
+    if (!ctx->timing || !outer) return;
+    e1 = ev_get(ctx);
+    if (e1) (void)hipEventRecord(e1, ctx->stream);
+}
+
+TimedScope::~TimedScope() {
+    --ctx->tdepth;
+    if (!ctx->timing || !e1) return;
+    hipEvent_t e2 = ev_get(ctx);
+    if (!e2) {
+        ctx->ev_pool.push_back(e1);
+        return;
+    }
+    (void)hipEventRecord(e2, ctx->stream);
+    ctx->ev_pending.push_back({slot, {e1, e2}});
+}
+
+// resolve recorded event pairs (waits for them)
+void timing_flush(tms_ctx *ctx) {
+    for (auto &pe : ctx->ev_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pe.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+            ctx->t_ms[pe.first] += ms;
+            ctx->t_launch[pe.first] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        ctx->ev_pool.push_back(pe.second.first);
+        ctx->ev_pool.push_back(pe.second.second);
+    }
+    ctx->ev_pending.clear();
+}
+
 }  // namespace tms
 
 void tms_cells::release() {
@@ -161,17 +211,27 @@ hipError_t d2h(T *dst, const void *src, size_t count, hipStream_t s) {
 int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int64_t *total) {
     HIPCK(ctx->scan_c.ensure(scan_tmp_bytes(n) + 512));
     int32_t *tot = ctx->counters.as<int32_t>() + 60;
-    HIPCK(exclusive_scan(in, out, n, tot, ctx->scan_c.p, ctx->stream));
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(exclusive_scan(in, out, n, tot, ctx->scan_c.p, ctx->stream));
+    }
     int32_t h = 0;
     HIPCK(d2h(&h, tot, 1, ctx->stream));
     *total = h;
     return TMS_OK;
 }
 
-// phi at m points of `pts` into uphi (with single-precision guard); returns
-// the number of points recomputed in double precision
+// Corner values within this relative distance of c are always recomputed
+// with exact exponentials.  An edge root t = (c - phi0)/(phi1 - phi0) from
+// FAST values (relative error eps = kFastExpErr) is off by at most
+// eps (phi0 + phi1) / |phi1 - phi0|; with every corner of |phi - c| <= b c
+// exact, that is at most eps (1 + 1/b) <= 5e-6 for b = 0.07.
+constexpr double kCornerBand = 0.07;
+
+// phi at m points of `pts` (with the FAST-exponential guard); returns the
+// number of points recomputed with exact exponentials
 int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
-                       double *phi, double *grad, int64_t *n_guard) {
+                       double *phi, double *grad, int64_t *n_guard, double band_rel) {
     const int prec = cells->p.precision;
     const Grid &g = cells->g;
     *n_guard = 0;
@@ -181,9 +241,13 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, 
         HIPCK(ctx->uguard.ensure((size_t)m));
         gbuf = ctx->uguard.as<uint8_t>();
     }
-    HIPCK(launch_phi_points(g, prec, pts, m, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
-                            cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
-                            phi, grad, gbuf, ctx->stream));
+    {
+        TimedScope ts_(ctx, TMS_T_PHI);
+        HIPCK(launch_phi_points(g, prec, pts, m, cells->cell_start.as<int32_t>(),
+                                cells->ax.as<double>(), cells->ay.as<double>(),
+                                cells->az.as<double>(), cells->aw.as<double>(), band_rel, phi,
+                                grad, gbuf, ctx->stream));
+    }
     if (prec == TMS_PREC_FP32_GUARD) {
         HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)m));
         HIPCK(ctx->scan_a.ensure(sizeof(int32_t) * (size_t)m));
@@ -195,6 +259,7 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, 
             HIPCK(ctx->idx.ensure(sizeof(int32_t) * (size_t)ng));
             HIPCK(launch_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), m,
                                    ctx->idx.as<int32_t>(), ctx->stream));
+            TimedScope ts_(ctx, TMS_T_GUARD);
             HIPCK(launch_phi_points_subset(g, pts, ctx->idx.as<int32_t>(), ng,
                                            cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
                                            cells->ay.as<double>(), cells->az.as<double>(),
@@ -222,12 +287,15 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     HIPCK(ctx->slot.ensure(sizeof(uint32_t) * (size_t)ncand));
     HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)ncand));
     HIPCK(ctx->scan_a.ensure(sizeof(int32_t) * (size_t)ncand));
-    HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
-    HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
-    HIPCK(launch_corner_insert(leaves, n, g.K, ctx->hkeys.as<uint64_t>(), ctx->hown.as<uint32_t>(),
-                               hcap, ctx->slot.as<uint32_t>(), s));
-    HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
-                             ctx->flags.as<int32_t>(), s));
+    {
+        TimedScope ts_(ctx, TMS_T_CORNER);
+        HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
+        HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
+        HIPCK(launch_corner_insert(leaves, n, g.K, ctx->hkeys.as<uint64_t>(),
+                                   ctx->hown.as<uint32_t>(), hcap, ctx->slot.as<uint32_t>(), s));
+        HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
+                                 ctx->flags.as<int32_t>(), s));
+    }
     int64_t nu = 0;
     int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), ncand, &nu);
     if (rc) return rc;
@@ -237,14 +305,20 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     uint32_t *slot2u = ctx->hown.as<uint32_t>();
     HIPCK(ctx->lc.ensure(sizeof(uint32_t) * (size_t)hcap));
     slot2u = ctx->lc.as<uint32_t>();
-    HIPCK(launch_corner_unique(leaves, ncand, g.K, g, ctx->flags.as<int32_t>(),
-                               ctx->scan_a.as<int32_t>(), ctx->slot.as<uint32_t>(),
-                               ctx->uniq.as<double>(), slot2u, s));
+    {
+        TimedScope ts_(ctx, TMS_T_CORNER);
+        HIPCK(launch_corner_unique(leaves, ncand, g.K, g, ctx->flags.as<int32_t>(),
+                                   ctx->scan_a.as<int32_t>(), ctx->slot.as<uint32_t>(),
+                                   ctx->uniq.as<double>(), slot2u, s));
+    }
     rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nu, ctx->uphi.as<double>(), nullptr,
-                        n_guard);
+                        n_guard, kCornerBand);
     if (rc) return rc;
-    HIPCK(launch_corner_gather(leaves, n, ctx->slot.as<uint32_t>(), slot2u, ctx->uphi.as<double>(),
-                               g.c, leaves_out, cphi, s));
+    {
+        TimedScope ts_(ctx, TMS_T_CORNER);
+        HIPCK(launch_corner_gather(leaves, n, ctx->slot.as<uint32_t>(), slot2u,
+                                   ctx->uphi.as<double>(), g.c, leaves_out, cphi, s));
+    }
     *n_corners = nu;
     return TMS_OK;
 }
@@ -295,6 +369,8 @@ int32_t tms_destroy(tms_ctx *ctx) {
                            &ctx->hown, &ctx->slot, &ctx->uniq, &ctx->uphi, &ctx->uguard, &ctx->lc,
                            &ctx->ctmp, &ctx->counters, &ctx->hostpin};
     for (auto *b : bufs) b->release();
+    timing_flush(ctx);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return TMS_OK;
 }
@@ -367,6 +443,7 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     if (n >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many atoms");
     HIPCK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
+    TimedScope ts_build(ctx, TMS_T_BUILD);
     tms_cells *cells = *cells_io;
     if (cells && std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
         return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
@@ -521,7 +598,7 @@ int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, in
         return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_eval_phi");
     HIPCK(hipSetDevice(ctx->device));
     int64_t ng = 0;
-    int32_t rc = phi_with_guard(ctx, cells, pts, m, phi, grad, &ng);
+    int32_t rc = phi_with_guard(ctx, cells, pts, m, phi, grad, &ng, 0.0);
     if (rc) return rc;
     HIPCK(hipStreamSynchronize(ctx->stream));
     if (n_guard) *n_guard = ng;
@@ -554,7 +631,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         HIPCK(launch_uniform_points(g, ctx->uniq.as<double>(), m, s));
         int64_t ng = 0;
         int32_t rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), m, ctx->uphi.as<double>(),
-                                    nullptr, &ng);
+                                    nullptr, &ng, kCornerBand);
         if (rc) return rc;
         HIPCK(launch_uniform_gather(g, ctx->uphi.as<double>(), g.c, ctx->leaves.as<tms_leaf>(), L,
                                     ctx->corner_phi.as<double>(), s));
@@ -565,14 +642,20 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         const int64_t nr = cells->nroots;
         HIPCK(ctx->flags.ensure(4 * (size_t)nr));
         HIPCK(ctx->scan_a.ensure(4 * (size_t)nr));
-        HIPCK(launch_roots_flags(cells->root_start.as<int32_t>(), nr, ctx->flags.as<int32_t>(), s));
+        {
+            TimedScope ts_(ctx, TMS_T_COMPACT);
+            HIPCK(launch_roots_flags(cells->root_start.as<int32_t>(), nr, ctx->flags.as<int32_t>(), s));
+        }
         int64_t nq = 0;
         int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nr, &nq);
         if (rc) return rc;
         int cur = 0;
         HIPCK(ctx->q[0].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nq, 1)));
-        HIPCK(launch_roots_emit(g, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nr,
-                                ctx->q[0].as<int4>(), s));
+        {
+            TimedScope ts_(ctx, TMS_T_COMPACT);
+            HIPCK(launch_roots_emit(g, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nr,
+                                    ctx->q[0].as<int4>(), s));
+        }
         for (int lev = 0; lev <= g.K && nq > 0; ++lev) {
             if (nq >= (int64_t)0x7FFFFFFF / 8) return fail(ctx, TMS_E_INVALID, "queue too large");
             st.n_est[lev] = nq;
@@ -581,23 +664,35 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             HIPCK(ctx->dec.ensure((size_t)nq));
             HIPCK(hipMemsetAsync(ctr, 0, 256, s));
             const int4 *q = ctx->q[cur].as<int4>();
-            HIPCK(launch_estimate(g, lev, prec, q, nq, nullptr, cells->root_start.as<int32_t>(),
-                                  cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
-                                  cells->ay.as<double>(), cells->az.as<double>(),
-                                  cells->aw.as<double>(), ctx->abuf.as<double>(),
-                                  ctx->ebuf.as<double>(), reinterpret_cast<int64_t *>(ctr + 0), s));
-            HIPCK(launch_decide(g, lev, prec, ctx->abuf.as<double>(), ctx->ebuf.as<double>(), nq,
-                                nullptr, ctx->dec.as<uint8_t>(),
-                                reinterpret_cast<int32_t *>(ctr + 1), s));
+            {  // Step 1: tensor of every queued cube
+                TimedScope ts_(ctx, TMS_T_ESTIMATE);
+                HIPCK(launch_estimate(g, lev, prec, q, nq, nullptr, cells->root_start.as<int32_t>(),
+                                      cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
+                                      cells->ay.as<double>(), cells->az.as<double>(),
+                                      cells->aw.as<double>(), ctx->abuf.as<double>(),
+                                      ctx->ebuf.as<double>(), reinterpret_cast<int64_t *>(ctr + 0),
+                                      s));
+            }
+            {  // Steps 2-3: stopping rule and bound test
+                TimedScope ts_(ctx, TMS_T_DECIDE);
+                HIPCK(launch_decide(g, lev, prec, ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
+                                    nq, nullptr, ctx->dec.as<uint8_t>(),
+                                    reinterpret_cast<int32_t *>(ctr + 1), s));
+            }
             if (prec == TMS_PREC_FP32_GUARD) {
                 HIPCK(ctx->flags.ensure(4 * (size_t)nq));
                 HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
-                HIPCK(launch_guard_list_flags(ctx->dec.as<uint8_t>(), nq, ctx->flags.as<int32_t>(), s));
+                {
+                    TimedScope ts_(ctx, TMS_T_COMPACT);
+                    HIPCK(launch_guard_list_flags(ctx->dec.as<uint8_t>(), nq,
+                                                  ctx->flags.as<int32_t>(), s));
+                }
                 int64_t ng = 0;
                 rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &ng);
                 if (rc) return rc;
                 if (ng > 0) {
                     HIPCK(ctx->idx.ensure(4 * (size_t)ng));
+                    TimedScope ts_(ctx, TMS_T_GUARD);
                     HIPCK(launch_guard_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(),
                                                  nq, ctx->idx.as<int32_t>(), s));
                     HIPCK(launch_estimate(g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(),
@@ -613,13 +708,16 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 }
                 st.guard_cubes += ng;
             }
-            HIPCK(launch_level_histo(ctx->dec.as<uint8_t>(), nq, ctr + 8, s));
             HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
             HIPCK(ctx->scan_b.ensure(4 * (size_t)nq));
             HIPCK(ctx->flags.ensure(4 * (size_t)nq));
             HIPCK(ctx->idx.ensure(4 * (size_t)nq));
             int32_t *lcnt = ctx->flags.as<int32_t>(), *ccnt = ctx->idx.as<int32_t>();
-            HIPCK(launch_level_counts(ctx->dec.as<uint8_t>(), nq, lcnt, ccnt, s));
+            {
+                TimedScope ts_(ctx, TMS_T_COMPACT);
+                HIPCK(launch_level_histo(ctx->dec.as<uint8_t>(), nq, ctr + 8, s));
+                HIPCK(launch_level_counts(ctx->dec.as<uint8_t>(), nq, lcnt, ccnt, s));
+            }
             int64_t nl = 0, nc = 0;
             rc = scan_total(ctx, lcnt, ctx->scan_a.as<int32_t>(), nq, &nl);
             if (rc) return rc;
@@ -635,9 +733,12 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             st.n_hmin[lev] = (int64_t)h[8 + DEC_HMIN];
             HIPCK(grow_keep(ctx->leaves, sizeof(tms_leaf) * (size_t)(L + nl), sizeof(tms_leaf) * (size_t)L, s));
             HIPCK(ctx->q[cur ^ 1].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nc, 1)));
-            HIPCK(launch_level_emit(q, ctx->dec.as<uint8_t>(), nq, lev, ctx->scan_a.as<int32_t>(),
-                                    ctx->scan_b.as<int32_t>(), ctx->leaves.as<tms_leaf>(), L,
-                                    ctx->q[cur ^ 1].as<int4>(), s));
+            {
+                TimedScope ts_(ctx, TMS_T_COMPACT);
+                HIPCK(launch_level_emit(q, ctx->dec.as<uint8_t>(), nq, lev, ctx->scan_a.as<int32_t>(),
+                                        ctx->scan_b.as<int32_t>(), ctx->leaves.as<tms_leaf>(), L,
+                                        ctx->q[cur ^ 1].as<int4>(), s));
+            }
             L += nl;
             nq = nc;
             cur ^= 1;
@@ -652,7 +753,10 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         st.guard_points = ng;
     }
     HIPCK(hipMemsetAsync(ctr, 0, 8, s));
-    HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr, s));
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr, s));
+    }
     unsigned long long ns = 0;
     HIPCK(d2h(&ns, ctr, 1, s));
     st.n_leaves = L;
@@ -721,7 +825,10 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
     if (n > 0) {
         unsigned long long *ctr = ctx->counters.as<unsigned long long>();
         HIPCK(hipMemsetAsync(ctr, 0, 8, s));
-        HIPCK(launch_edge_count(lv, n, ctr, s));
+        {
+            TimedScope ts_(ctx, TMS_T_EXTRACT);
+            HIPCK(launch_edge_count(lv, n, ctr, s));
+        }
         unsigned long long ncr = 0;
         HIPCK(d2h(&ncr, ctr, 1, s));
         const int64_t ncand = 12 * n;
@@ -731,20 +838,21 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         HIPCK(ctx->slot.ensure(sizeof(uint32_t) * (size_t)ncand));
         HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)ncand));
         HIPCK(ctx->scan_b.ensure(sizeof(int32_t) * (size_t)ncand));
-        HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
-        HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
-        HIPCK(launch_edge_insert(lv, n, g.K, ctx->hkeys.as<uint64_t>(), ctx->hown.as<uint32_t>(),
-                                 hcap, ctx->slot.as<uint32_t>(), s));
-        HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
-                                 ctx->flags.as<int32_t>(), s));
+        {
+            TimedScope ts_(ctx, TMS_T_EXTRACT);
+            HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
+            HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
+            HIPCK(launch_edge_insert(lv, n, g.K, ctx->hkeys.as<uint64_t>(),
+                                     ctx->hown.as<uint32_t>(), hcap, ctx->slot.as<uint32_t>(), s));
+            HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
+                                     ctx->flags.as<int32_t>(), s));
+        }
         int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), ncand, &nv);
         if (rc) return rc;
         HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
-        HIPCK(launch_edge_emit(g, cells->p.precision, lv, cphi, ncand, ctx->flags.as<int32_t>(),
-                               ctx->scan_b.as<int32_t>(), cells->cell_start.as<int32_t>(),
-                               cells->ax.as<double>(), cells->ay.as<double>(),
-                               cells->az.as<double>(), cells->aw.as<double>(),
-                               ctx->verts.as<tms_vertex>(), s));
+        TimedScope ts_(ctx, TMS_T_EXTRACT);
+        HIPCK(launch_edge_emit(g, lv, cphi, ncand, ctx->flags.as<int32_t>(),
+                               ctx->scan_b.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
     }
     ctx->n_verts = nv;
     *n_out = nv;
@@ -777,8 +885,29 @@ int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_
     return TMS_OK;
 }
 
+int32_t tms_set_timing(tms_ctx *ctx, int32_t enable) {
+    if (!ctx) return TMS_E_INVALID;
+    timing_flush(ctx);
+    ctx->timing = enable != 0;
+    return TMS_OK;
+}
+
+int32_t tms_get_timing(tms_ctx *ctx, tms_timing *out, int32_t reset) {
+    if (!ctx || !out) return TMS_E_INVALID;
+    timing_flush(ctx);
+    for (int i = 0; i < TMS_T_SLOTS; ++i) {
+        out->ms[i] = ctx->t_ms[i];
+        out->launches[i] = ctx->t_launch[i];
+        if (reset) {
+            ctx->t_ms[i] = 0;
+            ctx->t_launch[i] = 0;
+        }
+    }
+    return TMS_OK;
+}
+
 int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cubes, int64_t n,
-                         int32_t precision, double *A) {
+                         int32_t precision, double *A, double *S) {
     if (!ctx) return TMS_E_INVALID;
     if (!cells || n < 0 || (n > 0 && (!cubes || !A)) ||
         (precision != TMS_PREC_FP64 && precision != TMS_PREC_FP32_GUARD))
@@ -819,14 +948,26 @@ int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cu
                               A, ctx->ebuf.as<double>(), nullptr, s));
         HIPCK(hipStreamSynchronize(s));
     }
+    if (S) HIPCK(hipMemcpyAsync(S, ctx->ebuf.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
     return TMS_OK;
 }
 
-int32_t tms_debug_bound(tms_ctx *ctx, const double *A, int64_t n, double *out) {
+int32_t tms_debug_fast_exp(tms_ctx *ctx, const double *x, int64_t n, double *y) {
+    if (!ctx) return TMS_E_INVALID;
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(ctx, TMS_E_INVALID, "invalid arguments");
+    HIPCK(hipSetDevice(ctx->device));
+    HIPCK(launch_fast_exp_debug(x, n, y, ctx->stream));
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return TMS_OK;
+}
+
+int32_t tms_debug_bound(tms_ctx *ctx, const double *A, const double *band, int64_t n,
+                        double *out) {
     if (!ctx) return TMS_E_INVALID;
     if (n < 0 || (n > 0 && (!A || !out))) return fail(ctx, TMS_E_INVALID, "invalid arguments");
     HIPCK(hipSetDevice(ctx->device));
-    HIPCK(launch_bound_debug(A, n, out, ctx->stream));
+    HIPCK(launch_bound_debug(A, band, n, out, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
     return TMS_OK;
 }

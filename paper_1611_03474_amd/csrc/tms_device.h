@@ -17,62 +17,70 @@
 namespace tms {
 
 // ---------------------------------------------------------------------------
-// Exponentials.  Single precision uses the hardware base-2 exponential on a
-// pre-scaled argument; double precision uses the device math library.
+// Exponentials.  On gfx950 a double-precision FMA issues at the same rate as
+// an (unpacked) single-precision one, so the only place where single
+// precision pays is the transcendental itself.  The FAST policy evaluates
+// exp(x), x <= 0, as 2^n * 2^f with n = floor(x log2 e) and f = x log2 e - n
+// split in double precision, 2^f from the hardware single-precision v_exp_f32
+// (f in [0,1)), and the scaling by 2^n exact.  Its relative error is the
+// exp2 rounding plus the rounding of f to single precision; kFastExpErr
+// bounds it (checked on the device by the test-suite).  Everything around the
+// exponential stays in double precision.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float exp_neg(float a_log2e) {  // 2^(a)
-    return __builtin_amdgcn_exp2f(a_log2e);
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kFastExpErr = 1.5e-7;  // 1 ulp of v_exp_f32 + rounding of f
+
+template <bool FAST>
+__device__ __forceinline__ double expn(double x) {
+    if constexpr (FAST) {
+        const double y = x * kLog2e;
+        const double n = floor(y);
+        const float f = (float)(y - n);
+        const float e = __builtin_amdgcn_exp2f(f);
+        return ldexp((double)e, (int)fmax(n, -1070.0));
+    } else {
+        return exp(x);
+    }
 }
-
-template <typename T>
-struct Arith;
-
-template <>
-struct Arith<float> {
-    // exp(-D u^2) with Dl = D log2(e)
-    static __device__ __forceinline__ float gauss(float Dl, float u) {
-        return __builtin_amdgcn_exp2f(-Dl * u * u);
-    }
-    static __device__ __forceinline__ float gauss2(float Dl, float u2) {
-        return __builtin_amdgcn_exp2f(-Dl * u2);
-    }
-    static constexpr double kLogScale = 1.4426950408889634074;  // log2(e)
-};
-
-template <>
-struct Arith<double> {
-    static __device__ __forceinline__ double gauss(double D, double u) { return exp(-D * u * u); }
-    static __device__ __forceinline__ double gauss2(double D, double u2) { return exp(-D * u2); }
-    static constexpr double kLogScale = 1.0;
-};
 
 // ---------------------------------------------------------------------------
 // Endpoint-corrected degree-3 Legendre projection of f(t) = exp(-D (s t + d)^2)
 // on t in [-1,1] (x = m + s t, d = m - x_i).  a[0..3] receive the corrected
 // coefficients of eq. alpha.  QH is half the number of quadrature nodes.
+// With FAST exponentials, *err receives an l1 bound on the error of a[]:
+// every f value carries a relative error <= eps = kFastExpErr.  The
+// endpoint correction cancels the errors of the raw a2, a3 exactly:
+//   da~2 = (df(1) + df(-1))/2 - da0,   da~3 = (df(1) - df(-1))/2 - da1,
+// and with c0, c1 >= 0 at the positive nodes and f > 0,
+//   |da0| <= eps a0,  |da1| <= eps b1,  b1 = sum_q c1_q (f(t_q) + f(-t_q)),
+// so sum_j |da~_j| <= eps (2 a0 + 2 b1 + f(1) + f(-1)).
 // ---------------------------------------------------------------------------
-template <typename T, int QH>
-__device__ __forceinline__ void project(const GLRule<T> &R, T Dk, T s, T d, T a[4]) {
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+template <bool FAST, int QH>
+__device__ __forceinline__ void project(const GLRule<double> &R, double D, double s, double d,
+                                        double a[4], double &err) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, sf = 0;
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
-        T fp = Arith<T>::gauss(Dk, s * R.t[q] + d);
-        T fm = Arith<T>::gauss(Dk, d - s * R.t[q]);
-        T ev = fp + fm, od = fp - fm;
+        const double up = s * R.t[q] + d, um = d - s * R.t[q];
+        const double fp = expn<FAST>(-D * up * up);
+        const double fm = expn<FAST>(-D * um * um);
+        const double ev = fp + fm, od = fp - fm;
         a0 += R.c0[q] * ev;
         a2 += R.c2[q] * ev;
         a1 += R.c1[q] * od;
         a3 += R.c3[q] * od;
+        if (FAST) sf += R.c1[q] * ev;
     }
     // eq. condition1: match f at t = +-1 by adding e0 L2 + e1 L3
-    T f1 = Arith<T>::gauss(Dk, s + d);
-    T fm1 = Arith<T>::gauss(Dk, d - s);
-    T ep = f1 - (a0 + a1 + a2 + a3);
-    T em = fm1 - (a0 - a1 + a2 - a3);
+    const double f1 = expn<FAST>(-D * (s + d) * (s + d));
+    const double fm1 = expn<FAST>(-D * (d - s) * (d - s));
+    const double ep = f1 - (a0 + a1 + a2 + a3);
+    const double em = fm1 - (a0 - a1 + a2 - a3);
     a[0] = a0;
     a[1] = a1;
-    a[2] = a2 + T(0.5) * (ep + em);
-    a[3] = a3 + T(0.5) * (ep - em);
+    a[2] = a2 + 0.5 * (ep + em);
+    a[3] = a3 + 0.5 * (ep - em);
+    err = FAST ? kFastExpErr * (2.0 * (a0 + sf) + f1 + fm1) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -225,19 +233,34 @@ __device__ __forceinline__ int rank99(const double s[4], double &m_hi, double &m
 struct BoundResult {
     double L, U, rho;
     int r;
-    bool unstable;  // a rank rule or singular gap lies within the guard band
+    bool jump;   // a 0.99 rank rule lies within its perturbation band
+    double amp;  // first-order amplification of an l1 perturbation of A into L, U
 };
+
+// gap of sorted value i to its neighbours that are part of the kept set
+// boundary (i-1 if i > 0, i+1 always)
+__device__ __forceinline__ double sgap(const double s[4], int i) {
+    double g = (i + 1 < 4) ? s[i] - s[i + 1] : s[i];
+    if (i > 0) g = fmin(g, s[i - 1] - s[i]);
+    return g;
+}
 
 // Nested-SVD bound of Section 2.2.2 (eqs. matrix1, SVD1-SVD7, Sxyz,
 // bound1-bound3) in double precision.  The 4 x 16 unfolding carries the
 // x-degree on its rows and (k,l) as 4k+l on its columns.  The singular
 // triplets come from the eigen-decomposition of the 4x4 Gram matrices
 // (A1 A1^T, then V_i V_i^T), sigma = sqrt(lambda), right vectors by
-// back-substitution.  band > 0 marks results whose discrete choices (ranks,
-// singular subspaces) could flip under an l1 perturbation of A of size band.
+// back-substitution.
+//
+// With band > 0 (A known only up to an l1 perturbation of that size) it also
+// reports whether a rank decision could flip (jump) and a first-order
+// amplification factor amp: singular values move by at most band, singular
+// vectors rotate by about band / gap (Wedin), and the interval bound moves by
+// about sigma times that rotation, so |dL|, |dU| <~ band * amp.
 __device__ inline BoundResult nested_bound(const double *A, double band) {
     BoundResult R;
-    R.unstable = false;
+    R.jump = false;
+    R.amp = 1.0;
     double S[4][4], W[4][4], lam[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -256,12 +279,7 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
     double mhi, mlo;
     int r = rank99(sig, mhi, mlo);
     R.r = r;
-    const double kb = 4.0 * band;
-    if (band > 0.0) {
-        if (mhi <= kb || mlo <= kb) R.unstable = true;
-        for (int i = 0; i < r && i < 3; ++i)
-            if (sig[i] - sig[i + 1] <= kb + 1e-6 * sig[0]) R.unstable = true;
-    }
+    if (band > 0.0 && (mhi <= 8.0 * band || mlo <= 8.0 * band)) R.jump = true;
     double At[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) At[e] = 0.0;
@@ -291,10 +309,15 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
         double nhi, nlo;
         int ri = rank99(d, nhi, nlo);
         if (band > 0.0) {
-            double kbi = kb * inv;
-            if (nhi <= kbi || nlo <= kbi) R.unstable = true;
-            for (int k = 0; k < ri && k < 3; ++k)
-                if (d[k] - d[k + 1] <= kbi + 1e-6 * d[0]) R.unstable = true;
+            // outer rotation of (u_i, v_i) and the inner perturbation of V_i
+            const double go = sgap(sig, i);
+            const double rot = (go > 0.0) ? band / go : 1e300;
+            const double dv = band * inv + rot;  // |dV_i| (unit-norm matrix)
+            double dg = 1e300;
+            for (int k = 0; k < ri; ++k) dg = fmin(dg, sgap(d, k));
+            const double irot = (dg > 0.0) ? dv / dg : 1e300;
+            R.amp += sig[i] * (rot + irot) / band + 1.0;
+            if (nhi <= 8.0 * dv || nlo <= 8.0 * dv) R.jump = true;
         }
         double ux0, ux1;
         leg3_range(u, ux0, ux1);
@@ -333,6 +356,7 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
     R.rho = rho;
     R.L = msum - rho;
     R.U = Msum + rho;
+    if (!(R.amp < 1e300)) R.amp = 1e300;
     return R;
 }
 
@@ -386,17 +410,16 @@ __device__ __forceinline__ void sample_range(const double *A, double &lo, double
 // ---------------------------------------------------------------------------
 // phi and grad phi at one point (eq. Gaussian1).
 // ---------------------------------------------------------------------------
-// Sum over atoms within R_c of p.  The pair predicate and the differences run
-// in double; the exponentials and sums in T.
-template <typename T>
+// Sum over atoms within R_c of p, in canonical atom order (cell rows of the
+// 5x5x5 stencil, atoms in cell order).  *err (FAST only) bounds |dphi|.
+template <bool FAST>
 __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                                        const int32_t *__restrict__ cs, const double *__restrict__ ax,
                                        const double *__restrict__ ay, const double *__restrict__ az,
-                                       const double *__restrict__ aw, T &phi, T gr[3]) {
-    const T Dk = (T)(g.D * Arith<T>::kLogScale);
-    const T m2D = (T)(-2.0 * g.D);
-    phi = T(0);
-    gr[0] = gr[1] = gr[2] = T(0);
+                                       const double *__restrict__ aw, double &phi, double gr[3]) {
+    const double D = g.D, m2D = -2.0 * g.D;
+    phi = 0.0;
+    gr[0] = gr[1] = gr[2] = 0.0;
     int c0[3], c1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -415,12 +438,12 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                 const double dx = p[0] - ax[i], dy = p[1] - ay[i], dz = p[2] - az[i];
                 const double d2 = dx * dx + dy * dy + dz * dz;
                 if (d2 > g.rc2) continue;
-                const T term = (T)aw[i] * Arith<T>::gauss2(Dk, (T)d2);
+                const double term = aw[i] * expn<FAST>(-D * d2);
                 phi += term;
-                const T f = m2D * term;
-                gr[0] += f * (T)dx;
-                gr[1] += f * (T)dy;
-                gr[2] += f * (T)dz;
+                const double f = m2D * term;
+                gr[0] += f * dx;
+                gr[1] += f * dy;
+                gr[2] += f * dz;
             }
         }
 }

@@ -32,9 +32,10 @@ struct Grid {
 // with f+ = f(t_q) + f(-t_q), f- = f(t_q) - f(-t_q) for the positive nodes t_q,
 //   a0 = sum c0 f+,  a1 = sum c1 f-,  a2 = sum c2 f+,  a3 = sum c3 f-
 // gives the four Legendre projection coefficients (2j+1)/2 int f L_j.
+// cs[q] = |c0| + |c1| + |c2| + |c3| at node q (error propagation).
 template <typename T>
 struct GLRule {
-    T t[8], c0[8], c1[8], c2[8], c3[8];
+    T t[8], c0[8], c1[8], c2[8], c3[8], cs[8];
 };
 
 // Number of positive nodes (half the rule) used on a level whose cubes have
@@ -104,7 +105,26 @@ struct tms_ctx {
         slot, uniq, uphi, uguard, lc, ctmp;
     tms::DevBuf counters;  // small device counters
     tms::DevBuf hostpin;   // unused
+    // per-phase device timing (HIP events on `stream`)
+    bool timing = false;
+    int tdepth = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double t_ms[TMS_T_SLOTS] = {0};
+    int64_t t_launch[TMS_T_SLOTS] = {0};
 };
+
+namespace tms {
+// Brackets the launches issued in its scope with events when timing is on.
+struct TimedScope {
+    tms_ctx *ctx;
+    int slot;
+    hipEvent_t e1 = nullptr;
+    TimedScope(tms_ctx *c, int s);
+    ~TimedScope();
+};
+void timing_flush(tms_ctx *ctx);
+}  // namespace tms
 
 // ---------------------------------------------------------------------------
 // Launch wrappers (defined in the .hip files).
@@ -158,13 +178,15 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
                              int64_t leaf_base, int4 *qnext, hipStream_t s);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
                               hipStream_t s);
-hipError_t launch_bound_debug(const double *A, int64_t n, double *out, hipStream_t s);
+hipError_t launch_bound_debug(const double *A, const double *band, int64_t n, double *out,
+                              hipStream_t s);
+hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStream_t s);
 
 // k_phi.hip
 hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
                              const int32_t *cell_start, const double *ax, const double *ay,
-                             const double *az, const double *aw, double *phi, double *grad,
-                             uint8_t *guard, hipStream_t s);
+                             const double *az, const double *aw, double band_rel, double *phi,
+                             double *grad, uint8_t *guard, hipStream_t s);
 hipError_t launch_phi_points_subset(const Grid &g, const double *pts, const int32_t *list,
                                     int64_t m, const int32_t *cell_start, const double *ax,
                                     const double *ay, const double *az, const double *aw,
@@ -194,10 +216,8 @@ hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long
 // k_extract.hip
 hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                               uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
-hipError_t launch_edge_emit(const Grid &g, int precision, const tms_leaf *leaves,
-                            const double *corner_phi, int64_t ncand, const int32_t *flags,
-                            const int32_t *off, const int32_t *cs, const double *ax,
-                            const double *ay, const double *az, const double *aw,
+hipError_t launch_edge_emit(const Grid &g, const tms_leaf *leaves, const double *corner_phi,
+                            int64_t ncand, const int32_t *flags, const int32_t *off,
                             tms_vertex *out, hipStream_t s);
 
 }  // namespace tms

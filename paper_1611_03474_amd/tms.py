@@ -30,6 +30,17 @@ VERTEX_DTYPE = np.dtype([("edge_key", "<u8"), ("t", "<f8"), ("x", "<f8"), ("y", 
 assert LEAF_DTYPE.itemsize == 20 and VERTEX_DTYPE.itemsize == 40
 
 
+T_SLOTS = ["build", "estimate", "decide", "guard", "compact", "corner", "phi", "extract"]
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+
+    def as_dict(self) -> dict:
+        return {k: {"ms": self.ms[i], "launches": int(self.launches[i])}
+                for i, k in enumerate(T_SLOTS)}
+
+
 class TmsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("tms error %d: %s" % (code, msg))
@@ -89,12 +100,16 @@ def load_library(path: str = LIB_PATH):
     L.tms_get_leaves.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
     L.tms_extract_cube_vertices.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(i64)]
     L.tms_get_vertices.argtypes = [_VP, _VP, i64, C.POINTER(i64)]
-    L.tms_debug_tensor.argtypes = [_VP, _VP, _VP, i64, i32, _VP]
-    L.tms_debug_bound.argtypes = [_VP, _VP, i64, _VP]
+    L.tms_set_timing.argtypes = [_VP, i32]
+    L.tms_get_timing.argtypes = [_VP, C.POINTER(Timing), i32]
+    L.tms_debug_tensor.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP]
+    L.tms_debug_bound.argtypes = [_VP, _VP, _VP, i64, _VP]
+    L.tms_debug_fast_exp.argtypes = [_VP, _VP, i64, _VP]
     for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
-              "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound"):
+              "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
+              "tms_get_timing", "tms_debug_fast_exp"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -282,21 +297,44 @@ class Context:
         self._check(rc)
         return n.value
 
+    # ---------------------------------------------------------------- timing
+    def set_timing(self, enable: bool):
+        self._check(self.lib.tms_set_timing(self.h, int(bool(enable))))
+
+    def get_timing(self, reset: bool = False) -> dict:
+        t = Timing()
+        self._check(self.lib.tms_get_timing(self.h, C.byref(t), int(bool(reset))))
+        return t.as_dict()
+
     # ----------------------------------------------------------------- debug
-    def debug_tensor(self, cells: Cells, cubes, precision=PREC_FP64):
+    def debug_tensor(self, cells: Cells, cubes, precision=PREC_FP64, with_scale=False):
         t = self._torch
         cb = t.as_tensor(np.asarray(cubes, dtype=np.int32)).to(self.device).contiguous()
         A = t.zeros((cb.shape[0], 64), dtype=t.float64, device=self.device)
+        S = t.zeros(cb.shape[0], dtype=t.float64, device=self.device) if with_scale else None
         self._check(self.lib.tms_debug_tensor(self.h, cells.handle, _VP(_ptr(cb)), cb.shape[0],
-                                              int(precision), _VP(_ptr(A))))
-        return A
+                                              int(precision), _VP(_ptr(A)), _VP(_ptr(S))))
+        return (A, S) if with_scale else A
 
-    def debug_bound(self, A):
+    def debug_fast_exp(self, x):
+        t = self._torch
+        xx = t.as_tensor(np.asarray(x, dtype=np.float64)).to(self.device).contiguous()
+        y = t.empty_like(xx)
+        self._check(self.lib.tms_debug_fast_exp(self.h, _VP(_ptr(xx)), xx.shape[0],
+                                                _VP(_ptr(y))))
+        return y
+
+    def debug_bound(self, A, band=None):
+        """Returns [n, 6]: L, U, rho, r, jump, amp."""
         t = self._torch
         a = t.as_tensor(np.asarray(A, dtype=np.float64)).reshape(-1, 64).to(self.device)
         a = a.contiguous()
-        out = t.zeros((a.shape[0], 4), dtype=t.float64, device=self.device)
-        self._check(self.lib.tms_debug_bound(self.h, _VP(_ptr(a)), a.shape[0], _VP(_ptr(out))))
+        b = None
+        if band is not None:
+            b = t.as_tensor(np.asarray(band, dtype=np.float64)).to(self.device).contiguous()
+        out = t.zeros((a.shape[0], 6), dtype=t.float64, device=self.device)
+        self._check(self.lib.tms_debug_bound(self.h, _VP(_ptr(a)), _VP(_ptr(b)), a.shape[0],
+                                             _VP(_ptr(out))))
         return out
 
 

@@ -140,8 +140,13 @@ def test_phi_and_grad_parity(ctx, g200, prec):
     phi, grad = phi.cpu().numpy(), grad.cpu().numpy()
     rphi, rgrad = oracle.phi(g200, D, pts, grad=True)
     tol = _phi_tol(prec)
-    print("max relative phi error %.3e" % np.max(np.abs(phi - rphi) / np.maximum(rphi, 1e-300)))
+    rel = np.abs(phi - rphi) / np.maximum(rphi, 1e-300)
+    print("max relative phi error %.3e" % rel.max())
     assert np.all(np.abs(phi - rphi) <= tol * rphi + 1e-300)
+    if prec == tms.PREC_FP32_GUARD:
+        # single-precision exponentials: relative error within the design
+        # bound kFastExpErr = 1.5e-7 of every term (plus double rounding)
+        assert rel.max() <= 1.5e-7 + 1e-13
     scale = 2 * D * math.sqrt(cells.rc2) * rphi
     assert np.all(np.abs(grad - rgrad) <= tol * scale[:, None] + 1e-300)
     assert np.array_equal(phi >= 1.0, rphi >= 1.0)
@@ -165,28 +170,40 @@ def test_tensor_parity(ctx, g200, prec):
             i = np.clip(i, 0, n - 1)
             cubes.append([lev, *i])
     cubes = np.array(cubes, dtype=np.int32)
-    A = ctx.debug_tensor(cells, cubes, precision=prec).cpu().numpy()
+    A, EA = ctx.debug_tensor(cells, cubes, precision=prec, with_scale=True)
+    A, EA = A.cpu().numpy(), EA.cpu().numpy()
+    A64 = ctx.debug_tensor(cells, cubes, precision=tms.PREC_FP64).cpu().numpy()
+    worst = 0.0
     for row, (lev, ix, iy, iz) in enumerate(cubes):
         h = 2.0 / 2 ** lev
         lo = cells.origin + np.array([ix, iy, iz]) * h
         R, _ = oracle.cube_tensor(g200, D, lo, lo + h)
         R = R.reshape(64)
-        err = np.abs(A[row] - R).sum()
+        scale = max(np.abs(R).sum(), 1e-300)
         if prec == tms.PREC_FP64:
-            assert err <= 1e-12 * max(np.abs(R).sum(), 1e-300)
+            assert EA[row] == 0.0
+            assert np.abs(A[row] - R).sum() <= 1e-12 * scale
         else:
-            # l1 error within the single-precision band 2^-14 S,
-            # S = sum_i w_i |a~x|_1 |a~y|_1 |a~z|_1 (oracle projections)
-            S = 0.0
-            rc2 = cells.rc2
-            for x, y, z, r in g200:
-                d = np.maximum(np.maximum(lo - [x, y, z], [x, y, z] - (lo + h)), 0)
-                if d @ d <= rc2:
-                    S += math.exp(D * r * r) * np.prod(
-                        [np.abs(oracle.project(D, lo[k], lo[k] + h, [x, y, z][k])).sum()
-                         for k in range(3)])
-            assert err <= S / 16384.0 + 1e-300
+            # the kernel's own a-posteriori l1 bound covers the difference
+            # to the exact-exponential tensor
+            err = np.abs(A[row] - A64[row]).sum()
+            assert err <= EA[row] + 1e-13 * scale
+            assert np.abs(A[row] - R).sum() <= EA[row] + 1e-12 * scale
+            if EA[row] > 0:
+                worst = max(worst, err / EA[row])
+    print("max actual/bound tensor error ratio %.3f" % worst)
     ctx.free_cells(cells)
+
+
+def test_fast_exp_error_bound(ctx):
+    # the guard band of the FP32+guard path assumes |exp_fast(x)/exp(x) - 1|
+    # <= 1.5e-7 for every x <= 0; sweep the range the kernels use densely
+    x = -np.concatenate([np.linspace(0.0, 60.0, 4_000_001),
+                         np.random.default_rng(3).uniform(0.0, 60.0, 2_000_000)])
+    y = ctx.debug_fast_exp(x).cpu().numpy()
+    rel = np.abs(y / np.exp(x) - 1.0)
+    print("fast exp max relative error %.3e" % rel.max())
+    assert rel.max() <= 1.5e-7
 
 
 def test_bound_parity(ctx, g200):
@@ -209,6 +226,7 @@ def test_bound_parity(ctx, g200):
     As.append(np.zeros(64))
     refs.append(oracle.bound(np.zeros(64)))
     out = ctx.debug_bound(np.array(As)).cpu().numpy()
+    assert out.shape[1] == 6
     refs = np.array(refs)
     for k in range(len(As)):
         scale = max(np.abs(As[k]).sum(), 1e-300)
