@@ -3,11 +3,12 @@
 //
 //   roots      Q_0: root cubes with a non-empty neighbourhood, raster order
 //   estimate   per cube: A = sum_i w_i a~x (x) a~y (x) a~z over the atoms within
-//              R_c of the cube (eqs. polynew, tensor1, tensor2), plus the l1
-//              scale S = sum_i w_i |a~x|_1 |a~y|_1 |a~z|_1 that sizes the
-//              single-precision error band
-//   decide     per cube: Step 3's stopping rule (2E <= tau, children only),
-//              else Step 2's bound test L <= c <= U, then leaf / divide
+//              R_c of the cube (eqs. polynew, tensor1, tensor2); its epilogue
+//              takes the decisions that need no bound (Step 3's stopping
+//              rule 2E <= tau for children; sampled values of P on both sides
+//              of c) and appends the other cubes to a dense "hard" list
+//   bound      per hard cube: Step 2's test L <= c <= U with the nested-SVD
+//              bound, then leaf / divide
 //   compaction stable: leaves in queue order, children of a divided cube in
 //              octant order at their parent's position
 #include "tms_device.h"
@@ -40,25 +41,119 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long 
     if ((threadIdx.x & 63) == 0) atomicAdd(ctr, v);
 }
 
-// One thread per cube.  The thread walks its root's neighbourhood list (all
-// threads of a wavefront usually share a root, so the list loads are
-// uniform), keeps the atoms within R_c of its own cube, projects the three
-// Gaussian factors and accumulates the 4x4x4 rank-one update in double
-// precision.  With FAST exponentials it also accumulates the l1 error bound
-// E of the tensor: a perturbation da of a factor moves w a (x) b (x) c by at
-// most w (|da| |b| |c| + |a| |db| |c| + |a| |b| |dc|) in l1.
-template <bool FAST, int QH>
-__global__ __launch_bounds__(kBS) void k_estimate(
+// ---------------------------------------------------------------------------
+// Estimate epilogue: the decisions that need no bound, and the hard list.
+// ---------------------------------------------------------------------------
+struct EstOut {
+    uint8_t *dec;        // [n] decision per queue entry (255: in the hard list)
+    double *hardA;       // [cap][64] tensors of hard cubes
+    double *hardE;       // [cap] their error bounds (0 for exact exponentials)
+    int32_t *hardIdx;    // [cap] their queue indices
+    unsigned *hardCount; // device counter (reset by the host per pass)
+};
+
+constexpr uint8_t DEC_HARD = 255;
+
+// slot of this lane in a list appended by the whole wavefront
+__device__ __forceinline__ unsigned wave_append(unsigned *ctr, bool want) {
+    const unsigned long long m = __ballot(want);
+    const int lane = threadIdx.x & 63;
+    unsigned base = 0;
+    const int leader = __ffsll((long long)m) - 1;
+    if (m && lane == leader) base = atomicAdd(ctr, (unsigned)__popcll(m));
+    base = __shfl(base, leader < 0 ? 0 : leader, 64);
+    return base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// l1 mass of the entries of degree above one (Step 3) and of all entries
+__device__ __forceinline__ void masses(const double *A, double &E, double &asum) {
+    E = 0.0;
+    asum = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const double v = fabs(A[16 * j + 4 * k + l]);
+                asum += v;
+                if (j >= 2 || k >= 2 || l >= 2) E += v;
+            }
+}
+
+// l1 error band of A: the accumulated bound of the FAST exponentials plus a
+// floor for double-precision rounding; zero for exact exponentials (no guard)
+__device__ __forceinline__ double error_band(bool fast, double EA, double asum) {
+    return fast ? EA + 1e-13 * asum : 0.0;
+}
+
+__device__ __forceinline__ uint8_t keep_code(const Grid &g, int level) {
+    return (level == g.K) ? DEC_HMIN : DEC_REFINE;
+}
+
+// Decisions without the bound; DEC_HARD when the bound is needed.
+__device__ __forceinline__ uint8_t easy_decision(const Grid &g, int level, bool fast,
+                                                 const double *A, double EA) {
+    double E, asum;
+    masses(A, E, asum);
+    const double band = error_band(fast, EA, asum);
+    if (level >= 1) {
+        // Step 3: higher-order mass under the user bound -> trilinear leaf
+        if (band > 0.0 && fabs(2.0 * E - g.tau) <= 2.0 * band) return DEC_GUARD;
+        if (2.0 * E <= g.tau) return DEC_CONV;
+    }
+    // two sampled values of P on either side of c imply L <= c <= U for every
+    // valid enclosure [L, U] of P, so Step 2 keeps the cube
+    double slo, shi;
+    sample_range(A, slo, shi);
+    const double tiny = 1e-12 * asum + band;
+    if (slo <= g.c - tiny && shi >= g.c + tiny) return keep_code(g, level);
+    return DEC_HARD;
+}
+
+__device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, const double *A,
+                                         double EA, int64_t qi, bool valid, const EstOut &o) {
+    const uint8_t d = valid ? easy_decision(g, level, fast, A, EA) : (uint8_t)0;
+    const bool hard = valid && d == DEC_HARD;
+    const unsigned slot = wave_append(o.hardCount, hard);
+    if (hard) {
+        double *dst = o.hardA + 64 * (int64_t)slot;
+#pragma unroll
+        for (int e = 0; e < 64; ++e) dst[e] = A[e];
+        o.hardE[slot] = EA;
+        o.hardIdx[slot] = (int32_t)qi;
+    }
+    if (valid) o.dec[qi] = d;
+}
+
+// ---------------------------------------------------------------------------
+// Tensor estimate, one thread per cube.  The thread walks its root's
+// neighbourhood list (threads of a wavefront usually share a root, so the
+// list loads are uniform), keeps the atoms within R_c of its own cube,
+// projects the three Gaussian factors and accumulates the 4x4x4 rank-one
+// update in double precision.  With FAST exponentials it also accumulates the
+// l1 error bound of the tensor: a perturbation da of a factor moves
+// w a (x) b (x) c by at most w (|da| |b| |c| + |a| |db| |c| + |a| |b| |dc|).
+// Used for the shallow levels (few cubes per root) and the debug hook.
+// ---------------------------------------------------------------------------
+template <bool FAST, int QH, bool EPI>
+__global__ __launch_bounds__(kBS) void k_estimate_thread(
     Grid g, int level, GLRule<double> R, const int4 *__restrict__ q, int64_t n,
     const int32_t *__restrict__ subset, const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
-    double *__restrict__ Aout, double *__restrict__ Eout, unsigned long long *__restrict__ pairs) {
-    int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    double *__restrict__ Aout, double *__restrict__ Eout, EstOut o,
+    unsigned long long *__restrict__ pairs) {
+    const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     unsigned long long np = 0;
-    if (t < n) {
-        int64_t qi = subset ? subset[t] : t;
-        int4 c = q[qi];
+    const bool valid = t < n;
+    const int64_t qi = valid ? (subset ? subset[t] : t) : 0;
+    double A[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) A[e] = 0.0;
+    double EA = 0.0;
+    if (valid) {
+        const int4 c = q[qi];
         const double h = ldexp(g.h0, -level);
         const double lo[3] = {g.o[0] + c.x * h, g.o[1] + c.y * h, g.o[2] + c.z * h};
         const double hi[3] = {lo[0] + h, lo[1] + h, lo[2] + h};
@@ -66,10 +161,6 @@ __global__ __launch_bounds__(kBS) void k_estimate(
         const double s = 0.5 * h;
         const int64_t root =
             ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
-        double A[64];
-#pragma unroll
-        for (int e = 0; e < 64; ++e) A[e] = 0.0;
-        double EA = 0.0;
         const int b = root_start[root], e_ = root_start[root + 1];
         for (int p = b; p < e_; ++p) {
             const int i = root_atoms[p];
@@ -101,6 +192,10 @@ __global__ __launch_bounds__(kBS) void k_estimate(
                 EA += w * ((ex * ny + nx * ey) * nz + nx * ny * ez);
             }
         }
+    }
+    if (EPI) {
+        epilogue(g, level, FAST, A, EA, qi, valid, o);
+    } else if (valid) {
         double *dst = Aout + 64 * qi;
 #pragma unroll
         for (int e = 0; e < 64; ++e) dst[e] = A[e];
@@ -109,73 +204,215 @@ __global__ __launch_bounds__(kBS) void k_estimate(
     if (pairs) wave_add(pairs, np);
 }
 
+// ---------------------------------------------------------------------------
+// Tensor estimate for deep levels: one 64-lane workgroup per chunk of at most
+// 64 consecutive queue entries of one root (a root's cubes are contiguous in
+// refinement order).  Atoms of the root list are staged CH at a time; an
+// atom farther than R_c from the chunk's bounding box is skipped by the whole
+// wavefront.  For the others, each 1-D projection (atom, axis, interval) is
+// computed once into LDS and shared by every cube of the chunk on that
+// interval; each lane then applies the per-cube R_c test and the rank-one
+// update of its cube.  Same arithmetic, in the same atom order, as the
+// per-thread kernel.
+// ---------------------------------------------------------------------------
+constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
+
+template <bool FAST, int QH, int CH>
+__global__ __launch_bounds__(64, 2) void k_estimate_tiled(
+    Grid g, int level, GLRule<double> R, const int4 *__restrict__ q,
+    const int2 *__restrict__ chunks, const int32_t *__restrict__ root_start,
+    const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
+    const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
+    EstOut o, unsigned long long *__restrict__ pairs) {
+    // tab[a][axis][iv] = {a0, a1, a2, a3, err, dist^2}
+    __shared__ double tab[CH][3][kTileIv][6];
+    __shared__ double s_w[CH];
+    __shared__ int s_use[CH];
+    const int lane = threadIdx.x;
+    const int2 ch = chunks[blockIdx.x];
+    const bool valid = lane < ch.y;
+    const int64_t qi = (int64_t)ch.x + (valid ? lane : 0);
+    const int4 c = q[qi];
+    const int4 c0 = q[ch.x];
+    const double h = ldexp(g.h0, -level);
+    const double s = 0.5 * h;
+    const int rxyz[3] = {c0.x >> level, c0.y >> level, c0.z >> level};
+    const int64_t root = ((int64_t)rxyz[2] * g.nr[1] + rxyz[1]) * g.nr[0] + rxyz[0];
+    // local interval indices of this lane's cube, and the chunk's range
+    const int li[3] = {c.x - (rxyz[0] << level), c.y - (rxyz[1] << level),
+                       c.z - (rxyz[2] << level)};
+    int mn[3], mx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int vlo = valid ? li[a] : 1 << 20, vhi = valid ? li[a] : -1;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            vlo = min(vlo, __shfl_xor(vlo, d, 64));
+            vhi = max(vhi, __shfl_xor(vhi, d, 64));
+        }
+        mn[a] = vlo;
+        mx[a] = vhi;
+    }
+    const int nv[3] = {mx[0] - mn[0] + 1, mx[1] - mn[1] + 1, mx[2] - mn[2] + 1};
+    double base[3], blo[3], bhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        base[a] = g.o[a] + (double)(rxyz[a] << level) * h;
+        blo[a] = base[a] + mn[a] * h;
+        bhi[a] = base[a] + (mx[a] + 1) * h;
+    }
+    const int rb = root_start[root], re = root_start[root + 1];
+    double A[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) A[e] = 0.0;
+    double EA = 0.0;
+    unsigned long long np = 0;
+    const int per_atom = nv[0] + nv[1] + nv[2];
+    for (int p0 = rb; p0 < re; p0 += CH) {
+        const int na = min(CH, re - p0);
+        if (lane < na) {
+            const int i = root_atoms[p0 + lane];
+            const double x[3] = {ax[i], ay[i], az[i]};
+            double d2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double d = fmax(fmax(blo[a] - x[a], x[a] - bhi[a]), 0.0);
+                d2 += d * d;
+            }
+            s_use[lane] = d2 <= g.rc2;
+            s_w[lane] = aw[i];
+        }
+        __syncthreads();
+        for (int w = lane; w < na * per_atom; w += 64) {
+            const int a_idx = w / per_atom;
+            if (!s_use[a_idx]) continue;
+            int r = w - a_idx * per_atom, axis = 0;
+            if (r >= nv[0]) {
+                r -= nv[0];
+                axis = 1;
+                if (r >= nv[1]) {
+                    r -= nv[1];
+                    axis = 2;
+                }
+            }
+            const int i = root_atoms[p0 + a_idx];
+            const double xa = axis == 0 ? ax[i] : (axis == 1 ? ay[i] : az[i]);
+            const double lo = base[axis] + (mn[axis] + r) * h, hi = lo + h;
+            const double d = fmax(fmax(lo - xa, xa - hi), 0.0);
+            double *t = tab[a_idx][axis][r];
+            t[5] = d * d;
+            double pr[4], err;
+            project<FAST, QH>(R, g.D, s, (lo + s) - xa, pr, err);
+            t[0] = pr[0];
+            t[1] = pr[1];
+            t[2] = pr[2];
+            t[3] = pr[3];
+            t[4] = err;
+        }
+        __syncthreads();
+        if (valid) {
+            const int lx = li[0] - mn[0], ly = li[1] - mn[1], lz = li[2] - mn[2];
+            for (int a = 0; a < na; ++a) {
+                if (!s_use[a]) continue;
+                const double *tx = tab[a][0][lx], *ty = tab[a][1][ly], *tz = tab[a][2][lz];
+                if (tx[5] + ty[5] + tz[5] > g.rc2) continue;
+                ++np;
+                const double px[4] = {tx[0], tx[1], tx[2], tx[3]};
+                const double py[4] = {ty[0], ty[1], ty[2], ty[3]};
+                const double pz[4] = {tz[0], tz[1], tz[2], tz[3]};
+                const double wgt = s_w[a];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double wx = wgt * px[j];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double wxy = wx * py[k];
+#pragma unroll
+                        for (int l = 0; l < 4; ++l) A[16 * j + 4 * k + l] += wxy * pz[l];
+                    }
+                }
+                if (FAST) {
+                    const double nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
+                    const double ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
+                    const double nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
+                    EA += wgt * ((tx[4] * ny + nx * ty[4]) * nz + nx * ny * tz[4]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    epilogue(g, level, FAST, A, EA, qi, valid, o);
+    if (pairs) wave_add(pairs, np);
+}
+
+// ---------------------------------------------------------------------------
+// Step 2 on the hard list: nested-SVD bound, keep iff L <= c <= U.  For
+// tensors built with FAST exponentials, a decision whose margin lies within
+// the error band amplified by the first-order factor amp, or a 0.99 rank rule
+// within its band, becomes DEC_GUARD and is redone with exact exponentials.
+// The list length is read on the device.
+// ---------------------------------------------------------------------------
+
 // Safety factor on the first-order perturbation estimate band * amp of the
-// bound (measured deviations of single-precision bounds stay below
-// 0.25 band * amp; see the calibration notes in the design document).
+// bound (measured deviations of bounds from FAST tensors stay below
+// 0.25 band * amp).
 constexpr double kKappa = 8.0;
 
-// Per-cube decision in double precision.  For tensors built with FAST
-// exponentials, decisions whose margin lies within the tensor's error band
-// (amplified for the bound by the first-order factor amp) become DEC_GUARD
-// and are redone with exact exponentials.
-__global__ __launch_bounds__(kBS) void k_decide(Grid g, int level, int fast,
-                                                const double *__restrict__ Ain,
-                                                const double *__restrict__ Ein, int64_t n,
-                                                const int32_t *__restrict__ subset,
-                                                uint8_t *__restrict__ dec,
-                                                unsigned long long *__restrict__ nbound) {
-    int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    unsigned long long nb = 0;
-    if (t < n) {
-        const int64_t qi = subset ? subset[t] : t;
-        double A[64];
-        const double *src = Ain + 64 * qi;
+__global__ __launch_bounds__(kBS) void k_bound(Grid g, int level, int fast, EstOut o) {
+    const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (t >= (int64_t)*o.hardCount) return;
+    double A[64];
+    const double *src = o.hardA + 64 * t;
 #pragma unroll
-        for (int e = 0; e < 64; ++e) A[e] = src[e];
-        double E = 0.0, asum = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const double v = fabs(A[16 * j + 4 * k + l]);
-                    asum += v;
-                    if (j >= 2 || k >= 2 || l >= 2) E += v;
-                }
-        // l1 error band of A: the accumulated bound of the FAST exponentials
-        // plus a floor for double-precision rounding; zero for exact
-        // exponentials (no guard)
-        const double band = fast ? Ein[qi] + 1e-13 * asum : 0.0;
-        uint8_t d = 255;
-        if (level >= 1) {
-            // Step 3: higher-order mass under the user bound -> trilinear leaf
-            if (band > 0.0 && fabs(2.0 * E - g.tau) <= 2.0 * band) d = DEC_GUARD;
-            else if (2.0 * E <= g.tau) d = DEC_CONV;
-        }
-        if (d == 255) {
-            bool keep;
-            // any two sampled values of P on either side of c imply
-            // L <= c <= U for every valid enclosure [L, U] of P
-            double slo, shi;
-            sample_range(A, slo, shi);
-            const double tiny = 1e-12 * asum + band;
-            if (slo <= g.c - tiny && shi >= g.c + tiny) {
-                keep = true;
-            } else {
-                ++nb;
-                BoundResult B = nested_bound(A, band);
-                if (band > 0.0 && (B.jump || fabs(B.L - g.c) <= kKappa * band * B.amp ||
-                                   fabs(B.U - g.c) <= kKappa * band * B.amp)) {
-                    d = DEC_GUARD;
-                }
-                keep = (B.L <= g.c && g.c <= B.U);  // Step 2
-            }
-            if (d == 255) d = keep ? ((level == g.K) ? DEC_HMIN : DEC_REFINE) : DEC_DISCARD;
-        }
-        dec[qi] = d;
-    }
-    if (nbound) wave_add(nbound, nb);
+    for (int e = 0; e < 64; ++e) A[e] = src[e];
+    double E, asum;
+    masses(A, E, asum);
+    const double band = error_band(fast != 0, o.hardE[t], asum);
+    const BoundResult B = nested_bound(A, band);
+    uint8_t d;
+    if (band > 0.0 && (B.jump || fabs(B.L - g.c) <= kKappa * band * B.amp ||
+                       fabs(B.U - g.c) <= kKappa * band * B.amp))
+        d = DEC_GUARD;
+    else
+        d = (B.L <= g.c && g.c <= B.U) ? keep_code(g, level) : DEC_DISCARD;
+    o.dec[o.hardIdx[t]] = d;
+}
+
+// chunking of a level queue into runs of one root, at most 64 entries each
+__device__ __forceinline__ int64_t root_of(const Grid &g, int level, int4 c) {
+    return ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
+}
+
+__global__ void k_run_flags(Grid g, int level, const int4 *__restrict__ q, int64_t n,
+                            int32_t *__restrict__ f) {
+    const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i >= n) return;
+    f[i] = (i == 0 || root_of(g, level, q[i]) != root_of(g, level, q[i - 1]) ||
+            q[i].w != q[i - 1].w) ? 1 : 0;
+}
+
+__global__ void k_run_starts(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
+                             int64_t n, int32_t *__restrict__ starts) {
+    const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i < n && f[i]) starts[off[i]] = (int32_t)i;
+}
+
+__global__ void k_run_chunk_counts(const int32_t *__restrict__ starts, int64_t nruns, int64_t n,
+                                   int32_t *__restrict__ cnt) {
+    const int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (r >= nruns) return;
+    const int64_t len = ((r + 1 < nruns) ? starts[r + 1] : n) - starts[r];
+    cnt[r] = (int32_t)((len + 63) / 64);
+}
+
+__global__ void k_run_chunk_emit(const int32_t *__restrict__ starts, int64_t nruns, int64_t n,
+                                 const int32_t *__restrict__ coff, int2 *__restrict__ chunks) {
+    const int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (r >= nruns) return;
+    const int64_t b = starts[r], len = ((r + 1 < nruns) ? starts[r + 1] : n) - b;
+    int2 *o = chunks + coff[r];
+    for (int64_t k = 0; k * 64 < len; ++k)
+        o[k] = make_int2((int32_t)(b + 64 * k), (int32_t)min<int64_t>(64, len - 64 * k));
 }
 
 __global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n, int32_t *__restrict__ f) {
@@ -259,28 +496,60 @@ __global__ void k_fast_exp_debug(const double *__restrict__ x, int64_t n, double
 }
 
 template <bool FAST, int QH>
-hipError_t estimate_t(const Grid &g, int level, const int4 *q, int64_t n, const int32_t *subset,
-                      const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
-                      const double *az, const double *aw, double *A, double *E,
-                      unsigned long long *pairs, hipStream_t s) {
+hipError_t estimate_thread_t(const Grid &g, int level, const int4 *q, int64_t n,
+                             const int32_t *subset, const int32_t *rs, const int32_t *ra,
+                             const double *ax, const double *ay, const double *az, const double *aw,
+                             double *A, double *E, const EstOut *o, unsigned long long *pairs,
+                             hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
-    hipLaunchKernelGGL((k_estimate<FAST, QH>), dim3(nblk(n)), dim3(kBS), 0, s, g, level, R, q, n,
-                       subset, rs, ra, ax, ay, az, aw, A, E, pairs);
+    if (o)
+        hipLaunchKernelGGL((k_estimate_thread<FAST, QH, true>), dim3(nblk(n)), dim3(kBS), 0, s, g,
+                           level, R, q, n, subset, rs, ra, ax, ay, az, aw, A, E, *o, pairs);
+    else
+        hipLaunchKernelGGL((k_estimate_thread<FAST, QH, false>), dim3(nblk(n)), dim3(kBS), 0, s, g,
+                           level, R, q, n, subset, rs, ra, ax, ay, az, aw, A, E, EstOut{}, pairs);
     return hipGetLastError();
 }
 
-template <bool FAST>
-hipError_t estimate_dispatch(int qh, const Grid &g, int level, const int4 *q, int64_t n,
-                             const int32_t *subset, const int32_t *rs, const int32_t *ra,
-                             const double *ax, const double *ay, const double *az, const double *aw,
-                             double *A, double *E, unsigned long long *pairs, hipStream_t s) {
-    switch (qh) {
-    case 4: return estimate_t<FAST, 4>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
-    case 5: return estimate_t<FAST, 5>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
-    case 6: return estimate_t<FAST, 6>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
-    case 8: return estimate_t<FAST, 8>(g, level, q, n, subset, rs, ra, ax, ay, az, aw, A, E, pairs, s);
-    default: return hipErrorInvalidValue;
+constexpr int kCH = 16;
+
+template <bool FAST, int QH>
+hipError_t estimate_tiled_t(const Grid &g, int level, const int4 *q, const int2 *chunks,
+                            int64_t nchunks, const int32_t *rs, const int32_t *ra, const double *ax,
+                            const double *ay, const double *az, const double *aw, const EstOut &o,
+                            unsigned long long *pairs, hipStream_t s) {
+    GLRule<double> R = gl_rule<double>(QH);
+    hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, kCH>), dim3((unsigned)nchunks), dim3(64), 0, s, g,
+                       level, R, q, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+    return hipGetLastError();
+}
+
+#define TMS_QH_SWITCH(qh, CALL)                    \
+    switch (qh) {                                  \
+    case 4: { constexpr int QH = 4; return CALL; } \
+    case 5: { constexpr int QH = 5; return CALL; } \
+    case 6: { constexpr int QH = 6; return CALL; } \
+    case 8: { constexpr int QH = 8; return CALL; } \
+    default: return hipErrorInvalidValue;          \
     }
+
+template <bool FAST>
+hipError_t thread_dispatch(int qh, const Grid &g, int level, const int4 *q, int64_t n,
+                           const int32_t *subset, const int32_t *rs, const int32_t *ra,
+                           const double *ax, const double *ay, const double *az, const double *aw,
+                           double *A, double *E, const EstOut *o, unsigned long long *pairs,
+                           hipStream_t s) {
+    TMS_QH_SWITCH(qh, (estimate_thread_t<FAST, QH>(g, level, q, n, subset, rs, ra, ax, ay, az, aw,
+                                                   A, E, o, pairs, s)))
+}
+
+template <bool FAST>
+hipError_t tiled_dispatch(int qh, const Grid &g, int level, const int4 *q, const int2 *chunks,
+                          int64_t nchunks, const int32_t *rs, const int32_t *ra, const double *ax,
+                          const double *ay, const double *az, const double *aw, const EstOut &o,
+                          unsigned long long *pairs, hipStream_t s) {
+    TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(g, level, q, chunks, nchunks, rs, ra, ax, ay, az,
+                                                  aw, o, pairs, s)))
 }
 
 }  // namespace
@@ -367,30 +636,88 @@ hipError_t launch_roots_emit(const Grid &g, const int32_t *flags, const int32_t 
     return hipGetLastError();
 }
 
+static int qh_for(const Grid &g, int level) {
+    return gl_half_nodes(0.5 * ldexp(g.h0, -level) * sqrt(g.D), false);
+}
+
 hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *q, int64_t n,
                            const int32_t *subset, const int32_t *root_start,
                            const int32_t *root_atoms, const double *ax, const double *ay,
                            const double *az, const double *aw, double *A, double *S,
                            int64_t *pairs, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const double beta = 0.5 * ldexp(g.h0, -level) * sqrt(g.D);
-    const bool fast = precision == TMS_PREC_FP32_GUARD;
-    const int qh = gl_half_nodes(beta, fast);
+    const int qh = qh_for(g, level);
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    if (fast)
-        return estimate_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay,
-                                       az, aw, A, S, pc, s);
-    return estimate_dispatch<false>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
-                                    aw, A, S, pc, s);
+    if (precision == TMS_PREC_FP32_GUARD)
+        return thread_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
+                                     aw, A, S, nullptr, pc, s);
+    return thread_dispatch<false>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az, aw,
+                                  A, S, nullptr, pc, s);
 }
 
-hipError_t launch_decide(const Grid &g, int level, int precision, const double *A, const double *S,
-                         int64_t n, const int32_t *subset, uint8_t *dec, int32_t *nbound,
-                         hipStream_t s) {
+hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+                                  const int32_t *subset, const int2 *chunks, int64_t nchunks,
+                                  const int32_t *root_start, const int32_t *root_atoms,
+                                  const double *ax, const double *ay, const double *az,
+                                  const double *aw, uint8_t *dec, double *hardA, double *hardE,
+                                  int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
+                                  hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int fast = (precision == TMS_PREC_FP32_GUARD) ? 1 : 0;
-    hipLaunchKernelGGL(k_decide, dim3(nblk(n)), dim3(kBS), 0, s, g, level, fast, A, S, n, subset,
-                       dec, reinterpret_cast<unsigned long long *>(nbound));
+    const int qh = qh_for(g, level);
+    const bool fast = precision == TMS_PREC_FP32_GUARD;
+    auto *pc = reinterpret_cast<unsigned long long *>(pairs);
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount};
+    if (chunks) {
+        if (nchunks <= 0) return hipSuccess;
+        if (fast)
+            return tiled_dispatch<true>(qh, g, level, q, chunks, nchunks, root_start, root_atoms, ax,
+                                        ay, az, aw, o, pc, s);
+        return tiled_dispatch<false>(qh, g, level, q, chunks, nchunks, root_start, root_atoms, ax,
+                                     ay, az, aw, o, pc, s);
+    }
+    if (fast)
+        return thread_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
+                                     aw, nullptr, nullptr, &o, pc, s);
+    return thread_dispatch<false>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az, aw,
+                                  nullptr, nullptr, &o, pc, s);
+}
+
+hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
+                        double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
+                        hipStream_t s) {
+    if (max_n <= 0) return hipSuccess;
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount};
+    hipLaunchKernelGGL(k_bound, dim3(nblk(max_n)), dim3(kBS), 0, s, g, level,
+                       precision == TMS_PREC_FP32_GUARD ? 1 : 0, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, int64_t n, int32_t *f,
+                            hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, n, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, int32_t *starts,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run_starts, dim3(nblk(n)), dim3(kBS), 0, s, f, off, n, starts);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
+                                   hipStream_t s) {
+    if (nruns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run_chunk_counts, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n,
+                                 const int32_t *coff, int2 *chunks, hipStream_t s) {
+    if (nruns <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_run_chunk_emit, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, coff,
+                       chunks);
     return hipGetLastError();
 }
 

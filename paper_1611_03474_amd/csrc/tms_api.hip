@@ -367,7 +367,8 @@ int32_t tms_destroy(tms_ctx *ctx) {
                            &ctx->qmeta, &ctx->abuf, &ctx->ebuf, &ctx->dec, &ctx->scan_a,
                            &ctx->scan_b, &ctx->scan_c, &ctx->flags, &ctx->idx, &ctx->hkeys,
                            &ctx->hown, &ctx->slot, &ctx->uniq, &ctx->uphi, &ctx->uguard, &ctx->lc,
-                           &ctx->ctmp, &ctx->counters, &ctx->hostpin};
+                           &ctx->ctmp, &ctx->counters, &ctx->hostpin, &ctx->hidx, &ctx->chunks,
+                           &ctx->runs};
     for (auto *b : bufs) b->release();
     timing_flush(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -661,27 +662,62 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             st.n_est[lev] = nq;
             HIPCK(ctx->abuf.ensure(sizeof(double) * 64 * (size_t)nq));
             HIPCK(ctx->ebuf.ensure(sizeof(double) * (size_t)nq));
+            HIPCK(ctx->hidx.ensure(sizeof(int32_t) * (size_t)nq));
             HIPCK(ctx->dec.ensure((size_t)nq));
+            HIPCK(ctx->flags.ensure(4 * (size_t)nq));
+            HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
+            HIPCK(ctx->scan_b.ensure(4 * (size_t)nq));
+            HIPCK(ctx->idx.ensure(4 * (size_t)nq));
             HIPCK(hipMemsetAsync(ctr, 0, 256, s));
+            unsigned *hard1 = reinterpret_cast<unsigned *>(ctr + 20);
+            unsigned *hard2 = reinterpret_cast<unsigned *>(ctr + 21);
             const int4 *q = ctx->q[cur].as<int4>();
-            {  // Step 1: tensor of every queued cube
-                TimedScope ts_(ctx, TMS_T_ESTIMATE);
-                HIPCK(launch_estimate(g, lev, prec, q, nq, nullptr, cells->root_start.as<int32_t>(),
-                                      cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
-                                      cells->ay.as<double>(), cells->az.as<double>(),
-                                      cells->aw.as<double>(), ctx->abuf.as<double>(),
-                                      ctx->ebuf.as<double>(), reinterpret_cast<int64_t *>(ctr + 0),
-                                      s));
+            // deep levels: chunks of <= 64 consecutive cubes of one root
+            const int2 *chunks = nullptr;
+            int64_t nchunks = 0;
+            if (lev >= 2 && lev <= 3) {
+                int64_t nruns = 0;
+                {
+                    TimedScope ts_(ctx, TMS_T_COMPACT);
+                    HIPCK(launch_run_flags(g, lev, q, nq, ctx->flags.as<int32_t>(), s));
+                }
+                rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &nruns);
+                if (rc) return rc;
+                HIPCK(ctx->runs.ensure(4 * (size_t)std::max<int64_t>(nruns, 1)));
+                {
+                    TimedScope ts_(ctx, TMS_T_COMPACT);
+                    HIPCK(launch_run_starts(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq,
+                                            ctx->runs.as<int32_t>(), s));
+                    HIPCK(launch_run_chunk_counts(ctx->runs.as<int32_t>(), nruns, nq,
+                                                  ctx->flags.as<int32_t>(), s));
+                }
+                rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), nruns,
+                                &nchunks);
+                if (rc) return rc;
+                HIPCK(ctx->chunks.ensure(sizeof(int2) * (size_t)std::max<int64_t>(nchunks, 1)));
+                {
+                    TimedScope ts_(ctx, TMS_T_COMPACT);
+                    HIPCK(launch_run_chunk_emit(ctx->runs.as<int32_t>(), nruns, nq,
+                                                ctx->scan_b.as<int32_t>(), ctx->chunks.as<int2>(),
+                                                s));
+                }
+                chunks = ctx->chunks.as<int2>();
             }
-            {  // Steps 2-3: stopping rule and bound test
+            {  // Step 1 (tensor) and the decisions that need no bound
+                TimedScope ts_(ctx, TMS_T_ESTIMATE);
+                HIPCK(launch_estimate_decide(
+                    g, lev, prec, q, nq, nullptr, chunks, nchunks, cells->root_start.as<int32_t>(),
+                    cells->root_atoms.as<int32_t>(), cells->ax.as<double>(), cells->ay.as<double>(),
+                    cells->az.as<double>(), cells->aw.as<double>(), ctx->dec.as<uint8_t>(),
+                    ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard1,
+                    reinterpret_cast<int64_t *>(ctr + 0), s));
+            }
+            {  // Step 2: nested-SVD bound on the cubes that need it
                 TimedScope ts_(ctx, TMS_T_DECIDE);
-                HIPCK(launch_decide(g, lev, prec, ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
-                                    nq, nullptr, ctx->dec.as<uint8_t>(),
-                                    reinterpret_cast<int32_t *>(ctr + 1), s));
+                HIPCK(launch_bound(g, lev, prec, nq, ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
+                                   ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard1, s));
             }
             if (prec == TMS_PREC_FP32_GUARD) {
-                HIPCK(ctx->flags.ensure(4 * (size_t)nq));
-                HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
                 {
                     TimedScope ts_(ctx, TMS_T_COMPACT);
                     HIPCK(launch_guard_list_flags(ctx->dec.as<uint8_t>(), nq,
@@ -691,27 +727,21 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &ng);
                 if (rc) return rc;
                 if (ng > 0) {
-                    HIPCK(ctx->idx.ensure(4 * (size_t)ng));
                     TimedScope ts_(ctx, TMS_T_GUARD);
                     HIPCK(launch_guard_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(),
                                                  nq, ctx->idx.as<int32_t>(), s));
-                    HIPCK(launch_estimate(g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(),
-                                          cells->root_start.as<int32_t>(),
-                                          cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
-                                          cells->ay.as<double>(), cells->az.as<double>(),
-                                          cells->aw.as<double>(), ctx->abuf.as<double>(),
-                                          ctx->ebuf.as<double>(), nullptr, s));
-                    HIPCK(launch_decide(g, lev, TMS_PREC_FP64, ctx->abuf.as<double>(),
-                                        ctx->ebuf.as<double>(), ng, ctx->idx.as<int32_t>(),
-                                        ctx->dec.as<uint8_t>(), reinterpret_cast<int32_t *>(ctr + 1),
-                                        s));
+                    HIPCK(launch_estimate_decide(
+                        g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(), nullptr, 0,
+                        cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
+                        cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
+                        cells->aw.as<double>(), ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
+                        ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard2, nullptr, s));
+                    HIPCK(launch_bound(g, lev, TMS_PREC_FP64, ng, ctx->dec.as<uint8_t>(),
+                                       ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
+                                       ctx->hidx.as<int32_t>(), hard2, s));
                 }
                 st.guard_cubes += ng;
             }
-            HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
-            HIPCK(ctx->scan_b.ensure(4 * (size_t)nq));
-            HIPCK(ctx->flags.ensure(4 * (size_t)nq));
-            HIPCK(ctx->idx.ensure(4 * (size_t)nq));
             int32_t *lcnt = ctx->flags.as<int32_t>(), *ccnt = ctx->idx.as<int32_t>();
             {
                 TimedScope ts_(ctx, TMS_T_COMPACT);
@@ -723,10 +753,10 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             if (rc) return rc;
             rc = scan_total(ctx, ccnt, ctx->scan_b.as<int32_t>(), nq, &nc);
             if (rc) return rc;
-            unsigned long long h[16];
-            HIPCK(d2h(h, ctr, 16, s));
+            unsigned long long h[24];
+            HIPCK(d2h(h, ctr, 24, s));
             st.n_pairs += (int64_t)h[0];
-            st.n_bound += (int64_t)h[1];
+            st.n_bound += (int64_t)(h[20] & 0xFFFFFFFFull) + (int64_t)(h[21] & 0xFFFFFFFFull);
             st.n_disc[lev] = (int64_t)h[8 + DEC_DISCARD];
             st.n_refine[lev] = (int64_t)h[8 + DEC_REFINE];
             st.n_conv[lev] = (int64_t)h[8 + DEC_CONV];

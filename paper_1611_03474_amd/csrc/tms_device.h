@@ -252,12 +252,17 @@ __device__ __forceinline__ double sgap(const double s[4], int i) {
 // (A1 A1^T, then V_i V_i^T), sigma = sqrt(lambda), right vectors by
 // back-substitution.
 //
+// The residual R = A - A~ is formed in place: subtracting sigma_i u_i (x) V~_i
+// does not change u_j^T A1 for j > i (the u are orthonormal), so the later
+// right vectors come out the same, and rho = sum |R| is read off at the end.
+// A is overwritten.
+//
 // With band > 0 (A known only up to an l1 perturbation of that size) it also
 // reports whether a rank decision could flip (jump) and a first-order
 // amplification factor amp: singular values move by at most band, singular
 // vectors rotate by about band / gap (Wedin), and the interval bound moves by
 // about sigma times that rotation, so |dL|, |dU| <~ band * amp.
-__device__ inline BoundResult nested_bound(const double *A, double band) {
+__device__ inline BoundResult nested_bound(double *A, double band) {
     BoundResult R;
     R.jump = false;
     R.amp = 1.0;
@@ -280,9 +285,6 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
     int r = rank99(sig, mhi, mlo);
     R.r = r;
     if (band > 0.0 && (mhi <= 8.0 * band || mlo <= 8.0 * band)) R.jump = true;
-    double At[64];
-#pragma unroll
-    for (int e = 0; e < 64; ++e) At[e] = 0.0;
     double Msum = 0.0, msum = 0.0;
     for (int i = 0; i < r; ++i) {
         double u[4] = {W[0][i], W[1][i], W[2][i], W[3][i]};
@@ -329,6 +331,7 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
 #pragma unroll
             for (int l = 0; l < 4; ++l)
                 z[l] = (w[0] * v[l] + w[1] * v[4 + l] + w[2] * v[8 + l] + w[3] * v[12 + l]) * iz;
+            // residual: A -= sigma_i u_i (x) d_k w_k (x) z_k  (eq. SVD7)
             double coef = sig[i] * d[k];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -336,7 +339,7 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
                 for (int kk = 0; kk < 4; ++kk) {
                     double cjk = coef * u[j] * w[kk];
 #pragma unroll
-                    for (int l = 0; l < 4; ++l) At[16 * j + 4 * kk + l] += cjk * z[l];
+                    for (int l = 0; l < 4; ++l) A[16 * j + 4 * kk + l] -= cjk * z[l];
                 }
             double w0, w1, z0, z1, p0, p1;
             leg3_range(w, w0, w1);
@@ -352,7 +355,7 @@ __device__ inline BoundResult nested_bound(const double *A, double band) {
     }
     double rho = 0.0;
 #pragma unroll
-    for (int e = 0; e < 64; ++e) rho += fabs(A[e] - At[e]);
+    for (int e = 0; e < 64; ++e) rho += fabs(A[e]);
     R.rho = rho;
     R.L = msum - rho;
     R.U = Msum + rho;

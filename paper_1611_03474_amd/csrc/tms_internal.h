@@ -102,7 +102,7 @@ struct tms_ctx {
     int64_t n_verts = 0;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
-        slot, uniq, uphi, uguard, lc, ctmp;
+        slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs;
     tms::DevBuf counters;  // small device counters
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -165,9 +165,26 @@ hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *
                            const int32_t *root_atoms, const double *ax, const double *ay,
                            const double *az, const double *aw, double *A, double *E,
                            int64_t *pairs, hipStream_t s);
-hipError_t launch_decide(const Grid &g, int level, int precision, const double *A,
-                         const double *E, int64_t n, const int32_t *subset, uint8_t *dec,
-                         int32_t *nbound, hipStream_t s);
+// estimate + easy decisions; cubes needing the bound go to the hard list.
+// chunks != nullptr selects the tiled kernel (levels 2..3, no subset).
+hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+                                  const int32_t *subset, const int2 *chunks, int64_t nchunks,
+                                  const int32_t *root_start, const int32_t *root_atoms,
+                                  const double *ax, const double *ay, const double *az,
+                                  const double *aw, uint8_t *dec, double *hardA, double *hardE,
+                                  int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
+                                  hipStream_t s);
+hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
+                        double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
+                        hipStream_t s);
+hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, int64_t n, int32_t *f,
+                            hipStream_t s);
+hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, int32_t *starts,
+                             hipStream_t s);
+hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
+                                   hipStream_t s);
+hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n,
+                                 const int32_t *coff, int2 *chunks, hipStream_t s);
 hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s);
 hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
                                   int32_t *list, hipStream_t s);
