@@ -200,10 +200,9 @@ int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64
 /* Edge intersection points of the trilinear surface g = c (eq. intersection):
  * on every edge of a SURFACE leaf whose end signs differ, g is linear, and
  * the point is at t = (c - phi0)/(phi1 - phi0) from the lower end.  An edge
- * shared by leaves of the same level is emitted once, by the first leaf (in
- * input order) that has it.  Vertices come out in (leaf, edge) order, the 12
- * edges of a leaf ordered by axis, then by the offsets of the two other axes
- * (lower axis first).
+ * shared by leaves of the same level is emitted once.  Vertices come out in
+ * ascending edge_key order.  Leaves that share an edge must carry the same
+ * values at its ends (the corner values tms_partition_estimate produces do).
  *  leaves     device [n] tms_leaf (as produced by tms_partition_estimate).
  *  corner_phi device [n][8] double, or NULL to evaluate phi at the corners.
  *  out        device [cap] tms_vertex, or NULL to only count.
@@ -258,9 +257,10 @@ int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cu
  *  band  device [n] double or NULL (zeros): l1 perturbation size for the
  *        stability flag;
  *  out   device [n][6] double: L, U, rho (l1 mass of the residual tensor),
- *        r (outer rank kept by the 0.99 rule), jump (1 if a 0.99 rank rule
- *        lies within the perturbation band, else 0), amp (first-order factor
- *        by which an l1 perturbation of A of size band can move L and U). */
+ *        r (outer rank kept by the 0.99 rule), jump (largest move of L and U
+ *        that a 0.99 rank rule flipping within the perturbation band could
+ *        cause; 0 if none can flip), amp (first-order factor by which an l1
+ *        perturbation of A of size band can move L and U). */
 int32_t tms_debug_bound(tms_ctx *ctx, const double *A, const double *band, int64_t n,
                         double *out);
 

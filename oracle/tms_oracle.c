@@ -713,6 +713,13 @@ static int cmp_u64(const void *a, const void *b)
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
+static const uint64_t *sort_keys_ctx;
+static int cmp_by_key(const void *a, const void *b)
+{
+    uint64_t x = sort_keys_ctx[*(const int64_t *)a], y = sort_keys_ctx[*(const int64_t *)b];
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
 static int64_t find_u64(const uint64_t *v, int64_t n, uint64_t key)
 {
     int64_t lo = 0, hi = n - 1;
@@ -1030,7 +1037,7 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
      * t = (c - phi0) / (phi1 - phi0), measured from the lower end.  Edges are
      * visited leaf by leaf (leaf order), edge by edge (axis-major; inside an
      * axis the two other offsets with the lower axis first); an edge key that
-     * was already emitted is skipped. */
+     * was already emitted is skipped.  The list is finally sorted by key. */
     int64_t vcap = 1024, nv = 0;
     R->vkey = (uint64_t *)malloc(sizeof(uint64_t) * vcap);
     R->vt = (double *)malloc(sizeof(double) * vcap);
@@ -1089,6 +1096,30 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
     }
     free(hset);
     R->n_vert = nv;
+    /* canonical order of the vertex list: ascending edge key */
+    {
+        int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv ? nv : 1));
+        for (int64_t i = 0; i < nv; ++i)
+            ord[i] = i;
+        sort_keys_ctx = R->vkey;
+        qsort(ord, (size_t)nv, sizeof(int64_t), cmp_by_key);
+        uint64_t *k2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nv ? nv : 1));
+        double *t2 = (double *)malloc(sizeof(double) * (size_t)(nv ? nv : 1));
+        double *x2 = (double *)malloc(sizeof(double) * 3 * (size_t)(nv ? nv : 1));
+        for (int64_t i = 0; i < nv; ++i) {
+            k2[i] = R->vkey[ord[i]];
+            t2[i] = R->vt[ord[i]];
+            for (int a = 0; a < 3; ++a)
+                x2[3 * i + a] = R->vxyz[3 * ord[i] + a];
+        }
+        free(R->vkey);
+        free(R->vt);
+        free(R->vxyz);
+        R->vkey = k2;
+        R->vt = t2;
+        R->vxyz = x2;
+        free(ord);
+    }
     bins_free(&bins);
     return R;
 #undef PUSH_LEAF

@@ -119,7 +119,80 @@ __global__ void k_edge_count(const tms_leaf *__restrict__ leaves, int64_t n,
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
+// ---- dense-bitmap edge de-duplication ------------------------------------
+__device__ __forceinline__ int64_t edge_bit(const EdgeLat &el, const tms_leaf &L, int axis,
+                                            const int off[3]) {
+    const Lat &lat = el.l[L.level][axis];
+    return (lat.base << 6) +
+           (((int64_t)(L.ix + off[0]) * lat.n[1] + (L.iy + off[1])) * lat.n[2] + (L.iz + off[2]));
+}
+
+__global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n, EdgeLat el,
+                            unsigned long long *__restrict__ bm) {
+    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= 12 * n) return;
+    const tms_leaf L = leaves[c / 12];
+    if (L.cls != TMS_CLS_SURFACE) return;
+    int axis, off[3], v0, v1;
+    edge_corners((int)(c % 12), axis, off, v0, v1);
+    if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) return;
+    const int64_t b = edge_bit(el, L, axis, off);
+    atomicOr(bm + (b >> 6), 1ull << (b & 63));
+}
+
+// every leaf that has a crossing edge writes its vertex at the edge's rank
+// (leaves sharing the edge share its corner values, so they write the same
+// bits); the list comes out in edge-key order
+__global__ void k_edge_write(Grid g, const tms_leaf *__restrict__ leaves,
+                             const double *__restrict__ cphi, int64_t n, EdgeLat el,
+                             const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
+                             tms_vertex *__restrict__ out) {
+    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= 12 * n) return;
+    const int64_t q = c / 12;
+    const tms_leaf L = leaves[q];
+    if (L.cls != TMS_CLS_SURFACE) return;
+    int axis, off[3], v0, v1;
+    edge_corners((int)(c % 12), axis, off, v0, v1);
+    if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) return;
+    const int64_t b = edge_bit(el, L, axis, off);
+    const int64_t w = b >> 6;
+    const int64_t r = (int64_t)woff[w] + __popcll(bm[w] & ((1ull << (b & 63)) - 1ull));
+    const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
+    const int sh = g.K - L.level;
+    const double h = ldexp(g.h0, -(int)L.level);
+    double p[3] = {g.o[0] + (double)((L.ix + off[0]) << sh) * g.hmin,
+                   g.o[1] + (double)((L.iy + off[1]) << sh) * g.hmin,
+                   g.o[2] + (double)((L.iz + off[2]) << sh) * g.hmin};
+    const double t = (g.c - f0) / (f1 - f0);
+    p[axis] += t * h;
+    tms_vertex V;
+    V.edge_key = edge_key(L, axis, off, g.K);
+    V.t = t;
+    V.x = p[0];
+    V.y = p[1];
+    V.z = p[2];
+    out[r] = V;
+}
+
 }  // namespace
+
+hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, int K, const EdgeLat &el,
+                            unsigned long long *bm, hipStream_t s) {
+    (void)K;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, el, bm);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_write(const Grid &g, const tms_leaf *leaves, const double *cphi, int64_t n,
+                             const EdgeLat &el, const uint64_t *bm, const int32_t *woff,
+                             tms_vertex *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_write, dim3(nblk(12 * n)), dim3(kBS), 0, s, g, leaves, cphi, n, el, bm,
+                       woff, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_edge_count(const tms_leaf *leaves, int64_t n, unsigned long long *count,
                              hipStream_t s) {

@@ -206,8 +206,8 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
 
 // ---------------------------------------------------------------------------
 // Tensor estimate for deep levels: one 64-lane workgroup per chunk of at most
-// 64 consecutive queue entries of one root (a root's cubes are contiguous in
-// refinement order).  Atoms of the root list are staged CH at a time; an
+// 64 consecutive queue entries (or entries of a sorted subset of the queue)
+// of one root (a root's cubes are contiguous in refinement order).  Atoms of the root list are staged CH at a time; an
 // atom farther than R_c from the chunk's bounding box is skipped by the whole
 // wavefront.  For the others, each 1-D projection (atom, axis, interval) is
 // computed once into LDS and shared by every cube of the chunk on that
@@ -220,7 +220,8 @@ constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
 template <bool FAST, int QH, int CH>
 __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     Grid g, int level, GLRule<double> R, const int4 *__restrict__ q,
-    const int2 *__restrict__ chunks, const int32_t *__restrict__ root_start,
+    const int32_t *__restrict__ subset, const int2 *__restrict__ chunks,
+    const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
     EstOut o, unsigned long long *__restrict__ pairs) {
@@ -231,9 +232,10 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const int lane = threadIdx.x;
     const int2 ch = chunks[blockIdx.x];
     const bool valid = lane < ch.y;
-    const int64_t qi = (int64_t)ch.x + (valid ? lane : 0);
+    const int64_t pos = (int64_t)ch.x + (valid ? lane : 0);
+    const int64_t qi = subset ? subset[pos] : pos;
     const int4 c = q[qi];
-    const int4 c0 = q[ch.x];
+    const int4 c0 = q[subset ? subset[ch.x] : ch.x];
     const double h = ldexp(g.h0, -level);
     const double s = 0.5 * h;
     const int rxyz[3] = {c0.x >> level, c0.y >> level, c0.z >> level};
@@ -347,9 +349,9 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
 
 // ---------------------------------------------------------------------------
 // Step 2 on the hard list: nested-SVD bound, keep iff L <= c <= U.  For
-// tensors built with FAST exponentials, a decision whose margin lies within
-// the error band amplified by the first-order factor amp, or a 0.99 rank rule
-// within its band, becomes DEC_GUARD and is redone with exact exponentials.
+// tensors built with FAST exponentials, a decision whose margin |L - c| or
+// |U - c| lies within kKappa * band * amp plus the rank-flip cap becomes
+// DEC_GUARD and is redone with exact exponentials.
 // The list length is read on the device.
 // ---------------------------------------------------------------------------
 
@@ -370,8 +372,8 @@ __global__ __launch_bounds__(kBS) void k_bound(Grid g, int level, int fast, EstO
     const double band = error_band(fast != 0, o.hardE[t], asum);
     const BoundResult B = nested_bound(A, band);
     uint8_t d;
-    if (band > 0.0 && (B.jump || fabs(B.L - g.c) <= kKappa * band * B.amp ||
-                       fabs(B.U - g.c) <= kKappa * band * B.amp))
+    const double tol = kKappa * band * B.amp + B.jump;
+    if (band > 0.0 && (fabs(B.L - g.c) <= tol || fabs(B.U - g.c) <= tol))
         d = DEC_GUARD;
     else
         d = (B.L <= g.c && g.c <= B.U) ? keep_code(g, level) : DEC_DISCARD;
@@ -383,12 +385,17 @@ __device__ __forceinline__ int64_t root_of(const Grid &g, int level, int4 c) {
     return ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
 }
 
-__global__ void k_run_flags(Grid g, int level, const int4 *__restrict__ q, int64_t n,
+__global__ void k_run_flags(Grid g, int level, const int4 *__restrict__ q,
+                            const int32_t *__restrict__ subset, int64_t n,
                             int32_t *__restrict__ f) {
     const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (i >= n) return;
-    f[i] = (i == 0 || root_of(g, level, q[i]) != root_of(g, level, q[i - 1]) ||
-            q[i].w != q[i - 1].w) ? 1 : 0;
+    if (i == 0) {
+        f[i] = 1;
+        return;
+    }
+    const int4 a = q[subset ? subset[i] : i], b = q[subset ? subset[i - 1] : i - 1];
+    f[i] = (root_of(g, level, a) != root_of(g, level, b) || a.w != b.w) ? 1 : 0;
 }
 
 __global__ void k_run_starts(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(kBS) void k_bound_debug(const double *__restrict__ 
     out[6 * t + 1] = B.U;
     out[6 * t + 2] = B.rho;
     out[6 * t + 3] = (double)B.r;
-    out[6 * t + 4] = B.jump ? 1.0 : 0.0;
+    out[6 * t + 4] = B.jump;
     out[6 * t + 5] = B.amp;
 }
 
@@ -514,13 +521,14 @@ hipError_t estimate_thread_t(const Grid &g, int level, const int4 *q, int64_t n,
 constexpr int kCH = 16;
 
 template <bool FAST, int QH>
-hipError_t estimate_tiled_t(const Grid &g, int level, const int4 *q, const int2 *chunks,
-                            int64_t nchunks, const int32_t *rs, const int32_t *ra, const double *ax,
-                            const double *ay, const double *az, const double *aw, const EstOut &o,
-                            unsigned long long *pairs, hipStream_t s) {
+hipError_t estimate_tiled_t(const Grid &g, int level, const int4 *q, const int32_t *subset,
+                            const int2 *chunks, int64_t nchunks, const int32_t *rs,
+                            const int32_t *ra, const double *ax, const double *ay, const double *az,
+                            const double *aw, const EstOut &o, unsigned long long *pairs,
+                            hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
     hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, kCH>), dim3((unsigned)nchunks), dim3(64), 0, s, g,
-                       level, R, q, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+                       level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
     return hipGetLastError();
 }
 
@@ -544,12 +552,12 @@ hipError_t thread_dispatch(int qh, const Grid &g, int level, const int4 *q, int6
 }
 
 template <bool FAST>
-hipError_t tiled_dispatch(int qh, const Grid &g, int level, const int4 *q, const int2 *chunks,
-                          int64_t nchunks, const int32_t *rs, const int32_t *ra, const double *ax,
-                          const double *ay, const double *az, const double *aw, const EstOut &o,
-                          unsigned long long *pairs, hipStream_t s) {
-    TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(g, level, q, chunks, nchunks, rs, ra, ax, ay, az,
-                                                  aw, o, pairs, s)))
+hipError_t tiled_dispatch(int qh, const Grid &g, int level, const int4 *q, const int32_t *subset,
+                          const int2 *chunks, int64_t nchunks, const int32_t *rs, const int32_t *ra,
+                          const double *ax, const double *ay, const double *az, const double *aw,
+                          const EstOut &o, unsigned long long *pairs, hipStream_t s) {
+    TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(g, level, q, subset, chunks, nchunks, rs, ra, ax,
+                                                  ay, az, aw, o, pairs, s)))
 }
 
 }  // namespace
@@ -670,10 +678,10 @@ hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
-            return tiled_dispatch<true>(qh, g, level, q, chunks, nchunks, root_start, root_atoms, ax,
-                                        ay, az, aw, o, pc, s);
-        return tiled_dispatch<false>(qh, g, level, q, chunks, nchunks, root_start, root_atoms, ax,
-                                     ay, az, aw, o, pc, s);
+            return tiled_dispatch<true>(qh, g, level, q, subset, chunks, nchunks, root_start,
+                                        root_atoms, ax, ay, az, aw, o, pc, s);
+        return tiled_dispatch<false>(qh, g, level, q, subset, chunks, nchunks, root_start,
+                                     root_atoms, ax, ay, az, aw, o, pc, s);
     }
     if (fast)
         return thread_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
@@ -692,10 +700,10 @@ hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, 
     return hipGetLastError();
 }
 
-hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, int64_t n, int32_t *f,
-                            hipStream_t s) {
+hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, const int32_t *subset,
+                            int64_t n, int32_t *f, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, n, f);
+    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, subset, n, f);
     return hipGetLastError();
 }
 

@@ -236,7 +236,117 @@ __global__ void k_count_surface(const tms_leaf *__restrict__ leaves, int64_t n,
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
+// ---- dense-bitmap corner de-duplication -----------------------------------
+// Corner bitmaps are tiled: one 64-bit word per 4x4x4 block of lattice
+// points (lat.n counts blocks per axis), blocks in raster order, so the
+// unique corners come out in compact spatial groups and a wavefront of the
+// phi kernel works on neighbouring points.
+__device__ __forceinline__ int64_t lat_bit(const Lat &lat, int64_t X, int64_t Y, int64_t Z) {
+    const int64_t w = ((X >> 2) * lat.n[1] + (Y >> 2)) * lat.n[2] + (Z >> 2);
+    return ((lat.base + w) << 6) + ((X & 3) << 4) + ((Y & 3) << 2) + (Z & 3);
+}
+
+__device__ __forceinline__ int64_t bit_rank(const uint64_t *__restrict__ bm,
+                                            const int32_t *__restrict__ woff, int64_t b) {
+    const int64_t w = b >> 6;
+    const uint64_t below = bm[w] & ((1ull << (b & 63)) - 1ull);
+    return (int64_t)woff[w] + __popcll(below);
+}
+
+__device__ __forceinline__ void leaf_corner(const tms_leaf &L, int v, int K, int64_t &X, int64_t &Y,
+                                            int64_t &Z) {
+    const int sh = K - L.level;
+    X = (int64_t)(L.ix + (v & 1)) << sh;
+    Y = (int64_t)(L.iy + ((v >> 1) & 1)) << sh;
+    Z = (int64_t)(L.iz + ((v >> 2) & 1)) << sh;
+}
+
+__global__ void k_popc(const uint64_t *__restrict__ bm, int64_t nw, int32_t *__restrict__ cnt) {
+    const int64_t w = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (w < nw) cnt[w] = __popcll(bm[w]);
+}
+
+__global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, int K, Lat lat,
+                              unsigned long long *__restrict__ bm) {
+    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= 8 * n) return;
+    const tms_leaf L = leaves[c >> 3];
+    int64_t X, Y, Z;
+    leaf_corner(L, (int)(c & 7), K, X, Y, Z);
+    const int64_t b = lat_bit(lat, X, Y, Z);
+    atomicOr(bm + (b >> 6), 1ull << (b & 63));
+}
+
+// every candidate writes its corner's coordinates at the corner's rank (all
+// writers of one corner write the same bits)
+__global__ void k_corner_write(const tms_leaf *__restrict__ leaves, int64_t n, int K, Lat lat,
+                               const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
+                               Grid g, double *__restrict__ upts) {
+    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (c >= 8 * n) return;
+    const tms_leaf L = leaves[c >> 3];
+    int64_t X, Y, Z;
+    leaf_corner(L, (int)(c & 7), K, X, Y, Z);
+    const int64_t u = bit_rank(bm, woff, lat_bit(lat, X, Y, Z));
+    upts[3 * u] = g.o[0] + (double)X * g.hmin;
+    upts[3 * u + 1] = g.o[1] + (double)Y * g.hmin;
+    upts[3 * u + 2] = g.o[2] + (double)Z * g.hmin;
+}
+
+__global__ void k_corner_gather_bm(const tms_leaf *__restrict__ lin, int64_t n, int K, Lat lat,
+                                   const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
+                                   const double *__restrict__ uphi, double c,
+                                   tms_leaf *__restrict__ lout, double *__restrict__ cphi) {
+    const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n) return;
+    tms_leaf L = lin[q];
+    double f[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        int64_t X, Y, Z;
+        leaf_corner(L, v, K, X, Y, Z);
+        f[v] = uphi[bit_rank(bm, woff, lat_bit(lat, X, Y, Z))];
+    }
+    classify(L, f, c);
+    lout[q] = L;
+    if (cphi) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) cphi[8 * q + v] = f[v];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStream_t s) {
+    if (nwords <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_popc, dim3(nblk(nwords)), dim3(kBS), 0, s, bm, nwords, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
+                              unsigned long long *bm, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, lat, bm);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
+                               const uint64_t *bm, const int32_t *woff, const Grid &g, double *upts,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_write, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, lat, bm, woff,
+                       g, upts);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Lat &lat,
+                                   const uint64_t *bm, const int32_t *woff, const double *uphi,
+                                   double c, tms_leaf *lout, double *cphi, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_gather_bm, dim3(nblk(n)), dim3(kBS), 0, s, lin, n, K, lat, bm, woff,
+                       uphi, c, lout, cphi);
+    return hipGetLastError();
+}
 
 hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
                              const int32_t *cs, const double *ax, const double *ay, const double *az,

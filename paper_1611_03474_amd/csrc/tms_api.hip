@@ -228,6 +228,10 @@ int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int
 // exact, that is at most eps (1 + 1/b) <= 5e-6 for b = 0.07.
 constexpr double kCornerBand = 0.07;
 
+// Largest dense bitmap (bits) used for corner and edge de-duplication; larger
+// lattices fall back to hashing.  8 GiB.
+constexpr double kMaxBitmapBits = 68719476736.0;
+
 // phi at m points of `pts` (with the FAST-exponential guard); returns the
 // number of points recomputed with exact exponentials
 int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
@@ -281,6 +285,52 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     if (n <= 0) return TMS_OK;
     const int64_t ncand = 8 * n;
     if (ncand >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves (%lld)", (long long)n);
+    {
+        // dense bitmap over the finest lattice (4x4x4 point blocks per word)
+        // when it fits the budget
+        Lat lat{};
+        double bits = 64.0;
+        for (int a = 0; a < 3; ++a) {
+            lat.n[a] = ((((int64_t)g.nr[a] << g.K) + 1) + 3) / 4;
+            bits *= (double)lat.n[a];
+        }
+        const int64_t nwords = (int64_t)(bits / 64.0);
+        if (bits <= kMaxBitmapBits && nwords < (int64_t)0x7FFFFFFF) {
+            HIPCK(ctx->bmap.ensure(sizeof(uint64_t) * (size_t)nwords));
+            HIPCK(ctx->bmcnt.ensure(sizeof(int32_t) * (size_t)nwords));
+            HIPCK(ctx->bmoff.ensure(sizeof(int32_t) * (size_t)nwords));
+            {
+                TimedScope ts_(ctx, TMS_T_CORNER);
+                HIPCK(launch_fill_u64(ctx->bmap.as<uint64_t>(), 0ull, nwords, s));
+                HIPCK(launch_corner_mark(leaves, n, g.K, lat,
+                                         ctx->bmap.as<unsigned long long>(), s));
+                HIPCK(launch_popc(ctx->bmap.as<uint64_t>(), nwords, ctx->bmcnt.as<int32_t>(), s));
+            }
+            int64_t nu = 0;
+            int32_t rc = scan_total(ctx, ctx->bmcnt.as<int32_t>(), ctx->bmoff.as<int32_t>(), nwords,
+                                    &nu);
+            if (rc) return rc;
+            HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(nu, 1)));
+            HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)std::max<int64_t>(nu, 1)));
+            {
+                TimedScope ts_(ctx, TMS_T_CORNER);
+                HIPCK(launch_corner_write(leaves, n, g.K, lat, ctx->bmap.as<uint64_t>(),
+                                          ctx->bmoff.as<int32_t>(), g, ctx->uniq.as<double>(), s));
+            }
+            rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nu, ctx->uphi.as<double>(),
+                                nullptr, n_guard, kCornerBand);
+            if (rc) return rc;
+            {
+                TimedScope ts_(ctx, TMS_T_CORNER);
+                HIPCK(launch_corner_gather_bm(leaves, n, g.K, lat, ctx->bmap.as<uint64_t>(),
+                                              ctx->bmoff.as<int32_t>(), ctx->uphi.as<double>(), g.c,
+                                              leaves_out, cphi, s));
+            }
+            *n_corners = nu;
+            return TMS_OK;
+        }
+    }
+    // otherwise: open-addressing hash on the corner keys
     const int64_t hcap = next_pow2(2 * ncand);
     HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
     HIPCK(ctx->hown.ensure(sizeof(uint32_t) * (size_t)hcap));
@@ -320,6 +370,39 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
                                    ctx->uphi.as<double>(), g.c, leaves_out, cphi, s));
     }
     *n_corners = nu;
+    return TMS_OK;
+}
+
+// Chunks of <= 64 consecutive entries of one root over q (or over the
+// sorted subset list) for the tiled estimate kernel; uses flags/scan_a/
+// scan_b/runs as scratch.
+int32_t build_chunks(tms_ctx *ctx, const Grid &g, int lev, const int4 *q, const int32_t *subset,
+                     int64_t n, const int2 **chunks, int64_t *nchunks) {
+    hipStream_t s = ctx->stream;
+    int64_t nruns = 0;
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(launch_run_flags(g, lev, q, subset, n, ctx->flags.as<int32_t>(), s));
+    }
+    int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), n, &nruns);
+    if (rc) return rc;
+    HIPCK(ctx->runs.ensure(4 * (size_t)std::max<int64_t>(nruns, 1)));
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(launch_run_starts(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), n,
+                                ctx->runs.as<int32_t>(), s));
+        HIPCK(launch_run_chunk_counts(ctx->runs.as<int32_t>(), nruns, n, ctx->flags.as<int32_t>(),
+                                      s));
+    }
+    rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), nruns, nchunks);
+    if (rc) return rc;
+    HIPCK(ctx->chunks.ensure(sizeof(int2) * (size_t)std::max<int64_t>(*nchunks, 1)));
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(launch_run_chunk_emit(ctx->runs.as<int32_t>(), nruns, n, ctx->scan_b.as<int32_t>(),
+                                    ctx->chunks.as<int2>(), s));
+    }
+    *chunks = ctx->chunks.as<int2>();
     return TMS_OK;
 }
 
@@ -673,35 +756,12 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             unsigned *hard2 = reinterpret_cast<unsigned *>(ctr + 21);
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
+            const bool tiled = lev >= 2 && lev <= 3;
             const int2 *chunks = nullptr;
             int64_t nchunks = 0;
-            if (lev >= 2 && lev <= 3) {
-                int64_t nruns = 0;
-                {
-                    TimedScope ts_(ctx, TMS_T_COMPACT);
-                    HIPCK(launch_run_flags(g, lev, q, nq, ctx->flags.as<int32_t>(), s));
-                }
-                rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &nruns);
+            if (tiled) {
+                rc = build_chunks(ctx, g, lev, q, nullptr, nq, &chunks, &nchunks);
                 if (rc) return rc;
-                HIPCK(ctx->runs.ensure(4 * (size_t)std::max<int64_t>(nruns, 1)));
-                {
-                    TimedScope ts_(ctx, TMS_T_COMPACT);
-                    HIPCK(launch_run_starts(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq,
-                                            ctx->runs.as<int32_t>(), s));
-                    HIPCK(launch_run_chunk_counts(ctx->runs.as<int32_t>(), nruns, nq,
-                                                  ctx->flags.as<int32_t>(), s));
-                }
-                rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), nruns,
-                                &nchunks);
-                if (rc) return rc;
-                HIPCK(ctx->chunks.ensure(sizeof(int2) * (size_t)std::max<int64_t>(nchunks, 1)));
-                {
-                    TimedScope ts_(ctx, TMS_T_COMPACT);
-                    HIPCK(launch_run_chunk_emit(ctx->runs.as<int32_t>(), nruns, nq,
-                                                ctx->scan_b.as<int32_t>(), ctx->chunks.as<int2>(),
-                                                s));
-                }
-                chunks = ctx->chunks.as<int2>();
             }
             {  // Step 1 (tensor) and the decisions that need no bound
                 TimedScope ts_(ctx, TMS_T_ESTIMATE);
@@ -727,11 +787,19 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &ng);
                 if (rc) return rc;
                 if (ng > 0) {
+                    {
+                        TimedScope ts_(ctx, TMS_T_GUARD);
+                        HIPCK(launch_guard_list_emit(ctx->flags.as<int32_t>(),
+                                                     ctx->scan_a.as<int32_t>(), nq,
+                                                     ctx->idx.as<int32_t>(), s));
+                    }
+                    // the guarded cubes are sparse (well under 1 %): one thread per
+                    // cube beats root chunks holding a handful of cubes each
+                    const int2 *gch = nullptr;
+                    const int64_t ngch = 0;
                     TimedScope ts_(ctx, TMS_T_GUARD);
-                    HIPCK(launch_guard_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(),
-                                                 nq, ctx->idx.as<int32_t>(), s));
                     HIPCK(launch_estimate_decide(
-                        g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(), nullptr, 0,
+                        g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(), gch, ngch,
                         cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
                         cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
                         cells->aw.as<double>(), ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
@@ -852,7 +920,42 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         cphi = ct;
     }
     int64_t nv = 0;
-    if (n > 0) {
+    EdgeLat el{};
+    double ebits = 0.0;
+    {
+        int64_t words = 0;
+        for (int lev = 0; lev <= g.K; ++lev)
+            for (int a = 0; a < 3; ++a) {
+                Lat &l = el.l[lev][a];
+                double b = 1.0;
+                for (int k = 0; k < 3; ++k) {
+                    l.n[k] = ((int64_t)g.nr[k] << lev) + 1;
+                    b *= (double)l.n[k];
+                }
+                l.base = words;
+                words += (int64_t)((b + 63.0) / 64.0);
+                ebits += b;
+            }
+        el.words = words;
+    }
+    if (n > 0 && ebits <= kMaxBitmapBits && el.words < (int64_t)0x7FFFFFFF) {
+        const int64_t nwords = el.words;
+        HIPCK(ctx->bmap.ensure(sizeof(uint64_t) * (size_t)nwords));
+        HIPCK(ctx->bmcnt.ensure(sizeof(int32_t) * (size_t)nwords));
+        HIPCK(ctx->bmoff.ensure(sizeof(int32_t) * (size_t)nwords));
+        {
+            TimedScope ts_(ctx, TMS_T_EXTRACT);
+            HIPCK(launch_fill_u64(ctx->bmap.as<uint64_t>(), 0ull, nwords, s));
+            HIPCK(launch_edge_mark(lv, n, g.K, el, ctx->bmap.as<unsigned long long>(), s));
+            HIPCK(launch_popc(ctx->bmap.as<uint64_t>(), nwords, ctx->bmcnt.as<int32_t>(), s));
+        }
+        int32_t rc = scan_total(ctx, ctx->bmcnt.as<int32_t>(), ctx->bmoff.as<int32_t>(), nwords, &nv);
+        if (rc) return rc;
+        HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
+        TimedScope ts_(ctx, TMS_T_EXTRACT);
+        HIPCK(launch_edge_write(g, lv, cphi, n, el, ctx->bmap.as<uint64_t>(),
+                                ctx->bmoff.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
+    } else if (n > 0) {
         unsigned long long *ctr = ctx->counters.as<unsigned long long>();
         HIPCK(hipMemsetAsync(ctr, 0, 8, s));
         {

@@ -233,8 +233,8 @@ __device__ __forceinline__ int rank99(const double s[4], double &m_hi, double &m
 struct BoundResult {
     double L, U, rho;
     int r;
-    bool jump;   // a 0.99 rank rule lies within its perturbation band
-    double amp;  // first-order amplification of an l1 perturbation of A into L, U
+    double jump;  // largest move of L, U that a rank flip within the band could cause
+    double amp;   // first-order amplification of an l1 perturbation of A into L, U
 };
 
 // gap of sorted value i to its neighbours that are part of the kept set
@@ -258,13 +258,17 @@ __device__ __forceinline__ double sgap(const double s[4], int i) {
 // A is overwritten.
 //
 // With band > 0 (A known only up to an l1 perturbation of that size) it also
-// reports whether a rank decision could flip (jump) and a first-order
-// amplification factor amp: singular values move by at most band, singular
-// vectors rotate by about band / gap (Wedin), and the interval bound moves by
-// about sigma times that rotation, so |dL|, |dU| <~ band * amp.
+// reports a first-order amplification factor amp -- singular values move by
+// at most band, singular vectors rotate by about band / gap (Wedin), and the
+// interval bound moves by about sigma times that rotation, so
+// |dL|, |dU| <~ band * amp -- and a cap on the move a 0.99 rank rule within
+// its band could cause by flipping: with unit singular vectors every
+// Legendre series range lies in [-2, 2] (|sum q_j L_j| <= |q|_1 <= 2), so
+// adding or dropping inner term k of outer term i moves L and U by at most
+// 16 sigma_i d_k, and an outer term i by at most 32 sigma_i.
 __device__ inline BoundResult nested_bound(double *A, double band) {
     BoundResult R;
-    R.jump = false;
+    R.jump = 0.0;
     R.amp = 1.0;
     double S[4][4], W[4][4], lam[4];
 #pragma unroll
@@ -284,7 +288,11 @@ __device__ inline BoundResult nested_bound(double *A, double band) {
     double mhi, mlo;
     int r = rank99(sig, mhi, mlo);
     R.r = r;
-    if (band > 0.0 && (mhi <= 8.0 * band || mlo <= 8.0 * band)) R.jump = true;
+    if (band > 0.0) {
+        // cum_r and the 0.99 target move by at most (r + 4) band <= 8 band
+        if (mhi <= 8.0 * band && r < 4) R.jump += 32.0 * sig[r];
+        if (mlo <= 8.0 * band && r > 0) R.jump += 32.0 * sig[r - 1];
+    }
     double Msum = 0.0, msum = 0.0;
     for (int i = 0; i < r; ++i) {
         double u[4] = {W[0][i], W[1][i], W[2][i], W[3][i]};
@@ -319,7 +327,8 @@ __device__ inline BoundResult nested_bound(double *A, double band) {
             for (int k = 0; k < ri; ++k) dg = fmin(dg, sgap(d, k));
             const double irot = (dg > 0.0) ? dv / dg : 1e300;
             R.amp += sig[i] * (rot + irot) / band + 1.0;
-            if (nhi <= 8.0 * dv || nlo <= 8.0 * dv) R.jump = true;
+            if (nhi <= 8.0 * dv && ri < 4) R.jump += 16.0 * sig[i] * d[ri];
+            if (nlo <= 8.0 * dv && ri > 0) R.jump += 16.0 * sig[i] * d[ri - 1];
         }
         double ux0, ux1;
         leg3_range(u, ux0, ux1);

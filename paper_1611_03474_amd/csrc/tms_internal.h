@@ -45,6 +45,20 @@ int gl_half_nodes(double beta, bool fp32);
 template <typename T>
 GLRule<T> gl_rule(int half);
 
+// Dense bitmaps over lattices of points, one bit per point, bit index
+// (X * ny + Y) * nz + Z (X-major, which is also the order of the packed
+// keys).  Sub-lattices start on 64-bit word boundaries.
+struct Lat {
+    int64_t n[3];   // points per axis
+    int64_t base;   // first word
+};
+// Edge lattices: one per (level, axis), at the level's resolution, laid out
+// level-major then axis, so the bit order is the edge-key order.
+struct EdgeLat {
+    Lat l[TMS_MAX_LEVELS][3];
+    int64_t words;
+};
+
 // Decision codes of the per-cube state machine.
 enum : uint8_t {
     DEC_DISCARD = 0,
@@ -102,7 +116,7 @@ struct tms_ctx {
     int64_t n_verts = 0;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
-        slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs;
+        slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs, bmap, bmcnt, bmoff;
     tms::DevBuf counters;  // small device counters
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -166,7 +180,8 @@ hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *
                            const double *az, const double *aw, double *A, double *E,
                            int64_t *pairs, hipStream_t s);
 // estimate + easy decisions; cubes needing the bound go to the hard list.
-// chunks != nullptr selects the tiled kernel (levels 2..3, no subset).
+// chunks != nullptr selects the tiled kernel (levels 2..3); chunk positions
+// index the subset list when one is given.
 hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const int4 *q, int64_t n,
                                   const int32_t *subset, const int2 *chunks, int64_t nchunks,
                                   const int32_t *root_start, const int32_t *root_atoms,
@@ -177,8 +192,8 @@ hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s);
-hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, int64_t n, int32_t *f,
-                            hipStream_t s);
+hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, const int32_t *subset,
+                            int64_t n, int32_t *f, hipStream_t s);
 hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, int32_t *starts,
                              hipStream_t s);
 hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
@@ -230,7 +245,23 @@ hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
 hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
                                 hipStream_t s);
 
+// bitmap helpers (k_phi.hip)
+hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStream_t s);
+hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
+                              unsigned long long *bm, hipStream_t s);
+hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
+                               const uint64_t *bm, const int32_t *woff, const Grid &g, double *upts,
+                               hipStream_t s);
+hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Lat &lat,
+                                   const uint64_t *bm, const int32_t *woff, const double *uphi,
+                                   double c, tms_leaf *lout, double *cphi, hipStream_t s);
+
 // k_extract.hip
+hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, int K, const EdgeLat &el,
+                            unsigned long long *bm, hipStream_t s);
+hipError_t launch_edge_write(const Grid &g, const tms_leaf *leaves, const double *cphi, int64_t n,
+                             const EdgeLat &el, const uint64_t *bm, const int32_t *woff,
+                             tms_vertex *out, hipStream_t s);
 hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                               uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
 hipError_t launch_edge_emit(const Grid &g, const tms_leaf *leaves, const double *corner_phi,
