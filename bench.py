@@ -31,6 +31,11 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per step of the estimate phase from rocprofv3 FETCH_SIZE +
+# WRITE_SIZE (scaled by the copy-kernel factor; profiles/estimate_assembly110k_pmc.md),
+# or None when the kernel changed since the counters were taken
+TRAFFIC_ESTIMATE = None
+
 # algorithmic work per unit ("Measurement")
 FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
 FLOP_PER_PHI_PAIR = 14   # phi + grad per in-range (point, atom) pair, excl. exp
@@ -107,6 +112,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="assembly110k")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (counter scale for HBM traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -123,6 +130,13 @@ def main():
     atoms = workloads.atoms(w)
     log("  %d atoms in %.1f s" % (len(atoms), time.perf_counter() - t0))
     atoms_dev = torch.as_tensor(atoms, dtype=torch.float64, device="cuda:0").contiguous()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = tms.Context(0)
 
     log("FP32+guard run")
@@ -144,20 +158,17 @@ def main():
     st = f32["stats"]
     # dominant kernel by device time
     tm = f32["timing"]
-    dom = max(("estimate", "decide", "phi"), key=lambda k: tm[k]["ms"])
-    if dom == "estimate":
-        work = st["n_pairs"] * FLOP_PER_PAIR
-        peak = PEAK_FP32_TFLOPS
-    elif dom == "phi":
-        work = None
-        peak = PEAK_FP32_TFLOPS
-    else:
-        work = None
-        peak = PEAK_FP64_TFLOPS
-    achieved = (work / (tm[dom]["ms"] * 1e-3) / 1e12) if work else None
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
-                "traffic": None}
+    # dominant kernel: the tensor estimate (rank-one updates run in FP64 in
+    # both modes, so the FP64 vector peak applies)
+    work = st["n_pairs"] * FLOP_PER_PAIR
+    achieved = work / (tm["estimate"]["ms"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "estimate (k_estimate_tiled levels 2-3, "
+                "k_estimate_thread levels 0-1)", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": TRAFFIC_ESTIMATE,
+                "work_per_unit": "%d flop per in-range (cube, atom) pair" % FLOP_PER_PAIR,
+                "units_per_step": st["n_pairs"],
+                "launches_per_step": tm["estimate"]["launches"]}
 
     out = {
         "metric": "cubes estimated/sec and phi evals/sec at 100k atoms, FP32+guard vs FP64",

@@ -34,11 +34,13 @@ __global__ void k_roots_emit(Grid g, const int32_t *__restrict__ f, const int32_
     q[off[r]] = make_int4(rx, ry, rz, 0);
 }
 
-// wavefront sum of a 64-bit counter, one atomic per wavefront
+// wavefront sum of a 64-bit counter, one atomic per wavefront, striped over
+// 64 slots (the host adds them) so that wavefronts do not queue on one address
 __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long long v) {
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-    if ((threadIdx.x & 63) == 0) atomicAdd(ctr, v);
+    if ((threadIdx.x & 63) == 0 && v)
+        atomicAdd(ctr + ((blockIdx.x * (kBS / 64) + (threadIdx.x >> 6)) & 63), v);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,15 +471,37 @@ __global__ void k_level_emit(const int4 *__restrict__ q, const uint8_t *__restri
     }
 }
 
+// decision histogram in two passes (block partials, then one block), with
+// no atomics on shared addresses
+constexpr int kHistoBlocks = 1024;
+
 __global__ void k_level_histo(const uint8_t *__restrict__ dec, int64_t n,
-                              unsigned long long *__restrict__ h) {
-    __shared__ unsigned long long sh[5];
-    if (threadIdx.x < 5) sh[threadIdx.x] = 0;
+                              unsigned long long *__restrict__ part) {
+    __shared__ unsigned long long sh[5][kBS];
+    unsigned long long c[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBS) {
+        const uint8_t d = dec[i];
+        if (d < 5) c[d] += 1;
+    }
+#pragma unroll
+    for (int b = 0; b < 5; ++b) sh[b][threadIdx.x] = c[b];
     __syncthreads();
-    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i < n && dec[i] < 5) atomicAdd(&sh[dec[i]], 1ull);
-    __syncthreads();
-    if (threadIdx.x < 5 && sh[threadIdx.x]) atomicAdd(&h[threadIdx.x], sh[threadIdx.x]);
+    for (int st = kBS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) sh[b][threadIdx.x] += sh[b][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 5) part[5 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_level_histo_final(const unsigned long long *__restrict__ part, int nb,
+                                    unsigned long long *__restrict__ out) {
+    if (threadIdx.x >= 5) return;
+    unsigned long long t = 0;
+    for (int b = 0; b < nb; ++b) t += part[5 * b + threadIdx.x];
+    out[threadIdx.x] = t;
 }
 
 __global__ __launch_bounds__(kBS) void k_bound_debug(const double *__restrict__ Ain,
@@ -758,9 +782,12 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
     return hipGetLastError();
 }
 
-hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h, hipStream_t s) {
+hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h,
+                              unsigned long long *part, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_level_histo, dim3(nblk(n)), dim3(kBS), 0, s, dec, n, h);
+    const int nb = (int)std::min<int64_t>(kHistoBlocks, (n + kBS - 1) / kBS);
+    hipLaunchKernelGGL(k_level_histo, dim3(nb), dim3(kBS), 0, s, dec, n, part);
+    hipLaunchKernelGGL(k_level_histo_final, dim3(1), dim3(64), 0, s, part, nb, h);
     return hipGetLastError();
 }
 

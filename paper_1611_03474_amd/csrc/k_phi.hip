@@ -227,13 +227,35 @@ __global__ void k_list_emit2(const int32_t *__restrict__ f, const int32_t *__res
     if (i < n && f[i]) list[off[i]] = (int32_t)i;
 }
 
+// number of SURFACE leaves: block partials, then one block
 __global__ void k_count_surface(const tms_leaf *__restrict__ leaves, int64_t n,
-                                unsigned long long *__restrict__ cnt) {
-    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    unsigned long long c = (i < n && leaves[i].cls == TMS_CLS_SURFACE) ? 1ull : 0ull;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
+                                unsigned long long *__restrict__ part) {
+    __shared__ unsigned long long sh[kBS];
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBS)
+        c += leaves[i].cls == TMS_CLS_SURFACE;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = kBS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_final(const unsigned long long *__restrict__ part, int nb,
+                            unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long sh[kBS];
+    unsigned long long t = 0;
+    for (int b = threadIdx.x; b < nb; b += kBS) t += part[b];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int st = kBS / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 // ---- dense-bitmap corner de-duplication -----------------------------------
@@ -266,15 +288,36 @@ __global__ void k_popc(const uint64_t *__restrict__ bm, int64_t nw, int32_t *__r
     if (w < nw) cnt[w] = __popcll(bm[w]);
 }
 
+// one thread per leaf: its 8 corner bits, merged per 64-bit word (a
+// finest-level leaf usually has all 8 in one 4x4x4 block), one atomic OR per
+// distinct word
 __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, int K, Lat lat,
                               unsigned long long *__restrict__ bm) {
-    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 8 * n) return;
-    const tms_leaf L = leaves[c >> 3];
-    int64_t X, Y, Z;
-    leaf_corner(L, (int)(c & 7), K, X, Y, Z);
-    const int64_t b = lat_bit(lat, X, Y, Z);
-    atomicOr(bm + (b >> 6), 1ull << (b & 63));
+    const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n) return;
+    const tms_leaf L = leaves[q];
+    int64_t w[8];
+    unsigned long long m[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        int64_t X, Y, Z;
+        leaf_corner(L, v, K, X, Y, Z);
+        const int64_t b = lat_bit(lat, X, Y, Z);
+        w[v] = b >> 6;
+        m[v] = 1ull << (b & 63);
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        if (m[v] == 0) continue;
+        unsigned long long bits = m[v];
+#pragma unroll
+        for (int u = v + 1; u < 8; ++u)
+            if (w[u] == w[v]) {
+                bits |= m[u];
+                m[u] = 0;
+            }
+        atomicOr(bm + w[v], bits);
+    }
 }
 
 // every candidate writes its corner's coordinates at the corner's rank (all
@@ -326,7 +369,7 @@ hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStre
 hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
                               unsigned long long *bm, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, lat, bm);
+    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, K, lat, bm);
     return hipGetLastError();
 }
 
@@ -445,9 +488,11 @@ hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
 }
 
 hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
-                                hipStream_t s) {
+                                unsigned long long *part, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_surface, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, count);
+    const int nb = (int)std::min<int64_t>(1024, (n + kBS - 1) / kBS);
+    hipLaunchKernelGGL(k_count_surface, dim3(nb), dim3(kBS), 0, s, leaves, n, part);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBS), 0, s, part, nb, count);
     return hipGetLastError();
 }
 

@@ -210,7 +210,7 @@ hipError_t d2h(T *dst, const void *src, size_t count, hipStream_t s) {
 // scan `n` int32 values of `in` into `out` and return the total on the host
 int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int64_t *total) {
     HIPCK(ctx->scan_c.ensure(scan_tmp_bytes(n) + 512));
-    int32_t *tot = ctx->counters.as<int32_t>() + 60;
+    int32_t *tot = reinterpret_cast<int32_t *>(ctx->counters.as<unsigned long long>() + 100);
     {
         TimedScope ts_(ctx, TMS_T_COMPACT);
         HIPCK(exclusive_scan(in, out, n, tot, ctx->scan_c.p, ctx->stream));
@@ -225,8 +225,8 @@ int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int
 // with exact exponentials.  An edge root t = (c - phi0)/(phi1 - phi0) from
 // FAST values (relative error eps = kFastExpErr) is off by at most
 // eps (phi0 + phi1) / |phi1 - phi0|; with every corner of |phi - c| <= b c
-// exact, that is at most eps (1 + 1/b) <= 5e-6 for b = 0.07.
-constexpr double kCornerBand = 0.07;
+// exact, that is at most eps (1 + 1/b) <= 4.4e-6 for b = 0.035.
+constexpr double kCornerBand = 0.035;
 
 // Largest dense bitmap (bits) used for corner and edge de-duplication; larger
 // lattices fall back to hashing.  8 GiB.
@@ -429,7 +429,7 @@ int32_t tms_create(tms_ctx **out, int32_t device, void *stream) {
     tms_ctx *ctx = new tms_ctx();
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
-    e = ctx->counters.ensure(4096);
+    e = ctx->counters.ensure(65536);
     if (e != hipSuccess) {
         delete ctx;
         return fail(nullptr, TMS_E_OOM, "counter allocation failed");
@@ -751,9 +751,9 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
             HIPCK(ctx->scan_b.ensure(4 * (size_t)nq));
             HIPCK(ctx->idx.ensure(4 * (size_t)nq));
-            HIPCK(hipMemsetAsync(ctr, 0, 256, s));
-            unsigned *hard1 = reinterpret_cast<unsigned *>(ctr + 20);
-            unsigned *hard2 = reinterpret_cast<unsigned *>(ctr + 21);
+            HIPCK(hipMemsetAsync(ctr, 0, 96 * sizeof(unsigned long long), s));
+            unsigned *hard1 = reinterpret_cast<unsigned *>(ctr + 64);
+            unsigned *hard2 = reinterpret_cast<unsigned *>(ctr + 65);
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
             const bool tiled = lev >= 2 && lev <= 3;
@@ -813,7 +813,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             int32_t *lcnt = ctx->flags.as<int32_t>(), *ccnt = ctx->idx.as<int32_t>();
             {
                 TimedScope ts_(ctx, TMS_T_COMPACT);
-                HIPCK(launch_level_histo(ctx->dec.as<uint8_t>(), nq, ctr + 8, s));
+                HIPCK(launch_level_histo(ctx->dec.as<uint8_t>(), nq, ctr + 72, ctr + 256, s));
                 HIPCK(launch_level_counts(ctx->dec.as<uint8_t>(), nq, lcnt, ccnt, s));
             }
             int64_t nl = 0, nc = 0;
@@ -821,14 +821,14 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             if (rc) return rc;
             rc = scan_total(ctx, ccnt, ctx->scan_b.as<int32_t>(), nq, &nc);
             if (rc) return rc;
-            unsigned long long h[24];
-            HIPCK(d2h(h, ctr, 24, s));
-            st.n_pairs += (int64_t)h[0];
-            st.n_bound += (int64_t)(h[20] & 0xFFFFFFFFull) + (int64_t)(h[21] & 0xFFFFFFFFull);
-            st.n_disc[lev] = (int64_t)h[8 + DEC_DISCARD];
-            st.n_refine[lev] = (int64_t)h[8 + DEC_REFINE];
-            st.n_conv[lev] = (int64_t)h[8 + DEC_CONV];
-            st.n_hmin[lev] = (int64_t)h[8 + DEC_HMIN];
+            unsigned long long h[80];
+            HIPCK(d2h(h, ctr, 80, s));
+            for (int k = 0; k < 64; ++k) st.n_pairs += (int64_t)h[k];
+            st.n_bound += (int64_t)(h[64] & 0xFFFFFFFFull) + (int64_t)(h[65] & 0xFFFFFFFFull);
+            st.n_disc[lev] = (int64_t)h[72 + DEC_DISCARD];
+            st.n_refine[lev] = (int64_t)h[72 + DEC_REFINE];
+            st.n_conv[lev] = (int64_t)h[72 + DEC_CONV];
+            st.n_hmin[lev] = (int64_t)h[72 + DEC_HMIN];
             HIPCK(grow_keep(ctx->leaves, sizeof(tms_leaf) * (size_t)(L + nl), sizeof(tms_leaf) * (size_t)L, s));
             HIPCK(ctx->q[cur ^ 1].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nc, 1)));
             {
@@ -850,13 +850,13 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         st.n_corners = nu;
         st.guard_points = ng;
     }
-    HIPCK(hipMemsetAsync(ctr, 0, 8, s));
+    HIPCK(hipMemsetAsync(ctr + 80, 0, 8, s));
     {
         TimedScope ts_(ctx, TMS_T_COMPACT);
-        HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr, s));
+        HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr + 80, ctr + 256, s));
     }
     unsigned long long ns = 0;
-    HIPCK(d2h(&ns, ctr, 1, s));
+    HIPCK(d2h(&ns, ctr + 80, 1, s));
     st.n_leaves = L;
     st.n_surface = (int64_t)ns;
     ctx->n_leaves = L;

@@ -117,7 +117,10 @@ struct tms_ctx {
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
         slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs, bmap, bmcnt, bmoff;
-    tms::DevBuf counters;  // small device counters
+    // small device counters (u64 slots): [0,64) striped pair counts,
+    // 64/65 hard-list lengths, [72,77) decision histogram, 80 surface count,
+    // 100 scan total; [256, 256 + 5*1024) reduction partials
+    tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
     bool timing = false;
@@ -209,7 +212,7 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
                              const int32_t *leaf_off, const int32_t *child_off, tms_leaf *leaves,
                              int64_t leaf_base, int4 *qnext, hipStream_t s);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
-                              hipStream_t s);
+                              unsigned long long *part, hipStream_t s);
 hipError_t launch_bound_debug(const double *A, const double *band, int64_t n, double *out,
                               hipStream_t s);
 hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStream_t s);
@@ -243,7 +246,7 @@ hipError_t launch_guard_flags_u8(const uint8_t *g, int64_t n, int32_t *flags, hi
 hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
                             hipStream_t s);
 hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
-                                hipStream_t s);
+                                unsigned long long *part, hipStream_t s);
 
 // bitmap helpers (k_phi.hip)
 hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStream_t s);
