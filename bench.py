@@ -31,10 +31,12 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per step of the estimate phase from rocprofv3 FETCH_SIZE +
-# WRITE_SIZE (scaled by the copy-kernel factor; profiles/estimate_assembly110k_pmc.md),
-# or None when the kernel changed since the counters were taken
-TRAFFIC_ESTIMATE = None
+# HBM bytes per launch of k_estimate_tiled from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, each scaled by what the same counter reads for a plain copy of
+# known size (FETCH x2.0, WRITE x1.0), mean of the level-2 and level-3
+# launches on the 110,000-atom assembly (profiles/estimate_tiled_assembly110k_traffic.md);
+# None when the kernel changed since the counters were taken
+TRAFFIC_TILED = 9.05e9
 
 # algorithmic work per unit ("Measurement")
 FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
@@ -156,19 +158,25 @@ def main():
 
     r32 = rates(f32)
     st = f32["stats"]
-    # dominant kernel by device time
+    # dominant kernel: the wave-per-chunk tensor estimate on the two deep
+    # levels.  Its rank-one updates run in FP64 in both modes, so the FP64
+    # vector peak applies; algorithmic work = in-range (cube, atom) pairs at
+    # those levels x FLOP_PER_PAIR.
     tm = f32["timing"]
-    # dominant kernel: the tensor estimate (rank-one updates run in FP64 in
-    # both modes, so the FP64 vector peak applies)
-    work = st["n_pairs"] * FLOP_PER_PAIR
-    achieved = work / (tm["estimate"]["ms"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "estimate (k_estimate_tiled levels 2-3, "
-                "k_estimate_thread levels 0-1)", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": TRAFFIC_ESTIMATE,
+    deep_pairs = sum(st["n_pairs_lvl"][2:4])
+    launches = tm["tiled"]["launches"]
+    avg_launch_s = tm["tiled"]["ms"] * 1e-3 / max(launches, 1)
+    work_per_launch = deep_pairs * FLOP_PER_PAIR / max(launches, 1)
+    achieved = work_per_launch / avg_launch_s / 1e12
+    roofline = {"bound": "alu", "kernel": "k_estimate_tiled (levels 2-3)",
+                "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": TRAFFIC_TILED if w.name == "assembly110k" else None,
+                "traffic_unit": "HBM bytes per launch",
                 "work_per_unit": "%d flop per in-range (cube, atom) pair" % FLOP_PER_PAIR,
-                "units_per_step": st["n_pairs"],
-                "launches_per_step": tm["estimate"]["launches"]}
+                "units_per_launch": deep_pairs / max(launches, 1),
+                "launches_per_step": launches,
+                "avg_launch_ms": avg_launch_s * 1e3}
 
     out = {
         "metric": "cubes estimated/sec and phi evals/sec at 100k atoms, FP32+guard vs FP64",
@@ -195,6 +203,7 @@ def main():
         "guard_cubes": st["guard_cubes"], "guard_points": st["guard_points"],
         "guard_cube_fraction": st["guard_cubes"] / max(1, st["cubes_estimated"]),
         "device_ms_per_step": {k: round(v["ms"], 4) for k, v in tm.items()},
+        "pairs_per_level": st["n_pairs_lvl"][:4],
         "roofline": roofline,
     }
     if f64 is not None:

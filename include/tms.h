@@ -117,6 +117,7 @@ typedef struct {
     int64_t guard_cubes;    /* cubes recomputed in double precision            */
     int64_t guard_points;   /* corner points recomputed in double precision    */
     int64_t n_pairs;        /* cube-atom pairs inside R_c (algorithmic work)   */
+    int64_t n_pairs_lvl[TMS_MAX_LEVELS]; /* the same, per level           */
 } tms_stats;
 
 /* Create a context on HIP device `device`, enqueueing work on `stream`
@@ -221,14 +222,17 @@ int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_
  * the context's stream and accumulates the elapsed device time per phase
  * (TMS_T_* slots).  Off by default; costs two event records per launch. */
 #define TMS_T_BUILD 0    /* binning and neighbourhood lists           */
-#define TMS_T_ESTIMATE 1 /* tensor estimate kernels (all levels)       */
+#define TMS_T_ESTIMATE 1 /* tensor estimate, one thread per cube        */
 #define TMS_T_DECIDE 2   /* decision / nested-SVD bound kernels        */
 #define TMS_T_GUARD 3    /* double-precision recomputation of guards   */
 #define TMS_T_COMPACT 4  /* scans, queue and leaf compaction           */
 #define TMS_T_CORNER 5   /* corner de-duplication and gathering        */
 #define TMS_T_PHI 6      /* phi kernels (corner values, tms_eval_phi)   */
 #define TMS_T_EXTRACT 7  /* edge de-duplication and vertex emission    */
-#define TMS_T_SLOTS 8
+#define TMS_T_TILED 8    /* tensor estimate, one wave per chunk of
+                            cubes of one root (levels 2 and 3)         */
+#define TMS_T_BACKWARD 9 /* adjoint kernels                             */
+#define TMS_T_SLOTS 10
 
 typedef struct {
     double ms[TMS_T_SLOTS];       /* accumulated device milliseconds */

@@ -764,7 +764,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 if (rc) return rc;
             }
             {  // Step 1 (tensor) and the decisions that need no bound
-                TimedScope ts_(ctx, TMS_T_ESTIMATE);
+                TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
                 HIPCK(launch_estimate_decide(
                     g, lev, prec, q, nq, nullptr, chunks, nchunks, cells->root_start.as<int32_t>(),
                     cells->root_atoms.as<int32_t>(), cells->ax.as<double>(), cells->ay.as<double>(),
@@ -823,7 +823,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             if (rc) return rc;
             unsigned long long h[80];
             HIPCK(d2h(h, ctr, 80, s));
-            for (int k = 0; k < 64; ++k) st.n_pairs += (int64_t)h[k];
+            for (int k = 0; k < 64; ++k) st.n_pairs_lvl[lev] += (int64_t)h[k];
+            st.n_pairs += st.n_pairs_lvl[lev];
             st.n_bound += (int64_t)(h[64] & 0xFFFFFFFFull) + (int64_t)(h[65] & 0xFFFFFFFFull);
             st.n_disc[lev] = (int64_t)h[72 + DEC_DISCARD];
             st.n_refine[lev] = (int64_t)h[72 + DEC_REFINE];

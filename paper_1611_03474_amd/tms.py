@@ -30,11 +30,12 @@ VERTEX_DTYPE = np.dtype([("edge_key", "<u8"), ("t", "<f8"), ("x", "<f8"), ("y", 
 assert LEAF_DTYPE.itemsize == 20 and VERTEX_DTYPE.itemsize == 40
 
 
-T_SLOTS = ["build", "estimate", "decide", "guard", "compact", "corner", "phi", "extract"]
+T_SLOTS = ["build", "estimate", "decide", "guard", "compact", "corner", "phi", "extract",
+           "tiled", "backward"]
 
 
 class Timing(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+    _fields_ = [("ms", C.c_double * len(T_SLOTS)), ("launches", C.c_int64 * len(T_SLOTS))]
 
     def as_dict(self) -> dict:
         return {k: {"ms": self.ms[i], "launches": int(self.launches[i])}
@@ -60,7 +61,7 @@ class Stats(C.Structure):
     _fields_ = [("n_est", _I64L), ("n_disc", _I64L), ("n_refine", _I64L), ("n_conv", _I64L),
                 ("n_hmin", _I64L), ("n_leaves", C.c_int64), ("n_surface", C.c_int64),
                 ("n_corners", C.c_int64), ("n_bound", C.c_int64), ("guard_cubes", C.c_int64),
-                ("guard_points", C.c_int64), ("n_pairs", C.c_int64)]
+                ("guard_points", C.c_int64), ("n_pairs", C.c_int64), ("n_pairs_lvl", _I64L)]
 
     def as_dict(self) -> dict:
         d = {}
