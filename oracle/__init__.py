@@ -80,6 +80,8 @@ def lib():
         L.or_cutoff2.restype = C.c_double
         L.or_phi.argtypes = [_DP, C.c_int64, C.c_double, C.c_double, _DP, C.c_int64, _DP, _DP,
                              C.c_int]
+        L.or_phi_adjoint.argtypes = [_DP, C.c_int64, C.c_double, C.c_double, _DP, C.c_int64,
+                                     _DP, _DP, C.c_int]
         L.or_cube_tensor.argtypes = [_DP, C.c_int64, C.c_double, C.c_double, C.c_int, _DP, _DP,
                                      _DP, C.POINTER(C.c_int64)]
         L.or_tensor_eval.argtypes = [_DP, C.c_double, C.c_double, C.c_double]
@@ -148,6 +150,20 @@ def phi(xyzr, D, pts, eps_cut=1e-10, grad=False, nthreads=0):
     lib().or_phi(_dp(a), a.shape[0], float(D), float(eps_cut), _dp(p), p.shape[0], _dp(out),
                  _dp(g) if grad else None, int(nthreads))
     return (out, g) if grad else out
+
+
+def phi_adjoint(xyzr, D, pts, wbar, eps_cut=1e-10, nthreads=0):
+    """sum_p wbar_p d phi(p)/d(x_i, y_i, z_i, r_i) for every atom i: the
+    derivative of eq. Gaussian1 (Section 1), cut-off radius held fixed.
+    Returns [n, 4]."""
+    a = _atoms(xyzr)
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    w = np.ascontiguousarray(np.asarray(wbar, dtype=np.float64).reshape(-1))
+    assert w.shape[0] == p.shape[0]
+    out = np.zeros((a.shape[0], 4))
+    lib().or_phi_adjoint(_dp(a), a.shape[0], float(D), float(eps_cut), _dp(p), p.shape[0],
+                         _dp(w), _dp(out), int(nthreads))
+    return out
 
 
 def cube_tensor(xyzr, D, lo, hi, eps_cut=1e-10, nodes=0):
@@ -258,4 +274,78 @@ def partition(xyzr, D, c=1.0, tau=1e-3, h0=2.0, h_min=0.25, pad=3.0, eps_cut=1e-
         lib().or_free(rp)
     if res.status != 0:
         raise ValueError("oracle rejected the input (status %d)" % res.status)
+    res.h0 = float(h0)
     return res
+
+
+# --------------------------------------------------------------------------
+# Surface loss and its gradient (the adjoint workload)
+# --------------------------------------------------------------------------
+
+def corner_list(res: Result):
+    """Unique leaf corners of a pass: finest-lattice keys X<<32 | Y<<16 | Z
+    (ascending), their points and phi values.  Each corner value was
+    evaluated once per unique point by the oracle, so any leaf that holds the
+    corner gives the same value."""
+    sh = (res.K - res.level.astype(np.int64))[:, None]
+    keys, vals = [], []
+    for v in range(8):
+        d = np.array([v & 1, (v >> 1) & 1, (v >> 2) & 1], dtype=np.int64)
+        X = (res.ijk.astype(np.int64) + d[None, :]) << sh
+        keys.append((X[:, 0] << 32) | (X[:, 1] << 16) | X[:, 2])
+        vals.append(res.corner_phi[:, v])
+    keys = np.concatenate(keys)
+    vals = np.concatenate(vals)
+    uk, first = np.unique(keys, return_index=True)
+    hmin = 2.0 ** -res.K * res.h0
+    X = np.stack([(uk >> 32) & 0xFFFF, (uk >> 16) & 0xFFFF, uk & 0xFFFF], 1).astype(np.float64)
+    pts = res.origin[None, :] + X * hmin
+    return uk, pts, vals[first]
+
+
+def vertex_edges(res: Result):
+    """For every vertex: the keys of the lower and upper end of its edge and
+    the edge length h (eq. intersection)."""
+    k = res.vkey.astype(np.uint64)
+    level = ((k >> np.uint64(50)) & np.uint64(7)).astype(np.int64)
+    axis = ((k >> np.uint64(48)) & np.uint64(3)).astype(np.int64)
+    X = np.stack([(k >> np.uint64(32)) & np.uint64(0xFFFF), (k >> np.uint64(16)) & np.uint64(0xFFFF),
+                  k & np.uint64(0xFFFF)], 1).astype(np.int64)
+    k0 = (X[:, 0] << 32) | (X[:, 1] << 16) | X[:, 2]
+    step = np.int64(1) << (res.K - level)
+    X1 = X.copy()
+    X1[np.arange(len(X)), axis] += step
+    k1 = (X1[:, 0] << 32) | (X1[:, 1] << 16) | X1[:, 2]
+    h = res.h0 * 2.0 ** (-level.astype(np.float64))
+    return k0, k1, h
+
+
+def surface_loss(phi_c, c, t, h):
+    """Loss of the adjoint workload: sum over unique leaf corners of
+    (phi - c)^2 plus the squared distance of every edge point from its edge
+    midpoint, ((t - 1/2) h)^2."""
+    return float(np.sum((phi_c - c) ** 2) + np.sum(((t - 0.5) * h) ** 2))
+
+
+def surface_loss_grad(xyzr, D, c, res: Result, eps_cut=1e-10, nthreads=0):
+    """Loss and its gradient with respect to every atom's (x, y, z, r), with
+    the discrete structure of the pass (leaves, masks, edges) held fixed.
+
+    Chain: dL/dphi_p = 2 (phi_p - c) at every corner; every edge point adds
+    dL/dt = 2 (t - 1/2) h^2 times dt/dphi0 = (t - 1)/(phi1 - phi0) at its
+    lower end and dt/dphi1 = -t/(phi1 - phi0) at its upper end, since
+    t = (c - phi0)/(phi1 - phi0) (eq. intersection); then phi_adjoint."""
+    keys, pts, ph = corner_list(res)
+    k0, k1, h = vertex_edges(res)
+    i0 = np.searchsorted(keys, k0)
+    i1 = np.searchsorted(keys, k1)
+    assert np.all(keys[i0] == k0) and np.all(keys[i1] == k1)
+    f0, f1 = ph[i0], ph[i1]
+    t = (c - f0) / (f1 - f0)
+    wbar = 2.0 * (ph - c)
+    dldt = 2.0 * (t - 0.5) * h * h
+    np.add.at(wbar, i0, dldt * (t - 1.0) / (f1 - f0))
+    np.add.at(wbar, i1, dldt * (-t) / (f1 - f0))
+    grad = phi_adjoint(xyzr, D, pts, wbar, eps_cut=eps_cut, nthreads=nthreads)
+    return surface_loss(ph, c, t, h), grad, dict(keys=keys, pts=pts, phi=ph, wbar=wbar, t=t,
+                                                 k0=k0, k1=k1, h=h)

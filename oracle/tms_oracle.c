@@ -350,6 +350,58 @@ void or_phi(const double *xyzr, int64_t n, double D, double eps_cut, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Adjoint of phi: derivative of eq. Gaussian1 with respect to the atom       */
+/* centres and radii.  For weights wbar_p at points p,                        */
+/*   out[i] = sum_p wbar_p d phi(p) / d(x_i, y_i, z_i, r_i)                   */
+/*          = sum_p wbar_p term_ip (2D (p - x_i), 2D r_i),                    */
+/*   term_ip = exp(-D(|p - x_i|^2 - r_i^2)),                                  */
+/* over the pairs inside the cut-off.  Reading: the cut-off radius is a       */
+/* truncation level, not part of the model, so it is held fixed (its own     */
+/* derivative would only move terms below eps_cut).  Atom-major loop over a   */
+/* bin grid of the points; each atom's sum is independent.                    */
+/* ------------------------------------------------------------------------ */
+
+void or_phi_adjoint(const double *xyzr, int64_t n, double D, double eps_cut, const double *pts,
+                    int64_t m, const double *wbar, double *out, int nthreads)
+{
+    double rc2 = or_cutoff2(xyzr, n, D, eps_cut);
+    double R = sqrt(rc2);
+    /* points with their weights in the [m][4] layout the bin grid takes */
+    double *pw = (double *)malloc(sizeof(double) * 4 * (size_t)(m ? m : 1));
+    for (int64_t k = 0; k < m; ++k) {
+        for (int a = 0; a < 3; ++a)
+            pw[4 * k + a] = pts[3 * k + a];
+        pw[4 * k + 3] = wbar[k];
+    }
+    or_bins b;
+    bins_build(&b, pw, m, R);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const double *x = xyzr + 4 * i;
+        double acc[4] = {0, 0, 0, 0};
+        if (m > 0)
+            BINS_FOREACH(&b, x, x, R, k, {
+                const double *p = pw + 4 * k;
+                double d[3] = {p[0] - x[0], p[1] - x[1], p[2] - x[2]};
+                double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (d2 <= rc2) {
+                    double f = p[3] * exp(-D * (d2 - x[3] * x[3]));
+                    for (int a = 0; a < 3; ++a)
+                        acc[a] += f * 2.0 * D * d[a];
+                    acc[3] += f * 2.0 * D * x[3];
+                }
+            });
+        for (int a = 0; a < 4; ++a)
+            out[4 * i + a] = acc[a];
+    }
+    bins_free(&b);
+    free(pw);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Coefficient tensor of one cube (eqs. polynew, tensor1, tensor2)            */
 /*   A[j][k][l] = sum_{i in N(Q)} exp(D r_i^2) a~x_j a~y_k a~z_l               */
 /* j: x-degree, k: y-degree, l: z-degree; flat index 16 j + 4 k + l.          */
