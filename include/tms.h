@@ -217,6 +217,45 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
 
 int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_out);
 
+/* Unique leaf corners of the last pass (eq. linear1 evaluates phi once per
+ * lattice corner shared by any number of leaves): their points and phi
+ * values.  The pass is the last tms_partition_estimate, or the last
+ * tms_extract_cube_vertices called with corner_phi NULL, whichever came
+ * last.  Order: the corner-bitmap order of the adaptive pass (4x4x4 blocks
+ * of the finest lattice, blocks x-major, points inside a block x-major), or
+ * the raster order of the uniform grid.
+ *  xyz  device [cap][3] double or NULL;  phi  device [cap] double or NULL.
+ *  n_out host out: number of corners (both NULL: only count).
+ * Errors: TMS_E_CAPACITY (*n_out = required), TMS_E_INVALID. */
+int32_t tms_get_corners(tms_ctx *ctx, double *xyz, double *phi, int64_t cap, int64_t *n_out);
+
+/* Adjoint of the kept corner values and edge points with respect to the
+ * atoms (derivative of eq. Gaussian1 and of eq. intersection): for a loss L
+ * given through dL/dphi at the kept corners and dL/dt at the kept edge
+ * points, writes dL/d(x_i, y_i, z_i, r_i) for every atom.  Each edge point
+ * t = (c - phi0)/(phi1 - phi0) passes dL/dt (t - 1)/(phi1 - phi0) to its
+ * lower end and -dL/dt t/(phi1 - phi0) to its upper end; then
+ *   dL/dx_i = sum_p wbar_p 2D (p - x_i) term_ip,
+ *   dL/dr_i = sum_p wbar_p 2D r_i term_ip,
+ * term_ip = exp(-D(|p - x_i|^2 - r_i^2)) over the pairs inside R_c.  The
+ * leaves, masks and edge set are held fixed, and so is R_c (a truncation
+ * level).  Each (atom, corner) term is recomputed, nothing per pair is
+ * stored; terms use the precision of `cells` (TMS_PREC_FP32_GUARD: single
+ * precision exponentials, relative error per term <= 1.5e-7, double sums).
+ *  cells  the cells of the kept pass (the handle and its last build).
+ *  dphi   device [m] double, dL/dphi in tms_get_corners order, or NULL (0);
+ *         m must equal the kept corner count when dphi is given.
+ *  dt     device [nv] double, dL/dt in the order of the last
+ *         tms_extract_cube_vertices output, or NULL (0); nv must equal the
+ *         kept vertex count.  That extraction must have been made from the
+ *         kept leaves and corner values.
+ *  dxyzr  device [n_atoms][4] double, written in the caller's atom order.
+ * Errors: TMS_E_INVALID (no kept adaptive pass on these cells, count
+ * mismatch, edge points that do not end on kept corners, or a pass too large
+ * for the dense corner/edge bitmaps), TMS_E_DEVICE. */
+int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, int64_t m,
+                     const double *dt, int64_t nv, double *dxyzr);
+
 /* ---- device-time instrumentation ----------------------------------------
  * When enabled, the library brackets its kernel launches with HIP events on
  * the context's stream and accumulates the elapsed device time per phase

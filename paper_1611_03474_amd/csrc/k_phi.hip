@@ -263,18 +263,6 @@ __global__ void k_sum_final(const unsigned long long *__restrict__ part, int nb,
 // points (lat.n counts blocks per axis), blocks in raster order, so the
 // unique corners come out in compact spatial groups and a wavefront of the
 // phi kernel works on neighbouring points.
-__device__ __forceinline__ int64_t lat_bit(const Lat &lat, int64_t X, int64_t Y, int64_t Z) {
-    const int64_t w = ((X >> 2) * lat.n[1] + (Y >> 2)) * lat.n[2] + (Z >> 2);
-    return ((lat.base + w) << 6) + ((X & 3) << 4) + ((Y & 3) << 2) + (Z & 3);
-}
-
-__device__ __forceinline__ int64_t bit_rank(const uint64_t *__restrict__ bm,
-                                            const int32_t *__restrict__ woff, int64_t b) {
-    const int64_t w = b >> 6;
-    const uint64_t below = bm[w] & ((1ull << (b & 63)) - 1ull);
-    return (int64_t)woff[w] + __popcll(below);
-}
-
 __device__ __forceinline__ void leaf_corner(const tms_leaf &L, int v, int K, int64_t &X, int64_t &Y,
                                             int64_t &Z) {
     const int sh = K - L.level;

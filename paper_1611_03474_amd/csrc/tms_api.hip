@@ -3,6 +3,7 @@
 // partition/estimation kernels (Section 2.2 of Liu, Chen & Lu,
 // arXiv:1611.03474) on one HIP stream.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -228,6 +229,8 @@ int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int
 // exact, that is at most eps (1 + 1/b) <= 4.4e-6 for b = 0.035.
 constexpr double kCornerBand = 0.035;
 
+std::atomic<uint64_t> g_cells_ids{0};
+
 // Largest dense bitmap (bits) used for corner and edge de-duplication; larger
 // lattices fall back to hashing.  8 GiB.
 constexpr double kMaxBitmapBits = 68719476736.0;
@@ -282,6 +285,9 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     hipStream_t s = ctx->stream;
     *n_corners = 0;
     *n_guard = 0;
+    ctx->n_corners = 0;
+    ctx->corner_cells = cells->id;
+    ctx->corner_dense = n <= 0;  // an empty pass has a (trivially) dense corner set
     if (n <= 0) return TMS_OK;
     const int64_t ncand = 8 * n;
     if (ncand >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves (%lld)", (long long)n);
@@ -327,6 +333,9 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
                                               leaves_out, cphi, s));
             }
             *n_corners = nu;
+            ctx->n_corners = nu;
+            ctx->corner_dense = true;
+            ctx->corner_lat = lat;
             return TMS_OK;
         }
     }
@@ -370,6 +379,7 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
                                    ctx->uphi.as<double>(), g.c, leaves_out, cphi, s));
     }
     *n_corners = nu;
+    ctx->n_corners = nu;
     return TMS_OK;
 }
 
@@ -545,6 +555,7 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     };
     cells->p = *p;
     cells->n = n;
+    cells->id = ++g_cells_ids;
     if (p->mode == TMS_MODE_UNIFORM) K = 0;
 
     // bounding box, radii, finiteness
@@ -721,6 +732,9 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                                     ctx->corner_phi.as<double>(), s));
         st.n_corners = m;
         st.guard_points = ng;
+        ctx->n_corners = m;
+        ctx->corner_cells = cells->id;
+        ctx->corner_dense = false;
     } else {
         // Q_0: roots with a non-empty neighbourhood, raster order
         const int64_t nr = cells->nroots;
@@ -939,23 +953,30 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
             }
         el.words = words;
     }
+    ctx->n_verts = 0;
+    ctx->edge_cells = cells->id;
+    ctx->edge_dense = n == 0;
     if (n > 0 && ebits <= kMaxBitmapBits && el.words < (int64_t)0x7FFFFFFF) {
+        // edge bitmaps in buffers of their own: the corner bitmap stays
+        // valid for the adjoint
         const int64_t nwords = el.words;
-        HIPCK(ctx->bmap.ensure(sizeof(uint64_t) * (size_t)nwords));
-        HIPCK(ctx->bmcnt.ensure(sizeof(int32_t) * (size_t)nwords));
-        HIPCK(ctx->bmoff.ensure(sizeof(int32_t) * (size_t)nwords));
+        HIPCK(ctx->ebmap.ensure(sizeof(uint64_t) * (size_t)nwords));
+        HIPCK(ctx->ebcnt.ensure(sizeof(int32_t) * (size_t)nwords));
+        HIPCK(ctx->eboff.ensure(sizeof(int32_t) * (size_t)nwords));
         {
             TimedScope ts_(ctx, TMS_T_EXTRACT);
-            HIPCK(launch_fill_u64(ctx->bmap.as<uint64_t>(), 0ull, nwords, s));
-            HIPCK(launch_edge_mark(lv, n, g.K, el, ctx->bmap.as<unsigned long long>(), s));
-            HIPCK(launch_popc(ctx->bmap.as<uint64_t>(), nwords, ctx->bmcnt.as<int32_t>(), s));
+            HIPCK(launch_fill_u64(ctx->ebmap.as<uint64_t>(), 0ull, nwords, s));
+            HIPCK(launch_edge_mark(lv, n, g.K, el, ctx->ebmap.as<unsigned long long>(), s));
+            HIPCK(launch_popc(ctx->ebmap.as<uint64_t>(), nwords, ctx->ebcnt.as<int32_t>(), s));
         }
-        int32_t rc = scan_total(ctx, ctx->bmcnt.as<int32_t>(), ctx->bmoff.as<int32_t>(), nwords, &nv);
+        int32_t rc = scan_total(ctx, ctx->ebcnt.as<int32_t>(), ctx->eboff.as<int32_t>(), nwords, &nv);
         if (rc) return rc;
         HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
         TimedScope ts_(ctx, TMS_T_EXTRACT);
-        HIPCK(launch_edge_write(g, lv, cphi, n, el, ctx->bmap.as<uint64_t>(),
-                                ctx->bmoff.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
+        HIPCK(launch_edge_write(g, lv, cphi, n, el, ctx->ebmap.as<uint64_t>(),
+                                ctx->eboff.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
+        ctx->edge_dense = true;
+        ctx->edge_lat = el;
     } else if (n > 0) {
         unsigned long long *ctr = ctx->counters.as<unsigned long long>();
         HIPCK(hipMemsetAsync(ctr, 0, 8, s));
@@ -1016,6 +1037,81 @@ int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_
         HIPCK(hipMemcpyAsync(out, ctx->verts.p, sizeof(tms_vertex) * (size_t)ctx->n_verts,
                              hipMemcpyDeviceToDevice, ctx->stream));
     HIPCK(hipStreamSynchronize(ctx->stream));
+    return TMS_OK;
+}
+
+int32_t tms_get_corners(tms_ctx *ctx, double *xyz, double *phi, int64_t cap, int64_t *n_out) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!n_out) return fail(ctx, TMS_E_INVALID, "n_out is NULL");
+    const int64_t m = ctx->n_corners;
+    *n_out = m;
+    if (!xyz && !phi) return TMS_OK;
+    if (cap < m) return fail(ctx, TMS_E_CAPACITY, "corner capacity %lld < %lld", (long long)cap, (long long)m);
+    HIPCK(hipSetDevice(ctx->device));
+    if (m > 0) {
+        if (xyz)
+            HIPCK(hipMemcpyAsync(xyz, ctx->uniq.p, sizeof(double) * 3 * (size_t)m,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+        if (phi)
+            HIPCK(hipMemcpyAsync(phi, ctx->uphi.p, sizeof(double) * (size_t)m,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIPCK(hipStreamSynchronize(ctx->stream));
+    return TMS_OK;
+}
+
+int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, int64_t m,
+                     const double *dt, int64_t nv, double *dxyzr) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    if (cells->n > 0 && !dxyzr) return fail(ctx, TMS_E_INVALID, "dxyzr is NULL");
+    if (ctx->corner_cells != cells->id || !ctx->corner_dense)
+        return fail(ctx, TMS_E_INVALID,
+                    "no kept corners of an adaptive pass on these cells (run "
+                    "tms_partition_estimate on them first; the hashed corner path has no adjoint)");
+    if (dphi && m != ctx->n_corners)
+        return fail(ctx, TMS_E_INVALID, "dphi holds %lld values, %lld corners are kept",
+                    (long long)m, (long long)ctx->n_corners);
+    if (dt) {
+        if (ctx->edge_cells != cells->id || !ctx->edge_dense)
+            return fail(ctx, TMS_E_INVALID,
+                        "no kept edge points of these cells (run tms_extract_cube_vertices on the "
+                        "kept leaves first; the hashed edge path has no adjoint)");
+        if (nv != ctx->n_verts)
+            return fail(ctx, TMS_E_INVALID, "dt holds %lld values, %lld edge points are kept",
+                        (long long)nv, (long long)ctx->n_verts);
+    }
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const Grid &g = cells->g;
+    const int64_t M = ctx->n_corners;
+    if (M == 0) {  // no corners: every derivative is zero
+        if (cells->n > 0)
+            HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(dxyzr), 0ull, 4 * cells->n, s));
+        HIPCK(hipStreamSynchronize(s));
+        return TMS_OK;
+    }
+    HIPCK(ctx->wbar.ensure(sizeof(double) * (size_t)M));
+    unsigned *bad = reinterpret_cast<unsigned *>(ctx->counters.as<unsigned long long>() + 96);
+    HIPCK(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
+    {
+        TimedScope ts_(ctx, TMS_T_BACKWARD);
+        HIPCK(launch_adjoint_fold(g, ctx->corner_lat, ctx->bmap.as<uint64_t>(),
+                                  ctx->bmoff.as<int32_t>(), ctx->uniq.as<double>(),
+                                  ctx->uphi.as<double>(), M, dphi, ctx->edge_lat,
+                                  ctx->ebmap.as<uint64_t>(), ctx->eboff.as<int32_t>(), dt,
+                                  ctx->wbar.as<double>(), bad, s));
+        HIPCK(launch_adjoint_atoms(g, cells->p.precision, ctx->corner_lat, ctx->bmap.as<uint64_t>(),
+                                   ctx->bmoff.as<int32_t>(), ctx->uniq.as<double>(),
+                                   ctx->wbar.as<double>(), cells->n, cells->ax.as<double>(),
+                                   cells->ay.as<double>(), cells->az.as<double>(),
+                                   cells->aw.as<double>(), cells->ar.as<double>(),
+                                   cells->aidx.as<int32_t>(), dxyzr, s));
+    }
+    unsigned hb = 0;
+    HIPCK(d2h(&hb, bad, 1, s));
+    if (hb) return fail(ctx, TMS_E_INVALID, "kept edge points do not end on kept corners");
     return TMS_OK;
 }
 

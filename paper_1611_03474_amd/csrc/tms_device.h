@@ -460,4 +460,24 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
         }
 }
 
+// Bit of finest-lattice point (X, Y, Z) in a dense corner bitmap: 4x4x4
+// point blocks per 64-bit word, words X-major over blocks.
+__device__ __forceinline__ int64_t lat_bit(const Lat &lat, int64_t X, int64_t Y, int64_t Z) {
+    const int64_t w = ((X >> 2) * lat.n[1] + (Y >> 2)) * lat.n[2] + (Z >> 2);
+    return ((lat.base + w) << 6) + ((X & 3) << 4) + ((Y & 3) << 2) + (Z & 3);
+}
+
+// Rank of set bit b among all set bits (woff: exclusive scan of word counts).
+__device__ __forceinline__ int64_t bit_rank(const uint64_t *__restrict__ bm,
+                                            const int32_t *__restrict__ woff, int64_t b) {
+    const int64_t w = b >> 6;
+    const uint64_t below = bm[w] & ((1ull << (b & 63)) - 1ull);
+    return (int64_t)woff[w] + __popcll(below);
+}
+
+__device__ __forceinline__ bool bit_test(const uint64_t *__restrict__ bm, int64_t b) {
+    return (bm[b >> 6] >> (b & 63)) & 1ull;
+}
+
 }  // namespace tms
+

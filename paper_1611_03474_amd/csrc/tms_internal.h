@@ -94,6 +94,7 @@ struct tms_cells {
     int64_t n_root_entries = 0;  // sum of root neighbourhood sizes
     int64_t n_nonempty = 0;      // roots with a non-empty neighbourhood
     double rmax = 0;
+    uint64_t id = 0;             // changes with every build (kept results name it)
     // device memory, atoms sorted by cell (ascending original index inside a cell)
     tms::DevBuf ax, ay, az, aw, aidx, ar;   // double x3, w = exp(D r^2), int32 index, r
     tms::DevBuf cell_start;                 // int32 [ncells + 1]
@@ -114,12 +115,22 @@ struct tms_ctx {
     // last extract result
     tms::DevBuf verts;
     int64_t n_verts = 0;
+    // unique corners of the last corner stage (uniq, uphi; ranks in the dense
+    // corner bitmap bmap/bmoff when corner_dense) and the edge bitmaps of the
+    // last extraction (ebmap/eboff when edge_dense); kept for the adjoint
+    int64_t n_corners = 0;
+    uint64_t corner_cells = 0, edge_cells = 0;  // tms_cells::id they belong to
+    bool corner_dense = false, edge_dense = false;
+    tms::Lat corner_lat{};
+    tms::EdgeLat edge_lat{};
+    tms::DevBuf ebmap, ebcnt, eboff, wbar;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
         slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs, bmap, bmcnt, bmoff;
     // small device counters (u64 slots): [0,64) striped pair counts,
     // 64/65 hard-list lengths, [72,77) decision histogram, 80 surface count,
-    // 100 scan total; [256, 256 + 5*1024) reduction partials
+    // 96 adjoint consistency flag, 100 scan total; [256, 256 + 5*1024)
+    // reduction partials
     tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -163,6 +174,18 @@ hipError_t launch_root_count(const Grid &g, const int32_t *cell_start, const dou
 hipError_t launch_root_fill(const Grid &g, const int32_t *cell_start, const double *ax,
                             const double *ay, const double *az, int64_t nroots,
                             const int32_t *start, int32_t *atoms, hipStream_t s);
+
+// k_adjoint.hip
+hipError_t launch_adjoint_fold(const Grid &g, const Lat &lat, const uint64_t *cbm,
+                               const int32_t *coff, const double *upts, const double *uphi,
+                               int64_t m, const double *dphi, const EdgeLat &el,
+                               const uint64_t *ebm, const int32_t *eoff, const double *dt,
+                               double *wbar, unsigned *bad, hipStream_t s);
+hipError_t launch_adjoint_atoms(const Grid &g, int precision, const Lat &lat, const uint64_t *cbm,
+                                const int32_t *coff, const double *upts, const double *wbar,
+                                int64_t n, const double *ax, const double *ay, const double *az,
+                                const double *aw, const double *ar, const int32_t *aidx,
+                                double *out, hipStream_t s);
 
 // k_scan.hip -- exclusive scan of int32 values into int32 offsets; total
 // written to *total_dev (device).  tmp must hold scan_tmp_bytes(n).

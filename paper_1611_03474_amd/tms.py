@@ -101,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     L.tms_get_leaves.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
     L.tms_extract_cube_vertices.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(i64)]
     L.tms_get_vertices.argtypes = [_VP, _VP, i64, C.POINTER(i64)]
+    L.tms_get_corners.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
+    L.tms_backward.argtypes = [_VP, _VP, _VP, i64, _VP, i64, _VP]
     L.tms_set_timing.argtypes = [_VP, i32]
     L.tms_get_timing.argtypes = [_VP, C.POINTER(Timing), i32]
     L.tms_debug_tensor.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP]
@@ -110,7 +112,7 @@ def load_library(path: str = LIB_PATH):
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
-              "tms_get_timing", "tms_debug_fast_exp"):
+              "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -286,6 +288,15 @@ class Context:
             self._check(rc)
         return out[:n.value]
 
+    def get_vertices(self):
+        """Vertices [V, 40] of the last extraction."""
+        t = self._torch
+        n = C.c_int64()
+        self._check(self.lib.tms_get_vertices(self.h, None, 0, C.byref(n)))
+        out = t.empty((max(n.value, 1), 40), dtype=t.uint8, device=self.device)
+        self._check(self.lib.tms_get_vertices(self.h, _VP(_ptr(out)), n.value, C.byref(n)))
+        return out[:n.value]
+
     def extract_into(self, cells: Cells, leaves, nl: int, corner_phi, out):
         n = C.c_int64()
         rc = self.lib.tms_extract_cube_vertices(self.h, cells.handle, _VP(_ptr(leaves)), nl,
@@ -297,6 +308,33 @@ class Context:
             raise e
         self._check(rc)
         return n.value
+
+    # --------------------------------------------------------------- adjoint
+    def get_corners(self):
+        """Unique corners of the last pass: (xyz [M, 3], phi [M])."""
+        t = self._torch
+        n = C.c_int64()
+        self._check(self.lib.tms_get_corners(self.h, None, None, 0, C.byref(n)))
+        m = n.value
+        xyz = t.empty((max(m, 1), 3), dtype=t.float64, device=self.device)
+        phi = t.empty(max(m, 1), dtype=t.float64, device=self.device)
+        self._check(self.lib.tms_get_corners(self.h, _VP(_ptr(xyz)), _VP(_ptr(phi)), m,
+                                             C.byref(n)))
+        return xyz[:m], phi[:m]
+
+    def backward(self, cells: Cells, dphi=None, dt=None, out=None):
+        """dL/d(x, y, z, r) of every atom [N, 4] from dL/dphi at the kept corners
+        and dL/dt at the kept edge points (either may be None)."""
+        t = self._torch
+        if out is None:
+            out = t.empty((cells.n_atoms, 4), dtype=t.float64, device=self.device)
+        assert out.dtype == t.float64 and out.is_contiguous() and out.shape == (cells.n_atoms, 4)
+        for a in (dphi, dt):
+            assert a is None or (a.dtype == t.float64 and a.is_contiguous() and a.dim() == 1)
+        self._check(self.lib.tms_backward(self.h, cells.handle, _VP(_ptr(dphi)),
+                                          0 if dphi is None else dphi.shape[0], _VP(_ptr(dt)),
+                                          0 if dt is None else dt.shape[0], _VP(_ptr(out))))
+        return out
 
     # ---------------------------------------------------------------- timing
     def set_timing(self, enable: bool):
@@ -345,3 +383,60 @@ def leaves_to_numpy(leaves) -> np.ndarray:
 
 def vertices_to_numpy(verts) -> np.ndarray:
     return verts.cpu().numpy().reshape(-1).view(VERTEX_DTYPE)
+
+
+def vertex_t(verts):
+    """The t column of a vertex tensor [V, 40] (uint8) as float64 [V]."""
+    return verts.view(-1).view(__import__("torch").float64).view(-1, 5)[:, 1]
+
+
+def vertex_edge_h(verts, h0: float):
+    """Edge length of every vertex's edge, from the level in its key."""
+    import torch
+    key = verts.view(-1).view(torch.int64).view(-1, 5)[:, 0]
+    level = (key >> 50) & 7
+    return h0 * torch.pow(torch.tensor(0.5, dtype=torch.float64, device=verts.device),
+                          level.to(torch.float64))
+
+
+def _surface_function():
+    import torch
+
+    class GaussianSurface(torch.autograd.Function):
+        """Differentiable pass: atoms [N, 4] (x, y, z, r) -> (phi at the unique
+        leaf corners [M], t of the edge points [V]).  The backward runs the
+        library's adjoint kernels with the discrete structure of the forward
+        pass held fixed."""
+
+        @staticmethod
+        def forward(fctx, xyzr, tctx, params):
+            cells = tctx.build_cells(xyzr.detach(), params)
+            leaves, cphi, st = tctx.partition_estimate(cells)
+            verts = tctx.extract(cells, leaves, cphi)
+            _, phi = tctx.get_corners()
+            fctx.tctx = tctx
+            fctx.cells = cells
+            fctx.info = dict(leaves=leaves, verts=verts, stats=st)
+            return phi, vertex_t(verts).clone()
+
+        @staticmethod
+        def backward(fctx, dphi, dt):
+            tctx, cells = fctx.tctx, fctx.cells
+            g = tctx.backward(cells, None if dphi is None else dphi.contiguous(),
+                              None if dt is None else dt.contiguous())
+            tctx.free_cells(cells)
+            return g, None, None
+
+    return GaussianSurface
+
+
+_GS = None
+
+
+def gaussian_surface(xyzr, tctx: Context, params: Params):
+    """(phi at the unique leaf corners, t of the edge points), differentiable
+    with respect to xyzr through the library's adjoint."""
+    global _GS
+    if _GS is None:
+        _GS = _surface_function()
+    return _GS.apply(xyzr, tctx, params)
