@@ -85,6 +85,43 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
     return dict(ms_per_step=ms, stats=sd, n_leaves=nl, n_vertices=nv, timing=per_step)
 
 
+def run_adjoint(ctx, tms, steps, warmup):
+    """Differentiation workload: forward pass (partition, corners, edge
+    points) and the adjoint of the surface loss on a 20,000-atom globule."""
+    import torch
+    from paper_1611_03474_amd import workloads
+    w = workloads.GLOBULE20K_ADJOINT
+    atoms = torch.as_tensor(workloads.atoms(w), dtype=torch.float64, device="cuda:0")
+    p = w.params(tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells(atoms, p)
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    _, phi = ctx.get_corners()
+    t = tms.vertex_t(verts).clone()
+    h = tms.vertex_edge_h(verts, w.h0)
+    dphi = (2.0 * (phi - w.c)).contiguous()
+    dt = (2.0 * (t - 0.5) * h * h).contiguous()
+    g = torch.empty((atoms.shape[0], 4), dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        ctx.backward(cells, dphi, dt, out=g)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.get_timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.backward(cells, dphi, dt, out=g)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = ctx.get_timing(reset=True)
+    ctx.set_timing(False)
+    ctx.free_cells(cells)
+    return {"workload": w.name, "atoms": int(atoms.shape[0]), "leaves": int(leaves.shape[0]),
+            "corners": int(phi.shape[0]), "vertices": int(t.shape[0]),
+            "backward_ms": (t1 - t0) * 1e3 / steps,
+            "backward_device_ms": tm["backward"]["ms"] / steps,
+            "atoms_per_s": atoms.shape[0] / ((t1 - t0) / steps)}
+
+
 def cpu_baseline(atoms, w):
     """FP64 oracle on a bounded sample: the first globule of the assembly and
     its hydrogens (about 1/20 of the workload)."""
@@ -113,6 +150,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--workload", default="assembly110k")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (counter scale for HBM traffic)")
@@ -214,6 +252,10 @@ def main():
                                               for k, v in f64["timing"].items()},
                        "same_leaf_count": f64["n_leaves"] == f32["n_leaves"]}
         out["speedup_fp32guard_vs_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+    if not args.no_adjoint:
+        log("adjoint run")
+        out["adjoint"] = run_adjoint(ctx, tms, args.steps, args.warmup)
+        log("  %.2f ms per backward" % out["adjoint"]["backward_ms"])
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(atoms, w)

@@ -577,7 +577,6 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     g.c = p->c;
     g.tau = p->tau;
     g.K = K;
-    g.span = 2;
     cells->rmax = n > 0 ? st[6] : 0.0;
     g.rc2 = cells->rmax * cells->rmax + std::log(1.0 / p->eps_cut) / p->D;
     for (int a = 0; a < 3; ++a) {
@@ -589,10 +588,14 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
             return bail(fail(ctx, TMS_E_INVALID, "finest lattice exceeds 65535 points per axis"));
         g.nr[a] = (int32_t)d;
     }
-    // atom cells: edge h0 * 2^m >= R_c / 2, so a +-2 cell stencil covers R_c
+    // atom cells: the smallest edge h0 * 2^m >= R_c / 4, and a stencil of
+    // +-span cells (span = ceil(R_c / edge)) around a point's cell; point
+    // queries clip each row of the stencil to the R_c sphere
     const double Rc = std::sqrt(g.rc2);
     g.cs = p->h0;
-    while (g.cs < 0.5 * Rc) g.cs *= 2.0;
+    while (g.cs < 0.25 * Rc) g.cs *= 2.0;
+    while (0.5 * g.cs >= 0.25 * Rc) g.cs *= 0.5;
+    g.span = (int32_t)std::ceil(Rc / g.cs);
     int64_t ncells = 1;
     for (int a = 0; a < 3; ++a) {
         g.nc[a] = (int32_t)std::max(1.0, std::ceil(g.nr[a] * p->h0 / g.cs));

@@ -423,7 +423,7 @@ __device__ __forceinline__ void sample_range(const double *A, double &lo, double
 // phi and grad phi at one point (eq. Gaussian1).
 // ---------------------------------------------------------------------------
 // Sum over atoms within R_c of p, in canonical atom order (cell rows of the
-// 5x5x5 stencil, atoms in cell order).  *err (FAST only) bounds |dphi|.
+// stencil, atoms in cell order).  *err (FAST only) bounds |dphi|.
 template <bool FAST>
 __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                                        const int32_t *__restrict__ cs, const double *__restrict__ ax,
@@ -441,11 +441,24 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
         c0[a] = max(ci - g.span, 0);
         c1[a] = min(ci + g.span, g.nc[a] - 1);
     }
-    for (int cz = c0[2]; cz <= c1[2]; ++cz)
+    // rows of the stencil along x, each clipped to the chord of the R_c
+    // sphere; skipped cells hold only atoms beyond R_c
+    for (int cz = c0[2]; cz <= c1[2]; ++cz) {
+        const double lz = g.o[2] + cz * g.cs;
+        const double ez = fmax(fmax(lz - p[2], p[2] - (lz + g.cs)), 0.0);
+        const double rz = g.rc2 - ez * ez;
+        if (rz < 0.0) continue;
         for (int cy = c0[1]; cy <= c1[1]; ++cy) {
+            const double ly = g.o[1] + cy * g.cs;
+            const double ey = fmax(fmax(ly - p[1], p[1] - (ly + g.cs)), 0.0);
+            const double ryz = rz - ey * ey;
+            if (ryz < 0.0) continue;
+            const double hx = sqrt(ryz);
+            const int x0 = max(c0[0], (int)floor((p[0] - hx - g.o[0]) / g.cs));
+            const int x1 = min(c1[0], (int)floor((p[0] + hx - g.o[0]) / g.cs));
+            if (x0 > x1) continue;
             const int row = (cz * g.nc[1] + cy) * g.nc[0];
-            if (c0[0] > c1[0]) continue;
-            const int b = cs[row + c0[0]], e = cs[row + c1[0] + 1];
+            const int b = cs[row + x0], e = cs[row + x1 + 1];
             for (int i = b; i < e; ++i) {
                 const double dx = p[0] - ax[i], dy = p[1] - ay[i], dz = p[2] - az[i];
                 const double d2 = dx * dx + dy * dy + dz * dz;
@@ -458,6 +471,7 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                 gr[2] += f * dz;
             }
         }
+    }
 }
 
 // Bit of finest-lattice point (X, Y, Z) in a dense corner bitmap: 4x4x4

@@ -21,11 +21,11 @@ struct Grid {
     double hmin;     // finest cube edge
     double D, c, tau;
     double rc2;      // squared cut-off radius
-    double cs;       // atom-cell edge (h0 * 2^m >= R_c / 2)
+    double cs;       // atom-cell edge (smallest h0 * 2^m >= R_c / 4)
     int32_t nr[3];   // root cubes per axis
     int32_t nc[3];   // atom cells per axis
     int32_t K;       // finest level
-    int32_t span;    // cell stencil half-width (2)
+    int32_t span;    // cell stencil half-width, ceil(R_c / cs)
 };
 
 // Gauss-Legendre rule folded for the even/odd parts of a function on [-1,1]:

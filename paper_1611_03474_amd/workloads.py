@@ -36,6 +36,10 @@ GLOBULE200_UNIFORM = Workload(
     D=0.9, h0=0.5, h_min=0.5, uniform=True)
 GLOBULE5K = {D: Workload("globule5k_D%g" % D, "5,000-atom globule, adaptive 2 -> 0.25, tau 1e-3",
                          D=D) for D in (0.5, 0.9, 1.5)}
+GLOBULE20K_ADJOINT = Workload(
+    "globule20k_adjoint",
+    "20,000-atom globule, adaptive 2 -> 0.25, tau 1e-3; loss sum (phi - c)^2 over unique leaf "
+    "corners + sum ((t - 1/2) h)^2 over edge points, gradient w.r.t. centres and radii", D=0.9)
 ASSEMBLY110K = Workload(
     "assembly110k",
     "110,000-atom assembly (20 globules of 5,000 atoms, 2 A gaps, plus 10% hydrogens r=1.2), "
@@ -47,9 +51,12 @@ def atoms(w: Workload):
         return synth.globule(200, 1001)
     if w.name.startswith("globule5k"):
         return synth.globule(5000, 1002)
+    if w.name == "globule20k_adjoint":
+        return synth.globule(20000, 1004)
     if w.name == "assembly110k":
         return synth.assembly(20, 5000, seed=1003, h_frac=0.10)
     raise KeyError(w.name)
 
 
-ALL = {w.name: w for w in [GLOBULE200_UNIFORM, *GLOBULE5K.values(), ASSEMBLY110K]}
+ALL = {w.name: w for w in [GLOBULE200_UNIFORM, *GLOBULE5K.values(), GLOBULE20K_ADJOINT,
+                           ASSEMBLY110K]}
