@@ -157,6 +157,34 @@ int32_t tms_check_atoms_host(const double *xyzr, int64_t n, const tms_params *p,
 int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_params *p,
                         tms_cells **cells);
 
+/* Cells of a batch of conformations refined together (the same method and
+ * parameters on every conformation, Section 2.2; each conformation keeps its
+ * own root grid, cut-off radius and atom cells, exactly as if it were built
+ * alone).  One tms_partition_estimate then refines every conformation in the
+ * same launches: each level's work queue holds the cubes of all
+ * conformations.
+ *  xyzr     device [offsets[n_conf]][4] double: the conformations' atoms,
+ *           concatenated; conformation b is atoms [offsets[b], offsets[b+1]).
+ *           Caller-owned, copied.
+ *  offsets  host [n_conf + 1] int64, offsets[0] = 0, non-decreasing.
+ *  n_conf   1 .. 2048 (the conformation id takes 11 bits of an edge key).
+ * Leaves carry their conformation in tms_leaf.conf and come out grouped by
+ * conformation (each group in the single-conformation order); vertices are
+ * in edge-key order, hence grouped by conformation too; tms_batch_counts
+ * gives the group boundaries.  tms_eval_phi and tms_backward take
+ * single-conformation cells only; the uniform grid takes one conformation.
+ * Errors: as tms_build_cells, plus TMS_E_INVALID for bad offsets. */
+int32_t tms_build_cells_batch(tms_ctx *ctx, const double *xyzr, const int64_t *offsets,
+                              int32_t n_conf, const tms_params *p, tms_cells **cells);
+
+/* Per-conformation boundaries of the kept results of `cells`: leaf_offsets
+ * [n_conf + 1] of the last partition pass, vertex_offsets [n_conf + 1] of
+ * the last extraction (host arrays; either may be NULL).
+ * Errors: TMS_E_INVALID (no kept result of these cells; vertex offsets of a
+ * hashed extraction of more than one conformation). */
+int32_t tms_batch_counts(tms_ctx *ctx, const tms_cells *cells, int64_t *leaf_offsets,
+                         int64_t *vertex_offsets);
+
 /* Grid of a cell structure (host outputs; any pointer may be NULL). */
 int32_t tms_cells_info(const tms_cells *cells, double origin[3], int64_t dims[3], int32_t *K,
                        double *rc2, int64_t *n_atoms);

@@ -1,13 +1,17 @@
 // Atom binning and per-root neighbourhood lists (gfx950).
 //
 // The sums of Section 2.2.1 (after eq. polynew) run only over atoms near a
-// cube.  Atoms are counting-sorted into cells of edge cs >= R_c/2 aligned with
-// the root grid; inside a cell they keep ascending input order, so every sum
-// below visits atoms in one canonical order and results are reproducible bit
-// for bit.  Each root cube then gets the list of atoms whose squared distance
-// to the root box is <= R_c^2 -- a superset of the neighbourhood of every cube
-// inside it.
-#include "tms_internal.h"
+// cube.  Atoms are counting-sorted into cells (edge: the smallest h0 * 2^m
+// >= R_c / 4) aligned with the root grid; inside a cell they keep ascending
+// input order, so every sum below visits atoms in one canonical order and
+// results are reproducible bit for bit.  Each root cube then gets the list of
+// atoms whose squared distance to the root box is <= R_c^2 -- a superset of
+// the neighbourhood of every cube inside it.
+//
+// A batch of conformations shares these arrays: conformation b owns the
+// cells [cell_base, ...) and roots [root_base, ...) of its geometry entry,
+// and its atoms [atom_base, ...) of the concatenated input.
+#include "tms_device.h"
 
 namespace tms {
 
@@ -17,12 +21,17 @@ constexpr int kBS = 256;
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// out[0..2] min xyz, [3..5] max xyz, [6] max r, [7] min r, [8] count of
-// non-finite values; partials per block then one final block.
-__global__ void k_stats_partial(const double *__restrict__ xyzr, int64_t n, double *__restrict__ part) {
+// Per conformation b (one workgroup each, atoms [off[b], off[b+1])):
+// out[9b + 0..2] min xyz, [3..5] max xyz, [6] max r, [7] min r, [8] count of
+// non-finite values.
+__global__ __launch_bounds__(kBS) void k_stats_conf(const double *__restrict__ xyzr,
+                                                    const int64_t *__restrict__ off,
+                                                    double *__restrict__ out) {
+    const int b = blockIdx.x;
+    const int64_t i0 = off[b], i1 = off[b + 1];
     double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
     double rmax = -1e308, rmin = 1e308, bad = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBS) {
         double v[4] = {xyzr[4 * i], xyzr[4 * i + 1], xyzr[4 * i + 2], xyzr[4 * i + 3]};
         bool ok = true;
 #pragma unroll
@@ -49,7 +58,7 @@ __global__ void k_stats_partial(const double *__restrict__ xyzr, int64_t n, doub
     sh[8][threadIdx.x] = bad;
     __syncthreads();
     for (int st = kBS / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
+        if ((int)threadIdx.x < st) {
             int o = threadIdx.x + st;
             for (int a = 0; a < 3; ++a) {
                 sh[a][threadIdx.x] = fmin(sh[a][threadIdx.x], sh[a][o]);
@@ -61,42 +70,26 @@ __global__ void k_stats_partial(const double *__restrict__ xyzr, int64_t n, doub
         }
         __syncthreads();
     }
-    if (threadIdx.x < 9) part[blockIdx.x * 9 + threadIdx.x] = sh[threadIdx.x][0];
-}
-
-__global__ void k_stats_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
-    if (threadIdx.x != 0) return;
-    double r[9];
-    for (int a = 0; a < 9; ++a) r[a] = part[a];
-    for (int b = 1; b < nb; ++b) {
-        const double *p = part + 9 * b;
-        for (int a = 0; a < 3; ++a) {
-            r[a] = fmin(r[a], p[a]);
-            r[3 + a] = fmax(r[3 + a], p[3 + a]);
-        }
-        r[6] = fmax(r[6], p[6]);
-        r[7] = fmin(r[7], p[7]);
-        r[8] += p[8];
-    }
-    for (int a = 0; a < 9; ++a) out[a] = r[a];
+    if (threadIdx.x < 9) out[9 * b + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __device__ __forceinline__ int cell_of(const Grid &g, double x, int a) {
     return clampi((int)floor((x - g.o[a]) / g.cs), 0, g.nc[a] - 1);
 }
 
-__global__ void k_bin(Grid g, const double *__restrict__ xyzr, int64_t n, int32_t *__restrict__ key,
-                      int32_t *__restrict__ cnt) {
+__global__ void k_bin(const Grid *__restrict__ gt, int nconf, const double *__restrict__ xyzr,
+                      int64_t n, int32_t *__restrict__ key, int32_t *__restrict__ cnt) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (i >= n) return;
+    const Grid &g = gt[conf_of_atom(gt, nconf, i)];
     int cx = cell_of(g, xyzr[4 * i], 0), cy = cell_of(g, xyzr[4 * i + 1], 1),
         cz = cell_of(g, xyzr[4 * i + 2], 2);
-    int k = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+    int k = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0] + cx;
     key[i] = k;
     atomicAdd(&cnt[k], 1);
 }
 
-__global__ void k_scatter(Grid g, const double *__restrict__ xyzr, int64_t n,
+__global__ void k_scatter(const Grid *__restrict__ gt, const double *__restrict__ xyzr, int64_t n,
                           const int32_t *__restrict__ key, int32_t *__restrict__ fill,
                           double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
                           double *__restrict__ aw, double *__restrict__ ar,
@@ -109,7 +102,7 @@ __global__ void k_scatter(Grid g, const double *__restrict__ xyzr, int64_t n,
     ay[pos] = xyzr[4 * i + 1];
     az[pos] = xyzr[4 * i + 2];
     ar[pos] = r;
-    aw[pos] = exp(g.D * r * r);
+    aw[pos] = exp(gt[0].D * r * r);
     aidx[pos] = (int32_t)i;
 }
 
@@ -145,17 +138,20 @@ __global__ void k_sort_cells(const int32_t *__restrict__ start, int64_t ncells, 
 // Visit the atoms whose squared distance to the root box is <= R_c^2, in
 // cell order.  EMIT=false counts, EMIT=true writes the sorted-atom indices.
 template <bool EMIT>
-__global__ void k_root_lists(Grid g, const int32_t *__restrict__ cs, const double *__restrict__ ax,
-                             const double *__restrict__ ay, const double *__restrict__ az,
-                             int64_t nroots, const int32_t *__restrict__ start,
-                             int32_t *__restrict__ out) {
+__global__ void k_root_lists(const Grid *__restrict__ gt, int nconf, const int32_t *__restrict__ cs,
+                             const double *__restrict__ ax, const double *__restrict__ ay,
+                             const double *__restrict__ az, int64_t nroots,
+                             const int32_t *__restrict__ start, int32_t *__restrict__ out) {
     int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (r >= nroots) return;
-    int rx = (int)(r % g.nr[0]), ry = (int)((r / g.nr[0]) % g.nr[1]),
-        rz = (int)(r / ((int64_t)g.nr[0] * g.nr[1]));
+    const Grid &g = gt[conf_of_root(gt, nconf, r)];
+    const int64_t rl = r - g.root_base;
+    int rx = (int)(rl % g.nr[0]), ry = (int)((rl / g.nr[0]) % g.nr[1]),
+        rz = (int)(rl / ((int64_t)g.nr[0] * g.nr[1]));
     double lo[3] = {g.o[0] + rx * g.h0, g.o[1] + ry * g.h0, g.o[2] + rz * g.h0};
     double hi[3] = {lo[0] + g.h0, lo[1] + g.h0, lo[2] + g.h0};
-    double R = sqrt(g.rc2);
+    const double rc2 = g.rc2;
+    double R = sqrt(rc2);
     int c0[3], c1[3];
     for (int a = 0; a < 3; ++a) {
         c0[a] = clampi((int)floor((lo[a] - R - g.o[a]) / g.cs), 0, g.nc[a] - 1);
@@ -165,14 +161,14 @@ __global__ void k_root_lists(Grid g, const int32_t *__restrict__ cs, const doubl
     int w = EMIT ? start[r] : 0;
     for (int cz = c0[2]; cz <= c1[2]; ++cz)
         for (int cy = c0[1]; cy <= c1[1]; ++cy) {
-            int row = (cz * g.nc[1] + cy) * g.nc[0];
+            int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
             int b = cs[row + c0[0]], e = cs[row + c1[0] + 1];
             for (int i = b; i < e; ++i) {
                 double x = ax[i], y = ay[i], z = az[i];
                 double dx = fmax(fmax(lo[0] - x, x - hi[0]), 0.0);
                 double dy = fmax(fmax(lo[1] - y, y - hi[1]), 0.0);
                 double dz = fmax(fmax(lo[2] - z, z - hi[2]), 0.0);
-                if (dx * dx + dy * dy + dz * dz <= g.rc2) {
+                if (dx * dx + dy * dy + dz * dz <= rc2) {
                     if (EMIT) out[w++] = i;
                     else ++cnt;
                 }
@@ -185,29 +181,25 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
 
 }  // namespace
 
-hipError_t launch_atom_stats(const double *xyzr, int64_t n, double *out, hipStream_t s) {
-    // out must hold 9 + 9 * 1024 doubles; partials live after the result
-    int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kBS - 1) / kBS));
-    double *part = out + 16;
-    hipLaunchKernelGGL(k_stats_partial, dim3(nb), dim3(kBS), 0, s, xyzr, n, part);
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, s, part, nb, out);
+hipError_t launch_atom_stats(const double *xyzr, const int64_t *off, int nconf, double *out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_stats_conf, dim3(nconf), dim3(kBS), 0, s, xyzr, off, out);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_atoms(const Grid &g, const double *xyzr, int64_t n, int32_t *key, int32_t *cnt,
-                            int64_t ncells, hipStream_t s) {
-    (void)ncells;
+hipError_t launch_bin_atoms(const Grid *gt, int nconf, const double *xyzr, int64_t n, int32_t *key,
+                            int32_t *cnt, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin, dim3(nblk(n)), dim3(kBS), 0, s, g, xyzr, n, key, cnt);
+    hipLaunchKernelGGL(k_bin, dim3(nblk(n)), dim3(kBS), 0, s, gt, nconf, xyzr, n, key, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_atoms(const Grid &g, const double *xyzr, int64_t n, const int32_t *key,
+hipError_t launch_scatter_atoms(const Grid *gt, const double *xyzr, int64_t n, const int32_t *key,
                                 int32_t *fill, double *ax, double *ay, double *az, double *aw,
                                 double *ar, int32_t *aidx, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(kBS), 0, s, g, xyzr, n, key, fill, ax, ay, az,
-                       aw, ar, aidx);
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(kBS), 0, s, gt, xyzr, n, key, fill, ax, ay,
+                       az, aw, ar, aidx);
     return hipGetLastError();
 }
 
@@ -218,19 +210,21 @@ hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *
     return hipGetLastError();
 }
 
-hipError_t launch_root_count(const Grid &g, const int32_t *cell_start, const double *ax,
-                             const double *ay, const double *az, int64_t nroots, int32_t *cnt,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_root_lists<false>, dim3(nblk(nroots)), dim3(kBS), 0, s, g, cell_start, ax,
-                       ay, az, nroots, nullptr, cnt);
+hipError_t launch_root_count(const Grid *gt, int nconf, const int32_t *cell_start,
+                             const double *ax, const double *ay, const double *az, int64_t nroots,
+                             int32_t *cnt, hipStream_t s) {
+    if (nroots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_root_lists<false>, dim3(nblk(nroots)), dim3(kBS), 0, s, gt, nconf,
+                       cell_start, ax, ay, az, nroots, nullptr, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_root_fill(const Grid &g, const int32_t *cell_start, const double *ax,
+hipError_t launch_root_fill(const Grid *gt, int nconf, const int32_t *cell_start, const double *ax,
                             const double *ay, const double *az, int64_t nroots,
                             const int32_t *start, int32_t *atoms, hipStream_t s) {
-    hipLaunchKernelGGL(k_root_lists<true>, dim3(nblk(nroots)), dim3(kBS), 0, s, g, cell_start, ax,
-                       ay, az, nroots, start, atoms);
+    if (nroots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_root_lists<true>, dim3(nblk(nroots)), dim3(kBS), 0, s, gt, nconf,
+                       cell_start, ax, ay, az, nroots, start, atoms);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ __global__ void k_edge_insert(const tms_leaf *__restrict__ leaves, int64_t n, in
     atomicMin(&hown[s], (uint32_t)c);
 }
 
-__global__ void k_edge_emit(Grid g, const tms_leaf *__restrict__ leaves,
+__global__ void k_edge_emit(const Grid *__restrict__ gt, const tms_leaf *__restrict__ leaves,
                             const double *__restrict__ cphi, int64_t ncand,
                             const int32_t *__restrict__ f, const int32_t *__restrict__ off_,
                             tms_vertex *__restrict__ out) {
@@ -82,6 +82,7 @@ __global__ void k_edge_emit(Grid g, const tms_leaf *__restrict__ leaves,
     if (c >= ncand || !f[c]) return;
     const int64_t q = c / 12;
     const tms_leaf L = leaves[q];
+    const Grid &g = gt[L.conf];
     int axis, off[3], v0, v1;
     edge_corners((int)(c % 12), axis, off, v0, v1);
     const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
@@ -127,8 +128,8 @@ __device__ __forceinline__ int64_t edge_bit(const EdgeLat &el, const tms_leaf &L
            (((int64_t)(L.ix + off[0]) * lat.n[1] + (L.iy + off[1])) * lat.n[2] + (L.iz + off[2]));
 }
 
-__global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n, EdgeLat el,
-                            unsigned long long *__restrict__ bm) {
+__global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n,
+                            const EdgeLat *__restrict__ et, unsigned long long *__restrict__ bm) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (c >= 12 * n) return;
     const tms_leaf L = leaves[c / 12];
@@ -136,17 +137,17 @@ __global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n, Edge
     int axis, off[3], v0, v1;
     edge_corners((int)(c % 12), axis, off, v0, v1);
     if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) return;
-    const int64_t b = edge_bit(el, L, axis, off);
+    const int64_t b = edge_bit(et[L.conf], L, axis, off);
     atomicOr(bm + (b >> 6), 1ull << (b & 63));
 }
 
 // every leaf that has a crossing edge writes its vertex at the edge's rank
 // (leaves sharing the edge share its corner values, so they write the same
 // bits); the list comes out in edge-key order
-__global__ void k_edge_write(Grid g, const tms_leaf *__restrict__ leaves,
-                             const double *__restrict__ cphi, int64_t n, EdgeLat el,
-                             const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
-                             tms_vertex *__restrict__ out) {
+__global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__restrict__ leaves,
+                             const double *__restrict__ cphi, int64_t n,
+                             const EdgeLat *__restrict__ et, const uint64_t *__restrict__ bm,
+                             const int32_t *__restrict__ woff, tms_vertex *__restrict__ out) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (c >= 12 * n) return;
     const int64_t q = c / 12;
@@ -155,7 +156,8 @@ __global__ void k_edge_write(Grid g, const tms_leaf *__restrict__ leaves,
     int axis, off[3], v0, v1;
     edge_corners((int)(c % 12), axis, off, v0, v1);
     if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) return;
-    const int64_t b = edge_bit(el, L, axis, off);
+    const Grid &g = gt[L.conf];
+    const int64_t b = edge_bit(et[L.conf], L, axis, off);
     const int64_t w = b >> 6;
     const int64_t r = (int64_t)woff[w] + __popcll(bm[w] & ((1ull << (b & 63)) - 1ull));
     const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
@@ -177,20 +179,19 @@ __global__ void k_edge_write(Grid g, const tms_leaf *__restrict__ leaves,
 
 }  // namespace
 
-hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, int K, const EdgeLat &el,
+hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
                             unsigned long long *bm, hipStream_t s) {
-    (void)K;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, el, bm);
+    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, et, bm);
     return hipGetLastError();
 }
 
-hipError_t launch_edge_write(const Grid &g, const tms_leaf *leaves, const double *cphi, int64_t n,
-                             const EdgeLat &el, const uint64_t *bm, const int32_t *woff,
+hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
+                             const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
                              tms_vertex *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_write, dim3(nblk(12 * n)), dim3(kBS), 0, s, g, leaves, cphi, n, el, bm,
-                       woff, out);
+    hipLaunchKernelGGL(k_edge_write, dim3(nblk(12 * n)), dim3(kBS), 0, s, gt, leaves, cphi, n, et,
+                       bm, woff, out);
     return hipGetLastError();
 }
 
@@ -209,12 +210,12 @@ hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t
     return hipGetLastError();
 }
 
-hipError_t launch_edge_emit(const Grid &g, const tms_leaf *leaves, const double *corner_phi,
+hipError_t launch_edge_emit(const Grid *gt, const tms_leaf *leaves, const double *corner_phi,
                             int64_t ncand, const int32_t *flags, const int32_t *off,
                             tms_vertex *out, hipStream_t s) {
     if (ncand <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_emit, dim3(nblk(ncand)), dim3(kBS), 0, s, g, leaves, corner_phi, ncand,
-                       flags, off, out);
+    hipLaunchKernelGGL(k_edge_emit, dim3(nblk(ncand)), dim3(kBS), 0, s, gt, leaves, corner_phi,
+                       ncand, flags, off, out);
     return hipGetLastError();
 }
 

@@ -25,13 +25,19 @@ __global__ void k_roots_flags(const int32_t *__restrict__ rs, int64_t nroots, in
     if (r < nroots) f[r] = (rs[r + 1] > rs[r]) ? 1 : 0;
 }
 
-__global__ void k_roots_emit(Grid g, const int32_t *__restrict__ f, const int32_t *__restrict__ off,
-                             int64_t nroots, int4 *__restrict__ q) {
+// queue entry (ix, iy, iz, conformation) of every root with atoms nearby;
+// roots of the batch in conformation order, each in raster order (x fastest)
+__global__ void k_roots_emit(const Grid *__restrict__ gt, int nconf, const int32_t *__restrict__ f,
+                             const int32_t *__restrict__ off, int64_t nroots,
+                             int4 *__restrict__ q) {
     int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (r >= nroots || !f[r]) return;
-    int rx = (int)(r % g.nr[0]), ry = (int)((r / g.nr[0]) % g.nr[1]),
-        rz = (int)(r / ((int64_t)g.nr[0] * g.nr[1]));
-    q[off[r]] = make_int4(rx, ry, rz, 0);
+    const int b = conf_of_root(gt, nconf, r);
+    const Grid &g = gt[b];
+    const int64_t rl = r - g.root_base;
+    int rx = (int)(rl % g.nr[0]), ry = (int)((rl / g.nr[0]) % g.nr[1]),
+        rz = (int)(rl / ((int64_t)g.nr[0] * g.nr[1]));
+    q[off[r]] = make_int4(rx, ry, rz, b);
 }
 
 // wavefront sum of a 64-bit counter, one atomic per wavefront, striped over
@@ -140,7 +146,7 @@ __device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, co
 // ---------------------------------------------------------------------------
 template <bool FAST, int QH, bool EPI>
 __global__ __launch_bounds__(kBS) void k_estimate_thread(
-    Grid g, int level, GLRule<double> R, const int4 *__restrict__ q, int64_t n,
+    const Grid *__restrict__ gt, int level, GLRule<double> R, const int4 *__restrict__ q, int64_t n,
     const int32_t *__restrict__ subset, const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
@@ -150,19 +156,21 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
     unsigned long long np = 0;
     const bool valid = t < n;
     const int64_t qi = valid ? (subset ? subset[t] : t) : 0;
+    const int4 c = valid ? q[qi] : make_int4(0, 0, 0, 0);
+    const Grid &g = gt[c.w];
     double A[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) A[e] = 0.0;
     double EA = 0.0;
     if (valid) {
-        const int4 c = q[qi];
         const double h = ldexp(g.h0, -level);
         const double lo[3] = {g.o[0] + c.x * h, g.o[1] + c.y * h, g.o[2] + c.z * h};
         const double hi[3] = {lo[0] + h, lo[1] + h, lo[2] + h};
         const double mid[3] = {lo[0] + 0.5 * h, lo[1] + 0.5 * h, lo[2] + 0.5 * h};
         const double s = 0.5 * h;
-        const int64_t root =
+        const int64_t root = g.root_base +
             ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
+        const double rc2 = g.rc2;
         const int b = root_start[root], e_ = root_start[root + 1];
         for (int p = b; p < e_; ++p) {
             const int i = root_atoms[p];
@@ -170,7 +178,7 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
             const double dx = fmax(fmax(lo[0] - x, x - hi[0]), 0.0);
             const double dy = fmax(fmax(lo[1] - y, y - hi[1]), 0.0);
             const double dz = fmax(fmax(lo[2] - z, z - hi[2]), 0.0);
-            if (dx * dx + dy * dy + dz * dz > g.rc2) continue;
+            if (dx * dx + dy * dy + dz * dz > rc2) continue;
             ++np;
             double px[4], py[4], pz[4], ex, ey, ez;
             project<FAST, QH>(R, g.D, s, mid[0] - x, px, ex);
@@ -221,7 +229,7 @@ constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
 
 template <bool FAST, int QH, int CH>
 __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
-    Grid g, int level, GLRule<double> R, const int4 *__restrict__ q,
+    const Grid *__restrict__ gt, int level, GLRule<double> R, const int4 *__restrict__ q,
     const int32_t *__restrict__ subset, const int2 *__restrict__ chunks,
     const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
@@ -238,10 +246,12 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const int64_t qi = subset ? subset[pos] : pos;
     const int4 c = q[qi];
     const int4 c0 = q[subset ? subset[ch.x] : ch.x];
+    const Grid &g = gt[c0.w];  // one root, hence one conformation, per chunk
+    const double rc2 = g.rc2, D = g.D;
     const double h = ldexp(g.h0, -level);
     const double s = 0.5 * h;
     const int rxyz[3] = {c0.x >> level, c0.y >> level, c0.z >> level};
-    const int64_t root = ((int64_t)rxyz[2] * g.nr[1] + rxyz[1]) * g.nr[0] + rxyz[0];
+    const int64_t root = g.root_base + ((int64_t)rxyz[2] * g.nr[1] + rxyz[1]) * g.nr[0] + rxyz[0];
     // local interval indices of this lane's cube, and the chunk's range
     const int li[3] = {c.x - (rxyz[0] << level), c.y - (rxyz[1] << level),
                        c.z - (rxyz[2] << level)};
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
                 const double d = fmax(fmax(blo[a] - x[a], x[a] - bhi[a]), 0.0);
                 d2 += d * d;
             }
-            s_use[lane] = d2 <= g.rc2;
+            s_use[lane] = d2 <= rc2;
             s_w[lane] = aw[i];
         }
         __syncthreads();
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
             double *t = tab[a_idx][axis][r];
             t[5] = d * d;
             double pr[4], err;
-            project<FAST, QH>(R, g.D, s, (lo + s) - xa, pr, err);
+            project<FAST, QH>(R, D, s, (lo + s) - xa, pr, err);
             t[0] = pr[0];
             t[1] = pr[1];
             t[2] = pr[2];
@@ -319,7 +329,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
             for (int a = 0; a < na; ++a) {
                 if (!s_use[a]) continue;
                 const double *tx = tab[a][0][lx], *ty = tab[a][1][ly], *tz = tab[a][2][lz];
-                if (tx[5] + ty[5] + tz[5] > g.rc2) continue;
+                if (tx[5] + ty[5] + tz[5] > rc2) continue;
                 ++np;
                 const double px[4] = {tx[0], tx[1], tx[2], tx[3]};
                 const double py[4] = {ty[0], ty[1], ty[2], ty[3]};
@@ -383,11 +393,13 @@ __global__ __launch_bounds__(kBS) void k_bound(Grid g, int level, int fast, EstO
 }
 
 // chunking of a level queue into runs of one root, at most 64 entries each
-__device__ __forceinline__ int64_t root_of(const Grid &g, int level, int4 c) {
-    return ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
+__device__ __forceinline__ int64_t root_of(const Grid *__restrict__ gt, int level, int4 c) {
+    const Grid &g = gt[c.w];
+    return g.root_base +
+           ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
 }
 
-__global__ void k_run_flags(Grid g, int level, const int4 *__restrict__ q,
+__global__ void k_run_flags(const Grid *__restrict__ gt, int level, const int4 *__restrict__ q,
                             const int32_t *__restrict__ subset, int64_t n,
                             int32_t *__restrict__ f) {
     const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
@@ -397,7 +409,7 @@ __global__ void k_run_flags(Grid g, int level, const int4 *__restrict__ q,
         return;
     }
     const int4 a = q[subset ? subset[i] : i], b = q[subset ? subset[i - 1] : i - 1];
-    f[i] = (root_of(g, level, a) != root_of(g, level, b) || a.w != b.w) ? 1 : 0;
+    f[i] = (root_of(gt, level, a) != root_of(gt, level, b)) ? 1 : 0;
 }
 
 __global__ void k_run_starts(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
@@ -471,6 +483,27 @@ __global__ void k_level_emit(const int4 *__restrict__ q, const uint8_t *__restri
     }
 }
 
+// A batch's leaves come out level by level, conformations in order inside a
+// level.  Segment (level, conformation) heads, then a move that regroups the
+// leaves conformation by conformation (order inside a segment kept).
+__global__ void k_leaf_seg_heads(const tms_leaf *__restrict__ lv, int64_t n, int nconf,
+                                 int64_t *__restrict__ src) {
+    const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i >= n) return;
+    const int seg = lv[i].level * nconf + lv[i].conf;
+    if (i == 0 || seg != lv[i - 1].level * nconf + lv[i - 1].conf) src[seg] = i;
+}
+
+__global__ void k_leaf_seg_move(const tms_leaf *__restrict__ lv, int64_t n, int nconf,
+                                const int64_t *__restrict__ src, const int64_t *__restrict__ dst,
+                                tms_leaf *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i >= n) return;
+    const tms_leaf L = lv[i];
+    const int seg = L.level * nconf + L.conf;
+    out[dst[seg] + (i - src[seg])] = L;
+}
+
 // decision histogram in two passes (block partials, then one block), with
 // no atomics on shared addresses
 constexpr int kHistoBlocks = 1024;
@@ -527,7 +560,7 @@ __global__ void k_fast_exp_debug(const double *__restrict__ x, int64_t n, double
 }
 
 template <bool FAST, int QH>
-hipError_t estimate_thread_t(const Grid &g, int level, const int4 *q, int64_t n,
+hipError_t estimate_thread_t(const Grid *g, int level, const int4 *q, int64_t n,
                              const int32_t *subset, const int32_t *rs, const int32_t *ra,
                              const double *ax, const double *ay, const double *az, const double *aw,
                              double *A, double *E, const EstOut *o, unsigned long long *pairs,
@@ -545,7 +578,7 @@ hipError_t estimate_thread_t(const Grid &g, int level, const int4 *q, int64_t n,
 constexpr int kCH = 16;
 
 template <bool FAST, int QH>
-hipError_t estimate_tiled_t(const Grid &g, int level, const int4 *q, const int32_t *subset,
+hipError_t estimate_tiled_t(const Grid *g, int level, const int4 *q, const int32_t *subset,
                             const int2 *chunks, int64_t nchunks, const int32_t *rs,
                             const int32_t *ra, const double *ax, const double *ay, const double *az,
                             const double *aw, const EstOut &o, unsigned long long *pairs,
@@ -566,7 +599,7 @@ hipError_t estimate_tiled_t(const Grid &g, int level, const int4 *q, const int32
     }
 
 template <bool FAST>
-hipError_t thread_dispatch(int qh, const Grid &g, int level, const int4 *q, int64_t n,
+hipError_t thread_dispatch(int qh, const Grid *g, int level, const int4 *q, int64_t n,
                            const int32_t *subset, const int32_t *rs, const int32_t *ra,
                            const double *ax, const double *ay, const double *az, const double *aw,
                            double *A, double *E, const EstOut *o, unsigned long long *pairs,
@@ -576,7 +609,7 @@ hipError_t thread_dispatch(int qh, const Grid &g, int level, const int4 *q, int6
 }
 
 template <bool FAST>
-hipError_t tiled_dispatch(int qh, const Grid &g, int level, const int4 *q, const int32_t *subset,
+hipError_t tiled_dispatch(int qh, const Grid *g, int level, const int4 *q, const int32_t *subset,
                           const int2 *chunks, int64_t nchunks, const int32_t *rs, const int32_t *ra,
                           const double *ax, const double *ay, const double *az, const double *aw,
                           const EstOut &o, unsigned long long *pairs, hipStream_t s) {
@@ -662,9 +695,11 @@ hipError_t launch_roots_flags(const int32_t *root_start, int64_t nroots, int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_roots_emit(const Grid &g, const int32_t *flags, const int32_t *off, int64_t nroots,
-                             int4 *q, hipStream_t s) {
-    hipLaunchKernelGGL(k_roots_emit, dim3(nblk(nroots)), dim3(kBS), 0, s, g, flags, off, nroots, q);
+hipError_t launch_roots_emit(const Grid *gt, int nconf, const int32_t *flags, const int32_t *off,
+                             int64_t nroots, int4 *q, hipStream_t s) {
+    if (nroots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_roots_emit, dim3(nblk(nroots)), dim3(kBS), 0, s, gt, nconf, flags, off,
+                       nroots, q);
     return hipGetLastError();
 }
 
@@ -672,7 +707,8 @@ static int qh_for(const Grid &g, int level) {
     return gl_half_nodes(0.5 * ldexp(g.h0, -level) * sqrt(g.D), false);
 }
 
-hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+hipError_t launch_estimate(const Grid &g, const Grid *gt, int level, int precision, const int4 *q,
+                           int64_t n,
                            const int32_t *subset, const int32_t *root_start,
                            const int32_t *root_atoms, const double *ax, const double *ay,
                            const double *az, const double *aw, double *A, double *S,
@@ -681,13 +717,14 @@ hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *
     const int qh = qh_for(g, level);
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
     if (precision == TMS_PREC_FP32_GUARD)
-        return thread_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
-                                     aw, A, S, nullptr, pc, s);
-    return thread_dispatch<false>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az, aw,
-                                  A, S, nullptr, pc, s);
+        return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,
+                                     az, aw, A, S, nullptr, pc, s);
+    return thread_dispatch<false>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay, az,
+                                  aw, A, S, nullptr, pc, s);
 }
 
-hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int precision,
+                                  const int4 *q, int64_t n,
                                   const int32_t *subset, const int2 *chunks, int64_t nchunks,
                                   const int32_t *root_start, const int32_t *root_atoms,
                                   const double *ax, const double *ay, const double *az,
@@ -702,16 +739,16 @@ hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
-            return tiled_dispatch<true>(qh, g, level, q, subset, chunks, nchunks, root_start,
+            return tiled_dispatch<true>(qh, gt, level, q, subset, chunks, nchunks, root_start,
                                         root_atoms, ax, ay, az, aw, o, pc, s);
-        return tiled_dispatch<false>(qh, g, level, q, subset, chunks, nchunks, root_start,
+        return tiled_dispatch<false>(qh, gt, level, q, subset, chunks, nchunks, root_start,
                                      root_atoms, ax, ay, az, aw, o, pc, s);
     }
     if (fast)
-        return thread_dispatch<true>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az,
-                                     aw, nullptr, nullptr, &o, pc, s);
-    return thread_dispatch<false>(qh, g, level, q, n, subset, root_start, root_atoms, ax, ay, az, aw,
-                                  nullptr, nullptr, &o, pc, s);
+        return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,
+                                     az, aw, nullptr, nullptr, &o, pc, s);
+    return thread_dispatch<false>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay, az,
+                                  aw, nullptr, nullptr, &o, pc, s);
 }
 
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
@@ -724,10 +761,10 @@ hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, 
     return hipGetLastError();
 }
 
-hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, const int32_t *subset,
+hipError_t launch_run_flags(const Grid *gt, int level, const int4 *q, const int32_t *subset,
                             int64_t n, int32_t *f, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, subset, n, f);
+    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, gt, level, q, subset, n, f);
     return hipGetLastError();
 }
 
@@ -794,6 +831,21 @@ hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long 
 hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fast_exp_debug, dim3(nblk(n)), dim3(kBS), 0, s, x, n, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_seg_heads(const tms_leaf *leaves, int64_t n, int nconf, int64_t *src,
+                                 hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_leaf_seg_heads, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, nconf, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_seg_move(const tms_leaf *leaves, int64_t n, int nconf, const int64_t *src,
+                                const int64_t *dst, tms_leaf *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_leaf_seg_move, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, nconf, src, dst,
+                       out);
     return hipGetLastError();
 }
 

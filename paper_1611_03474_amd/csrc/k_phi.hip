@@ -20,7 +20,9 @@ constexpr uint64_t kEmpty = ~0ull;
 // certain (|phi - c| <= 2 kFastExpErr phi) or when |phi - c| <= band_rel * c;
 // the caller recomputes those points with exact exponentials.
 template <bool FAST>
-__global__ __launch_bounds__(kBS) void k_phi_points(Grid g, const double *__restrict__ pts,
+__global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
+                                                    const int32_t *__restrict__ pconf,
+                                                    const double *__restrict__ pts,
                                                     int64_t m, const int32_t *__restrict__ cs,
                                                     const double *__restrict__ ax,
                                                     const double *__restrict__ ay,
@@ -31,6 +33,7 @@ __global__ __launch_bounds__(kBS) void k_phi_points(Grid g, const double *__rest
                                                     uint8_t *__restrict__ guard) {
     int64_t k = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (k >= m) return;
+    const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
     phi_at<FAST>(g, p, cs, ax, ay, az, aw, f, gr);
@@ -46,7 +49,9 @@ __global__ __launch_bounds__(kBS) void k_phi_points(Grid g, const double *__rest
     }
 }
 
-__global__ __launch_bounds__(kBS) void k_phi_subset(Grid g, const double *__restrict__ pts,
+__global__ __launch_bounds__(kBS) void k_phi_subset(const Grid *__restrict__ gt,
+                                                    const int32_t *__restrict__ pconf,
+                                                    const double *__restrict__ pts,
                                                     const int32_t *__restrict__ list, int64_t m,
                                                     const int32_t *__restrict__ cs,
                                                     const double *__restrict__ ax,
@@ -58,6 +63,7 @@ __global__ __launch_bounds__(kBS) void k_phi_subset(Grid g, const double *__rest
     int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= m) return;
     const int64_t k = list[t];
+    const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
     phi_at<false>(g, p, cs, ax, ay, az, aw, f, gr);
@@ -119,18 +125,21 @@ __global__ void k_owner_flags(const uint32_t *__restrict__ slot, const uint32_t 
     f[c] = (s != 0xFFFFFFFFu && hown[s] == (uint32_t)c) ? 1 : 0;
 }
 
-__global__ void k_corner_unique(const tms_leaf *__restrict__ leaves, int64_t ncand, int K, Grid g,
-                                const int32_t *__restrict__ f, const int32_t *__restrict__ off,
-                                const uint32_t *__restrict__ slot, double *__restrict__ upts,
+__global__ void k_corner_unique(const tms_leaf *__restrict__ leaves, int64_t ncand, int K,
+                                const Grid *__restrict__ gt, const int32_t *__restrict__ f,
+                                const int32_t *__restrict__ off, const uint32_t *__restrict__ slot,
+                                double *__restrict__ upts, int32_t *__restrict__ uconf,
                                 uint32_t *__restrict__ slot2u) {
     int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (c >= ncand || !f[c]) return;
     const tms_leaf L = leaves[c >> 3];
+    const Grid &g = gt[L.conf];
     const int v = (int)(c & 7), sh = K - L.level;
     const int64_t u = off[c];
     upts[3 * u] = g.o[0] + (double)((L.ix + (v & 1)) << sh) * g.hmin;
     upts[3 * u + 1] = g.o[1] + (double)((L.iy + ((v >> 1) & 1)) << sh) * g.hmin;
     upts[3 * u + 2] = g.o[2] + (double)((L.iz + ((v >> 2) & 1)) << sh) * g.hmin;
+    uconf[u] = L.conf;
     slot2u[slot[c]] = (uint32_t)u;
 }
 
@@ -279,11 +288,12 @@ __global__ void k_popc(const uint64_t *__restrict__ bm, int64_t nw, int32_t *__r
 // one thread per leaf: its 8 corner bits, merged per 64-bit word (a
 // finest-level leaf usually has all 8 in one 4x4x4 block), one atomic OR per
 // distinct word
-__global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, int K, Lat lat,
-                              unsigned long long *__restrict__ bm) {
+__global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, int K,
+                              const Grid *__restrict__ gt, unsigned long long *__restrict__ bm) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (q >= n) return;
     const tms_leaf L = leaves[q];
+    const Lat lat = gt[L.conf].clat;
     int64_t w[8];
     unsigned long long m[8];
 #pragma unroll
@@ -310,27 +320,32 @@ __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, in
 
 // every candidate writes its corner's coordinates at the corner's rank (all
 // writers of one corner write the same bits)
-__global__ void k_corner_write(const tms_leaf *__restrict__ leaves, int64_t n, int K, Lat lat,
-                               const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
-                               Grid g, double *__restrict__ upts) {
+__global__ void k_corner_write(const tms_leaf *__restrict__ leaves, int64_t n, int K,
+                               const Grid *__restrict__ gt, const uint64_t *__restrict__ bm,
+                               const int32_t *__restrict__ woff, double *__restrict__ upts,
+                               int32_t *__restrict__ uconf) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (c >= 8 * n) return;
     const tms_leaf L = leaves[c >> 3];
+    const Grid &g = gt[L.conf];
     int64_t X, Y, Z;
     leaf_corner(L, (int)(c & 7), K, X, Y, Z);
-    const int64_t u = bit_rank(bm, woff, lat_bit(lat, X, Y, Z));
+    const int64_t u = bit_rank(bm, woff, lat_bit(g.clat, X, Y, Z));
     upts[3 * u] = g.o[0] + (double)X * g.hmin;
     upts[3 * u + 1] = g.o[1] + (double)Y * g.hmin;
     upts[3 * u + 2] = g.o[2] + (double)Z * g.hmin;
+    uconf[u] = L.conf;
 }
 
-__global__ void k_corner_gather_bm(const tms_leaf *__restrict__ lin, int64_t n, int K, Lat lat,
-                                   const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
-                                   const double *__restrict__ uphi, double c,
-                                   tms_leaf *__restrict__ lout, double *__restrict__ cphi) {
+__global__ void k_corner_gather_bm(const tms_leaf *__restrict__ lin, int64_t n, int K,
+                                   const Grid *__restrict__ gt, const uint64_t *__restrict__ bm,
+                                   const int32_t *__restrict__ woff, const double *__restrict__ uphi,
+                                   double c, tms_leaf *__restrict__ lout,
+                                   double *__restrict__ cphi) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (q >= n) return;
     tms_leaf L = lin[q];
+    const Lat lat = gt[L.conf].clat;
     double f[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
@@ -354,52 +369,52 @@ hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
+hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
                               unsigned long long *bm, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, K, lat, bm);
+    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, K, gt, bm);
     return hipGetLastError();
 }
 
-hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
-                               const uint64_t *bm, const int32_t *woff, const Grid &g, double *upts,
-                               hipStream_t s) {
+hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
+                               const uint64_t *bm, const int32_t *woff, double *upts,
+                               int32_t *uconf, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_write, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, lat, bm, woff,
-                       g, upts);
+    hipLaunchKernelGGL(k_corner_write, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, gt, bm,
+                       woff, upts, uconf);
     return hipGetLastError();
 }
 
-hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Lat &lat,
+hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Grid *gt,
                                    const uint64_t *bm, const int32_t *woff, const double *uphi,
                                    double c, tms_leaf *lout, double *cphi, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_gather_bm, dim3(nblk(n)), dim3(kBS), 0, s, lin, n, K, lat, bm, woff,
+    hipLaunchKernelGGL(k_corner_gather_bm, dim3(nblk(n)), dim3(kBS), 0, s, lin, n, K, gt, bm, woff,
                        uphi, c, lout, cphi);
     return hipGetLastError();
 }
 
-hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
-                             const int32_t *cs, const double *ax, const double *ay, const double *az,
-                             const double *aw, double band_rel, double *phi, double *grad,
-                             uint8_t *guard, hipStream_t s) {
+hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision, const double *pts,
+                             int64_t m, const int32_t *cs, const double *ax, const double *ay,
+                             const double *az, const double *aw, double band_rel, double *phi,
+                             double *grad, uint8_t *guard, hipStream_t s) {
     if (m <= 0) return hipSuccess;
     if (precision == TMS_PREC_FP32_GUARD)
-        hipLaunchKernelGGL(k_phi_points<true>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
-                           ay, az, aw, band_rel, phi, grad, guard);
+        hipLaunchKernelGGL(k_phi_points<true>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
+                           cs, ax, ay, az, aw, band_rel, phi, grad, guard);
     else
-        hipLaunchKernelGGL(k_phi_points<false>, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, m, cs, ax,
-                           ay, az, aw, 0.0, phi, grad, nullptr);
+        hipLaunchKernelGGL(k_phi_points<false>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
+                           cs, ax, ay, az, aw, 0.0, phi, grad, nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_phi_points_subset(const Grid &g, const double *pts, const int32_t *list, int64_t m,
-                                    const int32_t *cs, const double *ax, const double *ay,
-                                    const double *az, const double *aw, double *phi, double *grad,
-                                    hipStream_t s) {
+hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
+                                    const int32_t *list, int64_t m, const int32_t *cs,
+                                    const double *ax, const double *ay, const double *az,
+                                    const double *aw, double *phi, double *grad, hipStream_t s) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, g, pts, list, m, cs, ax, ay, az,
-                       aw, phi, grad);
+    hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, list, m, cs, ax,
+                       ay, az, aw, phi, grad);
     return hipGetLastError();
 }
 
@@ -418,12 +433,12 @@ hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid &g,
+hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid *gt,
                                 const int32_t *flags, const int32_t *off, const uint32_t *slot,
-                                double *upts, uint32_t *slot2u, hipStream_t s) {
+                                double *upts, int32_t *uconf, uint32_t *slot2u, hipStream_t s) {
     if (ncand <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_unique, dim3(nblk(ncand)), dim3(kBS), 0, s, leaves, ncand, K, g,
-                       flags, off, slot, upts, slot2u);
+    hipLaunchKernelGGL(k_corner_unique, dim3(nblk(ncand)), dim3(kBS), 0, s, leaves, ncand, K, gt,
+                       flags, off, slot, upts, uconf, slot2u);
     return hipGetLastError();
 }
 

@@ -160,4 +160,19 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+__global__ void k_gather_i32(const int32_t *__restrict__ src, const int64_t *__restrict__ idx,
+                             int n, int64_t *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = src[idx[i]];
+}
+}  // namespace
+
+hipError_t launch_gather_i32(const int32_t *src, const int64_t *idx, int n, int64_t *out,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_i32, dim3((n + 255) / 256), dim3(256), 0, s, src, idx, n, out);
+    return hipGetLastError();
+}
+
 }  // namespace tms

@@ -94,6 +94,8 @@ void timing_flush(tms_ctx *ctx) {
 }  // namespace tms
 
 void tms_cells::release() {
+    gtab.release();
+    aoff.release();
     ax.release();
     ay.release();
     az.release();
@@ -229,6 +231,11 @@ int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int
 // exact, that is at most eps (1 + 1/b) <= 4.4e-6 for b = 0.035.
 constexpr double kCornerBand = 0.035;
 
+// Queue slices per level (estimate + bound); their hard-list lengths live in
+// counter slots [kSliceCtr, kSliceCtr + kMaxSlices), the guard pass's after.
+constexpr int64_t kMaxSlices = 256;
+constexpr int64_t kSliceCtr = 8192;
+
 std::atomic<uint64_t> g_cells_ids{0};
 
 // Largest dense bitmap (bits) used for corner and edge de-duplication; larger
@@ -237,10 +244,11 @@ constexpr double kMaxBitmapBits = 68719476736.0;
 
 // phi at m points of `pts` (with the FAST-exponential guard); returns the
 // number of points recomputed with exact exponentials
-int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
-                       double *phi, double *grad, int64_t *n_guard, double band_rel) {
+int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts,
+                       const int32_t *pconf, int64_t m, double *phi, double *grad,
+                       int64_t *n_guard, double band_rel) {
     const int prec = cells->p.precision;
-    const Grid &g = cells->g;
+    const Grid *gt = cells->gtab.as<Grid>();
     *n_guard = 0;
     if (m <= 0) return TMS_OK;
     uint8_t *gbuf = nullptr;
@@ -250,7 +258,7 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, 
     }
     {
         TimedScope ts_(ctx, TMS_T_PHI);
-        HIPCK(launch_phi_points(g, prec, pts, m, cells->cell_start.as<int32_t>(),
+        HIPCK(launch_phi_points(gt, pconf, prec, pts, m, cells->cell_start.as<int32_t>(),
                                 cells->ax.as<double>(), cells->ay.as<double>(),
                                 cells->az.as<double>(), cells->aw.as<double>(), band_rel, phi,
                                 grad, gbuf, ctx->stream));
@@ -267,7 +275,7 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, 
             HIPCK(launch_list_emit(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), m,
                                    ctx->idx.as<int32_t>(), ctx->stream));
             TimedScope ts_(ctx, TMS_T_GUARD);
-            HIPCK(launch_phi_points_subset(g, pts, ctx->idx.as<int32_t>(), ng,
+            HIPCK(launch_phi_points_subset(gt, pconf, pts, ctx->idx.as<int32_t>(), ng,
                                            cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
                                            cells->ay.as<double>(), cells->az.as<double>(),
                                            cells->aw.as<double>(), phi, grad, ctx->stream));
@@ -282,6 +290,7 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts, 
 int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
                      tms_leaf *leaves_out, double *cphi, int64_t *n_corners, int64_t *n_guard) {
     const Grid &g = cells->g;
+    const Grid *gt = cells->gtab.as<Grid>();
     hipStream_t s = ctx->stream;
     *n_corners = 0;
     *n_guard = 0;
@@ -290,17 +299,12 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     ctx->corner_dense = n <= 0;  // an empty pass has a (trivially) dense corner set
     if (n <= 0) return TMS_OK;
     const int64_t ncand = 8 * n;
-    if (ncand >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves (%lld)", (long long)n);
     {
-        // dense bitmap over the finest lattice (4x4x4 point blocks per word)
-        // when it fits the budget
-        Lat lat{};
-        double bits = 64.0;
-        for (int a = 0; a < 3; ++a) {
-            lat.n[a] = ((((int64_t)g.nr[a] << g.K) + 1) + 3) / 4;
-            bits *= (double)lat.n[a];
-        }
-        const int64_t nwords = (int64_t)(bits / 64.0);
+        // dense bitmap over the finest lattice of every conformation (4x4x4
+        // point blocks per word, one block of words per conformation) when
+        // it fits the budget
+        const int64_t nwords = cells->corner_words;
+        const double bits = 64.0 * (double)nwords;
         if (bits <= kMaxBitmapBits && nwords < (int64_t)0x7FFFFFFF) {
             HIPCK(ctx->bmap.ensure(sizeof(uint64_t) * (size_t)nwords));
             HIPCK(ctx->bmcnt.ensure(sizeof(int32_t) * (size_t)nwords));
@@ -308,8 +312,8 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
             {
                 TimedScope ts_(ctx, TMS_T_CORNER);
                 HIPCK(launch_fill_u64(ctx->bmap.as<uint64_t>(), 0ull, nwords, s));
-                HIPCK(launch_corner_mark(leaves, n, g.K, lat,
-                                         ctx->bmap.as<unsigned long long>(), s));
+                HIPCK(launch_corner_mark(leaves, n, g.K, gt, ctx->bmap.as<unsigned long long>(),
+                                         s));
                 HIPCK(launch_popc(ctx->bmap.as<uint64_t>(), nwords, ctx->bmcnt.as<int32_t>(), s));
             }
             int64_t nu = 0;
@@ -318,28 +322,31 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
             if (rc) return rc;
             HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(nu, 1)));
             HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)std::max<int64_t>(nu, 1)));
+            HIPCK(ctx->uconf.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1)));
             {
                 TimedScope ts_(ctx, TMS_T_CORNER);
-                HIPCK(launch_corner_write(leaves, n, g.K, lat, ctx->bmap.as<uint64_t>(),
-                                          ctx->bmoff.as<int32_t>(), g, ctx->uniq.as<double>(), s));
+                HIPCK(launch_corner_write(leaves, n, g.K, gt, ctx->bmap.as<uint64_t>(),
+                                          ctx->bmoff.as<int32_t>(), ctx->uniq.as<double>(),
+                                          ctx->uconf.as<int32_t>(), s));
             }
-            rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nu, ctx->uphi.as<double>(),
-                                nullptr, n_guard, kCornerBand);
+            rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), nu,
+                                ctx->uphi.as<double>(), nullptr, n_guard, kCornerBand);
             if (rc) return rc;
             {
                 TimedScope ts_(ctx, TMS_T_CORNER);
-                HIPCK(launch_corner_gather_bm(leaves, n, g.K, lat, ctx->bmap.as<uint64_t>(),
+                HIPCK(launch_corner_gather_bm(leaves, n, g.K, gt, ctx->bmap.as<uint64_t>(),
                                               ctx->bmoff.as<int32_t>(), ctx->uphi.as<double>(), g.c,
                                               leaves_out, cphi, s));
             }
             *n_corners = nu;
             ctx->n_corners = nu;
             ctx->corner_dense = true;
-            ctx->corner_lat = lat;
             return TMS_OK;
         }
     }
     // otherwise: open-addressing hash on the corner keys
+    if (ncand >= (int64_t)0x7FFFFFFF)
+        return fail(ctx, TMS_E_INVALID, "too many leaves for hashed corners (%lld)", (long long)n);
     const int64_t hcap = next_pow2(2 * ncand);
     HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
     HIPCK(ctx->hown.ensure(sizeof(uint32_t) * (size_t)hcap));
@@ -358,20 +365,20 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     int64_t nu = 0;
     int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), ncand, &nu);
     if (rc) return rc;
-    HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)nu));
-    HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)nu));
-    // slot -> unique index map reuses the owner array (same size, u32)
-    uint32_t *slot2u = ctx->hown.as<uint32_t>();
+    HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(nu, 1)));
+    HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)std::max<int64_t>(nu, 1)));
+    HIPCK(ctx->uconf.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1)));
+    // slot -> unique index map
     HIPCK(ctx->lc.ensure(sizeof(uint32_t) * (size_t)hcap));
-    slot2u = ctx->lc.as<uint32_t>();
+    uint32_t *slot2u = ctx->lc.as<uint32_t>();
     {
         TimedScope ts_(ctx, TMS_T_CORNER);
-        HIPCK(launch_corner_unique(leaves, ncand, g.K, g, ctx->flags.as<int32_t>(),
+        HIPCK(launch_corner_unique(leaves, ncand, g.K, gt, ctx->flags.as<int32_t>(),
                                    ctx->scan_a.as<int32_t>(), ctx->slot.as<uint32_t>(),
-                                   ctx->uniq.as<double>(), slot2u, s));
+                                   ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), slot2u, s));
     }
-    rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nu, ctx->uphi.as<double>(), nullptr,
-                        n_guard, kCornerBand);
+    rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), nu,
+                        ctx->uphi.as<double>(), nullptr, n_guard, kCornerBand);
     if (rc) return rc;
     {
         TimedScope ts_(ctx, TMS_T_CORNER);
@@ -386,13 +393,13 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
 // Chunks of <= 64 consecutive entries of one root over q (or over the
 // sorted subset list) for the tiled estimate kernel; uses flags/scan_a/
 // scan_b/runs as scratch.
-int32_t build_chunks(tms_ctx *ctx, const Grid &g, int lev, const int4 *q, const int32_t *subset,
+int32_t build_chunks(tms_ctx *ctx, const Grid *gt, int lev, const int4 *q, const int32_t *subset,
                      int64_t n, const int2 **chunks, int64_t *nchunks) {
     hipStream_t s = ctx->stream;
     int64_t nruns = 0;
     {
         TimedScope ts_(ctx, TMS_T_COMPACT);
-        HIPCK(launch_run_flags(g, lev, q, subset, n, ctx->flags.as<int32_t>(), s));
+        HIPCK(launch_run_flags(gt, lev, q, subset, n, ctx->flags.as<int32_t>(), s));
     }
     int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), n, &nruns);
     if (rc) return rc;
@@ -413,6 +420,56 @@ int32_t build_chunks(tms_ctx *ctx, const Grid &g, int lev, const int4 *q, const 
                                     ctx->chunks.as<int2>(), s));
     }
     *chunks = ctx->chunks.as<int2>();
+    return TMS_OK;
+}
+
+// A batch's leaves come out level by level with the conformations in order
+// inside each level; regroup them conformation by conformation, each keeping
+// the order of its own single-conformation pass (level, refinement order).
+int32_t regroup_by_conf(tms_ctx *ctx, const tms_cells *cells, int64_t L) {
+    hipStream_t s = ctx->stream;
+    const int nconf = cells->nconf;
+    const int nseg = (cells->g.K + 1) * nconf;
+    ctx->leaf_off.assign((size_t)nconf + 1, 0);
+    if (L == 0) return TMS_OK;
+    HIPCK(ctx->ctab.ensure(sizeof(int64_t) * 2 * (size_t)nseg));
+    int64_t *src = ctx->ctab.as<int64_t>(), *dst = src + nseg;
+    HIPCK(ctx->lsort.ensure(sizeof(tms_leaf) * (size_t)L));
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(src), ~0ull, nseg, s));
+        HIPCK(launch_leaf_seg_heads(ctx->leaves.as<tms_leaf>(), L, nconf, src, s));
+    }
+    std::vector<int64_t> hs((size_t)nseg), hd((size_t)nseg, 0), cnt((size_t)nseg, 0);
+    HIPCK(d2h(hs.data(), src, (size_t)nseg, s));
+    // segments ascend in the source order; a segment ends where the next
+    // present one starts
+    int64_t prev = -1;
+    for (int seg = 0; seg < nseg; ++seg) {
+        if (hs[(size_t)seg] < 0) continue;
+        if (prev >= 0) cnt[(size_t)prev] = hs[(size_t)seg] - hs[(size_t)prev];
+        prev = seg;
+    }
+    if (prev >= 0) cnt[(size_t)prev] = L - hs[(size_t)prev];
+    int64_t pos = 0;
+    for (int b = 0; b < nconf; ++b) {
+        ctx->leaf_off[(size_t)b] = pos;
+        for (int lev = 0; lev <= cells->g.K; ++lev) {
+            const size_t seg = (size_t)lev * nconf + b;
+            hd[seg] = pos;
+            pos += cnt[seg];
+        }
+    }
+    ctx->leaf_off[(size_t)nconf] = pos;
+    if (pos != L) return fail(ctx, TMS_E_DEVICE, "leaf regrouping lost leaves");
+    HIPCK(hipMemcpyAsync(dst, hd.data(), sizeof(int64_t) * (size_t)nseg, hipMemcpyHostToDevice, s));
+    {
+        TimedScope ts_(ctx, TMS_T_COMPACT);
+        HIPCK(launch_leaf_seg_move(ctx->leaves.as<tms_leaf>(), L, nconf, src, dst,
+                                   ctx->lsort.as<tms_leaf>(), s));
+    }
+    HIPCK(hipStreamSynchronize(s));  // hd goes out of scope
+    std::swap(ctx->leaves, ctx->lsort);
     return TMS_OK;
 }
 
@@ -439,7 +496,7 @@ int32_t tms_create(tms_ctx **out, int32_t device, void *stream) {
     tms_ctx *ctx = new tms_ctx();
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
-    e = ctx->counters.ensure(65536);
+    e = ctx->counters.ensure(1 << 20);
     if (e != hipSuccess) {
         delete ctx;
         return fail(nullptr, TMS_E_OOM, "counter allocation failed");
@@ -526,15 +583,31 @@ int32_t tms_check_atoms_host(const double *xyzr, int64_t n, const tms_params *p,
     return TMS_OK;
 }
 
-int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_params *p,
-                        tms_cells **cells_io) {
-    if (!ctx) return TMS_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+// Largest batch: the conformation id occupies 11 bits of the edge keys.
+constexpr int kMaxConf = 2048;
+
+// Cells of a batch of conformations (one conformation: off = {0, n}).
+int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int64_t> &off,
+                         const tms_params *p, tms_cells **cells_io) {
     if (!cells_io) return fail(ctx, TMS_E_INVALID, "cells is NULL");
     std::string why;
     int K = 0;
     if (!check_params(p, why, &K)) return fail(ctx, TMS_E_INVALID, "%s", why.c_str());
-    if (n < 0 || (n > 0 && !xyzr)) return fail(ctx, TMS_E_INVALID, "n < 0 or xyzr NULL");
+    const int nconf = (int)off.size() - 1;
+    if (nconf < 1 || nconf > kMaxConf)
+        return fail(ctx, TMS_E_INVALID, "batch of %d conformations (1..%d)", nconf, kMaxConf);
+    if (off[0] != 0) return fail(ctx, TMS_E_INVALID, "atom offsets must start at 0");
+    for (int b = 0; b < nconf; ++b)
+        if (off[b + 1] < off[b]) return fail(ctx, TMS_E_INVALID, "atom offsets must not decrease");
+    const int64_t n = off[nconf];
+    if (n > 0 && !xyzr) return fail(ctx, TMS_E_INVALID, "xyzr is NULL");
     if (n >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many atoms");
+    if (p->mode == TMS_MODE_UNIFORM && nconf > 1)
+        return fail(ctx, TMS_E_INVALID, "the uniform grid takes one conformation");
     HIPCK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     TimedScope ts_build(ctx, TMS_T_BUILD);
@@ -556,54 +629,90 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     cells->p = *p;
     cells->n = n;
     cells->id = ++g_cells_ids;
+    cells->nconf = nconf;
+    cells->atom_off = off;
     if (p->mode == TMS_MODE_UNIFORM) K = 0;
 
-    // bounding box, radii, finiteness
-    double st[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // bounding box, radii, finiteness per conformation
+    std::vector<double> st(9 * (size_t)nconf, 0.0);
     if (n > 0) {
-        tms::DevBuf &tb = ctx->ctmp;
-        hipError_t e = tb.ensure(sizeof(double) * (16 + 9 * 1024));
-        if (e != hipSuccess) return bail(hip_fail(ctx, e, "stats buffer"));
-        e = launch_atom_stats(xyzr, n, tb.as<double>(), s);
-        if (e == hipSuccess) e = d2h(st, tb.p, 9, s);
+        hipError_t e = cells->aoff.ensure(sizeof(int64_t) * (size_t)(nconf + 1));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(cells->aoff.p, off.data(), sizeof(int64_t) * (size_t)(nconf + 1),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = ctx->ctmp.ensure(sizeof(double) * 9 * (size_t)nconf);
+        if (e == hipSuccess)
+            e = launch_atom_stats(xyzr, cells->aoff.as<int64_t>(), nconf, ctx->ctmp.as<double>(), s);
+        if (e == hipSuccess) e = d2h(st.data(), ctx->ctmp.p, 9 * (size_t)nconf, s);
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "atom stats"));
-        if (st[8] > 0) return bail(fail(ctx, TMS_E_INVALID, "atom array holds NaN or Inf"));
-        if (!(st[7] > 0)) return bail(fail(ctx, TMS_E_INVALID, "atom radius must be > 0"));
+        for (int b = 0; b < nconf; ++b) {
+            if (st[9 * b + 8] > 0)
+                return bail(fail(ctx, TMS_E_INVALID, "atom array holds NaN or Inf (conformation %d)", b));
+            if (off[b + 1] > off[b] && !(st[9 * b + 7] > 0))
+                return bail(fail(ctx, TMS_E_INVALID, "atom radius must be > 0 (conformation %d)", b));
+        }
     }
-    Grid g{};
-    g.h0 = p->h0;
-    g.hmin = (p->mode == TMS_MODE_UNIFORM) ? p->h0 : p->h_min;
-    g.D = p->D;
-    g.c = p->c;
-    g.tau = p->tau;
-    g.K = K;
-    cells->rmax = n > 0 ? st[6] : 0.0;
-    g.rc2 = cells->rmax * cells->rmax + std::log(1.0 / p->eps_cut) / p->D;
-    for (int a = 0; a < 3; ++a) {
-        double mn = n > 0 ? st[a] : 0.0, mx = n > 0 ? st[3 + a] : 0.0;
-        g.o[a] = p->h0 * std::floor((mn - p->pad) / p->h0);
-        double d = std::ceil((mx + p->pad - g.o[a]) / p->h0);
-        if (d < 1) d = 1;
-        if (d * std::ldexp(1.0, K) > 65535.0)
-            return bail(fail(ctx, TMS_E_INVALID, "finest lattice exceeds 65535 points per axis"));
-        g.nr[a] = (int32_t)d;
+    cells->gh.assign((size_t)nconf, Grid{});
+    int64_t root_base = 0, cell_base = 0, words = 0;
+    cells->rmax = 0.0;
+    for (int b = 0; b < nconf; ++b) {
+        const bool has = off[b + 1] > off[b];
+        const double *sb = st.data() + 9 * b;
+        Grid g{};
+        g.h0 = p->h0;
+        g.hmin = (p->mode == TMS_MODE_UNIFORM) ? p->h0 : p->h_min;
+        g.D = p->D;
+        g.c = p->c;
+        g.tau = p->tau;
+        g.K = K;
+        const double rmax = has ? sb[6] : 0.0;
+        cells->rmax = std::max(cells->rmax, rmax);
+        g.rc2 = rmax * rmax + std::log(1.0 / p->eps_cut) / p->D;
+        for (int a = 0; a < 3; ++a) {
+            double mn = has ? sb[a] : 0.0, mx = has ? sb[3 + a] : 0.0;
+            g.o[a] = p->h0 * std::floor((mn - p->pad) / p->h0);
+            double d = std::ceil((mx + p->pad - g.o[a]) / p->h0);
+            if (d < 1) d = 1;
+            if (d * std::ldexp(1.0, K) > 65535.0)
+                return bail(fail(ctx, TMS_E_INVALID, "finest lattice exceeds 65535 points per axis"));
+            g.nr[a] = (int32_t)d;
+        }
+        // atom cells: the smallest edge h0 * 2^m >= R_c / 4, and a stencil
+        // of +-span cells (span = ceil(R_c / edge)) around a point's cell;
+        // point queries clip each row of the stencil to the R_c sphere
+        const double Rc = std::sqrt(g.rc2);
+        g.cs = p->h0;
+        while (g.cs < 0.25 * Rc) g.cs *= 2.0;
+        while (0.5 * g.cs >= 0.25 * Rc) g.cs *= 0.5;
+        g.span = (int32_t)std::ceil(Rc / g.cs);
+        int64_t nc = 1, nrt = 1;
+        for (int a = 0; a < 3; ++a) {
+            g.nc[a] = (int32_t)std::max(1.0, std::ceil(g.nr[a] * p->h0 / g.cs));
+            nc *= g.nc[a];
+            nrt *= g.nr[a];
+        }
+        g.root_base = root_base;
+        g.cell_base = cell_base;
+        g.atom_base = off[b];
+        // corner bitmap block: 4x4x4 finest-lattice points per word
+        int64_t wb = 1;
+        for (int a = 0; a < 3; ++a) {
+            g.clat.n[a] = ((((int64_t)g.nr[a] << K) + 1) + 3) / 4;
+            wb *= g.clat.n[a];
+        }
+        g.clat.base = words;
+        words += wb;
+        root_base += nrt;
+        cell_base += nc;
+        cells->gh[(size_t)b] = g;
     }
-    // atom cells: the smallest edge h0 * 2^m >= R_c / 4, and a stencil of
-    // +-span cells (span = ceil(R_c / edge)) around a point's cell; point
-    // queries clip each row of the stencil to the R_c sphere
-    const double Rc = std::sqrt(g.rc2);
-    g.cs = p->h0;
-    while (g.cs < 0.25 * Rc) g.cs *= 2.0;
-    while (0.5 * g.cs >= 0.25 * Rc) g.cs *= 0.5;
-    g.span = (int32_t)std::ceil(Rc / g.cs);
-    int64_t ncells = 1;
-    for (int a = 0; a < 3; ++a) {
-        g.nc[a] = (int32_t)std::max(1.0, std::ceil(g.nr[a] * p->h0 / g.cs));
-        ncells *= g.nc[a];
-    }
-    cells->g = g;
-    cells->ncells = ncells;
-    cells->nroots = (int64_t)g.nr[0] * g.nr[1] * g.nr[2];
+    if (cell_base >= (int64_t)0x7FFFFFFF || root_base >= (int64_t)0x7FFFFFFF)
+        return bail(fail(ctx, TMS_E_INVALID, "batch grid too large"));
+    cells->g = cells->gh[0];
+    cells->ncells = cell_base;
+    cells->nroots = root_base;
+    cells->corner_words = words;
+    const int64_t ncells = cell_base;
 
     auto ck = [&](hipError_t e, const char *what) -> int32_t {
         return e == hipSuccess ? TMS_OK : hip_fail(ctx, e, what);
@@ -613,6 +722,10 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
         int32_t rc_ = ck((expr), #expr);                \
         if (rc_) return bail(rc_);                      \
     } while (0)
+    CK(cells->gtab.ensure(sizeof(Grid) * (size_t)nconf));
+    CK(hipMemcpyAsync(cells->gtab.p, cells->gh.data(), sizeof(Grid) * (size_t)nconf,
+                      hipMemcpyHostToDevice, s));
+    const Grid *gt = cells->gtab.as<Grid>();
     const size_t na = (size_t)std::max<int64_t>(n, 1);
     CK(cells->ax.ensure(8 * na));
     CK(cells->ay.ensure(8 * na));
@@ -625,7 +738,7 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     CK(cells->tmp_cnt.ensure(4 * (size_t)(ncells + 1)));
     int32_t *cnt = cells->tmp_cnt.as<int32_t>();
     CK(launch_fill_u32(reinterpret_cast<uint32_t *>(cnt), 0u, ncells + 1, s));
-    CK(launch_bin_atoms(g, xyzr, n, cells->tmp_key.as<int32_t>(), cnt, ncells, s));
+    CK(launch_bin_atoms(gt, nconf, xyzr, n, cells->tmp_key.as<int32_t>(), cnt, s));
     {
         int64_t tot = 0;
         int32_t rc = scan_total(ctx, cnt, cells->cell_start.as<int32_t>(), ncells + 1, &tot);
@@ -633,7 +746,7 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     }
     // scatter positions start from the cell offsets
     CK(hipMemcpyAsync(cnt, cells->cell_start.p, 4 * (size_t)ncells, hipMemcpyDeviceToDevice, s));
-    CK(launch_scatter_atoms(g, xyzr, n, cells->tmp_key.as<int32_t>(), cnt, cells->ax.as<double>(),
+    CK(launch_scatter_atoms(gt, xyzr, n, cells->tmp_key.as<int32_t>(), cnt, cells->ax.as<double>(),
                             cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
                             cells->ar.as<double>(), cells->aidx.as<int32_t>(), s));
     CK(launch_sort_cells(cells->cell_start.as<int32_t>(), ncells, cells->ax.as<double>(),
@@ -646,14 +759,14 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
         CK(ctx->flags.ensure(4 * (size_t)(nr + 1)));
         int32_t *rc_cnt = ctx->flags.as<int32_t>();
         CK(launch_fill_u32(reinterpret_cast<uint32_t *>(rc_cnt), 0u, nr + 1, s));
-        CK(launch_root_count(g, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
+        CK(launch_root_count(gt, nconf, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
                              cells->ay.as<double>(), cells->az.as<double>(), nr, rc_cnt, s));
         int64_t tot = 0;
         int32_t rc = scan_total(ctx, rc_cnt, cells->root_start.as<int32_t>(), nr + 1, &tot);
         if (rc) return bail(rc);
         cells->n_root_entries = tot;
         CK(cells->root_atoms.ensure(4 * (size_t)std::max<int64_t>(tot, 1)));
-        CK(launch_root_fill(g, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
+        CK(launch_root_fill(gt, nconf, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
                             cells->ay.as<double>(), cells->az.as<double>(), nr,
                             cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(), s));
     }
@@ -662,6 +775,26 @@ int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_p
     if (fresh) ctx->cells.push_back(cells);
     *cells_io = cells;
     return TMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t tms_build_cells(tms_ctx *ctx, const double *xyzr, int64_t n, const tms_params *p,
+                        tms_cells **cells_io) {
+    if (!ctx) return TMS_E_INVALID;
+    if (n < 0 || (n > 0 && !xyzr)) return fail(ctx, TMS_E_INVALID, "n < 0 or xyzr NULL");
+    return build_cells_impl(ctx, xyzr, std::vector<int64_t>{0, n}, p, cells_io);
+}
+
+int32_t tms_build_cells_batch(tms_ctx *ctx, const double *xyzr, const int64_t *offsets,
+                              int32_t n_conf, const tms_params *p, tms_cells **cells_io) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!offsets || n_conf < 1 || n_conf > kMaxConf)
+        return fail(ctx, TMS_E_INVALID, "offsets NULL or n_conf outside 1..%d", kMaxConf);
+    return build_cells_impl(ctx, xyzr, std::vector<int64_t>(offsets, offsets + n_conf + 1), p,
+                            cells_io);
 }
 
 int32_t tms_cells_info(const tms_cells *cells, double origin[3], int64_t dims[3], int32_t *K,
@@ -694,9 +827,11 @@ int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, in
     if (!ctx) return TMS_E_INVALID;
     if (!cells || m < 0 || (m > 0 && (!pts || !phi)))
         return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_eval_phi");
+    if (cells->nconf != 1)
+        return fail(ctx, TMS_E_INVALID, "tms_eval_phi takes cells of one conformation");
     HIPCK(hipSetDevice(ctx->device));
     int64_t ng = 0;
-    int32_t rc = phi_with_guard(ctx, cells, pts, m, phi, grad, &ng, 0.0);
+    int32_t rc = phi_with_guard(ctx, cells, pts, nullptr, m, phi, grad, &ng, 0.0);
     if (rc) return rc;
     HIPCK(hipStreamSynchronize(ctx->stream));
     if (n_guard) *n_guard = ng;
@@ -710,12 +845,15 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
     if (!cells || !n_leaves || cap < 0) return fail(ctx, TMS_E_INVALID, "invalid arguments");
     HIPCK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const Grid &g = cells->g;
+    const Grid &g = cells->g;  // shared parameters (every conformation has the same)
+    const Grid *gt = cells->gtab.as<Grid>();
+    const int nconf = cells->nconf;
     const int prec = cells->p.precision;
     tms_stats st;
     memset(&st, 0, sizeof st);
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     int64_t L = 0;
+    ctx->leaf_off.assign(1, 0);
 
     if (cells->p.mode == TMS_MODE_UNIFORM) {
         L = cells->nroots;
@@ -728,18 +866,20 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)m));
         HIPCK(launch_uniform_points(g, ctx->uniq.as<double>(), m, s));
         int64_t ng = 0;
-        int32_t rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), m, ctx->uphi.as<double>(),
+        int32_t rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nullptr, m, ctx->uphi.as<double>(),
                                     nullptr, &ng, kCornerBand);
         if (rc) return rc;
         HIPCK(launch_uniform_gather(g, ctx->uphi.as<double>(), g.c, ctx->leaves.as<tms_leaf>(), L,
                                     ctx->corner_phi.as<double>(), s));
         st.n_corners = m;
         st.guard_points = ng;
+        ctx->leaf_off = {0, L};
         ctx->n_corners = m;
         ctx->corner_cells = cells->id;
         ctx->corner_dense = false;
     } else {
-        // Q_0: roots with a non-empty neighbourhood, raster order
+        // Q_0: roots with a non-empty neighbourhood, conformation by
+        // conformation, each in raster order
         const int64_t nr = cells->nroots;
         HIPCK(ctx->flags.ensure(4 * (size_t)nr));
         HIPCK(ctx->scan_a.ensure(4 * (size_t)nr));
@@ -754,45 +894,56 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         HIPCK(ctx->q[0].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nq, 1)));
         {
             TimedScope ts_(ctx, TMS_T_COMPACT);
-            HIPCK(launch_roots_emit(g, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nr,
-                                    ctx->q[0].as<int4>(), s));
+            HIPCK(launch_roots_emit(gt, nconf, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(),
+                                    nr, ctx->q[0].as<int4>(), s));
         }
         for (int lev = 0; lev <= g.K && nq > 0; ++lev) {
-            if (nq >= (int64_t)0x7FFFFFFF / 8) return fail(ctx, TMS_E_INVALID, "queue too large");
+            if (nq >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "queue too large");
             st.n_est[lev] = nq;
-            HIPCK(ctx->abuf.ensure(sizeof(double) * 64 * (size_t)nq));
-            HIPCK(ctx->ebuf.ensure(sizeof(double) * (size_t)nq));
-            HIPCK(ctx->hidx.ensure(sizeof(int32_t) * (size_t)nq));
+            // the tensors of the cubes that need the bound are staged in
+            // slices of at most slice_cubes queue entries
+            const int64_t S = std::max<int64_t>(1, ctx->slice_cubes);
+            const int64_t cap = std::min(nq, S);
+            const int64_t nslices = (nq + S - 1) / S;
+            if (nslices > kMaxSlices) return fail(ctx, TMS_E_INVALID, "queue too large for the slice size");
+            HIPCK(ctx->abuf.ensure(sizeof(double) * 64 * (size_t)cap));
+            HIPCK(ctx->ebuf.ensure(sizeof(double) * (size_t)cap));
+            HIPCK(ctx->hidx.ensure(sizeof(int32_t) * (size_t)cap));
             HIPCK(ctx->dec.ensure((size_t)nq));
             HIPCK(ctx->flags.ensure(4 * (size_t)nq));
             HIPCK(ctx->scan_a.ensure(4 * (size_t)nq));
             HIPCK(ctx->scan_b.ensure(4 * (size_t)nq));
             HIPCK(ctx->idx.ensure(4 * (size_t)nq));
             HIPCK(hipMemsetAsync(ctr, 0, 96 * sizeof(unsigned long long), s));
-            unsigned *hard1 = reinterpret_cast<unsigned *>(ctr + 64);
-            unsigned *hard2 = reinterpret_cast<unsigned *>(ctr + 65);
+            HIPCK(hipMemsetAsync(ctr + kSliceCtr, 0, 2 * kMaxSlices * sizeof(unsigned long long), s));
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
             const bool tiled = lev >= 2 && lev <= 3;
-            const int2 *chunks = nullptr;
-            int64_t nchunks = 0;
-            if (tiled) {
-                rc = build_chunks(ctx, g, lev, q, nullptr, nq, &chunks, &nchunks);
-                if (rc) return rc;
-            }
-            {  // Step 1 (tensor) and the decisions that need no bound
-                TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
-                HIPCK(launch_estimate_decide(
-                    g, lev, prec, q, nq, nullptr, chunks, nchunks, cells->root_start.as<int32_t>(),
-                    cells->root_atoms.as<int32_t>(), cells->ax.as<double>(), cells->ay.as<double>(),
-                    cells->az.as<double>(), cells->aw.as<double>(), ctx->dec.as<uint8_t>(),
-                    ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard1,
-                    reinterpret_cast<int64_t *>(ctr + 0), s));
-            }
-            {  // Step 2: nested-SVD bound on the cubes that need it
-                TimedScope ts_(ctx, TMS_T_DECIDE);
-                HIPCK(launch_bound(g, lev, prec, nq, ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
-                                   ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard1, s));
+            for (int64_t k = 0; k < nslices; ++k) {
+                const int64_t off = k * S, ns = std::min(S, nq - off);
+                unsigned *hard = reinterpret_cast<unsigned *>(ctr + kSliceCtr + k);
+                const int2 *chunks = nullptr;
+                int64_t nchunks = 0;
+                if (tiled) {
+                    rc = build_chunks(ctx, gt, lev, q + off, nullptr, ns, &chunks, &nchunks);
+                    if (rc) return rc;
+                }
+                {  // Step 1 (tensor) and the decisions that need no bound
+                    TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
+                    HIPCK(launch_estimate_decide(
+                        g, gt, lev, prec, q + off, ns, nullptr, chunks, nchunks,
+                        cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
+                        cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
+                        cells->aw.as<double>(), ctx->dec.as<uint8_t>() + off,
+                        ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
+                        hard, reinterpret_cast<int64_t *>(ctr + 0), s));
+                }
+                {  // Step 2: nested-SVD bound on the cubes that need it
+                    TimedScope ts_(ctx, TMS_T_DECIDE);
+                    HIPCK(launch_bound(g, lev, prec, ns, ctx->dec.as<uint8_t>() + off,
+                                       ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
+                                       ctx->hidx.as<int32_t>(), hard, s));
+                }
             }
             if (prec == TMS_PREC_FP32_GUARD) {
                 {
@@ -812,18 +963,23 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                     }
                     // the guarded cubes are sparse (well under 1 %): one thread per
                     // cube beats root chunks holding a handful of cubes each
-                    const int2 *gch = nullptr;
-                    const int64_t ngch = 0;
-                    TimedScope ts_(ctx, TMS_T_GUARD);
-                    HIPCK(launch_estimate_decide(
-                        g, lev, TMS_PREC_FP64, q, ng, ctx->idx.as<int32_t>(), gch, ngch,
-                        cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
-                        cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
-                        cells->aw.as<double>(), ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
-                        ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard2, nullptr, s));
-                    HIPCK(launch_bound(g, lev, TMS_PREC_FP64, ng, ctx->dec.as<uint8_t>(),
-                                       ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
-                                       ctx->hidx.as<int32_t>(), hard2, s));
+                    const int64_t gslices = (ng + S - 1) / S;
+                    if (gslices > kMaxSlices) return fail(ctx, TMS_E_INVALID, "guard list too large");
+                    for (int64_t k = 0; k < gslices; ++k) {
+                        const int64_t off = k * S, ns = std::min(S, ng - off);
+                        unsigned *hard =
+                            reinterpret_cast<unsigned *>(ctr + kSliceCtr + kMaxSlices + k);
+                        TimedScope ts_(ctx, TMS_T_GUARD);
+                        HIPCK(launch_estimate_decide(
+                            g, gt, lev, TMS_PREC_FP64, q, ns, ctx->idx.as<int32_t>() + off, nullptr,
+                            0, cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
+                            cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
+                            cells->aw.as<double>(), ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
+                            ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard, nullptr, s));
+                        HIPCK(launch_bound(g, lev, TMS_PREC_FP64, ns, ctx->dec.as<uint8_t>(),
+                                           ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
+                                           ctx->hidx.as<int32_t>(), hard, s));
+                    }
                 }
                 st.guard_cubes += ng;
             }
@@ -842,11 +998,18 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             HIPCK(d2h(h, ctr, 80, s));
             for (int k = 0; k < 64; ++k) st.n_pairs_lvl[lev] += (int64_t)h[k];
             st.n_pairs += st.n_pairs_lvl[lev];
-            st.n_bound += (int64_t)(h[64] & 0xFFFFFFFFull) + (int64_t)(h[65] & 0xFFFFFFFFull);
+            {
+                std::vector<unsigned long long> hs(2 * (size_t)kMaxSlices);
+                HIPCK(d2h(hs.data(), ctr + kSliceCtr, 2 * (size_t)kMaxSlices, s));
+                for (unsigned long long v : hs) st.n_bound += (int64_t)(v & 0xFFFFFFFFull);
+            }
             st.n_disc[lev] = (int64_t)h[72 + DEC_DISCARD];
             st.n_refine[lev] = (int64_t)h[72 + DEC_REFINE];
             st.n_conv[lev] = (int64_t)h[72 + DEC_CONV];
             st.n_hmin[lev] = (int64_t)h[72 + DEC_HMIN];
+            if (8 * st.n_refine[lev] >= (int64_t)0x7FFFFFFF ||
+                st.n_conv[lev] + st.n_hmin[lev] >= (int64_t)0x7FFFFFFF)
+                return fail(ctx, TMS_E_INVALID, "level %d too large (32-bit offsets)", lev);
             HIPCK(grow_keep(ctx->leaves, sizeof(tms_leaf) * (size_t)(L + nl), sizeof(tms_leaf) * (size_t)L, s));
             HIPCK(ctx->q[cur ^ 1].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nc, 1)));
             {
@@ -861,6 +1024,12 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         }
         HIPCK(ctx->leaves.ensure(sizeof(tms_leaf) * (size_t)std::max<int64_t>(L, 1)));
         HIPCK(ctx->corner_phi.ensure(sizeof(double) * 8 * (size_t)std::max<int64_t>(L, 1)));
+        if (nconf > 1) {
+            rc = regroup_by_conf(ctx, cells, L);
+            if (rc) return rc;
+        } else {
+            ctx->leaf_off = {0, L};
+        }
         int64_t nu = 0, ng = 0;
         rc = corner_stage(ctx, cells, ctx->leaves.as<tms_leaf>(), L, ctx->leaves.as<tms_leaf>(),
                           ctx->corner_phi.as<double>(), &nu, &ng);
@@ -919,7 +1088,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
     if (!ctx) return TMS_E_INVALID;
     if (!cells || !n_out || n < 0 || cap < 0 || (n > 0 && !leaves))
         return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_extract_cube_vertices");
-    if (12 * n >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves");
+    if (n >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "too many leaves");
     HIPCK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const Grid &g = cells->g;
@@ -938,49 +1107,73 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         cphi = ct;
     }
     int64_t nv = 0;
-    EdgeLat el{};
+    // edge lattices of every conformation, one block of words each
+    // (conformation-major, then level, then axis: the edge-key order)
+    const int nconf = cells->nconf;
+    std::vector<EdgeLat> etab((size_t)nconf);
+    std::vector<int64_t> first_word((size_t)nconf);
     double ebits = 0.0;
-    {
-        int64_t words = 0;
+    int64_t words = 0;
+    for (int b = 0; b < nconf; ++b) {
+        const Grid &gb = cells->gh[(size_t)b];
+        EdgeLat &el = etab[(size_t)b];
+        first_word[(size_t)b] = words;
         for (int lev = 0; lev <= g.K; ++lev)
             for (int a = 0; a < 3; ++a) {
                 Lat &l = el.l[lev][a];
-                double b = 1.0;
+                double bits = 1.0;
                 for (int k = 0; k < 3; ++k) {
-                    l.n[k] = ((int64_t)g.nr[k] << lev) + 1;
-                    b *= (double)l.n[k];
+                    l.n[k] = ((int64_t)gb.nr[k] << lev) + 1;
+                    bits *= (double)l.n[k];
                 }
                 l.base = words;
-                words += (int64_t)((b + 63.0) / 64.0);
-                ebits += b;
+                words += (int64_t)((bits + 63.0) / 64.0);
+                ebits += bits;
             }
-        el.words = words;
+        el.words = words - first_word[(size_t)b];
     }
     ctx->n_verts = 0;
     ctx->edge_cells = cells->id;
     ctx->edge_dense = n == 0;
-    if (n > 0 && ebits <= kMaxBitmapBits && el.words < (int64_t)0x7FFFFFFF) {
+    ctx->vert_off.assign((size_t)nconf + 1, 0);
+    if (n > 0 && ebits <= kMaxBitmapBits && words < (int64_t)0x7FFFFFFF) {
         // edge bitmaps in buffers of their own: the corner bitmap stays
         // valid for the adjoint
-        const int64_t nwords = el.words;
+        const int64_t nwords = words;
+        HIPCK(ctx->etab.ensure(sizeof(EdgeLat) * (size_t)nconf + sizeof(int64_t) * (size_t)(2 * nconf)));
+        EdgeLat *et = ctx->etab.as<EdgeLat>();
+        int64_t *fw = reinterpret_cast<int64_t *>(et + nconf), *vo = fw + nconf;
+        HIPCK(hipMemcpyAsync(et, etab.data(), sizeof(EdgeLat) * (size_t)nconf,
+                             hipMemcpyHostToDevice, s));
+        HIPCK(hipMemcpyAsync(fw, first_word.data(), sizeof(int64_t) * (size_t)nconf,
+                             hipMemcpyHostToDevice, s));
         HIPCK(ctx->ebmap.ensure(sizeof(uint64_t) * (size_t)nwords));
         HIPCK(ctx->ebcnt.ensure(sizeof(int32_t) * (size_t)nwords));
         HIPCK(ctx->eboff.ensure(sizeof(int32_t) * (size_t)nwords));
         {
             TimedScope ts_(ctx, TMS_T_EXTRACT);
             HIPCK(launch_fill_u64(ctx->ebmap.as<uint64_t>(), 0ull, nwords, s));
-            HIPCK(launch_edge_mark(lv, n, g.K, el, ctx->ebmap.as<unsigned long long>(), s));
+            HIPCK(launch_edge_mark(lv, n, et, ctx->ebmap.as<unsigned long long>(), s));
             HIPCK(launch_popc(ctx->ebmap.as<uint64_t>(), nwords, ctx->ebcnt.as<int32_t>(), s));
         }
         int32_t rc = scan_total(ctx, ctx->ebcnt.as<int32_t>(), ctx->eboff.as<int32_t>(), nwords, &nv);
         if (rc) return rc;
         HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
-        TimedScope ts_(ctx, TMS_T_EXTRACT);
-        HIPCK(launch_edge_write(g, lv, cphi, n, el, ctx->ebmap.as<uint64_t>(),
-                                ctx->eboff.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
+        {
+            TimedScope ts_(ctx, TMS_T_EXTRACT);
+            HIPCK(launch_edge_write(cells->gtab.as<Grid>(), lv, cphi, n, et,
+                                    ctx->ebmap.as<uint64_t>(), ctx->eboff.as<int32_t>(),
+                                    ctx->verts.as<tms_vertex>(), s));
+        }
+        // first vertex of every conformation: the rank of its first word
+        HIPCK(launch_gather_i32(ctx->eboff.as<int32_t>(), fw, nconf, vo, s));
+        HIPCK(d2h(ctx->vert_off.data(), vo, (size_t)nconf, s));
+        ctx->vert_off[(size_t)nconf] = nv;
         ctx->edge_dense = true;
-        ctx->edge_lat = el;
+        ctx->edge_lat = etab[0];
     } else if (n > 0) {
+        if (12 * n >= (int64_t)0x7FFFFFFF)
+            return fail(ctx, TMS_E_INVALID, "too many leaves for hashed edges");
         unsigned long long *ctr = ctx->counters.as<unsigned long long>();
         HIPCK(hipMemsetAsync(ctr, 0, 8, s));
         {
@@ -1009,8 +1202,12 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         if (rc) return rc;
         HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
         TimedScope ts_(ctx, TMS_T_EXTRACT);
-        HIPCK(launch_edge_emit(g, lv, cphi, ncand, ctx->flags.as<int32_t>(),
+        HIPCK(launch_edge_emit(cells->gtab.as<Grid>(), lv, cphi, ncand, ctx->flags.as<int32_t>(),
                                ctx->scan_b.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
+        // hashed edges come out in leaf order: per-conformation offsets only
+        // for a single conformation
+        if (nconf == 1) ctx->vert_off = {0, nv};
+        else ctx->vert_off.clear();
     }
     ctx->n_verts = nv;
     *n_out = nv;
@@ -1069,6 +1266,8 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
     if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
         return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
     if (cells->n > 0 && !dxyzr) return fail(ctx, TMS_E_INVALID, "dxyzr is NULL");
+    if (cells->nconf != 1)
+        return fail(ctx, TMS_E_INVALID, "tms_backward takes cells of one conformation");
     if (ctx->corner_cells != cells->id || !ctx->corner_dense)
         return fail(ctx, TMS_E_INVALID,
                     "no kept corners of an adaptive pass on these cells (run "
@@ -1100,12 +1299,12 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
     HIPCK(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
     {
         TimedScope ts_(ctx, TMS_T_BACKWARD);
-        HIPCK(launch_adjoint_fold(g, ctx->corner_lat, ctx->bmap.as<uint64_t>(),
+        HIPCK(launch_adjoint_fold(g, g.clat, ctx->bmap.as<uint64_t>(),
                                   ctx->bmoff.as<int32_t>(), ctx->uniq.as<double>(),
                                   ctx->uphi.as<double>(), M, dphi, ctx->edge_lat,
                                   ctx->ebmap.as<uint64_t>(), ctx->eboff.as<int32_t>(), dt,
                                   ctx->wbar.as<double>(), bad, s));
-        HIPCK(launch_adjoint_atoms(g, cells->p.precision, ctx->corner_lat, ctx->bmap.as<uint64_t>(),
+        HIPCK(launch_adjoint_atoms(g, cells->p.precision, g.clat, ctx->bmap.as<uint64_t>(),
                                    ctx->bmoff.as<int32_t>(), ctx->uniq.as<double>(),
                                    ctx->wbar.as<double>(), cells->n, cells->ax.as<double>(),
                                    cells->ay.as<double>(), cells->az.as<double>(),
@@ -1115,6 +1314,25 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
     unsigned hb = 0;
     HIPCK(d2h(&hb, bad, 1, s));
     if (hb) return fail(ctx, TMS_E_INVALID, "kept edge points do not end on kept corners");
+    return TMS_OK;
+}
+
+int32_t tms_batch_counts(tms_ctx *ctx, const tms_cells *cells, int64_t *leaf_offsets,
+                         int64_t *vertex_offsets) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    const size_t nb = (size_t)cells->nconf + 1;
+    if (leaf_offsets) {
+        if (ctx->corner_cells != cells->id || ctx->leaf_off.size() != nb)
+            return fail(ctx, TMS_E_INVALID, "no kept pass of these cells");
+        std::copy(ctx->leaf_off.begin(), ctx->leaf_off.end(), leaf_offsets);
+    }
+    if (vertex_offsets) {
+        if (ctx->edge_cells != cells->id || ctx->vert_off.size() != nb)
+            return fail(ctx, TMS_E_INVALID, "no kept per-conformation vertex offsets of these cells");
+        std::copy(ctx->vert_off.begin(), ctx->vert_off.end(), vertex_offsets);
+    }
     return TMS_OK;
 }
 
@@ -1174,7 +1392,8 @@ int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cu
         if (sub.empty()) continue;
         HIPCK(hipMemcpyAsync(ctx->idx.p, sub.data(), sizeof(int32_t) * sub.size(),
                              hipMemcpyHostToDevice, s));
-        HIPCK(launch_estimate(g, lev, precision, ctx->q[0].as<int4>(), (int64_t)sub.size(),
+        HIPCK(launch_estimate(g, cells->gtab.as<Grid>(), lev, precision, ctx->q[0].as<int4>(),
+                              (int64_t)sub.size(),
                               ctx->idx.as<int32_t>(), cells->root_start.as<int32_t>(),
                               cells->root_atoms.as<int32_t>(), cells->ax.as<double>(),
                               cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),

@@ -457,7 +457,7 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
             const int x0 = max(c0[0], (int)floor((p[0] - hx - g.o[0]) / g.cs));
             const int x1 = min(c1[0], (int)floor((p[0] + hx - g.o[0]) / g.cs));
             if (x0 > x1) continue;
-            const int row = (cz * g.nc[1] + cy) * g.nc[0];
+            const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
             const int b = cs[row + x0], e = cs[row + x1 + 1];
             for (int i = b; i < e; ++i) {
                 const double dx = p[0] - ax[i], dy = p[1] - ay[i], dz = p[2] - az[i];
@@ -493,5 +493,28 @@ __device__ __forceinline__ bool bit_test(const uint64_t *__restrict__ bm, int64_
     return (bm[b >> 6] >> (b & 63)) & 1ull;
 }
 
+// Conformation owning position i of a batch-wide atom or root array: the
+// last b whose base is <= i (bases ascend with b).
+__device__ __forceinline__ int conf_of_atom(const Grid *__restrict__ gt, int nconf, int64_t i) {
+    int lo = 0, hi = nconf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (gt[mid].atom_base <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int conf_of_root(const Grid *__restrict__ gt, int nconf, int64_t r) {
+    int lo = 0, hi = nconf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (gt[mid].root_base <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 }  // namespace tms
+
 

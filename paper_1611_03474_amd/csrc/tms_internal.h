@@ -12,20 +12,41 @@
 
 namespace tms {
 
+// Dense bitmaps over lattices of points, one bit per point, bit index
+// (X * ny + Y) * nz + Z (X-major, which is also the order of the packed
+// keys).  Sub-lattices start on 64-bit word boundaries.
+struct Lat {
+    int64_t n[3];   // points per axis
+    int64_t base;   // first word
+};
+// Edge lattices: one per (level, axis), at the level's resolution, laid out
+// level-major then axis, so the bit order is the edge-key order.
+struct EdgeLat {
+    Lat l[TMS_MAX_LEVELS][3];
+    int64_t words;
+};
+
 // ---------------------------------------------------------------------------
-// Grid description passed by value to kernels.
+// Geometry of one conformation.  A batch keeps one per conformation in a
+// device table (kernels index it by the conformation id carried by each
+// cube, leaf and point); the method's parameters (h0, hmin, D, c, tau, K)
+// are the same in every entry.
 // ---------------------------------------------------------------------------
 struct Grid {
     double o[3];     // origin of the root grid (multiple of h0)
     double h0;       // root cube edge
     double hmin;     // finest cube edge
     double D, c, tau;
-    double rc2;      // squared cut-off radius
+    double rc2;      // squared cut-off radius (this conformation's largest radius)
     double cs;       // atom-cell edge (smallest h0 * 2^m >= R_c / 4)
     int32_t nr[3];   // root cubes per axis
     int32_t nc[3];   // atom cells per axis
     int32_t K;       // finest level
     int32_t span;    // cell stencil half-width, ceil(R_c / cs)
+    int64_t root_base;  // first root / cell / atom of this conformation in the
+    int64_t cell_base;  // batch-wide root, cell and atom arrays
+    int64_t atom_base;
+    Lat clat;           // its block of the batch's corner bitmap
 };
 
 // Gauss-Legendre rule folded for the even/odd parts of a function on [-1,1]:
@@ -44,20 +65,6 @@ struct GLRule {
 int gl_half_nodes(double beta, bool fp32);
 template <typename T>
 GLRule<T> gl_rule(int half);
-
-// Dense bitmaps over lattices of points, one bit per point, bit index
-// (X * ny + Y) * nz + Z (X-major, which is also the order of the packed
-// keys).  Sub-lattices start on 64-bit word boundaries.
-struct Lat {
-    int64_t n[3];   // points per axis
-    int64_t base;   // first word
-};
-// Edge lattices: one per (level, axis), at the level's resolution, laid out
-// level-major then axis, so the bit order is the edge-key order.
-struct EdgeLat {
-    Lat l[TMS_MAX_LEVELS][3];
-    int64_t words;
-};
 
 // Decision codes of the per-cube state machine.
 enum : uint8_t {
@@ -86,10 +93,14 @@ struct DevBuf {
 // Public opaque types.
 // ---------------------------------------------------------------------------
 struct tms_cells {
-    tms::Grid g{};
+    tms::Grid g{};               // geometry of conformation 0 (the only one unless batched)
     tms_params p{};
+    int32_t nconf = 1;           // conformations in the batch
+    std::vector<tms::Grid> gh;   // geometry per conformation (host copy of gtab)
+    std::vector<int64_t> atom_off;  // [nconf + 1] atom offsets of the conformations
+    int64_t corner_words = 0;    // words of the batch's corner bitmap
     int64_t n = 0;               // atoms
-    int64_t nroots = 0;          // root cubes (nr[0]*nr[1]*nr[2])
+    int64_t nroots = 0;          // root cubes, all conformations
     int64_t ncells = 0;
     int64_t n_root_entries = 0;  // sum of root neighbourhood sizes
     int64_t n_nonempty = 0;      // roots with a non-empty neighbourhood
@@ -101,6 +112,8 @@ struct tms_cells {
     tms::DevBuf root_start;                 // int32 [nroots + 1]
     tms::DevBuf root_atoms;                 // int32 [n_root_entries]
     tms::DevBuf tmp_key, tmp_cnt;           // scratch for binning
+    tms::DevBuf gtab;                       // Grid [nconf] (device geometry table)
+    tms::DevBuf aoff;                       // int64 [nconf + 1]
     void release();
 };
 
@@ -121,16 +134,19 @@ struct tms_ctx {
     int64_t n_corners = 0;
     uint64_t corner_cells = 0, edge_cells = 0;  // tms_cells::id they belong to
     bool corner_dense = false, edge_dense = false;
-    tms::Lat corner_lat{};
     tms::EdgeLat edge_lat{};
-    tms::DevBuf ebmap, ebcnt, eboff, wbar;
+    tms::DevBuf ebmap, ebcnt, eboff, wbar, uconf, etab, lsort, ctab;
+    // batch bookkeeping of the last partition / extraction: per-conformation
+    // leaf and vertex offsets ([nconf + 1] each)
+    std::vector<int64_t> leaf_off, vert_off;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
         slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs, bmap, bmcnt, bmoff;
     // small device counters (u64 slots): [0,64) striped pair counts,
-    // 64/65 hard-list lengths, [72,77) decision histogram, 80 surface count,
-    // 96 adjoint consistency flag, 100 scan total; [256, 256 + 5*1024)
-    // reduction partials
+    // [72,77) decision histogram, 80 surface count, 96 adjoint consistency
+    // flag, 100 scan total; [256, 256 + 5*1024) reduction partials;
+    // [8192, 8192 + 512) hard-list lengths of the queue slices
+    int64_t slice_cubes = (int64_t)1 << 25;  // queue entries per estimate slice
     tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -159,19 +175,20 @@ void timing_flush(tms_ctx *ctx);
 // ---------------------------------------------------------------------------
 namespace tms {
 
-// k_cells.hip
-hipError_t launch_atom_stats(const double *xyzr, int64_t n, double *out8, hipStream_t s);
-hipError_t launch_bin_atoms(const Grid &g, const double *xyzr, int64_t n, int32_t *key,
-                            int32_t *cnt, int64_t ncells, hipStream_t s);
-hipError_t launch_scatter_atoms(const Grid &g, const double *xyzr, int64_t n, const int32_t *key,
+// k_cells.hip -- batch-wide arrays; gt: device table of nconf geometries
+hipError_t launch_atom_stats(const double *xyzr, const int64_t *off, int nconf, double *out9,
+                             hipStream_t s);
+hipError_t launch_bin_atoms(const Grid *gt, int nconf, const double *xyzr, int64_t n, int32_t *key,
+                            int32_t *cnt, hipStream_t s);
+hipError_t launch_scatter_atoms(const Grid *gt, const double *xyzr, int64_t n, const int32_t *key,
                                 int32_t *fill, double *ax, double *ay, double *az, double *aw,
                                 double *ar, int32_t *aidx, hipStream_t s);
 hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *ax, double *ay,
                              double *az, double *aw, double *ar, int32_t *aidx, hipStream_t s);
-hipError_t launch_root_count(const Grid &g, const int32_t *cell_start, const double *ax,
-                             const double *ay, const double *az, int64_t nroots, int32_t *cnt,
-                             hipStream_t s);
-hipError_t launch_root_fill(const Grid &g, const int32_t *cell_start, const double *ax,
+hipError_t launch_root_count(const Grid *gt, int nconf, const int32_t *cell_start,
+                             const double *ax, const double *ay, const double *az, int64_t nroots,
+                             int32_t *cnt, hipStream_t s);
+hipError_t launch_root_fill(const Grid *gt, int nconf, const int32_t *cell_start, const double *ax,
                             const double *ay, const double *az, int64_t nroots,
                             const int32_t *start, int32_t *atoms, hipStream_t s);
 
@@ -194,13 +211,18 @@ hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *t
                           void *tmp, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// out[i] = src[idx[i]]
+hipError_t launch_gather_i32(const int32_t *src, const int64_t *idx, int n, int64_t *out,
+                             hipStream_t s);
 
 // k_partition.hip
 hipError_t launch_roots_flags(const int32_t *root_start, int64_t nroots, int32_t *flags,
                               hipStream_t s);
-hipError_t launch_roots_emit(const Grid &g, const int32_t *flags, const int32_t *off,
+hipError_t launch_roots_emit(const Grid *gt, int nconf, const int32_t *flags, const int32_t *off,
                              int64_t nroots, int4 *q, hipStream_t s);
-hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+// g: the batch's shared parameters (host copy); gt: device geometry table
+hipError_t launch_estimate(const Grid &g, const Grid *gt, int level, int precision, const int4 *q,
+                           int64_t n,
                            const int32_t *subset, const int32_t *root_start,
                            const int32_t *root_atoms, const double *ax, const double *ay,
                            const double *az, const double *aw, double *A, double *E,
@@ -208,7 +230,8 @@ hipError_t launch_estimate(const Grid &g, int level, int precision, const int4 *
 // estimate + easy decisions; cubes needing the bound go to the hard list.
 // chunks != nullptr selects the tiled kernel (levels 2..3); chunk positions
 // index the subset list when one is given.
-hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const int4 *q, int64_t n,
+hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int precision,
+                                  const int4 *q, int64_t n,
                                   const int32_t *subset, const int2 *chunks, int64_t nchunks,
                                   const int32_t *root_start, const int32_t *root_atoms,
                                   const double *ax, const double *ay, const double *az,
@@ -218,7 +241,7 @@ hipError_t launch_estimate_decide(const Grid &g, int level, int precision, const
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s);
-hipError_t launch_run_flags(const Grid &g, int level, const int4 *q, const int32_t *subset,
+hipError_t launch_run_flags(const Grid *gt, int level, const int4 *q, const int32_t *subset,
                             int64_t n, int32_t *f, hipStream_t s);
 hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, int32_t *starts,
                              hipStream_t s);
@@ -236,26 +259,32 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
                              int64_t leaf_base, int4 *qnext, hipStream_t s);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
                               unsigned long long *part, hipStream_t s);
+// regrouping of a batch's leaves by conformation (segments level * nconf + conf)
+hipError_t launch_leaf_seg_heads(const tms_leaf *leaves, int64_t n, int nconf, int64_t *src,
+                                 hipStream_t s);
+hipError_t launch_leaf_seg_move(const tms_leaf *leaves, int64_t n, int nconf, const int64_t *src,
+                                const int64_t *dst, tms_leaf *out, hipStream_t s);
 hipError_t launch_bound_debug(const double *A, const double *band, int64_t n, double *out,
                               hipStream_t s);
 hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStream_t s);
 
 // k_phi.hip
-hipError_t launch_phi_points(const Grid &g, int precision, const double *pts, int64_t m,
-                             const int32_t *cell_start, const double *ax, const double *ay,
-                             const double *az, const double *aw, double band_rel, double *phi,
-                             double *grad, uint8_t *guard, hipStream_t s);
-hipError_t launch_phi_points_subset(const Grid &g, const double *pts, const int32_t *list,
-                                    int64_t m, const int32_t *cell_start, const double *ax,
-                                    const double *ay, const double *az, const double *aw,
-                                    double *phi, double *grad, hipStream_t s);
+// pconf: conformation of every point (NULL: all in conformation 0)
+hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision, const double *pts,
+                             int64_t m, const int32_t *cell_start, const double *ax,
+                             const double *ay, const double *az, const double *aw, double band_rel,
+                             double *phi, double *grad, uint8_t *guard, hipStream_t s);
+hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
+                                    const int32_t *list, int64_t m, const int32_t *cell_start,
+                                    const double *ax, const double *ay, const double *az,
+                                    const double *aw, double *phi, double *grad, hipStream_t s);
 hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                                 uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
 hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_t ncand,
                               int32_t *flags, hipStream_t s);
-hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid &g,
+hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid *gt,
                                 const int32_t *flags, const int32_t *off, const uint32_t *slot,
-                                double *upts, uint32_t *slot2u, hipStream_t s);
+                                double *upts, int32_t *uconf, uint32_t *slot2u, hipStream_t s);
 hipError_t launch_corner_gather(const tms_leaf *leaves_in, int64_t n, const uint32_t *slot,
                                 const uint32_t *slot2u, const double *uphi, double c,
                                 tms_leaf *leaves_out, double *corner_phi, hipStream_t s);
@@ -273,24 +302,26 @@ hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long
 
 // bitmap helpers (k_phi.hip)
 hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStream_t s);
-hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
+// corner bitmap: conformation L.conf owns the words of gt[L.conf].clat
+hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
                               unsigned long long *bm, hipStream_t s);
-hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Lat &lat,
-                               const uint64_t *bm, const int32_t *woff, const Grid &g, double *upts,
-                               hipStream_t s);
-hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Lat &lat,
+hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
+                               const uint64_t *bm, const int32_t *woff, double *upts,
+                               int32_t *uconf, hipStream_t s);
+hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Grid *gt,
                                    const uint64_t *bm, const int32_t *woff, const double *uphi,
                                    double c, tms_leaf *lout, double *cphi, hipStream_t s);
 
 // k_extract.hip
-hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, int K, const EdgeLat &el,
+// et: device table of edge lattices, one per conformation
+hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
                             unsigned long long *bm, hipStream_t s);
-hipError_t launch_edge_write(const Grid &g, const tms_leaf *leaves, const double *cphi, int64_t n,
-                             const EdgeLat &el, const uint64_t *bm, const int32_t *woff,
+hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
+                             const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
                              tms_vertex *out, hipStream_t s);
 hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                               uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
-hipError_t launch_edge_emit(const Grid &g, const tms_leaf *leaves, const double *corner_phi,
+hipError_t launch_edge_emit(const Grid *gt, const tms_leaf *leaves, const double *corner_phi,
                             int64_t ncand, const int32_t *flags, const int32_t *off,
                             tms_vertex *out, hipStream_t s);
 

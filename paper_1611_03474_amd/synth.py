@@ -50,37 +50,44 @@ class _Grid:
     def __init__(self, cell: float):
         self.cell = cell
         self.cells: dict = {}
-        self.pts: list = []
-
-    def _key(self, p):
-        return (int(math.floor(p[0] / self.cell)), int(math.floor(p[1] / self.cell)),
-                int(math.floor(p[2] / self.cell)))
+        self.n = 0
 
     def add(self, p) -> int:
-        idx = len(self.pts)
-        self.pts.append((float(p[0]), float(p[1]), float(p[2])))
-        self.cells.setdefault(self._key(p), []).append(idx)
+        idx = self.n
+        self.n += 1
+        x, y, z = float(p[0]), float(p[1]), float(p[2])
+        c = self.cell
+        key = (math.floor(x / c), math.floor(y / c), math.floor(z / c))
+        self.cells.setdefault(key, []).append((idx, x, y, z))
         return idx
 
     def near(self, p, r: float, skip: int = -1) -> bool:
-        kx, ky, kz = self._key(p)
+        px, py, pz = float(p[0]), float(p[1]), float(p[2])
+        c = self.cell
+        kx, ky, kz = math.floor(px / c), math.floor(py / c), math.floor(pz / c)
         r2 = r * r
+        get = self.cells.get
         for dx in (-1, 0, 1):
             for dy in (-1, 0, 1):
                 for dz in (-1, 0, 1):
-                    for j in self.cells.get((kx + dx, ky + dy, kz + dz), ()):
-                        if j == skip:
-                            continue
-                        q = self.pts[j]
-                        ex, ey, ez = p[0] - q[0], p[1] - q[1], p[2] - q[2]
-                        if ex * ex + ey * ey + ez * ez < r2:
+                    lst = get((kx + dx, ky + dy, kz + dz))
+                    if lst is None:
+                        continue
+                    for j, qx, qy, qz in lst:
+                        ex, ey, ez = px - qx, py - qy, pz - qz
+                        if ex * ex + ey * ey + ez * ez < r2 and j != skip:
                             return True
         return False
 
 
 def _unit(rng):
-    v = rng.normal(size=3)
-    return v / np.linalg.norm(v)
+    x, y, z = rng.normal(size=3).tolist()
+    n = math.sqrt(x * x + y * y + z * z)
+    return (x / n, y / n, z / n)
+
+
+def _step(p, d, u):
+    return (p[0] + d * u[0], p[1] + d * u[1], p[2] + d * u[2])
 
 
 def globule(n: int, seed: int) -> np.ndarray:
@@ -91,25 +98,26 @@ def globule(n: int, seed: int) -> np.ndarray:
     ca = _Grid(3.0)       # C-alphas only
     allg = _Grid(2.0)     # every atom
     pos = []
-    cur = np.zeros(3)
+    cur = (0.0, 0.0, 0.0)
     ca_idx = []
     fails = 0
     while len(pos) < n:
         # next C-alpha
         if not ca_idx:
-            p = np.zeros(3)
+            p = (0.0, 0.0, 0.0)
         else:
             placed = False
             for _ in range(100):
-                p = cur + 3.8 * _unit(rng)
-                if np.linalg.norm(p) <= rwalk and not ca.near(p, 3.0):
+                p = _step(cur, 3.8, _unit(rng))
+                if math.sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) <= rwalk \
+                        and not ca.near(p, 3.0):
                     placed = True
                     break
             if not placed:
                 fails += 1
                 if fails % 50 == 0:
                     rwalk *= 1.1  # too tight for the walk: loosen the sphere
-                cur = np.array(pos[ca_idx[int(rng.integers(len(ca_idx)))]])
+                cur = pos[ca_idx[int(rng.integers(len(ca_idx)))]]
                 continue
         ca.add(p)
         gi = allg.add(p)
@@ -124,7 +132,8 @@ def globule(n: int, seed: int) -> np.ndarray:
                 break
             ok = False
             for _ in range(100):
-                q = parent + rng.uniform(1.2, 1.5) * _unit(rng)
+                d = rng.uniform(1.2, 1.5)
+                q = _step(parent, d, _unit(rng))
                 if not allg.near(q, 2.0, skip=pidx):
                     ok = True
                     break
@@ -150,7 +159,7 @@ def add_hydrogens(heavy: np.ndarray, frac: float, seed: int) -> np.ndarray:
     hs = []
     while len(hs) < nh:
         k = int(rng.integers(heavy.shape[0]))
-        q = heavy[k, :3] + 1.0 * _unit(rng)
+        q = _step(tuple(heavy[k, :3].tolist()), 1.0, _unit(rng))
         if g.near(q, 1.5, skip=k):
             continue
         hs.append(q)

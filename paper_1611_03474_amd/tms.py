@@ -102,6 +102,9 @@ def load_library(path: str = LIB_PATH):
     L.tms_extract_cube_vertices.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(i64)]
     L.tms_get_vertices.argtypes = [_VP, _VP, i64, C.POINTER(i64)]
     L.tms_get_corners.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
+    L.tms_build_cells_batch.argtypes = [_VP, _VP, C.POINTER(i64), i32, C.POINTER(Params),
+                                        C.POINTER(_VP)]
+    L.tms_batch_counts.argtypes = [_VP, _VP, C.POINTER(i64), C.POINTER(i64)]
     L.tms_backward.argtypes = [_VP, _VP, _VP, i64, _VP, i64, _VP]
     L.tms_set_timing.argtypes = [_VP, i32]
     L.tms_get_timing.argtypes = [_VP, C.POINTER(Timing), i32]
@@ -112,7 +115,8 @@ def load_library(path: str = LIB_PATH):
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
-              "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward"):
+              "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
+              "tms_build_cells_batch", "tms_batch_counts"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -148,10 +152,11 @@ class Cells:
     handle: C.c_void_p
     params: Params
     n_atoms: int
-    origin: np.ndarray
-    dims: np.ndarray
+    origin: np.ndarray   # conformation 0
+    dims: np.ndarray     # conformation 0
     K: int
-    rc2: float
+    rc2: float           # conformation 0
+    n_conf: int = 1
 
 
 class Context:
@@ -203,6 +208,44 @@ class Context:
         self.lib.tms_cells_info(h, o, d, C.byref(K), C.byref(rc2), C.byref(na))
         return Cells(h, params, int(na.value), np.array(o[:]), np.array(d[:]), int(K.value),
                      float(rc2.value))
+
+    def build_cells_batch(self, confs, params: Params, cells: Cells | None = None) -> Cells:
+        """Cells of a batch: `confs` is a list of [N_b, 4] arrays/tensors, or a
+        (concatenated [N, 4] tensor, offsets [n_conf + 1]) pair."""
+        t = self._torch
+        if isinstance(confs, tuple):
+            a, off = confs
+            off = np.asarray(off, dtype=np.int64)
+        else:
+            parts = [np.asarray(c.cpu() if isinstance(c, t.Tensor) else c, dtype=np.float64)
+                     .reshape(-1, 4) for c in confs]
+            off = np.zeros(len(parts) + 1, dtype=np.int64)
+            off[1:] = np.cumsum([len(x) for x in parts])
+            a = np.concatenate(parts, axis=0) if parts else np.zeros((0, 4))
+        a = a if isinstance(a, t.Tensor) else t.as_tensor(np.asarray(a))
+        a = a.to(device=self.device, dtype=t.float64).contiguous()
+        offc = np.ascontiguousarray(off, dtype=np.int64)
+        h = cells.handle if cells is not None else _VP()
+        self._check(self.lib.tms_build_cells_batch(
+            self.h, _VP(_ptr(a)), offc.ctypes.data_as(C.POINTER(C.c_int64)), len(offc) - 1,
+            C.byref(params), C.byref(h)))
+        o = (C.c_double * 3)()
+        d = (C.c_int64 * 3)()
+        K = C.c_int32()
+        rc2 = C.c_double()
+        na = C.c_int64()
+        self.lib.tms_cells_info(h, o, d, C.byref(K), C.byref(rc2), C.byref(na))
+        return Cells(h, params, int(na.value), np.array(o[:]), np.array(d[:]), int(K.value),
+                     float(rc2.value), n_conf=len(offc) - 1)
+
+    def batch_counts(self, cells: Cells, vertices: bool = True):
+        """(leaf offsets, vertex offsets or None) [n_conf + 1] of the kept results."""
+        lo = np.zeros(cells.n_conf + 1, dtype=np.int64)
+        vo = np.zeros(cells.n_conf + 1, dtype=np.int64)
+        P = C.POINTER(C.c_int64)
+        self._check(self.lib.tms_batch_counts(self.h, cells.handle, lo.ctypes.data_as(P),
+                                              vo.ctypes.data_as(P) if vertices else None))
+        return lo, (vo if vertices else None)
 
     def free_cells(self, cells: Cells):
         self._check(self.lib.tms_free_cells(self.h, cells.handle))

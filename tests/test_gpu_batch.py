@@ -1,0 +1,153 @@
+"""Batched refinement: many conformations of uneven size in one pass.
+
+Each conformation's group of the batch output must be bit-identical to the
+single-conformation pass of the HIP path (the same arithmetic in the same
+atom order) and, for the small ones, equal to the FP64 oracle run with that
+conformation id (leaf list bit-exact, vertex keys bit-exact including the
+conformation bits, t within the bar of the precision).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1611_03474_amd import synth, tms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = tms.Context(0)
+    yield c
+    c.close()
+
+
+def _confs():
+    # uneven sizes, one empty conformation, one with hydrogens (a different
+    # largest radius, hence a different cut-off), perturbed copies
+    out = []
+    for k, n in enumerate([180, 420, 0, 260, 90, 350]):
+        if n == 0:
+            out.append(np.zeros((0, 4)))
+            continue
+        g = synth.globule(n, 2000 + k)
+        rng = np.random.default_rng(77 + k)
+        g[:, :3] += rng.normal(scale=0.3, size=(n, 3))
+        out.append(g)
+    h = synth.add_hydrogens(synth.globule(200, 2100), 0.1, 2101)
+    h = h[h[:, 3] < 1.75]  # drop the 1.8 A atoms: the largest radius is 1.7
+    out.append(h)
+    return out
+
+
+def _single(ctx, atoms, p):
+    cells = ctx.build_cells(atoms, p)
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    r = (tms.leaves_to_numpy(leaves), cphi.cpu().numpy(), tms.vertices_to_numpy(verts))
+    ctx.free_cells(cells)
+    return r
+
+
+@pytest.mark.parametrize("prec", [tms.PREC_FP64, tms.PREC_FP32_GUARD], ids=["fp64", "fp32g"])
+def test_batch_equals_single_and_oracle(ctx, prec):
+    confs = _confs()
+    D, c, tau = 0.9, 1.0, 0.1
+    p = tms.make_params(D=D, c=c, tau=tau, precision=prec)
+    cells = ctx.build_cells_batch(confs, p)
+    assert cells.n_conf == len(confs)
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    lo, vo = ctx.batch_counts(cells)
+    L = tms.leaves_to_numpy(leaves)
+    CP = cphi.cpu().numpy()
+    V = tms.vertices_to_numpy(verts)
+    assert lo[-1] == len(L) and vo[-1] == len(V)
+    assert np.all(np.diff(L["conf"]) >= 0)
+    for b, atoms in enumerate(confs):
+        Lb, CPb, Vb = L[lo[b]:lo[b + 1]], CP[lo[b]:lo[b + 1]], V[vo[b]:vo[b + 1]]
+        assert np.all(Lb["conf"] == b)
+        if len(atoms) == 0:
+            assert len(Lb) == 0 and len(Vb) == 0
+            continue
+        Ls, CPs, Vs = _single(ctx, atoms, p)
+        assert len(Lb) == len(Ls), b
+        for f in ("level", "ix", "iy", "iz", "reason", "mask", "cls"):
+            assert np.array_equal(Lb[f], Ls[f]), (b, f)
+        assert np.array_equal(CPb, CPs), b  # same arithmetic, same order: same bits
+        conf_bits = np.uint64(b) << np.uint64(53)
+        assert np.array_equal(Vb["edge_key"], Vs["edge_key"] | conf_bits), b
+        assert np.array_equal(Vb["t"], Vs["t"]), b
+        ref = oracle.partition(atoms, D, c=c, tau=tau, conf=b)
+        assert ref.tie_cube == 0 and ref.tie_corner == 0
+        assert np.array_equal(Lb["level"], ref.level)
+        assert np.array_equal(np.stack([Lb["ix"], Lb["iy"], Lb["iz"]], 1), ref.ijk)
+        assert np.array_equal(Lb["mask"], ref.mask) and np.array_equal(Lb["cls"], ref.cls)
+        assert np.array_equal(Vb["edge_key"], ref.vkey)
+        tol = 1e-12 if prec == tms.PREC_FP64 else 1e-5
+        assert np.max(np.abs(Vb["t"] - ref.vt), initial=0.0) <= tol
+    ctx.free_cells(cells)
+
+
+def test_batch_of_one_is_the_single_pass(ctx):
+    atoms = synth.globule(300, 2200)
+    p = tms.make_params(D=1.5, tau=0.1, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells_batch([atoms], p)
+    leaves, cphi, _ = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    Ls, CPs, Vs = _single(ctx, atoms, p)
+    L = tms.leaves_to_numpy(leaves)
+    assert np.array_equal(L, Ls)
+    assert np.array_equal(cphi.cpu().numpy(), CPs)
+    assert np.array_equal(tms.vertices_to_numpy(verts), Vs)
+    ctx.free_cells(cells)
+
+
+def test_batch_rejects_bad_offsets(ctx):
+    import torch
+    a = torch.zeros((10, 4), dtype=torch.float64, device="cuda:0")
+    a[:, 3] = 1.5
+    p = tms.make_params(tau=0.1)
+    with pytest.raises(tms.TmsError):
+        ctx.build_cells_batch((a, [0, 6, 4, 10]), p)   # decreasing
+    with pytest.raises(tms.TmsError):
+        ctx.build_cells_batch((a, [1, 10]), p)         # not starting at 0
+    pu = tms.make_params(tau=0.1, h0=0.5, h_min=0.5, mode=tms.MODE_UNIFORM)
+    with pytest.raises(tms.TmsError):
+        ctx.build_cells_batch((a, [0, 5, 10]), pu)     # uniform grid: one conformation
+
+
+def test_batch_full_size_sampled(ctx):
+    # 256 conformations, sizes log-uniform in [500, 20000], FP32+guard: a
+    # sample of conformations must match their single-conformation passes
+    # bit for bit; two small ones also match the oracle
+    confs = synth.batch(256)
+    p = tms.make_params(D=0.9, tau=1e-3, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells_batch(confs, p)
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    lo, vo = ctx.batch_counts(cells)
+    print("batch: %d atoms, %d leaves, %d vertices, %d cubes estimated"
+          % (sum(len(x) for x in confs), lo[-1], vo[-1], sum(st["n_est"])))
+    rng = np.random.default_rng(11)
+    sizes = np.array([len(x) for x in confs])
+    small = [int(i) for i in np.argsort(sizes)[:2]]
+    pick = sorted(set(small) | set(int(i) for i in rng.choice(256, 4, replace=False)))
+    for b in pick:
+        sel = slice(lo[b], lo[b + 1])
+        Lb = tms.leaves_to_numpy(leaves[sel])
+        Vb = tms.vertices_to_numpy(verts[vo[b]:vo[b + 1]])
+        Ls, CPs, Vs = _single(ctx, confs[b], p)
+        for f in ("level", "ix", "iy", "iz", "reason", "mask", "cls"):
+            assert np.array_equal(Lb[f], Ls[f]), (b, f)
+        assert np.array_equal(cphi[sel].cpu().numpy(), CPs), b
+        assert np.array_equal(Vb["edge_key"], Vs["edge_key"] | (np.uint64(b) << np.uint64(53)))
+        if b in small:
+            ref = oracle.partition(confs[b], 0.9, c=1.0, tau=1e-3, conf=b)
+            if ref.tie_cube == 0 and ref.tie_corner == 0:
+                assert np.array_equal(np.stack([Lb["ix"], Lb["iy"], Lb["iz"]], 1), ref.ijk)
+                assert np.array_equal(Lb["mask"], ref.mask)
+                assert np.array_equal(Vb["edge_key"], ref.vkey)
+    ctx.free_cells(cells)
