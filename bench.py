@@ -122,6 +122,75 @@ def run_adjoint(ctx, tms, steps, warmup):
             "atoms_per_s": atoms.shape[0] / ((t1 - t0) / steps)}
 
 
+def run_batch(ctx, tms, confs, steps, warmup):
+    """Batched refinement: every conformation of the batch in one pass
+    (build, partition, extract), after the library's autotuner picked the
+    launch shapes; beside it the same conformations one pass each, in
+    FP32+guard and in FP64."""
+    import numpy as np
+    import torch
+    from paper_1611_03474_amd import workloads
+    w = workloads.BATCH256
+    p = w.params(tms.PREC_FP32_GUARD)
+    off = np.zeros(len(confs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(c) for c in confs])
+    a = torch.as_tensor(np.concatenate(confs, axis=0), dtype=torch.float64, device="cuda:0")
+    singles = [torch.as_tensor(c, dtype=torch.float64, device="cuda:0") for c in confs]
+    cells = ctx.build_cells_batch((a, off), p)
+    tuning, tune_ms, tune_n = ctx.autotune(cells)
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    nl0, nv0 = leaves.shape[0], verts.shape[0]
+    del leaves, cphi, verts
+    lb = torch.empty((nl0 + 1024, 20), dtype=torch.uint8, device="cuda:0")
+    cb = torch.empty((nl0 + 1024, 8), dtype=torch.float64, device="cuda:0")
+    vb = torch.empty((nv0 + 1024, 40), dtype=torch.uint8, device="cuda:0")
+
+    def step():
+        ctx.build_cells_batch((a, off), p, cells)
+        nl, s_ = ctx.partition_into(cells, lb, cb)
+        nv = ctx.extract_into(cells, lb, nl, cb, vb)
+        return nl, nv, s_
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        nl, nv, s_ = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    sd = s_.as_dict()
+    ctx.free_cells(cells)
+
+    def loop(prec):
+        # the same conformations one pass each (the first sweep warms up)
+        pp = w.params(prec)
+        c1 = None
+        dt = 0.0
+        for sweep in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for c in singles:
+                c1 = ctx.build_cells(c, pp, c1)
+                n1, _ = ctx.partition_into(c1, lb, cb)
+                ctx.extract_into(c1, lb, n1, cb, vb)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) * 1e3
+        ctx.free_cells(c1)
+        return dt
+
+    loop32 = loop(tms.PREC_FP32_GUARD)
+    loop64 = loop(tms.PREC_FP64)
+    est = int(sum(sd["n_est"]))
+    return {"workload": w.name, "conformations": len(confs), "atoms": int(off[-1]),
+            "leaves": int(nl), "vertices": int(nv), "cubes_estimated": est,
+            "ms_per_pass": ms, "cubes_per_s": est / (ms * 1e-3),
+            "tuning": tuning, "autotune_best_ms": tune_ms, "autotune_passes": tune_n,
+            "loop_fp32g_ms": loop32, "loop_fp64_ms": loop64,
+            "speedup_vs_loop_fp32g": loop32 / ms, "speedup_vs_loop_fp64": loop64 / ms}
+
+
 def cpu_baseline(atoms, w):
     """FP64 oracle on a bounded sample: the first globule of the assembly and
     its hydrogens (about 1/20 of the workload)."""
@@ -151,6 +220,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--workload", default="assembly110k")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (counter scale for HBM traffic)")
@@ -169,6 +239,12 @@ def main():
     t0 = time.perf_counter()
     atoms = workloads.atoms(w)
     log("  %d atoms in %.1f s" % (len(atoms), time.perf_counter() - t0))
+    batch_confs = None
+    if not args.no_batch:
+        t0 = time.perf_counter()
+        batch_confs = workloads.atoms(workloads.BATCH256)
+        log("  batch of %d conformations (%d atoms) in %.1f s"
+            % (len(batch_confs), sum(len(c) for c in batch_confs), time.perf_counter() - t0))
     atoms_dev = torch.as_tensor(atoms, dtype=torch.float64, device="cuda:0").contiguous()
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
@@ -252,6 +328,12 @@ def main():
                                               for k, v in f64["timing"].items()},
                        "same_leaf_count": f64["n_leaves"] == f32["n_leaves"]}
         out["speedup_fp32guard_vs_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+    if batch_confs is not None:
+        log("batch run")
+        out["batch"] = run_batch(ctx, tms, batch_confs, args.steps, args.warmup)
+        log("  %.1f ms per batched pass, %.1f ms looped FP32+guard, %.1f ms looped FP64"
+            % (out["batch"]["ms_per_pass"], out["batch"]["loop_fp32g_ms"],
+               out["batch"]["loop_fp64_ms"]))
     if not args.no_adjoint:
         log("adjoint run")
         out["adjoint"] = run_adjoint(ctx, tms, args.steps, args.warmup)

@@ -284,6 +284,38 @@ int32_t tms_get_corners(tms_ctx *ctx, double *xyz, double *phi, int64_t cap, int
 int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, int64_t m,
                      const double *dt, int64_t nv, double *dxyzr);
 
+/* ---- tuning ---------------------------------------------------------------
+ * Launch-shape knobs of the partition pass.  Results do not depend on them
+ * (every cube's arithmetic is the same under any setting); only the time
+ * does.  Defaults: slice_cubes 2^25, tiled_min_level 2, tile_atoms 16. */
+typedef struct {
+    int64_t slice_cubes;     /* queue entries per estimate + bound slice; the
+                                staged tensors take 512 B each (>= 4096)   */
+    int32_t tiled_min_level; /* first level estimated one wavefront per chunk
+                                of <= 64 cubes of one root (1..3; 4: none;
+                                levels above 3 always use one thread per
+                                cube)                                        */
+    int32_t tile_atoms;      /* atoms staged per LDS tile of that kernel:
+                                8, 16 or 32                                  */
+} tms_tuning;
+
+/* Set / read ctx's tuning.  Errors: TMS_E_INVALID (values out of range). */
+int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t);
+int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t);
+
+/* Autotuner: times tms_partition_estimate on `cells` (count only, device
+ * results discarded) under candidate tunings -- atoms per tile, then the
+ * first tiled level, then the slice size, each with the others at their
+ * best so far -- checks that every candidate gives the same leaf and cube
+ * counts, and leaves the fastest set on ctx.
+ *  best     host out (or NULL): the chosen tuning.
+ *  best_ms  host out (or NULL): its wall time in ms.
+ *  n_tried  host out (or NULL): passes timed.
+ * Errors: those of tms_partition_estimate; TMS_E_DEVICE if two candidates
+ * disagree. */
+int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, double *best_ms,
+                     int32_t *n_tried);
+
 /* ---- device-time instrumentation ----------------------------------------
  * When enabled, the library brackets its kernel launches with HIP events on
  * the context's stream and accumulates the elapsed device time per phase
@@ -297,7 +329,7 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
 #define TMS_T_PHI 6      /* phi kernels (corner values, tms_eval_phi)   */
 #define TMS_T_EXTRACT 7  /* edge de-duplication and vertex emission    */
 #define TMS_T_TILED 8    /* tensor estimate, one wave per chunk of
-                            cubes of one root (levels 2 and 3)         */
+                            cubes of one root (tiled levels)           */
 #define TMS_T_BACKWARD 9 /* adjoint kernels                             */
 #define TMS_T_SLOTS 10
 

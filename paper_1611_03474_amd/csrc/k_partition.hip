@@ -575,17 +575,27 @@ hipError_t estimate_thread_t(const Grid *g, int level, const int4 *q, int64_t n,
     return hipGetLastError();
 }
 
-constexpr int kCH = 16;
-
 template <bool FAST, int QH>
-hipError_t estimate_tiled_t(const Grid *g, int level, const int4 *q, const int32_t *subset,
+hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, const int32_t *subset,
                             const int2 *chunks, int64_t nchunks, const int32_t *rs,
                             const int32_t *ra, const double *ax, const double *ay, const double *az,
                             const double *aw, const EstOut &o, unsigned long long *pairs,
                             hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
-    hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, kCH>), dim3((unsigned)nchunks), dim3(64), 0, s, g,
-                       level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+    // atoms staged per LDS tile (a tuning knob; the arithmetic is the same)
+    switch (ch) {
+    case 8:
+        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 8>), dim3((unsigned)nchunks), dim3(64), 0, s,
+                           g, level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+        break;
+    case 32:
+        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 32>), dim3((unsigned)nchunks), dim3(64), 0, s,
+                           g, level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+        break;
+    default:
+        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 16>), dim3((unsigned)nchunks), dim3(64), 0, s,
+                           g, level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+    }
     return hipGetLastError();
 }
 
@@ -609,12 +619,13 @@ hipError_t thread_dispatch(int qh, const Grid *g, int level, const int4 *q, int6
 }
 
 template <bool FAST>
-hipError_t tiled_dispatch(int qh, const Grid *g, int level, const int4 *q, const int32_t *subset,
-                          const int2 *chunks, int64_t nchunks, const int32_t *rs, const int32_t *ra,
-                          const double *ax, const double *ay, const double *az, const double *aw,
-                          const EstOut &o, unsigned long long *pairs, hipStream_t s) {
-    TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(g, level, q, subset, chunks, nchunks, rs, ra, ax,
-                                                  ay, az, aw, o, pairs, s)))
+hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *q,
+                          const int32_t *subset, const int2 *chunks, int64_t nchunks,
+                          const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
+                          const double *az, const double *aw, const EstOut &o,
+                          unsigned long long *pairs, hipStream_t s) {
+    TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(ch, g, level, q, subset, chunks, nchunks, rs, ra,
+                                                  ax, ay, az, aw, o, pairs, s)))
 }
 
 }  // namespace
@@ -730,7 +741,7 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *ax, const double *ay, const double *az,
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
-                                  hipStream_t s) {
+                                  int tile_atoms, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
@@ -739,10 +750,10 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
-            return tiled_dispatch<true>(qh, gt, level, q, subset, chunks, nchunks, root_start,
-                                        root_atoms, ax, ay, az, aw, o, pc, s);
-        return tiled_dispatch<false>(qh, gt, level, q, subset, chunks, nchunks, root_start,
-                                     root_atoms, ax, ay, az, aw, o, pc, s);
+            return tiled_dispatch<true>(qh, tile_atoms, gt, level, q, subset, chunks, nchunks,
+                                        root_start, root_atoms, ax, ay, az, aw, o, pc, s);
+        return tiled_dispatch<false>(qh, tile_atoms, gt, level, q, subset, chunks, nchunks,
+                                     root_start, root_atoms, ax, ay, az, aw, o, pc, s);
     }
     if (fast)
         return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,

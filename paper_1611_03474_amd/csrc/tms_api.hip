@@ -4,6 +4,7 @@
 // arXiv:1611.03474) on one HIP stream.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -918,7 +919,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             HIPCK(hipMemsetAsync(ctr + kSliceCtr, 0, 2 * kMaxSlices * sizeof(unsigned long long), s));
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
-            const bool tiled = lev >= 2 && lev <= 3;
+            const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
             for (int64_t k = 0; k < nslices; ++k) {
                 const int64_t off = k * S, ns = std::min(S, nq - off);
                 unsigned *hard = reinterpret_cast<unsigned *>(ctr + kSliceCtr + k);
@@ -936,7 +937,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
                         cells->aw.as<double>(), ctx->dec.as<uint8_t>() + off,
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
-                        hard, reinterpret_cast<int64_t *>(ctr + 0), s));
+                        hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
@@ -975,7 +976,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                             0, cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
                             cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
                             cells->aw.as<double>(), ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
-                            ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard, nullptr, s));
+                            ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard, nullptr,
+                            ctx->tile_atoms, s));
                         HIPCK(launch_bound(g, lev, TMS_PREC_FP64, ns, ctx->dec.as<uint8_t>(),
                                            ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
                                            ctx->hidx.as<int32_t>(), hard, s));
@@ -1333,6 +1335,101 @@ int32_t tms_batch_counts(tms_ctx *ctx, const tms_cells *cells, int64_t *leaf_off
             return fail(ctx, TMS_E_INVALID, "no kept per-conformation vertex offsets of these cells");
         std::copy(ctx->vert_off.begin(), ctx->vert_off.end(), vertex_offsets);
     }
+    return TMS_OK;
+}
+
+int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!t) return fail(ctx, TMS_E_INVALID, "tuning is NULL");
+    if (t->slice_cubes < 4096) return fail(ctx, TMS_E_INVALID, "slice_cubes < 4096");
+    if (t->tiled_min_level < 1 || t->tiled_min_level > 4)
+        return fail(ctx, TMS_E_INVALID, "tiled_min_level outside 1..4");
+    if (t->tile_atoms != 8 && t->tile_atoms != 16 && t->tile_atoms != 32)
+        return fail(ctx, TMS_E_INVALID, "tile_atoms must be 8, 16 or 32");
+    ctx->slice_cubes = t->slice_cubes;
+    ctx->tiled_min_level = t->tiled_min_level;
+    ctx->tile_atoms = t->tile_atoms;
+    return TMS_OK;
+}
+
+int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t) {
+    if (!ctx || !t) return TMS_E_INVALID;
+    t->slice_cubes = ctx->slice_cubes;
+    t->tiled_min_level = ctx->tiled_min_level;
+    t->tile_atoms = ctx->tile_atoms;
+    return TMS_OK;
+}
+
+int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, double *best_ms,
+                     int32_t *n_tried) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells) return fail(ctx, TMS_E_INVALID, "cells is NULL");
+    tms_tuning cur{};
+    tms_get_tuning(ctx, &cur);
+    int64_t ref_leaves = -1, ref_est = -1;
+    int tried = 0;
+    // one timed count-only pass under tuning t
+    auto run = [&](const tms_tuning &t, double *ms) -> int32_t {
+        int32_t rc = tms_set_tuning(ctx, &t);
+        if (rc) return rc;
+        tms_stats st;
+        int64_t nl = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = tms_partition_estimate(ctx, cells, nullptr, 0, &nl, nullptr, &st);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rc) return rc;
+        ++tried;
+        int64_t est = 0;
+        for (int l = 0; l < TMS_MAX_LEVELS; ++l) est += st.n_est[l];
+        if (ref_leaves < 0) {
+            ref_leaves = nl;
+            ref_est = est;
+        } else if (nl != ref_leaves || est != ref_est) {
+            return fail(ctx, TMS_E_DEVICE, "tuning changed the result (%lld vs %lld leaves)",
+                        (long long)nl, (long long)ref_leaves);
+        }
+        *ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        return TMS_OK;
+    };
+    double ms = 0.0, bms = 0.0;
+    int32_t rc = run(cur, &ms);  // warm-up (buffers grow to size)
+    if (rc) return rc;
+    rc = run(cur, &bms);
+    if (rc) return rc;
+    tms_tuning b = cur;
+    auto consider = [&](tms_tuning t) -> int32_t {
+        int32_t r = run(t, &ms);
+        if (r) return r;
+        if (ms < bms) {
+            bms = ms;
+            b = t;
+        }
+        return TMS_OK;
+    };
+    for (int ch : {8, 16, 32}) {
+        if (ch == b.tile_atoms) continue;
+        tms_tuning t = b;
+        t.tile_atoms = ch;
+        if ((rc = consider(t))) return rc;
+    }
+    const tms_tuning bch = b;
+    for (int lv : {1, 2, 3}) {
+        if (lv == bch.tiled_min_level) continue;
+        tms_tuning t = bch;
+        t.tiled_min_level = lv;
+        if ((rc = consider(t))) return rc;
+    }
+    const tms_tuning blv = b;
+    for (int64_t sc : {(int64_t)1 << 23, (int64_t)1 << 24, (int64_t)1 << 25, (int64_t)1 << 26}) {
+        if (sc == blv.slice_cubes) continue;
+        tms_tuning t = blv;
+        t.slice_cubes = sc;
+        if ((rc = consider(t))) return rc;
+    }
+    tms_set_tuning(ctx, &b);
+    if (best) *best = b;
+    if (best_ms) *best_ms = bms;
+    if (n_tried) *n_tried = tried;
     return TMS_OK;
 }
 

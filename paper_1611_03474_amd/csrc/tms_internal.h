@@ -146,7 +146,11 @@ struct tms_ctx {
     // [72,77) decision histogram, 80 surface count, 96 adjoint consistency
     // flag, 100 scan total; [256, 256 + 5*1024) reduction partials;
     // [8192, 8192 + 512) hard-list lengths of the queue slices
-    int64_t slice_cubes = (int64_t)1 << 25;  // queue entries per estimate slice
+    // tuning (results do not depend on it): queue entries per estimate
+    // slice, first level estimated by the tiled kernel, atoms per LDS tile
+    int64_t slice_cubes = (int64_t)1 << 25;
+    int tiled_min_level = 2;
+    int tile_atoms = 16;
     tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -237,7 +241,7 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *ax, const double *ay, const double *az,
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
-                                  hipStream_t s);
+                                  int tile_atoms, hipStream_t s);
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s);

@@ -42,6 +42,14 @@ class Timing(C.Structure):
                 for i, k in enumerate(T_SLOTS)}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("slice_cubes", C.c_int64), ("tiled_min_level", C.c_int32),
+                ("tile_atoms", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TmsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("tms error %d: %s" % (code, msg))
@@ -105,6 +113,10 @@ def load_library(path: str = LIB_PATH):
     L.tms_build_cells_batch.argtypes = [_VP, _VP, C.POINTER(i64), i32, C.POINTER(Params),
                                         C.POINTER(_VP)]
     L.tms_batch_counts.argtypes = [_VP, _VP, C.POINTER(i64), C.POINTER(i64)]
+    L.tms_set_tuning.argtypes = [_VP, C.POINTER(Tuning)]
+    L.tms_get_tuning.argtypes = [_VP, C.POINTER(Tuning)]
+    L.tms_autotune.argtypes = [_VP, _VP, C.POINTER(Tuning), C.POINTER(C.c_double),
+                               C.POINTER(i32)]
     L.tms_backward.argtypes = [_VP, _VP, _VP, i64, _VP, i64, _VP]
     L.tms_set_timing.argtypes = [_VP, i32]
     L.tms_get_timing.argtypes = [_VP, C.POINTER(Timing), i32]
@@ -116,7 +128,8 @@ def load_library(path: str = LIB_PATH):
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
               "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
-              "tms_build_cells_batch", "tms_batch_counts"):
+              "tms_build_cells_batch", "tms_batch_counts", "tms_set_tuning", "tms_get_tuning",
+              "tms_autotune"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -378,6 +391,31 @@ class Context:
                                           0 if dphi is None else dphi.shape[0], _VP(_ptr(dt)),
                                           0 if dt is None else dt.shape[0], _VP(_ptr(out))))
         return out
+
+    # ---------------------------------------------------------------- tuning
+    def set_tuning(self, slice_cubes=None, tiled_min_level=None, tile_atoms=None):
+        t = self.get_tuning()
+        if slice_cubes is not None:
+            t.slice_cubes = int(slice_cubes)
+        if tiled_min_level is not None:
+            t.tiled_min_level = int(tiled_min_level)
+        if tile_atoms is not None:
+            t.tile_atoms = int(tile_atoms)
+        self._check(self.lib.tms_set_tuning(self.h, C.byref(t)))
+
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        self._check(self.lib.tms_get_tuning(self.h, C.byref(t)))
+        return t
+
+    def autotune(self, cells: Cells):
+        """Runs the library's autotuner on `cells`; returns (tuning dict, best ms, passes)."""
+        t = Tuning()
+        ms = C.c_double()
+        n = C.c_int32()
+        self._check(self.lib.tms_autotune(self.h, cells.handle, C.byref(t), C.byref(ms),
+                                          C.byref(n)))
+        return t.as_dict(), ms.value, n.value
 
     # ---------------------------------------------------------------- timing
     def set_timing(self, enable: bool):

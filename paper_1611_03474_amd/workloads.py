@@ -40,6 +40,10 @@ GLOBULE20K_ADJOINT = Workload(
     "globule20k_adjoint",
     "20,000-atom globule, adaptive 2 -> 0.25, tau 1e-3; loss sum (phi - c)^2 over unique leaf "
     "corners + sum ((t - 1/2) h)^2 over edge points, gradient w.r.t. centres and radii", D=0.9)
+BATCH256 = Workload(
+    "batch256",
+    "256 conformations, atom counts log-uniform in [500, 20000] (each its own globule plus "
+    "N(0, 0.3^2) A coordinate noise), adaptive 2 -> 0.25, tau 1e-3, refined as one batch", D=0.9)
 ASSEMBLY110K = Workload(
     "assembly110k",
     "110,000-atom assembly (20 globules of 5,000 atoms, 2 A gaps, plus 10% hydrogens r=1.2), "
@@ -53,10 +57,12 @@ def atoms(w: Workload):
         return synth.globule(5000, 1002)
     if w.name == "globule20k_adjoint":
         return synth.globule(20000, 1004)
+    if w.name == "batch256":
+        return synth.batch(256, 1005)
     if w.name == "assembly110k":
         return synth.assembly(20, 5000, seed=1003, h_frac=0.10)
     raise KeyError(w.name)
 
 
 ALL = {w.name: w for w in [GLOBULE200_UNIFORM, *GLOBULE5K.values(), GLOBULE20K_ADJOINT,
-                           ASSEMBLY110K]}
+                           BATCH256, ASSEMBLY110K]}

@@ -151,3 +151,26 @@ def test_batch_full_size_sampled(ctx):
                 assert np.array_equal(Lb["mask"], ref.mask)
                 assert np.array_equal(Vb["edge_key"], ref.vkey)
     ctx.free_cells(cells)
+
+
+def test_tuning_does_not_change_results(ctx):
+    confs = _confs()
+    p = tms.make_params(D=0.9, tau=0.1, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells_batch(confs, p)
+    base = ctx.get_tuning().as_dict()
+    ref = None
+    for tml, ch, sc in [(2, 16, 1 << 25), (1, 8, 4096), (3, 32, 5000), (4, 16, 1 << 23)]:
+        ctx.set_tuning(slice_cubes=sc, tiled_min_level=tml, tile_atoms=ch)
+        leaves, cphi, st = ctx.partition_estimate(cells)
+        got = (tms.leaves_to_numpy(leaves).tobytes(), cphi.cpu().numpy().tobytes(),
+               st["n_est"], st["n_bound"])
+        if ref is None:
+            ref = got
+        assert got == ref, (tml, ch, sc)
+    with pytest.raises(tms.TmsError):
+        ctx.set_tuning(tile_atoms=12)
+    best, ms, n = ctx.autotune(cells)
+    print("autotune: %s in %.2f ms after %d passes" % (best, ms, n))
+    assert n >= 8 and ms > 0
+    ctx.set_tuning(**base)
+    ctx.free_cells(cells)
