@@ -287,10 +287,12 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
 /* ---- tuning ---------------------------------------------------------------
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
- * does.  Defaults: slice_cubes 2^25, tiled_min_level 2, tile_atoms 16. */
+ * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 16. */
 typedef struct {
-    int64_t slice_cubes;     /* queue entries per estimate + bound slice; the
-                                staged tensors take 512 B each (>= 4096)   */
+    int64_t slice_cubes;     /* largest queue slice per estimate + bound
+                                launch (a level is cut into ceil(n / this)
+                                equal slices); the staged tensors take
+                                512 B per entry (>= 4096)                   */
     int32_t tiled_min_level; /* first level estimated one wavefront per chunk
                                 of <= 64 cubes of one root (1..3; 4: none;
                                 levels above 3 always use one thread per

@@ -903,9 +903,11 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             st.n_est[lev] = nq;
             // the tensors of the cubes that need the bound are staged in
             // slices of at most slice_cubes queue entries
-            const int64_t S = std::max<int64_t>(1, ctx->slice_cubes);
+            // (equal slices: ceil(nq / slice_cubes) of them)
+            const int64_t S0 = std::max<int64_t>(1, ctx->slice_cubes);
+            const int64_t nslices = (nq + S0 - 1) / S0;
+            const int64_t S = (nq + nslices - 1) / nslices;
             const int64_t cap = std::min(nq, S);
-            const int64_t nslices = (nq + S - 1) / S;
             if (nslices > kMaxSlices) return fail(ctx, TMS_E_INVALID, "queue too large for the slice size");
             HIPCK(ctx->abuf.ensure(sizeof(double) * 64 * (size_t)cap));
             HIPCK(ctx->ebuf.ensure(sizeof(double) * (size_t)cap));
@@ -1420,7 +1422,8 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
         if ((rc = consider(t))) return rc;
     }
     const tms_tuning blv = b;
-    for (int64_t sc : {(int64_t)1 << 23, (int64_t)1 << 24, (int64_t)1 << 25, (int64_t)1 << 26}) {
+    for (int64_t sc : {(int64_t)1 << 23, (int64_t)1 << 24, (int64_t)1 << 25, (int64_t)1 << 26,
+                       (int64_t)1 << 27}) {
         if (sc == blv.slice_cubes) continue;
         tms_tuning t = blv;
         t.slice_cubes = sc;

@@ -148,7 +148,7 @@ struct tms_ctx {
     // [8192, 8192 + 512) hard-list lengths of the queue slices
     // tuning (results do not depend on it): queue entries per estimate
     // slice, first level estimated by the tiled kernel, atoms per LDS tile
-    int64_t slice_cubes = (int64_t)1 << 25;
+    int64_t slice_cubes = (int64_t)1 << 26;
     int tiled_min_level = 2;
     int tile_atoms = 16;
     tms::DevBuf counters;
