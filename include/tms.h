@@ -284,6 +284,38 @@ int32_t tms_get_corners(tms_ctx *ctx, double *xyz, double *phi, int64_t cap, int
 int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, int64_t m,
                      const double *dt, int64_t nv, double *dxyzr);
 
+/* ---- captured pass ---------------------------------------------------------
+ * The whole pass of tms_partition_estimate followed by
+ * tms_extract_cube_vertices (roots, every level with its guard re-runs and
+ * compaction, a batch's regrouping, corners, edge points) recorded once into
+ * a HIP graph.  Every size stays on the device: launches are sized by
+ * capacities (the counts of an eager pass of the same cells times `margin`)
+ * and read their actual counts there, so a replay needs no host round trip
+ * until its results are read.  Results are those of the eager pass, bit for
+ * bit.  Needs the dense corner and edge bitmaps (not the hashed paths).
+ *
+ * tms_graph_capture: requires an eager tms_partition_estimate and
+ * tms_extract_cube_vertices of `cells` (the last ones on ctx); margin in
+ * [1, 64].  The context keeps one capture (private buffers); a new capture
+ * replaces it.  Errors: TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
+int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin);
+
+/* Replay the captured pass on ctx's stream.  `cells` must be the captured
+ * cells, or a rebuild of them with the same geometry and buffers.
+ *  leaves, corner_phi  device [leaf_cap] tms_leaf / [leaf_cap][8] double, or NULL;
+ *  verts               device [vert_cap] tms_vertex, or NULL;
+ *  n_leaves, n_verts   host out (or NULL);
+ *  leaf_offsets, vertex_offsets  host [n_conf + 1] (or NULL): per-conformation
+ *                      boundaries, as tms_batch_counts;
+ *  stats               host out (or NULL).
+ * Errors: TMS_E_CAPACITY when a count exceeded its captured capacity (capture
+ * again with a larger margin) or an output buffer is too small (counts are
+ * set); TMS_E_INVALID (no capture, other cells); TMS_E_DEVICE. */
+int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
+                         double *corner_phi, int64_t leaf_cap, int64_t *n_leaves,
+                         tms_vertex *verts, int64_t vert_cap, int64_t *n_verts,
+                         int64_t *leaf_offsets, int64_t *vertex_offsets, tms_stats *stats);
+
 /* ---- tuning ---------------------------------------------------------------
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time

@@ -129,9 +129,10 @@ __device__ __forceinline__ int64_t edge_bit(const EdgeLat &el, const tms_leaf &L
 }
 
 __global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n,
-                            const EdgeLat *__restrict__ et, unsigned long long *__restrict__ bm) {
+                            const EdgeLat *__restrict__ et, unsigned long long *__restrict__ bm,
+                            const int64_t *__restrict__ nd) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 12 * n) return;
+    if (c >= 12 * n || (nd && c >= 12 * *nd)) return;
     const tms_leaf L = leaves[c / 12];
     if (L.cls != TMS_CLS_SURFACE) return;
     int axis, off[3], v0, v1;
@@ -147,9 +148,11 @@ __global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n,
 __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__restrict__ leaves,
                              const double *__restrict__ cphi, int64_t n,
                              const EdgeLat *__restrict__ et, const uint64_t *__restrict__ bm,
-                             const int32_t *__restrict__ woff, tms_vertex *__restrict__ out) {
+                             const int32_t *__restrict__ woff, tms_vertex *__restrict__ out,
+                             const int64_t *__restrict__ nd, int64_t vcap,
+                             unsigned *__restrict__ ovf) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 12 * n) return;
+    if (c >= 12 * n || (nd && c >= 12 * *nd)) return;
     const int64_t q = c / 12;
     const tms_leaf L = leaves[q];
     if (L.cls != TMS_CLS_SURFACE) return;
@@ -160,6 +163,10 @@ __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__rest
     const int64_t b = edge_bit(et[L.conf], L, axis, off);
     const int64_t w = b >> 6;
     const int64_t r = (int64_t)woff[w] + __popcll(bm[w] & ((1ull << (b & 63)) - 1ull));
+    if (ovf && r >= vcap) {  // capacity-sized buffer (capture path)
+        atomicOr(ovf, 1u);
+        return;
+    }
     const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
     const int sh = g.K - L.level;
     const double h = ldexp(g.h0, -(int)L.level);
@@ -180,18 +187,19 @@ __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__rest
 }  // namespace
 
 hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
-                            unsigned long long *bm, hipStream_t s) {
+                            unsigned long long *bm, hipStream_t s, const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, et, bm);
+    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, et, bm, nd);
     return hipGetLastError();
 }
 
 hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
                              const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
-                             tms_vertex *out, hipStream_t s) {
+                             tms_vertex *out, hipStream_t s, const int64_t *nd, int64_t vcap,
+                             unsigned *ovf) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_edge_write, dim3(nblk(12 * n)), dim3(kBS), 0, s, gt, leaves, cphi, n, et,
-                       bm, woff, out);
+                       bm, woff, out, nd, vcap, ovf);
     return hipGetLastError();
 }
 

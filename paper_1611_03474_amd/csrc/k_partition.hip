@@ -58,6 +58,8 @@ struct EstOut {
     double *hardE;       // [cap] their error bounds (0 for exact exponentials)
     int32_t *hardIdx;    // [cap] their queue indices
     unsigned *hardCount; // device counter (reset by the host per pass)
+    const int32_t *ncount;  // device count of entries (or chunks) when the
+                            // launch is sized by a capacity; null: the launch size
 };
 
 constexpr uint8_t DEC_HARD = 255;
@@ -154,7 +156,8 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
     unsigned long long *__restrict__ pairs) {
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     unsigned long long np = 0;
-    const bool valid = t < n;
+    const int64_t n_ = o.ncount ? min((int64_t)*o.ncount, n) : n;
+    const bool valid = t < n_;
     const int64_t qi = valid ? (subset ? subset[t] : t) : 0;
     const int4 c = valid ? q[qi] : make_int4(0, 0, 0, 0);
     const Grid &g = gt[c.w];
@@ -240,6 +243,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     __shared__ double s_w[CH];
     __shared__ int s_use[CH];
     const int lane = threadIdx.x;
+    if (o.ncount && (int64_t)blockIdx.x >= (int64_t)*o.ncount) return;  // whole workgroup
     const int2 ch = chunks[blockIdx.x];
     const bool valid = lane < ch.y;
     const int64_t pos = (int64_t)ch.x + (valid ? lane : 0);
@@ -401,9 +405,13 @@ __device__ __forceinline__ int64_t root_of(const Grid *__restrict__ gt, int leve
 
 __global__ void k_run_flags(const Grid *__restrict__ gt, int level, const int4 *__restrict__ q,
                             const int32_t *__restrict__ subset, int64_t n,
-                            int32_t *__restrict__ f) {
+                            const int32_t *__restrict__ nd, int32_t *__restrict__ f) {
     const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (i >= n) return;
+    if (nd && i >= (int64_t)*nd) {  // capacity-sized launch: zero the tail for the scan
+        f[i] = 0;
+        return;
+    }
     if (i == 0) {
         f[i] = 1;
         return;
@@ -419,26 +427,35 @@ __global__ void k_run_starts(const int32_t *__restrict__ f, const int32_t *__res
 }
 
 __global__ void k_run_chunk_counts(const int32_t *__restrict__ starts, int64_t nruns, int64_t n,
+                                   const int32_t *__restrict__ nrd, const int32_t *__restrict__ nd,
                                    int32_t *__restrict__ cnt) {
     const int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (r >= nruns) return;
-    const int64_t len = ((r + 1 < nruns) ? starts[r + 1] : n) - starts[r];
+    const int64_t R = nrd ? min((int64_t)*nrd, nruns) : nruns, N = nd ? (int64_t)*nd : n;
+    if (r >= R) {
+        cnt[r] = 0;
+        return;
+    }
+    const int64_t len = ((r + 1 < R) ? starts[r + 1] : N) - starts[r];
     cnt[r] = (int32_t)((len + 63) / 64);
 }
 
 __global__ void k_run_chunk_emit(const int32_t *__restrict__ starts, int64_t nruns, int64_t n,
+                                 const int32_t *__restrict__ nrd, const int32_t *__restrict__ nd,
                                  const int32_t *__restrict__ coff, int2 *__restrict__ chunks) {
     const int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (r >= nruns) return;
-    const int64_t b = starts[r], len = ((r + 1 < nruns) ? starts[r + 1] : n) - b;
+    const int64_t R = nrd ? min((int64_t)*nrd, nruns) : nruns, N = nd ? (int64_t)*nd : n;
+    if (r >= R) return;
+    const int64_t b = starts[r], len = ((r + 1 < R) ? starts[r + 1] : N) - b;
     int2 *o = chunks + coff[r];
     for (int64_t k = 0; k * 64 < len; ++k)
         o[k] = make_int2((int32_t)(b + 64 * k), (int32_t)min<int64_t>(64, len - 64 * k));
 }
 
-__global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n, int32_t *__restrict__ f) {
+__global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n,
+                              const int32_t *__restrict__ nd, int32_t *__restrict__ f) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i < n) f[i] = dec[i] == DEC_GUARD;
+    if (i < n) f[i] = (!nd || i < (int64_t)*nd) && dec[i] == DEC_GUARD;
 }
 
 __global__ void k_list_emit(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
@@ -447,23 +464,42 @@ __global__ void k_list_emit(const int32_t *__restrict__ f, const int32_t *__rest
     if (i < n && f[i]) list[off[i]] = (int32_t)i;
 }
 
-__global__ void k_level_counts(const uint8_t *__restrict__ dec, int64_t n, int32_t *__restrict__ lc,
+__global__ void k_level_counts(const uint8_t *__restrict__ dec, int64_t n,
+                               const int32_t *__restrict__ nd, int32_t *__restrict__ lc,
                                int32_t *__restrict__ cc) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (i >= n) return;
+    if (nd && i >= (int64_t)*nd) {
+        lc[i] = 0;
+        cc[i] = 0;
+        return;
+    }
     const uint8_t d = dec[i];
     lc[i] = (d == DEC_CONV || d == DEC_HMIN) ? 1 : 0;
     cc[i] = (d == DEC_REFINE) ? 8 : 0;
 }
 
+// Capacity-sized launches (nd given) read the leaf base from *lbd and guard
+// the leaf and child capacities (setting *ovf instead of writing past them).
 __global__ void k_level_emit(const int4 *__restrict__ q, const uint8_t *__restrict__ dec, int64_t n,
                              int level, const int32_t *__restrict__ loff,
                              const int32_t *__restrict__ coff, tms_leaf *__restrict__ leaves,
-                             int64_t leaf_base, int4 *__restrict__ qn) {
+                             int64_t leaf_base, int4 *__restrict__ qn, const int32_t *__restrict__ nd,
+                             const int64_t *__restrict__ lbd, int64_t lcap, int64_t qcap,
+                             unsigned *__restrict__ ovf) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (nd && i >= (int64_t)*nd)) return;
     const uint8_t d = dec[i];
     const int4 c = q[i];
+    if (nd) {
+        const int64_t li = *lbd + loff[i];
+        if (((d == DEC_CONV || d == DEC_HMIN) && li >= lcap) ||
+            (d == DEC_REFINE && (int64_t)coff[i] + 8 > qcap)) {
+            atomicOr(ovf, 1u);
+            return;
+        }
+        leaf_base = *lbd;
+    }
     if (d == DEC_CONV || d == DEC_HMIN) {
         tms_leaf L;
         L.ix = c.x;
@@ -487,18 +523,18 @@ __global__ void k_level_emit(const int4 *__restrict__ q, const uint8_t *__restri
 // level.  Segment (level, conformation) heads, then a move that regroups the
 // leaves conformation by conformation (order inside a segment kept).
 __global__ void k_leaf_seg_heads(const tms_leaf *__restrict__ lv, int64_t n, int nconf,
-                                 int64_t *__restrict__ src) {
+                                 const int64_t *__restrict__ nd, int64_t *__restrict__ src) {
     const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (nd && i >= *nd)) return;
     const int seg = lv[i].level * nconf + lv[i].conf;
     if (i == 0 || seg != lv[i - 1].level * nconf + lv[i - 1].conf) src[seg] = i;
 }
 
 __global__ void k_leaf_seg_move(const tms_leaf *__restrict__ lv, int64_t n, int nconf,
-                                const int64_t *__restrict__ src, const int64_t *__restrict__ dst,
-                                tms_leaf *__restrict__ out) {
+                                const int64_t *__restrict__ nd, const int64_t *__restrict__ src,
+                                const int64_t *__restrict__ dst, tms_leaf *__restrict__ out) {
     const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (nd && i >= *nd)) return;
     const tms_leaf L = lv[i];
     const int seg = L.level * nconf + L.conf;
     out[dst[seg] + (i - src[seg])] = L;
@@ -509,9 +545,11 @@ __global__ void k_leaf_seg_move(const tms_leaf *__restrict__ lv, int64_t n, int 
 constexpr int kHistoBlocks = 1024;
 
 __global__ void k_level_histo(const uint8_t *__restrict__ dec, int64_t n,
+                              const int32_t *__restrict__ nd,
                               unsigned long long *__restrict__ part) {
     __shared__ unsigned long long sh[5][kBS];
     unsigned long long c[5] = {0, 0, 0, 0, 0};
+    if (nd) n = min(n, (int64_t)*nd);
     for (int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBS) {
         const uint8_t d = dec[i];
@@ -741,12 +779,12 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *ax, const double *ay, const double *az,
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
-                                  int tile_atoms, hipStream_t s) {
+                                  int tile_atoms, hipStream_t s, const int32_t *ncount) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount};
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
@@ -766,16 +804,16 @@ hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, 
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s) {
     if (max_n <= 0) return hipSuccess;
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, nullptr};
     hipLaunchKernelGGL(k_bound, dim3(nblk(max_n)), dim3(kBS), 0, s, g, level,
                        precision == TMS_PREC_FP32_GUARD ? 1 : 0, o);
     return hipGetLastError();
 }
 
 hipError_t launch_run_flags(const Grid *gt, int level, const int4 *q, const int32_t *subset,
-                            int64_t n, int32_t *f, hipStream_t s) {
+                            int64_t n, int32_t *f, hipStream_t s, const int32_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, gt, level, q, subset, n, f);
+    hipLaunchKernelGGL(k_run_flags, dim3(nblk(n)), dim3(kBS), 0, s, gt, level, q, subset, n, nd, f);
     return hipGetLastError();
 }
 
@@ -787,23 +825,26 @@ hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, in
 }
 
 hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
-                                   hipStream_t s) {
+                                   hipStream_t s, const int32_t *nrd, const int32_t *nd) {
     if (nruns <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_run_chunk_counts, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, cnt);
+    hipLaunchKernelGGL(k_run_chunk_counts, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, nrd,
+                       nd, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n,
-                                 const int32_t *coff, int2 *chunks, hipStream_t s) {
+                                 const int32_t *coff, int2 *chunks, hipStream_t s,
+                                 const int32_t *nrd, const int32_t *nd) {
     if (nruns <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_run_chunk_emit, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, coff,
-                       chunks);
+    hipLaunchKernelGGL(k_run_chunk_emit, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, nrd,
+                       nd, coff, chunks);
     return hipGetLastError();
 }
 
-hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s) {
+hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s,
+                                   const int32_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_guard_flags, dim3(nblk(n)), dim3(kBS), 0, s, dec, n, flags);
+    hipLaunchKernelGGL(k_guard_flags, dim3(nblk(n)), dim3(kBS), 0, s, dec, n, nd, flags);
     return hipGetLastError();
 }
 
@@ -815,26 +856,27 @@ hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int6
 }
 
 hipError_t launch_level_counts(const uint8_t *dec, int64_t n, int32_t *lc, int32_t *cc,
-                               hipStream_t s) {
+                               hipStream_t s, const int32_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_level_counts, dim3(nblk(n)), dim3(kBS), 0, s, dec, n, lc, cc);
+    hipLaunchKernelGGL(k_level_counts, dim3(nblk(n)), dim3(kBS), 0, s, dec, n, nd, lc, cc);
     return hipGetLastError();
 }
 
 hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int level,
                              const int32_t *loff, const int32_t *coff, tms_leaf *leaves,
-                             int64_t leaf_base, int4 *qn, hipStream_t s) {
+                             int64_t leaf_base, int4 *qn, hipStream_t s, const int32_t *nd,
+                             const int64_t *lbd, int64_t lcap, int64_t qcap, unsigned *ovf) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_level_emit, dim3(nblk(n)), dim3(kBS), 0, s, q, dec, n, level, loff, coff,
-                       leaves, leaf_base, qn);
+                       leaves, leaf_base, qn, nd, lbd, lcap, qcap, ovf);
     return hipGetLastError();
 }
 
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h,
-                              unsigned long long *part, hipStream_t s) {
+                              unsigned long long *part, hipStream_t s, const int32_t *nd) {
     if (n <= 0) return hipSuccess;
     const int nb = (int)std::min<int64_t>(kHistoBlocks, (n + kBS - 1) / kBS);
-    hipLaunchKernelGGL(k_level_histo, dim3(nb), dim3(kBS), 0, s, dec, n, part);
+    hipLaunchKernelGGL(k_level_histo, dim3(nb), dim3(kBS), 0, s, dec, n, nd, part);
     hipLaunchKernelGGL(k_level_histo_final, dim3(1), dim3(64), 0, s, part, nb, h);
     return hipGetLastError();
 }
@@ -846,17 +888,18 @@ hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStrea
 }
 
 hipError_t launch_leaf_seg_heads(const tms_leaf *leaves, int64_t n, int nconf, int64_t *src,
-                                 hipStream_t s) {
+                                 hipStream_t s, const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_leaf_seg_heads, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, nconf, src);
+    hipLaunchKernelGGL(k_leaf_seg_heads, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, nconf, nd, src);
     return hipGetLastError();
 }
 
 hipError_t launch_leaf_seg_move(const tms_leaf *leaves, int64_t n, int nconf, const int64_t *src,
-                                const int64_t *dst, tms_leaf *out, hipStream_t s) {
+                                const int64_t *dst, tms_leaf *out, hipStream_t s,
+                                const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_leaf_seg_move, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, nconf, src, dst,
-                       out);
+    hipLaunchKernelGGL(k_leaf_seg_move, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, nconf, nd, src,
+                       dst, out);
     return hipGetLastError();
 }
 

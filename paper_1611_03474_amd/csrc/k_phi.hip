@@ -30,9 +30,10 @@ __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
                                                     const double *__restrict__ aw,
                                                     double band_rel, double *__restrict__ phi,
                                                     double *__restrict__ grad,
-                                                    uint8_t *__restrict__ guard) {
+                                                    uint8_t *__restrict__ guard,
+                                                    const int32_t *__restrict__ nd) {
     int64_t k = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (k >= m) return;
+    if (k >= m || (nd && k >= (int64_t)*nd)) return;
     const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
@@ -59,9 +60,10 @@ __global__ __launch_bounds__(kBS) void k_phi_subset(const Grid *__restrict__ gt,
                                                     const double *__restrict__ az,
                                                     const double *__restrict__ aw,
                                                     double *__restrict__ phi,
-                                                    double *__restrict__ grad) {
+                                                    double *__restrict__ grad,
+                                                    const int32_t *__restrict__ nd) {
     int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (t >= m) return;
+    if (t >= m || (nd && t >= (int64_t)*nd)) return;
     const int64_t k = list[t];
     const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
@@ -225,9 +227,10 @@ __global__ void k_count_u8(const uint8_t *__restrict__ v, int64_t n, uint8_t val
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
-__global__ void k_flags_u8(const uint8_t *__restrict__ gd, int64_t n, int32_t *__restrict__ f) {
+__global__ void k_flags_u8(const uint8_t *__restrict__ gd, int64_t n,
+                           const int32_t *__restrict__ nd, int32_t *__restrict__ f) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i < n) f[i] = gd[i] ? 1 : 0;
+    if (i < n) f[i] = ((!nd || i < (int64_t)*nd) && gd[i]) ? 1 : 0;
 }
 
 __global__ void k_list_emit2(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
@@ -238,9 +241,11 @@ __global__ void k_list_emit2(const int32_t *__restrict__ f, const int32_t *__res
 
 // number of SURFACE leaves: block partials, then one block
 __global__ void k_count_surface(const tms_leaf *__restrict__ leaves, int64_t n,
+                                const int64_t *__restrict__ nd,
                                 unsigned long long *__restrict__ part) {
     __shared__ unsigned long long sh[kBS];
     unsigned long long c = 0;
+    if (nd) n = min(n, *nd);
     for (int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBS)
         c += leaves[i].cls == TMS_CLS_SURFACE;
@@ -289,9 +294,10 @@ __global__ void k_popc(const uint64_t *__restrict__ bm, int64_t nw, int32_t *__r
 // finest-level leaf usually has all 8 in one 4x4x4 block), one atomic OR per
 // distinct word
 __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, int K,
-                              const Grid *__restrict__ gt, unsigned long long *__restrict__ bm) {
+                              const Grid *__restrict__ gt, unsigned long long *__restrict__ bm,
+                              const int64_t *__restrict__ nd) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (q >= n) return;
+    if (q >= n || (nd && q >= *nd)) return;
     const tms_leaf L = leaves[q];
     const Lat lat = gt[L.conf].clat;
     int64_t w[8];
@@ -323,14 +329,19 @@ __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, in
 __global__ void k_corner_write(const tms_leaf *__restrict__ leaves, int64_t n, int K,
                                const Grid *__restrict__ gt, const uint64_t *__restrict__ bm,
                                const int32_t *__restrict__ woff, double *__restrict__ upts,
-                               int32_t *__restrict__ uconf) {
+                               int32_t *__restrict__ uconf, const int64_t *__restrict__ nd,
+                               int64_t ucap, unsigned *__restrict__ ovf) {
     const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 8 * n) return;
+    if (c >= 8 * n || (nd && c >= 8 * *nd)) return;
     const tms_leaf L = leaves[c >> 3];
     const Grid &g = gt[L.conf];
     int64_t X, Y, Z;
     leaf_corner(L, (int)(c & 7), K, X, Y, Z);
     const int64_t u = bit_rank(bm, woff, lat_bit(g.clat, X, Y, Z));
+    if (ovf && u >= ucap) {  // capacity-sized buffers (capture path)
+        atomicOr(ovf, 1u);
+        return;
+    }
     upts[3 * u] = g.o[0] + (double)X * g.hmin;
     upts[3 * u + 1] = g.o[1] + (double)Y * g.hmin;
     upts[3 * u + 2] = g.o[2] + (double)Z * g.hmin;
@@ -341,9 +352,10 @@ __global__ void k_corner_gather_bm(const tms_leaf *__restrict__ lin, int64_t n, 
                                    const Grid *__restrict__ gt, const uint64_t *__restrict__ bm,
                                    const int32_t *__restrict__ woff, const double *__restrict__ uphi,
                                    double c, tms_leaf *__restrict__ lout,
-                                   double *__restrict__ cphi) {
+                                   double *__restrict__ cphi, const int64_t *__restrict__ nd,
+                                   int64_t ucap, unsigned *__restrict__ ovf) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (q >= n) return;
+    if (q >= n || (nd && q >= *nd)) return;
     tms_leaf L = lin[q];
     const Lat lat = gt[L.conf].clat;
     double f[8];
@@ -351,7 +363,13 @@ __global__ void k_corner_gather_bm(const tms_leaf *__restrict__ lin, int64_t n, 
     for (int v = 0; v < 8; ++v) {
         int64_t X, Y, Z;
         leaf_corner(L, v, K, X, Y, Z);
-        f[v] = uphi[bit_rank(bm, woff, lat_bit(lat, X, Y, Z))];
+        const int64_t u = bit_rank(bm, woff, lat_bit(lat, X, Y, Z));
+        if (ovf && u >= ucap) {
+            atomicOr(ovf, 1u);
+            f[v] = 0.0;
+        } else {
+            f[v] = uphi[u];
+        }
     }
     classify(L, f, c);
     lout[q] = L;
@@ -370,51 +388,54 @@ hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStre
 }
 
 hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
-                              unsigned long long *bm, hipStream_t s) {
+                              unsigned long long *bm, hipStream_t s, const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, K, gt, bm);
+    hipLaunchKernelGGL(k_corner_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, K, gt, bm, nd);
     return hipGetLastError();
 }
 
 hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
                                const uint64_t *bm, const int32_t *woff, double *upts,
-                               int32_t *uconf, hipStream_t s) {
+                               int32_t *uconf, hipStream_t s, const int64_t *nd, int64_t ucap,
+                               unsigned *ovf) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_corner_write, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, gt, bm,
-                       woff, upts, uconf);
+                       woff, upts, uconf, nd, ucap, ovf);
     return hipGetLastError();
 }
 
 hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Grid *gt,
                                    const uint64_t *bm, const int32_t *woff, const double *uphi,
-                                   double c, tms_leaf *lout, double *cphi, hipStream_t s) {
+                                   double c, tms_leaf *lout, double *cphi, hipStream_t s,
+                                   const int64_t *nd, int64_t ucap, unsigned *ovf) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_corner_gather_bm, dim3(nblk(n)), dim3(kBS), 0, s, lin, n, K, gt, bm, woff,
-                       uphi, c, lout, cphi);
+                       uphi, c, lout, cphi, nd, ucap, ovf);
     return hipGetLastError();
 }
 
 hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision, const double *pts,
                              int64_t m, const int32_t *cs, const double *ax, const double *ay,
                              const double *az, const double *aw, double band_rel, double *phi,
-                             double *grad, uint8_t *guard, hipStream_t s) {
+                             double *grad, uint8_t *guard, hipStream_t s, const int32_t *nd) {
     if (m <= 0) return hipSuccess;
     if (precision == TMS_PREC_FP32_GUARD)
         hipLaunchKernelGGL(k_phi_points<true>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
-                           cs, ax, ay, az, aw, band_rel, phi, grad, guard);
+                           cs, ax, ay, az, aw, band_rel, phi, grad, guard, nd);
     else
         hipLaunchKernelGGL(k_phi_points<false>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
-                           cs, ax, ay, az, aw, 0.0, phi, grad, nullptr);
+                           cs, ax, ay, az, aw, 0.0, phi, grad, nullptr, nd);
     return hipGetLastError();
 }
 
 hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
                                     const int32_t *list, int64_t m, const int32_t *cs,
                                     const double *ax, const double *ay, const double *az,
-                                    const double *aw, double *phi, double *grad, hipStream_t s) {
+                                    const double *aw, double *phi, double *grad, hipStream_t s,
+                                    const int32_t *nd) {
     if (m <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, list, m, cs, ax,
-                       ay, az, aw, phi, grad);
+                       ay, az, aw, phi, grad, nd);
     return hipGetLastError();
 }
 
@@ -477,9 +498,10 @@ hipError_t launch_count_u8(const uint8_t *v, int64_t n, uint8_t value, unsigned 
     return hipGetLastError();
 }
 
-hipError_t launch_guard_flags_u8(const uint8_t *gd, int64_t n, int32_t *flags, hipStream_t s) {
+hipError_t launch_guard_flags_u8(const uint8_t *gd, int64_t n, int32_t *flags, hipStream_t s,
+                                 const int32_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flags_u8, dim3(nblk(n)), dim3(kBS), 0, s, gd, n, flags);
+    hipLaunchKernelGGL(k_flags_u8, dim3(nblk(n)), dim3(kBS), 0, s, gd, n, nd, flags);
     return hipGetLastError();
 }
 
@@ -491,10 +513,10 @@ hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
 }
 
 hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
-                                unsigned long long *part, hipStream_t s) {
+                                unsigned long long *part, hipStream_t s, const int64_t *nd) {
     if (n <= 0) return hipSuccess;
     const int nb = (int)std::min<int64_t>(1024, (n + kBS - 1) / kBS);
-    hipLaunchKernelGGL(k_count_surface, dim3(nb), dim3(kBS), 0, s, leaves, n, part);
+    hipLaunchKernelGGL(k_count_surface, dim3(nb), dim3(kBS), 0, s, leaves, n, nd, part);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBS), 0, s, part, nb, count);
     return hipGetLastError();
 }

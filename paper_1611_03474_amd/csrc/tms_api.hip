@@ -94,6 +94,21 @@ void timing_flush(tms_ctx *ctx) {
 
 }  // namespace tms
 
+void tms_graph_state::release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    exec = nullptr;
+    graph = nullptr;
+    cap_stream = nullptr;
+    cells_id = 0;
+    tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
+                        &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
+                        &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
+                        &stmp, &seg};
+    for (auto *x : b) x->release();
+}
+
 void tms_cells::release() {
     gtab.release();
     aoff.release();
@@ -521,6 +536,7 @@ int32_t tms_destroy(tms_ctx *ctx) {
                            &ctx->ctmp, &ctx->counters, &ctx->hostpin, &ctx->hidx, &ctx->chunks,
                            &ctx->runs};
     for (auto *b : bufs) b->release();
+    ctx->graph.release();
     timing_flush(ctx);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
@@ -778,6 +794,282 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
     return TMS_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Captured pass: the whole partition (roots, every level, guard re-runs,
+// compaction, batch regrouping), corner stage and edge extraction recorded
+// once into a HIP graph.  Every size the eager pass reads back stays on the
+// device; launches are sized by capacities planned from an eager pass of the
+// same cells, and the kernels read their actual counts on the device.  A
+// count beyond its capacity sets an overflow flag (nothing is written out of
+// bounds) and the replay reports TMS_E_CAPACITY.
+// ---------------------------------------------------------------------------
+
+// device size slots (int32 unless noted)
+constexpr int kSzNq = 0;        // [K + 2] queue entries per level
+constexpr int kSzNl = 16;       // [K + 1] leaves per level
+constexpr int kSzRuns = 32, kSzChunks = 33, kSzNu = 35, kSzNgp = 36, kSzNv = 37;
+constexpr int kSzNg = 40;       // [K + 1] guarded cubes per level
+constexpr int kSzSlices = 64;   // [kMaxSlices] entries of each slice
+constexpr int kSzGSlices = 64 + (int)kMaxSlices;  // [kMaxSlices] guard-list slices
+constexpr int kSz64 = 1024;     // int64 region: [0] leaves, [1] overflow, [8..) offsets
+// counter slots (u64)
+constexpr int kCtPairs = 0;     // [64 * lev, +64) pair counts of level lev
+constexpr int kCtHisto = 1024;  // [8 lev, +5) decision histogram of level lev
+constexpr int kCtHard = 2048;   // [2 kMaxSlices lev + k] hard-list lengths (guard after)
+constexpr int kCtSurf = 6144;
+constexpr int kCtPart = 8192;   // [5 * 1024] reduction partials
+constexpr int kCtSlots = kCtPart + 5 * 1024;
+
+void cells_buffers(const tms_cells *c, const void *p[8]) {
+    p[0] = c->ax.p;
+    p[1] = c->ay.p;
+    p[2] = c->az.p;
+    p[3] = c->aw.p;
+    p[4] = c->cell_start.p;
+    p[5] = c->root_start.p;
+    p[6] = c->root_atoms.p;
+    p[7] = c->gtab.p;
+}
+
+// Capacities and private buffers of a capture of `cells`, from the eager
+// pass kept in ctx (its counts times `margin`).
+int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
+    tms_graph_state &G = ctx->graph;
+    const Grid &g = cells->g;
+    const tms_stats &st = ctx->last_stats;
+    auto grow = [&](int64_t v) { return (int64_t)std::ceil((double)v * margin) + 4096; };
+    G.nlev = g.K + 1;
+    G.nconf = cells->nconf;
+    G.qcap[0] = std::max<int64_t>(cells->nroots, 1);
+    for (int l = 1; l <= g.K; ++l) G.qcap[l] = grow(st.n_est[l]);
+    G.qcap[g.K + 1] = 0;
+    G.lcap = grow(st.n_leaves);
+    G.ucap = grow(st.n_corners);
+    G.vcap = grow(ctx->n_verts);
+    int64_t qmax = 1, smax = 1;
+    for (int l = 0; l <= g.K; ++l) {
+        const int64_t S0 = std::max<int64_t>(4096, ctx->slice_cubes);
+        G.nslices[l] = (G.qcap[l] + S0 - 1) / S0;
+        if (G.nslices[l] > kMaxSlices) return fail(ctx, TMS_E_INVALID, "capture: level too large for the slice size");
+        G.slice[l] = (G.qcap[l] + G.nslices[l] - 1) / G.nslices[l];
+        qmax = std::max(qmax, G.qcap[l]);
+        smax = std::max(smax, G.slice[l]);
+    }
+    // edge lattices, as the eager extraction lays them out
+    std::vector<EdgeLat> et((size_t)G.nconf);
+    std::vector<int64_t> fw((size_t)G.nconf);
+    int64_t ewords = 0;
+    double ebits = 0.0;
+    for (int b = 0; b < G.nconf; ++b) {
+        const Grid &gb = cells->gh[(size_t)b];
+        fw[(size_t)b] = ewords;
+        for (int lev = 0; lev <= g.K; ++lev)
+            for (int a = 0; a < 3; ++a) {
+                Lat &l = et[(size_t)b].l[lev][a];
+                double bits = 1.0;
+                for (int k = 0; k < 3; ++k) {
+                    l.n[k] = ((int64_t)gb.nr[k] << lev) + 1;
+                    bits *= (double)l.n[k];
+                }
+                l.base = ewords;
+                ewords += (int64_t)((bits + 63.0) / 64.0);
+                ebits += bits;
+            }
+        et[(size_t)b].words = ewords - fw[(size_t)b];
+    }
+    const int64_t cwords = cells->corner_words;
+    G.ewords = ewords;
+    if (64.0 * (double)cwords > kMaxBitmapBits || ebits > kMaxBitmapBits ||
+        cwords >= (int64_t)0x7FFFFFFF || ewords >= (int64_t)0x7FFFFFFF)
+        return fail(ctx, TMS_E_INVALID, "capture needs the dense corner and edge bitmaps");
+    const int64_t nmax = std::max({qmax, G.ucap, cells->nroots + 1, (int64_t)1});
+    HIPCK(G.q[0].ensure(sizeof(int4) * (size_t)qmax));
+    HIPCK(G.q[1].ensure(sizeof(int4) * (size_t)qmax));
+    HIPCK(G.dec.ensure((size_t)qmax));
+    HIPCK(G.abuf.ensure(sizeof(double) * 64 * (size_t)smax));
+    HIPCK(G.ebuf.ensure(sizeof(double) * (size_t)smax));
+    HIPCK(G.hidx.ensure(sizeof(int32_t) * (size_t)smax));
+    HIPCK(G.flags.ensure(4 * (size_t)nmax));
+    HIPCK(G.scan_a.ensure(4 * (size_t)nmax));
+    HIPCK(G.scan_b.ensure(4 * (size_t)nmax));
+    HIPCK(G.idx.ensure(4 * (size_t)nmax));
+    HIPCK(G.runs.ensure(4 * (size_t)smax));
+    HIPCK(G.chunks.ensure(sizeof(int2) * (size_t)smax));
+    HIPCK(G.leaves.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
+    HIPCK(G.lsort.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
+    HIPCK(G.cphi.ensure(sizeof(double) * 8 * (size_t)G.lcap));
+    HIPCK(G.bmap.ensure(sizeof(uint64_t) * (size_t)cwords));
+    HIPCK(G.bmcnt.ensure(4 * (size_t)cwords));
+    HIPCK(G.bmoff.ensure(4 * (size_t)cwords));
+    HIPCK(G.uniq.ensure(sizeof(double) * 3 * (size_t)G.ucap));
+    HIPCK(G.uphi.ensure(sizeof(double) * (size_t)G.ucap));
+    HIPCK(G.uconf.ensure(4 * (size_t)G.ucap));
+    HIPCK(G.uguard.ensure((size_t)G.ucap));
+    HIPCK(G.ebmap.ensure(sizeof(uint64_t) * (size_t)ewords));
+    HIPCK(G.ebcnt.ensure(4 * (size_t)ewords));
+    HIPCK(G.eboff.ensure(4 * (size_t)ewords));
+    HIPCK(G.verts.ensure(sizeof(tms_vertex) * (size_t)G.vcap));
+    HIPCK(G.etab.ensure(sizeof(EdgeLat) * (size_t)G.nconf + sizeof(int64_t) * (size_t)G.nconf));
+    HIPCK(G.sz.ensure(sizeof(int32_t) * kSz64 + sizeof(int64_t) * (size_t)(16 + 2 * (G.nconf + 1))));
+    HIPCK(G.ctr.ensure(sizeof(unsigned long long) * kCtSlots));
+    HIPCK(G.stmp.ensure(scan_tmp_bytes(std::max(nmax, std::max(cwords, ewords))) + 512));
+    HIPCK(G.seg.ensure(sizeof(int64_t) * 2 * (size_t)(G.nlev * G.nconf)));
+    hipStream_t s = ctx->stream;
+    HIPCK(hipMemsetAsync(G.q[0].p, 0, G.q[0].cap, s));
+    HIPCK(hipMemsetAsync(G.q[1].p, 0, G.q[1].cap, s));
+    HIPCK(hipMemcpyAsync(G.etab.p, et.data(), sizeof(EdgeLat) * (size_t)G.nconf,
+                         hipMemcpyHostToDevice, s));
+    HIPCK(hipMemcpyAsync(G.etab.as<EdgeLat>() + G.nconf, fw.data(), sizeof(int64_t) * (size_t)G.nconf,
+                         hipMemcpyHostToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
+    return TMS_OK;
+}
+
+// Enqueue the whole pass on stream s with device-side sizes only.
+int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
+    tms_graph_state &G = ctx->graph;
+    const Grid &g = cells->g;
+    const Grid *gt = cells->gtab.as<Grid>();
+    const int prec = cells->p.precision, nconf = cells->nconf, K = g.K;
+    int32_t *sz = G.sz.as<int32_t>();
+    int32_t *nq = sz + kSzNq, *nl = sz + kSzNl;
+    int32_t *nruns = sz + kSzRuns, *nchunks = sz + kSzChunks;
+    int32_t *nu = sz + kSzNu, *ngp = sz + kSzNgp, *nv = sz + kSzNv;
+    int32_t *ns = sz + kSzSlices, *ngs = sz + kSzGSlices;
+    int64_t *s64 = reinterpret_cast<int64_t *>(sz + kSz64);
+    int64_t *Ld = s64;
+    unsigned *ovf = reinterpret_cast<unsigned *>(s64 + 1);
+    int64_t *leaf_off = s64 + 16, *vert_off = leaf_off + (nconf + 1);
+    unsigned long long *ctr = G.ctr.as<unsigned long long>();
+    const int32_t *rs = cells->root_start.as<int32_t>(), *ra = cells->root_atoms.as<int32_t>();
+    const double *ax = cells->ax.as<double>(), *ay = cells->ay.as<double>(),
+                 *az = cells->az.as<double>(), *aw = cells->aw.as<double>();
+    int32_t *flags = G.flags.as<int32_t>(), *sa = G.scan_a.as<int32_t>(),
+            *sb = G.scan_b.as<int32_t>(), *idx = G.idx.as<int32_t>();
+    void *tmp = G.stmp.p;
+    uint8_t *dec = G.dec.as<uint8_t>();
+    // sizes and counters start at zero (fill kernels: the graph holds no memset nodes)
+    HIPCK(launch_fill_u32(reinterpret_cast<uint32_t *>(sz), 0u, (int64_t)(G.sz.cap / 4), s));
+    HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(ctr), 0ull, kCtSlots, s));
+    // Q_0
+    const int64_t nr = cells->nroots;
+    HIPCK(launch_roots_flags(rs, nr, flags, s));
+    HIPCK(exclusive_scan(flags, sa, nr, nq + 0, tmp, s));
+    HIPCK(launch_roots_emit(gt, nconf, flags, sa, nr, G.q[0].as<int4>(), s));
+    for (int lev = 0; lev <= K; ++lev) {
+        const int cur = lev & 1;
+        const int4 *q = G.q[cur].as<int4>();
+        const int64_t QC = G.qcap[lev], S = G.slice[lev];
+        const int nsl = (int)G.nslices[lev];
+        const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
+        HIPCK(launch_slice_counts(nq + lev, S, nsl, ns, s));
+        for (int k = 0; k < nsl; ++k) {
+            const int64_t off = (int64_t)k * S, cap = std::min(S, QC - off);
+            unsigned *hard = reinterpret_cast<unsigned *>(ctr + kCtHard + 2 * kMaxSlices * lev + k);
+            const int2 *chunks = nullptr;
+            const int32_t *ncount = ns + k;
+            if (tiled) {
+                HIPCK(launch_run_flags(gt, lev, q + off, nullptr, cap, flags, s, ns + k));
+                HIPCK(exclusive_scan(flags, sa, cap, nruns, tmp, s));
+                HIPCK(launch_run_starts(flags, sa, cap, G.runs.as<int32_t>(), s));
+                HIPCK(launch_run_chunk_counts(G.runs.as<int32_t>(), cap, cap, flags, s, nruns,
+                                              ns + k));
+                HIPCK(exclusive_scan(flags, sb, cap, nchunks, tmp, s));
+                HIPCK(launch_run_chunk_emit(G.runs.as<int32_t>(), cap, cap, sb, G.chunks.as<int2>(),
+                                            s, nruns, ns + k));
+                chunks = G.chunks.as<int2>();
+                ncount = nchunks;
+            }
+            HIPCK(launch_estimate_decide(g, gt, lev, prec, q + off, cap, nullptr, chunks, cap, rs, ra,
+                                         ax, ay, az, aw, dec + off, G.abuf.as<double>(),
+                                         G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
+                                         reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
+                                         ctx->tile_atoms, s, ncount));
+            HIPCK(launch_bound(g, lev, prec, cap, dec + off, G.abuf.as<double>(),
+                               G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
+        }
+        if (prec == TMS_PREC_FP32_GUARD) {
+            int32_t *ng = sz + kSzNg + lev;
+            HIPCK(launch_guard_list_flags(dec, QC, flags, s, nq + lev));
+            HIPCK(exclusive_scan(flags, sa, QC, ng, tmp, s));
+            HIPCK(launch_guard_list_emit(flags, sa, QC, idx, s));
+            HIPCK(launch_slice_counts(ng, S, nsl, ngs, s));
+            for (int k = 0; k < nsl; ++k) {
+                const int64_t off = (int64_t)k * S, cap = std::min(S, QC - off);
+                unsigned *hard = reinterpret_cast<unsigned *>(ctr + kCtHard + 2 * kMaxSlices * lev +
+                                                              kMaxSlices + k);
+                HIPCK(launch_estimate_decide(g, gt, lev, TMS_PREC_FP64, q, cap, idx + off, nullptr,
+                                             0, rs, ra, ax, ay, az, aw, dec, G.abuf.as<double>(),
+                                             G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
+                                             nullptr, ctx->tile_atoms, s, ngs + k));
+                HIPCK(launch_bound(g, lev, TMS_PREC_FP64, cap, dec, G.abuf.as<double>(),
+                                   G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
+            }
+        }
+        HIPCK(launch_level_histo(dec, QC, ctr + kCtHisto + 8 * lev, ctr + kCtPart, s, nq + lev));
+        HIPCK(launch_level_counts(dec, QC, flags, idx, s, nq + lev));
+        HIPCK(exclusive_scan(flags, sa, QC, nl + lev, tmp, s));
+        HIPCK(exclusive_scan(idx, sb, QC, nq + lev + 1, tmp, s));
+        HIPCK(launch_level_emit(q, dec, QC, lev, sa, sb, G.leaves.as<tms_leaf>(), 0,
+                                G.q[cur ^ 1].as<int4>(), s, nq + lev, Ld, G.lcap, G.qcap[lev + 1],
+                                ovf));
+        HIPCK(launch_acc_i64(Ld, nl + lev, s));
+        HIPCK(launch_stop_on_overflow(ovf, nq + lev + 1, s));
+    }
+    // regrouping by conformation (and the per-conformation leaf offsets)
+    const int nseg = G.nlev * nconf;
+    int64_t *seg_src = G.seg.as<int64_t>(), *seg_dst = seg_src + nseg;
+    HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(seg_src), ~0ull, nseg, s));
+    HIPCK(launch_leaf_seg_heads(G.leaves.as<tms_leaf>(), G.lcap, nconf, seg_src, s, Ld));
+    HIPCK(launch_seg_plan(seg_src, G.nlev, nconf, Ld, G.lcap, seg_dst, leaf_off, s));
+    tms_leaf *lv = G.leaves.as<tms_leaf>();
+    G.leaves_in_lsort = false;
+    if (nconf > 1) {
+        HIPCK(launch_leaf_seg_move(G.leaves.as<tms_leaf>(), G.lcap, nconf, seg_src, seg_dst,
+                                   G.lsort.as<tms_leaf>(), s, Ld));
+        lv = G.lsort.as<tms_leaf>();
+        G.leaves_in_lsort = true;
+    }
+    // corners: dense bitmap, phi once per corner (exact recomputation near c
+    // and inside the guard band), classes
+    const int64_t cw = cells->corner_words;
+    HIPCK(launch_fill_u64(G.bmap.as<uint64_t>(), 0ull, cw, s));
+    HIPCK(launch_corner_mark(lv, G.lcap, K, gt, G.bmap.as<unsigned long long>(), s, Ld));
+    HIPCK(launch_popc(G.bmap.as<uint64_t>(), cw, G.bmcnt.as<int32_t>(), s));
+    HIPCK(exclusive_scan(G.bmcnt.as<int32_t>(), G.bmoff.as<int32_t>(), cw, nu, tmp, s));
+    HIPCK(launch_corner_write(lv, G.lcap, K, gt, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(),
+                              G.uniq.as<double>(), G.uconf.as<int32_t>(), s, Ld, G.ucap, ovf));
+    const bool fast = prec == TMS_PREC_FP32_GUARD;
+    HIPCK(launch_phi_points(gt, G.uconf.as<int32_t>(), prec, G.uniq.as<double>(), G.ucap,
+                            cells->cell_start.as<int32_t>(), ax, ay, az, aw, kCornerBand,
+                            G.uphi.as<double>(), nullptr, fast ? G.uguard.as<uint8_t>() : nullptr, s,
+                            nu));
+    if (fast) {
+        HIPCK(launch_guard_flags_u8(G.uguard.as<uint8_t>(), G.ucap, flags, s, nu));
+        HIPCK(exclusive_scan(flags, sa, G.ucap, ngp, tmp, s));
+        HIPCK(launch_list_emit(flags, sa, G.ucap, idx, s));
+        HIPCK(launch_phi_points_subset(gt, G.uconf.as<int32_t>(), G.uniq.as<double>(), idx, G.ucap,
+                                       cells->cell_start.as<int32_t>(), ax, ay, az, aw,
+                                       G.uphi.as<double>(), nullptr, s, ngp));
+    }
+    HIPCK(launch_corner_gather_bm(lv, G.lcap, K, gt, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(),
+                                  G.uphi.as<double>(), g.c, lv, G.cphi.as<double>(), s, Ld, G.ucap,
+                                  ovf));
+    HIPCK(launch_count_surface(lv, G.lcap, ctr + kCtSurf, ctr + kCtPart, s, Ld));
+    // edge points: bitmaps in key order, one rank per edge
+    const EdgeLat *et = G.etab.as<EdgeLat>();
+    const int64_t *fw = reinterpret_cast<const int64_t *>(et + nconf);
+    const int64_t ew = G.ewords;
+    HIPCK(launch_fill_u64(G.ebmap.as<uint64_t>(), 0ull, ew, s));
+    HIPCK(launch_edge_mark(lv, G.lcap, et, G.ebmap.as<unsigned long long>(), s, Ld));
+    HIPCK(launch_popc(G.ebmap.as<uint64_t>(), ew, G.ebcnt.as<int32_t>(), s));
+    HIPCK(exclusive_scan(G.ebcnt.as<int32_t>(), G.eboff.as<int32_t>(), ew, nv, tmp, s));
+    HIPCK(launch_edge_write(gt, lv, G.cphi.as<double>(), G.lcap, et, G.ebmap.as<uint64_t>(),
+                            G.eboff.as<int32_t>(), G.verts.as<tms_vertex>(), s, Ld, G.vcap, ovf));
+    HIPCK(launch_gather_i32(G.eboff.as<int32_t>(), fw, nconf, vert_off, s));
+    return TMS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1051,6 +1343,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
     st.n_leaves = L;
     st.n_surface = (int64_t)ns;
     ctx->n_leaves = L;
+    ctx->last_stats = st;
+    ctx->last_stats_cells = cells->id;
     if (stats) *stats = st;
     *n_leaves = L;
     if (!leaves_out) return TMS_OK;
@@ -1337,6 +1631,137 @@ int32_t tms_batch_counts(tms_ctx *ctx, const tms_cells *cells, int64_t *leaf_off
             return fail(ctx, TMS_E_INVALID, "no kept per-conformation vertex offsets of these cells");
         std::copy(ctx->vert_off.begin(), ctx->vert_off.end(), vertex_offsets);
     }
+    return TMS_OK;
+}
+
+int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    if (cells->p.mode != TMS_MODE_ADAPTIVE)
+        return fail(ctx, TMS_E_INVALID, "capture takes cells built in adaptive mode");
+    if (!(margin >= 1.0 && margin <= 64.0))
+        return fail(ctx, TMS_E_INVALID, "margin must lie in [1, 64]");
+    if (ctx->last_stats_cells != cells->id || ctx->edge_cells != cells->id)
+        return fail(ctx, TMS_E_INVALID,
+                    "capture is sized from an eager tms_partition_estimate and "
+                    "tms_extract_cube_vertices of the same cells; run them first");
+    HIPCK(hipSetDevice(ctx->device));
+    tms_graph_state &G = ctx->graph;
+    G.release();
+    int32_t rc = plan_graph(ctx, cells, margin);
+    if (rc) {
+        G.release();
+        return rc;
+    }
+    HIPCK(hipStreamCreateWithFlags(&G.cap_stream, hipStreamNonBlocking));
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    hipError_t e = hipStreamBeginCapture(G.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        ctx->timing = timing;
+        G.release();
+        return hip_fail(ctx, e, "hipStreamBeginCapture");
+    }
+    rc = record_pass(ctx, cells, G.cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(G.cap_stream, &graph);
+    ctx->timing = timing;
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        G.release();
+        return rc ? rc : hip_fail(ctx, e, "hipStreamEndCapture");
+    }
+    G.graph = graph;
+    e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        G.release();
+        return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    G.cells_id = cells->id;
+    G.gh = cells->gh;
+    cells_buffers(cells, G.cells_buf);
+    return TMS_OK;
+}
+
+int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
+                         double *corner_phi, int64_t leaf_cap, int64_t *n_leaves,
+                         tms_vertex *verts, int64_t vert_cap, int64_t *n_verts,
+                         int64_t *leaf_offsets, int64_t *vertex_offsets, tms_stats *stats) {
+    if (!ctx) return TMS_E_INVALID;
+    tms_graph_state &G = ctx->graph;
+    if (!G.exec) return fail(ctx, TMS_E_INVALID, "no captured pass (tms_graph_capture)");
+    if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    if (cells->id != G.cells_id) {
+        // a rebuild keeps the graph valid when geometry and buffers are unchanged
+        const void *p[8];
+        cells_buffers(cells, p);
+        bool same = cells->gh.size() == G.gh.size() &&
+                    memcmp(cells->gh.data(), G.gh.data(), sizeof(Grid) * G.gh.size()) == 0;
+        for (int k = 0; k < 8 && same; ++k) same = p[k] == G.cells_buf[k];
+        if (!same)
+            return fail(ctx, TMS_E_INVALID,
+                        "cells changed geometry or buffers since the capture; capture again");
+    }
+    HIPCK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    HIPCK(hipGraphLaunch(G.exec, s));
+    const int nconf = G.nconf, K = G.nlev - 1;
+    std::vector<int32_t> hs(kSz64);
+    std::vector<int64_t> h64((size_t)(16 + 2 * (nconf + 1)));
+    std::vector<unsigned long long> hc(kCtSurf + 1);
+    HIPCK(hipMemcpyAsync(hs.data(), G.sz.p, sizeof(int32_t) * kSz64, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(h64.data(), G.sz.as<int32_t>() + kSz64, sizeof(int64_t) * h64.size(),
+                         hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(hc.data(), G.ctr.p, sizeof(unsigned long long) * hc.size(),
+                         hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    const int64_t L = h64[0];
+    const int64_t nv = hs[kSzNv];
+    if (n_leaves) *n_leaves = L;
+    if (n_verts) *n_verts = nv;
+    if ((h64[1] & 0xFFFFFFFFll) != 0)
+        return fail(ctx, TMS_E_CAPACITY,
+                    "a count exceeded the captured capacity; capture again with a larger margin");
+    tms_stats st;
+    memset(&st, 0, sizeof st);
+    for (int l = 0; l <= K; ++l) {
+        st.n_est[l] = hs[kSzNq + l];
+        const unsigned long long *h = hc.data() + kCtHisto + 8 * l;
+        st.n_disc[l] = (int64_t)h[DEC_DISCARD];
+        st.n_refine[l] = (int64_t)h[DEC_REFINE];
+        st.n_conv[l] = (int64_t)h[DEC_CONV];
+        st.n_hmin[l] = (int64_t)h[DEC_HMIN];
+        for (int k = 0; k < 64; ++k) st.n_pairs_lvl[l] += (int64_t)hc[kCtPairs + 64 * l + k];
+        st.n_pairs += st.n_pairs_lvl[l];
+        for (int k = 0; k < 2 * kMaxSlices; ++k)
+            st.n_bound += (int64_t)(hc[kCtHard + 2 * kMaxSlices * l + k] & 0xFFFFFFFFull);
+        st.guard_cubes += hs[kSzNg + l];
+    }
+    st.n_leaves = L;
+    st.n_surface = (int64_t)hc[kCtSurf];
+    st.n_corners = hs[kSzNu];
+    st.guard_points = cells->p.precision == TMS_PREC_FP32_GUARD ? hs[kSzNgp] : 0;
+    if (stats) *stats = st;
+    if (leaf_offsets) std::copy(h64.begin() + 16, h64.begin() + 16 + nconf + 1, leaf_offsets);
+    if (vertex_offsets) {
+        std::copy(h64.begin() + 16 + nconf + 1, h64.begin() + 16 + 2 * nconf + 1, vertex_offsets);
+        vertex_offsets[nconf] = nv;
+    }
+    if ((leaves && leaf_cap < L) || (verts && vert_cap < nv))
+        return fail(ctx, TMS_E_CAPACITY, "output capacity too small (%lld leaves, %lld vertices)",
+                    (long long)L, (long long)nv);
+    const tms_leaf *lsrc = G.leaves_in_lsort ? G.lsort.as<tms_leaf>() : G.leaves.as<tms_leaf>();
+    if (leaves && L > 0)
+        HIPCK(hipMemcpyAsync(leaves, lsrc, sizeof(tms_leaf) * (size_t)L, hipMemcpyDeviceToDevice, s));
+    if (corner_phi && L > 0)
+        HIPCK(hipMemcpyAsync(corner_phi, G.cphi.p, sizeof(double) * 8 * (size_t)L,
+                             hipMemcpyDeviceToDevice, s));
+    if (verts && nv > 0)
+        HIPCK(hipMemcpyAsync(verts, G.verts.p, sizeof(tms_vertex) * (size_t)nv,
+                             hipMemcpyDeviceToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
     return TMS_OK;
 }
 

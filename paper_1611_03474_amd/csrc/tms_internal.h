@@ -117,6 +117,25 @@ struct tms_cells {
     void release();
 };
 
+// A pass recorded once into a HIP graph with every size kept on the device
+// (capacity-sized launches), replayed without host round trips.
+struct tms_graph_state {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    uint64_t cells_id = 0;          // cells build the graph was recorded for
+    const void *cells_buf[8] = {};  // their device buffers (a rebuild must keep them)
+    std::vector<tms::Grid> gh;      // and their geometry
+    int nlev = 0, nconf = 1;
+    int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0;
+    int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
+    tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
+        lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, verts,
+        etab, sz, ctr, stmp, seg;
+    bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
+    void release();
+};
+
 struct tms_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -139,6 +158,10 @@ struct tms_ctx {
     // batch bookkeeping of the last partition / extraction: per-conformation
     // leaf and vertex offsets ([nconf + 1] each)
     std::vector<int64_t> leaf_off, vert_off;
+    // counters of the last partition (sizes the capture), and the capture
+    tms_stats last_stats{};
+    uint64_t last_stats_cells = 0;
+    tms_graph_state graph;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
         slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs, bmap, bmcnt, bmoff;
@@ -208,6 +231,14 @@ hipError_t launch_adjoint_atoms(const Grid &g, int precision, const Lat &lat, co
                                 const double *aw, const double *ar, const int32_t *aidx,
                                 double *out, hipStream_t s);
 
+// k_graph.hip
+hipError_t launch_slice_counts(const int32_t *n, int64_t S, int nslices, int32_t *ns,
+                               hipStream_t s);
+hipError_t launch_acc_i64(int64_t *acc, const int32_t *v, hipStream_t s);
+hipError_t launch_seg_plan(const int64_t *src, int nlev, int nconf, const int64_t *L, int64_t lcap,
+                           int64_t *dst, int64_t *leaf_off, hipStream_t s);
+hipError_t launch_stop_on_overflow(const unsigned *ovf, int32_t *n, hipStream_t s);
+
 // k_scan.hip -- exclusive scan of int32 values into int32 offsets; total
 // written to *total_dev (device).  tmp must hold scan_tmp_bytes(n).
 size_t scan_tmp_bytes(int64_t n);
@@ -241,33 +272,41 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *ax, const double *ay, const double *az,
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
-                                  int tile_atoms, hipStream_t s);
+                                  int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr);
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s);
+// Trailing device-count arguments (nd: count on the device, n then a
+// capacity that sizes the launch) are for the capture path; null elsewhere.
 hipError_t launch_run_flags(const Grid *gt, int level, const int4 *q, const int32_t *subset,
-                            int64_t n, int32_t *f, hipStream_t s);
+                            int64_t n, int32_t *f, hipStream_t s, const int32_t *nd = nullptr);
 hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, int32_t *starts,
                              hipStream_t s);
 hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
-                                   hipStream_t s);
+                                   hipStream_t s, const int32_t *nrd = nullptr,
+                                   const int32_t *nd = nullptr);
 hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n,
-                                 const int32_t *coff, int2 *chunks, hipStream_t s);
-hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s);
+                                 const int32_t *coff, int2 *chunks, hipStream_t s,
+                                 const int32_t *nrd = nullptr, const int32_t *nd = nullptr);
+hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s,
+                                   const int32_t *nd = nullptr);
 hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
                                   int32_t *list, hipStream_t s);
 hipError_t launch_level_counts(const uint8_t *dec, int64_t n, int32_t *leaf_cnt,
-                               int32_t *child_cnt, hipStream_t s);
+                               int32_t *child_cnt, hipStream_t s, const int32_t *nd = nullptr);
 hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int level,
                              const int32_t *leaf_off, const int32_t *child_off, tms_leaf *leaves,
-                             int64_t leaf_base, int4 *qnext, hipStream_t s);
+                             int64_t leaf_base, int4 *qnext, hipStream_t s,
+                             const int32_t *nd = nullptr, const int64_t *leaf_base_dev = nullptr,
+                             int64_t leaf_cap = 0, int64_t queue_cap = 0, unsigned *ovf = nullptr);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
-                              unsigned long long *part, hipStream_t s);
+                              unsigned long long *part, hipStream_t s, const int32_t *nd = nullptr);
 // regrouping of a batch's leaves by conformation (segments level * nconf + conf)
 hipError_t launch_leaf_seg_heads(const tms_leaf *leaves, int64_t n, int nconf, int64_t *src,
-                                 hipStream_t s);
+                                 hipStream_t s, const int64_t *nd = nullptr);
 hipError_t launch_leaf_seg_move(const tms_leaf *leaves, int64_t n, int nconf, const int64_t *src,
-                                const int64_t *dst, tms_leaf *out, hipStream_t s);
+                                const int64_t *dst, tms_leaf *out, hipStream_t s,
+                                const int64_t *nd = nullptr);
 hipError_t launch_bound_debug(const double *A, const double *band, int64_t n, double *out,
                               hipStream_t s);
 hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStream_t s);
@@ -277,11 +316,13 @@ hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStrea
 hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision, const double *pts,
                              int64_t m, const int32_t *cell_start, const double *ax,
                              const double *ay, const double *az, const double *aw, double band_rel,
-                             double *phi, double *grad, uint8_t *guard, hipStream_t s);
+                             double *phi, double *grad, uint8_t *guard, hipStream_t s,
+                             const int32_t *nd = nullptr);
 hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
                                     const int32_t *list, int64_t m, const int32_t *cell_start,
                                     const double *ax, const double *ay, const double *az,
-                                    const double *aw, double *phi, double *grad, hipStream_t s);
+                                    const double *aw, double *phi, double *grad, hipStream_t s,
+                                    const int32_t *nd = nullptr);
 hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                                 uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
 hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_t ncand,
@@ -298,31 +339,37 @@ hipError_t launch_uniform_gather(const Grid &g, const double *uphi, double c, tm
                                  int64_t n, double *corner_phi, hipStream_t s);
 hipError_t launch_count_u8(const uint8_t *v, int64_t n, uint8_t value,
                            unsigned long long *count, hipStream_t s);
-hipError_t launch_guard_flags_u8(const uint8_t *g, int64_t n, int32_t *flags, hipStream_t s);
+hipError_t launch_guard_flags_u8(const uint8_t *g, int64_t n, int32_t *flags, hipStream_t s,
+                                 const int32_t *nd = nullptr);
 hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
                             hipStream_t s);
 hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
-                                unsigned long long *part, hipStream_t s);
+                                unsigned long long *part, hipStream_t s,
+                                const int64_t *nd = nullptr);
 
 // bitmap helpers (k_phi.hip)
 hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStream_t s);
 // corner bitmap: conformation L.conf owns the words of gt[L.conf].clat
 hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
-                              unsigned long long *bm, hipStream_t s);
+                              unsigned long long *bm, hipStream_t s, const int64_t *nd = nullptr);
 hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
                                const uint64_t *bm, const int32_t *woff, double *upts,
-                               int32_t *uconf, hipStream_t s);
+                               int32_t *uconf, hipStream_t s, const int64_t *nd = nullptr,
+                               int64_t ucap = 0, unsigned *ovf = nullptr);
 hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Grid *gt,
                                    const uint64_t *bm, const int32_t *woff, const double *uphi,
-                                   double c, tms_leaf *lout, double *cphi, hipStream_t s);
+                                   double c, tms_leaf *lout, double *cphi, hipStream_t s,
+                                   const int64_t *nd = nullptr, int64_t ucap = 0,
+                                   unsigned *ovf = nullptr);
 
 // k_extract.hip
 // et: device table of edge lattices, one per conformation
 hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
-                            unsigned long long *bm, hipStream_t s);
+                            unsigned long long *bm, hipStream_t s, const int64_t *nd = nullptr);
 hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
                              const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
-                             tms_vertex *out, hipStream_t s);
+                             tms_vertex *out, hipStream_t s, const int64_t *nd = nullptr,
+                             int64_t vcap = 0, unsigned *ovf = nullptr);
 hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                               uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
 hipError_t launch_edge_emit(const Grid *gt, const tms_leaf *leaves, const double *corner_phi,

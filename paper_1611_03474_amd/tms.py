@@ -113,6 +113,10 @@ def load_library(path: str = LIB_PATH):
     L.tms_build_cells_batch.argtypes = [_VP, _VP, C.POINTER(i64), i32, C.POINTER(Params),
                                         C.POINTER(_VP)]
     L.tms_batch_counts.argtypes = [_VP, _VP, C.POINTER(i64), C.POINTER(i64)]
+    L.tms_graph_capture.argtypes = [_VP, _VP, C.c_double]
+    L.tms_graph_launch.argtypes = [_VP, _VP, _VP, _VP, i64, C.POINTER(i64), _VP, i64,
+                                   C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                                   C.POINTER(Stats)]
     L.tms_set_tuning.argtypes = [_VP, C.POINTER(Tuning)]
     L.tms_get_tuning.argtypes = [_VP, C.POINTER(Tuning)]
     L.tms_autotune.argtypes = [_VP, _VP, C.POINTER(Tuning), C.POINTER(C.c_double),
@@ -129,7 +133,7 @@ def load_library(path: str = LIB_PATH):
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
               "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
               "tms_build_cells_batch", "tms_batch_counts", "tms_set_tuning", "tms_get_tuning",
-              "tms_autotune"):
+              "tms_autotune", "tms_graph_capture", "tms_graph_launch"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -391,6 +395,30 @@ class Context:
                                           0 if dphi is None else dphi.shape[0], _VP(_ptr(dt)),
                                           0 if dt is None else dt.shape[0], _VP(_ptr(out))))
         return out
+
+    # --------------------------------------------------------- captured pass
+    def graph_capture(self, cells: Cells, margin: float = 1.25):
+        """Record the pass (partition + corners + extraction) of `cells` into a
+        HIP graph; needs an eager partition and extraction of them first."""
+        self._check(self.lib.tms_graph_capture(self.h, cells.handle, float(margin)))
+
+    def graph_launch(self, cells: Cells, leaves=None, cphi=None, verts=None, offsets=False):
+        """Replay the captured pass; returns (n_leaves, n_verts, stats dict
+        [, (leaf offsets, vertex offsets)])."""
+        nl = C.c_int64()
+        nv = C.c_int64()
+        st = Stats()
+        lo = np.zeros(cells.n_conf + 1, dtype=np.int64) if offsets else None
+        vo = np.zeros(cells.n_conf + 1, dtype=np.int64) if offsets else None
+        P = C.POINTER(C.c_int64)
+        self._check(self.lib.tms_graph_launch(
+            self.h, cells.handle, _VP(_ptr(leaves)), _VP(_ptr(cphi)),
+            0 if leaves is None else leaves.shape[0], C.byref(nl), _VP(_ptr(verts)),
+            0 if verts is None else verts.shape[0], C.byref(nv),
+            lo.ctypes.data_as(P) if offsets else None, vo.ctypes.data_as(P) if offsets else None,
+            C.byref(st)))
+        r = (nl.value, nv.value, st.as_dict())
+        return r + ((lo, vo),) if offsets else r
 
     # ---------------------------------------------------------------- tuning
     def set_tuning(self, slice_cubes=None, tiled_min_level=None, tile_atoms=None):

@@ -1,0 +1,83 @@
+"""The captured pass (one HIP graph, every size on the device) against the
+eager pass of the same cells: bit-identical leaves, corner values, vertices,
+per-conformation offsets and counters, over several replays with eager work
+in between."""
+import numpy as np
+import pytest
+
+from paper_1611_03474_amd import synth, tms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = tms.Context(0)
+    yield c
+    c.close()
+
+
+def _eager(ctx, cells):
+    leaves, cphi, st = ctx.partition_estimate(cells)
+    verts = ctx.extract(cells, leaves, cphi)
+    return leaves.clone(), cphi.clone(), verts.clone(), st
+
+
+def _check_replays(ctx, cells, n_conf, reps=3):
+    import torch
+    L0, C0, V0, st0 = _eager(ctx, cells)
+    lo0 = vo0 = None
+    if n_conf > 1:
+        lo0, vo0 = ctx.batch_counts(cells)
+    ctx.graph_capture(cells, margin=1.25)
+    lb = torch.empty((L0.shape[0] + 100, 20), dtype=torch.uint8, device="cuda:0")
+    cb = torch.empty((L0.shape[0] + 100, 8), dtype=torch.float64, device="cuda:0")
+    vb = torch.empty((V0.shape[0] + 100, 40), dtype=torch.uint8, device="cuda:0")
+    for r in range(reps):
+        lb.fill_(0)
+        vb.fill_(0)
+        nl, nv, st, (lo, vo) = ctx.graph_launch(cells, lb, cb, vb, offsets=True)
+        assert nl == L0.shape[0] and nv == V0.shape[0], r
+        assert torch.equal(lb[:nl], L0) and torch.equal(cb[:nl], C0) and torch.equal(vb[:nv], V0), r
+        for k in ("n_est", "n_disc", "n_refine", "n_conv", "n_hmin", "n_leaves", "n_surface",
+                  "n_corners", "n_bound", "guard_cubes", "guard_points", "n_pairs"):
+            assert st[k] == st0[k], (r, k, st[k], st0[k])
+        if n_conf > 1:
+            assert np.array_equal(lo, lo0) and np.array_equal(vo, vo0)
+        # eager work on the same context between replays
+        ctx.eval_phi(cells, torch.zeros((5, 3), dtype=torch.float64, device="cuda:0")) \
+            if n_conf == 1 else ctx.partition_estimate(cells)
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [tms.PREC_FP64, tms.PREC_FP32_GUARD], ids=["fp64", "fp32g"])
+def test_graph_single(ctx, prec):
+    atoms = synth.globule(1000, 1006)
+    cells = ctx.build_cells(atoms, tms.make_params(D=0.9, tau=0.1, precision=prec))
+    _check_replays(ctx, cells, 1)
+    ctx.free_cells(cells)
+
+
+def test_graph_batch_sliced(ctx):
+    # a batch, with queue slices far smaller than the levels so the slicing
+    # of the captured pass is exercised too
+    confs = [synth.globule(n, 3000 + k) for k, n in enumerate([300, 120, 500, 220])]
+    cells = ctx.build_cells_batch(confs, tms.make_params(D=0.9, tau=1e-3,
+                                                         precision=tms.PREC_FP32_GUARD))
+    base = ctx.get_tuning().as_dict()
+    ctx.set_tuning(slice_cubes=4096)
+    try:
+        _check_replays(ctx, cells, len(confs))
+    finally:
+        ctx.set_tuning(**base)
+    ctx.free_cells(cells)
+
+
+def test_graph_rejects_without_eager_pass(ctx):
+    atoms = synth.globule(200, 1001)
+    cells = ctx.build_cells(atoms, tms.make_params(tau=0.1))
+    with pytest.raises(tms.TmsError):
+        ctx.graph_capture(cells)
+    ctx.free_cells(cells)
