@@ -78,11 +78,28 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
     tm = ctx.get_timing(reset=True)
     ctx.set_timing(False)
     sd = s.as_dict()
-    ctx.free_cells(cells)
     ms = (t1 - t0) * 1e3 / steps
     per_step = {k: {"ms": v["ms"] / steps, "launches": v["launches"] / steps}
                 for k, v in tm.items()}
-    return dict(ms_per_step=ms, stats=sd, n_leaves=nl, n_vertices=nv, timing=per_step)
+    # the same pass replayed from a captured graph (build eager, rest one graph)
+    ctx.graph_capture(cells, margin=1.1)
+
+    def gstep():
+        ctx.build_cells(atoms_dev, p, cells)
+        return ctx.graph_launch(cells, lb, cb, vb)
+
+    for _ in range(warmup):
+        gstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gnl, gnv, _ = gstep()
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / steps
+    assert gnl == nl and gnv == nv
+    ctx.free_cells(cells)
+    return dict(ms_per_step=ms, stats=sd, n_leaves=nl, n_vertices=nv, timing=per_step,
+                graph_ms_per_step=gms)
 
 
 def run_adjoint(ctx, tms, steps, warmup):
@@ -161,6 +178,22 @@ def run_batch(ctx, tms, confs, steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     sd = s_.as_dict()
+    # one captured graph for the whole batched pass
+    ctx.graph_capture(cells, margin=1.1)
+
+    def gstep():
+        ctx.build_cells_batch((a, off), p, cells)
+        return ctx.graph_launch(cells, lb, cb, vb)
+
+    for _ in range(warmup):
+        gstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gnl, gnv, _ = gstep()
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / steps
+    assert gnl == nl and gnv == nv
     ctx.free_cells(cells)
 
     def loop(prec):
@@ -186,6 +219,7 @@ def run_batch(ctx, tms, confs, steps, warmup):
     return {"workload": w.name, "conformations": len(confs), "atoms": int(off[-1]),
             "leaves": int(nl), "vertices": int(nv), "cubes_estimated": est,
             "ms_per_pass": ms, "cubes_per_s": est / (ms * 1e-3),
+            "graph_ms_per_pass": gms, "graph_cubes_per_s": est / (gms * 1e-3),
             "tuning": tuning, "autotune_best_ms": tune_ms, "autotune_passes": tune_n,
             "loop_fp32g_ms": loop32, "loop_fp64_ms": loop64,
             "speedup_vs_loop_fp32g": loop32 / ms, "speedup_vs_loop_fp64": loop64 / ms}
@@ -311,6 +345,8 @@ def main():
                    "D": w.D, "c": w.c, "tau": w.tau, "h0": w.h0, "h_min": w.h_min,
                    "precision": "fp32+fp64 guard"},
         "phi_evals_per_s": r32["phi_evals_per_s"],
+        "graph_ms_per_step": f32["graph_ms_per_step"],
+        "graph_cubes_per_s": st["cubes_estimated"] / (f32["graph_ms_per_step"] * 1e-3),
         "cubes_estimated": st["cubes_estimated"],
         "per_level_estimated": st["n_est"][:4],
         "leaves": f32["n_leaves"], "surface_leaves": st["n_surface"],
@@ -325,6 +361,7 @@ def main():
     if f64 is not None:
         r64 = rates(f64)
         out["fp64"] = {"value": r64["cubes_per_s"], "ms_per_step": f64["ms_per_step"],
+                       "graph_ms_per_step": f64["graph_ms_per_step"],
                        "phi_evals_per_s": r64["phi_evals_per_s"],
                        "device_ms_per_step": {k: round(v["ms"], 4)
                                               for k, v in f64["timing"].items()},

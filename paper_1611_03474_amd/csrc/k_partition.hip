@@ -229,11 +229,12 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
 // per-thread kernel.
 // ---------------------------------------------------------------------------
 constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
+constexpr int64_t kStrideGrid = 16384;  // workgroups of a capacity-sized tiled launch
 
 template <bool FAST, int QH, int CH>
 __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const Grid *__restrict__ gt, int level, GLRule<double> R, const int4 *__restrict__ q,
-    const int32_t *__restrict__ subset, const int2 *__restrict__ chunks,
+    const int32_t *__restrict__ subset, const int2 *__restrict__ chunks, int64_t nch_cap,
     const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
@@ -243,8 +244,10 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     __shared__ double s_w[CH];
     __shared__ int s_use[CH];
     const int lane = threadIdx.x;
-    if (o.ncount && (int64_t)blockIdx.x >= (int64_t)*o.ncount) return;  // whole workgroup
-    const int2 ch = chunks[blockIdx.x];
+    // chunks in a grid-stride loop (one pass when the grid covers them all)
+    const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
+    for (int64_t cix = blockIdx.x; cix < nch; cix += gridDim.x) {
+    const int2 ch = chunks[cix];
     const bool valid = lane < ch.y;
     const int64_t pos = (int64_t)ch.x + (valid ? lane : 0);
     const int64_t qi = subset ? subset[pos] : pos;
@@ -361,6 +364,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     }
     epilogue(g, level, FAST, A, EA, qi, valid, o);
     if (pairs) wave_add(pairs, np);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -620,19 +624,23 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
                             const double *aw, const EstOut &o, unsigned long long *pairs,
                             hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
+    // a capacity-sized launch (chunk count on the device) takes a fixed grid
+    // that strides over the chunks; otherwise one workgroup per chunk
+    const unsigned grid =
+        (unsigned)(o.ncount ? std::min<int64_t>(nchunks, kStrideGrid) : nchunks);
     // atoms staged per LDS tile (a tuning knob; the arithmetic is the same)
     switch (ch) {
     case 8:
-        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 8>), dim3((unsigned)nchunks), dim3(64), 0, s,
-                           g, level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 8>), dim3(grid), dim3(64), 0, s, g, level, R,
+                           q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs);
         break;
     case 32:
-        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 32>), dim3((unsigned)nchunks), dim3(64), 0, s,
-                           g, level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 32>), dim3(grid), dim3(64), 0, s, g, level,
+                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs);
         break;
     default:
-        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 16>), dim3((unsigned)nchunks), dim3(64), 0, s,
-                           g, level, R, q, subset, chunks, rs, ra, ax, ay, az, aw, o, pairs);
+        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 16>), dim3(grid), dim3(64), 0, s, g, level,
+                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs);
     }
     return hipGetLastError();
 }
