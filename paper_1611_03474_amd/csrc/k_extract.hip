@@ -128,23 +128,45 @@ __device__ __forceinline__ int64_t edge_bit(const EdgeLat &el, const tms_leaf &L
            (((int64_t)(L.ix + off[0]) * lat.n[1] + (L.iy + off[1])) * lat.n[2] + (L.iz + off[2]));
 }
 
+// one thread per leaf: the bits of its crossing edges, merged per 64-bit word
+// (the four edges of one axis fall in at most two words, usually), one
+// atomic OR per distinct word
 __global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n,
                             const EdgeLat *__restrict__ et, unsigned long long *__restrict__ bm,
                             const int64_t *__restrict__ nd) {
-    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 12 * n || (nd && c >= 12 * *nd)) return;
-    const tms_leaf L = leaves[c / 12];
+    const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n || (nd && q >= *nd)) return;
+    const tms_leaf L = leaves[q];
     if (L.cls != TMS_CLS_SURFACE) return;
-    int axis, off[3], v0, v1;
-    edge_corners((int)(c % 12), axis, off, v0, v1);
-    if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) return;
-    const int64_t b = edge_bit(et[L.conf], L, axis, off);
-    atomicOr(bm + (b >> 6), 1ull << (b & 63));
+    const EdgeLat &el = et[L.conf];
+    int64_t w[12];
+    unsigned long long m[12];
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        int axis, off[3], v0, v1;
+        edge_corners(e, axis, off, v0, v1);
+        const bool cross = ((L.mask >> v0) ^ (L.mask >> v1)) & 1;
+        const int64_t b = edge_bit(el, L, axis, off);
+        w[e] = b >> 6;
+        m[e] = cross ? 1ull << (b & 63) : 0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        if (m[e] == 0) continue;
+        unsigned long long bits = m[e];
+#pragma unroll
+        for (int u = e + 1; u < 12; ++u)
+            if (w[u] == w[e]) {
+                bits |= m[u];
+                m[u] = 0;
+            }
+        atomicOr(bm + w[e], bits);
+    }
 }
 
 // every leaf that has a crossing edge writes its vertex at the edge's rank
 // (leaves sharing the edge share its corner values, so they write the same
-// bits); the list comes out in edge-key order
+// bits); the list comes out in edge-key order.  One thread per (leaf, edge).
 __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__restrict__ leaves,
                              const double *__restrict__ cphi, int64_t n,
                              const EdgeLat *__restrict__ et, const uint64_t *__restrict__ bm,
@@ -189,7 +211,7 @@ __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__rest
 hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
                             unsigned long long *bm, hipStream_t s, const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, et, bm, nd);
+    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, et, bm, nd);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ constexpr uint64_t kEmpty = ~0ull;
 // |dphi| <= kFastExpErr phi.  guard[k] = 1 when the sign of phi - c is not
 // certain (|phi - c| <= 2 kFastExpErr phi) or when |phi - c| <= band_rel * c;
 // the caller recomputes those points with exact exponentials.
-template <bool FAST>
+template <bool FAST, bool GRAD>
 __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
                                                     const int32_t *__restrict__ pconf,
                                                     const double *__restrict__ pts,
@@ -37,9 +37,9 @@ __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
     const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
-    phi_at<FAST>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi_at<FAST, GRAD>(g, p, cs, ax, ay, az, aw, f, gr);
     phi[k] = f;
-    if (grad) {
+    if (GRAD) {
         grad[3 * k] = gr[0];
         grad[3 * k + 1] = gr[1];
         grad[3 * k + 2] = gr[2];
@@ -419,12 +419,22 @@ hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision
                              const double *az, const double *aw, double band_rel, double *phi,
                              double *grad, uint8_t *guard, hipStream_t s, const int32_t *nd) {
     if (m <= 0) return hipSuccess;
-    if (precision == TMS_PREC_FP32_GUARD)
-        hipLaunchKernelGGL(k_phi_points<true>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
-                           cs, ax, ay, az, aw, band_rel, phi, grad, guard, nd);
-    else
-        hipLaunchKernelGGL(k_phi_points<false>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
-                           cs, ax, ay, az, aw, 0.0, phi, grad, nullptr, nd);
+    // corner values need no gradient: a variant without it
+    if (precision == TMS_PREC_FP32_GUARD) {
+        if (grad)
+            hipLaunchKernelGGL((k_phi_points<true, true>), dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf,
+                               pts, m, cs, ax, ay, az, aw, band_rel, phi, grad, guard, nd);
+        else
+            hipLaunchKernelGGL((k_phi_points<true, false>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
+                               pconf, pts, m, cs, ax, ay, az, aw, band_rel, phi, grad, guard, nd);
+    } else {
+        if (grad)
+            hipLaunchKernelGGL((k_phi_points<false, true>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
+                               pconf, pts, m, cs, ax, ay, az, aw, 0.0, phi, grad, nullptr, nd);
+        else
+            hipLaunchKernelGGL((k_phi_points<false, false>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
+                               pconf, pts, m, cs, ax, ay, az, aw, 0.0, phi, grad, nullptr, nd);
+    }
     return hipGetLastError();
 }
 

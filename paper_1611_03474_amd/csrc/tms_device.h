@@ -424,7 +424,7 @@ __device__ __forceinline__ void sample_range(const double *A, double &lo, double
 // ---------------------------------------------------------------------------
 // Sum over atoms within R_c of p, in canonical atom order (cell rows of the
 // stencil, atoms in cell order).  *err (FAST only) bounds |dphi|.
-template <bool FAST>
+template <bool FAST, bool GRAD = true>
 __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                                        const int32_t *__restrict__ cs, const double *__restrict__ ax,
                                        const double *__restrict__ ay, const double *__restrict__ az,
@@ -465,10 +465,12 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                 if (d2 > g.rc2) continue;
                 const double term = aw[i] * expn<FAST>(-D * d2);
                 phi += term;
-                const double f = m2D * term;
-                gr[0] += f * dx;
-                gr[1] += f * dy;
-                gr[2] += f * dz;
+                if (GRAD) {
+                    const double f = m2D * term;
+                    gr[0] += f * dx;
+                    gr[1] += f * dy;
+                    gr[2] += f * dz;
+                }
             }
         }
     }
