@@ -319,7 +319,8 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
 /* ---- tuning ---------------------------------------------------------------
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
- * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 16. */
+ * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 16,
+ * proj_table 1. */
 typedef struct {
     int64_t slice_cubes;     /* largest queue slice per estimate + bound
                                 launch (a level is cut into ceil(n / this)
@@ -331,6 +332,14 @@ typedef struct {
                                 cube)                                        */
     int32_t tile_atoms;      /* atoms staged per LDS tile of that kernel:
                                 8, 16 or 32                                  */
+    int32_t proj_table;      /* 1: the tiled levels first tabulate every
+                                atom's 1-D projections (Section 2.2.1) on
+                                the intervals within R_c of it (48 B per
+                                atom, axis and interval: about
+                                3 * ceil(2 R_c / h) + 9 entries per atom at
+                                spacing h) and gather from that table;
+                                0: each chunk projects in place          */
+    int32_t reserved;        /* 0                                          */
 } tms_tuning;
 
 /* Set / read ctx's tuning.  Errors: TMS_E_INVALID (values out of range). */
@@ -339,8 +348,9 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t);
 
 /* Autotuner: times tms_partition_estimate on `cells` (count only, device
  * results discarded) under candidate tunings -- atoms per tile, then the
- * first tiled level, then the slice size, each with the others at their
- * best so far -- checks that every candidate gives the same leaf and cube
+ * projection table on or off, then the first tiled level, then the slice
+ * size, each with the others at their best so far -- checks that every
+ * candidate gives the same leaf and cube
  * counts, and leaves the fastest set on ctx.
  *  best     host out (or NULL): the chosen tuning.
  *  best_ms  host out (or NULL): its wall time in ms.

@@ -220,14 +220,32 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
 // ---------------------------------------------------------------------------
 // Tensor estimate for deep levels: one 64-lane workgroup per chunk of at most
 // 64 consecutive queue entries (or entries of a sorted subset of the queue)
-// of one root (a root's cubes are contiguous in refinement order).  Atoms of the root list are staged CH at a time; an
-// atom farther than R_c from the chunk's bounding box is skipped by the whole
-// wavefront.  For the others, each 1-D projection (atom, axis, interval) is
-// computed once into LDS and shared by every cube of the chunk on that
-// interval; each lane then applies the per-cube R_c test and the rank-one
-// update of its cube.  Same arithmetic, in the same atom order, as the
-// per-thread kernel.
+// of one root (a root's cubes are contiguous in refinement order).
+//
+// The root's neighbourhood list is first filtered, 64 atoms at a time, down
+// to the atoms within R_c of the chunk's bounding box, kept in list order in
+// an LDS buffer; tiles of CH such atoms are then staged.  For a tile, each
+// 1-D projection (atom, axis, interval) is put once into LDS and shared by
+// every cube of the chunk on that interval; each lane then applies the
+// per-cube R_c test and the rank-one update of its cube.  Same arithmetic,
+// in the same atom order, as the per-thread kernel.
+//
+// A projection is needed only if some cube of the chunk on that interval can
+// be within R_c of the atom: its 1-D distance squared plus the chunk's
+// bounding-box distances squared on the other two axes, summed in the order
+// of the per-cube test, must not exceed R_c^2 (floating-point addition is
+// monotone, so the per-cube sum is at least that).  With a projection table
+// the needed entries go from the table straight into LDS (global-to-LDS
+// loads: no registers, many in flight); they are bit-identical to the
+// projections computed here (same lattice points, same routine).
 // ---------------------------------------------------------------------------
+// First interval of an atom's row of the projection table along one axis:
+// one below the interval holding x - R_c.  The table and the tiled kernel
+// evaluate this same expression.
+__device__ __forceinline__ int proj_first(double x, double o, double rc, double h) {
+    return (int)floor((x - o - rc) / h) - 1;
+}
+
 constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
 constexpr int64_t kStrideGrid = 16384;  // workgroups of a capacity-sized tiled launch
 
@@ -238,12 +256,18 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
-    EstOut o, unsigned long long *__restrict__ pairs) {
-    // tab[a][axis][iv] = {a0, a1, a2, a3, err, dist^2}
-    __shared__ double tab[CH][3][kTileIv][6];
-    __shared__ double s_w[CH];
-    __shared__ int s_use[CH];
+    EstOut o, unsigned long long *__restrict__ pairs, ProjTab P) {
+    constexpr int W = CH * 3 * kTileIv;  // projection items of a tile
+    constexpr int NB = CH + 64;          // atom buffer (a refill adds at most 64)
+    // item w = a * per_atom + (axis offset) + interval: {a0, a1}, {a2, a3},
+    // {err, squared 1-D distance}
+    __shared__ double2 t01[W], t23[W], ted[W];
+    __shared__ int b_i[NB];
+    __shared__ int b_lo[NB][3];  // first table interval per axis
+    __shared__ double b_w[NB];
+    __shared__ double b_x[NB][3];
     const int lane = threadIdx.x;
+    using lds_ptr = __attribute__((address_space(3))) void *;
     // chunks in a grid-stride loop (one pass when the grid covers them all)
     const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
     for (int64_t cix = blockIdx.x; cix < nch; cix += gridDim.x) {
@@ -254,7 +278,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const int4 c = q[qi];
     const int4 c0 = q[subset ? subset[ch.x] : ch.x];
     const Grid &g = gt[c0.w];  // one root, hence one conformation, per chunk
-    const double rc2 = g.rc2, D = g.D;
+    const double rc2 = g.rc2, D = g.D, rc = sqrt(rc2);
     const double h = ldexp(g.h0, -level);
     const double s = 0.5 * h;
     const int rxyz[3] = {c0.x >> level, c0.y >> level, c0.z >> level};
@@ -282,66 +306,115 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
         blo[a] = base[a] + mn[a] * h;
         bhi[a] = base[a] + (mx[a] + 1) * h;
     }
-    const int rb = root_start[root], re = root_start[root + 1];
+    const int per_atom = nv[0] + nv[1] + nv[2];
+    // this lane's items in a tile: x, y, z interval of its cube
+    const int ox = li[0] - mn[0], oy = nv[0] + li[1] - mn[1], oz = nv[0] + nv[1] + li[2] - mn[2];
+    const int re = root_start[root + 1];
+    int head = root_start[root], nbuf = 0;
     double A[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) A[e] = 0.0;
     double EA = 0.0;
     unsigned long long np = 0;
-    const int per_atom = nv[0] + nv[1] + nv[2];
-    for (int p0 = rb; p0 < re; p0 += CH) {
-        const int na = min(CH, re - p0);
-        if (lane < na) {
-            const int i = root_atoms[p0 + lane];
-            const double x[3] = {ax[i], ay[i], az[i]};
-            double d2 = 0.0;
+    for (;;) {
+        // refill: atoms of the list within R_c of the chunk's box, in order
+        while (nbuf < CH && head < re) {
+            const int p = head + lane;
+            bool use = false;
+            int i = 0;
+            double x[3] = {0.0, 0.0, 0.0};
+            if (p < re) {
+                i = root_atoms[p];
+                x[0] = ax[i];
+                x[1] = ay[i];
+                x[2] = az[i];
+                double d2 = 0.0;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double d = fmax(fmax(blo[a] - x[a], x[a] - bhi[a]), 0.0);
-                d2 += d * d;
+                for (int a = 0; a < 3; ++a) {
+                    const double d = fmax(fmax(blo[a] - x[a], x[a] - bhi[a]), 0.0);
+                    d2 += d * d;
+                }
+                use = d2 <= rc2;
             }
-            s_use[lane] = d2 <= rc2;
-            s_w[lane] = aw[i];
-        }
-        __syncthreads();
-        for (int w = lane; w < na * per_atom; w += 64) {
-            const int a_idx = w / per_atom;
-            if (!s_use[a_idx]) continue;
-            int r = w - a_idx * per_atom, axis = 0;
-            if (r >= nv[0]) {
-                r -= nv[0];
-                axis = 1;
-                if (r >= nv[1]) {
-                    r -= nv[1];
-                    axis = 2;
+            const unsigned long long m = __ballot(use);
+            if (use) {
+                const int at = nbuf + __popcll(m & ((1ull << lane) - 1ull));
+                b_i[at] = i;
+                b_w[at] = aw[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b_x[at][a] = x[a];
+                    b_lo[at][a] = proj_first(x[a], g.o[a], rc, h);
                 }
             }
-            const int i = root_atoms[p0 + a_idx];
-            const double xa = axis == 0 ? ax[i] : (axis == 1 ? ay[i] : az[i]);
-            const double lo = base[axis] + (mn[axis] + r) * h, hi = lo + h;
-            const double d = fmax(fmax(lo - xa, xa - hi), 0.0);
-            double *t = tab[a_idx][axis][r];
-            t[5] = d * d;
-            double pr[4], err;
-            project<FAST, QH>(R, D, s, (lo + s) - xa, pr, err);
-            t[0] = pr[0];
-            t[1] = pr[1];
-            t[2] = pr[2];
-            t[3] = pr[3];
-            t[4] = err;
+            nbuf += __popcll(m);
+            head += 64;
         }
         __syncthreads();
+        const int na = min(CH, nbuf);
+        if (na == 0) break;
+        // projections of the tile's atoms on the chunk's intervals
+        const int nw = na * per_atom;
+        for (int k0 = 0; k0 < nw; k0 += 64) {
+            const int w = k0 + lane;
+            const double *src = nullptr;
+            if (w < nw) {
+                const int a_idx = w / per_atom;
+                int r = w - a_idx * per_atom, axis = 0;
+                if (r >= nv[0]) {
+                    r -= nv[0];
+                    axis = 1;
+                    if (r >= nv[1]) {
+                        r -= nv[1];
+                        axis = 2;
+                    }
+                }
+                const double xa = b_x[a_idx][axis];
+                const double lo = base[axis] + (mn[axis] + r) * h, hi = lo + h;
+                const double d = fmax(fmax(lo - xa, xa - hi), 0.0);
+                const double dd = d * d;
+                // no cube of the chunk on this interval is in range: only the
+                // distance is read
+                double b[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double e = fmax(fmax(blo[a] - b_x[a_idx][a], b_x[a_idx][a] - bhi[a]), 0.0);
+                    b[a] = a == axis ? dd : e * e;
+                }
+                const int slot = (rxyz[axis] << level) + mn[axis] + r - b_lo[a_idx][axis];
+                if (b[0] + b[1] + b[2] > rc2) {
+                    ted[w] = make_double2(0.0, dd);
+                } else if (P.t && slot >= 0 && slot < P.ns) {
+                    src = P.t + 6 * (((int64_t)axis * P.n + b_i[a_idx]) * P.ns + slot);
+                } else {
+                    double pr[4], err;
+                    project<FAST, QH>(R, D, s, (lo + s) - xa, pr, err);
+                    t01[w] = make_double2(pr[0], pr[1]);
+                    t23[w] = make_double2(pr[2], pr[3]);
+                    ted[w] = make_double2(err, dd);
+                }
+            }
+            if (src) {  // lane w's 16-byte pieces land at [k0 + lane] = [w]
+                __builtin_amdgcn_global_load_lds(src, (lds_ptr)(t01 + k0), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(src + 2, (lds_ptr)(t23 + k0), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)(ted + k0), 16, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         if (valid) {
-            const int lx = li[0] - mn[0], ly = li[1] - mn[1], lz = li[2] - mn[2];
             for (int a = 0; a < na; ++a) {
-                if (!s_use[a]) continue;
-                const double *tx = tab[a][0][lx], *ty = tab[a][1][ly], *tz = tab[a][2][lz];
-                if (tx[5] + ty[5] + tz[5] > rc2) continue;
+                const int ba = a * per_atom;
+                const double2 ex = ted[ba + ox], ey = ted[ba + oy], ez = ted[ba + oz];
+                if (ex.y + ey.y + ez.y > rc2) continue;
                 ++np;
-                const double px[4] = {tx[0], tx[1], tx[2], tx[3]};
-                const double py[4] = {ty[0], ty[1], ty[2], ty[3]};
-                const double pz[4] = {tz[0], tz[1], tz[2], tz[3]};
-                const double wgt = s_w[a];
+                const double2 x01 = t01[ba + ox], x23 = t23[ba + ox];
+                const double2 y01 = t01[ba + oy], y23 = t23[ba + oy];
+                const double2 z01 = t01[ba + oz], z23 = t23[ba + oz];
+                const double px[4] = {x01.x, x01.y, x23.x, x23.y};
+                const double py[4] = {y01.x, y01.y, y23.x, y23.y};
+                const double pz[4] = {z01.x, z01.y, z23.x, z23.y};
+                const double wgt = b_w[a];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const double wx = wgt * px[j];
@@ -356,15 +429,73 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
                     const double nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
                     const double ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
                     const double nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
-                    EA += wgt * ((tx[4] * ny + nx * ty[4]) * nz + nx * ny * tz[4]);
+                    EA += wgt * ((ex.x * ny + nx * ey.x) * nz + nx * ny * ez.x);
                 }
             }
         }
         __syncthreads();
+        // move the atoms not yet staged (fewer than 64) to the buffer's front
+        const int rest = nbuf - na;
+        int mi = 0, ml[3] = {0, 0, 0};
+        double mw = 0.0, mx3[3] = {0.0, 0.0, 0.0};
+        if (lane < rest) {
+            mi = b_i[na + lane];
+            mw = b_w[na + lane];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ml[a] = b_lo[na + lane][a];
+                mx3[a] = b_x[na + lane][a];
+            }
+        }
+        __syncthreads();
+        if (lane < rest) {
+            b_i[lane] = mi;
+            b_w[lane] = mw;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b_lo[lane][a] = ml[a];
+                b_x[lane][a] = mx3[a];
+            }
+        }
+        nbuf = rest;
     }
     epilogue(g, level, FAST, A, EA, qi, valid, o);
     if (pairs) wave_add(pairs, np);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Projection table of one level: one thread per (axis, atom, slot).  A row
+// (axis, atom) starts at proj_first and holds ceil(2 R_c / h) + 3 intervals,
+// so every interval within R_c of the atom along the axis has a slot (the
+// tiled kernel still checks, and projects in place on a miss).  An entry is
+// {a0, a1, a2, a3, err, squared 1-D distance}.  Lattice points are exact
+// multiples of the finest spacing, so an interval's bounds are the same
+// doubles here and in the estimate kernels.
+// ---------------------------------------------------------------------------
+template <bool FAST, int QH>
+__global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, GLRule<double> R,
+                             const double *__restrict__ ax, const double *__restrict__ ay,
+                             const double *__restrict__ az, int64_t n, int ns,
+                             double *__restrict__ T) {
+    const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (t >= 3 * n * ns) return;
+    const int64_t ia = t / ns;  // axis * n + atom
+    const int slot = (int)(t - ia * ns);
+    const int axis = (int)(ia / n);
+    const int64_t i = ia - axis * n;
+    const Grid &g = gt[conf_of_atom(gt, nconf, i)];
+    const double x = axis == 0 ? ax[i] : (axis == 1 ? ay[i] : az[i]);
+    const double h = ldexp(g.h0, -level), s = 0.5 * h;
+    const int first = proj_first(x, g.o[axis], sqrt(g.rc2), h);
+    const double lo = g.o[axis] + (double)(first + slot) * h, hi = lo + h;
+    const double d = fmax(fmax(lo - x, x - hi), 0.0);
+    double pr[4] = {0.0, 0.0, 0.0, 0.0}, err = 0.0;
+    if (d * d <= g.rc2) project<FAST, QH>(R, g.D, s, (lo + s) - x, pr, err);
+    double2 *dst = reinterpret_cast<double2 *>(T + 6 * t);
+    dst[0] = make_double2(pr[0], pr[1]);
+    dst[1] = make_double2(pr[2], pr[3]);
+    dst[2] = make_double2(err, d * d);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,7 +753,7 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
                             const int2 *chunks, int64_t nchunks, const int32_t *rs,
                             const int32_t *ra, const double *ax, const double *ay, const double *az,
                             const double *aw, const EstOut &o, unsigned long long *pairs,
-                            hipStream_t s) {
+                            const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
     // a capacity-sized launch (chunk count on the device) takes a fixed grid
     // that strides over the chunks; otherwise one workgroup per chunk
@@ -632,15 +763,15 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
     switch (ch) {
     case 8:
         hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 8>), dim3(grid), dim3(64), 0, s, g, level, R,
-                           q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs);
+                           q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
         break;
     case 32:
         hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 32>), dim3(grid), dim3(64), 0, s, g, level,
-                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs);
+                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
         break;
     default:
         hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 16>), dim3(grid), dim3(64), 0, s, g, level,
-                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs);
+                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
     }
     return hipGetLastError();
 }
@@ -669,9 +800,25 @@ hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *
                           const int32_t *subset, const int2 *chunks, int64_t nchunks,
                           const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
                           const double *az, const double *aw, const EstOut &o,
-                          unsigned long long *pairs, hipStream_t s) {
+                          unsigned long long *pairs, const ProjTab &P, hipStream_t s) {
     TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(ch, g, level, q, subset, chunks, nchunks, rs, ra,
-                                                  ax, ay, az, aw, o, pairs, s)))
+                                                  ax, ay, az, aw, o, pairs, P, s)))
+}
+
+template <bool FAST, int QH>
+hipError_t proj_table_t(const Grid *gt, int nconf, int level, const double *ax, const double *ay,
+                        const double *az, int64_t n, int ns, double *t, hipStream_t s) {
+    GLRule<double> R = gl_rule<double>(QH);
+    hipLaunchKernelGGL((k_proj_table<FAST, QH>), dim3(nblk(3 * n * ns)), dim3(kBS), 0, s, gt, nconf,
+                       level, R, ax, ay, az, n, ns, t);
+    return hipGetLastError();
+}
+
+template <bool FAST>
+hipError_t proj_table_dispatch(int qh, const Grid *gt, int nconf, int level, const double *ax,
+                               const double *ay, const double *az, int64_t n, int ns, double *t,
+                               hipStream_t s) {
+    TMS_QH_SWITCH(qh, (proj_table_t<FAST, QH>(gt, nconf, level, ax, ay, az, n, ns, t, s)))
 }
 
 }  // namespace
@@ -787,7 +934,8 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *ax, const double *ay, const double *az,
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
-                                  int tile_atoms, hipStream_t s, const int32_t *ncount) {
+                                  int tile_atoms, hipStream_t s, const int32_t *ncount,
+                                  const ProjTab &pt) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
@@ -797,15 +945,32 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
         if (nchunks <= 0) return hipSuccess;
         if (fast)
             return tiled_dispatch<true>(qh, tile_atoms, gt, level, q, subset, chunks, nchunks,
-                                        root_start, root_atoms, ax, ay, az, aw, o, pc, s);
+                                        root_start, root_atoms, ax, ay, az, aw, o, pc, pt, s);
         return tiled_dispatch<false>(qh, tile_atoms, gt, level, q, subset, chunks, nchunks,
-                                     root_start, root_atoms, ax, ay, az, aw, o, pc, s);
+                                     root_start, root_atoms, ax, ay, az, aw, o, pc, pt, s);
     }
     if (fast)
         return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,
                                      az, aw, nullptr, nullptr, &o, pc, s);
     return thread_dispatch<false>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay, az,
                                   aw, nullptr, nullptr, &o, pc, s);
+}
+
+int proj_table_slots(const tms_cells *cells, int level) {
+    double rc2 = 0.0;
+    for (const Grid &gb : cells->gh) rc2 = std::max(rc2, gb.rc2);
+    const double h = ldexp(cells->g.h0, -level);
+    return (int)std::ceil(2.0 * std::sqrt(rc2) / h) + 3;
+}
+
+hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level, int precision,
+                             const double *ax, const double *ay, const double *az, int64_t n,
+                             int ns, double *t, hipStream_t s) {
+    if (n <= 0 || ns <= 0) return hipSuccess;
+    const int qh = qh_for(g, level);
+    if (precision == TMS_PREC_FP32_GUARD)
+        return proj_table_dispatch<true>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
+    return proj_table_dispatch<false>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
 }
 
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,

@@ -105,7 +105,7 @@ void tms_graph_state::release() {
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
-                        &stmp, &seg};
+                        &stmp, &seg, &ptab};
     for (auto *x : b) x->release();
 }
 
@@ -915,6 +915,18 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.ctr.ensure(sizeof(unsigned long long) * kCtSlots));
     HIPCK(G.stmp.ensure(scan_tmp_bytes(std::max(nmax, std::max(cwords, ewords))) + 512));
     HIPCK(G.seg.ensure(sizeof(int64_t) * 2 * (size_t)(G.nlev * G.nconf)));
+    // projection tables of the tiled levels (one buffer, refilled per level;
+    // the finest tiled level has the most intervals per atom)
+    G.proj_table = false;
+    if (ctx->proj_table && cells->n > 0) {
+        int ns = 0;
+        for (int lev = std::max(ctx->tiled_min_level, 0); lev <= std::min(3, g.K); ++lev)
+            ns = std::max(ns, proj_table_slots(cells, lev));
+        if (ns > 0) {
+            HIPCK(G.ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)ns));
+            G.proj_table = true;
+        }
+    }
     hipStream_t s = ctx->stream;
     HIPCK(hipMemsetAsync(G.q[0].p, 0, G.q[0].cap, s));
     HIPCK(hipMemsetAsync(G.q[1].p, 0, G.q[1].cap, s));
@@ -963,6 +975,16 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         const int64_t QC = G.qcap[lev], S = G.slice[lev];
         const int nsl = (int)G.nslices[lev];
         const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
+        ProjTab pt;
+        int lprec = prec;  // precision of this level's estimate
+        if (tiled && G.proj_table) {
+            // tabulated projections are exact in either mode
+            lprec = TMS_PREC_FP64;
+            const int pns = proj_table_slots(cells, lev);
+            HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, ax, ay, az, cells->n, pns,
+                                    G.ptab.as<double>(), s));
+            pt = ProjTab{G.ptab.as<double>(), cells->n, pns};
+        }
         HIPCK(launch_slice_counts(nq + lev, S, nsl, ns, s));
         for (int k = 0; k < nsl; ++k) {
             const int64_t off = (int64_t)k * S, cap = std::min(S, QC - off);
@@ -981,15 +1003,15 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                 chunks = G.chunks.as<int2>();
                 ncount = nchunks;
             }
-            HIPCK(launch_estimate_decide(g, gt, lev, prec, q + off, cap, nullptr, chunks, cap, rs, ra,
+            HIPCK(launch_estimate_decide(g, gt, lev, lprec, q + off, cap, nullptr, chunks, cap, rs, ra,
                                          ax, ay, az, aw, dec + off, G.abuf.as<double>(),
                                          G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
                                          reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
-                                         ctx->tile_atoms, s, ncount));
-            HIPCK(launch_bound(g, lev, prec, cap, dec + off, G.abuf.as<double>(),
+                                         ctx->tile_atoms, s, ncount, pt));
+            HIPCK(launch_bound(g, lev, lprec, cap, dec + off, G.abuf.as<double>(),
                                G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
         }
-        if (prec == TMS_PREC_FP32_GUARD) {
+        if (lprec == TMS_PREC_FP32_GUARD) {
             int32_t *ng = sz + kSzNg + lev;
             HIPCK(launch_guard_list_flags(dec, QC, flags, s, nq + lev));
             HIPCK(exclusive_scan(flags, sa, QC, ng, tmp, s));
@@ -1214,6 +1236,24 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
             const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
+            ProjTab pt;
+            int lprec = prec;  // precision of this level's estimate
+            if (tiled && ctx->proj_table) {
+                // the table amortises the exponentials over every chunk that
+                // reads an entry, so its projections are exact in either mode
+                // (and this level needs no guard)
+                lprec = TMS_PREC_FP64;
+                const int ns = proj_table_slots(cells, lev);
+                const int64_t na = cells->n;
+                HIPCK(ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)na * (size_t)ns));
+                {
+                    TimedScope ts_(ctx, TMS_T_TILED);
+                    HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, cells->ax.as<double>(),
+                                            cells->ay.as<double>(), cells->az.as<double>(), na, ns,
+                                            ctx->ptab.as<double>(), s));
+                }
+                pt = ProjTab{ctx->ptab.as<double>(), na, ns};
+            }
             for (int64_t k = 0; k < nslices; ++k) {
                 const int64_t off = k * S, ns = std::min(S, nq - off);
                 unsigned *hard = reinterpret_cast<unsigned *>(ctr + kSliceCtr + k);
@@ -1226,21 +1266,22 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 {  // Step 1 (tensor) and the decisions that need no bound
                     TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
                     HIPCK(launch_estimate_decide(
-                        g, gt, lev, prec, q + off, ns, nullptr, chunks, nchunks,
+                        g, gt, lev, lprec, q + off, ns, nullptr, chunks, nchunks,
                         cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
                         cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
                         cells->aw.as<double>(), ctx->dec.as<uint8_t>() + off,
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
-                        hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s));
+                        hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s, nullptr,
+                        pt));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
-                    HIPCK(launch_bound(g, lev, prec, ns, ctx->dec.as<uint8_t>() + off,
+                    HIPCK(launch_bound(g, lev, lprec, ns, ctx->dec.as<uint8_t>() + off,
                                        ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
                                        ctx->hidx.as<int32_t>(), hard, s));
                 }
             }
-            if (prec == TMS_PREC_FP32_GUARD) {
+            if (lprec == TMS_PREC_FP32_GUARD) {
                 {
                     TimedScope ts_(ctx, TMS_T_COMPACT);
                     HIPCK(launch_guard_list_flags(ctx->dec.as<uint8_t>(), nq,
@@ -1773,9 +1814,12 @@ int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
         return fail(ctx, TMS_E_INVALID, "tiled_min_level outside 1..4");
     if (t->tile_atoms != 8 && t->tile_atoms != 16 && t->tile_atoms != 32)
         return fail(ctx, TMS_E_INVALID, "tile_atoms must be 8, 16 or 32");
+    if (t->proj_table != 0 && t->proj_table != 1)
+        return fail(ctx, TMS_E_INVALID, "proj_table must be 0 or 1");
     ctx->slice_cubes = t->slice_cubes;
     ctx->tiled_min_level = t->tiled_min_level;
     ctx->tile_atoms = t->tile_atoms;
+    ctx->proj_table = t->proj_table;
     return TMS_OK;
 }
 
@@ -1784,6 +1828,8 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t) {
     t->slice_cubes = ctx->slice_cubes;
     t->tiled_min_level = ctx->tiled_min_level;
     t->tile_atoms = ctx->tile_atoms;
+    t->proj_table = ctx->proj_table;
+    t->reserved = 0;
     return TMS_OK;
 }
 
@@ -1837,6 +1883,11 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
         if (ch == b.tile_atoms) continue;
         tms_tuning t = b;
         t.tile_atoms = ch;
+        if ((rc = consider(t))) return rc;
+    }
+    {
+        tms_tuning t = b;
+        t.proj_table = 1 - b.proj_table;
         if ((rc = consider(t))) return rc;
     }
     const tms_tuning bch = b;

@@ -59,6 +59,21 @@ struct GLRule {
     T t[8], c0[8], c1[8], c2[8], c3[8], cs[8];
 };
 
+// Per-level table of the 1-D projections of Section 2.2.1 (eq. 1D-project):
+// for every atom i, axis a and interval j of the level's lattice within R_c
+// of the atom along that axis, the four Legendre coefficients of the atom's
+// Gaussian factor on that interval, their exponential error bound and the
+// squared distance from the atom to the interval, at
+// t[6 * ((a * n + i) * ns + (j - first))], first = one interval below the
+// one holding x_a - R_c.  Projections farther than R_c are zero.  Built once
+// per level; the tiled estimate gathers from it instead of recomputing each
+// projection for every chunk that needs it.
+struct ProjTab {
+    const double *t = nullptr;   // null: projections are computed in place
+    int64_t n = 0;               // atoms
+    int ns = 0;                  // intervals per (axis, atom)
+};
+
 // Number of positive nodes (half the rule) used on a level whose cubes have
 // half-width s: chosen from beta = s sqrt(D) so that the quadrature error of
 // the projection stays below the arithmetic's own rounding.
@@ -131,7 +146,8 @@ struct tms_graph_state {
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
         lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, verts,
-        etab, sz, ctr, stmp, seg;
+        etab, sz, ctr, stmp, seg, ptab;
+    bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
 };
@@ -174,6 +190,8 @@ struct tms_ctx {
     int64_t slice_cubes = (int64_t)1 << 26;
     int tiled_min_level = 2;
     int tile_atoms = 16;
+    int proj_table = 1;     // tiled levels gather 1-D projections from a table
+    tms::DevBuf ptab;       // that table
     tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -272,7 +290,14 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *ax, const double *ay, const double *az,
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
-                                  int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr);
+                                  int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
+                                  const ProjTab &pt = ProjTab{});
+// intervals per (axis, atom) of the projection table of a level
+int proj_table_slots(const tms_cells *cells, int level);
+// fill the projection table (t: [3 n ns][6] doubles)
+hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level, int precision,
+                             const double *ax, const double *ay, const double *az, int64_t n,
+                             int ns, double *t, hipStream_t s);
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s);

@@ -44,10 +44,10 @@ class Timing(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("slice_cubes", C.c_int64), ("tiled_min_level", C.c_int32),
-                ("tile_atoms", C.c_int32)]
+                ("tile_atoms", C.c_int32), ("proj_table", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class TmsError(RuntimeError):
@@ -421,7 +421,8 @@ class Context:
         return r + ((lo, vo),) if offsets else r
 
     # ---------------------------------------------------------------- tuning
-    def set_tuning(self, slice_cubes=None, tiled_min_level=None, tile_atoms=None):
+    def set_tuning(self, slice_cubes=None, tiled_min_level=None, tile_atoms=None,
+                   proj_table=None):
         t = self.get_tuning()
         if slice_cubes is not None:
             t.slice_cubes = int(slice_cubes)
@@ -429,6 +430,8 @@ class Context:
             t.tiled_min_level = int(tiled_min_level)
         if tile_atoms is not None:
             t.tile_atoms = int(tile_atoms)
+        if proj_table is not None:
+            t.proj_table = int(proj_table)
         self._check(self.lib.tms_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self) -> Tuning:

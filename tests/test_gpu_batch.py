@@ -159,18 +159,55 @@ def test_tuning_does_not_change_results(ctx):
     cells = ctx.build_cells_batch(confs, p)
     base = ctx.get_tuning().as_dict()
     ref = None
-    for tml, ch, sc in [(2, 16, 1 << 25), (1, 8, 4096), (3, 32, 5000), (4, 16, 1 << 23)]:
-        ctx.set_tuning(slice_cubes=sc, tiled_min_level=tml, tile_atoms=ch)
+    counts = {}
+    for tml, ch, sc, pt in [(2, 16, 1 << 25, 1), (1, 8, 4096, 0), (3, 32, 5000, 1),
+                            (2, 16, 1 << 23, 1), (1, 16, 1 << 25, 1), (2, 32, 4096, 0),
+                            (2, 8, 1 << 25, 0), (4, 16, 1 << 23, 1)]:
+        ctx.set_tuning(slice_cubes=sc, tiled_min_level=tml, tile_atoms=ch, proj_table=pt)
         leaves, cphi, st = ctx.partition_estimate(cells)
-        got = (tms.leaves_to_numpy(leaves).tobytes(), cphi.cpu().numpy().tobytes(),
-               st["n_est"], st["n_bound"])
+        got = (tms.leaves_to_numpy(leaves).tobytes(), cphi.cpu().numpy().tobytes(), st["n_est"])
         if ref is None:
             ref = got
-        assert got == ref, (tml, ch, sc)
+        assert got == ref, (tml, ch, sc, pt)
+        # with the table the tiled levels are exact, so the bound and guard
+        # counts (not the results) depend on the first tiled level and on it
+        key = (tml if pt else 0, pt)
+        counts.setdefault(key, (st["n_bound"], st["guard_cubes"]))
+        assert counts[key] == (st["n_bound"], st["guard_cubes"]), (tml, ch, sc, pt)
     with pytest.raises(tms.TmsError):
         ctx.set_tuning(tile_atoms=12)
+    with pytest.raises(tms.TmsError):
+        ctx.set_tuning(proj_table=2)
     best, ms, n = ctx.autotune(cells)
     print("autotune: %s in %.2f ms after %d passes" % (best, ms, n))
     assert n >= 8 and ms > 0
     ctx.set_tuning(**base)
     ctx.free_cells(cells)
+
+
+@pytest.mark.parametrize("prec", [tms.PREC_FP64, tms.PREC_FP32_GUARD], ids=["fp64", "fp32g"])
+def test_projection_table_is_bit_identical(ctx, prec):
+    # a 3000-atom globule with hydrogens (levels 2 and 3 tiled): in double
+    # precision the pass that gathers projections from the table and the one
+    # that projects in place agree bit for bit, down to the bound counts; in
+    # FP32+guard mode the table makes the tiled levels exact, so the leaves
+    # and corner values agree (the guard's purpose) and the bound count
+    # equals that of the double-precision pass on those levels
+    atoms = synth.add_hydrogens(synth.globule(3000, 2300), 0.1, 2301)
+    base = ctx.get_tuning().as_dict()
+    out = {}
+    for pr in {prec, tms.PREC_FP64}:
+        cells = ctx.build_cells(atoms, tms.make_params(D=0.9, tau=1e-3, precision=pr))
+        for pt in (0, 1):
+            ctx.set_tuning(proj_table=pt)
+            leaves, cphi, st = ctx.partition_estimate(cells)
+            out[pr, pt] = (tms.leaves_to_numpy(leaves).tobytes(), cphi.cpu().numpy().tobytes(),
+                           st["n_est"], st["n_pairs"], st["n_bound"], st["guard_cubes"],
+                           st["n_pairs_lvl"])
+        ctx.free_cells(cells)
+    ctx.set_tuning(**base)
+    assert out[tms.PREC_FP64, 0] == out[tms.PREC_FP64, 1]
+    if prec == tms.PREC_FP32_GUARD:
+        a, b = out[prec, 0], out[prec, 1]
+        assert a[:4] == b[:4]
+        assert b[5] <= a[5]  # guards only on the levels estimated per thread
