@@ -136,6 +136,26 @@ __device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, co
     if (valid) o.dec[qi] = d;
 }
 
+// Projection of atom i on interval j along `axis` from the table, when the
+// interval has a slot in the atom's row (it always has when it lies within
+// R_c); false: not tabulated, project in place.  The table and the
+// in-place projection agree bit for bit (lo + s, the interval's midpoint,
+// is the same double for the lattice index j).
+__device__ __forceinline__ bool tab_proj(const ProjTab &P, int axis, int64_t i, int j,
+                                         double a[4], double &err) {
+    const int64_t ia = (int64_t)axis * P.n + i;
+    const int slot = j - P.lo[ia];
+    if (slot < 0 || slot >= P.ns) return false;
+    const double2 *src = reinterpret_cast<const double2 *>(P.t + 6 * (ia * P.ns + slot));
+    const double2 u0 = src[0], u1 = src[1], u2 = src[2];
+    a[0] = u0.x;
+    a[1] = u0.y;
+    a[2] = u1.x;
+    a[3] = u1.y;
+    err = u2.x;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Tensor estimate, one thread per cube.  The thread walks its root's
 // neighbourhood list (threads of a wavefront usually share a root, so the
@@ -153,7 +173,7 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
     double *__restrict__ Aout, double *__restrict__ Eout, EstOut o,
-    unsigned long long *__restrict__ pairs) {
+    unsigned long long *__restrict__ pairs, ProjTab P) {
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     unsigned long long np = 0;
     const int64_t n_ = o.ncount ? min((int64_t)*o.ncount, n) : n;
@@ -184,9 +204,12 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
             if (dx * dx + dy * dy + dz * dz > rc2) continue;
             ++np;
             double px[4], py[4], pz[4], ex, ey, ez;
-            project<FAST, QH>(R, g.D, s, mid[0] - x, px, ex);
-            project<FAST, QH>(R, g.D, s, mid[1] - y, py, ey);
-            project<FAST, QH>(R, g.D, s, mid[2] - z, pz, ez);
+            if (!P.t || !tab_proj(P, 0, i, c.x, px, ex))
+                project<FAST, QH>(R, g.D, s, mid[0] - x, px, ex);
+            if (!P.t || !tab_proj(P, 1, i, c.y, py, ey))
+                project<FAST, QH>(R, g.D, s, mid[1] - y, py, ey);
+            if (!P.t || !tab_proj(P, 2, i, c.z, pz, ez))
+                project<FAST, QH>(R, g.D, s, mid[2] - z, pz, ez);
             const double w = aw[i];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -477,7 +500,7 @@ template <bool FAST, int QH>
 __global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, GLRule<double> R,
                              const double *__restrict__ ax, const double *__restrict__ ay,
                              const double *__restrict__ az, int64_t n, int ns,
-                             double *__restrict__ T) {
+                             int32_t *__restrict__ ilo, double *__restrict__ T) {
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= 3 * n * ns) return;
     const int64_t ia = t / ns;  // axis * n + atom
@@ -488,6 +511,7 @@ __global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, 
     const double x = axis == 0 ? ax[i] : (axis == 1 ? ay[i] : az[i]);
     const double h = ldexp(g.h0, -level), s = 0.5 * h;
     const int first = proj_first(x, g.o[axis], sqrt(g.rc2), h);
+    if (slot == 0) ilo[ia] = first;
     const double lo = g.o[axis] + (double)(first + slot) * h, hi = lo + h;
     const double d = fmax(fmax(lo - x, x - hi), 0.0);
     double pr[4] = {0.0, 0.0, 0.0, 0.0}, err = 0.0;
@@ -737,14 +761,15 @@ hipError_t estimate_thread_t(const Grid *g, int level, const int4 *q, int64_t n,
                              const int32_t *subset, const int32_t *rs, const int32_t *ra,
                              const double *ax, const double *ay, const double *az, const double *aw,
                              double *A, double *E, const EstOut *o, unsigned long long *pairs,
-                             hipStream_t s) {
+                             const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
     if (o)
         hipLaunchKernelGGL((k_estimate_thread<FAST, QH, true>), dim3(nblk(n)), dim3(kBS), 0, s, g,
-                           level, R, q, n, subset, rs, ra, ax, ay, az, aw, A, E, *o, pairs);
+                           level, R, q, n, subset, rs, ra, ax, ay, az, aw, A, E, *o, pairs, P);
     else
         hipLaunchKernelGGL((k_estimate_thread<FAST, QH, false>), dim3(nblk(n)), dim3(kBS), 0, s, g,
-                           level, R, q, n, subset, rs, ra, ax, ay, az, aw, A, E, EstOut{}, pairs);
+                           level, R, q, n, subset, rs, ra, ax, ay, az, aw, A, E, EstOut{}, pairs,
+                           P);
     return hipGetLastError();
 }
 
@@ -790,9 +815,9 @@ hipError_t thread_dispatch(int qh, const Grid *g, int level, const int4 *q, int6
                            const int32_t *subset, const int32_t *rs, const int32_t *ra,
                            const double *ax, const double *ay, const double *az, const double *aw,
                            double *A, double *E, const EstOut *o, unsigned long long *pairs,
-                           hipStream_t s) {
+                           const ProjTab &P, hipStream_t s) {
     TMS_QH_SWITCH(qh, (estimate_thread_t<FAST, QH>(g, level, q, n, subset, rs, ra, ax, ay, az, aw,
-                                                   A, E, o, pairs, s)))
+                                                   A, E, o, pairs, P, s)))
 }
 
 template <bool FAST>
@@ -807,18 +832,19 @@ hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *
 
 template <bool FAST, int QH>
 hipError_t proj_table_t(const Grid *gt, int nconf, int level, const double *ax, const double *ay,
-                        const double *az, int64_t n, int ns, double *t, hipStream_t s) {
+                        const double *az, int64_t n, int ns, int32_t *lo, double *t,
+                        hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
     hipLaunchKernelGGL((k_proj_table<FAST, QH>), dim3(nblk(3 * n * ns)), dim3(kBS), 0, s, gt, nconf,
-                       level, R, ax, ay, az, n, ns, t);
+                       level, R, ax, ay, az, n, ns, lo, t);
     return hipGetLastError();
 }
 
 template <bool FAST>
 hipError_t proj_table_dispatch(int qh, const Grid *gt, int nconf, int level, const double *ax,
-                               const double *ay, const double *az, int64_t n, int ns, double *t,
-                               hipStream_t s) {
-    TMS_QH_SWITCH(qh, (proj_table_t<FAST, QH>(gt, nconf, level, ax, ay, az, n, ns, t, s)))
+                               const double *ay, const double *az, int64_t n, int ns, int32_t *lo,
+                               double *t, hipStream_t s) {
+    TMS_QH_SWITCH(qh, (proj_table_t<FAST, QH>(gt, nconf, level, ax, ay, az, n, ns, lo, t, s)))
 }
 
 }  // namespace
@@ -922,9 +948,9 @@ hipError_t launch_estimate(const Grid &g, const Grid *gt, int level, int precisi
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
     if (precision == TMS_PREC_FP32_GUARD)
         return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,
-                                     az, aw, A, S, nullptr, pc, s);
+                                     az, aw, A, S, nullptr, pc, ProjTab{}, s);
     return thread_dispatch<false>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay, az,
-                                  aw, A, S, nullptr, pc, s);
+                                  aw, A, S, nullptr, pc, ProjTab{}, s);
 }
 
 hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int precision,
@@ -951,9 +977,9 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
     }
     if (fast)
         return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,
-                                     az, aw, nullptr, nullptr, &o, pc, s);
+                                     az, aw, nullptr, nullptr, &o, pc, pt, s);
     return thread_dispatch<false>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay, az,
-                                  aw, nullptr, nullptr, &o, pc, s);
+                                  aw, nullptr, nullptr, &o, pc, pt, s);
 }
 
 int proj_table_slots(const tms_cells *cells, int level) {
@@ -965,12 +991,12 @@ int proj_table_slots(const tms_cells *cells, int level) {
 
 hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level, int precision,
                              const double *ax, const double *ay, const double *az, int64_t n,
-                             int ns, double *t, hipStream_t s) {
+                             int ns, int32_t *lo, double *t, hipStream_t s) {
     if (n <= 0 || ns <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     if (precision == TMS_PREC_FP32_GUARD)
-        return proj_table_dispatch<true>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
-    return proj_table_dispatch<false>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
+        return proj_table_dispatch<true>(qh, gt, nconf, level, ax, ay, az, n, ns, lo, t, s);
+    return proj_table_dispatch<false>(qh, gt, nconf, level, ax, ay, az, n, ns, lo, t, s);
 }
 
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,

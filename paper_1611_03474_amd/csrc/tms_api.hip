@@ -105,7 +105,7 @@ void tms_graph_state::release() {
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
-                        &stmp, &seg, &ptab};
+                        &stmp, &seg, &ptab, &pilo};
     for (auto *x : b) x->release();
 }
 
@@ -915,17 +915,14 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.ctr.ensure(sizeof(unsigned long long) * kCtSlots));
     HIPCK(G.stmp.ensure(scan_tmp_bytes(std::max(nmax, std::max(cwords, ewords))) + 512));
     HIPCK(G.seg.ensure(sizeof(int64_t) * 2 * (size_t)(G.nlev * G.nconf)));
-    // projection tables of the tiled levels (one buffer, refilled per level;
-    // the finest tiled level has the most intervals per atom)
+    // projection tables (one buffer, refilled per level; the finest level
+    // has the most intervals per atom)
     G.proj_table = false;
     if (ctx->proj_table && cells->n > 0) {
-        int ns = 0;
-        for (int lev = std::max(ctx->tiled_min_level, 0); lev <= std::min(3, g.K); ++lev)
-            ns = std::max(ns, proj_table_slots(cells, lev));
-        if (ns > 0) {
-            HIPCK(G.ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)ns));
-            G.proj_table = true;
-        }
+        const int ns = proj_table_slots(cells, g.K);
+        HIPCK(G.ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)ns));
+        HIPCK(G.pilo.ensure(sizeof(int32_t) * 3 * (size_t)cells->n));
+        G.proj_table = true;
     }
     hipStream_t s = ctx->stream;
     HIPCK(hipMemsetAsync(G.q[0].p, 0, G.q[0].cap, s));
@@ -977,13 +974,13 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
         ProjTab pt;
         int lprec = prec;  // precision of this level's estimate
-        if (tiled && G.proj_table) {
+        if (G.proj_table) {
             // tabulated projections are exact in either mode
             lprec = TMS_PREC_FP64;
             const int pns = proj_table_slots(cells, lev);
             HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, ax, ay, az, cells->n, pns,
-                                    G.ptab.as<double>(), s));
-            pt = ProjTab{G.ptab.as<double>(), cells->n, pns};
+                                    G.pilo.as<int32_t>(), G.ptab.as<double>(), s));
+            pt = ProjTab{G.ptab.as<double>(), G.pilo.as<int32_t>(), cells->n, pns};
         }
         HIPCK(launch_slice_counts(nq + lev, S, nsl, ns, s));
         for (int k = 0; k < nsl; ++k) {
@@ -1238,21 +1235,22 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
             ProjTab pt;
             int lprec = prec;  // precision of this level's estimate
-            if (tiled && ctx->proj_table) {
-                // the table amortises the exponentials over every chunk that
+            if (ctx->proj_table) {
+                // the table amortises the exponentials over every cube that
                 // reads an entry, so its projections are exact in either mode
-                // (and this level needs no guard)
+                // (and the level needs no guard)
                 lprec = TMS_PREC_FP64;
                 const int ns = proj_table_slots(cells, lev);
                 const int64_t na = cells->n;
                 HIPCK(ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)na * (size_t)ns));
+                HIPCK(ctx->pilo.ensure(sizeof(int32_t) * 3 * (size_t)na));
                 {
-                    TimedScope ts_(ctx, TMS_T_TILED);
+                    TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
                     HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, cells->ax.as<double>(),
                                             cells->ay.as<double>(), cells->az.as<double>(), na, ns,
-                                            ctx->ptab.as<double>(), s));
+                                            ctx->pilo.as<int32_t>(), ctx->ptab.as<double>(), s));
                 }
-                pt = ProjTab{ctx->ptab.as<double>(), na, ns};
+                pt = ProjTab{ctx->ptab.as<double>(), ctx->pilo.as<int32_t>(), na, ns};
             }
             for (int64_t k = 0; k < nslices; ++k) {
                 const int64_t off = k * S, ns = std::min(S, nq - off);
