@@ -135,38 +135,67 @@ __device__ __forceinline__ void imul(double a0, double a1, double b0, double b1,
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric 4x4 eigen-decomposition by cyclic Jacobi rotations.
+// Symmetric 4x4 eigen-decomposition by Jacobi rotations in the parallel
+// (round-robin) ordering: each sweep is three rounds of two rotations on
+// disjoint index pairs, (0,1)+(2,3), (0,2)+(1,3), (0,3)+(1,2).  The two
+// rotations of a round commute, so both parameter sets are taken from the
+// matrix before the round -- two independent dependency chains per round.
 // S is overwritten (diagonal = eigenvalues); V receives eigenvectors as
 // columns; lam/vec are returned sorted by descending eigenvalue.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void jacobi_rot(double S[4][4], double V[4][4], int p, int q) {
-    double spq = S[p][q];
-    if (spq == 0.0) return;
-    double theta = (S[q][q] - S[p][p]) / (2.0 * spq);
-    double t;
-    if (fabs(theta) > 1e150)
-        t = 0.5 / theta;
-    else
-        t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
-    double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+struct JRot {
+    double c, s, t;
+    bool on;
+};
+
+// Rotation [[c, s], [-s, c]] on (p, q) that zeroes e in [[a, e], [e, b]]:
+// t = tan(angle) is the root of smaller magnitude of t^2 + 2 theta t - 1 = 0,
+// theta = (b - a) / (2 e), written as 2 e / (d + sign(d) sqrt(d^2 + 4 e^2))
+// with d = b - a; then the new diagonal is a - t e, b + t e.
+__device__ __forceinline__ JRot jrot_params(double a, double b, double e) {
+    JRot R{1.0, 0.0, 0.0, false};
+    if (e == 0.0) return R;
+    const double d = b - a, r = sqrt(d * d + 4.0 * e * e);
+    if (!(r > 0.0)) return R;  // e negligible (its square underflows)
+    R.t = 2.0 * e / (d + copysign(r, d));
+    R.c = rsqrt(1.0 + R.t * R.t);
+    R.s = R.t * R.c;
+    R.on = true;
+    return R;
+}
+
+__device__ __forceinline__ void jrot_apply(double S[4][4], double V[4][4], int p, int q,
+                                           const JRot &R) {
+    if (!R.on) return;
+    const double e = S[p][q];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double kp = S[k][p], kq = S[k][q];
-        S[k][p] = c * kp - s * kq;
-        S[k][q] = s * kp + c * kq;
+        if (k == p || k == q) continue;
+        const double g = S[k][p], h = S[k][q];
+        const double np = R.c * g - R.s * h, nq = R.s * g + R.c * h;
+        S[k][p] = np;
+        S[p][k] = np;
+        S[k][q] = nq;
+        S[q][k] = nq;
     }
+    S[p][p] -= R.t * e;
+    S[q][q] += R.t * e;
+    S[p][q] = 0.0;
+    S[q][p] = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double pk = S[p][k], qk = S[q][k];
-        S[p][k] = c * pk - s * qk;
-        S[q][k] = s * pk + c * qk;
+        const double g = V[k][p], h = V[k][q];
+        V[k][p] = R.c * g - R.s * h;
+        V[k][q] = R.s * g + R.c * h;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double kp = V[k][p], kq = V[k][q];
-        V[k][p] = c * kp - s * kq;
-        V[k][q] = s * kp + c * kq;
-    }
+}
+
+__device__ __forceinline__ void jrot_round(double S[4][4], double V[4][4], int p1, int q1, int p2,
+                                           int q2) {
+    const JRot A = jrot_params(S[p1][p1], S[q1][q1], S[p1][q1]);
+    const JRot B = jrot_params(S[p2][p2], S[q2][q2], S[p2][q2]);
+    jrot_apply(S, V, p1, q1, A);
+    jrot_apply(S, V, p2, q2, B);
 }
 
 __device__ __forceinline__ void eig4_sorted(double S[4][4], double lam[4], double V[4][4]) {
@@ -179,12 +208,9 @@ __device__ __forceinline__ void eig4_sorted(double S[4][4], double lam[4], doubl
                      S[1][2] * S[1][2] + S[1][3] * S[1][3] + S[2][3] * S[2][3];
         double dg = S[0][0] * S[0][0] + S[1][1] * S[1][1] + S[2][2] * S[2][2] + S[3][3] * S[3][3];
         if (off <= 1e-34 * dg || off == 0.0) break;
-        jacobi_rot(S, V, 0, 1);
-        jacobi_rot(S, V, 0, 2);
-        jacobi_rot(S, V, 0, 3);
-        jacobi_rot(S, V, 1, 2);
-        jacobi_rot(S, V, 1, 3);
-        jacobi_rot(S, V, 2, 3);
+        jrot_round(S, V, 0, 1, 2, 3);
+        jrot_round(S, V, 0, 2, 1, 3);
+        jrot_round(S, V, 0, 3, 1, 2);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) lam[i] = S[i][i];
