@@ -319,7 +319,7 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
 /* ---- tuning ---------------------------------------------------------------
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
- * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 16,
+ * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 8,
  * proj_table 1. */
 typedef struct {
     int64_t slice_cubes;     /* largest queue slice per estimate + bound

@@ -535,7 +535,9 @@ __global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, 
 // 0.25 band * amp).
 constexpr double kKappa = 8.0;
 
-__global__ __launch_bounds__(kBS) void k_bound(Grid g, int level, int fast, EstOut o) {
+template <bool FAST>
+__global__ __launch_bounds__(kBS, 2) void k_bound(Grid g, int level, EstOut o) {
+    __shared__ double wsh[20 * kBS];
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= (int64_t)*o.hardCount) return;
     double A[64];
@@ -544,8 +546,8 @@ __global__ __launch_bounds__(kBS) void k_bound(Grid g, int level, int fast, EstO
     for (int e = 0; e < 64; ++e) A[e] = src[e];
     double E, asum;
     masses(A, E, asum);
-    const double band = error_band(fast != 0, o.hardE[t], asum);
-    const BoundResult B = nested_bound(A, band);
+    const double band = error_band(FAST, o.hardE[t], asum);
+    const BoundResult B = nested_bound<FAST>(A, band, wsh + threadIdx.x, kBS);
     uint8_t d;
     const double tol = kKappa * band * B.amp + B.jump;
     if (band > 0.0 && (fabs(B.L - g.c) <= tol || fabs(B.U - g.c) <= tol))
@@ -737,12 +739,13 @@ __global__ void k_level_histo_final(const unsigned long long *__restrict__ part,
 __global__ __launch_bounds__(kBS) void k_bound_debug(const double *__restrict__ Ain,
                                                      const double *__restrict__ band, int64_t n,
                                                      double *__restrict__ out) {
+    __shared__ double wsh[20 * kBS];
     int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= n) return;
     double A[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) A[e] = Ain[64 * t + e];
-    BoundResult B = nested_bound(A, band ? band[t] : 0.0);
+    BoundResult B = nested_bound(A, band ? band[t] : 0.0, wsh + threadIdx.x, kBS);
     out[6 * t + 0] = B.L;
     out[6 * t + 1] = B.U;
     out[6 * t + 2] = B.rho;
@@ -1004,8 +1007,10 @@ hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, 
                         hipStream_t s) {
     if (max_n <= 0) return hipSuccess;
     EstOut o{dec, hardA, hardE, hardIdx, hardCount, nullptr};
-    hipLaunchKernelGGL(k_bound, dim3(nblk(max_n)), dim3(kBS), 0, s, g, level,
-                       precision == TMS_PREC_FP32_GUARD ? 1 : 0, o);
+    if (precision == TMS_PREC_FP32_GUARD)
+        hipLaunchKernelGGL(k_bound<true>, dim3(nblk(max_n)), dim3(kBS), 0, s, g, level, o);
+    else
+        hipLaunchKernelGGL(k_bound<false>, dim3(nblk(max_n)), dim3(kBS), 0, s, g, level, o);
     return hipGetLastError();
 }
 

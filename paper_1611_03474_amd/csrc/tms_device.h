@@ -292,7 +292,12 @@ __device__ __forceinline__ double sgap(const double s[4], int i) {
 // Legendre series range lies in [-2, 2] (|sum q_j L_j| <= |q|_1 <= 2), so
 // adding or dropping inner term k of outer term i moves L and U by at most
 // 16 sigma_i d_k, and an outer term i by at most 32 sigma_i.
-__device__ inline BoundResult nested_bound(double *A, double band) {
+// BAND = false: exact tensors (band is 0 and the perturbation terms are not
+// formed).  The outer singular vectors and values are parked in LDS (ws:
+// this thread's 20 doubles at stride wstride) while the inner problems run,
+// which keeps the register footprint within two waves per SIMD.
+template <bool BAND = true>
+__device__ inline BoundResult nested_bound(double *A, double band, double *ws, int wstride) {
     BoundResult R;
     R.jump = 0.0;
     R.amp = 1.0;
@@ -314,15 +319,23 @@ __device__ inline BoundResult nested_bound(double *A, double band) {
     double mhi, mlo;
     int r = rank99(sig, mhi, mlo);
     R.r = r;
-    if (band > 0.0) {
+    if (BAND && band > 0.0) {
         // cum_r and the 0.99 target move by at most (r + 4) band <= 8 band
         if (mhi <= 8.0 * band && r < 4) R.jump += 32.0 * sig[r];
         if (mlo <= 8.0 * band && r > 0) R.jump += 32.0 * sig[r - 1];
     }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) ws[(4 * a + b) * wstride] = W[a][b];
+        ws[(16 + a) * wstride] = sig[a];
+    }
     double Msum = 0.0, msum = 0.0;
     for (int i = 0; i < r; ++i) {
-        double u[4] = {W[0][i], W[1][i], W[2][i], W[3][i]};
-        double inv = 1.0 / sig[i];
+        double u[4] = {ws[i * wstride], ws[(4 + i) * wstride], ws[(8 + i) * wstride],
+                       ws[(12 + i) * wstride]};
+        const double sgi = ws[(16 + i) * wstride];
+        double inv = 1.0 / sgi;
         double v[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e)
@@ -339,22 +352,36 @@ __device__ inline BoundResult nested_bound(double *A, double band) {
                 H[k2][k] = g;
             }
         eig4_sorted(H, mu, Z);
+        // v again, from A (unchanged so far) -- the same operations, hence the
+        // same bits; the empty asm hides the equality from the optimiser so v
+        // is not held in registers across the eigen-solve
+        {
+            double uu[4] = {u[0], u[1], u[2], u[3]}, iv = inv;
+            __asm__ volatile("" : "+v"(uu[0]), "+v"(uu[1]), "+v"(uu[2]), "+v"(uu[3]), "+v"(iv));
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                v[e] = (uu[0] * A[e] + uu[1] * A[16 + e] + uu[2] * A[32 + e] + uu[3] * A[48 + e]) *
+                       iv;
+        }
         double d[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) d[k] = sqrt(fmax(mu[k], 0.0));
         double nhi, nlo;
         int ri = rank99(d, nhi, nlo);
-        if (band > 0.0) {
+        if (BAND && band > 0.0) {
             // outer rotation of (u_i, v_i) and the inner perturbation of V_i
-            const double go = sgap(sig, i);
+            double sv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) sv[a] = ws[(16 + a) * wstride];
+            const double go = sgap(sv, i);
             const double rot = (go > 0.0) ? band / go : 1e300;
             const double dv = band * inv + rot;  // |dV_i| (unit-norm matrix)
             double dg = 1e300;
             for (int k = 0; k < ri; ++k) dg = fmin(dg, sgap(d, k));
             const double irot = (dg > 0.0) ? dv / dg : 1e300;
-            R.amp += sig[i] * (rot + irot) / band + 1.0;
-            if (nhi <= 8.0 * dv && ri < 4) R.jump += 16.0 * sig[i] * d[ri];
-            if (nlo <= 8.0 * dv && ri > 0) R.jump += 16.0 * sig[i] * d[ri - 1];
+            R.amp += sgi * (rot + irot) / band + 1.0;
+            if (nhi <= 8.0 * dv && ri < 4) R.jump += 16.0 * sgi * d[ri];
+            if (nlo <= 8.0 * dv && ri > 0) R.jump += 16.0 * sgi * d[ri - 1];
         }
         double ux0, ux1;
         leg3_range(u, ux0, ux1);
@@ -367,7 +394,7 @@ __device__ inline BoundResult nested_bound(double *A, double band) {
             for (int l = 0; l < 4; ++l)
                 z[l] = (w[0] * v[l] + w[1] * v[4 + l] + w[2] * v[8 + l] + w[3] * v[12 + l]) * iz;
             // residual: A -= sigma_i u_i (x) d_k w_k (x) z_k  (eq. SVD7)
-            double coef = sig[i] * d[k];
+            double coef = sgi * d[k];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -385,8 +412,8 @@ __device__ inline BoundResult nested_bound(double *A, double band) {
         }
         double q0, q1;
         imul(ux0, ux1, myz, Myz, q0, q1);
-        Msum += sig[i] * q1;
-        msum += sig[i] * q0;
+        Msum += sgi * q1;
+        msum += sgi * q0;
     }
     double rho = 0.0;
 #pragma unroll
