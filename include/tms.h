@@ -297,7 +297,10 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
  * tms_graph_capture: requires an eager tms_partition_estimate and
  * tms_extract_cube_vertices of `cells` (the last ones on ctx); margin in
  * [1, 64].  The context keeps one capture (private buffers); a new capture
- * replaces it.  Errors: TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
+ * replaces it.  The capture first frees the eager partition's workspace
+ * (queues, staged tensors, projection table), which it duplicates; kept
+ * results are untouched and the next eager pass allocates the workspace
+ * again.  Errors: TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
 int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin);
 
 /* Replay the captured pass on ctx's stream.  `cells` must be the captured
@@ -375,7 +378,8 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
 #define TMS_T_TILED 8    /* tensor estimate, one wave per chunk of
                             cubes of one root (tiled levels)           */
 #define TMS_T_BACKWARD 9 /* adjoint kernels                             */
-#define TMS_T_SLOTS 10
+#define TMS_T_TABLE 10   /* per-level projection tables                */
+#define TMS_T_SLOTS 11
 
 typedef struct {
     double ms[TMS_T_SLOTS];       /* accumulated device milliseconds */

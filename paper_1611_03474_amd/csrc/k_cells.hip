@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kBS) void k_stats_conf(const double *__restrict__ x
 }
 
 __device__ __forceinline__ int cell_of(const Grid &g, double x, int a) {
-    return clampi((int)floor((x - g.o[a]) / g.cs), 0, g.nc[a] - 1);
+    return clampi((int)floor(over_cs(g, x - g.o[a])), 0, g.nc[a] - 1);
 }
 
 __global__ void k_bin(const Grid *__restrict__ gt, int nconf, const double *__restrict__ xyzr,
@@ -154,8 +154,8 @@ __global__ void k_root_lists(const Grid *__restrict__ gt, int nconf, const int32
     double R = sqrt(rc2);
     int c0[3], c1[3];
     for (int a = 0; a < 3; ++a) {
-        c0[a] = clampi((int)floor((lo[a] - R - g.o[a]) / g.cs), 0, g.nc[a] - 1);
-        c1[a] = clampi((int)floor((hi[a] + R - g.o[a]) / g.cs), 0, g.nc[a] - 1);
+        c0[a] = clampi((int)floor(over_cs(g, lo[a] - R - g.o[a])), 0, g.nc[a] - 1);
+        c1[a] = clampi((int)floor(over_cs(g, hi[a] + R - g.o[a])), 0, g.nc[a] - 1);
     }
     int cnt = 0;
     int w = EMIT ? start[r] : 0;

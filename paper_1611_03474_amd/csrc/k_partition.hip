@@ -269,8 +269,21 @@ __device__ __forceinline__ int proj_first(double x, double o, double rc, double 
     return (int)floor((x - o - rc) / h) - 1;
 }
 
+constexpr int64_t kXcdBlock = 256;  // consecutive chunks per XCD turn
+
+// Bijection of [0, n): slot v = 8 j + x (x: the XCD the slot lands on) maps
+// to block (j / B) * 8 + x, offset j % B, for the slots below the last whole
+// group of 8 blocks; the remaining slots map to themselves.
+__device__ __forceinline__ int64_t xcd_chunk(int64_t v, int64_t n) {
+    const int64_t nf = n - n % (8 * kXcdBlock);
+    if (v >= nf) return v;
+    const int64_t j = v >> 3, x = v & 7;
+    return ((j / kXcdBlock) * 8 + x) * kXcdBlock + j % kXcdBlock;
+}
+
 constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
-constexpr int64_t kStrideGrid = 16384;  // workgroups of a capacity-sized tiled launch
+constexpr int64_t kStrideGrid = 2048;  // workgroups of a capacity-sized tiled launch
+                                       // (about the resident count: 256 CUs x 8)
 
 template <bool FAST, int QH, int CH>
 __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
@@ -291,9 +304,15 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     __shared__ double b_x[NB][3];
     const int lane = threadIdx.x;
     using lds_ptr = __attribute__((address_space(3))) void *;
-    // chunks in a grid-stride loop (one pass when the grid covers them all)
+    // XCD-aware assignment: the hardware deals workgroups round-robin to the
+    // 8 XCDs, each with its own L2, and neighbouring chunks read the same atoms
+    // and table rows.  Workgroup slot v (v % 8 = its XCD) takes chunk
+    // xcd_chunk(v): blocks of kXcdBlock consecutive chunks are dealt to the
+    // XCDs in turn, so an XCD works through one block at a time while the
+    // blocks of all XCDs interleave over the queue (balanced work).
     const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
-    for (int64_t cix = blockIdx.x; cix < nch; cix += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < nch; v += gridDim.x) {
+    const int64_t cix = xcd_chunk(v, nch);
     const int2 ch = chunks[cix];
     const bool valid = lane < ch.y;
     const int64_t pos = (int64_t)ch.x + (valid ? lane : 0);

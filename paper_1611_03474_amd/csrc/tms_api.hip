@@ -702,6 +702,10 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         while (g.cs < 0.25 * Rc) g.cs *= 2.0;
         while (0.5 * g.cs >= 0.25 * Rc) g.cs *= 0.5;
         g.span = (int32_t)std::ceil(Rc / g.cs);
+        {
+            int ex = 0;
+            g.inv_cs = (std::frexp(g.cs, &ex) == 0.5) ? 1.0 / g.cs : 0.0;
+        }
         int64_t nc = 1, nrt = 1;
         for (int a = 0; a < 3; ++a) {
             g.nc[a] = (int32_t)std::max(1.0, std::ceil(g.nr[a] * p->h0 / g.cs));
@@ -1245,7 +1249,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 HIPCK(ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)na * (size_t)ns));
                 HIPCK(ctx->pilo.ensure(sizeof(int32_t) * 3 * (size_t)na));
                 {
-                    TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
+                    TimedScope ts_(ctx, TMS_T_TABLE);
                     HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, cells->ax.as<double>(),
                                             cells->ay.as<double>(), cells->az.as<double>(), na, ns,
                                             ctx->pilo.as<int32_t>(), ctx->ptab.as<double>(), s));
@@ -1688,6 +1692,11 @@ int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(hipSetDevice(ctx->device));
     tms_graph_state &G = ctx->graph;
     G.release();
+    // the captured pass has private copies of the eager partition's
+    // workspace; give that back first (the next eager pass grows it again)
+    for (tms::DevBuf *b : {&ctx->q[0], &ctx->q[1], &ctx->abuf, &ctx->ebuf, &ctx->hidx, &ctx->dec,
+                           &ctx->ptab, &ctx->pilo, &ctx->chunks, &ctx->runs})
+        b->release();
     int32_t rc = plan_graph(ctx, cells, margin);
     if (rc) {
         G.release();

@@ -472,6 +472,11 @@ __device__ __forceinline__ void sample_range(const double *A, double &lo, double
     hi = fmax(hi, ctr);
 }
 
+// x / cs, as a multiplication when that is exact
+__device__ __forceinline__ double over_cs(const Grid &g, double x) {
+    return g.inv_cs != 0.0 ? x * g.inv_cs : x / g.cs;
+}
+
 // ---------------------------------------------------------------------------
 // phi and grad phi at one point (eq. Gaussian1).
 // ---------------------------------------------------------------------------
@@ -489,7 +494,7 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         // points far outside the grid (or NaN) get an empty stencil
-        const double fc = floor((p[a] - g.o[a]) / g.cs);
+        const double fc = floor(over_cs(g, p[a] - g.o[a]));
         const int ci = (fc > -1.0e8 && fc < 1.0e8) ? (int)fc : -1000000;
         c0[a] = max(ci - g.span, 0);
         c1[a] = min(ci + g.span, g.nc[a] - 1);
@@ -507,8 +512,8 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
             const double ryz = rz - ey * ey;
             if (ryz < 0.0) continue;
             const double hx = sqrt(ryz);
-            const int x0 = max(c0[0], (int)floor((p[0] - hx - g.o[0]) / g.cs));
-            const int x1 = min(c1[0], (int)floor((p[0] + hx - g.o[0]) / g.cs));
+            const int x0 = max(c0[0], (int)floor(over_cs(g, p[0] - hx - g.o[0])));
+            const int x1 = min(c1[0], (int)floor(over_cs(g, p[0] + hx - g.o[0])));
             if (x0 > x1) continue;
             const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
             const int b = cs[row + x0], e = cs[row + x1 + 1];

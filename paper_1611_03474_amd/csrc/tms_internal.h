@@ -39,6 +39,8 @@ struct Grid {
     double D, c, tau;
     double rc2;      // squared cut-off radius (this conformation's largest radius)
     double cs;       // atom-cell edge (smallest h0 * 2^m >= R_c / 4)
+    double inv_cs;   // 1 / cs when cs is a power of two (division by it is then
+                     // exact scaling, so x * inv_cs == x / cs), else 0
     int32_t nr[3];   // root cubes per axis
     int32_t nc[3];   // atom cells per axis
     int32_t K;       // finest level
