@@ -136,15 +136,24 @@ __device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, co
     if (valid) o.dec[qi] = d;
 }
 
+// First interval of an atom's row of the projection table along one axis:
+// one below the interval holding x - R_c.  Every kernel evaluates this same
+// expression (a multiplication when h is a power of two: then exact).
+__device__ __forceinline__ int proj_first(const Grid &g, int axis, double x, double rc, double h,
+                                          int level) {
+    const double u = x - g.o[axis] - rc;
+    return (int)floor(g.inv_h0 != 0.0 ? u * ldexp(g.inv_h0, level) : u / h) - 1;
+}
+
 // Projection of atom i on interval j along `axis` from the table, when the
 // interval has a slot in the atom's row (it always has when it lies within
 // R_c); false: not tabulated, project in place.  The table and the
 // in-place projection agree bit for bit (lo + s, the interval's midpoint,
 // is the same double for the lattice index j).
-__device__ __forceinline__ bool tab_proj(const ProjTab &P, int axis, int64_t i, int j,
+__device__ __forceinline__ bool tab_proj(const ProjTab &P, int axis, int64_t i, int j, int first,
                                          double a[4], double &err) {
     const int64_t ia = (int64_t)axis * P.n + i;
-    const int slot = j - P.lo[ia];
+    const int slot = j - first;
     if (slot < 0 || slot >= P.ns) return false;
     const double2 *src = reinterpret_cast<const double2 *>(P.t + 6 * (ia * P.ns + slot));
     const double2 u0 = src[0], u1 = src[1], u2 = src[2];
@@ -193,7 +202,7 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
         const double s = 0.5 * h;
         const int64_t root = g.root_base +
             ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
-        const double rc2 = g.rc2;
+        const double rc2 = g.rc2, rc = sqrt(rc2);
         const int b = root_start[root], e_ = root_start[root + 1];
         for (int p = b; p < e_; ++p) {
             const int i = root_atoms[p];
@@ -204,11 +213,11 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
             if (dx * dx + dy * dy + dz * dz > rc2) continue;
             ++np;
             double px[4], py[4], pz[4], ex, ey, ez;
-            if (!P.t || !tab_proj(P, 0, i, c.x, px, ex))
+            if (!P.t || !tab_proj(P, 0, i, c.x, proj_first(g, 0, x, rc, h, level), px, ex))
                 project<FAST, QH>(R, g.D, s, mid[0] - x, px, ex);
-            if (!P.t || !tab_proj(P, 1, i, c.y, py, ey))
+            if (!P.t || !tab_proj(P, 1, i, c.y, proj_first(g, 1, y, rc, h, level), py, ey))
                 project<FAST, QH>(R, g.D, s, mid[1] - y, py, ey);
-            if (!P.t || !tab_proj(P, 2, i, c.z, pz, ez))
+            if (!P.t || !tab_proj(P, 2, i, c.z, proj_first(g, 2, z, rc, h, level), pz, ez))
                 project<FAST, QH>(R, g.D, s, mid[2] - z, pz, ez);
             const double w = aw[i];
 #pragma unroll
@@ -262,12 +271,6 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
 // loads: no registers, many in flight); they are bit-identical to the
 // projections computed here (same lattice points, same routine).
 // ---------------------------------------------------------------------------
-// First interval of an atom's row of the projection table along one axis:
-// one below the interval holding x - R_c.  The table and the tiled kernel
-// evaluate this same expression.
-__device__ __forceinline__ int proj_first(double x, double o, double rc, double h) {
-    return (int)floor((x - o - rc) / h) - 1;
-}
 
 constexpr int64_t kXcdBlock = 256;  // consecutive chunks per XCD turn
 
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     b_x[at][a] = x[a];
-                    b_lo[at][a] = proj_first(x[a], g.o[a], rc, h);
+                    b_lo[at][a] = proj_first(g, a, x[a], rc, h, level);
                 }
             }
             nbuf += __popcll(m);
@@ -519,7 +522,7 @@ template <bool FAST, int QH>
 __global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, GLRule<double> R,
                              const double *__restrict__ ax, const double *__restrict__ ay,
                              const double *__restrict__ az, int64_t n, int ns,
-                             int32_t *__restrict__ ilo, double *__restrict__ T) {
+                             double *__restrict__ T) {
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= 3 * n * ns) return;
     const int64_t ia = t / ns;  // axis * n + atom
@@ -529,8 +532,7 @@ __global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, 
     const Grid &g = gt[conf_of_atom(gt, nconf, i)];
     const double x = axis == 0 ? ax[i] : (axis == 1 ? ay[i] : az[i]);
     const double h = ldexp(g.h0, -level), s = 0.5 * h;
-    const int first = proj_first(x, g.o[axis], sqrt(g.rc2), h);
-    if (slot == 0) ilo[ia] = first;
+    const int first = proj_first(g, axis, x, sqrt(g.rc2), h, level);
     const double lo = g.o[axis] + (double)(first + slot) * h, hi = lo + h;
     const double d = fmax(fmax(lo - x, x - hi), 0.0);
     double pr[4] = {0.0, 0.0, 0.0, 0.0}, err = 0.0;
@@ -854,19 +856,18 @@ hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *
 
 template <bool FAST, int QH>
 hipError_t proj_table_t(const Grid *gt, int nconf, int level, const double *ax, const double *ay,
-                        const double *az, int64_t n, int ns, int32_t *lo, double *t,
-                        hipStream_t s) {
+                        const double *az, int64_t n, int ns, double *t, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
     hipLaunchKernelGGL((k_proj_table<FAST, QH>), dim3(nblk(3 * n * ns)), dim3(kBS), 0, s, gt, nconf,
-                       level, R, ax, ay, az, n, ns, lo, t);
+                       level, R, ax, ay, az, n, ns, t);
     return hipGetLastError();
 }
 
 template <bool FAST>
 hipError_t proj_table_dispatch(int qh, const Grid *gt, int nconf, int level, const double *ax,
-                               const double *ay, const double *az, int64_t n, int ns, int32_t *lo,
-                               double *t, hipStream_t s) {
-    TMS_QH_SWITCH(qh, (proj_table_t<FAST, QH>(gt, nconf, level, ax, ay, az, n, ns, lo, t, s)))
+                               const double *ay, const double *az, int64_t n, int ns, double *t,
+                               hipStream_t s) {
+    TMS_QH_SWITCH(qh, (proj_table_t<FAST, QH>(gt, nconf, level, ax, ay, az, n, ns, t, s)))
 }
 
 }  // namespace
@@ -1013,12 +1014,12 @@ int proj_table_slots(const tms_cells *cells, int level) {
 
 hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level, int precision,
                              const double *ax, const double *ay, const double *az, int64_t n,
-                             int ns, int32_t *lo, double *t, hipStream_t s) {
+                             int ns, double *t, hipStream_t s) {
     if (n <= 0 || ns <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     if (precision == TMS_PREC_FP32_GUARD)
-        return proj_table_dispatch<true>(qh, gt, nconf, level, ax, ay, az, n, ns, lo, t, s);
-    return proj_table_dispatch<false>(qh, gt, nconf, level, ax, ay, az, n, ns, lo, t, s);
+        return proj_table_dispatch<true>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
+    return proj_table_dispatch<false>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
 }
 
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,

@@ -105,7 +105,7 @@ void tms_graph_state::release() {
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
-                        &stmp, &seg, &ptab, &pilo};
+                        &stmp, &seg, &ptab};
     for (auto *x : b) x->release();
 }
 
@@ -705,6 +705,7 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         {
             int ex = 0;
             g.inv_cs = (std::frexp(g.cs, &ex) == 0.5) ? 1.0 / g.cs : 0.0;
+            g.inv_h0 = (std::frexp(g.h0, &ex) == 0.5) ? 1.0 / g.h0 : 0.0;
         }
         int64_t nc = 1, nrt = 1;
         for (int a = 0; a < 3; ++a) {
@@ -925,7 +926,6 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     if (ctx->proj_table && cells->n > 0) {
         const int ns = proj_table_slots(cells, g.K);
         HIPCK(G.ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)ns));
-        HIPCK(G.pilo.ensure(sizeof(int32_t) * 3 * (size_t)cells->n));
         G.proj_table = true;
     }
     hipStream_t s = ctx->stream;
@@ -983,8 +983,8 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
             lprec = TMS_PREC_FP64;
             const int pns = proj_table_slots(cells, lev);
             HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, ax, ay, az, cells->n, pns,
-                                    G.pilo.as<int32_t>(), G.ptab.as<double>(), s));
-            pt = ProjTab{G.ptab.as<double>(), G.pilo.as<int32_t>(), cells->n, pns};
+                                    G.ptab.as<double>(), s));
+            pt = ProjTab{G.ptab.as<double>(), cells->n, pns};
         }
         HIPCK(launch_slice_counts(nq + lev, S, nsl, ns, s));
         for (int k = 0; k < nsl; ++k) {
@@ -1247,14 +1247,13 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 const int ns = proj_table_slots(cells, lev);
                 const int64_t na = cells->n;
                 HIPCK(ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)na * (size_t)ns));
-                HIPCK(ctx->pilo.ensure(sizeof(int32_t) * 3 * (size_t)na));
                 {
                     TimedScope ts_(ctx, TMS_T_TABLE);
                     HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, cells->ax.as<double>(),
                                             cells->ay.as<double>(), cells->az.as<double>(), na, ns,
-                                            ctx->pilo.as<int32_t>(), ctx->ptab.as<double>(), s));
+                                            ctx->ptab.as<double>(), s));
                 }
-                pt = ProjTab{ctx->ptab.as<double>(), ctx->pilo.as<int32_t>(), na, ns};
+                pt = ProjTab{ctx->ptab.as<double>(), na, ns};
             }
             for (int64_t k = 0; k < nslices; ++k) {
                 const int64_t off = k * S, ns = std::min(S, nq - off);
@@ -1695,7 +1694,7 @@ int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin) {
     // the captured pass has private copies of the eager partition's
     // workspace; give that back first (the next eager pass grows it again)
     for (tms::DevBuf *b : {&ctx->q[0], &ctx->q[1], &ctx->abuf, &ctx->ebuf, &ctx->hidx, &ctx->dec,
-                           &ctx->ptab, &ctx->pilo, &ctx->chunks, &ctx->runs})
+                           &ctx->ptab, &ctx->chunks, &ctx->runs})
         b->release();
     int32_t rc = plan_graph(ctx, cells, margin);
     if (rc) {

@@ -41,6 +41,7 @@ struct Grid {
     double cs;       // atom-cell edge (smallest h0 * 2^m >= R_c / 4)
     double inv_cs;   // 1 / cs when cs is a power of two (division by it is then
                      // exact scaling, so x * inv_cs == x / cs), else 0
+    double inv_h0;   // 1 / h0 when h0 is a power of two, else 0 (likewise)
     int32_t nr[3];   // root cubes per axis
     int32_t nc[3];   // atom cells per axis
     int32_t K;       // finest level
@@ -67,12 +68,11 @@ struct GLRule {
 // Gaussian factor on that interval, their exponential error bound and the
 // squared distance from the atom to the interval, at
 // t[6 * ((a * n + i) * ns + (j - first))], first = one interval below the
-// one holding x_a - R_c.  Projections farther than R_c are zero.  Built once
+// one holding x_a - R_c (every kernel evaluates the same expression for it).  Projections farther than R_c are zero.  Built once
 // per level; the tiled estimate gathers from it instead of recomputing each
 // projection for every chunk that needs it.
 struct ProjTab {
     const double *t = nullptr;   // null: projections are computed in place
-    const int32_t *lo = nullptr; // [3 n] first interval of each (axis, atom) row
     int64_t n = 0;               // atoms
     int ns = 0;                  // intervals per (axis, atom)
 };
@@ -149,7 +149,7 @@ struct tms_graph_state {
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
         lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, verts,
-        etab, sz, ctr, stmp, seg, ptab, pilo;
+        etab, sz, ctr, stmp, seg, ptab;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
@@ -194,7 +194,7 @@ struct tms_ctx {
     int tiled_min_level = 2;
     int tile_atoms = 8;
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
-    tms::DevBuf ptab, pilo; // that table and its row starts
+    tms::DevBuf ptab;       // that table
     tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
@@ -297,10 +297,10 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const ProjTab &pt = ProjTab{});
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
-// fill the projection table (t: [3 n ns][6] doubles, lo: [3 n] int32)
+// fill the projection table (t: [3 n ns][6] doubles)
 hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level, int precision,
                              const double *ax, const double *ay, const double *az, int64_t n,
-                             int ns, int32_t *lo, double *t, hipStream_t s);
+                             int ns, double *t, hipStream_t s);
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
                         hipStream_t s);
