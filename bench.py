@@ -36,9 +36,9 @@ PEAK_HBM_GBS = 8000.0
 # known size (FETCH x2.0, WRITE x1.0), mean of the level-2 and level-3
 # launches on the 110,000-atom assembly (profiles/estimate_tiled_assembly110k_traffic.md);
 # None when the kernel changed since the counters were taken
-TRAFFIC_TILED = 9.02e9
+TRAFFIC_TILED = None
 
-# algorithmic work per unit ("Measurement")
+# algorithmic work per unit
 FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
 FLOP_PER_PHI_PAIR = 14   # phi + grad per in-range (point, atom) pair, excl. exp
 

@@ -60,6 +60,7 @@ struct EstOut {
     unsigned *hardCount; // device counter (reset by the host per pass)
     const int32_t *ncount;  // device count of entries (or chunks) when the
                             // launch is sized by a capacity; null: the launch size
+    unsigned *tick = nullptr;  // [8] zeroed slot counters (capacity-sized tiled launch)
 };
 
 constexpr uint8_t DEC_HARD = 255;
@@ -288,7 +289,7 @@ constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
 constexpr int64_t kStrideGrid = 2048;  // workgroups of a capacity-sized tiled launch
                                        // (about the resident count: 256 CUs x 8)
 
-template <bool FAST, int QH, int CH>
+template <bool FAST, int QH, int CH, bool DYN>
 __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const Grid *__restrict__ gt, int level, GLRule<double> R, const int4 *__restrict__ q,
     const int32_t *__restrict__ subset, const int2 *__restrict__ chunks, int64_t nch_cap,
@@ -313,8 +314,21 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     // xcd_chunk(v): blocks of kXcdBlock consecutive chunks are dealt to the
     // XCDs in turn, so an XCD works through one block at a time while the
     // blocks of all XCDs interleave over the queue (balanced work).
+    //
+    //
+    // Slots: DYN = false, one per workgroup (the grid covers the chunks);
+    // DYN = true, a capacity-sized launch (grid a multiple of 8, o.tick zeroed):
+    // the workgroups on XCD x = blockIdx % 8 draw slots 8 t + x from their own
+    // counter tick[x] (drawn one chunk ahead), so each XCD walks its slots in
+    // order however long single chunks take.  Every workgroup stops at its
+    // first slot past the end; the counters only grow.
     const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
-    for (int64_t v = blockIdx.x; v < nch; v += gridDim.x) {
+    const unsigned xq = blockIdx.x & 7u;
+    unsigned tdraw = 0;
+    if (DYN && lane == 0) tdraw = atomicAdd(o.tick + xq, 1u);
+    int64_t v = DYN ? 8 * (int64_t)__shfl(tdraw, 0, 64) + xq : (int64_t)blockIdx.x;
+    while (v < nch) {
+    if (DYN && lane == 0) tdraw = atomicAdd(o.tick + xq, 1u);
     const int64_t cix = xcd_chunk(v, nch);
     const int2 ch = chunks[cix];
     const bool valid = lane < ch.y;
@@ -506,6 +520,8 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     }
     epilogue(g, level, FAST, A, EA, qi, valid, o);
     if (pairs) wave_add(pairs, np);
+    if (!DYN) break;
+    v = 8 * (int64_t)__shfl(tdraw, 0, 64) + xq;
     }
 }
 
@@ -805,23 +821,27 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
                             const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
     // a capacity-sized launch (chunk count on the device) takes a fixed grid
-    // that strides over the chunks; otherwise one workgroup per chunk
-    const unsigned grid =
-        (unsigned)(o.ncount ? std::min<int64_t>(nchunks, kStrideGrid) : nchunks);
+    // (a multiple of 8) drawing chunks from per-XCD counters; otherwise one
+    // workgroup per chunk
+    const bool dyn = o.ncount != nullptr;
+    if (dyn && !o.tick) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(dyn ? std::min<int64_t>((nchunks + 7) / 8 * 8, kStrideGrid)
+                                         : nchunks);
     // atoms staged per LDS tile (a tuning knob; the arithmetic is the same)
+#define TMS_TILED_LAUNCH(C, D)                                                                   \
+    hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, C, D>), dim3(grid), dim3(64), 0, s, g, level, R, \
+                       q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P)
     switch (ch) {
     case 8:
-        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 8>), dim3(grid), dim3(64), 0, s, g, level, R,
-                           q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+        if (dyn) TMS_TILED_LAUNCH(8, true); else TMS_TILED_LAUNCH(8, false);
         break;
     case 32:
-        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 32>), dim3(grid), dim3(64), 0, s, g, level,
-                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+        if (dyn) TMS_TILED_LAUNCH(32, true); else TMS_TILED_LAUNCH(32, false);
         break;
     default:
-        hipLaunchKernelGGL((k_estimate_tiled<FAST, QH, 16>), dim3(grid), dim3(64), 0, s, g, level,
-                           R, q, subset, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+        if (dyn) TMS_TILED_LAUNCH(16, true); else TMS_TILED_LAUNCH(16, false);
     }
+#undef TMS_TILED_LAUNCH
     return hipGetLastError();
 }
 
@@ -984,12 +1004,12 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount,
-                                  const ProjTab &pt) {
+                                  const ProjTab &pt, unsigned *tick) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick};
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)

@@ -105,7 +105,7 @@ void tms_graph_state::release() {
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
-                        &stmp, &seg, &ptab};
+                        &stmp, &seg, &ptab, &tick};
     for (auto *x : b) x->release();
 }
 
@@ -920,6 +920,7 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.ctr.ensure(sizeof(unsigned long long) * kCtSlots));
     HIPCK(G.stmp.ensure(scan_tmp_bytes(std::max(nmax, std::max(cwords, ewords))) + 512));
     HIPCK(G.seg.ensure(sizeof(int64_t) * 2 * (size_t)(G.nlev * G.nconf)));
+    HIPCK(G.tick.ensure(8 * sizeof(unsigned)));
     // projection tables (one buffer, refilled per level; the finest level
     // has the most intervals per atom)
     G.proj_table = false;
@@ -1003,12 +1004,14 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                             s, nruns, ns + k));
                 chunks = G.chunks.as<int2>();
                 ncount = nchunks;
+                HIPCK(launch_fill_u32(G.tick.as<uint32_t>(), 0u, 8, s));
             }
             HIPCK(launch_estimate_decide(g, gt, lev, lprec, q + off, cap, nullptr, chunks, cap, rs, ra,
                                          ax, ay, az, aw, dec + off, G.abuf.as<double>(),
                                          G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
                                          reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
-                                         ctx->tile_atoms, s, ncount, pt));
+                                         ctx->tile_atoms, s, ncount, pt,
+                                         tiled ? G.tick.as<unsigned>() : nullptr));
             HIPCK(launch_bound(g, lev, lprec, cap, dec + off, G.abuf.as<double>(),
                                G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
         }

@@ -149,7 +149,7 @@ struct tms_graph_state {
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
         lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, verts,
-        etab, sz, ctr, stmp, seg, ptab;
+        etab, sz, ctr, stmp, seg, ptab, tick;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
@@ -294,7 +294,7 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
-                                  const ProjTab &pt = ProjTab{});
+                                  const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr);
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
 // fill the projection table (t: [3 n ns][6] doubles)

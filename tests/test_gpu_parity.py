@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Bars (stated here, derived in the design doc):
+Bars:
   * discrete results -- leaf list, levels, reasons, masks, classes, vertex
     keys -- bit-exact, in order;
   * phi, corner values, vertex t: FP64 path 1e-12 relative; FP32+guard path
