@@ -323,7 +323,8 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
  * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 8,
- * proj_table 1. */
+ * proj_table 1, tiled_persistent 0 (captured passes always draw chunks from
+ * the per-XCD counters). */
 typedef struct {
     int64_t slice_cubes;     /* largest queue slice per estimate + bound
                                 launch (a level is cut into ceil(n / this)
@@ -342,7 +343,10 @@ typedef struct {
                                 3 * ceil(2 R_c / h) + 9 entries per atom at
                                 spacing h) and gather from that table;
                                 0: each chunk projects in place          */
-    int32_t reserved;        /* 0                                          */
+    int32_t tiled_persistent; /* 1: the tiled estimate runs a fixed grid of
+                                workgroups that draw chunks from per-XCD
+                                counters (each XCD walks its chunks in
+                                order); 0: one workgroup per chunk        */
 } tms_tuning;
 
 /* Set / read ctx's tuning.  Errors: TMS_E_INVALID (values out of range). */
@@ -351,8 +355,9 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t);
 
 /* Autotuner: times tms_partition_estimate on `cells` (count only, device
  * results discarded) under candidate tunings -- atoms per tile, then the
- * projection table on or off, then the first tiled level, then the slice
- * size, each with the others at their best so far -- checks that every
+ * projection table on or off, the tiled grid (persistent or one workgroup
+ * per chunk), the first tiled level, then the slice size, each with the
+ * others at their best so far -- checks that every
  * candidate gives the same leaf and cube
  * counts, and leaves the fastest set on ctx.
  *  best     host out (or NULL): the chosen tuning.

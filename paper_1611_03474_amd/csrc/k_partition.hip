@@ -820,11 +820,11 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
                             const double *aw, const EstOut &o, unsigned long long *pairs,
                             const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
-    // a capacity-sized launch (chunk count on the device) takes a fixed grid
-    // (a multiple of 8) drawing chunks from per-XCD counters; otherwise one
-    // workgroup per chunk
-    const bool dyn = o.ncount != nullptr;
-    if (dyn && !o.tick) return hipErrorInvalidValue;
+    // with slot counters (required when the chunk count is on the device) a
+    // fixed grid (a multiple of 8) draws chunks from per-XCD counters;
+    // otherwise one workgroup per chunk
+    const bool dyn = o.tick != nullptr;
+    if (o.ncount && !dyn) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)(dyn ? std::min<int64_t>((nchunks + 7) / 8 * 8, kStrideGrid)
                                          : nchunks);
     // atoms staged per LDS tile (a tuning knob; the arithmetic is the same)

@@ -1267,6 +1267,12 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                     rc = build_chunks(ctx, gt, lev, q + off, nullptr, ns, &chunks, &nchunks);
                     if (rc) return rc;
                 }
+                unsigned *tick = nullptr;
+                if (tiled && ctx->tiled_dyn) {
+                    HIPCK(ctx->tick.ensure(8 * sizeof(unsigned)));
+                    tick = ctx->tick.as<unsigned>();
+                    HIPCK(launch_fill_u32(ctx->tick.as<uint32_t>(), 0u, 8, s));
+                }
                 {  // Step 1 (tensor) and the decisions that need no bound
                     TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
                     HIPCK(launch_estimate_decide(
@@ -1276,7 +1282,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         cells->aw.as<double>(), ctx->dec.as<uint8_t>() + off,
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
                         hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s, nullptr,
-                        pt));
+                        pt, tick));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
@@ -1825,10 +1831,13 @@ int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
         return fail(ctx, TMS_E_INVALID, "tile_atoms must be 8, 16 or 32");
     if (t->proj_table != 0 && t->proj_table != 1)
         return fail(ctx, TMS_E_INVALID, "proj_table must be 0 or 1");
+    if (t->tiled_persistent != 0 && t->tiled_persistent != 1)
+        return fail(ctx, TMS_E_INVALID, "tiled_persistent must be 0 or 1");
     ctx->slice_cubes = t->slice_cubes;
     ctx->tiled_min_level = t->tiled_min_level;
     ctx->tile_atoms = t->tile_atoms;
     ctx->proj_table = t->proj_table;
+    ctx->tiled_dyn = t->tiled_persistent != 0;
     return TMS_OK;
 }
 
@@ -1838,7 +1847,7 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t) {
     t->tiled_min_level = ctx->tiled_min_level;
     t->tile_atoms = ctx->tile_atoms;
     t->proj_table = ctx->proj_table;
-    t->reserved = 0;
+    t->tiled_persistent = ctx->tiled_dyn ? 1 : 0;
     return TMS_OK;
 }
 
@@ -1897,6 +1906,11 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
     {
         tms_tuning t = b;
         t.proj_table = 1 - b.proj_table;
+        if ((rc = consider(t))) return rc;
+    }
+    {
+        tms_tuning t = b;
+        t.tiled_persistent = 1 - b.tiled_persistent;
         if ((rc = consider(t))) return rc;
     }
     const tms_tuning bch = b;

@@ -195,6 +195,8 @@ struct tms_ctx {
     int tile_atoms = 8;
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
     tms::DevBuf ptab;       // that table
+    tms::DevBuf tick;       // [8] chunk slot counters of the tiled estimate
+    bool tiled_dyn = false; // eager tiled launches draw chunks from them
     tms::DevBuf counters;
     tms::DevBuf hostpin;   // unused
     // per-phase device timing (HIP events on `stream`)
