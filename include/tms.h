@@ -322,7 +322,7 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
 /* ---- tuning ---------------------------------------------------------------
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
- * does.  Defaults: slice_cubes 2^26, tiled_min_level 2, tile_atoms 8,
+ * does.  Defaults: slice_cubes 2^26, tiled_min_level 1, tile_atoms 8,
  * proj_table 1, tiled_persistent 0 (captured passes always draw chunks from
  * the per-XCD counters). */
 typedef struct {
@@ -331,9 +331,11 @@ typedef struct {
                                 equal slices); the staged tensors take
                                 512 B per entry (>= 4096)                   */
     int32_t tiled_min_level; /* first level estimated one wavefront per chunk
-                                of <= 64 cubes of one root (1..3; 4: none;
-                                levels above 3 always use one thread per
-                                cube)                                        */
+                                of <= 64 cubes of one root (level 1: eight
+                                roots of <= 8 cubes per wavefront, one
+                                8-lane group each) (1..3; 4: none; level 0
+                                and levels above 3 always use one thread
+                                per cube)                                   */
     int32_t tile_atoms;      /* atoms staged per LDS tile of that kernel:
                                 8, 16 or 32                                  */
     int32_t proj_table;      /* 1: the tiled levels first tabulate every

@@ -526,6 +526,247 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
 }
 
 // ---------------------------------------------------------------------------
+// Tensor estimate for level 1, where a root holds at most 2 x 2 x 2 cubes: one
+// wavefront takes 8 consecutive chunks (roots), one 8-lane group each.  Every
+// group runs the steps of the tiled kernel on its own -- filters its root's
+// list to the atoms within R_c of its cubes' box (in list order), stages CH
+// of them, puts each needed projection once into LDS (from the projection
+// table when there is one) and lets each lane apply the per-cube test and
+// update -- and the wavefront loops while any group has atoms left.  Same
+// arithmetic, in the same atom order per cube, as the per-thread kernel.
+// ---------------------------------------------------------------------------
+constexpr int kGrp = 8;    // lanes (cubes) per group and groups per wavefront
+constexpr int kGrpIv = 2;  // intervals per axis inside a level-1 root
+
+template <bool FAST, int QH, int CH>
+__global__ __launch_bounds__(64, 2) void k_estimate_groups(
+    const Grid *__restrict__ gt, int level, GLRule<double> R, const int4 *__restrict__ q,
+    const int2 *__restrict__ chunks, int64_t nch_cap, const int32_t *__restrict__ root_start,
+    const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
+    const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
+    EstOut o, unsigned long long *__restrict__ pairs, ProjTab P) {
+    constexpr int PA = 3 * kGrpIv;                           // items per atom, at most
+    constexpr int WI = (CH * PA + kGrp - 1) / kGrp * kGrp;   // items per group (multiple of 8)
+    constexpr int NB = CH + kGrp;                            // atom buffer per group
+    // item w of group gr sits at (w / 8) * 64 + gr * 8 + w % 8, so the 8
+    // items of all groups handled in one step are 64 consecutive slots
+    __shared__ double2 t01[WI * kGrp], t23[WI * kGrp], ted[WI * kGrp];
+    __shared__ int b_i[kGrp][NB];
+    __shared__ int b_lo[kGrp][NB][3];
+    __shared__ double b_w[kGrp][NB];
+    __shared__ double b_x[kGrp][NB][3];
+    const int lane = threadIdx.x, gr = lane >> 3, gl = lane & 7;
+    using lds_ptr = __attribute__((address_space(3))) void *;
+    const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
+    for (int64_t wv = blockIdx.x; wv * kGrp < nch; wv += gridDim.x) {
+    const int64_t cix = wv * kGrp + gr;
+    const int2 ch = cix < nch ? chunks[cix] : make_int2(0, 0);
+    const bool valid = gl < ch.y;
+    const int64_t qi = (int64_t)ch.x + (valid ? gl : 0);
+    const int4 c = q[qi];
+    const int4 c0 = q[ch.x];
+    const Grid &g = gt[c0.w];  // one root, hence one conformation, per group
+    const double rc2 = g.rc2, D = g.D, rc = sqrt(rc2);
+    const double h = ldexp(g.h0, -level);
+    const double s = 0.5 * h;
+    const int rxyz[3] = {c0.x >> level, c0.y >> level, c0.z >> level};
+    const int64_t root = g.root_base + ((int64_t)rxyz[2] * g.nr[1] + rxyz[1]) * g.nr[0] + rxyz[0];
+    const int li[3] = {c.x - (rxyz[0] << level), c.y - (rxyz[1] << level),
+                       c.z - (rxyz[2] << level)};
+    int mn[3], mx[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int vlo = valid ? li[a] : 1 << 20, vhi = valid ? li[a] : -1;
+#pragma unroll
+        for (int d = 4; d > 0; d >>= 1) {  // within the group of 8 lanes
+            vlo = min(vlo, __shfl_xor(vlo, d, 64));
+            vhi = max(vhi, __shfl_xor(vhi, d, 64));
+        }
+        mn[a] = vlo;
+        mx[a] = vhi;
+    }
+    const bool gact = ch.y > 0;  // the group has cubes
+    int nv[3];
+    double base[3], blo[3], bhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nv[a] = gact ? mx[a] - mn[a] + 1 : 0;
+        base[a] = g.o[a] + (double)(rxyz[a] << level) * h;
+        blo[a] = base[a] + mn[a] * h;
+        bhi[a] = base[a] + (mx[a] + 1) * h;
+    }
+    const int per_atom = nv[0] + nv[1] + nv[2];
+    const int ox = li[0] - mn[0], oy = nv[0] + li[1] - mn[1], oz = nv[0] + nv[1] + li[2] - mn[2];
+    const int re = gact ? root_start[root + 1] : 0;
+    int head = gact ? root_start[root] : 0, nbuf = 0;
+    double A[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) A[e] = 0.0;
+    double EA = 0.0;
+    unsigned long long np = 0;
+    for (;;) {
+        // refill each group's buffer, 8 atoms of its list per step
+        for (;;) {
+            const bool need = nbuf < CH && head < re;
+            if (!__any(need)) break;
+            const int p = head + gl;
+            bool use = false;
+            int i = 0;
+            double x[3] = {0.0, 0.0, 0.0};
+            if (need && p < re) {
+                i = root_atoms[p];
+                x[0] = ax[i];
+                x[1] = ay[i];
+                x[2] = az[i];
+                double d2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double d = fmax(fmax(blo[a] - x[a], x[a] - bhi[a]), 0.0);
+                    d2 += d * d;
+                }
+                use = d2 <= rc2;
+            }
+            const unsigned gm = (unsigned)(__ballot(use) >> (8 * gr)) & 0xFFu;
+            if (use) {
+                const int at = nbuf + __popc(gm & ((1u << gl) - 1u));
+                b_i[gr][at] = i;
+                b_w[gr][at] = aw[i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b_x[gr][at][a] = x[a];
+                    b_lo[gr][at][a] = proj_first(g, a, x[a], rc, h, level);
+                }
+            }
+            if (need) {
+                nbuf += __popc(gm);
+                head += kGrp;
+            }
+        }
+        __syncthreads();
+        const int na = min(CH, nbuf);
+        if (!__any(na > 0)) break;
+        // projections of each group's staged atoms on its intervals
+        const int nw = na * per_atom;
+        int nw_max = nw;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) nw_max = max(nw_max, __shfl_xor(nw_max, d, 64));
+        for (int k0 = 0; k0 < nw_max; k0 += kGrp) {
+            const int w = k0 + gl;
+            const int slot_lds = (k0 / kGrp) * 64 + lane;
+            const double *src = nullptr;
+            if (w < nw) {
+                const int a_idx = w / per_atom;
+                int r = w - a_idx * per_atom, axis = 0;
+                if (r >= nv[0]) {
+                    r -= nv[0];
+                    axis = 1;
+                    if (r >= nv[1]) {
+                        r -= nv[1];
+                        axis = 2;
+                    }
+                }
+                const double xa = b_x[gr][a_idx][axis];
+                const double lo = base[axis] + (mn[axis] + r) * h, hi = lo + h;
+                const double d = fmax(fmax(lo - xa, xa - hi), 0.0);
+                const double dd = d * d;
+                double b[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double e =
+                        fmax(fmax(blo[a] - b_x[gr][a_idx][a], b_x[gr][a_idx][a] - bhi[a]), 0.0);
+                    b[a] = a == axis ? dd : e * e;
+                }
+                const int slot = (rxyz[axis] << level) + mn[axis] + r - b_lo[gr][a_idx][axis];
+                if (b[0] + b[1] + b[2] > rc2) {
+                    ted[slot_lds] = make_double2(0.0, dd);
+                } else if (P.t && slot >= 0 && slot < P.ns) {
+                    src = P.t + 6 * (((int64_t)axis * P.n + b_i[gr][a_idx]) * P.ns + slot);
+                } else {
+                    double pr[4], err;
+                    project<FAST, QH>(R, D, s, (lo + s) - xa, pr, err);
+                    t01[slot_lds] = make_double2(pr[0], pr[1]);
+                    t23[slot_lds] = make_double2(pr[2], pr[3]);
+                    ted[slot_lds] = make_double2(err, dd);
+                }
+            }
+            if (src) {  // lane's 16-byte pieces land at [(k0 / 8) * 64 + lane]
+                const int blk = (k0 / kGrp) * 64;
+                __builtin_amdgcn_global_load_lds(src, (lds_ptr)(t01 + blk), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(src + 2, (lds_ptr)(t23 + blk), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)(ted + blk), 16, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int gofs = gr * kGrp;
+        int na_max = na;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) na_max = max(na_max, __shfl_xor(na_max, d, 64));
+        for (int a = 0; a < na_max; ++a) {
+            if (!valid || a >= na) continue;
+            const int wa = a * per_atom;
+            const int ix = ((wa + ox) >> 3) * 64 + gofs + ((wa + ox) & 7);
+            const int iy = ((wa + oy) >> 3) * 64 + gofs + ((wa + oy) & 7);
+            const int iz = ((wa + oz) >> 3) * 64 + gofs + ((wa + oz) & 7);
+            const double2 ex = ted[ix], ey = ted[iy], ez = ted[iz];
+            if (ex.y + ey.y + ez.y > rc2) continue;
+            ++np;
+            const double2 x01 = t01[ix], x23 = t23[ix];
+            const double2 y01 = t01[iy], y23 = t23[iy];
+            const double2 z01 = t01[iz], z23 = t23[iz];
+            const double px[4] = {x01.x, x01.y, x23.x, x23.y};
+            const double py[4] = {y01.x, y01.y, y23.x, y23.y};
+            const double pz[4] = {z01.x, z01.y, z23.x, z23.y};
+            const double wgt = b_w[gr][a];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double wx = wgt * px[j];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double wxy = wx * py[k];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) A[16 * j + 4 * k + l] += wxy * pz[l];
+                }
+            }
+            if (FAST) {
+                const double nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
+                const double ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
+                const double nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
+                EA += wgt * ((ex.x * ny + nx * ey.x) * nz + nx * ny * ez.x);
+            }
+        }
+        __syncthreads();
+        // move each group's atoms not yet staged (fewer than 8) to the front
+        const int rest = nbuf - na;
+        int mi = 0, ml[3] = {0, 0, 0};
+        double mw = 0.0, mx3[3] = {0.0, 0.0, 0.0};
+        if (gl < rest) {
+            mi = b_i[gr][na + gl];
+            mw = b_w[gr][na + gl];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ml[a] = b_lo[gr][na + gl][a];
+                mx3[a] = b_x[gr][na + gl][a];
+            }
+        }
+        __syncthreads();
+        if (gl < rest) {
+            b_i[gr][gl] = mi;
+            b_w[gr][gl] = mw;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b_lo[gr][gl][a] = ml[a];
+                b_x[gr][gl][a] = mx3[a];
+            }
+        }
+        nbuf = rest;
+    }
+    epilogue(g, level, FAST, A, EA, qi, valid, o);
+    if (pairs) wave_add(pairs, np);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Projection table of one level: one thread per (axis, atom, slot).  A row
 // (axis, atom) starts at proj_first and holds ceil(2 R_c / h) + 3 intervals,
 // so every interval within R_c of the atom along the axis has a slot (the
@@ -845,6 +1086,22 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
     return hipGetLastError();
 }
 
+// level 1: 8 roots per wavefront, tiles of 8 atoms (the LDS footprint of
+// larger tiles would cost occupancy)
+template <bool FAST, int QH>
+hipError_t estimate_groups_t(const Grid *g, int level, const int4 *q, const int2 *chunks,
+                             int64_t nchunks, const int32_t *rs, const int32_t *ra,
+                             const double *ax, const double *ay, const double *az,
+                             const double *aw, const EstOut &o, unsigned long long *pairs,
+                             const ProjTab &P, hipStream_t s) {
+    GLRule<double> R = gl_rule<double>(QH);
+    const int64_t waves = (nchunks + kGrp - 1) / kGrp;
+    const unsigned grid = (unsigned)(o.ncount ? std::min<int64_t>(waves, kStrideGrid) : waves);
+    hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8>), dim3(grid), dim3(64), 0, s, g, level, R,
+                       q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+    return hipGetLastError();
+}
+
 #define TMS_QH_SWITCH(qh, CALL)                    \
     switch (qh) {                                  \
     case 4: { constexpr int QH = 4; return CALL; } \
@@ -870,6 +1127,9 @@ hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *
                           const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
                           const double *az, const double *aw, const EstOut &o,
                           unsigned long long *pairs, const ProjTab &P, hipStream_t s) {
+    if (level == 1 && !subset)
+        TMS_QH_SWITCH(qh, (estimate_groups_t<FAST, QH>(g, level, q, chunks, nchunks, rs, ra, ax,
+                                                       ay, az, aw, o, pairs, P, s)))
     TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(ch, g, level, q, subset, chunks, nchunks, rs, ra,
                                                   ax, ay, az, aw, o, pairs, P, s)))
 }

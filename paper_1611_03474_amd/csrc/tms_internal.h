@@ -191,7 +191,7 @@ struct tms_ctx {
     // tuning (results do not depend on it): queue entries per estimate
     // slice, first level estimated by the tiled kernel, atoms per LDS tile
     int64_t slice_cubes = (int64_t)1 << 26;
-    int tiled_min_level = 2;
+    int tiled_min_level = 1;
     int tile_atoms = 8;
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
     tms::DevBuf ptab;       // that table
