@@ -386,7 +386,9 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
                             cubes of one root (tiled levels)           */
 #define TMS_T_BACKWARD 9 /* adjoint kernels                             */
 #define TMS_T_TABLE 10   /* per-level projection tables                */
-#define TMS_T_SLOTS 11
+#define TMS_T_GROUPED 11 /* tensor estimate, eight level-1 roots per
+                            wavefront                                  */
+#define TMS_T_SLOTS 12
 
 typedef struct {
     double ms[TMS_T_SLOTS];       /* accumulated device milliseconds */

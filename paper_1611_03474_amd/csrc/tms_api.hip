@@ -1274,7 +1274,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                     HIPCK(launch_fill_u32(ctx->tick.as<uint32_t>(), 0u, 8, s));
                 }
                 {  // Step 1 (tensor) and the decisions that need no bound
-                    TimedScope ts_(ctx, tiled ? TMS_T_TILED : TMS_T_ESTIMATE);
+                    TimedScope ts_(ctx, !tiled ? TMS_T_ESTIMATE
+                                               : (lev == 1 ? TMS_T_GROUPED : TMS_T_TILED));
                     HIPCK(launch_estimate_decide(
                         g, gt, lev, lprec, q + off, ns, nullptr, chunks, nchunks,
                         cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),

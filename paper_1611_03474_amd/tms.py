@@ -31,7 +31,7 @@ assert LEAF_DTYPE.itemsize == 20 and VERTEX_DTYPE.itemsize == 40
 
 
 T_SLOTS = ["build", "estimate", "decide", "guard", "compact", "corner", "phi", "extract",
-           "tiled", "backward", "table"]
+           "tiled", "backward", "table", "grouped"]
 
 
 class Timing(C.Structure):
