@@ -324,28 +324,44 @@ __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, in
     }
 }
 
-// every candidate writes its corner's coordinates at the corner's rank (all
-// writers of one corner write the same bits)
-__global__ void k_corner_write(const tms_leaf *__restrict__ leaves, int64_t n, int K,
-                               const Grid *__restrict__ gt, const uint64_t *__restrict__ bm,
-                               const int32_t *__restrict__ woff, double *__restrict__ upts,
-                               int32_t *__restrict__ uconf, const int64_t *__restrict__ nd,
-                               int64_t ucap, unsigned *__restrict__ ovf) {
-    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 8 * n || (nd && c >= 8 * *nd)) return;
-    const tms_leaf L = leaves[c >> 3];
-    const Grid &g = gt[L.conf];
-    int64_t X, Y, Z;
-    leaf_corner(L, (int)(c & 7), K, X, Y, Z);
-    const int64_t u = bit_rank(bm, woff, lat_bit(g.clat, X, Y, Z));
-    if (ovf && u >= ucap) {  // capacity-sized buffers (capture path)
-        atomicOr(ovf, 1u);
-        return;
+// Unique corner points from the bitmap alone: one thread per word writes the
+// lattice points of its set bits at their ranks (each point once, in rank
+// order).  Word w belongs to the last conformation whose block starts at or
+// before it; inside a block, word ((bx n1 + by) n2 + bz) covers points
+// (4 bx + i, 4 by + j, 4 bz + k) at bit 16 i + 4 j + k.
+__global__ void k_corner_enum(const Grid *__restrict__ gt, int nconf,
+                              const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
+                              int64_t nw, double *__restrict__ upts, int32_t *__restrict__ uconf,
+                              int64_t ucap, unsigned *__restrict__ ovf) {
+    const int64_t w = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (w >= nw) return;
+    uint64_t m = bm[w];
+    if (!m) return;
+    int lo = 0, hi = nconf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (gt[mid].clat.base <= w) lo = mid;
+        else hi = mid - 1;
     }
-    upts[3 * u] = g.o[0] + (double)X * g.hmin;
-    upts[3 * u + 1] = g.o[1] + (double)Y * g.hmin;
-    upts[3 * u + 2] = g.o[2] + (double)Z * g.hmin;
-    uconf[u] = L.conf;
+    const Grid &g = gt[lo];
+    const int64_t lw = w - g.clat.base;
+    const int64_t bz = lw % g.clat.n[2], t = lw / g.clat.n[2];
+    const int64_t by = t % g.clat.n[1], bx = t / g.clat.n[1];
+    int64_t u = woff[w];
+    while (m) {
+        const int b = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1ull;
+        if (ovf && u >= ucap) {  // capacity-sized buffers (capture path)
+            atomicOr(ovf, 1u);
+            return;
+        }
+        const int64_t X = 4 * bx + (b >> 4), Y = 4 * by + ((b >> 2) & 3), Z = 4 * bz + (b & 3);
+        upts[3 * u] = g.o[0] + (double)X * g.hmin;
+        upts[3 * u + 1] = g.o[1] + (double)Y * g.hmin;
+        upts[3 * u + 2] = g.o[2] + (double)Z * g.hmin;
+        uconf[u] = lo;
+        ++u;
+    }
 }
 
 __global__ void k_corner_gather_bm(const tms_leaf *__restrict__ lin, int64_t n, int K,
@@ -394,13 +410,12 @@ hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Gr
     return hipGetLastError();
 }
 
-hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
-                               const uint64_t *bm, const int32_t *woff, double *upts,
-                               int32_t *uconf, hipStream_t s, const int64_t *nd, int64_t ucap,
-                               unsigned *ovf) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_write, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, gt, bm,
-                       woff, upts, uconf, nd, ucap, ovf);
+hipError_t launch_corner_enum(const Grid *gt, int nconf, const uint64_t *bm, const int32_t *woff,
+                              int64_t nwords, double *upts, int32_t *uconf, hipStream_t s,
+                              int64_t ucap, unsigned *ovf) {
+    if (nwords <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_enum, dim3(nblk(nwords)), dim3(kBS), 0, s, gt, nconf, bm, woff,
+                       nwords, upts, uconf, ucap, ovf);
     return hipGetLastError();
 }
 

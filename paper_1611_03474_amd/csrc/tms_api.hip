@@ -341,9 +341,9 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
             HIPCK(ctx->uconf.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1)));
             {
                 TimedScope ts_(ctx, TMS_T_CORNER);
-                HIPCK(launch_corner_write(leaves, n, g.K, gt, ctx->bmap.as<uint64_t>(),
-                                          ctx->bmoff.as<int32_t>(), ctx->uniq.as<double>(),
-                                          ctx->uconf.as<int32_t>(), s));
+                HIPCK(launch_corner_enum(gt, cells->nconf, ctx->bmap.as<uint64_t>(),
+                                         ctx->bmoff.as<int32_t>(), nwords, ctx->uniq.as<double>(),
+                                         ctx->uconf.as<int32_t>(), s));
             }
             rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), nu,
                                 ctx->uphi.as<double>(), nullptr, n_guard, kCornerBand);
@@ -1064,8 +1064,8 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     HIPCK(launch_corner_mark(lv, G.lcap, K, gt, G.bmap.as<unsigned long long>(), s, Ld));
     HIPCK(launch_popc(G.bmap.as<uint64_t>(), cw, G.bmcnt.as<int32_t>(), s));
     HIPCK(exclusive_scan(G.bmcnt.as<int32_t>(), G.bmoff.as<int32_t>(), cw, nu, tmp, s));
-    HIPCK(launch_corner_write(lv, G.lcap, K, gt, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(),
-                              G.uniq.as<double>(), G.uconf.as<int32_t>(), s, Ld, G.ucap, ovf));
+    HIPCK(launch_corner_enum(gt, nconf, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(), cw,
+                             G.uniq.as<double>(), G.uconf.as<int32_t>(), s, G.ucap, ovf));
     const bool fast = prec == TMS_PREC_FP32_GUARD;
     HIPCK(launch_phi_points(gt, G.uconf.as<int32_t>(), prec, G.uniq.as<double>(), G.ucap,
                             cells->cell_start.as<int32_t>(), ax, ay, az, aw, kCornerBand,

@@ -382,10 +382,10 @@ hipError_t launch_popc(const uint64_t *bm, int64_t nwords, int32_t *cnt, hipStre
 // corner bitmap: conformation L.conf owns the words of gt[L.conf].clat
 hipError_t launch_corner_mark(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
                               unsigned long long *bm, hipStream_t s, const int64_t *nd = nullptr);
-hipError_t launch_corner_write(const tms_leaf *leaves, int64_t n, int K, const Grid *gt,
-                               const uint64_t *bm, const int32_t *woff, double *upts,
-                               int32_t *uconf, hipStream_t s, const int64_t *nd = nullptr,
-                               int64_t ucap = 0, unsigned *ovf = nullptr);
+// unique corner points and their conformations at their ranks, from the bitmap
+hipError_t launch_corner_enum(const Grid *gt, int nconf, const uint64_t *bm, const int32_t *woff,
+                              int64_t nwords, double *upts, int32_t *uconf, hipStream_t s,
+                              int64_t ucap = 0, unsigned *ovf = nullptr);
 hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const Grid *gt,
                                    const uint64_t *bm, const int32_t *woff, const double *uphi,
                                    double c, tms_leaf *lout, double *cphi, hipStream_t s,
