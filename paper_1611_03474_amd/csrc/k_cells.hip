@@ -24,11 +24,15 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // Per conformation b (one workgroup each, atoms [off[b], off[b+1])):
 // out[9b + 0..2] min xyz, [3..5] max xyz, [6] max r, [7] min r, [8] count of
 // non-finite values.
+// per (segment of kStatSeg atoms, conformation) partials: grid (S, nconf)
+constexpr int64_t kStatSeg = 4096;
+
 __global__ __launch_bounds__(kBS) void k_stats_conf(const double *__restrict__ xyzr,
                                                     const int64_t *__restrict__ off,
                                                     double *__restrict__ out) {
-    const int b = blockIdx.x;
-    const int64_t i0 = off[b], i1 = off[b + 1];
+    const int b = blockIdx.y;
+    const int64_t i0 = off[b] + (int64_t)blockIdx.x * kStatSeg,
+                  i1 = min(off[b + 1], i0 + kStatSeg);
     double mn[3] = {1e308, 1e308, 1e308}, mx[3] = {-1e308, -1e308, -1e308};
     double rmax = -1e308, rmin = 1e308, bad = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBS) {
@@ -70,7 +74,40 @@ __global__ __launch_bounds__(kBS) void k_stats_conf(const double *__restrict__ x
         }
         __syncthreads();
     }
-    if (threadIdx.x < 9) out[9 * b + threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 9)
+        out[9 * ((int64_t)b * gridDim.x + blockIdx.x) + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// per conformation: min / max / sum over its segments' partials (one
+// wavefront; order-free: min, max, and sums of integer-valued counts)
+__global__ void k_stats_final(const double *__restrict__ part, int S, double *__restrict__ out) {
+    const int b = blockIdx.x, lane = threadIdx.x;
+    double v[9] = {1e308, 1e308, 1e308, -1e308, -1e308, -1e308, -1e308, 1e308, 0.0};
+    for (int k = lane; k < S; k += 64) {
+        const double *p = part + 9 * ((int64_t)b * S + k);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fmin(v[a], p[a]);
+            v[3 + a] = fmax(v[3 + a], p[3 + a]);
+        }
+        v[6] = fmax(v[6], p[6]);
+        v[7] = fmin(v[7], p[7]);
+        v[8] += p[8];
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fmin(v[a], __shfl_xor(v[a], d, 64));
+            v[3 + a] = fmax(v[3 + a], __shfl_xor(v[3 + a], d, 64));
+        }
+        v[6] = fmax(v[6], __shfl_xor(v[6], d, 64));
+        v[7] = fmin(v[7], __shfl_xor(v[7], d, 64));
+        v[8] += __shfl_xor(v[8], d, 64);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int a = 0; a < 9; ++a) out[9 * b + a] = v[a];
 }
 
 __device__ __forceinline__ int cell_of(const Grid &g, double x, int a) {
@@ -181,9 +218,17 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
 
 }  // namespace
 
-hipError_t launch_atom_stats(const double *xyzr, const int64_t *off, int nconf, double *out,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_stats_conf, dim3(nconf), dim3(kBS), 0, s, xyzr, off, out);
+size_t atom_stats_tmp_bytes(int nconf, int64_t max_atoms) {
+    const int64_t S = std::max<int64_t>(1, (max_atoms + kStatSeg - 1) / kStatSeg);
+    return sizeof(double) * 9 * (size_t)nconf * (size_t)S;
+}
+
+hipError_t launch_atom_stats(const double *xyzr, const int64_t *off, int nconf, int64_t max_atoms,
+                             double *out, double *tmp, hipStream_t s) {
+    const int64_t S = std::max<int64_t>(1, (max_atoms + kStatSeg - 1) / kStatSeg);
+    hipLaunchKernelGGL(k_stats_conf, dim3((unsigned)S, (unsigned)nconf), dim3(kBS), 0, s, xyzr,
+                       off, tmp);
+    hipLaunchKernelGGL(k_stats_final, dim3((unsigned)nconf), dim3(64), 0, s, tmp, (int)S, out);
     return hipGetLastError();
 }
 

@@ -1006,12 +1006,21 @@ __global__ void k_level_histo(const uint8_t *__restrict__ dec, int64_t n,
     if (threadIdx.x < 5) part[5 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// one wavefront: lanes sum strided blocks, then a wavefront reduction
+// (integer sums: the order does not matter)
 __global__ void k_level_histo_final(const unsigned long long *__restrict__ part, int nb,
                                     unsigned long long *__restrict__ out) {
-    if (threadIdx.x >= 5) return;
-    unsigned long long t = 0;
-    for (int b = 0; b < nb; ++b) t += part[5 * b + threadIdx.x];
-    out[threadIdx.x] = t;
+    const int lane = threadIdx.x;
+    unsigned long long t[5] = {0, 0, 0, 0, 0};
+    for (int b = lane; b < nb; b += 64)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) t[k] += part[5 * b + k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) t[k] += __shfl_xor(t[k], d, 64);
+        if (lane == k) out[k] = t[k];
+    }
 }
 
 __global__ __launch_bounds__(kBS) void k_bound_debug(const double *__restrict__ Ain,

@@ -657,9 +657,15 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         if (e == hipSuccess)
             e = hipMemcpyAsync(cells->aoff.p, off.data(), sizeof(int64_t) * (size_t)(nconf + 1),
                                hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = ctx->ctmp.ensure(sizeof(double) * 9 * (size_t)nconf);
+        int64_t max_atoms = 0;
+        for (int b = 0; b < nconf; ++b) max_atoms = std::max(max_atoms, off[b + 1] - off[b]);
+        const size_t tmpb = atom_stats_tmp_bytes(nconf, max_atoms);
         if (e == hipSuccess)
-            e = launch_atom_stats(xyzr, cells->aoff.as<int64_t>(), nconf, ctx->ctmp.as<double>(), s);
+            e = ctx->ctmp.ensure(sizeof(double) * 9 * (size_t)nconf + 256 + tmpb);
+        if (e == hipSuccess)
+            e = launch_atom_stats(xyzr, cells->aoff.as<int64_t>(), nconf, max_atoms,
+                                  ctx->ctmp.as<double>(),
+                                  ctx->ctmp.as<double>() + 9 * (size_t)nconf + 32, s);
         if (e == hipSuccess) e = d2h(st.data(), ctx->ctmp.p, 9 * (size_t)nconf, s);
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "atom stats"));
         for (int b = 0; b < nconf; ++b) {

@@ -226,8 +226,11 @@ void timing_flush(tms_ctx *ctx);
 namespace tms {
 
 // k_cells.hip -- batch-wide arrays; gt: device table of nconf geometries
-hipError_t launch_atom_stats(const double *xyzr, const int64_t *off, int nconf, double *out9,
-                             hipStream_t s);
+// per conformation {min xyz, max xyz, max r, min r, non-finite count};
+// tmp: atom_stats_tmp_bytes of scratch
+size_t atom_stats_tmp_bytes(int nconf, int64_t max_atoms);
+hipError_t launch_atom_stats(const double *xyzr, const int64_t *off, int nconf, int64_t max_atoms,
+                             double *out, double *tmp, hipStream_t s);
 hipError_t launch_bin_atoms(const Grid *gt, int nconf, const double *xyzr, int64_t n, int32_t *key,
                             int32_t *cnt, hipStream_t s);
 hipError_t launch_scatter_atoms(const Grid *gt, const double *xyzr, int64_t n, const int32_t *key,
