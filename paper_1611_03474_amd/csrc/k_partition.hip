@@ -526,40 +526,42 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
 }
 
 // ---------------------------------------------------------------------------
-// Tensor estimate for level 1, where a root holds at most 2 x 2 x 2 cubes: one
-// wavefront takes 8 consecutive chunks (roots), one 8-lane group each.  Every
-// group runs the steps of the tiled kernel on its own -- filters its root's
-// list to the atoms within R_c of its cubes' box (in list order), stages CH
-// of them, puts each needed projection once into LDS (from the projection
-// table when there is one) and lets each lane apply the per-cube test and
-// update -- and the wavefront loops while any group has atoms left.  Same
-// arithmetic, in the same atom order per cube, as the per-thread kernel.
+// Tensor estimate with several chunks per wavefront: 64 / GL groups of GL
+// lanes, each taking one chunk of at most GL cubes of one root (level 1,
+// where a root holds at most 2 x 2 x 2 cubes: GL = 8; deeper levels
+// optionally in half-wave chunks, GL = 32).  Every group runs the steps of
+// the tiled kernel on its own -- filters its root's list to the atoms within
+// R_c of its cubes' box (in list order), stages CH of them, puts each needed
+// projection once into LDS (from the projection table when there is one) and
+// lets each lane apply the per-cube test and update -- and the wavefront
+// loops while any group has atoms left.  IV bounds the intervals per axis a
+// chunk spans.  Same arithmetic, in the same atom order per cube, as the
+// per-thread kernel.
 // ---------------------------------------------------------------------------
-constexpr int kGrp = 8;    // lanes (cubes) per group and groups per wavefront
-constexpr int kGrpIv = 2;  // intervals per axis inside a level-1 root
-
-template <bool FAST, int QH, int CH>
+template <bool FAST, int QH, int CH, int GL, int IV>
 __global__ __launch_bounds__(64, 2) void k_estimate_groups(
     const Grid *__restrict__ gt, int level, GLRule<double> R, const int4 *__restrict__ q,
     const int2 *__restrict__ chunks, int64_t nch_cap, const int32_t *__restrict__ root_start,
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
     EstOut o, unsigned long long *__restrict__ pairs, ProjTab P) {
-    constexpr int PA = 3 * kGrpIv;                           // items per atom, at most
-    constexpr int WI = (CH * PA + kGrp - 1) / kGrp * kGrp;   // items per group (multiple of 8)
-    constexpr int NB = CH + kGrp;                            // atom buffer per group
-    // item w of group gr sits at (w / 8) * 64 + gr * 8 + w % 8, so the 8
+    constexpr int NG = 64 / GL;                          // groups per wavefront
+    constexpr int PA = 3 * IV;                           // items per atom, at most
+    constexpr int WI = (CH * PA + GL - 1) / GL * GL;     // items per group (multiple of GL)
+    constexpr int NB = CH + GL;                          // atom buffer per group
+    constexpr unsigned long long GM = GL == 64 ? ~0ull : (1ull << GL) - 1ull;
+    // item w of group gr sits at (w / GL) * 64 + gr * GL + w % GL, so the GL
     // items of all groups handled in one step are 64 consecutive slots
-    __shared__ double2 t01[WI * kGrp], t23[WI * kGrp], ted[WI * kGrp];
-    __shared__ int b_i[kGrp][NB];
-    __shared__ int b_lo[kGrp][NB][3];
-    __shared__ double b_w[kGrp][NB];
-    __shared__ double b_x[kGrp][NB][3];
-    const int lane = threadIdx.x, gr = lane >> 3, gl = lane & 7;
+    __shared__ double2 t01[WI * NG], t23[WI * NG], ted[WI * NG];
+    __shared__ int b_i[NG][NB];
+    __shared__ int b_lo[NG][NB][3];
+    __shared__ double b_w[NG][NB];
+    __shared__ double b_x[NG][NB][3];
+    const int lane = threadIdx.x, gr = lane / GL, gl = lane % GL;
     using lds_ptr = __attribute__((address_space(3))) void *;
     const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
-    for (int64_t wv = blockIdx.x; wv * kGrp < nch; wv += gridDim.x) {
-    const int64_t cix = wv * kGrp + gr;
+    for (int64_t wv = blockIdx.x; wv * NG < nch; wv += gridDim.x) {
+    const int64_t cix = wv * NG + gr;
     const int2 ch = cix < nch ? chunks[cix] : make_int2(0, 0);
     const bool valid = gl < ch.y;
     const int64_t qi = (int64_t)ch.x + (valid ? gl : 0);
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
     for (int a = 0; a < 3; ++a) {
         int vlo = valid ? li[a] : 1 << 20, vhi = valid ? li[a] : -1;
 #pragma unroll
-        for (int d = 4; d > 0; d >>= 1) {  // within the group of 8 lanes
+        for (int d = GL / 2; d > 0; d >>= 1) {  // within the group
             vlo = min(vlo, __shfl_xor(vlo, d, 64));
             vhi = max(vhi, __shfl_xor(vhi, d, 64));
         }
@@ -626,9 +628,9 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
                 }
                 use = d2 <= rc2;
             }
-            const unsigned gm = (unsigned)(__ballot(use) >> (8 * gr)) & 0xFFu;
+            const unsigned long long gm = (__ballot(use) >> (GL * gr)) & GM;
             if (use) {
-                const int at = nbuf + __popc(gm & ((1u << gl) - 1u));
+                const int at = nbuf + __popcll(gm & ((1ull << gl) - 1ull));
                 b_i[gr][at] = i;
                 b_w[gr][at] = aw[i];
 #pragma unroll
@@ -638,8 +640,8 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
                 }
             }
             if (need) {
-                nbuf += __popc(gm);
-                head += kGrp;
+                nbuf += __popcll(gm);
+                head += GL;
             }
         }
         __syncthreads();
@@ -650,9 +652,9 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
         int nw_max = nw;
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) nw_max = max(nw_max, __shfl_xor(nw_max, d, 64));
-        for (int k0 = 0; k0 < nw_max; k0 += kGrp) {
+        for (int k0 = 0; k0 < nw_max; k0 += GL) {
             const int w = k0 + gl;
-            const int slot_lds = (k0 / kGrp) * 64 + lane;
+            const int slot_lds = (k0 / GL) * 64 + lane;
             const double *src = nullptr;
             if (w < nw) {
                 const int a_idx = w / per_atom;
@@ -689,8 +691,8 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
                     ted[slot_lds] = make_double2(err, dd);
                 }
             }
-            if (src) {  // lane's 16-byte pieces land at [(k0 / 8) * 64 + lane]
-                const int blk = (k0 / kGrp) * 64;
+            if (src) {  // lane's 16-byte pieces land at [(k0 / GL) * 64 + lane]
+                const int blk = (k0 / GL) * 64;
                 __builtin_amdgcn_global_load_lds(src, (lds_ptr)(t01 + blk), 16, 0, 0);
                 __builtin_amdgcn_global_load_lds(src + 2, (lds_ptr)(t23 + blk), 16, 0, 0);
                 __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)(ted + blk), 16, 0, 0);
@@ -698,16 +700,16 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        const int gofs = gr * kGrp;
+        const int gofs = gr * GL;
         int na_max = na;
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) na_max = max(na_max, __shfl_xor(na_max, d, 64));
         for (int a = 0; a < na_max; ++a) {
             if (!valid || a >= na) continue;
             const int wa = a * per_atom;
-            const int ix = ((wa + ox) >> 3) * 64 + gofs + ((wa + ox) & 7);
-            const int iy = ((wa + oy) >> 3) * 64 + gofs + ((wa + oy) & 7);
-            const int iz = ((wa + oz) >> 3) * 64 + gofs + ((wa + oz) & 7);
+            const int ix = ((wa + ox) / GL) * 64 + gofs + (wa + ox) % GL;
+            const int iy = ((wa + oy) / GL) * 64 + gofs + (wa + oy) % GL;
+            const int iz = ((wa + oz) / GL) * 64 + gofs + (wa + oz) % GL;
             const double2 ex = ted[ix], ey = ted[iy], ez = ted[iz];
             if (ex.y + ey.y + ez.y > rc2) continue;
             ++np;
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
             }
         }
         __syncthreads();
-        // move each group's atoms not yet staged (fewer than 8) to the front
+        // move each group's atoms not yet staged (fewer than GL) to the front
         const int rest = nbuf - na;
         int mi = 0, ml[3] = {0, 0, 0};
         double mw = 0.0, mx3[3] = {0.0, 0.0, 0.0};
@@ -867,7 +869,7 @@ __global__ void k_run_starts(const int32_t *__restrict__ f, const int32_t *__res
 
 __global__ void k_run_chunk_counts(const int32_t *__restrict__ starts, int64_t nruns, int64_t n,
                                    const int32_t *__restrict__ nrd, const int32_t *__restrict__ nd,
-                                   int32_t *__restrict__ cnt) {
+                                   int cmax, int32_t *__restrict__ cnt) {
     const int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (r >= nruns) return;
     const int64_t R = nrd ? min((int64_t)*nrd, nruns) : nruns, N = nd ? (int64_t)*nd : n;
@@ -876,19 +878,20 @@ __global__ void k_run_chunk_counts(const int32_t *__restrict__ starts, int64_t n
         return;
     }
     const int64_t len = ((r + 1 < R) ? starts[r + 1] : N) - starts[r];
-    cnt[r] = (int32_t)((len + 63) / 64);
+    cnt[r] = (int32_t)((len + cmax - 1) / cmax);
 }
 
 __global__ void k_run_chunk_emit(const int32_t *__restrict__ starts, int64_t nruns, int64_t n,
                                  const int32_t *__restrict__ nrd, const int32_t *__restrict__ nd,
-                                 const int32_t *__restrict__ coff, int2 *__restrict__ chunks) {
+                                 int cmax, const int32_t *__restrict__ coff,
+                                 int2 *__restrict__ chunks) {
     const int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
     const int64_t R = nrd ? min((int64_t)*nrd, nruns) : nruns, N = nd ? (int64_t)*nd : n;
     if (r >= R) return;
     const int64_t b = starts[r], len = ((r + 1 < R) ? starts[r + 1] : N) - b;
     int2 *o = chunks + coff[r];
-    for (int64_t k = 0; k * 64 < len; ++k)
-        o[k] = make_int2((int32_t)(b + 64 * k), (int32_t)min<int64_t>(64, len - 64 * k));
+    for (int64_t k = 0; k * cmax < len; ++k)
+        o[k] = make_int2((int32_t)(b + cmax * k), (int32_t)min<int64_t>(cmax, len - cmax * k));
 }
 
 __global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n,
@@ -1095,8 +1098,9 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
     return hipGetLastError();
 }
 
-// level 1: 8 roots per wavefront, tiles of 8 atoms (the LDS footprint of
-// larger tiles would cost occupancy)
+// several chunks per wavefront, tiles of 8 atoms (the LDS footprint of larger
+// tiles would cost occupancy): level 1 in 8-lane groups (roots of <= 8
+// cubes); levels 2-3 in half-wave groups of chunks of <= 32 cubes
 template <bool FAST, int QH>
 hipError_t estimate_groups_t(const Grid *g, int level, const int4 *q, const int2 *chunks,
                              int64_t nchunks, const int32_t *rs, const int32_t *ra,
@@ -1104,10 +1108,20 @@ hipError_t estimate_groups_t(const Grid *g, int level, const int4 *q, const int2
                              const double *aw, const EstOut &o, unsigned long long *pairs,
                              const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
-    const int64_t waves = (nchunks + kGrp - 1) / kGrp;
+    const int gl = level == 1 ? 8 : 32;
+    const int64_t waves = (nchunks + 64 / gl - 1) / (64 / gl);
     const unsigned grid = (unsigned)(o.ncount ? std::min<int64_t>(waves, kStrideGrid) : waves);
-    hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8>), dim3(grid), dim3(64), 0, s, g, level, R,
-                       q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+    if (level == 1)
+        hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8, 8, 2>), dim3(grid), dim3(64), 0, s, g,
+                           level, R, q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+    else if (level == 2)
+        hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8, 32, 4>), dim3(grid), dim3(64), 0, s, g,
+                           level, R, q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+    else if (level == 3)
+        hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8, 32, 8>), dim3(grid), dim3(64), 0, s, g,
+                           level, R, q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1135,8 +1149,8 @@ hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *
                           const int32_t *subset, const int2 *chunks, int64_t nchunks,
                           const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
                           const double *az, const double *aw, const EstOut &o,
-                          unsigned long long *pairs, const ProjTab &P, hipStream_t s) {
-    if (level == 1 && !subset)
+                          unsigned long long *pairs, const ProjTab &P, bool half, hipStream_t s) {
+    if (!subset && (level == 1 || (half && level <= 3)))
         TMS_QH_SWITCH(qh, (estimate_groups_t<FAST, QH>(g, level, q, chunks, nchunks, rs, ra, ax,
                                                        ay, az, aw, o, pairs, P, s)))
     TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(ch, g, level, q, subset, chunks, nchunks, rs, ra,
@@ -1273,7 +1287,7 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount,
-                                  const ProjTab &pt, unsigned *tick) {
+                                  const ProjTab &pt, unsigned *tick, bool half) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
@@ -1283,9 +1297,10 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
         if (nchunks <= 0) return hipSuccess;
         if (fast)
             return tiled_dispatch<true>(qh, tile_atoms, gt, level, q, subset, chunks, nchunks,
-                                        root_start, root_atoms, ax, ay, az, aw, o, pc, pt, s);
+                                        root_start, root_atoms, ax, ay, az, aw, o, pc, pt, half,
+                                        s);
         return tiled_dispatch<false>(qh, tile_atoms, gt, level, q, subset, chunks, nchunks,
-                                     root_start, root_atoms, ax, ay, az, aw, o, pc, pt, s);
+                                     root_start, root_atoms, ax, ay, az, aw, o, pc, pt, half, s);
     }
     if (fast)
         return thread_dispatch<true>(qh, gt, level, q, n, subset, root_start, root_atoms, ax, ay,
@@ -1338,19 +1353,21 @@ hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, in
 }
 
 hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
-                                   hipStream_t s, const int32_t *nrd, const int32_t *nd) {
+                                   hipStream_t s, const int32_t *nrd, const int32_t *nd, int cmax) {
     if (nruns <= 0) return hipSuccess;
+    if (cmax < 1 || cmax > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_run_chunk_counts, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, nrd,
-                       nd, cnt);
+                       nd, cmax, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n,
                                  const int32_t *coff, int2 *chunks, hipStream_t s,
-                                 const int32_t *nrd, const int32_t *nd) {
+                                 const int32_t *nrd, const int32_t *nd, int cmax) {
     if (nruns <= 0) return hipSuccess;
+    if (cmax < 1 || cmax > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_run_chunk_emit, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, nrd,
-                       nd, coff, chunks);
+                       nd, cmax, coff, chunks);
     return hipGetLastError();
 }
 

@@ -410,7 +410,7 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
 // sorted subset list) for the tiled estimate kernel; uses flags/scan_a/
 // scan_b/runs as scratch.
 int32_t build_chunks(tms_ctx *ctx, const Grid *gt, int lev, const int4 *q, const int32_t *subset,
-                     int64_t n, const int2 **chunks, int64_t *nchunks) {
+                     int64_t n, const int2 **chunks, int64_t *nchunks, int cmax) {
     hipStream_t s = ctx->stream;
     int64_t nruns = 0;
     {
@@ -425,7 +425,7 @@ int32_t build_chunks(tms_ctx *ctx, const Grid *gt, int lev, const int4 *q, const
         HIPCK(launch_run_starts(ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), n,
                                 ctx->runs.as<int32_t>(), s));
         HIPCK(launch_run_chunk_counts(ctx->runs.as<int32_t>(), nruns, n, ctx->flags.as<int32_t>(),
-                                      s));
+                                      s, nullptr, nullptr, cmax));
     }
     rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), nruns, nchunks);
     if (rc) return rc;
@@ -433,7 +433,7 @@ int32_t build_chunks(tms_ctx *ctx, const Grid *gt, int lev, const int4 *q, const
     {
         TimedScope ts_(ctx, TMS_T_COMPACT);
         HIPCK(launch_run_chunk_emit(ctx->runs.as<int32_t>(), nruns, n, ctx->scan_b.as<int32_t>(),
-                                    ctx->chunks.as<int2>(), s));
+                                    ctx->chunks.as<int2>(), s, nullptr, nullptr, cmax));
     }
     *chunks = ctx->chunks.as<int2>();
     return TMS_OK;
@@ -983,6 +983,8 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         const int64_t QC = G.qcap[lev], S = G.slice[lev];
         const int nsl = (int)G.nslices[lev];
         const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
+        const bool half = tiled && ctx->tiled_half && lev >= 2;
+        const int cmax = half ? 32 : 64;
         ProjTab pt;
         int lprec = prec;  // precision of this level's estimate
         if (G.proj_table) {
@@ -1004,10 +1006,10 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                 HIPCK(exclusive_scan(flags, sa, cap, nruns, tmp, s));
                 HIPCK(launch_run_starts(flags, sa, cap, G.runs.as<int32_t>(), s));
                 HIPCK(launch_run_chunk_counts(G.runs.as<int32_t>(), cap, cap, flags, s, nruns,
-                                              ns + k));
+                                              ns + k, cmax));
                 HIPCK(exclusive_scan(flags, sb, cap, nchunks, tmp, s));
                 HIPCK(launch_run_chunk_emit(G.runs.as<int32_t>(), cap, cap, sb, G.chunks.as<int2>(),
-                                            s, nruns, ns + k));
+                                            s, nruns, ns + k, cmax));
                 chunks = G.chunks.as<int2>();
                 ncount = nchunks;
                 HIPCK(launch_fill_u32(G.tick.as<uint32_t>(), 0u, 8, s));
@@ -1017,7 +1019,9 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                          G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
                                          reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
                                          ctx->tile_atoms, s, ncount, pt,
-                                         tiled ? G.tick.as<unsigned>() : nullptr));
+                                         tiled && !half && lev >= 2 ? G.tick.as<unsigned>()
+                                                                    : nullptr,
+                                         half));
             HIPCK(launch_bound(g, lev, lprec, cap, dec + off, G.abuf.as<double>(),
                                G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
         }
@@ -1246,6 +1250,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
             const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
+            const bool half = tiled && ctx->tiled_half && lev >= 2;
             ProjTab pt;
             int lprec = prec;  // precision of this level's estimate
             if (ctx->proj_table) {
@@ -1270,7 +1275,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 const int2 *chunks = nullptr;
                 int64_t nchunks = 0;
                 if (tiled) {
-                    rc = build_chunks(ctx, gt, lev, q + off, nullptr, ns, &chunks, &nchunks);
+                    rc = build_chunks(ctx, gt, lev, q + off, nullptr, ns, &chunks, &nchunks,
+                                      half ? 32 : 64);
                     if (rc) return rc;
                 }
                 unsigned *tick = nullptr;
@@ -1289,7 +1295,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         cells->aw.as<double>(), ctx->dec.as<uint8_t>() + off,
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
                         hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s, nullptr,
-                        pt, tick));
+                        pt, half ? nullptr : tick, half));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
@@ -1840,11 +1846,14 @@ int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
         return fail(ctx, TMS_E_INVALID, "proj_table must be 0 or 1");
     if (t->tiled_persistent != 0 && t->tiled_persistent != 1)
         return fail(ctx, TMS_E_INVALID, "tiled_persistent must be 0 or 1");
+    if (t->tiled_half != 0 && t->tiled_half != 1)
+        return fail(ctx, TMS_E_INVALID, "tiled_half must be 0 or 1");
     ctx->slice_cubes = t->slice_cubes;
     ctx->tiled_min_level = t->tiled_min_level;
     ctx->tile_atoms = t->tile_atoms;
     ctx->proj_table = t->proj_table;
     ctx->tiled_dyn = t->tiled_persistent != 0;
+    ctx->tiled_half = t->tiled_half != 0;
     return TMS_OK;
 }
 
@@ -1855,6 +1864,8 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t) {
     t->tile_atoms = ctx->tile_atoms;
     t->proj_table = ctx->proj_table;
     t->tiled_persistent = ctx->tiled_dyn ? 1 : 0;
+    t->tiled_half = ctx->tiled_half ? 1 : 0;
+    t->reserved = 0;
     return TMS_OK;
 }
 
@@ -1918,6 +1929,11 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
     {
         tms_tuning t = b;
         t.tiled_persistent = 1 - b.tiled_persistent;
+        if ((rc = consider(t))) return rc;
+    }
+    {
+        tms_tuning t = b;
+        t.tiled_half = 1 - b.tiled_half;
         if ((rc = consider(t))) return rc;
     }
     const tms_tuning bch = b;

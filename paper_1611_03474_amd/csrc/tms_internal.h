@@ -193,6 +193,7 @@ struct tms_ctx {
     int64_t slice_cubes = (int64_t)1 << 26;
     int tiled_min_level = 1;
     int tile_atoms = 8;
+    bool tiled_half = false;  // levels 2-3 in half-wave chunks of <= 32 cubes
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
     tms::DevBuf ptab;       // that table
     tms::DevBuf tick;       // [8] chunk slot counters of the tiled estimate
@@ -299,7 +300,8 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
-                                  const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr);
+                                  const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr,
+                                  bool half = false);
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
 // fill the projection table (t: [3 n ns][6] doubles)
@@ -315,12 +317,14 @@ hipError_t launch_run_flags(const Grid *gt, int level, const int4 *q, const int3
                             int64_t n, int32_t *f, hipStream_t s, const int32_t *nd = nullptr);
 hipError_t launch_run_starts(const int32_t *f, const int32_t *off, int64_t n, int32_t *starts,
                              hipStream_t s);
+// chunks of at most cmax (<= 64) consecutive entries of one run
 hipError_t launch_run_chunk_counts(const int32_t *starts, int64_t nruns, int64_t n, int32_t *cnt,
                                    hipStream_t s, const int32_t *nrd = nullptr,
-                                   const int32_t *nd = nullptr);
+                                   const int32_t *nd = nullptr, int cmax = 64);
 hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n,
                                  const int32_t *coff, int2 *chunks, hipStream_t s,
-                                 const int32_t *nrd = nullptr, const int32_t *nd = nullptr);
+                                 const int32_t *nrd = nullptr, const int32_t *nd = nullptr,
+                                 int cmax = 64);
 hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s,
                                    const int32_t *nd = nullptr);
 hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n,

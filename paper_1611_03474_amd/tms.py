@@ -45,10 +45,11 @@ class Timing(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("slice_cubes", C.c_int64), ("tiled_min_level", C.c_int32),
                 ("tile_atoms", C.c_int32), ("proj_table", C.c_int32),
-                ("tiled_persistent", C.c_int32)]
+                ("tiled_persistent", C.c_int32), ("tiled_half", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class TmsError(RuntimeError):
@@ -423,7 +424,7 @@ class Context:
 
     # ---------------------------------------------------------------- tuning
     def set_tuning(self, slice_cubes=None, tiled_min_level=None, tile_atoms=None,
-                   proj_table=None, tiled_persistent=None):
+                   proj_table=None, tiled_persistent=None, tiled_half=None):
         t = self.get_tuning()
         if slice_cubes is not None:
             t.slice_cubes = int(slice_cubes)
@@ -435,6 +436,8 @@ class Context:
             t.proj_table = int(proj_table)
         if tiled_persistent is not None:
             t.tiled_persistent = int(tiled_persistent)
+        if tiled_half is not None:
+            t.tiled_half = int(tiled_half)
         self._check(self.lib.tms_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self) -> Tuning:

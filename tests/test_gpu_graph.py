@@ -60,15 +60,16 @@ def test_graph_single(ctx, prec):
     ctx.free_cells(cells)
 
 
-@pytest.mark.parametrize("proj_table", [1, 0], ids=["table", "in_place"])
-def test_graph_batch_sliced(ctx, proj_table):
+@pytest.mark.parametrize("proj_table,half", [(1, 0), (0, 0), (1, 1)],
+                         ids=["table", "in_place", "half_chunks"])
+def test_graph_batch_sliced(ctx, proj_table, half):
     # a batch, with queue slices far smaller than the levels so the slicing
     # of the captured pass is exercised too
     confs = [synth.globule(n, 3000 + k) for k, n in enumerate([300, 120, 500, 220])]
     cells = ctx.build_cells_batch(confs, tms.make_params(D=0.9, tau=1e-3,
                                                          precision=tms.PREC_FP32_GUARD))
     base = ctx.get_tuning().as_dict()
-    ctx.set_tuning(slice_cubes=4096, proj_table=proj_table)
+    ctx.set_tuning(slice_cubes=4096, proj_table=proj_table, tiled_half=half)
     try:
         _check_replays(ctx, cells, len(confs))
     finally:
