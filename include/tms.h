@@ -343,7 +343,9 @@ typedef struct {
                                 the intervals within R_c of it (48 B per
                                 atom, axis and interval: about
                                 3 * ceil(2 R_c / h) + 9 entries per atom at
-                                spacing h) and gather from that table;
+                                spacing h) and gather from that table
+                                (a level whose table does not fit in
+                                device memory projects in place);
                                 0: each chunk projects in place          */
     int32_t tiled_persistent; /* 1: the tiled estimate runs a fixed grid of
                                 workgroups that draw chunks from per-XCD

@@ -931,9 +931,10 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     // has the most intervals per atom)
     G.proj_table = false;
     if (ctx->proj_table && cells->n > 0) {
+        // without room for the table the captured levels project in place
         const int ns = proj_table_slots(cells, g.K);
-        HIPCK(G.ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)ns));
-        G.proj_table = true;
+        G.proj_table =
+            G.ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)ns) == hipSuccess;
     }
     hipStream_t s = ctx->stream;
     HIPCK(hipMemsetAsync(G.q[0].p, 0, G.q[0].cap, s));
@@ -1253,14 +1254,18 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const bool half = tiled && ctx->tiled_half && lev >= 2;
             ProjTab pt;
             int lprec = prec;  // precision of this level's estimate
-            if (ctx->proj_table) {
+            const int pns = proj_table_slots(cells, lev);
+            // a table that does not fit in device memory leaves the level to
+            // in-place projections
+            if (ctx->proj_table &&
+                ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)pns) ==
+                    hipSuccess) {
                 // the table amortises the exponentials over every cube that
                 // reads an entry, so its projections are exact in either mode
                 // (and the level needs no guard)
                 lprec = TMS_PREC_FP64;
-                const int ns = proj_table_slots(cells, lev);
+                const int ns = pns;
                 const int64_t na = cells->n;
-                HIPCK(ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)na * (size_t)ns));
                 {
                     TimedScope ts_(ctx, TMS_T_TABLE);
                     HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, cells->ax.as<double>(),
