@@ -249,6 +249,17 @@ def test_adaptive_parity_small(ctx, g200, prec, tau):
     _compare(ctx, g200, prec, D=0.9, tau=tau)
 
 
+@pytest.mark.parametrize("prec", PRECS, ids=["fp64", "fp32g"])
+@pytest.mark.parametrize("h0,h_min,tau", [(1.5, 0.1875, 0.1), (2.0, 0.125, 0.1),
+                                          (2.0, 0.125, 1e-3)],
+                         ids=["h0_1.5", "K4_tau0.1", "K4_tau1e-3"])
+def test_adaptive_parity_lattices(ctx, g200, prec, h0, h_min, tau):
+    # h0 not a power of two (cell and table coordinates by division rather
+    # than exact scaling) and a fourth level (per-thread estimate from a wider
+    # projection table)
+    _compare(ctx, g200, prec, D=0.9, tau=tau, h0=h0, h_min=h_min)
+
+
 @pytest.mark.parametrize("D", [0.5, 0.9, 1.5])
 def test_adaptive_parity_1000(ctx, g1000, D):
     _compare(ctx, g1000, tms.PREC_FP32_GUARD, D=D, tau=1e-3)
