@@ -60,7 +60,8 @@ struct EstOut {
     unsigned *hardCount; // device counter (reset by the host per pass)
     const int32_t *ncount;  // device count of entries (or chunks) when the
                             // launch is sized by a capacity; null: the launch size
-    unsigned *tick = nullptr;  // [8] zeroed slot counters (capacity-sized tiled launch)
+    unsigned *tick = nullptr;  // [8] zeroed slot counters (persistent tiled grid)
+    unsigned *ovf = nullptr;   // set when a capacity-sized tiled grid is short of chunks
 };
 
 constexpr uint8_t DEC_HARD = 255;
@@ -323,6 +324,10 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     // order however long single chunks take.  Every workgroup stops at its
     // first slot past the end; the counters only grow.
     const int64_t nch = o.ncount ? min((int64_t)*o.ncount, nch_cap) : nch_cap;
+    // a capacity-sized grid of one workgroup per chunk that is too small for
+    // the device's chunk count reports it (the results are then not used)
+    if (!DYN && o.ovf && o.ncount && blockIdx.x == 0 && lane == 0 && *o.ncount > (int)gridDim.x)
+        atomicOr(o.ovf, 1u);
     const unsigned xq = blockIdx.x & 7u;
     unsigned tdraw = 0;
     if (DYN && lane == 0) tdraw = atomicAdd(o.tick + xq, 1u);
@@ -1073,11 +1078,10 @@ hipError_t estimate_tiled_t(int ch, const Grid *g, int level, const int4 *q, con
                             const double *aw, const EstOut &o, unsigned long long *pairs,
                             const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
-    // with slot counters (required when the chunk count is on the device) a
-    // fixed grid (a multiple of 8) draws chunks from per-XCD counters;
-    // otherwise one workgroup per chunk
+    // with slot counters a fixed grid (a multiple of 8) draws chunks from
+    // per-XCD counters; otherwise one workgroup per chunk (with the count on
+    // the device: nchunks is the capacity, and a shortfall is flagged)
     const bool dyn = o.tick != nullptr;
-    if (o.ncount && !dyn) return hipErrorInvalidValue;
     const unsigned grid = (unsigned)(dyn ? std::min<int64_t>((nchunks + 7) / 8 * 8, kStrideGrid)
                                          : nchunks);
     // atoms staged per LDS tile (a tuning knob; the arithmetic is the same)
@@ -1287,12 +1291,12 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount,
-                                  const ProjTab &pt, unsigned *tick, bool half) {
+                                  const ProjTab &pt, unsigned *tick, bool half, unsigned *ovf) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf};
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)

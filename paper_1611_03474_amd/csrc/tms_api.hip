@@ -105,7 +105,7 @@ void tms_graph_state::release() {
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
-                        &stmp, &seg, &ptab, &tick};
+                        &stmp, &seg, &ptab};
     for (auto *x : b) x->release();
 }
 
@@ -866,6 +866,12 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
         G.slice[l] = (G.qcap[l] + G.nslices[l] - 1) / G.nslices[l];
         qmax = std::max(qmax, G.qcap[l]);
         smax = std::max(smax, G.slice[l]);
+        // one workgroup per chunk for the tiled levels: a slice holds at most
+        // as many chunks as cubes, and at most the level's (from the eager
+        // pass, which counted them over its own slicing) plus one per cut
+        G.ccap[l] = ctx->last_chunks[l] < 0
+                        ? G.slice[l]
+                        : std::min(G.slice[l], grow(ctx->last_chunks[l]) + G.nslices[l]);
     }
     // edge lattices, as the eager extraction lays them out
     std::vector<EdgeLat> et((size_t)G.nconf);
@@ -926,7 +932,6 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.ctr.ensure(sizeof(unsigned long long) * kCtSlots));
     HIPCK(G.stmp.ensure(scan_tmp_bytes(std::max(nmax, std::max(cwords, ewords))) + 512));
     HIPCK(G.seg.ensure(sizeof(int64_t) * 2 * (size_t)(G.nlev * G.nconf)));
-    HIPCK(G.tick.ensure(8 * sizeof(unsigned)));
     // projection tables (one buffer, refilled per level; the finest level
     // has the most intervals per atom)
     G.proj_table = false;
@@ -1013,16 +1018,17 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                             s, nruns, ns + k, cmax));
                 chunks = G.chunks.as<int2>();
                 ncount = nchunks;
-                HIPCK(launch_fill_u32(G.tick.as<uint32_t>(), 0u, 8, s));
             }
-            HIPCK(launch_estimate_decide(g, gt, lev, lprec, q + off, cap, nullptr, chunks, cap, rs, ra,
+            // levels 2-3 in whole-wave chunks: one workgroup per chunk up to
+            // the planned capacity (the grouped kernels stride over theirs)
+            const bool percap = tiled && !half && lev >= 2;
+            HIPCK(launch_estimate_decide(g, gt, lev, lprec, q + off, cap, nullptr, chunks,
+                                         percap ? std::min(cap, G.ccap[lev]) : cap, rs, ra,
                                          ax, ay, az, aw, dec + off, G.abuf.as<double>(),
                                          G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
                                          reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
-                                         ctx->tile_atoms, s, ncount, pt,
-                                         tiled && !half && lev >= 2 ? G.tick.as<unsigned>()
-                                                                    : nullptr,
-                                         half));
+                                         ctx->tile_atoms, s, ncount, pt, nullptr, half,
+                                         percap ? ovf : nullptr));
             HIPCK(launch_bound(g, lev, lprec, cap, dec + off, G.abuf.as<double>(),
                                G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
         }
@@ -1184,6 +1190,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     int64_t L = 0;
     ctx->leaf_off.assign(1, 0);
+    int64_t chunks_lvl[TMS_MAX_LEVELS];  // whole-wave chunks per level (-1: not chunked so)
+    std::fill(chunks_lvl, chunks_lvl + TMS_MAX_LEVELS, (int64_t)-1);
 
     if (cells->p.mode == TMS_MODE_UNIFORM) {
         L = cells->nroots;
@@ -1252,6 +1260,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             // deep levels: chunks of <= 64 consecutive cubes of one root
             const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
             const bool half = tiled && ctx->tiled_half && lev >= 2;
+            int64_t level_chunks = 0;
             ProjTab pt;
             int lprec = prec;  // precision of this level's estimate
             const int pns = proj_table_slots(cells, lev);
@@ -1283,6 +1292,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                     rc = build_chunks(ctx, gt, lev, q + off, nullptr, ns, &chunks, &nchunks,
                                       half ? 32 : 64);
                     if (rc) return rc;
+                    level_chunks += nchunks;
                 }
                 unsigned *tick = nullptr;
                 if (tiled && ctx->tiled_dyn) {
@@ -1309,6 +1319,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                                        ctx->hidx.as<int32_t>(), hard, s));
                 }
             }
+            chunks_lvl[lev] = tiled && !half ? level_chunks : -1;
             if (lprec == TMS_PREC_FP32_GUARD) {
                 {
                     TimedScope ts_(ctx, TMS_T_COMPACT);
@@ -1414,6 +1425,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
     ctx->n_leaves = L;
     ctx->last_stats = st;
     ctx->last_stats_cells = cells->id;
+    for (int l = 0; l < TMS_MAX_LEVELS; ++l) ctx->last_chunks[l] = chunks_lvl[l];
     if (stats) *stats = st;
     *n_leaves = L;
     if (!leaves_out) return TMS_OK;

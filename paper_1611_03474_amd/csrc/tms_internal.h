@@ -147,9 +147,10 @@ struct tms_graph_state {
     int nlev = 0, nconf = 1;
     int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0;
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
+    int64_t ccap[TMS_MAX_LEVELS] = {};  // chunks per slice launch of a tiled level
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
         lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, verts,
-        etab, sz, ctr, stmp, seg, ptab, tick;
+        etab, sz, ctr, stmp, seg, ptab;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
@@ -180,6 +181,7 @@ struct tms_ctx {
     // counters of the last partition (sizes the capture), and the capture
     tms_stats last_stats{};
     uint64_t last_stats_cells = 0;
+    int64_t last_chunks[TMS_MAX_LEVELS] = {};  // whole-wave chunks per level of that pass (-1: none)
     tms_graph_state graph;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
@@ -301,7 +303,7 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
                                   const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr,
-                                  bool half = false);
+                                  bool half = false, unsigned *ovf = nullptr);
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
 // fill the projection table (t: [3 n ns][6] doubles)
