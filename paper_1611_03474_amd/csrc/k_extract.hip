@@ -130,98 +130,114 @@ __device__ __forceinline__ int64_t edge_bit(const EdgeLat &el, const tms_leaf &L
 
 // one thread per leaf: the bits of its crossing edges, merged per 64-bit word
 // (the four edges of one axis fall in at most two words, usually), one
-// atomic OR per distinct word
+// atomic OR per distinct word.  The OR that sets a bit makes its leaf the
+// edge's writer: own[q] receives those edges (bit e for edge e).  Leaves that
+// share an edge share its corner values, so whichever of them sets the bit,
+// the vertex written is the same.
 __global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n,
                             const EdgeLat *__restrict__ et, unsigned long long *__restrict__ bm,
-                            const int64_t *__restrict__ nd) {
+                            uint16_t *__restrict__ own, const int64_t *__restrict__ nd) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (q >= n || (nd && q >= *nd)) return;
     const tms_leaf L = leaves[q];
-    if (L.cls != TMS_CLS_SURFACE) return;
-    const EdgeLat &el = et[L.conf];
-    int64_t w[12];
-    unsigned long long m[12];
+    unsigned o = 0;
+    if (L.cls == TMS_CLS_SURFACE) {
+        const EdgeLat &el = et[L.conf];
+        int64_t w[12];
+        unsigned long long m[12];
 #pragma unroll
-    for (int e = 0; e < 12; ++e) {
-        int axis, off[3], v0, v1;
-        edge_corners(e, axis, off, v0, v1);
-        const bool cross = ((L.mask >> v0) ^ (L.mask >> v1)) & 1;
-        const int64_t b = edge_bit(el, L, axis, off);
-        w[e] = b >> 6;
-        m[e] = cross ? 1ull << (b & 63) : 0ull;
+        for (int e = 0; e < 12; ++e) {
+            int axis, off[3], v0, v1;
+            edge_corners(e, axis, off, v0, v1);
+            const bool cross = ((L.mask >> v0) ^ (L.mask >> v1)) & 1;
+            const int64_t b = edge_bit(el, L, axis, off);
+            w[e] = b >> 6;
+            m[e] = cross ? 1ull << (b & 63) : 0ull;
+        }
+        unsigned done = 0;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            if (m[e] == 0 || ((done >> e) & 1)) continue;
+            unsigned long long bits = 0;
+            unsigned grp = 0;
+#pragma unroll
+            for (int u = e; u < 12; ++u)
+                if (m[u] && w[u] == w[e]) {
+                    bits |= m[u];
+                    grp |= 1u << u;
+                }
+            done |= grp;
+            const unsigned long long old = atomicOr(bm + w[e], bits);
+#pragma unroll
+            for (int u = e; u < 12; ++u)
+                if (((grp >> u) & 1) && !(old & m[u])) o |= 1u << u;
+        }
     }
-#pragma unroll
-    for (int e = 0; e < 12; ++e) {
-        if (m[e] == 0) continue;
-        unsigned long long bits = m[e];
-#pragma unroll
-        for (int u = e + 1; u < 12; ++u)
-            if (w[u] == w[e]) {
-                bits |= m[u];
-                m[u] = 0;
-            }
-        atomicOr(bm + w[e], bits);
-    }
+    own[q] = (uint16_t)o;
 }
 
-// every leaf that has a crossing edge writes its vertex at the edge's rank
-// (leaves sharing the edge share its corner values, so they write the same
-// bits); the list comes out in edge-key order.  One thread per (leaf, edge).
+// the vertices of the edges a leaf owns, each at its edge's rank (the list
+// comes out in edge-key order).  One thread per leaf.
 __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__restrict__ leaves,
                              const double *__restrict__ cphi, int64_t n,
                              const EdgeLat *__restrict__ et, const uint64_t *__restrict__ bm,
-                             const int32_t *__restrict__ woff, tms_vertex *__restrict__ out,
-                             const int64_t *__restrict__ nd, int64_t vcap,
-                             unsigned *__restrict__ ovf) {
-    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 12 * n || (nd && c >= 12 * *nd)) return;
-    const int64_t q = c / 12;
+                             const int32_t *__restrict__ woff, const uint16_t *__restrict__ own,
+                             tms_vertex *__restrict__ out, const int64_t *__restrict__ nd,
+                             int64_t vcap, unsigned *__restrict__ ovf) {
+    const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (q >= n || (nd && q >= *nd)) return;
+    const unsigned o = own[q];
+    if (!o) return;
     const tms_leaf L = leaves[q];
-    if (L.cls != TMS_CLS_SURFACE) return;
-    int axis, off[3], v0, v1;
-    edge_corners((int)(c % 12), axis, off, v0, v1);
-    if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) return;
     const Grid &g = gt[L.conf];
-    const int64_t b = edge_bit(et[L.conf], L, axis, off);
-    const int64_t w = b >> 6;
-    const int64_t r = (int64_t)woff[w] + __popcll(bm[w] & ((1ull << (b & 63)) - 1ull));
-    if (ovf && r >= vcap) {  // capacity-sized buffer (capture path)
-        atomicOr(ovf, 1u);
-        return;
-    }
-    const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
+    const EdgeLat &el = et[L.conf];
     const int sh = g.K - L.level;
     const double h = ldexp(g.h0, -(int)L.level);
-    double p[3] = {g.o[0] + (double)((L.ix + off[0]) << sh) * g.hmin,
-                   g.o[1] + (double)((L.iy + off[1]) << sh) * g.hmin,
-                   g.o[2] + (double)((L.iz + off[2]) << sh) * g.hmin};
-    const double t = (g.c - f0) / (f1 - f0);
-    p[axis] += t * h;
-    tms_vertex V;
-    V.edge_key = edge_key(L, axis, off, g.K);
-    V.t = t;
-    V.x = p[0];
-    V.y = p[1];
-    V.z = p[2];
-    out[r] = V;
+#pragma unroll
+    for (int e = 0; e < 12; ++e) {
+        if (!((o >> e) & 1)) continue;
+        int axis, off[3], v0, v1;
+        edge_corners(e, axis, off, v0, v1);
+        const int64_t b = edge_bit(el, L, axis, off);
+        const int64_t w = b >> 6;
+        const int64_t r = (int64_t)woff[w] + __popcll(bm[w] & ((1ull << (b & 63)) - 1ull));
+        if (ovf && r >= vcap) {  // capacity-sized buffer (capture path)
+            atomicOr(ovf, 1u);
+            continue;
+        }
+        const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
+        double p[3] = {g.o[0] + (double)((L.ix + off[0]) << sh) * g.hmin,
+                       g.o[1] + (double)((L.iy + off[1]) << sh) * g.hmin,
+                       g.o[2] + (double)((L.iz + off[2]) << sh) * g.hmin};
+        const double t = (g.c - f0) / (f1 - f0);
+        p[axis] += t * h;
+        tms_vertex V;
+        V.edge_key = edge_key(L, axis, off, g.K);
+        V.t = t;
+        V.x = p[0];
+        V.y = p[1];
+        V.z = p[2];
+        out[r] = V;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
-                            unsigned long long *bm, hipStream_t s, const int64_t *nd) {
+                            unsigned long long *bm, uint16_t *own, hipStream_t s,
+                            const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, et, bm, nd);
+    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, et, bm, own, nd);
     return hipGetLastError();
 }
 
 hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
                              const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
-                             tms_vertex *out, hipStream_t s, const int64_t *nd, int64_t vcap,
-                             unsigned *ovf) {
+                             const uint16_t *own, tms_vertex *out, hipStream_t s,
+                             const int64_t *nd, int64_t vcap, unsigned *ovf) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_write, dim3(nblk(12 * n)), dim3(kBS), 0, s, gt, leaves, cphi, n, et,
-                       bm, woff, out, nd, vcap, ovf);
+    hipLaunchKernelGGL(k_edge_write, dim3(nblk(n)), dim3(kBS), 0, s, gt, leaves, cphi, n, et, bm,
+                       woff, own, out, nd, vcap, ovf);
     return hipGetLastError();
 }
 

@@ -104,7 +104,7 @@ void tms_graph_state::release() {
     cells_id = 0;
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
-                        &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &verts, &etab, &sz, &ctr,
+                        &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &eown, &verts, &etab, &sz, &ctr,
                         &stmp, &seg, &ptab};
     for (auto *x : b) x->release();
 }
@@ -925,6 +925,7 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.uguard.ensure((size_t)G.ucap));
     HIPCK(G.ebmap.ensure(sizeof(uint64_t) * (size_t)ewords));
     HIPCK(G.ebcnt.ensure(4 * (size_t)ewords));
+    HIPCK(G.eown.ensure(sizeof(uint16_t) * (size_t)G.lcap));
     HIPCK(G.eboff.ensure(4 * (size_t)ewords));
     HIPCK(G.verts.ensure(sizeof(tms_vertex) * (size_t)G.vcap));
     HIPCK(G.etab.ensure(sizeof(EdgeLat) * (size_t)G.nconf + sizeof(int64_t) * (size_t)G.nconf));
@@ -1105,11 +1106,13 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     const int64_t *fw = reinterpret_cast<const int64_t *>(et + nconf);
     const int64_t ew = G.ewords;
     HIPCK(launch_fill_u64(G.ebmap.as<uint64_t>(), 0ull, ew, s));
-    HIPCK(launch_edge_mark(lv, G.lcap, et, G.ebmap.as<unsigned long long>(), s, Ld));
+    HIPCK(launch_edge_mark(lv, G.lcap, et, G.ebmap.as<unsigned long long>(),
+                           G.eown.as<uint16_t>(), s, Ld));
     HIPCK(launch_popc(G.ebmap.as<uint64_t>(), ew, G.ebcnt.as<int32_t>(), s));
     HIPCK(exclusive_scan(G.ebcnt.as<int32_t>(), G.eboff.as<int32_t>(), ew, nv, tmp, s));
     HIPCK(launch_edge_write(gt, lv, G.cphi.as<double>(), G.lcap, et, G.ebmap.as<uint64_t>(),
-                            G.eboff.as<int32_t>(), G.verts.as<tms_vertex>(), s, Ld, G.vcap, ovf));
+                            G.eboff.as<int32_t>(), G.eown.as<uint16_t>(),
+                            G.verts.as<tms_vertex>(), s, Ld, G.vcap, ovf));
     HIPCK(launch_gather_i32(G.eboff.as<int32_t>(), fw, nconf, vert_off, s));
     return TMS_OK;
 }
@@ -1528,11 +1531,13 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
                              hipMemcpyHostToDevice, s));
         HIPCK(ctx->ebmap.ensure(sizeof(uint64_t) * (size_t)nwords));
         HIPCK(ctx->ebcnt.ensure(sizeof(int32_t) * (size_t)nwords));
+        HIPCK(ctx->eown.ensure(sizeof(uint16_t) * (size_t)n));
         HIPCK(ctx->eboff.ensure(sizeof(int32_t) * (size_t)nwords));
         {
             TimedScope ts_(ctx, TMS_T_EXTRACT);
             HIPCK(launch_fill_u64(ctx->ebmap.as<uint64_t>(), 0ull, nwords, s));
-            HIPCK(launch_edge_mark(lv, n, et, ctx->ebmap.as<unsigned long long>(), s));
+            HIPCK(launch_edge_mark(lv, n, et, ctx->ebmap.as<unsigned long long>(),
+                                   ctx->eown.as<uint16_t>(), s));
             HIPCK(launch_popc(ctx->ebmap.as<uint64_t>(), nwords, ctx->ebcnt.as<int32_t>(), s));
         }
         int32_t rc = scan_total(ctx, ctx->ebcnt.as<int32_t>(), ctx->eboff.as<int32_t>(), nwords, &nv);
@@ -1542,7 +1547,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
             TimedScope ts_(ctx, TMS_T_EXTRACT);
             HIPCK(launch_edge_write(cells->gtab.as<Grid>(), lv, cphi, n, et,
                                     ctx->ebmap.as<uint64_t>(), ctx->eboff.as<int32_t>(),
-                                    ctx->verts.as<tms_vertex>(), s));
+                                    ctx->eown.as<uint16_t>(), ctx->verts.as<tms_vertex>(), s));
         }
         // first vertex of every conformation: the rank of its first word
         HIPCK(launch_gather_i32(ctx->eboff.as<int32_t>(), fw, nconf, vo, s));

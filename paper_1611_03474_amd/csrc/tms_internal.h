@@ -149,8 +149,8 @@ struct tms_graph_state {
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
     int64_t ccap[TMS_MAX_LEVELS] = {};  // chunks per slice launch of a tiled level
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
-        lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, verts,
-        etab, sz, ctr, stmp, seg, ptab;
+        lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, eown,
+        verts, etab, sz, ctr, stmp, seg, ptab;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
@@ -174,7 +174,7 @@ struct tms_ctx {
     uint64_t corner_cells = 0, edge_cells = 0;  // tms_cells::id they belong to
     bool corner_dense = false, edge_dense = false;
     tms::EdgeLat edge_lat{};
-    tms::DevBuf ebmap, ebcnt, eboff, wbar, uconf, etab, lsort, ctab;
+    tms::DevBuf ebmap, ebcnt, eboff, eown, wbar, uconf, etab, lsort, ctab;
     // batch bookkeeping of the last partition / extraction: per-conformation
     // leaf and vertex offsets ([nconf + 1] each)
     std::vector<int64_t> leaf_off, vert_off;
@@ -403,12 +403,16 @@ hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const 
 
 // k_extract.hip
 // et: device table of edge lattices, one per conformation
+// own: [n] edges whose bit the leaf set (bit e for edge e), written by the
+// mark and read by the write
 hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
-                            unsigned long long *bm, hipStream_t s, const int64_t *nd = nullptr);
+                            unsigned long long *bm, uint16_t *own, hipStream_t s,
+                            const int64_t *nd = nullptr);
 hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
                              const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
-                             tms_vertex *out, hipStream_t s, const int64_t *nd = nullptr,
-                             int64_t vcap = 0, unsigned *ovf = nullptr);
+                             const uint16_t *own, tms_vertex *out, hipStream_t s,
+                             const int64_t *nd = nullptr, int64_t vcap = 0,
+                             unsigned *ovf = nullptr);
 hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                               uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
 hipError_t launch_edge_emit(const Grid *gt, const tms_leaf *leaves, const double *corner_phi,
