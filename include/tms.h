@@ -323,8 +323,9 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
  * does.  Defaults: slice_cubes 2^26, tiled_min_level 1, tile_atoms 8,
- * proj_table 1, tiled_persistent 0 (captured passes always draw chunks from
- * the per-XCD counters), tiled_half 0. */
+ * proj_table 1, tiled_persistent 0, tiled_half 0.  A captured pass takes
+ * them as they are at capture, except that its whole-wave tiled launches are
+ * always one workgroup per chunk (sized from the eager pass's chunk count). */
 typedef struct {
     int64_t slice_cubes;     /* largest queue slice per estimate + bound
                                 launch (a level is cut into ceil(n / this)
@@ -353,8 +354,9 @@ typedef struct {
                                 order); 0: one workgroup per chunk        */
     int32_t tiled_half;      /* 1: levels 2-3 in chunks of <= 32 cubes, two
                                 per wavefront (half-wave groups, each with
-                                its own atom stream); 0: one chunk of <= 64
-                                cubes per wavefront                        */
+                                its own atom stream); 2: level 2 so, level 3
+                                whole-wave; 0: one chunk of <= 64 cubes per
+                                wavefront                                   */
     int32_t reserved;        /* 0                                          */
 } tms_tuning;
 
@@ -365,11 +367,10 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t);
 /* Autotuner: times tms_partition_estimate on `cells` (count only, device
  * results discarded) under candidate tunings -- atoms per tile, then the
  * projection table on or off, the tiled grid (persistent or one workgroup
- * per chunk), half-wave chunks on or off, the first tiled level, then the
- * slice size, each with the
- * others at their best so far -- checks that every
- * candidate gives the same leaf and cube
- * counts, and leaves the fastest set on ctx.
+ * per chunk), half-wave chunks (off, levels 2-3, level 2), the first tiled
+ * level, then the slice size, each with the others at their best so far --
+ * checks that every candidate gives the same leaf and cube counts, and
+ * leaves the fastest set on ctx.
  *  best     host out (or NULL): the chosen tuning.
  *  best_ms  host out (or NULL): its wall time in ms.
  *  n_tried  host out (or NULL): passes timed.

@@ -248,6 +248,23 @@ hipError_t launch_scatter_atoms(const Grid *gt, const double *xyzr, int64_t n, c
     return hipGetLastError();
 }
 
+// (x, y, z, w) of each atom in one 32-byte record, in cell order: the point
+// kernels read an atom with one pair of 16-byte loads
+__global__ void k_pack_atoms(const double *__restrict__ ax, const double *__restrict__ ay,
+                             const double *__restrict__ az, const double *__restrict__ aw, int64_t n,
+                             double4 *__restrict__ xw) {
+    const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (i >= n) return;
+    xw[i] = make_double4(ax[i], ay[i], az[i], aw[i]);
+}
+
+hipError_t launch_pack_atoms(const double *ax, const double *ay, const double *az, const double *aw,
+                             int64_t n, double4 *xw, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_atoms, dim3(nblk(n)), dim3(kBS), 0, s, ax, ay, az, aw, n, xw);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *ax, double *ay,
                              double *az, double *aw, double *ar, int32_t *aidx, hipStream_t s) {
     hipLaunchKernelGGL(k_sort_cells, dim3(nblk(ncells)), dim3(kBS), 0, s, cell_start, ncells, ax, ay,

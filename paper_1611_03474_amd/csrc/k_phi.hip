@@ -24,10 +24,7 @@ __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
                                                     const int32_t *__restrict__ pconf,
                                                     const double *__restrict__ pts,
                                                     int64_t m, const int32_t *__restrict__ cs,
-                                                    const double *__restrict__ ax,
-                                                    const double *__restrict__ ay,
-                                                    const double *__restrict__ az,
-                                                    const double *__restrict__ aw,
+                                                    const double4 *__restrict__ xw,
                                                     double band_rel, double *__restrict__ phi,
                                                     double *__restrict__ grad,
                                                     uint8_t *__restrict__ guard,
@@ -37,7 +34,7 @@ __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
     const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
-    phi_at<FAST, GRAD>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi_at<FAST, GRAD>(g, p, cs, xw, f, gr);
     phi[k] = f;
     if (GRAD) {
         grad[3 * k] = gr[0];
@@ -55,10 +52,7 @@ __global__ __launch_bounds__(kBS) void k_phi_subset(const Grid *__restrict__ gt,
                                                     const double *__restrict__ pts,
                                                     const int32_t *__restrict__ list, int64_t m,
                                                     const int32_t *__restrict__ cs,
-                                                    const double *__restrict__ ax,
-                                                    const double *__restrict__ ay,
-                                                    const double *__restrict__ az,
-                                                    const double *__restrict__ aw,
+                                                    const double4 *__restrict__ xw,
                                                     double *__restrict__ phi,
                                                     double *__restrict__ grad,
                                                     const int32_t *__restrict__ nd) {
@@ -68,7 +62,7 @@ __global__ __launch_bounds__(kBS) void k_phi_subset(const Grid *__restrict__ gt,
     const Grid &g = gt[pconf ? pconf[k] : 0];
     const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
     double f, gr[3];
-    phi_at<false>(g, p, cs, ax, ay, az, aw, f, gr);
+    phi_at<false>(g, p, cs, xw, f, gr);
     phi[k] = f;
     if (grad) {
         grad[3 * k] = gr[0];
@@ -291,36 +285,68 @@ __global__ void k_popc(const uint64_t *__restrict__ bm, int64_t nw, int32_t *__r
 }
 
 // one thread per leaf: its 8 corner bits, merged per 64-bit word (a
-// finest-level leaf usually has all 8 in one 4x4x4 block), one atomic OR per
-// distinct word
+// finest-level leaf usually has all 8 in one 4x4x4 block); then the
+// wavefront merges the words of all its leaves (consecutive leaves share
+// blocks) and ORs each distinct word into the bitmap once
 __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, int K,
                               const Grid *__restrict__ gt, unsigned long long *__restrict__ bm,
                               const int64_t *__restrict__ nd) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (q >= n || (nd && q >= *nd)) return;
-    const tms_leaf L = leaves[q];
-    const Lat lat = gt[L.conf].clat;
+    const int lane = threadIdx.x & 63;
+    // every lane stays to the end: the merge reads all lanes' registers
+    const bool act = q < n && !(nd && q >= *nd);
     int64_t w[8];
     unsigned long long m[8];
+    unsigned pend = 0;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-        int64_t X, Y, Z;
-        leaf_corner(L, v, K, X, Y, Z);
-        const int64_t b = lat_bit(lat, X, Y, Z);
-        w[v] = b >> 6;
-        m[v] = 1ull << (b & 63);
+        w[v] = 0;
+        m[v] = 0;
     }
+    if (act) {
+        const tms_leaf L = leaves[q];
+        const Lat lat = gt[L.conf].clat;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        if (m[v] == 0) continue;
-        unsigned long long bits = m[v];
+        for (int v = 0; v < 8; ++v) {
+            int64_t X, Y, Z;
+            leaf_corner(L, v, K, X, Y, Z);
+            const int64_t b = lat_bit(lat, X, Y, Z);
+            w[v] = b >> 6;
+            m[v] = 1ull << (b & 63);
+        }
 #pragma unroll
-        for (int u = v + 1; u < 8; ++u)
-            if (w[u] == w[v]) {
-                bits |= m[u];
-                m[u] = 0;
+        for (int v = 0; v < 8; ++v) {
+            if (m[v] == 0) continue;
+#pragma unroll
+            for (int u = v + 1; u < 8; ++u)
+                if (m[u] != 0 && w[u] == w[v]) {
+                    m[v] |= m[u];
+                    m[u] = 0;
+                }
+            pend |= 1u << v;
+        }
+    }
+    // one distinct word per round: the first lane with a word left names
+    // it, every lane gives its bits of that word, one atomic OR
+    while (true) {
+        const unsigned long long left = __ballot(pend != 0);
+        if (left == 0) break;
+        const int leader = __ffsll(left) - 1;
+        int64_t fw = 0;
+#pragma unroll
+        for (int v = 7; v >= 0; --v)
+            if ((pend >> v) & 1) fw = w[v];
+        const int64_t W = __shfl(fw, leader, 64);
+        unsigned long long mine = 0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (((pend >> v) & 1) && w[v] == W) {
+                mine |= m[v];
+                pend &= ~(1u << v);
             }
-        atomicOr(bm + w[v], bits);
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) mine |= __shfl_xor(mine, d, 64);
+        if (lane == leader) atomicOr(bm + W, mine);
     }
 }
 
@@ -430,37 +456,36 @@ hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const 
 }
 
 hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision, const double *pts,
-                             int64_t m, const int32_t *cs, const double *ax, const double *ay,
-                             const double *az, const double *aw, double band_rel, double *phi,
-                             double *grad, uint8_t *guard, hipStream_t s, const int32_t *nd) {
+                             int64_t m, const int32_t *cs, const double4 *xw, double band_rel,
+                             double *phi, double *grad, uint8_t *guard, hipStream_t s,
+                             const int32_t *nd) {
     if (m <= 0) return hipSuccess;
     // corner values need no gradient: a variant without it
     if (precision == TMS_PREC_FP32_GUARD) {
         if (grad)
             hipLaunchKernelGGL((k_phi_points<true, true>), dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf,
-                               pts, m, cs, ax, ay, az, aw, band_rel, phi, grad, guard, nd);
+                               pts, m, cs, xw, band_rel, phi, grad, guard, nd);
         else
             hipLaunchKernelGGL((k_phi_points<true, false>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
-                               pconf, pts, m, cs, ax, ay, az, aw, band_rel, phi, grad, guard, nd);
+                               pconf, pts, m, cs, xw, band_rel, phi, grad, guard, nd);
     } else {
         if (grad)
             hipLaunchKernelGGL((k_phi_points<false, true>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
-                               pconf, pts, m, cs, ax, ay, az, aw, 0.0, phi, grad, nullptr, nd);
+                               pconf, pts, m, cs, xw, 0.0, phi, grad, nullptr, nd);
         else
             hipLaunchKernelGGL((k_phi_points<false, false>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
-                               pconf, pts, m, cs, ax, ay, az, aw, 0.0, phi, grad, nullptr, nd);
+                               pconf, pts, m, cs, xw, 0.0, phi, grad, nullptr, nd);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
                                     const int32_t *list, int64_t m, const int32_t *cs,
-                                    const double *ax, const double *ay, const double *az,
-                                    const double *aw, double *phi, double *grad, hipStream_t s,
+                                    const double4 *xw, double *phi, double *grad, hipStream_t s,
                                     const int32_t *nd) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, list, m, cs, ax,
-                       ay, az, aw, phi, grad, nd);
+    hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, list, m, cs, xw,
+                       phi, grad, nd);
     return hipGetLastError();
 }
 

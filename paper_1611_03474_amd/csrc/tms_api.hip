@@ -113,6 +113,7 @@ void tms_cells::release() {
     gtab.release();
     aoff.release();
     ax.release();
+    axw.release();
     ay.release();
     az.release();
     aw.release();
@@ -275,9 +276,7 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts,
     {
         TimedScope ts_(ctx, TMS_T_PHI);
         HIPCK(launch_phi_points(gt, pconf, prec, pts, m, cells->cell_start.as<int32_t>(),
-                                cells->ax.as<double>(), cells->ay.as<double>(),
-                                cells->az.as<double>(), cells->aw.as<double>(), band_rel, phi,
-                                grad, gbuf, ctx->stream));
+                                cells->axw.as<double4>(), band_rel, phi, grad, gbuf, ctx->stream));
     }
     if (prec == TMS_PREC_FP32_GUARD) {
         HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)m));
@@ -292,9 +291,8 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts,
                                    ctx->idx.as<int32_t>(), ctx->stream));
             TimedScope ts_(ctx, TMS_T_GUARD);
             HIPCK(launch_phi_points_subset(gt, pconf, pts, ctx->idx.as<int32_t>(), ng,
-                                           cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
-                                           cells->ay.as<double>(), cells->az.as<double>(),
-                                           cells->aw.as<double>(), phi, grad, ctx->stream));
+                                           cells->cell_start.as<int32_t>(),
+                                           cells->axw.as<double4>(), phi, grad, ctx->stream));
         }
         *n_guard = ng;
     }
@@ -759,6 +757,7 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
     CK(cells->ay.ensure(8 * na));
     CK(cells->az.ensure(8 * na));
     CK(cells->aw.ensure(8 * na));
+    CK(cells->axw.ensure(32 * na));
     CK(cells->ar.ensure(8 * na));
     CK(cells->aidx.ensure(4 * na));
     CK(cells->tmp_key.ensure(4 * na));
@@ -780,6 +779,8 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
     CK(launch_sort_cells(cells->cell_start.as<int32_t>(), ncells, cells->ax.as<double>(),
                          cells->ay.as<double>(), cells->az.as<double>(), cells->aw.as<double>(),
                          cells->ar.as<double>(), cells->aidx.as<int32_t>(), s));
+    CK(launch_pack_atoms(cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
+                         cells->aw.as<double>(), n, cells->axw.as<double4>(), s));
     cells->n_root_entries = 0;
     if (p->mode == TMS_MODE_ADAPTIVE) {
         const int64_t nr = cells->nroots;
@@ -805,6 +806,11 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
     return TMS_OK;
 }
 
+
+// whether level lev of the tiled path runs in half-wave chunks
+inline bool half_level(const tms_ctx *ctx, int lev) {
+    return (ctx->tiled_half == 1 && lev >= 2) || (ctx->tiled_half == 2 && lev == 2);
+}
 
 // ---------------------------------------------------------------------------
 // Captured pass: the whole partition (roots, every level, guard re-runs,
@@ -990,7 +996,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         const int64_t QC = G.qcap[lev], S = G.slice[lev];
         const int nsl = (int)G.nslices[lev];
         const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
-        const bool half = tiled && ctx->tiled_half && lev >= 2;
+        const bool half = tiled && half_level(ctx, lev);
         const int cmax = half ? 32 : 64;
         ProjTab pt;
         int lprec = prec;  // precision of this level's estimate
@@ -1086,7 +1092,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                              G.uniq.as<double>(), G.uconf.as<int32_t>(), s, G.ucap, ovf));
     const bool fast = prec == TMS_PREC_FP32_GUARD;
     HIPCK(launch_phi_points(gt, G.uconf.as<int32_t>(), prec, G.uniq.as<double>(), G.ucap,
-                            cells->cell_start.as<int32_t>(), ax, ay, az, aw, kCornerBand,
+                            cells->cell_start.as<int32_t>(), cells->axw.as<double4>(), kCornerBand,
                             G.uphi.as<double>(), nullptr, fast ? G.uguard.as<uint8_t>() : nullptr, s,
                             nu));
     if (fast) {
@@ -1094,7 +1100,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         HIPCK(exclusive_scan(flags, sa, G.ucap, ngp, tmp, s));
         HIPCK(launch_list_emit(flags, sa, G.ucap, idx, s));
         HIPCK(launch_phi_points_subset(gt, G.uconf.as<int32_t>(), G.uniq.as<double>(), idx, G.ucap,
-                                       cells->cell_start.as<int32_t>(), ax, ay, az, aw,
+                                       cells->cell_start.as<int32_t>(), cells->axw.as<double4>(),
                                        G.uphi.as<double>(), nullptr, s, ngp));
     }
     HIPCK(launch_corner_gather_bm(lv, G.lcap, K, gt, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(),
@@ -1262,7 +1268,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
             const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
-            const bool half = tiled && ctx->tiled_half && lev >= 2;
+            const bool half = tiled && half_level(ctx, lev);
             int64_t level_chunks = 0;
             ProjTab pt;
             int lprec = prec;  // precision of this level's estimate
@@ -1868,14 +1874,14 @@ int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
         return fail(ctx, TMS_E_INVALID, "proj_table must be 0 or 1");
     if (t->tiled_persistent != 0 && t->tiled_persistent != 1)
         return fail(ctx, TMS_E_INVALID, "tiled_persistent must be 0 or 1");
-    if (t->tiled_half != 0 && t->tiled_half != 1)
-        return fail(ctx, TMS_E_INVALID, "tiled_half must be 0 or 1");
+    if (t->tiled_half < 0 || t->tiled_half > 2)
+        return fail(ctx, TMS_E_INVALID, "tiled_half must be 0, 1 or 2");
     ctx->slice_cubes = t->slice_cubes;
     ctx->tiled_min_level = t->tiled_min_level;
     ctx->tile_atoms = t->tile_atoms;
     ctx->proj_table = t->proj_table;
     ctx->tiled_dyn = t->tiled_persistent != 0;
-    ctx->tiled_half = t->tiled_half != 0;
+    ctx->tiled_half = t->tiled_half;
     return TMS_OK;
 }
 
@@ -1886,7 +1892,7 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t) {
     t->tile_atoms = ctx->tile_atoms;
     t->proj_table = ctx->proj_table;
     t->tiled_persistent = ctx->tiled_dyn ? 1 : 0;
-    t->tiled_half = ctx->tiled_half ? 1 : 0;
+    t->tiled_half = ctx->tiled_half;
     t->reserved = 0;
     return TMS_OK;
 }
@@ -1953,9 +1959,11 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
         t.tiled_persistent = 1 - b.tiled_persistent;
         if ((rc = consider(t))) return rc;
     }
-    {
-        tms_tuning t = b;
-        t.tiled_half = 1 - b.tiled_half;
+    const tms_tuning bh = b;
+    for (int h : {0, 1, 2}) {
+        if (h == bh.tiled_half) continue;
+        tms_tuning t = bh;
+        t.tiled_half = h;
         if ((rc = consider(t))) return rc;
     }
     const tms_tuning bch = b;

@@ -481,15 +481,24 @@ __device__ __forceinline__ double over_cs(const Grid &g, double x) {
 // phi and grad phi at one point (eq. Gaussian1).
 // ---------------------------------------------------------------------------
 // Sum over atoms within R_c of p, in canonical atom order (cell rows of the
-// stencil, atoms in cell order).  *err (FAST only) bounds |dphi|.
+// stencil, atoms in cell order); xw holds the atoms as (x, y, z, w).
 template <bool FAST, bool GRAD = true>
 __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
-                                       const int32_t *__restrict__ cs, const double *__restrict__ ax,
-                                       const double *__restrict__ ay, const double *__restrict__ az,
-                                       const double *__restrict__ aw, double &phi, double gr[3]) {
+                                       const int32_t *__restrict__ cs,
+                                       const double4 *__restrict__ xw, double &phi, double gr[3]) {
     const double D = g.D, m2D = -2.0 * g.D;
     phi = 0.0;
     gr[0] = gr[1] = gr[2] = 0.0;
+    auto add = [&](double w, double dx, double dy, double dz, double d2) {
+        const double term = w * expn<FAST>(-D * d2);
+        phi += term;
+        if (GRAD) {
+            const double f = m2D * term;
+            gr[0] += f * dx;
+            gr[1] += f * dy;
+            gr[2] += f * dz;
+        }
+    };
     int c0[3], c1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -517,18 +526,22 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
             if (x0 > x1) continue;
             const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
             const int b = cs[row + x0], e = cs[row + x1 + 1];
-            for (int i = b; i < e; ++i) {
-                const double dx = p[0] - ax[i], dy = p[1] - ay[i], dz = p[2] - az[i];
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                if (d2 > g.rc2) continue;
-                const double term = aw[i] * expn<FAST>(-D * d2);
-                phi += term;
-                if (GRAD) {
-                    const double f = m2D * term;
-                    gr[0] += f * dx;
-                    gr[1] += f * dy;
-                    gr[2] += f * dz;
-                }
+            // two atoms per step, so that their loads are in flight together;
+            // the terms are still added one atom at a time, in cell order
+            for (int i = b; i < e; i += 2) {
+                const bool two = i + 1 < e;
+                const double4 a0 = xw[i], a1 = xw[two ? i + 1 : i];
+                // both records requested before either is used
+                __builtin_amdgcn_sched_barrier(0);
+                const double dx0 = p[0] - a0.x, dy0 = p[1] - a0.y, dz0 = p[2] - a0.z;
+                const double dx1 = p[0] - a1.x, dy1 = p[1] - a1.y, dz1 = p[2] - a1.z;
+                const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+                const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+                const bool in0 = !(d20 > g.rc2), in1 = two && !(d21 > g.rc2);
+                // weights selected here keep their loads beside the coordinates'
+                const double w0 = in0 ? a0.w : 0.0, w1 = in1 ? a1.w : 0.0;
+                if (in0) add(w0, dx0, dy0, dz0, d20);
+                if (in1) add(w1, dx1, dy1, dz1, d21);
             }
         }
     }

@@ -126,6 +126,7 @@ struct tms_cells {
     uint64_t id = 0;             // changes with every build (kept results name it)
     // device memory, atoms sorted by cell (ascending original index inside a cell)
     tms::DevBuf ax, ay, az, aw, aidx, ar;   // double x3, w = exp(D r^2), int32 index, r
+    tms::DevBuf axw;                        // double4 (x, y, z, w) per atom, cell order
     tms::DevBuf cell_start;                 // int32 [ncells + 1]
     tms::DevBuf root_start;                 // int32 [nroots + 1]
     tms::DevBuf root_atoms;                 // int32 [n_root_entries]
@@ -195,7 +196,7 @@ struct tms_ctx {
     int64_t slice_cubes = (int64_t)1 << 26;
     int tiled_min_level = 1;
     int tile_atoms = 8;
-    bool tiled_half = false;  // levels 2-3 in half-wave chunks of <= 32 cubes
+    int tiled_half = 0;  // half-wave chunks of <= 32 cubes: 1 levels 2-3, 2 level 2
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
     tms::DevBuf ptab;       // that table
     tms::DevBuf tick;       // [8] chunk slot counters of the tiled estimate
@@ -239,6 +240,8 @@ hipError_t launch_bin_atoms(const Grid *gt, int nconf, const double *xyzr, int64
 hipError_t launch_scatter_atoms(const Grid *gt, const double *xyzr, int64_t n, const int32_t *key,
                                 int32_t *fill, double *ax, double *ay, double *az, double *aw,
                                 double *ar, int32_t *aidx, hipStream_t s);
+hipError_t launch_pack_atoms(const double *ax, const double *ay, const double *az, const double *aw,
+                             int64_t n, double4 *xw, hipStream_t s);
 hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *ax, double *ay,
                              double *az, double *aw, double *ar, int32_t *aidx, hipStream_t s);
 hipError_t launch_root_count(const Grid *gt, int nconf, const int32_t *cell_start,
@@ -352,15 +355,14 @@ hipError_t launch_fast_exp_debug(const double *x, int64_t n, double *y, hipStrea
 
 // k_phi.hip
 // pconf: conformation of every point (NULL: all in conformation 0)
+// xw: the cells' packed atoms (x, y, z, w)
 hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision, const double *pts,
-                             int64_t m, const int32_t *cell_start, const double *ax,
-                             const double *ay, const double *az, const double *aw, double band_rel,
-                             double *phi, double *grad, uint8_t *guard, hipStream_t s,
-                             const int32_t *nd = nullptr);
+                             int64_t m, const int32_t *cell_start, const double4 *xw,
+                             double band_rel, double *phi, double *grad, uint8_t *guard,
+                             hipStream_t s, const int32_t *nd = nullptr);
 hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
                                     const int32_t *list, int64_t m, const int32_t *cell_start,
-                                    const double *ax, const double *ay, const double *az,
-                                    const double *aw, double *phi, double *grad, hipStream_t s,
+                                    const double4 *xw, double *phi, double *grad, hipStream_t s,
                                     const int32_t *nd = nullptr);
 hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
                                 uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);

@@ -60,8 +60,8 @@ def test_graph_single(ctx, prec):
     ctx.free_cells(cells)
 
 
-@pytest.mark.parametrize("proj_table,half", [(1, 0), (0, 0), (1, 1)],
-                         ids=["table", "in_place", "half_chunks"])
+@pytest.mark.parametrize("proj_table,half", [(1, 0), (0, 0), (1, 1), (1, 2)],
+                         ids=["table", "in_place", "half_chunks", "half_level2"])
 def test_graph_batch_sliced(ctx, proj_table, half):
     # a batch, with queue slices far smaller than the levels so the slicing
     # of the captured pass is exercised too
