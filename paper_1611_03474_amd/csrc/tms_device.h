@@ -477,6 +477,9 @@ __device__ __forceinline__ double over_cs(const Grid &g, double x) {
     return g.inv_cs != 0.0 ? x * g.inv_cs : x / g.cs;
 }
 
+// atoms whose records one step of the point loop loads together
+constexpr int kPhiBatch = 2;
+
 // ---------------------------------------------------------------------------
 // phi and grad phi at one point (eq. Gaussian1).
 // ---------------------------------------------------------------------------
@@ -526,22 +529,25 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
             if (x0 > x1) continue;
             const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
             const int b = cs[row + x0], e = cs[row + x1 + 1];
-            // two atoms per step, so that their loads are in flight together;
-            // the terms are still added one atom at a time, in cell order
-            for (int i = b; i < e; i += 2) {
-                const bool two = i + 1 < e;
-                const double4 a0 = xw[i], a1 = xw[two ? i + 1 : i];
-                // both records requested before either is used
+            // kPhiBatch atoms per step, so that their loads are in flight
+            // together; the terms are still added one atom at a time, in cell
+            // order
+            for (int i = b; i < e; i += kPhiBatch) {
+                double4 a[kPhiBatch];
+#pragma unroll
+                for (int k = 0; k < kPhiBatch; ++k) a[k] = xw[i + k < e ? i + k : i];
+                // every record requested before any is used
                 __builtin_amdgcn_sched_barrier(0);
-                const double dx0 = p[0] - a0.x, dy0 = p[1] - a0.y, dz0 = p[2] - a0.z;
-                const double dx1 = p[0] - a1.x, dy1 = p[1] - a1.y, dz1 = p[2] - a1.z;
-                const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
-                const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
-                const bool in0 = !(d20 > g.rc2), in1 = two && !(d21 > g.rc2);
-                // weights selected here keep their loads beside the coordinates'
-                const double w0 = in0 ? a0.w : 0.0, w1 = in1 ? a1.w : 0.0;
-                if (in0) add(w0, dx0, dy0, dz0, d20);
-                if (in1) add(w1, dx1, dy1, dz1, d21);
+#pragma unroll
+                for (int k = 0; k < kPhiBatch; ++k) {
+                    const double dx = p[0] - a[k].x, dy = p[1] - a[k].y, dz = p[2] - a[k].z;
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = i + k < e && !(d2 > g.rc2);
+                    // the weight selected here keeps its load beside the
+                    // coordinates'
+                    const double w = in ? a[k].w : 0.0;
+                    if (in) add(w, dx, dy, dz, d2);
+                }
             }
         }
     }
