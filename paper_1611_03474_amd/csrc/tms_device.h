@@ -145,28 +145,50 @@ __device__ __forceinline__ void imul(double a0, double a1, double b0, double b1,
 // ---------------------------------------------------------------------------
 struct JRot {
     double c, s, t;
-    bool on;
 };
+
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimates (about
+// single-precision accurate) refined by two Newton steps each, which reach
+// double precision (each step squares the relative error).
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double e = fma(-(x * y), y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double q = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) q = fma(q, fma(-x, q, 1.0), q);
+    return q;
+}
 
 // Rotation [[c, s], [-s, c]] on (p, q) that zeroes e in [[a, e], [e, b]]:
 // t = tan(angle) is the root of smaller magnitude of t^2 + 2 theta t - 1 = 0,
-// theta = (b - a) / (2 e), written as 2 e / (d + sign(d) sqrt(d^2 + 4 e^2))
-// with d = b - a; then the new diagonal is a - t e, b + t e.
+// theta = (b - a) / (2 e), written as sign(d) 2 e / (|d| + sqrt(d^2 + 4 e^2))
+// with d = b - a; then the new diagonal is a - t e, b + t e.  c and s are
+// computed from t, so the rotation is orthogonal to rounding whatever the
+// last bits of t; an off-diagonal whose rotation would need an r^2 below the
+// normal range (negligible against the diagonal) gets t = 0 and is dropped.
 __device__ __forceinline__ JRot jrot_params(double a, double b, double e) {
-    JRot R{1.0, 0.0, 0.0, false};
-    if (e == 0.0) return R;
-    const double d = b - a, r = sqrt(d * d + 4.0 * e * e);
-    if (!(r > 0.0)) return R;  // e negligible (its square underflows)
-    R.t = 2.0 * e / (d + copysign(r, d));
-    R.c = rsqrt(1.0 + R.t * R.t);
-    R.s = R.t * R.c;
-    R.on = true;
+    const double d = b - a, r2 = d * d + 4.0 * e * e;
+    const bool on = e != 0.0 && r2 >= 2.2250738585072014e-308;
+    const double r = r2 * rsq_nr(on ? r2 : 1.0);
+    double t = 2.0 * e * rcp_nr(on ? fabs(d) + r : 1.0);
+    t = signbit(d) ? -t : t;
+    t = on ? t : 0.0;
+    JRot R;
+    R.t = t;
+    R.c = rsq_nr(fma(t, t, 1.0));
+    R.s = t * R.c;
     return R;
 }
 
 __device__ __forceinline__ void jrot_apply(double S[4][4], double V[4][4], int p, int q,
                                            const JRot &R) {
-    if (!R.on) return;
     const double e = S[p][q];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
