@@ -534,42 +534,58 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
         c1[a] = min(ci + g.span, g.nc[a] - 1);
     }
     // rows of the stencil along x, each clipped to the chord of the R_c
-    // sphere; skipped cells hold only atoms beyond R_c
-    for (int cz = c0[2]; cz <= c1[2]; ++cz) {
+    // sphere (skipped cells hold only atoms beyond R_c); the chord's half
+    // length comes from the hardware reciprocal square root, enlarged by
+    // 2^-20 relative to cover its error, so a row may keep a cell more than
+    // needed (whose atoms the distance test drops) but never one less
+    auto row_range = [&](int cz, int cy, int &b, int &e) {
+        b = 0;
+        e = 0;
         const double lz = g.o[2] + cz * g.cs;
         const double ez = fmax(fmax(lz - p[2], p[2] - (lz + g.cs)), 0.0);
-        const double rz = g.rc2 - ez * ez;
-        if (rz < 0.0) continue;
-        for (int cy = c0[1]; cy <= c1[1]; ++cy) {
-            const double ly = g.o[1] + cy * g.cs;
-            const double ey = fmax(fmax(ly - p[1], p[1] - (ly + g.cs)), 0.0);
-            const double ryz = rz - ey * ey;
-            if (ryz < 0.0) continue;
-            const double hx = sqrt(ryz);
-            const int x0 = max(c0[0], (int)floor(over_cs(g, p[0] - hx - g.o[0])));
-            const int x1 = min(c1[0], (int)floor(over_cs(g, p[0] + hx - g.o[0])));
-            if (x0 > x1) continue;
-            const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
-            const int b = cs[row + x0], e = cs[row + x1 + 1];
-            // kPhiBatch atoms per step, so that their loads are in flight
-            // together; the terms are still added one atom at a time, in cell
-            // order
-            for (int i = b; i < e; i += kPhiBatch) {
-                double4 a[kPhiBatch];
+        const double ly = g.o[1] + cy * g.cs;
+        const double ey = fmax(fmax(ly - p[1], p[1] - (ly + g.cs)), 0.0);
+        const double ryz = (g.rc2 - ez * ez) - ey * ey;
+        if (!(ryz >= 0.0)) return;
+        const double hx = ryz > 0.0 ? ryz * __builtin_amdgcn_rsq(ryz) * (1.0 + 0x1p-20) : 0.0;
+        const int x0 = max(c0[0], (int)floor(over_cs(g, p[0] - hx - g.o[0])));
+        const int x1 = min(c1[0], (int)floor(over_cs(g, p[0] + hx - g.o[0])));
+        if (x0 > x1) return;
+        const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
+        b = cs[row + x0];
+        e = cs[row + x1 + 1];
+    };
+    const int ny = c1[1] - c0[1] + 1;
+    const int nrow = (ny > 0 && c1[2] >= c0[2]) ? (c1[2] - c0[2] + 1) * ny : 0;
+    int cz = c0[2], cy = c0[1], b = 0, e = 0;
+    if (nrow > 0) row_range(cz, cy, b, e);
+    for (int r = 0; r < nrow; ++r) {
+        const int rb = b, re = e;
+        // the next row's cell range is requested before this row's atoms
+        // are summed, so its loads overlap them
+        if (++cy > c1[1]) {
+            cy = c0[1];
+            ++cz;
+        }
+        if (r + 1 < nrow) row_range(cz, cy, b, e);
+        // kPhiBatch atoms per step, so that their loads are in flight
+        // together; the terms are still added one atom at a time, in cell
+        // order
+        for (int i = rb; i < re; i += kPhiBatch) {
+            double4 a[kPhiBatch];
 #pragma unroll
-                for (int k = 0; k < kPhiBatch; ++k) a[k] = xw[i + k < e ? i + k : i];
-                // every record requested before any is used
-                __builtin_amdgcn_sched_barrier(0);
+            for (int k = 0; k < kPhiBatch; ++k) a[k] = xw[i + k < re ? i + k : i];
+            // every record requested before any is used
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int k = 0; k < kPhiBatch; ++k) {
-                    const double dx = p[0] - a[k].x, dy = p[1] - a[k].y, dz = p[2] - a[k].z;
-                    const double d2 = dx * dx + dy * dy + dz * dz;
-                    const bool in = i + k < e && !(d2 > g.rc2);
-                    // the weight selected here keeps its load beside the
-                    // coordinates'
-                    const double w = in ? a[k].w : 0.0;
-                    if (in) add(w, dx, dy, dz, d2);
-                }
+            for (int k = 0; k < kPhiBatch; ++k) {
+                const double dx = p[0] - a[k].x, dy = p[1] - a[k].y, dz = p[2] - a[k].z;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                const bool in = i + k < re && !(d2 > g.rc2);
+                // the weight selected here keeps its load beside the
+                // coordinates'
+                const double w = in ? a[k].w : 0.0;
+                if (in) add(w, dx, dy, dz, d2);
             }
         }
     }
