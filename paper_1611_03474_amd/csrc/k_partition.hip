@@ -899,6 +899,56 @@ __global__ void k_run_chunk_emit(const int32_t *__restrict__ starts, int64_t nru
         o[k] = make_int2((int32_t)(b + cmax * k), (int32_t)min<int64_t>(cmax, len - cmax * k));
 }
 
+// Chunks reordered by the length of their root's atom list, longest first, in
+// buckets of 8 atoms: a wavefront of the grouped kernel then holds groups of
+// like length, which loop about equally long.  A counting sort: per-workgroup
+// bucket counts (LDS atomics), one scan over (bucket, workgroup), then each
+// workgroup scatters its chunks from its own offsets (the order inside a
+// workgroup's bucket is that of its LDS atomics).  Each chunk's result is its
+// own, so the order changes no value.
+__device__ __forceinline__ int chunk_len_bucket(const Grid *__restrict__ gt, int level,
+                                                const int4 *__restrict__ q, int2 ch,
+                                                const int32_t *__restrict__ root_start) {
+    const int4 c = q[ch.x];
+    const Grid &g = gt[c.w];
+    const int64_t root = g.root_base +
+        ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
+    const int len = root_start[root + 1] - root_start[root];
+    return kLenBuckets - 1 - min(len >> 3, kLenBuckets - 1);
+}
+
+// bcnt[b * gridDim.x + block]: chunks of workgroup `block` in bucket b
+__global__ __launch_bounds__(kLenBuckets) void k_chunk_len_hist(
+    const Grid *__restrict__ gt, int level, const int4 *__restrict__ q,
+    const int2 *__restrict__ chunks, int64_t n, const int32_t *__restrict__ ncount,
+    const int32_t *__restrict__ root_start, int32_t *__restrict__ bkt, int32_t *__restrict__ bcnt) {
+    __shared__ int h[kLenBuckets];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)kLenBuckets + t;
+    const int64_t nn = ncount ? min((int64_t)*ncount, n) : n;
+    if (i < nn) {
+        const int b = chunk_len_bucket(gt, level, q, chunks[i], root_start);
+        bkt[i] = b;
+        atomicAdd(&h[b], 1);
+    }
+    __syncthreads();
+    bcnt[(int64_t)t * gridDim.x + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(kLenBuckets) void k_chunk_len_scatter(
+    const int2 *__restrict__ chunks, int64_t n, const int32_t *__restrict__ ncount,
+    const int32_t *__restrict__ bkt, const int32_t *__restrict__ boff, int2 *__restrict__ out) {
+    __shared__ int h[kLenBuckets];
+    const int t = threadIdx.x;
+    h[t] = boff[(int64_t)t * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)kLenBuckets + t;
+    const int64_t nn = ncount ? min((int64_t)*ncount, n) : n;
+    if (i < nn) out[atomicAdd(&h[bkt[i]], 1)] = chunks[i];
+}
+
 __global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n,
                               const int32_t *__restrict__ nd, int32_t *__restrict__ f) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
@@ -1372,6 +1422,25 @@ hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n
     if (cmax < 1 || cmax > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_run_chunk_emit, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, nrd,
                        nd, cmax, coff, chunks);
+    return hipGetLastError();
+}
+
+int64_t chunks_by_length_scratch(int64_t n) {
+    return (int64_t)kLenBuckets * ((n + kLenBuckets - 1) / kLenBuckets);
+}
+
+hipError_t launch_chunks_by_length(const Grid *gt, int level, const int4 *q, const int2 *chunks,
+                                   int64_t n, const int32_t *ncount, const int32_t *root_start,
+                                   int32_t *bkt, int32_t *bcnt, int32_t *boff, void *tmp,
+                                   int2 *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + kLenBuckets - 1) / kLenBuckets;
+    hipLaunchKernelGGL(k_chunk_len_hist, dim3((unsigned)nb), dim3(kLenBuckets), 0, s, gt, level, q,
+                       chunks, n, ncount, root_start, bkt, bcnt);
+    hipError_t e = exclusive_scan(bcnt, boff, nb * kLenBuckets, nullptr, tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chunk_len_scatter, dim3((unsigned)nb), dim3(kLenBuckets), 0, s, chunks, n,
+                       ncount, bkt, boff, out);
     return hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ void tms_graph_state::release() {
     cap_stream = nullptr;
     cells_id = 0;
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
-                        &runs, &chunks, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
+                        &runs, &chunks, &chunks2, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &eown, &verts, &etab, &sz, &ctr,
                         &stmp, &seg, &ptab};
     for (auto *x : b) x->release();
@@ -437,6 +437,28 @@ int32_t build_chunks(tms_ctx *ctx, const Grid *gt, int lev, const int4 *q, const
     return TMS_OK;
 }
 
+// The chunks reordered by root-list length, longest first, for the grouped
+// kernel (whose wavefronts take several consecutive chunks); uses flags,
+// scan_a, scan_b and scan_c as scratch.
+int32_t chunks_by_length(tms_ctx *ctx, const tms_cells *cells, int lev, const int4 *q,
+                         const int2 **chunks, int64_t nchunks) {
+    if (nchunks <= 0) return TMS_OK;
+    hipStream_t s = ctx->stream;
+    const size_t m = (size_t)chunks_by_length_scratch(nchunks);
+    HIPCK(ctx->chunks2.ensure(sizeof(int2) * (size_t)nchunks));
+    HIPCK(ctx->flags.ensure(4 * (size_t)nchunks));
+    HIPCK(ctx->scan_a.ensure(4 * m));
+    HIPCK(ctx->scan_b.ensure(4 * m));
+    HIPCK(ctx->scan_c.ensure(scan_tmp_bytes((int64_t)m) + 512));
+    TimedScope ts_(ctx, TMS_T_COMPACT);
+    HIPCK(launch_chunks_by_length(cells->gtab.as<Grid>(), lev, q, *chunks, nchunks, nullptr,
+                                  cells->root_start.as<int32_t>(), ctx->flags.as<int32_t>(),
+                                  ctx->scan_a.as<int32_t>(), ctx->scan_b.as<int32_t>(),
+                                  ctx->scan_c.p, ctx->chunks2.as<int2>(), s));
+    *chunks = ctx->chunks2.as<int2>();
+    return TMS_OK;
+}
+
 // A batch's leaves come out level by level with the conformations in order
 // inside each level; regroup them conformation by conformation, each keeping
 // the order of its own single-conformation pass (level, refinement order).
@@ -532,7 +554,7 @@ int32_t tms_destroy(tms_ctx *ctx) {
                            &ctx->scan_b, &ctx->scan_c, &ctx->flags, &ctx->idx, &ctx->hkeys,
                            &ctx->hown, &ctx->slot, &ctx->uniq, &ctx->uphi, &ctx->uguard, &ctx->lc,
                            &ctx->ctmp, &ctx->counters, &ctx->hostpin, &ctx->hidx, &ctx->chunks,
-                           &ctx->runs};
+                           &ctx->chunks2, &ctx->runs};
     for (auto *b : bufs) b->release();
     ctx->graph.release();
     timing_flush(ctx);
@@ -906,7 +928,9 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     if (64.0 * (double)cwords > kMaxBitmapBits || ebits > kMaxBitmapBits ||
         cwords >= (int64_t)0x7FFFFFFF || ewords >= (int64_t)0x7FFFFFFF)
         return fail(ctx, TMS_E_INVALID, "capture needs the dense corner and edge bitmaps");
-    const int64_t nmax = std::max({qmax, G.ucap, cells->nroots + 1, (int64_t)1});
+    // (+ kLenBuckets: the bucket counts of a chunk reordering round the
+    // chunk count up to whole workgroups)
+    const int64_t nmax = std::max({qmax, G.ucap, cells->nroots + 1, (int64_t)1}) + kLenBuckets;
     HIPCK(G.q[0].ensure(sizeof(int4) * (size_t)qmax));
     HIPCK(G.q[1].ensure(sizeof(int4) * (size_t)qmax));
     HIPCK(G.dec.ensure((size_t)qmax));
@@ -919,6 +943,7 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.idx.ensure(4 * (size_t)nmax));
     HIPCK(G.runs.ensure(4 * (size_t)smax));
     HIPCK(G.chunks.ensure(sizeof(int2) * (size_t)smax));
+    HIPCK(G.chunks2.ensure(sizeof(int2) * (size_t)smax));
     HIPCK(G.leaves.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
     HIPCK(G.lsort.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
     HIPCK(G.cphi.ensure(sizeof(double) * 8 * (size_t)G.lcap));
@@ -1025,6 +1050,12 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                             s, nruns, ns + k, cmax));
                 chunks = G.chunks.as<int2>();
                 ncount = nchunks;
+                if (lev == 1 || half) {
+                    // grouped kernel: chunks by root-list length
+                    HIPCK(launch_chunks_by_length(gt, lev, q + off, chunks, cap, ncount, rs, flags,
+                                                  sa, idx, tmp, G.chunks2.as<int2>(), s));
+                    chunks = G.chunks2.as<int2>();
+                }
             }
             // levels 2-3 in whole-wave chunks: one workgroup per chunk up to
             // the planned capacity (the grouped kernels stride over theirs)
@@ -1302,6 +1333,10 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                                       half ? 32 : 64);
                     if (rc) return rc;
                     level_chunks += nchunks;
+                    if (lev == 1 || half) {
+                        rc = chunks_by_length(ctx, cells, lev, q + off, &chunks, nchunks);
+                        if (rc) return rc;
+                    }
                 }
                 unsigned *tick = nullptr;
                 if (tiled && ctx->tiled_dyn) {
@@ -1744,7 +1779,7 @@ int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin) {
     // the captured pass has private copies of the eager partition's
     // workspace; give that back first (the next eager pass grows it again)
     for (tms::DevBuf *b : {&ctx->q[0], &ctx->q[1], &ctx->abuf, &ctx->ebuf, &ctx->hidx, &ctx->dec,
-                           &ctx->ptab, &ctx->chunks, &ctx->runs})
+                           &ctx->ptab, &ctx->chunks, &ctx->chunks2, &ctx->runs})
         b->release();
     int32_t rc = plan_graph(ctx, cells, margin);
     if (rc) {

@@ -149,9 +149,9 @@ struct tms_graph_state {
     int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0;
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
     int64_t ccap[TMS_MAX_LEVELS] = {};  // chunks per slice launch of a tiled level
-    tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, leaves,
-        lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt, eboff, eown,
-        verts, etab, sz, ctr, stmp, seg, ptab;
+    tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, chunks2,
+        leaves, lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt,
+        eboff, eown, verts, etab, sz, ctr, stmp, seg, ptab;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
@@ -186,7 +186,7 @@ struct tms_ctx {
     tms_graph_state graph;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
-        slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, runs, bmap, bmcnt, bmoff;
+        slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, chunks2, runs, bmap, bmcnt, bmoff;
     // small device counters (u64 slots): [0,64) striped pair counts,
     // [72,77) decision histogram, 80 surface count, 96 adjoint consistency
     // flag, 100 scan total; [256, 256 + 5*1024) reduction partials;
@@ -330,6 +330,16 @@ hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n
                                  const int32_t *coff, int2 *chunks, hipStream_t s,
                                  const int32_t *nrd = nullptr, const int32_t *nd = nullptr,
                                  int cmax = 64);
+// the n chunks (ncount: their device count, or null) reordered into out by
+// the length of their root's atom list, longest first; bkt: [n] scratch,
+// bcnt and boff: [chunks_by_length_scratch(n)] scratch each, tmp: scan
+// scratch for that many entries
+constexpr int kLenBuckets = 256;
+int64_t chunks_by_length_scratch(int64_t n);
+hipError_t launch_chunks_by_length(const Grid *gt, int level, const int4 *q, const int2 *chunks,
+                                   int64_t n, const int32_t *ncount, const int32_t *root_start,
+                                   int32_t *bkt, int32_t *bcnt, int32_t *boff, void *tmp,
+                                   int2 *out, hipStream_t s);
 hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s,
                                    const int32_t *nd = nullptr);
 hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
