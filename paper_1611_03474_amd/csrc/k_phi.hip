@@ -350,43 +350,54 @@ __global__ void k_corner_mark(const tms_leaf *__restrict__ leaves, int64_t n, in
     }
 }
 
-// Unique corner points from the bitmap alone: one thread per word writes the
-// lattice points of its set bits at their ranks (each point once, in rank
-// order).  Word w belongs to the last conformation whose block starts at or
-// before it; inside a block, word ((bx n1 + by) n2 + bz) covers points
+// Unique corner points from the bitmap alone, each at its bit's rank (points
+// in rank order, each once).  A wavefront covers 64 consecutive words and
+// walks its non-empty ones together: for each, lane j writes the point of
+// bit j if it is set, so the points of a word go out as one contiguous run.
+// Word w belongs to the last conformation whose block starts at or before
+// it; inside a block, word ((bx n1 + by) n2 + bz) covers points
 // (4 bx + i, 4 by + j, 4 bz + k) at bit 16 i + 4 j + k.
 __global__ void k_corner_enum(const Grid *__restrict__ gt, int nconf,
                               const uint64_t *__restrict__ bm, const int32_t *__restrict__ woff,
                               int64_t nw, double *__restrict__ upts, int32_t *__restrict__ uconf,
                               int64_t ucap, unsigned *__restrict__ ovf) {
     const int64_t w = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (w >= nw) return;
-    uint64_t m = bm[w];
-    if (!m) return;
-    int lo = 0, hi = nconf - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (gt[mid].clat.base <= w) lo = mid;
-        else hi = mid - 1;
-    }
-    const Grid &g = gt[lo];
-    const int64_t lw = w - g.clat.base;
-    const int64_t bz = lw % g.clat.n[2], t = lw / g.clat.n[2];
-    const int64_t by = t % g.clat.n[1], bx = t / g.clat.n[1];
-    int64_t u = woff[w];
-    while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1ull;
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = w < nw ? bm[w] : 0ull;
+    const int32_t wo = m ? woff[w] : 0;
+    unsigned long long left = __ballot(m != 0ull);
+    const int64_t w0 = w - lane;  // the wavefront's first word
+    while (left) {
+        const int j = __ffsll(left) - 1;
+        left &= left - 1ull;
+        const int64_t ww = w0 + j;
+        const uint64_t mm = __shfl(m, j, 64);
+        const int64_t base = __shfl(wo, j, 64);
+        int lo = 0, hi = nconf - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (gt[mid].clat.base <= ww) lo = mid;
+            else hi = mid - 1;
+        }
+        const Grid &g = gt[lo];
+        // block coordinates in 32 bits (a conformation's bitmap holds fewer
+        // than 2^31 words)
+        const uint32_t lw = (uint32_t)(ww - g.clat.base);
+        const uint32_t n2 = (uint32_t)g.clat.n[2], n1 = (uint32_t)g.clat.n[1];
+        const uint32_t t = lw / n2, bz = lw - t * n2;
+        const uint32_t bx = t / n1, by = t - bx * n1;
+        if (!((mm >> lane) & 1ull)) continue;
+        const int64_t u = base + __popcll(mm & ((1ull << lane) - 1ull));
         if (ovf && u >= ucap) {  // capacity-sized buffers (capture path)
             atomicOr(ovf, 1u);
-            return;
+            continue;
         }
-        const int64_t X = 4 * bx + (b >> 4), Y = 4 * by + ((b >> 2) & 3), Z = 4 * bz + (b & 3);
+        const int64_t X = 4 * (int64_t)bx + (lane >> 4), Y = 4 * (int64_t)by + ((lane >> 2) & 3),
+                      Z = 4 * (int64_t)bz + (lane & 3);
         upts[3 * u] = g.o[0] + (double)X * g.hmin;
         upts[3 * u + 1] = g.o[1] + (double)Y * g.hmin;
         upts[3 * u + 2] = g.o[2] + (double)Z * g.hmin;
         uconf[u] = lo;
-        ++u;
     }
 }
 
