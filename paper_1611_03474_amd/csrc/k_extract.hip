@@ -128,49 +128,114 @@ __device__ __forceinline__ int64_t edge_bit(const EdgeLat &el, const tms_leaf &L
            (((int64_t)(L.ix + off[0]) * lat.n[1] + (L.iy + off[1])) * lat.n[2] + (L.iz + off[2]));
 }
 
-// one thread per leaf: the bits of its crossing edges, merged per 64-bit word
-// (the four edges of one axis fall in at most two words, usually), one
-// atomic OR per distinct word.  The OR that sets a bit makes its leaf the
-// edge's writer: own[q] receives those edges (bit e for edge e).  Leaves that
-// share an edge share its corner values, so whichever of them sets the bit,
-// the vertex written is the same.
+// Bit of cube (X, Y, Z) of level `lev` in the leaf-lattice bitmap; false
+// outside the lattice.
+__device__ __forceinline__ bool leaf_bit(const EdgeLat &el, int lev, int64_t X, int64_t Y,
+                                         int64_t Z, int64_t &b) {
+    const Lat &lat = el.leaf[lev];
+    if (X < 0 || Y < 0 || Z < 0 || (X >> 2) >= lat.n[0] || (Y >> 2) >= lat.n[1] ||
+        (Z >> 2) >= lat.n[2])
+        return false;
+    b = lat_bit(lat, X, Y, Z);
+    return true;
+}
+
+// one bit per surface leaf in its level's leaf lattice; the wavefront merges
+// the words of all its leaves (consecutive leaves share 4x4x4 blocks) and
+// ORs each distinct word into the bitmap once
+__global__ void k_leaf_mark(const tms_leaf *__restrict__ leaves, int64_t n,
+                            const EdgeLat *__restrict__ et, unsigned long long *__restrict__ lbm,
+                            const int64_t *__restrict__ nd) {
+    const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    // every lane stays to the end: the merge reads all lanes' registers
+    bool pend = false;
+    int64_t w = 0;
+    unsigned long long m = 0;
+    if (q < n && !(nd && q >= *nd)) {
+        const tms_leaf L = leaves[q];
+        int64_t b;
+        if (L.cls == TMS_CLS_SURFACE && leaf_bit(et[L.conf], L.level, L.ix, L.iy, L.iz, b)) {
+            w = b >> 6;
+            m = 1ull << (b & 63);
+            pend = true;
+        }
+    }
+    while (true) {
+        const unsigned long long left = __ballot(pend);
+        if (left == 0) break;
+        const int leader = __ffsll(left) - 1;
+        const int64_t W = __shfl(w, leader, 64);
+        unsigned long long mine = 0;
+        if (pend && w == W) {
+            mine = m;
+            pend = false;
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) mine |= __shfl_xor(mine, d, 64);
+        if (lane == leader) atomicOr(lbm + W, mine);
+    }
+}
+
+// One thread per surface leaf.  A crossing edge is shared by the leaves of
+// its level around it (all of them surface leaves: they hold both of its end
+// corners); the leaf in which the edge sits at the smallest offset pair
+// (2 o1 + o2 over the two other axes, in edge order) that exists owns it.
+// The owner ORs the edge's bit (merged per 64-bit word) and records the edge
+// in own[q]; the leaves sharing an edge share its corner values, so the
+// owner chosen does not change the vertex.
 __global__ void k_edge_mark(const tms_leaf *__restrict__ leaves, int64_t n,
-                            const EdgeLat *__restrict__ et, unsigned long long *__restrict__ bm,
-                            uint16_t *__restrict__ own, const int64_t *__restrict__ nd) {
+                            const EdgeLat *__restrict__ et, const uint64_t *__restrict__ lbm,
+                            unsigned long long *__restrict__ bm, uint16_t *__restrict__ own,
+                            const int64_t *__restrict__ nd) {
     const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (q >= n || (nd && q >= *nd)) return;
     const tms_leaf L = leaves[q];
     unsigned o = 0;
     if (L.cls == TMS_CLS_SURFACE) {
         const EdgeLat &el = et[L.conf];
+        const int64_t P[3] = {L.ix, L.iy, L.iz};
         int64_t w[12];
         unsigned long long m[12];
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
             int axis, off[3], v0, v1;
             edge_corners(e, axis, off, v0, v1);
-            const bool cross = ((L.mask >> v0) ^ (L.mask >> v1)) & 1;
+            m[e] = 0;
+            w[e] = 0;
+            if (!(((L.mask >> v0) ^ (L.mask >> v1)) & 1)) continue;
+            // the other axes in ascending order and this leaf's offsets there
+            const int b1 = axis == 0 ? 1 : 0, b2 = axis == 2 ? 1 : 2;
+            const int o1 = off[b1], o2 = off[b2];
+            bool mine = true;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int d1 = k >> 1, d2 = k & 1;  // offsets of the edge in that leaf
+                if (2 * d1 + d2 >= 2 * o1 + o2) continue;
+                int64_t C[3] = {P[0], P[1], P[2]};
+                C[b1] += o1 - d1;
+                C[b2] += o2 - d2;
+                int64_t lb;
+                if (leaf_bit(el, L.level, C[0], C[1], C[2], lb) && ((lbm[lb >> 6] >> (lb & 63)) & 1ull))
+                    mine = false;
+            }
+            if (!mine) continue;
             const int64_t b = edge_bit(el, L, axis, off);
             w[e] = b >> 6;
-            m[e] = cross ? 1ull << (b & 63) : 0ull;
+            m[e] = 1ull << (b & 63);
+            o |= 1u << e;
         }
-        unsigned done = 0;
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
-            if (m[e] == 0 || ((done >> e) & 1)) continue;
-            unsigned long long bits = 0;
-            unsigned grp = 0;
+            if (m[e] == 0) continue;
+            unsigned long long bits = m[e];
 #pragma unroll
-            for (int u = e; u < 12; ++u)
-                if (m[u] && w[u] == w[e]) {
+            for (int u = e + 1; u < 12; ++u)
+                if (m[u] != 0 && w[u] == w[e]) {
                     bits |= m[u];
-                    grp |= 1u << u;
+                    m[u] = 0;
                 }
-            done |= grp;
-            const unsigned long long old = atomicOr(bm + w[e], bits);
-#pragma unroll
-            for (int u = e; u < 12; ++u)
-                if (((grp >> u) & 1) && !(old & m[u])) o |= 1u << u;
+            atomicOr(bm + w[e], bits);
         }
     }
     own[q] = (uint16_t)o;
@@ -223,11 +288,19 @@ __global__ void k_edge_write(const Grid *__restrict__ gt, const tms_leaf *__rest
 
 }  // namespace
 
-hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
-                            unsigned long long *bm, uint16_t *own, hipStream_t s,
-                            const int64_t *nd) {
+hipError_t launch_leaf_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
+                            unsigned long long *lbm, hipStream_t s, const int64_t *nd) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, et, bm, own, nd);
+    hipLaunchKernelGGL(k_leaf_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, et, lbm, nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
+                            const uint64_t *lbm, unsigned long long *bm, uint16_t *own,
+                            hipStream_t s, const int64_t *nd) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_mark, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, et, lbm, bm, own,
+                       nd);
     return hipGetLastError();
 }
 

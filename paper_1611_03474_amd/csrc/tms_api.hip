@@ -104,7 +104,7 @@ void tms_graph_state::release() {
     cells_id = 0;
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &chunks2, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
-                        &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &eown, &verts, &etab, &sz, &ctr,
+                        &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &eown, &lbmap, &verts, &etab, &sz, &ctr,
                         &stmp, &seg, &ptab};
     for (auto *x : b) x->release();
 }
@@ -871,6 +871,30 @@ void cells_buffers(const tms_cells *c, const void *p[8]) {
     p[7] = c->gtab.p;
 }
 
+// Leaf lattices of every conformation (one bit per cube of each level, 4x4x4
+// blocks per word) into et[b].leaf; returns the words of their bitmap.
+int64_t leaf_lattices(std::vector<EdgeLat> &et, const tms_cells *cells) {
+    int64_t words = 0;
+    for (size_t b = 0; b < et.size(); ++b) {
+        const Grid &gb = cells->gh[b];
+        for (int lev = 0; lev < TMS_MAX_LEVELS; ++lev) {
+            Lat &l = et[b].leaf[lev];
+            if (lev > cells->g.K) {
+                l = Lat{{0, 0, 0}, words};
+                continue;
+            }
+            int64_t nw = 1;
+            for (int k = 0; k < 3; ++k) {
+                l.n[k] = (((int64_t)gb.nr[k] << lev) + 3) / 4;
+                nw *= l.n[k];
+            }
+            l.base = words;
+            words += nw;
+        }
+    }
+    return words;
+}
+
 // Capacities and private buffers of a capture of `cells`, from the eager
 // pass kept in ctx (its counts times `margin`).
 int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
@@ -925,8 +949,10 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     }
     const int64_t cwords = cells->corner_words;
     G.ewords = ewords;
+    G.lwords = leaf_lattices(et, cells);
     if (64.0 * (double)cwords > kMaxBitmapBits || ebits > kMaxBitmapBits ||
-        cwords >= (int64_t)0x7FFFFFFF || ewords >= (int64_t)0x7FFFFFFF)
+        64.0 * (double)G.lwords > kMaxBitmapBits || cwords >= (int64_t)0x7FFFFFFF ||
+        ewords >= (int64_t)0x7FFFFFFF)
         return fail(ctx, TMS_E_INVALID, "capture needs the dense corner and edge bitmaps");
     // (+ kLenBuckets: the bucket counts of a chunk reordering round the
     // chunk count up to whole workgroups)
@@ -957,6 +983,7 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.ebmap.ensure(sizeof(uint64_t) * (size_t)ewords));
     HIPCK(G.ebcnt.ensure(4 * (size_t)ewords));
     HIPCK(G.eown.ensure(sizeof(uint16_t) * (size_t)G.lcap));
+    HIPCK(G.lbmap.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(G.lwords, 1)));
     HIPCK(G.eboff.ensure(4 * (size_t)ewords));
     HIPCK(G.verts.ensure(sizeof(tms_vertex) * (size_t)G.vcap));
     HIPCK(G.etab.ensure(sizeof(EdgeLat) * (size_t)G.nconf + sizeof(int64_t) * (size_t)G.nconf));
@@ -1143,8 +1170,10 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     const int64_t *fw = reinterpret_cast<const int64_t *>(et + nconf);
     const int64_t ew = G.ewords;
     HIPCK(launch_fill_u64(G.ebmap.as<uint64_t>(), 0ull, ew, s));
-    HIPCK(launch_edge_mark(lv, G.lcap, et, G.ebmap.as<unsigned long long>(),
-                           G.eown.as<uint16_t>(), s, Ld));
+    HIPCK(launch_fill_u64(G.lbmap.as<uint64_t>(), 0ull, G.lwords, s));
+    HIPCK(launch_leaf_mark(lv, G.lcap, et, G.lbmap.as<unsigned long long>(), s, Ld));
+    HIPCK(launch_edge_mark(lv, G.lcap, et, G.lbmap.as<uint64_t>(),
+                           G.ebmap.as<unsigned long long>(), G.eown.as<uint16_t>(), s, Ld));
     HIPCK(launch_popc(G.ebmap.as<uint64_t>(), ew, G.ebcnt.as<int32_t>(), s));
     HIPCK(exclusive_scan(G.ebcnt.as<int32_t>(), G.eboff.as<int32_t>(), ew, nv, tmp, s));
     HIPCK(launch_edge_write(gt, lv, G.cphi.as<double>(), G.lcap, et, G.ebmap.as<uint64_t>(),
@@ -1555,11 +1584,13 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
             }
         el.words = words - first_word[(size_t)b];
     }
+    const int64_t lwords = leaf_lattices(etab, cells);
     ctx->n_verts = 0;
     ctx->edge_cells = cells->id;
     ctx->edge_dense = n == 0;
     ctx->vert_off.assign((size_t)nconf + 1, 0);
-    if (n > 0 && ebits <= kMaxBitmapBits && words < (int64_t)0x7FFFFFFF) {
+    if (n > 0 && ebits <= kMaxBitmapBits && 64.0 * (double)lwords <= kMaxBitmapBits &&
+        words < (int64_t)0x7FFFFFFF) {
         // edge bitmaps in buffers of their own: the corner bitmap stays
         // valid for the adjoint
         const int64_t nwords = words;
@@ -1573,12 +1604,16 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         HIPCK(ctx->ebmap.ensure(sizeof(uint64_t) * (size_t)nwords));
         HIPCK(ctx->ebcnt.ensure(sizeof(int32_t) * (size_t)nwords));
         HIPCK(ctx->eown.ensure(sizeof(uint16_t) * (size_t)n));
+        HIPCK(ctx->lbmap.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(lwords, 1)));
         HIPCK(ctx->eboff.ensure(sizeof(int32_t) * (size_t)nwords));
         {
             TimedScope ts_(ctx, TMS_T_EXTRACT);
             HIPCK(launch_fill_u64(ctx->ebmap.as<uint64_t>(), 0ull, nwords, s));
-            HIPCK(launch_edge_mark(lv, n, et, ctx->ebmap.as<unsigned long long>(),
-                                   ctx->eown.as<uint16_t>(), s));
+            HIPCK(launch_fill_u64(ctx->lbmap.as<uint64_t>(), 0ull, lwords, s));
+            HIPCK(launch_leaf_mark(lv, n, et, ctx->lbmap.as<unsigned long long>(), s));
+            HIPCK(launch_edge_mark(lv, n, et, ctx->lbmap.as<uint64_t>(),
+                                   ctx->ebmap.as<unsigned long long>(), ctx->eown.as<uint16_t>(),
+                                   s));
             HIPCK(launch_popc(ctx->ebmap.as<uint64_t>(), nwords, ctx->ebcnt.as<int32_t>(), s));
         }
         int32_t rc = scan_total(ctx, ctx->ebcnt.as<int32_t>(), ctx->eboff.as<int32_t>(), nwords, &nv);

@@ -24,6 +24,9 @@ struct Lat {
 struct EdgeLat {
     Lat l[TMS_MAX_LEVELS][3];
     int64_t words;
+    // leaf lattices: one bit per cube of each level, 4x4x4 blocks per word
+    // (n = blocks per axis), bases in a bitmap of their own
+    Lat leaf[TMS_MAX_LEVELS];
 };
 
 // ---------------------------------------------------------------------------
@@ -146,12 +149,12 @@ struct tms_graph_state {
     const void *cells_buf[8] = {};  // their device buffers (a rebuild must keep them)
     std::vector<tms::Grid> gh;      // and their geometry
     int nlev = 0, nconf = 1;
-    int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0;
+    int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0, lwords = 0;
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
     int64_t ccap[TMS_MAX_LEVELS] = {};  // chunks per slice launch of a tiled level
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, chunks2,
         leaves, lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt,
-        eboff, eown, verts, etab, sz, ctr, stmp, seg, ptab;
+        eboff, eown, lbmap, verts, etab, sz, ctr, stmp, seg, ptab;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
     void release();
@@ -175,7 +178,7 @@ struct tms_ctx {
     uint64_t corner_cells = 0, edge_cells = 0;  // tms_cells::id they belong to
     bool corner_dense = false, edge_dense = false;
     tms::EdgeLat edge_lat{};
-    tms::DevBuf ebmap, ebcnt, eboff, eown, wbar, uconf, etab, lsort, ctab;
+    tms::DevBuf ebmap, ebcnt, eboff, eown, lbmap, wbar, uconf, etab, lsort, ctab;
     // batch bookkeeping of the last partition / extraction: per-conformation
     // leaf and vertex offsets ([nconf + 1] each)
     std::vector<int64_t> leaf_off, vert_off;
@@ -415,11 +418,15 @@ hipError_t launch_corner_gather_bm(const tms_leaf *lin, int64_t n, int K, const 
 
 // k_extract.hip
 // et: device table of edge lattices, one per conformation
-// own: [n] edges whose bit the leaf set (bit e for edge e), written by the
+// lbm: the leaf-lattice bitmap (zeroed), one bit per surface leaf at its
+// level's cube, so that each crossing edge has one owner among the leaves that
+// share it; own: [n] edges the leaf owns (bit e for edge e), written by the
 // mark and read by the write
+hipError_t launch_leaf_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
+                            unsigned long long *lbm, hipStream_t s, const int64_t *nd = nullptr);
 hipError_t launch_edge_mark(const tms_leaf *leaves, int64_t n, const EdgeLat *et,
-                            unsigned long long *bm, uint16_t *own, hipStream_t s,
-                            const int64_t *nd = nullptr);
+                            const uint64_t *lbm, unsigned long long *bm, uint16_t *own,
+                            hipStream_t s, const int64_t *nd = nullptr);
 hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
                              const EdgeLat *et, const uint64_t *bm, const int32_t *woff,
                              const uint16_t *own, tms_vertex *out, hipStream_t s,
