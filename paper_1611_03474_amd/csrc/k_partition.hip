@@ -288,6 +288,10 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t v, int64_t n) {
 
 constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
 constexpr int64_t kStrideGrid = 2048;  // workgroups of a capacity-sized tiled launch
+// workgroups (one wavefront each) of a grouped launch whose chunk count is on
+// the device: many more than are resident, so the hardware balances them,
+// each striding over the chunk groups
+constexpr int64_t kGroupedGrid = 65536;
                                        // (about the resident count: 256 CUs x 8)
 
 template <bool FAST, int QH, int CH, bool DYN>
@@ -949,6 +953,28 @@ __global__ __launch_bounds__(kLenBuckets) void k_chunk_len_scatter(
     if (i < nn) out[atomicAdd(&h[bkt[i]], 1)] = chunks[i];
 }
 
+// Chunks starting in each bin of kChunkBin queue entries of a level (the
+// chunks of one slice, ascending starts relative to the slice at queue
+// position off): one thread per bin the slice touches, two binary searches.
+__global__ void k_chunk_bins(const int2 *__restrict__ chunks, int64_t n, int64_t off, int64_t len,
+                             int32_t *__restrict__ hist) {
+    const int64_t b0 = off / kChunkBin;
+    const int64_t j = b0 + blockIdx.x * (int64_t)kBS + threadIdx.x;
+    if (j * kChunkBin >= off + len) return;
+    // chunk starts in [lo, hi) relative to the slice
+    const int64_t lo = max((int64_t)0, j * kChunkBin - off), hi = min(len, (j + 1) * kChunkBin - off);
+    auto lower = [&](int64_t v) {
+        int64_t a = 0, b = n;
+        while (a < b) {
+            const int64_t m = (a + b) >> 1;
+            if ((int64_t)chunks[m].x < v) a = m + 1;
+            else b = m;
+        }
+        return a;
+    };
+    hist[j] += (int32_t)(lower(hi) - lower(lo));
+}
+
 __global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n,
                               const int32_t *__restrict__ nd, int32_t *__restrict__ f) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
@@ -1164,7 +1190,7 @@ hipError_t estimate_groups_t(const Grid *g, int level, const int4 *q, const int2
     GLRule<double> R = gl_rule<double>(QH);
     const int gl = level == 1 ? 8 : 32;
     const int64_t waves = (nchunks + 64 / gl - 1) / (64 / gl);
-    const unsigned grid = (unsigned)(o.ncount ? std::min<int64_t>(waves, kStrideGrid) : waves);
+    const unsigned grid = (unsigned)(o.ncount ? std::min<int64_t>(waves, kGroupedGrid) : waves);
     if (level == 1)
         hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8, 8, 2>), dim3(grid), dim3(64), 0, s, g,
                            level, R, q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
@@ -1422,6 +1448,14 @@ hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n
     if (cmax < 1 || cmax > 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_run_chunk_emit, dim3(nblk(nruns)), dim3(kBS), 0, s, starts, nruns, n, nrd,
                        nd, cmax, coff, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_bins(const int2 *chunks, int64_t n, int64_t off, int64_t len,
+                             int32_t *hist, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
+    const int64_t nb = (off + len - 1) / kChunkBin - off / kChunkBin + 1;
+    hipLaunchKernelGGL(k_chunk_bins, dim3(nblk(nb)), dim3(kBS), 0, s, chunks, n, off, len, hist);
     return hipGetLastError();
 }
 

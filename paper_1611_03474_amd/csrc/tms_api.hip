@@ -248,9 +248,9 @@ int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int
 // exact, that is at most eps (1 + 1/b) <= 4.4e-6 for b = 0.035.
 constexpr double kCornerBand = 0.035;
 
-// Queue slices per level (estimate + bound); their hard-list lengths live in
-// counter slots [kSliceCtr, kSliceCtr + kMaxSlices), the guard pass's after.
-constexpr int64_t kMaxSlices = 256;
+// Queue slices per level (estimate + bound, at most kMaxSlices); their
+// hard-list lengths live in counter slots [kSliceCtr, kSliceCtr + kMaxSlices),
+// the guard pass's after.
 constexpr int64_t kSliceCtr = 8192;
 
 std::atomic<uint64_t> g_cells_ids{0};
@@ -921,9 +921,23 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
         // one workgroup per chunk for the tiled levels: a slice holds at most
         // as many chunks as cubes, and at most the level's (from the eager
         // pass, which counted them over its own slicing) plus one per cut
-        G.ccap[l] = ctx->last_chunks[l] < 0
-                        ? G.slice[l]
-                        : std::min(G.slice[l], grow(ctx->last_chunks[l]) + G.nslices[l]);
+        for (int64_t k = 0; k < G.nslices[l]; ++k) {
+            int64_t c = G.slice[l];
+            const std::vector<int32_t> &bins = ctx->last_chunk_bins[l];
+            if (ctx->last_chunks[l] >= 0 && !bins.empty()) {
+                // chunks starting in the bins this slice overlaps, one more
+                // for a run cut at its start (the replay refines the same
+                // queue; the margin covers rebuilt cells)
+                const int64_t a = k * G.slice[l], b = (k + 1) * G.slice[l];
+                int64_t cnt = 1;
+                for (int64_t j = a / kChunkBin; j < (int64_t)bins.size() && j * kChunkBin < b; ++j)
+                    cnt += bins[(size_t)j];
+                c = std::min(c, grow(cnt));
+            } else if (ctx->last_chunks[l] >= 0) {
+                c = std::min(c, grow(ctx->last_chunks[l]) + G.nslices[l]);
+            }
+            G.ccap[l][k] = c;
+        }
     }
     // edge lattices, as the eager extraction lays them out
     std::vector<EdgeLat> et((size_t)G.nconf);
@@ -1088,7 +1102,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
             // the planned capacity (the grouped kernels stride over theirs)
             const bool percap = tiled && !half && lev >= 2;
             HIPCK(launch_estimate_decide(g, gt, lev, lprec, q + off, cap, nullptr, chunks,
-                                         percap ? std::min(cap, G.ccap[lev]) : cap, rs, ra,
+                                         percap ? std::min(cap, G.ccap[lev][k]) : cap, rs, ra,
                                          ax, ay, az, aw, dec + off, G.abuf.as<double>(),
                                          G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
                                          reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
@@ -1352,6 +1366,11 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 }
                 pt = ProjTab{ctx->ptab.as<double>(), na, ns};
             }
+            const int64_t nbins = (nq + kChunkBin - 1) / kChunkBin;
+            if (tiled && !half) {
+                HIPCK(ctx->chist.ensure(sizeof(int32_t) * (size_t)nbins));
+                HIPCK(launch_fill_u32(ctx->chist.as<uint32_t>(), 0u, nbins, s));
+            }
             for (int64_t k = 0; k < nslices; ++k) {
                 const int64_t off = k * S, ns = std::min(S, nq - off);
                 unsigned *hard = reinterpret_cast<unsigned *>(ctr + kSliceCtr + k);
@@ -1362,6 +1381,11 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                                       half ? 32 : 64);
                     if (rc) return rc;
                     level_chunks += nchunks;
+                    if (!half) {  // where the chunks start (sizes a captured pass's launches)
+                        TimedScope ts_(ctx, TMS_T_COMPACT);
+                        HIPCK(launch_chunk_bins(chunks, nchunks, off, ns,
+                                                ctx->chist.as<int32_t>(), s));
+                    }
                     if (lev == 1 || half) {
                         rc = chunks_by_length(ctx, cells, lev, q + off, &chunks, nchunks);
                         if (rc) return rc;
@@ -1393,6 +1417,11 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 }
             }
             chunks_lvl[lev] = tiled && !half ? level_chunks : -1;
+            ctx->last_chunk_bins[lev].clear();
+            if (tiled && !half) {
+                ctx->last_chunk_bins[lev].resize((size_t)nbins);
+                HIPCK(d2h(ctx->last_chunk_bins[lev].data(), ctx->chist.p, (size_t)nbins, s));
+            }
             if (lprec == TMS_PREC_FP32_GUARD) {
                 {
                     TimedScope ts_(ctx, TMS_T_COMPACT);

@@ -139,6 +139,9 @@ struct tms_cells {
     void release();
 };
 
+// queue slices per level at most (estimate + bound launches)
+constexpr int64_t kMaxSlices = 256;
+
 // A pass recorded once into a HIP graph with every size kept on the device
 // (capacity-sized launches), replayed without host round trips.
 struct tms_graph_state {
@@ -151,7 +154,7 @@ struct tms_graph_state {
     int nlev = 0, nconf = 1;
     int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0, lwords = 0;
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
-    int64_t ccap[TMS_MAX_LEVELS] = {};  // chunks per slice launch of a tiled level
+    int64_t ccap[TMS_MAX_LEVELS][kMaxSlices] = {};  // chunks per slice launch of a tiled level
     tms::DevBuf q[2], dec, abuf, ebuf, hidx, flags, scan_a, scan_b, idx, runs, chunks, chunks2,
         leaves, lsort, cphi, bmap, bmcnt, bmoff, uniq, uphi, uconf, uguard, ebmap, ebcnt,
         eboff, eown, lbmap, verts, etab, sz, ctr, stmp, seg, ptab;
@@ -186,6 +189,9 @@ struct tms_ctx {
     tms_stats last_stats{};
     uint64_t last_stats_cells = 0;
     int64_t last_chunks[TMS_MAX_LEVELS] = {};  // whole-wave chunks per level of that pass (-1: none)
+    // and their starts per kChunkBin queue positions (empty: not chunked so)
+    std::vector<int32_t> last_chunk_bins[TMS_MAX_LEVELS];
+    tms::DevBuf chist;
     tms_graph_state graph;
     // workspace (grow-only)
     tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
@@ -333,6 +339,12 @@ hipError_t launch_run_chunk_emit(const int32_t *starts, int64_t nruns, int64_t n
                                  const int32_t *coff, int2 *chunks, hipStream_t s,
                                  const int32_t *nrd = nullptr, const int32_t *nd = nullptr,
                                  int cmax = 64);
+// chunk starts of a slice (n chunks, ascending starts relative to the slice
+// at level position off, len entries) added to hist[bin] for the bins of
+// kChunkBin level positions the slice touches (hist zeroed per level)
+constexpr int64_t kChunkBin = 65536;
+hipError_t launch_chunk_bins(const int2 *chunks, int64_t n, int64_t off, int64_t len,
+                             int32_t *hist, hipStream_t s);
 // the n chunks (ncount: their device count, or null) reordered into out by
 // the length of their root's atom list, longest first; bkt: [n] scratch,
 // bcnt and boff: [chunks_by_length_scratch(n)] scratch each, tmp: scan
