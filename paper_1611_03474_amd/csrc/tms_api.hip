@@ -816,7 +816,10 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         int32_t rc = scan_total(ctx, rc_cnt, cells->root_start.as<int32_t>(), nr + 1, &tot);
         if (rc) return bail(rc);
         cells->n_root_entries = tot;
-        CK(cells->root_atoms.ensure(4 * (size_t)std::max<int64_t>(tot, 1)));
+        // a quarter of room to spare: a rebuild from moved atoms (whose
+        // lists may grow a little) keeps the buffer, and with it a capture
+        if (4 * (size_t)std::max<int64_t>(tot, 1) > cells->root_atoms.cap)
+            CK(cells->root_atoms.ensure(5 * (size_t)std::max<int64_t>(tot, 1) + 4096));
         CK(launch_root_fill(gt, nconf, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
                             cells->ay.as<double>(), cells->az.as<double>(), nr,
                             cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(), s));
@@ -860,7 +863,7 @@ constexpr int kCtSurf = 6144;
 constexpr int kCtPart = 8192;   // [5 * 1024] reduction partials
 constexpr int kCtSlots = kCtPart + 5 * 1024;
 
-void cells_buffers(const tms_cells *c, const void *p[8]) {
+void cells_buffers(const tms_cells *c, const void *p[kCellsBufs]) {
     p[0] = c->ax.p;
     p[1] = c->ay.p;
     p[2] = c->az.p;
@@ -869,6 +872,7 @@ void cells_buffers(const tms_cells *c, const void *p[8]) {
     p[5] = c->root_start.p;
     p[6] = c->root_atoms.p;
     p[7] = c->gtab.p;
+    p[8] = c->axw.p;
 }
 
 // Leaf lattices of every conformation (one bit per cube of each level, 4x4x4
@@ -1891,11 +1895,11 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
         return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
     if (cells->id != G.cells_id) {
         // a rebuild keeps the graph valid when geometry and buffers are unchanged
-        const void *p[8];
+        const void *p[kCellsBufs];
         cells_buffers(cells, p);
         bool same = cells->gh.size() == G.gh.size() &&
                     memcmp(cells->gh.data(), G.gh.data(), sizeof(Grid) * G.gh.size()) == 0;
-        for (int k = 0; k < 8 && same; ++k) same = p[k] == G.cells_buf[k];
+        for (int k = 0; k < kCellsBufs && same; ++k) same = p[k] == G.cells_buf[k];
         if (!same)
             return fail(ctx, TMS_E_INVALID,
                         "cells changed geometry or buffers since the capture; capture again");

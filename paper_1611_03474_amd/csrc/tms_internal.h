@@ -141,6 +141,8 @@ struct tms_cells {
 
 // queue slices per level at most (estimate + bound launches)
 constexpr int64_t kMaxSlices = 256;
+// device buffers of a cells object that a captured pass reads
+constexpr int kCellsBufs = 9;
 
 // A pass recorded once into a HIP graph with every size kept on the device
 // (capacity-sized launches), replayed without host round trips.
@@ -149,7 +151,7 @@ struct tms_graph_state {
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
     uint64_t cells_id = 0;          // cells build the graph was recorded for
-    const void *cells_buf[8] = {};  // their device buffers (a rebuild must keep them)
+    const void *cells_buf[kCellsBufs] = {};  // their device buffers (a rebuild must keep them)
     std::vector<tms::Grid> gh;      // and their geometry
     int nlev = 0, nconf = 1;
     int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0, lwords = 0;

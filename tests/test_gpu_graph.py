@@ -83,3 +83,50 @@ def test_graph_rejects_without_eager_pass(ctx):
     with pytest.raises(tms.TmsError):
         ctx.graph_capture(cells)
     ctx.free_cells(cells)
+
+
+def test_graph_replay_on_rebuilt_cells(ctx):
+    # the captured pass replayed on cells rebuilt in place from slightly moved
+    # atoms (same geometry): the counts shift against the capture's (queues,
+    # chunks per slice, leaves, corners, vertices), so the replay either
+    # matches an eager pass on the new cells bit for bit or reports the
+    # exceeded capacity -- never a wrong result
+    import torch
+    confs = [synth.globule(n, 4000 + k) for k, n in enumerate([400, 250, 600])]
+    p = tms.make_params(D=0.9, tau=1e-3, precision=tms.PREC_FP32_GUARD)
+    base = ctx.get_tuning().as_dict()
+    ctx.set_tuning(slice_cubes=4096)
+    try:
+        cells = ctx.build_cells_batch(confs, p)
+        L0, _, V0, _ = _eager(ctx, cells)
+        ctx.graph_capture(cells, margin=1.25)
+        nlc, nvc = 2 * L0.shape[0] + 1024, 2 * V0.shape[0] + 1024
+        replayed = 0
+        for seed in range(4):
+            rng = np.random.default_rng(50 + seed)
+            moved = []
+            for c in confs:
+                m = np.array(c, dtype=np.float64)
+                m[:, :3] += rng.normal(0.0, 0.02, size=(len(m), 3))
+                moved.append(m)
+            ctx.build_cells_batch(moved, p, cells)
+            lb = torch.zeros((nlc, 20), dtype=torch.uint8, device="cuda:0")
+            cb = torch.zeros((nlc, 8), dtype=torch.float64, device="cuda:0")
+            vb = torch.zeros((nvc, 40), dtype=torch.uint8, device="cuda:0")
+            try:
+                nl, nv, st = ctx.graph_launch(cells, lb, cb, vb)
+            except tms.TmsError as e:
+                assert e.code in (tms.TMS_E_CAPACITY, tms.TMS_E_INVALID), e
+                print("seed %d: replay refused (%s)" % (seed, e))
+                continue
+            L1, C1, V1, st1 = _eager(ctx, cells)
+            assert nl == L1.shape[0] and nv == V1.shape[0], seed
+            assert torch.equal(lb[:nl], L1) and torch.equal(cb[:nl], C1), seed
+            assert torch.equal(vb[:nv], V1), seed
+            assert st["n_est"] == st1["n_est"], seed
+            replayed += 1
+        print("replays on rebuilt cells that matched the eager pass: %d of 4" % replayed)
+        assert replayed >= 1
+        ctx.free_cells(cells)
+    finally:
+        ctx.set_tuning(**base)
