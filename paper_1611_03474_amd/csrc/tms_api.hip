@@ -39,6 +39,27 @@ void DevBuf::release() {
     cap = 0;
 }
 
+hipError_t PinBuf::ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    const size_t nb = std::max<size_t>(bytes, 65536);
+    hipError_t e = hipHostMalloc(&p, nb, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        cap = 0;
+        (void)hipGetLastError();
+        return e;
+    }
+    cap = nb;
+    return hipSuccess;
+}
+
+void PinBuf::release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
 hipError_t launch_edge_count(const tms_leaf *leaves, int64_t n, unsigned long long *count,
                              hipStream_t s);
 
@@ -220,11 +241,23 @@ hipError_t grow_keep(DevBuf &b, size_t need, size_t used, hipStream_t s) {
     return hipSuccess;
 }
 
+// Device-to-host read on the context's stream, synchronous; through the
+// context's pinned buffer (a DMA straight into page-locked memory returns
+// sooner than one into pageable memory), else directly.
 template <typename T>
-hipError_t d2h(T *dst, const void *src, size_t count, hipStream_t s) {
-    hipError_t e = hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(s);
+hipError_t d2h(tms_ctx *ctx, T *dst, const void *src, size_t count) {
+    const size_t bytes = sizeof(T) * count;
+    if (bytes == 0) return hipSuccess;
+    hipStream_t s = ctx->stream;
+    if (ctx->pin.ensure(bytes) != hipSuccess) {
+        hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+    hipError_t e = hipMemcpyAsync(ctx->pin.p, src, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) memcpy(dst, ctx->pin.p, bytes);
+    return e;
 }
 
 // scan `n` int32 values of `in` into `out` and return the total on the host
@@ -236,7 +269,7 @@ int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int
         HIPCK(exclusive_scan(in, out, n, tot, ctx->scan_c.p, ctx->stream));
     }
     int32_t h = 0;
-    HIPCK(d2h(&h, tot, 1, ctx->stream));
+    HIPCK(d2h(ctx, &h, tot, 1));
     *total = h;
     return TMS_OK;
 }
@@ -477,7 +510,7 @@ int32_t regroup_by_conf(tms_ctx *ctx, const tms_cells *cells, int64_t L) {
         HIPCK(launch_leaf_seg_heads(ctx->leaves.as<tms_leaf>(), L, nconf, src, s));
     }
     std::vector<int64_t> hs((size_t)nseg), hd((size_t)nseg, 0), cnt((size_t)nseg, 0);
-    HIPCK(d2h(hs.data(), src, (size_t)nseg, s));
+    HIPCK(d2h(ctx, hs.data(), src, (size_t)nseg));
     // segments ascend in the source order; a segment ends where the next
     // present one starts
     int64_t prev = -1;
@@ -553,7 +586,7 @@ int32_t tms_destroy(tms_ctx *ctx) {
                            &ctx->qmeta, &ctx->abuf, &ctx->ebuf, &ctx->dec, &ctx->scan_a,
                            &ctx->scan_b, &ctx->scan_c, &ctx->flags, &ctx->idx, &ctx->hkeys,
                            &ctx->hown, &ctx->slot, &ctx->uniq, &ctx->uphi, &ctx->uguard, &ctx->lc,
-                           &ctx->ctmp, &ctx->counters, &ctx->hostpin, &ctx->hidx, &ctx->chunks,
+                           &ctx->ctmp, &ctx->counters, &ctx->hidx, &ctx->chunks,
                            &ctx->chunks2, &ctx->runs};
     for (auto *b : bufs) b->release();
     ctx->graph.release();
@@ -686,7 +719,7 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
             e = launch_atom_stats(xyzr, cells->aoff.as<int64_t>(), nconf, max_atoms,
                                   ctx->ctmp.as<double>(),
                                   ctx->ctmp.as<double>() + 9 * (size_t)nconf + 32, s);
-        if (e == hipSuccess) e = d2h(st.data(), ctx->ctmp.p, 9 * (size_t)nconf, s);
+        if (e == hipSuccess) e = d2h(ctx, st.data(), ctx->ctmp.p, 9 * (size_t)nconf);
         if (e != hipSuccess) return bail(hip_fail(ctx, e, "atom stats"));
         for (int b = 0; b < nconf; ++b) {
             if (st[9 * b + 8] > 0)
@@ -1424,7 +1457,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             ctx->last_chunk_bins[lev].clear();
             if (tiled && !half) {
                 ctx->last_chunk_bins[lev].resize((size_t)nbins);
-                HIPCK(d2h(ctx->last_chunk_bins[lev].data(), ctx->chist.p, (size_t)nbins, s));
+                HIPCK(d2h(ctx, ctx->last_chunk_bins[lev].data(), ctx->chist.p, (size_t)nbins));
             }
             if (lprec == TMS_PREC_FP32_GUARD) {
                 {
@@ -1477,12 +1510,12 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             rc = scan_total(ctx, ccnt, ctx->scan_b.as<int32_t>(), nq, &nc);
             if (rc) return rc;
             unsigned long long h[80];
-            HIPCK(d2h(h, ctr, 80, s));
+            HIPCK(d2h(ctx, h, ctr, 80));
             for (int k = 0; k < 64; ++k) st.n_pairs_lvl[lev] += (int64_t)h[k];
             st.n_pairs += st.n_pairs_lvl[lev];
             {
                 std::vector<unsigned long long> hs(2 * (size_t)kMaxSlices);
-                HIPCK(d2h(hs.data(), ctr + kSliceCtr, 2 * (size_t)kMaxSlices, s));
+                HIPCK(d2h(ctx, hs.data(), ctr + kSliceCtr, 2 * (size_t)kMaxSlices));
                 for (unsigned long long v : hs) st.n_bound += (int64_t)(v & 0xFFFFFFFFull);
             }
             st.n_disc[lev] = (int64_t)h[72 + DEC_DISCARD];
@@ -1525,7 +1558,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr + 80, ctr + 256, s));
     }
     unsigned long long ns = 0;
-    HIPCK(d2h(&ns, ctr + 80, 1, s));
+    HIPCK(d2h(ctx, &ns, ctr + 80, 1));
     st.n_leaves = L;
     st.n_surface = (int64_t)ns;
     ctx->n_leaves = L;
@@ -1660,7 +1693,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         }
         // first vertex of every conformation: the rank of its first word
         HIPCK(launch_gather_i32(ctx->eboff.as<int32_t>(), fw, nconf, vo, s));
-        HIPCK(d2h(ctx->vert_off.data(), vo, (size_t)nconf, s));
+        HIPCK(d2h(ctx, ctx->vert_off.data(), vo, (size_t)nconf));
         ctx->vert_off[(size_t)nconf] = nv;
         ctx->edge_dense = true;
         ctx->edge_lat = etab[0];
@@ -1674,7 +1707,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
             HIPCK(launch_edge_count(lv, n, ctr, s));
         }
         unsigned long long ncr = 0;
-        HIPCK(d2h(&ncr, ctr, 1, s));
+        HIPCK(d2h(ctx, &ncr, ctr, 1));
         const int64_t ncand = 12 * n;
         const int64_t hcap = next_pow2(2 * (int64_t)ncr + 2);
         HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
@@ -1805,7 +1838,7 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
                                    cells->aidx.as<int32_t>(), dxyzr, s));
     }
     unsigned hb = 0;
-    HIPCK(d2h(&hb, bad, 1, s));
+    HIPCK(d2h(ctx, &hb, bad, 1));
     if (hb) return fail(ctx, TMS_E_INVALID, "kept edge points do not end on kept corners");
     return TMS_OK;
 }
@@ -2125,7 +2158,7 @@ int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cu
     hipStream_t s = ctx->stream;
     const Grid &g = cells->g;
     std::vector<int32_t> hc(4 * (size_t)n);
-    HIPCK(d2h(hc.data(), cubes, 4 * (size_t)n, s));
+    HIPCK(d2h(ctx, hc.data(), cubes, 4 * (size_t)n));
     std::vector<int4> hq((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         int lev = hc[4 * i];

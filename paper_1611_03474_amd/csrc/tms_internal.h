@@ -108,6 +108,16 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// Pinned (page-locked) host buffer, grow-only: device-to-host copies of
+// counts land here by DMA and are then copied out on the host.
+struct PinBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes);
+    void release();
+    ~PinBuf() { release(); }
+};
+
 }  // namespace tms
 
 // ---------------------------------------------------------------------------
@@ -213,7 +223,7 @@ struct tms_ctx {
     tms::DevBuf tick;       // [8] chunk slot counters of the tiled estimate
     bool tiled_dyn = false; // eager tiled launches draw chunks from them
     tms::DevBuf counters;
-    tms::DevBuf hostpin;   // unused
+    tms::PinBuf pin;       // pinned staging of device-to-host reads
     // per-phase device timing (HIP events on `stream`)
     bool timing = false;
     int tdepth = 0;
