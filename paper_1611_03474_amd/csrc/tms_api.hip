@@ -260,6 +260,44 @@ hipError_t d2h(tms_ctx *ctx, T *dst, const void *src, size_t count) {
     return e;
 }
 
+// Several device-to-host reads with one synchronization: each piece lands
+// in the pinned buffer at its own 256-byte-aligned offset.
+struct HostRead {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+hipError_t d2h_many(tms_ctx *ctx, const std::vector<HostRead> &rd) {
+    size_t total = 0;
+    for (const HostRead &r : rd) total += (r.bytes + 255) / 256 * 256;
+    if (total == 0) return hipSuccess;
+    hipStream_t s = ctx->stream;
+    if (ctx->pin.ensure(total) != hipSuccess) {
+        for (const HostRead &r : rd) {
+            hipError_t e = hipMemcpyAsync(r.dst, r.src, r.bytes, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipStreamSynchronize(s);
+    }
+    char *base = static_cast<char *>(ctx->pin.p);
+    size_t off = 0;
+    for (const HostRead &r : rd) {
+        if (r.bytes) {
+            hipError_t e = hipMemcpyAsync(base + off, r.src, r.bytes, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+        }
+        off += (r.bytes + 255) / 256 * 256;
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    off = 0;
+    for (const HostRead &r : rd) {
+        if (r.bytes) memcpy(r.dst, base + off, r.bytes);
+        off += (r.bytes + 255) / 256 * 256;
+    }
+    return hipSuccess;
+}
+
 // scan `n` int32 values of `in` into `out` and return the total on the host
 int32_t scan_total(tms_ctx *ctx, const int32_t *in, int32_t *out, int64_t n, int64_t *total) {
     HIPCK(ctx->scan_c.ensure(scan_tmp_bytes(n) + 512));
@@ -1455,10 +1493,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             }
             chunks_lvl[lev] = tiled && !half ? level_chunks : -1;
             ctx->last_chunk_bins[lev].clear();
-            if (tiled && !half) {
-                ctx->last_chunk_bins[lev].resize((size_t)nbins);
-                HIPCK(d2h(ctx, ctx->last_chunk_bins[lev].data(), ctx->chist.p, (size_t)nbins));
-            }
+            if (tiled && !half) ctx->last_chunk_bins[lev].resize((size_t)nbins);
             if (lprec == TMS_PREC_FP32_GUARD) {
                 {
                     TimedScope ts_(ctx, TMS_T_COMPACT);
@@ -1504,20 +1539,27 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 HIPCK(launch_level_histo(ctx->dec.as<uint8_t>(), nq, ctr + 72, ctr + 256, s));
                 HIPCK(launch_level_counts(ctx->dec.as<uint8_t>(), nq, lcnt, ccnt, s));
             }
-            int64_t nl = 0, nc = 0;
-            rc = scan_total(ctx, lcnt, ctx->scan_a.as<int32_t>(), nq, &nl);
-            if (rc) return rc;
-            rc = scan_total(ctx, ccnt, ctx->scan_b.as<int32_t>(), nq, &nc);
-            if (rc) return rc;
+            // both scans' totals, the counters and the chunk bins in one read
+            int32_t *tots = reinterpret_cast<int32_t *>(ctr + 104);
+            HIPCK(ctx->scan_c.ensure(scan_tmp_bytes(nq) + 512));
+            {
+                TimedScope ts_(ctx, TMS_T_COMPACT);
+                HIPCK(exclusive_scan(lcnt, ctx->scan_a.as<int32_t>(), nq, tots, ctx->scan_c.p, s));
+                HIPCK(exclusive_scan(ccnt, ctx->scan_b.as<int32_t>(), nq, tots + 1, ctx->scan_c.p,
+                                     s));
+            }
+            int32_t htot[2] = {0, 0};
             unsigned long long h[80];
-            HIPCK(d2h(ctx, h, ctr, 80));
+            std::vector<unsigned long long> hs(2 * (size_t)kMaxSlices);
+            std::vector<int32_t> &bins = ctx->last_chunk_bins[lev];
+            HIPCK(d2h_many(ctx, {{htot, tots, sizeof htot},
+                                 {h, ctr, sizeof h},
+                                 {hs.data(), ctr + kSliceCtr, sizeof(unsigned long long) * hs.size()},
+                                 {bins.data(), ctx->chist.p, sizeof(int32_t) * bins.size()}}));
+            const int64_t nl = htot[0], nc = htot[1];
             for (int k = 0; k < 64; ++k) st.n_pairs_lvl[lev] += (int64_t)h[k];
             st.n_pairs += st.n_pairs_lvl[lev];
-            {
-                std::vector<unsigned long long> hs(2 * (size_t)kMaxSlices);
-                HIPCK(d2h(ctx, hs.data(), ctr + kSliceCtr, 2 * (size_t)kMaxSlices));
-                for (unsigned long long v : hs) st.n_bound += (int64_t)(v & 0xFFFFFFFFull);
-            }
+            for (unsigned long long v : hs) st.n_bound += (int64_t)(v & 0xFFFFFFFFull);
             st.n_disc[lev] = (int64_t)h[72 + DEC_DISCARD];
             st.n_refine[lev] = (int64_t)h[72 + DEC_REFINE];
             st.n_conv[lev] = (int64_t)h[72 + DEC_CONV];

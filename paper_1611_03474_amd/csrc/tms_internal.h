@@ -210,7 +210,8 @@ struct tms_ctx {
         slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, chunks2, runs, bmap, bmcnt, bmoff;
     // small device counters (u64 slots): [0,64) striped pair counts,
     // [72,77) decision histogram, 80 surface count, 96 adjoint consistency
-    // flag, 100 scan total; [256, 256 + 5*1024) reduction partials;
+    // flag, 100 scan total, 104 and 105 a level's leaf and child totals;
+    // [256, 256 + 5*1024) reduction partials;
     // [8192, 8192 + 512) hard-list lengths of the queue slices
     // tuning (results do not depend on it): queue entries per estimate
     // slice, first level estimated by the tiled kernel, atoms per LDS tile
