@@ -214,15 +214,21 @@ int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, in
  * Leaves are ordered by level, then by refinement order: the roots in raster
  * order (x fastest), and the 8 children of a divided cube in octant order
  * (bit 0 x, bit 1 y, bit 2 z) at the position of their parent.
- * The result is kept in ctx until the next partition call; if cap is too
- * small the call returns TMS_E_CAPACITY with *n_leaves set to the required
- * count and nothing copied -- then call tms_get_leaves with a larger buffer.
+ * When `leaves` holds the result (cap >= the count) the classified leaves,
+ * and the corner values if corner_phi is given, are written straight into
+ * the caller's buffers and ctx keeps no copy of them.  Otherwise (leaves
+ * NULL, or cap too small) the result is kept in ctx until the next partition
+ * call; a too-small cap returns TMS_E_CAPACITY with *n_leaves set to the
+ * required count and nothing copied -- then call tms_get_leaves with a
+ * larger buffer.
  * Errors: TMS_E_CAPACITY, TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
 int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves, int64_t cap,
                                int64_t *n_leaves, double *corner_phi, tms_stats *stats);
 
 /* Copy the leaves (and corner values, if corner_phi is not NULL) of the last
- * partition pass.  Errors: TMS_E_CAPACITY (*n_leaves = required), TMS_E_INVALID. */
+ * partition pass, as kept in ctx; with leaves NULL only the count.
+ * Errors: TMS_E_CAPACITY (*n_leaves = required), TMS_E_INVALID (also when
+ * that pass wrote them into the caller's buffers and kept no copy). */
 int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64_t cap,
                        int64_t *n_leaves);
 
@@ -236,13 +242,19 @@ int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64
  *  corner_phi device [n][8] double, or NULL to evaluate phi at the corners.
  *  out        device [cap] tms_vertex, or NULL to only count.
  *  n_out      host out: number of vertices.
- * The result is kept in ctx until the next extract call (see
+ * When `out` holds the result (cap >= the count; dense edge bitmaps) the
+ * vertices are written straight into it and ctx keeps no copy; otherwise
+ * the result is kept in ctx until the next extract call (see
  * tms_get_vertices).  Errors: TMS_E_CAPACITY (*n_out = required),
  * TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
 int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves,
                                   int64_t n, const double *corner_phi, tms_vertex *out,
                                   int64_t cap, int64_t *n_out);
 
+/* Copy the vertices of the last extraction, as kept in ctx; with out NULL
+ * only the count.  Errors: TMS_E_CAPACITY (*n_out = required),
+ * TMS_E_INVALID (also when that extraction wrote them into the caller's
+ * buffer and kept no copy). */
 int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_out);
 
 /* Unique leaf corners of the last pass (eq. linear1 evaluates phi once per

@@ -1348,6 +1348,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
     unsigned long long *ctr = ctx->counters.as<unsigned long long>();
     int64_t L = 0;
     ctx->leaf_off.assign(1, 0);
+    bool direct = false;      // leaves written into the caller's buffer
+    tms_leaf *lres = nullptr;  // where the classified leaves are
     int64_t chunks_lvl[TMS_MAX_LEVELS];  // whole-wave chunks per level (-1: not chunked so)
     std::fill(chunks_lvl, chunks_lvl + TMS_MAX_LEVELS, (int64_t)-1);
 
@@ -1587,17 +1589,22 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         } else {
             ctx->leaf_off = {0, L};
         }
+        // a caller's buffer that holds the result receives the classified
+        // leaves (and corner values) directly; ctx then keeps no copy
+        direct = leaves_out && cap >= L;
+        lres = direct ? leaves_out : ctx->leaves.as<tms_leaf>();
+        double *cres = direct && corner_phi_out ? corner_phi_out : ctx->corner_phi.as<double>();
         int64_t nu = 0, ng = 0;
-        rc = corner_stage(ctx, cells, ctx->leaves.as<tms_leaf>(), L, ctx->leaves.as<tms_leaf>(),
-                          ctx->corner_phi.as<double>(), &nu, &ng);
+        rc = corner_stage(ctx, cells, ctx->leaves.as<tms_leaf>(), L, lres, cres, &nu, &ng);
         if (rc) return rc;
         st.n_corners = nu;
         st.guard_points = ng;
     }
+    if (!direct) lres = ctx->leaves.as<tms_leaf>();
     HIPCK(hipMemsetAsync(ctr + 80, 0, 8, s));
     {
         TimedScope ts_(ctx, TMS_T_COMPACT);
-        HIPCK(launch_count_surface(ctx->leaves.as<tms_leaf>(), L, ctr + 80, ctr + 256, s));
+        HIPCK(launch_count_surface(lres, L, ctr + 80, ctr + 256, s));
     }
     unsigned long long ns = 0;
     HIPCK(d2h(ctx, &ns, ctr + 80, 1));
@@ -1609,9 +1616,11 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
     for (int l = 0; l < TMS_MAX_LEVELS; ++l) ctx->last_chunks[l] = chunks_lvl[l];
     if (stats) *stats = st;
     *n_leaves = L;
+    ctx->leaves_kept = !direct;
+    ctx->cphi_kept = !(direct && corner_phi_out);
     if (!leaves_out) return TMS_OK;
     if (cap < L) return fail(ctx, TMS_E_CAPACITY, "leaf capacity %lld < %lld", (long long)cap, (long long)L);
-    if (L > 0) {
+    if (L > 0 && !direct) {
         HIPCK(hipMemcpyAsync(leaves_out, ctx->leaves.p, sizeof(tms_leaf) * (size_t)L,
                              hipMemcpyDeviceToDevice, s));
         if (corner_phi_out)
@@ -1628,6 +1637,9 @@ int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64
     if (!n_leaves) return fail(ctx, TMS_E_INVALID, "n_leaves is NULL");
     *n_leaves = ctx->n_leaves;
     if (!leaves) return TMS_OK;
+    if (!ctx->leaves_kept || (corner_phi && !ctx->cphi_kept))
+        return fail(ctx, TMS_E_INVALID,
+                    "the last pass wrote its leaves into the caller's buffers and kept no copy");
     if (cap < ctx->n_leaves) return fail(ctx, TMS_E_CAPACITY, "leaf capacity too small");
     HIPCK(hipSetDevice(ctx->device));
     const int64_t L = ctx->n_leaves;
@@ -1667,6 +1679,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         cphi = ct;
     }
     int64_t nv = 0;
+    bool vdirect = false;  // vertices written into the caller's buffer
     // edge lattices of every conformation, one block of words each
     // (conformation-major, then level, then axis: the edge-key order)
     const int nconf = cells->nconf;
@@ -1726,12 +1739,16 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         }
         int32_t rc = scan_total(ctx, ctx->ebcnt.as<int32_t>(), ctx->eboff.as<int32_t>(), nwords, &nv);
         if (rc) return rc;
-        HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
+        // a caller's buffer that holds the result receives the vertices
+        // directly; ctx then keeps no copy
+        vdirect = out && cap >= nv;
+        if (!vdirect) HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
         {
             TimedScope ts_(ctx, TMS_T_EXTRACT);
             HIPCK(launch_edge_write(cells->gtab.as<Grid>(), lv, cphi, n, et,
                                     ctx->ebmap.as<uint64_t>(), ctx->eboff.as<int32_t>(),
-                                    ctx->eown.as<uint16_t>(), ctx->verts.as<tms_vertex>(), s));
+                                    ctx->eown.as<uint16_t>(),
+                                    vdirect ? out : ctx->verts.as<tms_vertex>(), s));
         }
         // first vertex of every conformation: the rank of its first word
         HIPCK(launch_gather_i32(ctx->eboff.as<int32_t>(), fw, nconf, vo, s));
@@ -1778,6 +1795,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         else ctx->vert_off.clear();
     }
     ctx->n_verts = nv;
+    ctx->verts_kept = !vdirect;
     *n_out = nv;
     if (!out) {
         HIPCK(hipStreamSynchronize(s));
@@ -1787,7 +1805,7 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         HIPCK(hipStreamSynchronize(s));
         return fail(ctx, TMS_E_CAPACITY, "vertex capacity %lld < %lld", (long long)cap, (long long)nv);
     }
-    if (nv > 0)
+    if (nv > 0 && !vdirect)
         HIPCK(hipMemcpyAsync(out, ctx->verts.p, sizeof(tms_vertex) * (size_t)nv,
                              hipMemcpyDeviceToDevice, s));
     HIPCK(hipStreamSynchronize(s));
@@ -1799,6 +1817,9 @@ int32_t tms_get_vertices(tms_ctx *ctx, tms_vertex *out, int64_t cap, int64_t *n_
     if (!n_out) return fail(ctx, TMS_E_INVALID, "n_out is NULL");
     *n_out = ctx->n_verts;
     if (!out) return TMS_OK;
+    if (!ctx->verts_kept)
+        return fail(ctx, TMS_E_INVALID,
+                    "the last extraction wrote its vertices into the caller's buffer and kept no copy");
     if (cap < ctx->n_verts) return fail(ctx, TMS_E_CAPACITY, "vertex capacity too small");
     HIPCK(hipSetDevice(ctx->device));
     if (ctx->n_verts > 0)

@@ -225,6 +225,10 @@ struct tms_ctx {
     bool tiled_dyn = false; // eager tiled launches draw chunks from them
     tms::DevBuf counters;
     tms::PinBuf pin;       // pinned staging of device-to-host reads
+    // whether the last partition's leaves and corner values, and the last
+    // extraction's vertices, are kept in ctx (false: they went straight into
+    // the caller's buffers)
+    bool leaves_kept = true, cphi_kept = true, verts_kept = true;
     // per-phase device timing (HIP events on `stream`)
     bool timing = false;
     int tdepth = 0;

@@ -10,6 +10,7 @@ Cubes that the oracle reports as near ties (a decision margin below 1e-9
 relative, where both FP64 codes may legitimately differ) are excluded with
 their whole subtree; the count is printed.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -308,6 +309,38 @@ def test_capacity_protocol(ctx, g200):
     assert ei.value.code == tms.TMS_E_CAPACITY and ei.value.required == n
     v = ctx.extract(cells, leaves, cphi, cap=3)
     assert len(v) == len(ctx.extract(cells, leaves, cphi))
+    ctx.free_cells(cells)
+
+
+def test_direct_delivery(ctx, g200):
+    # buffers that hold the result receive it directly (bit-identical to the
+    # kept copy); ctx then keeps none, and the get calls say so
+    import torch
+    p = tms.make_params(D=0.9, tau=0.1, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells(g200, p)
+    leaves, cphi, _ = ctx.partition_estimate(cells)        # kept, then copied
+    verts = ctx.extract(cells, leaves, cphi)
+    lb = torch.zeros((len(leaves) + 7, 20), dtype=torch.uint8, device=ctx.device)
+    cb = torch.zeros((len(leaves) + 7, 8), dtype=torch.float64, device=ctx.device)
+    nl, _ = ctx.partition_into(cells, lb, cb)                # written in place
+    assert nl == len(leaves)
+    assert torch.equal(lb[:nl], leaves) and torch.equal(cb[:nl], cphi)
+    n = ctypes.c_int64()
+    with pytest.raises(tms.TmsError) as ei:
+        ctx._check(ctx.lib.tms_get_leaves(ctx.h, tms._VP(lb.data_ptr()), None, lb.shape[0],
+                                          ctypes.byref(n)))
+    assert ei.value.code == tms.TMS_E_INVALID
+    ctx._check(ctx.lib.tms_get_leaves(ctx.h, None, None, 0, ctypes.byref(n)))
+    assert n.value == nl                                     # the count stays
+    vb = torch.zeros((len(verts) + 7, 40), dtype=torch.uint8, device=ctx.device)
+    nv = ctx.extract_into(cells, lb, nl, cb, vb)
+    assert nv == len(verts) and torch.equal(vb[:nv], verts)
+    with pytest.raises(tms.TmsError) as ei:
+        ctx.get_vertices()
+    assert ei.value.code == tms.TMS_E_INVALID
+    # a count-only pass keeps its result again
+    leaves2, cphi2, _ = ctx.partition_estimate(cells)
+    assert torch.equal(leaves2, leaves) and torch.equal(cphi2, cphi)
     ctx.free_cells(cells)
 
 
