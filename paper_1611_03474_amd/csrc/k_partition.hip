@@ -287,7 +287,7 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t v, int64_t n) {
 }
 
 constexpr int kTileIv = 8;  // intervals per axis a chunk may span (levels <= 3)
-constexpr int64_t kStrideGrid = 2048;  // workgroups of a capacity-sized tiled launch
+constexpr int64_t kStrideGrid = 2048;  // workgroups of the persistent tiled grid (tuning option)
 // workgroups (one wavefront each) of a grouped launch whose chunk count is on
 // the device: many more than are resident, so the hardware balances them,
 // each striding over the chunk groups
@@ -321,8 +321,9 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     // blocks of all XCDs interleave over the queue (balanced work).
     //
     //
-    // Slots: DYN = false, one per workgroup (the grid covers the chunks);
-    // DYN = true, a capacity-sized launch (grid a multiple of 8, o.tick zeroed):
+    // Slots: DYN = false, one per workgroup (the grid covers the chunks, or
+    // with a device count their capacity); DYN = true, a fixed persistent
+    // grid (a multiple of 8, o.tick zeroed; a tuning option):
     // the workgroups on XCD x = blockIdx % 8 draw slots 8 t + x from their own
     // counter tick[x] (drawn one chunk ahead), so each XCD walks its slots in
     // order however long single chunks take.  Every workgroup stops at its
