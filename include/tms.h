@@ -344,11 +344,12 @@ typedef struct {
                                 equal slices); the staged tensors take
                                 512 B per entry (>= 4096)                   */
     int32_t tiled_min_level; /* first level estimated one wavefront per chunk
-                                of <= 64 cubes of one root (level 1: eight
-                                roots of <= 8 cubes per wavefront, one
-                                8-lane group each) (1..3; 4: none; level 0
-                                and levels above 3 always use one thread
-                                per cube)                                   */
+                                of <= 64 cubes of one root (levels 0 and 1:
+                                eight roots per wavefront, one 8-lane group
+                                each, a level-0 root being one cube and a
+                                level-1 root at most 8) (0..3; 4: none; the
+                                levels before it and those above 3 use one
+                                thread per cube)                             */
     int32_t tile_atoms;      /* atoms staged per LDS tile of that kernel:
                                 8, 16 or 32                                  */
     int32_t proj_table;      /* 1: the tiled levels first tabulate every

@@ -538,8 +538,9 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
 // ---------------------------------------------------------------------------
 // Tensor estimate with several chunks per wavefront: 64 / GL groups of GL
 // lanes, each taking one chunk of at most GL cubes of one root (level 1,
-// where a root holds at most 2 x 2 x 2 cubes: GL = 8; deeper levels
-// optionally in half-wave chunks, GL = 32).  Every group runs the steps of
+// where a root holds at most 2 x 2 x 2 cubes, and optionally level 0, where
+// it is one cube: GL = 8; deeper levels optionally in half-wave chunks,
+// GL = 32).  Every group runs the steps of
 // the tiled kernel on its own -- filters its root's list to the atoms within
 // R_c of its cubes' box (in list order), stages CH of them, puts each needed
 // projection once into LDS (from the projection table when there is one) and
@@ -1189,10 +1190,13 @@ hipError_t estimate_groups_t(const Grid *g, int level, const int4 *q, const int2
                              const double *aw, const EstOut &o, unsigned long long *pairs,
                              const ProjTab &P, hipStream_t s) {
     GLRule<double> R = gl_rule<double>(QH);
-    const int gl = level == 1 ? 8 : 32;
+    const int gl = level <= 1 ? 8 : 32;
     const int64_t waves = (nchunks + 64 / gl - 1) / (64 / gl);
     const unsigned grid = (unsigned)(o.ncount ? std::min<int64_t>(waves, kGroupedGrid) : waves);
-    if (level == 1)
+    if (level == 0)
+        hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8, 8, 1>), dim3(grid), dim3(64), 0, s, g,
+                           level, R, q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
+    else if (level == 1)
         hipLaunchKernelGGL((k_estimate_groups<FAST, QH, 8, 8, 2>), dim3(grid), dim3(64), 0, s, g,
                            level, R, q, chunks, nchunks, rs, ra, ax, ay, az, aw, o, pairs, P);
     else if (level == 2)
@@ -1231,7 +1235,7 @@ hipError_t tiled_dispatch(int qh, int ch, const Grid *g, int level, const int4 *
                           const int32_t *rs, const int32_t *ra, const double *ax, const double *ay,
                           const double *az, const double *aw, const EstOut &o,
                           unsigned long long *pairs, const ProjTab &P, bool half, hipStream_t s) {
-    if (!subset && (level == 1 || (half && level <= 3)))
+    if (!subset && (level <= 1 || (half && level <= 3)))
         TMS_QH_SWITCH(qh, (estimate_groups_t<FAST, QH>(g, level, q, chunks, nchunks, rs, ra, ax,
                                                        ay, az, aw, o, pairs, P, s)))
     TMS_QH_SWITCH(qh, (estimate_tiled_t<FAST, QH>(ch, g, level, q, subset, chunks, nchunks, rs, ra,

@@ -1166,7 +1166,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                             s, nruns, ns + k, cmax));
                 chunks = G.chunks.as<int2>();
                 ncount = nchunks;
-                if (lev == 1 || half) {
+                if (lev <= 1 || half) {
                     // grouped kernel: chunks by root-list length
                     HIPCK(launch_chunks_by_length(gt, lev, q + off, chunks, cap, ncount, rs, flags,
                                                   sa, idx, tmp, G.chunks2.as<int2>(), s));
@@ -1463,7 +1463,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         HIPCK(launch_chunk_bins(chunks, nchunks, off, ns,
                                                 ctx->chist.as<int32_t>(), s));
                     }
-                    if (lev == 1 || half) {
+                    if (lev <= 1 || half) {
                         rc = chunks_by_length(ctx, cells, lev, q + off, &chunks, nchunks);
                         if (rc) return rc;
                     }
@@ -1476,7 +1476,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 }
                 {  // Step 1 (tensor) and the decisions that need no bound
                     TimedScope ts_(ctx, !tiled ? TMS_T_ESTIMATE
-                                               : (lev == 1 ? TMS_T_GROUPED : TMS_T_TILED));
+                                               : (lev <= 1 ? TMS_T_GROUPED : TMS_T_TILED));
                     HIPCK(launch_estimate_decide(
                         g, gt, lev, lprec, q + off, ns, nullptr, chunks, nchunks,
                         cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
@@ -2065,8 +2065,8 @@ int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
     if (!ctx) return TMS_E_INVALID;
     if (!t) return fail(ctx, TMS_E_INVALID, "tuning is NULL");
     if (t->slice_cubes < 4096) return fail(ctx, TMS_E_INVALID, "slice_cubes < 4096");
-    if (t->tiled_min_level < 1 || t->tiled_min_level > 4)
-        return fail(ctx, TMS_E_INVALID, "tiled_min_level outside 1..4");
+    if (t->tiled_min_level < 0 || t->tiled_min_level > 4)
+        return fail(ctx, TMS_E_INVALID, "tiled_min_level outside 0..4");
     if (t->tile_atoms != 8 && t->tile_atoms != 16 && t->tile_atoms != 32)
         return fail(ctx, TMS_E_INVALID, "tile_atoms must be 8, 16 or 32");
     if (t->proj_table != 0 && t->proj_table != 1)
@@ -2166,7 +2166,7 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
         if ((rc = consider(t))) return rc;
     }
     const tms_tuning bch = b;
-    for (int lv : {1, 2, 3}) {
+    for (int lv : {0, 1, 2, 3}) {
         if (lv == bch.tiled_min_level) continue;
         tms_tuning t = bch;
         t.tiled_min_level = lv;

@@ -165,7 +165,8 @@ def test_tuning_does_not_change_results(ctx):
                                     (1, 16, 1 << 25, 1, 1, 1), (2, 32, 4096, 0, 1, 0),
                                     (2, 8, 1 << 25, 0, 1, 1), (4, 16, 1 << 23, 1, 0, 1),
                                     (2, 8, 1 << 25, 1, 0, 0), (1, 8, 1 << 25, 1, 0, 2),
-                                    (2, 16, 4096, 0, 0, 2)]:
+                                    (2, 16, 4096, 0, 0, 2), (0, 8, 1 << 25, 1, 0, 0),
+                                    (0, 16, 4096, 0, 0, 1)]:
         ctx.set_tuning(slice_cubes=sc, tiled_min_level=tml, tile_atoms=ch, proj_table=pt,
                        tiled_persistent=tp, tiled_half=th)
         leaves, cphi, st = ctx.partition_estimate(cells)
@@ -186,6 +187,8 @@ def test_tuning_does_not_change_results(ctx):
         ctx.set_tuning(tiled_persistent=3)
     with pytest.raises(tms.TmsError):
         ctx.set_tuning(tiled_half=3)
+    with pytest.raises(tms.TmsError):
+        ctx.set_tuning(tiled_min_level=-1)
     best, ms, n = ctx.autotune(cells)
     print("autotune: %s in %.2f ms after %d passes" % (best, ms, n))
     assert n >= 8 and ms > 0

@@ -60,16 +60,18 @@ def test_graph_single(ctx, prec):
     ctx.free_cells(cells)
 
 
-@pytest.mark.parametrize("proj_table,half", [(1, 0), (0, 0), (1, 1), (1, 2)],
-                         ids=["table", "in_place", "half_chunks", "half_level2"])
-def test_graph_batch_sliced(ctx, proj_table, half):
+@pytest.mark.parametrize("proj_table,half,tml", [(1, 0, 1), (0, 0, 1), (1, 1, 1), (1, 2, 1),
+                                                  (1, 0, 0)],
+                         ids=["table", "in_place", "half_chunks", "half_level2", "grouped_level0"])
+def test_graph_batch_sliced(ctx, proj_table, half, tml):
     # a batch, with queue slices far smaller than the levels so the slicing
     # of the captured pass is exercised too
     confs = [synth.globule(n, 3000 + k) for k, n in enumerate([300, 120, 500, 220])]
     cells = ctx.build_cells_batch(confs, tms.make_params(D=0.9, tau=1e-3,
                                                          precision=tms.PREC_FP32_GUARD))
     base = ctx.get_tuning().as_dict()
-    ctx.set_tuning(slice_cubes=4096, proj_table=proj_table, tiled_half=half)
+    ctx.set_tuning(slice_cubes=4096, proj_table=proj_table, tiled_half=half,
+                   tiled_min_level=tml)
     try:
         _check_replays(ctx, cells, len(confs))
     finally:
