@@ -206,9 +206,44 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
             ((int64_t)(c.z >> level) * g.nr[1] + (c.y >> level)) * g.nr[0] + (c.x >> level);
         const double rc2 = g.rc2, rc = sqrt(rc2);
         const int b = root_start[root], e_ = root_start[root + 1];
+        // exact instantiation: the list is walked with its loads ahead of
+        // use (the index two atoms ahead, the coordinates and weight one atom
+        // ahead), so an atom's step waits on its table entries alone; the
+        // FAST one has no registers to spare for that and loads in place
+        int i1 = 0, i2 = 0;
+        double nx_ = 0.0, ny_ = 0.0, nz_ = 0.0, nw_ = 0.0;
+        if (!FAST && b < e_) {
+            i1 = root_atoms[b];
+            i2 = b + 1 < e_ ? root_atoms[b + 1] : 0;
+            nx_ = ax[i1];
+            ny_ = ay[i1];
+            nz_ = az[i1];
+            nw_ = aw[i1];
+        }
         for (int p = b; p < e_; ++p) {
-            const int i = root_atoms[p];
-            const double x = ax[i], y = ay[i], z = az[i];
+            int i;
+            double x, y, z, w;
+            if constexpr (FAST) {
+                i = root_atoms[p];
+                x = ax[i];
+                y = ay[i];
+                z = az[i];
+                w = aw[i];
+            } else {
+                i = i1;
+                x = nx_;
+                y = ny_;
+                z = nz_;
+                w = nw_;
+                i1 = i2;
+                if (p + 2 < e_) i2 = root_atoms[p + 2];
+                if (p + 1 < e_) {
+                    nx_ = ax[i1];
+                    ny_ = ay[i1];
+                    nz_ = az[i1];
+                    nw_ = aw[i1];
+                }
+            }
             const double dx = fmax(fmax(lo[0] - x, x - hi[0]), 0.0);
             const double dy = fmax(fmax(lo[1] - y, y - hi[1]), 0.0);
             const double dz = fmax(fmax(lo[2] - z, z - hi[2]), 0.0);
@@ -221,7 +256,6 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
                 project<FAST, QH>(R, g.D, s, mid[1] - y, py, ey);
             if (!P.t || !tab_proj(P, 2, i, c.z, proj_first(g, 2, z, rc, h, level), pz, ez))
                 project<FAST, QH>(R, g.D, s, mid[2] - z, pz, ez);
-            const double w = aw[i];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const double wx = w * px[j];
