@@ -53,8 +53,8 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
     cells = ctx.build_cells(atoms_dev, p)
     leaves, cphi, st = ctx.partition_estimate(cells)
     verts = ctx.extract(cells, leaves, cphi)
-    cap_l = int(len(leaves) * 1.05) + 1024
-    cap_v = int(len(verts) * 1.05) + 1024
+    # sized for the captured pass as well, which writes into these buffers
+    cap_l, cap_v = ctx.graph_capacity(cells, margin=1.1)
     lb = torch.empty((cap_l, 20), dtype=torch.uint8, device=ctx.device)
     cb = torch.empty((cap_l, 8), dtype=torch.float64, device=ctx.device)
     vb = torch.empty((cap_v, 40), dtype=torch.uint8, device=ctx.device)
@@ -81,8 +81,9 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
     ms = (t1 - t0) * 1e3 / steps
     per_step = {k: {"ms": v["ms"] / steps, "launches": v["launches"] / steps}
                 for k, v in tm.items()}
-    # the same pass replayed from a captured graph (build eager, rest one graph)
-    ctx.graph_capture(cells, margin=1.1)
+    # the same pass replayed from a captured graph (build eager, rest one
+    # graph) that writes its results into lb, cb, vb
+    ctx.graph_capture(cells, margin=1.1, leaves=lb, cphi=cb, verts=vb)
 
     def gstep():
         ctx.build_cells(atoms_dev, p, cells)
@@ -157,11 +158,12 @@ def run_batch(ctx, tms, confs, steps, warmup):
     tuning, tune_ms, tune_n = ctx.autotune(cells)
     leaves, cphi, st = ctx.partition_estimate(cells)
     verts = ctx.extract(cells, leaves, cphi)
-    nl0, nv0 = leaves.shape[0], verts.shape[0]
     del leaves, cphi, verts
-    lb = torch.empty((nl0 + 1024, 20), dtype=torch.uint8, device="cuda:0")
-    cb = torch.empty((nl0 + 1024, 8), dtype=torch.float64, device="cuda:0")
-    vb = torch.empty((nv0 + 1024, 40), dtype=torch.uint8, device="cuda:0")
+    # sized for the captured pass as well, which writes into these buffers
+    cap_l, cap_v = ctx.graph_capacity(cells, margin=1.1)
+    lb = torch.empty((cap_l, 20), dtype=torch.uint8, device="cuda:0")
+    cb = torch.empty((cap_l, 8), dtype=torch.float64, device="cuda:0")
+    vb = torch.empty((cap_v, 40), dtype=torch.uint8, device="cuda:0")
 
     def step():
         ctx.build_cells_batch((a, off), p, cells)
@@ -178,8 +180,8 @@ def run_batch(ctx, tms, confs, steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     sd = s_.as_dict()
-    # one captured graph for the whole batched pass
-    ctx.graph_capture(cells, margin=1.1)
+    # one captured graph for the whole batched pass, writing into lb, cb, vb
+    ctx.graph_capture(cells, margin=1.1, leaves=lb, cphi=cb, verts=vb)
 
     def gstep():
         ctx.build_cells_batch((a, off), p, cells)

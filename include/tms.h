@@ -315,6 +315,28 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
  * again.  Errors: TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
 int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin);
 
+/* Capacities a capture of `cells` with this margin gives its results (the
+ * eager pass's leaf and vertex counts times margin, plus 4096): the sizes
+ * that buffers bound by tms_graph_capture_into must hold.  Same
+ * preconditions and errors as tms_graph_capture; host arithmetic only. */
+int32_t tms_graph_capacity(tms_ctx *ctx, const tms_cells *cells, double margin,
+                           int64_t *leaf_cap, int64_t *vert_cap);
+
+/* tms_graph_capture with the results written by the graph straight into
+ * caller buffers, so that a replay into the same buffers copies nothing:
+ *  leaves, corner_phi  device [leaf_cap] tms_leaf / [leaf_cap][8] double, or
+ *                      NULL (that result stays in a private buffer);
+ *  verts               device [vert_cap] tms_vertex, or NULL.
+ * The buffers are borrowed: they must stay allocated while the capture is in
+ * use (until the next capture or tms_destroy), and every replay overwrites
+ * them.  A replay may still name other buffers; results are then copied
+ * there from the bound ones.  Errors: TMS_E_CAPACITY when a bound buffer is
+ * smaller than tms_graph_capacity's figure (nothing is captured and an
+ * earlier capture stays); otherwise as tms_graph_capture. */
+int32_t tms_graph_capture_into(tms_ctx *ctx, const tms_cells *cells, double margin,
+                               tms_leaf *leaves, double *corner_phi, int64_t leaf_cap,
+                               tms_vertex *verts, int64_t vert_cap);
+
 /* Replay the captured pass on ctx's stream.  `cells` must be the captured
  * cells, or a rebuild of them with the same geometry and buffers.
  *  leaves, corner_phi  device [leaf_cap] tms_leaf / [leaf_cap][8] double, or NULL;

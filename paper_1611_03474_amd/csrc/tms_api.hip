@@ -123,6 +123,9 @@ void tms_graph_state::release() {
     graph = nullptr;
     cap_stream = nullptr;
     cells_id = 0;
+    out_leaves = nullptr;
+    out_cphi = nullptr;
+    out_verts = nullptr;
     tms::DevBuf *b[] = {&q[0], &q[1], &dec, &abuf, &ebuf, &hidx, &flags, &scan_a, &scan_b, &idx,
                         &runs, &chunks, &chunks2, &leaves, &lsort, &cphi, &bmap, &bmcnt, &bmoff, &uniq,
                         &uphi, &uconf, &uguard, &ebmap, &ebcnt, &eboff, &eown, &lbmap, &verts, &etab, &sz, &ctr,
@@ -970,13 +973,18 @@ int64_t leaf_lattices(std::vector<EdgeLat> &et, const tms_cells *cells) {
     return words;
 }
 
+// Captured capacity for a count of the eager pass.
+int64_t graph_grow(int64_t v, double margin) {
+    return (int64_t)std::ceil((double)v * margin) + 4096;
+}
+
 // Capacities and private buffers of a capture of `cells`, from the eager
 // pass kept in ctx (its counts times `margin`).
 int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     tms_graph_state &G = ctx->graph;
     const Grid &g = cells->g;
     const tms_stats &st = ctx->last_stats;
-    auto grow = [&](int64_t v) { return (int64_t)std::ceil((double)v * margin) + 4096; };
+    auto grow = [&](int64_t v) { return graph_grow(v, margin); };
     G.nlev = g.K + 1;
     G.nconf = cells->nconf;
     G.qcap[0] = std::max<int64_t>(cells->nroots, 1);
@@ -1059,9 +1067,11 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.runs.ensure(4 * (size_t)smax));
     HIPCK(G.chunks.ensure(sizeof(int2) * (size_t)smax));
     HIPCK(G.chunks2.ensure(sizeof(int2) * (size_t)smax));
-    HIPCK(G.leaves.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
-    HIPCK(G.lsort.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
-    HIPCK(G.cphi.ensure(sizeof(double) * 8 * (size_t)G.lcap));
+    // a result bound to a caller buffer needs no private one
+    const bool own_emit = !(G.out_leaves && G.nconf == 1);
+    if (own_emit) HIPCK(G.leaves.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
+    if (G.nconf > 1 && !G.out_leaves) HIPCK(G.lsort.ensure(sizeof(tms_leaf) * (size_t)G.lcap));
+    if (!G.out_cphi) HIPCK(G.cphi.ensure(sizeof(double) * 8 * (size_t)G.lcap));
     HIPCK(G.bmap.ensure(sizeof(uint64_t) * (size_t)cwords));
     HIPCK(G.bmcnt.ensure(4 * (size_t)cwords));
     HIPCK(G.bmoff.ensure(4 * (size_t)cwords));
@@ -1074,7 +1084,7 @@ int32_t plan_graph(tms_ctx *ctx, const tms_cells *cells, double margin) {
     HIPCK(G.eown.ensure(sizeof(uint16_t) * (size_t)G.lcap));
     HIPCK(G.lbmap.ensure(sizeof(uint64_t) * (size_t)std::max<int64_t>(G.lwords, 1)));
     HIPCK(G.eboff.ensure(4 * (size_t)ewords));
-    HIPCK(G.verts.ensure(sizeof(tms_vertex) * (size_t)G.vcap));
+    if (!G.out_verts) HIPCK(G.verts.ensure(sizeof(tms_vertex) * (size_t)G.vcap));
     HIPCK(G.etab.ensure(sizeof(EdgeLat) * (size_t)G.nconf + sizeof(int64_t) * (size_t)G.nconf));
     HIPCK(G.sz.ensure(sizeof(int32_t) * kSz64 + sizeof(int64_t) * (size_t)(16 + 2 * (G.nconf + 1))));
     HIPCK(G.ctr.ensure(sizeof(unsigned long long) * kCtSlots));
@@ -1111,6 +1121,12 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     int32_t *nruns = sz + kSzRuns, *nchunks = sz + kSzChunks;
     int32_t *nu = sz + kSzNu, *ngp = sz + kSzNgp, *nv = sz + kSzNv;
     int32_t *ns = sz + kSzSlices, *ngs = sz + kSzGSlices;
+    // result arrays: the caller's where the capture bound them; the level
+    // loop emits a single conformation's leaves in final order, a batch's
+    // are regrouped into the final array afterwards
+    tms_leaf *emit = (nconf == 1 && G.out_leaves) ? G.out_leaves : G.leaves.as<tms_leaf>();
+    double *cphi_out = G.out_cphi ? G.out_cphi : G.cphi.as<double>();
+    tms_vertex *vout = G.out_verts ? G.out_verts : G.verts.as<tms_vertex>();
     int64_t *s64 = reinterpret_cast<int64_t *>(sz + kSz64);
     int64_t *Ld = s64;
     unsigned *ovf = reinterpret_cast<unsigned *>(s64 + 1);
@@ -1208,7 +1224,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         HIPCK(launch_level_counts(dec, QC, flags, idx, s, nq + lev));
         HIPCK(exclusive_scan(flags, sa, QC, nl + lev, tmp, s));
         HIPCK(exclusive_scan(idx, sb, QC, nq + lev + 1, tmp, s));
-        HIPCK(launch_level_emit(q, dec, QC, lev, sa, sb, G.leaves.as<tms_leaf>(), 0,
+        HIPCK(launch_level_emit(q, dec, QC, lev, sa, sb, emit, 0,
                                 G.q[cur ^ 1].as<int4>(), s, nq + lev, Ld, G.lcap, G.qcap[lev + 1],
                                 ovf));
         HIPCK(launch_acc_i64(Ld, nl + lev, s));
@@ -1218,14 +1234,13 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     const int nseg = G.nlev * nconf;
     int64_t *seg_src = G.seg.as<int64_t>(), *seg_dst = seg_src + nseg;
     HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(seg_src), ~0ull, nseg, s));
-    HIPCK(launch_leaf_seg_heads(G.leaves.as<tms_leaf>(), G.lcap, nconf, seg_src, s, Ld));
+    HIPCK(launch_leaf_seg_heads(emit, G.lcap, nconf, seg_src, s, Ld));
     HIPCK(launch_seg_plan(seg_src, G.nlev, nconf, Ld, G.lcap, seg_dst, leaf_off, s));
-    tms_leaf *lv = G.leaves.as<tms_leaf>();
+    tms_leaf *lv = emit;
     G.leaves_in_lsort = false;
     if (nconf > 1) {
-        HIPCK(launch_leaf_seg_move(G.leaves.as<tms_leaf>(), G.lcap, nconf, seg_src, seg_dst,
-                                   G.lsort.as<tms_leaf>(), s, Ld));
-        lv = G.lsort.as<tms_leaf>();
+        lv = G.out_leaves ? G.out_leaves : G.lsort.as<tms_leaf>();
+        HIPCK(launch_leaf_seg_move(emit, G.lcap, nconf, seg_src, seg_dst, lv, s, Ld));
         G.leaves_in_lsort = true;
     }
     // corners: dense bitmap, phi once per corner (exact recomputation near c
@@ -1251,7 +1266,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                        G.uphi.as<double>(), nullptr, s, ngp));
     }
     HIPCK(launch_corner_gather_bm(lv, G.lcap, K, gt, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(),
-                                  G.uphi.as<double>(), g.c, lv, G.cphi.as<double>(), s, Ld, G.ucap,
+                                  G.uphi.as<double>(), g.c, lv, cphi_out, s, Ld, G.ucap,
                                   ovf));
     HIPCK(launch_count_surface(lv, G.lcap, ctr + kCtSurf, ctr + kCtPart, s, Ld));
     // edge points: bitmaps in key order, one rank per edge
@@ -1265,10 +1280,25 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                            G.ebmap.as<unsigned long long>(), G.eown.as<uint16_t>(), s, Ld));
     HIPCK(launch_popc(G.ebmap.as<uint64_t>(), ew, G.ebcnt.as<int32_t>(), s));
     HIPCK(exclusive_scan(G.ebcnt.as<int32_t>(), G.eboff.as<int32_t>(), ew, nv, tmp, s));
-    HIPCK(launch_edge_write(gt, lv, G.cphi.as<double>(), G.lcap, et, G.ebmap.as<uint64_t>(),
+    HIPCK(launch_edge_write(gt, lv, cphi_out, G.lcap, et, G.ebmap.as<uint64_t>(),
                             G.eboff.as<int32_t>(), G.eown.as<uint16_t>(),
-                            G.verts.as<tms_vertex>(), s, Ld, G.vcap, ovf));
+                            vout, s, Ld, G.vcap, ovf));
     HIPCK(launch_gather_i32(G.eboff.as<int32_t>(), fw, nconf, vert_off, s));
+    return TMS_OK;
+}
+
+// the checks shared by a capture and its capacity query
+int32_t capture_args(tms_ctx *ctx, const tms_cells *cells, double margin) {
+    if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    if (cells->p.mode != TMS_MODE_ADAPTIVE)
+        return fail(ctx, TMS_E_INVALID, "capture takes cells built in adaptive mode");
+    if (!(margin >= 1.0 && margin <= 64.0))
+        return fail(ctx, TMS_E_INVALID, "margin must lie in [1, 64]");
+    if (ctx->last_stats_cells != cells->id || ctx->edge_cells != cells->id)
+        return fail(ctx, TMS_E_INVALID,
+                    "capture is sized from an eager tms_partition_estimate and "
+                    "tms_extract_cube_vertices of the same cells; run them first");
     return TMS_OK;
 }
 }  // namespace
@@ -1925,21 +1955,38 @@ int32_t tms_batch_counts(tms_ctx *ctx, const tms_cells *cells, int64_t *leaf_off
     return TMS_OK;
 }
 
-int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin) {
+int32_t tms_graph_capacity(tms_ctx *ctx, const tms_cells *cells, double margin, int64_t *leaf_cap,
+                           int64_t *vert_cap) {
     if (!ctx) return TMS_E_INVALID;
-    if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
-        return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
-    if (cells->p.mode != TMS_MODE_ADAPTIVE)
-        return fail(ctx, TMS_E_INVALID, "capture takes cells built in adaptive mode");
-    if (!(margin >= 1.0 && margin <= 64.0))
-        return fail(ctx, TMS_E_INVALID, "margin must lie in [1, 64]");
-    if (ctx->last_stats_cells != cells->id || ctx->edge_cells != cells->id)
-        return fail(ctx, TMS_E_INVALID,
-                    "capture is sized from an eager tms_partition_estimate and "
-                    "tms_extract_cube_vertices of the same cells; run them first");
+    if (int32_t rc = capture_args(ctx, cells, margin)) return rc;
+    if (leaf_cap) *leaf_cap = graph_grow(ctx->last_stats.n_leaves, margin);
+    if (vert_cap) *vert_cap = graph_grow(ctx->n_verts, margin);
+    return TMS_OK;
+}
+
+int32_t tms_graph_capture(tms_ctx *ctx, const tms_cells *cells, double margin) {
+    return tms_graph_capture_into(ctx, cells, margin, nullptr, nullptr, 0, nullptr, 0);
+}
+
+int32_t tms_graph_capture_into(tms_ctx *ctx, const tms_cells *cells, double margin,
+                               tms_leaf *leaves, double *corner_phi, int64_t leaf_cap,
+                               tms_vertex *verts, int64_t vert_cap) {
+    if (!ctx) return TMS_E_INVALID;
+    if (int32_t rc = capture_args(ctx, cells, margin)) return rc;
+    const int64_t lneed = graph_grow(ctx->last_stats.n_leaves, margin);
+    const int64_t vneed = graph_grow(ctx->n_verts, margin);
+    if ((leaves || corner_phi) && leaf_cap < lneed)
+        return fail(ctx, TMS_E_CAPACITY, "bound leaf buffers hold %lld entries, the capture needs %lld",
+                    (long long)leaf_cap, (long long)lneed);
+    if (verts && vert_cap < vneed)
+        return fail(ctx, TMS_E_CAPACITY, "bound vertex buffer holds %lld entries, the capture needs %lld",
+                    (long long)vert_cap, (long long)vneed);
     HIPCK(hipSetDevice(ctx->device));
     tms_graph_state &G = ctx->graph;
     G.release();
+    G.out_leaves = leaves;
+    G.out_cphi = corner_phi;
+    G.out_verts = verts;
     // the captured pass has private copies of the eager partition's
     // workspace; give that back first (the next eager pass grows it again)
     for (tms::DevBuf *b : {&ctx->q[0], &ctx->q[1], &ctx->abuf, &ctx->ebuf, &ctx->hidx, &ctx->dec,
@@ -2048,14 +2095,19 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
     if ((leaves && leaf_cap < L) || (verts && vert_cap < nv))
         return fail(ctx, TMS_E_CAPACITY, "output capacity too small (%lld leaves, %lld vertices)",
                     (long long)L, (long long)nv);
-    const tms_leaf *lsrc = G.leaves_in_lsort ? G.lsort.as<tms_leaf>() : G.leaves.as<tms_leaf>();
-    if (leaves && L > 0)
+    // results already in a requested buffer (bound at capture) are not copied
+    const tms_leaf *lsrc = G.out_leaves       ? G.out_leaves
+                           : G.leaves_in_lsort ? G.lsort.as<tms_leaf>()
+                                               : G.leaves.as<tms_leaf>();
+    const double *csrc = G.out_cphi ? G.out_cphi : G.cphi.as<double>();
+    const tms_vertex *vsrc = G.out_verts ? G.out_verts : G.verts.as<tms_vertex>();
+    if (leaves && leaves != lsrc && L > 0)
         HIPCK(hipMemcpyAsync(leaves, lsrc, sizeof(tms_leaf) * (size_t)L, hipMemcpyDeviceToDevice, s));
-    if (corner_phi && L > 0)
-        HIPCK(hipMemcpyAsync(corner_phi, G.cphi.p, sizeof(double) * 8 * (size_t)L,
+    if (corner_phi && corner_phi != csrc && L > 0)
+        HIPCK(hipMemcpyAsync(corner_phi, csrc, sizeof(double) * 8 * (size_t)L,
                              hipMemcpyDeviceToDevice, s));
-    if (verts && nv > 0)
-        HIPCK(hipMemcpyAsync(verts, G.verts.p, sizeof(tms_vertex) * (size_t)nv,
+    if (verts && verts != vsrc && nv > 0)
+        HIPCK(hipMemcpyAsync(verts, vsrc, sizeof(tms_vertex) * (size_t)nv,
                              hipMemcpyDeviceToDevice, s));
     HIPCK(hipStreamSynchronize(s));
     return TMS_OK;

@@ -172,6 +172,10 @@ struct tms_graph_state {
         eboff, eown, lbmap, verts, etab, sz, ctr, stmp, seg, ptab;
     bool proj_table = false;        // recorded with projection tables
     bool leaves_in_lsort = false;   // a batch's regrouped leaves end in lsort
+    // caller buffers the pass writes its results into (null: private ones)
+    tms_leaf *out_leaves = nullptr;
+    double *out_cphi = nullptr;
+    tms_vertex *out_verts = nullptr;
     void release();
 };
 

@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH):
                                         C.POINTER(_VP)]
     L.tms_batch_counts.argtypes = [_VP, _VP, C.POINTER(i64), C.POINTER(i64)]
     L.tms_graph_capture.argtypes = [_VP, _VP, C.c_double]
+    L.tms_graph_capacity.argtypes = [_VP, _VP, C.c_double, C.POINTER(i64), C.POINTER(i64)]
+    L.tms_graph_capture_into.argtypes = [_VP, _VP, C.c_double, _VP, _VP, i64, _VP, i64]
     L.tms_graph_launch.argtypes = [_VP, _VP, _VP, _VP, i64, C.POINTER(i64), _VP, i64,
                                    C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(Stats)]
@@ -135,7 +137,8 @@ def load_library(path: str = LIB_PATH):
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
               "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
               "tms_build_cells_batch", "tms_batch_counts", "tms_set_tuning", "tms_get_tuning",
-              "tms_autotune", "tms_graph_capture", "tms_graph_launch"):
+              "tms_autotune", "tms_graph_capture", "tms_graph_capacity", "tms_graph_capture_into",
+              "tms_graph_launch"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -194,11 +197,13 @@ class Context:
         if rc != TMS_OK:
             raise TmsError(rc, self.lib.tms_last_error(None).decode())
         self.h = h
+        self._bound = None  # output tensors a capture writes into
 
     def close(self):
         if getattr(self, "h", None):
             self.lib.tms_destroy(self.h)
             self.h = None
+        self._bound = None
 
     def __del__(self):
         try:
@@ -399,10 +404,32 @@ class Context:
         return out
 
     # --------------------------------------------------------- captured pass
-    def graph_capture(self, cells: Cells, margin: float = 1.25):
+    def graph_capacity(self, cells: Cells, margin: float = 1.25):
+        """(leaf capacity, vertex capacity) of a capture with this margin: the
+        sizes buffers bound by graph_capture must hold."""
+        nl = C.c_int64()
+        nv = C.c_int64()
+        self._check(self.lib.tms_graph_capacity(self.h, cells.handle, float(margin),
+                                                C.byref(nl), C.byref(nv)))
+        return nl.value, nv.value
+
+    def graph_capture(self, cells: Cells, margin: float = 1.25, leaves=None, cphi=None,
+                      verts=None):
         """Record the pass (partition + corners + extraction) of `cells` into a
-        HIP graph; needs an eager partition and extraction of them first."""
-        self._check(self.lib.tms_graph_capture(self.h, cells.handle, float(margin)))
+        HIP graph; needs an eager partition and extraction of them first.
+        Tensors given for leaves (uint8 [cap, 20]), cphi (float64 [cap, 8]) or
+        verts (uint8 [cap, 40]) are bound: the graph writes its results there
+        (each must hold graph_capacity's figure), and the context keeps them
+        alive while the capture stands."""
+        if leaves is None and cphi is None and verts is None:
+            self._check(self.lib.tms_graph_capture(self.h, cells.handle, float(margin)))
+            self._bound = None
+            return
+        caps = [t.shape[0] for t in (leaves, cphi) if t is not None]
+        self._check(self.lib.tms_graph_capture_into(
+            self.h, cells.handle, float(margin), _VP(_ptr(leaves)), _VP(_ptr(cphi)),
+            min(caps) if caps else 0, _VP(_ptr(verts)), 0 if verts is None else verts.shape[0]))
+        self._bound = (leaves, cphi, verts)
 
     def graph_launch(self, cells: Cells, leaves=None, cphi=None, verts=None, offsets=False):
         """Replay the captured pass; returns (n_leaves, n_verts, stats dict

@@ -25,16 +25,31 @@ def _eager(ctx, cells):
     return leaves.clone(), cphi.clone(), verts.clone(), st
 
 
-def _check_replays(ctx, cells, n_conf, reps=3):
+def _check_replays(ctx, cells, n_conf, reps=3, bound=False):
     import torch
     L0, C0, V0, st0 = _eager(ctx, cells)
     lo0 = vo0 = None
     if n_conf > 1:
         lo0, vo0 = ctx.batch_counts(cells)
-    ctx.graph_capture(cells, margin=1.25)
-    lb = torch.empty((L0.shape[0] + 100, 20), dtype=torch.uint8, device="cuda:0")
-    cb = torch.empty((L0.shape[0] + 100, 8), dtype=torch.float64, device="cuda:0")
-    vb = torch.empty((V0.shape[0] + 100, 40), dtype=torch.uint8, device="cuda:0")
+    if bound:
+        # the graph writes straight into these (no copies on replay)
+        lcap, vcap = ctx.graph_capacity(cells, margin=1.25)
+        assert lcap >= L0.shape[0] and vcap >= V0.shape[0]
+        lb = torch.empty((lcap, 20), dtype=torch.uint8, device="cuda:0")
+        cb = torch.empty((lcap, 8), dtype=torch.float64, device="cuda:0")
+        vb = torch.empty((vcap, 40), dtype=torch.uint8, device="cuda:0")
+        ctx.graph_capture(cells, margin=1.25, leaves=lb, cphi=cb, verts=vb)
+        # a bound buffer below the capacity is refused, and the capture stays
+        with pytest.raises(tms.TmsError):
+            ctx.graph_capture(cells, margin=1.25, leaves=lb[:lcap - 1], cphi=cb[:lcap - 1],
+                              verts=vb)
+        with pytest.raises(tms.TmsError):
+            ctx.graph_capture(cells, margin=1.25, verts=vb[:vcap - 1])
+    else:
+        ctx.graph_capture(cells, margin=1.25)
+        lb = torch.empty((L0.shape[0] + 100, 20), dtype=torch.uint8, device="cuda:0")
+        cb = torch.empty((L0.shape[0] + 100, 8), dtype=torch.float64, device="cuda:0")
+        vb = torch.empty((V0.shape[0] + 100, 40), dtype=torch.uint8, device="cuda:0")
     for r in range(reps):
         lb.fill_(0)
         vb.fill_(0)
@@ -50,6 +65,12 @@ def _check_replays(ctx, cells, n_conf, reps=3):
         ctx.eval_phi(cells, torch.zeros((5, 3), dtype=torch.float64, device="cuda:0")) \
             if n_conf == 1 else ctx.partition_estimate(cells)
         torch.cuda.synchronize()
+    if bound:
+        # a replay into other buffers copies the results there
+        l2, c2, v2 = torch.zeros_like(L0), torch.zeros_like(C0), torch.zeros_like(V0)
+        nl, nv, _ = ctx.graph_launch(cells, l2, c2, v2)
+        assert nl == L0.shape[0] and nv == V0.shape[0]
+        assert torch.equal(l2, L0) and torch.equal(c2, C0) and torch.equal(v2, V0)
 
 
 @pytest.mark.parametrize("prec", [tms.PREC_FP64, tms.PREC_FP32_GUARD], ids=["fp64", "fp32g"])
@@ -57,6 +78,15 @@ def test_graph_single(ctx, prec):
     atoms = synth.globule(1000, 1006)
     cells = ctx.build_cells(atoms, tms.make_params(D=0.9, tau=0.1, precision=prec))
     _check_replays(ctx, cells, 1)
+    ctx.free_cells(cells)
+
+
+@pytest.mark.parametrize("n_conf", [1, 4], ids=["single", "batch"])
+def test_graph_bound_outputs(ctx, n_conf):
+    confs = [synth.globule(n, 3100 + k) for k, n in enumerate([600, 150, 400, 250][:n_conf])]
+    p = tms.make_params(D=0.9, tau=0.1, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells(confs[0], p) if n_conf == 1 else ctx.build_cells_batch(confs, p)
+    _check_replays(ctx, cells, n_conf, bound=True)
     ctx.free_cells(cells)
 
 
