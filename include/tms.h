@@ -338,7 +338,10 @@ int32_t tms_graph_capture_into(tms_ctx *ctx, const tms_cells *cells, double marg
                                tms_vertex *verts, int64_t vert_cap);
 
 /* Replay the captured pass on ctx's stream.  `cells` must be the captured
- * cells, or a rebuild of them with the same geometry and buffers.
+ * cells, or a rebuild of them with the same geometry and buffers.  Results
+ * of a capture made with tms_graph_capture_into are written into the bound
+ * buffers; naming those buffers here copies nothing, other buffers receive a
+ * copy.
  *  leaves, corner_phi  device [leaf_cap] tms_leaf / [leaf_cap][8] double, or NULL;
  *  verts               device [vert_cap] tms_vertex, or NULL;
  *  n_leaves, n_verts   host out (or NULL);
