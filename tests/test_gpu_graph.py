@@ -114,6 +114,11 @@ def test_graph_rejects_without_eager_pass(ctx):
     cells = ctx.build_cells(atoms, tms.make_params(tau=0.1))
     with pytest.raises(tms.TmsError):
         ctx.graph_capture(cells)
+    with pytest.raises(tms.TmsError):
+        ctx.graph_capacity(cells)
+    ctx.partition_estimate(cells)
+    with pytest.raises(tms.TmsError):  # the extraction is missing too
+        ctx.graph_capacity(cells)
     ctx.free_cells(cells)
 
 
