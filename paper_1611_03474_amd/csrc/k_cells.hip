@@ -174,10 +174,16 @@ __global__ void k_sort_cells(const int32_t *__restrict__ start, int64_t ncells, 
 
 // Visit the atoms whose squared distance to the root box is <= R_c^2, in
 // cell order.  EMIT=false counts, EMIT=true writes the sorted-atom indices.
+// Each stencil row is clipped to the cells its atoms can reach: with ey, ez
+// the row's y and z gaps to the box, an atom in it is within R_c only if its
+// x gap is at most sqrt(R_c^2 - ey^2 - ez^2).  That chord is taken from
+// R_c^2 enlarged by 2^-20 and the hardware reciprocal square root enlarged
+// by 2^-20 (far above its error and the rounding of the gaps), so a row may
+// keep a cell more than needed (whose atoms the test drops) but never one
+// less: the list is the same set in the same order.
 template <bool EMIT>
 __global__ void k_root_lists(const Grid *__restrict__ gt, int nconf, const int32_t *__restrict__ cs,
-                             const double *__restrict__ ax, const double *__restrict__ ay,
-                             const double *__restrict__ az, int64_t nroots,
+                             const double4 *__restrict__ xw, int64_t nroots,
                              const int32_t *__restrict__ start, int32_t *__restrict__ out) {
     int64_t r = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (r >= nroots) return;
@@ -187,7 +193,7 @@ __global__ void k_root_lists(const Grid *__restrict__ gt, int nconf, const int32
         rz = (int)(rl / ((int64_t)g.nr[0] * g.nr[1]));
     double lo[3] = {g.o[0] + rx * g.h0, g.o[1] + ry * g.h0, g.o[2] + rz * g.h0};
     double hi[3] = {lo[0] + g.h0, lo[1] + g.h0, lo[2] + g.h0};
-    const double rc2 = g.rc2;
+    const double rc2 = g.rc2, rc2m = rc2 * (1.0 + 0x1p-20);
     double R = sqrt(rc2);
     int c0[3], c1[3];
     for (int a = 0; a < 3; ++a) {
@@ -196,21 +202,33 @@ __global__ void k_root_lists(const Grid *__restrict__ gt, int nconf, const int32
     }
     int cnt = 0;
     int w = EMIT ? start[r] : 0;
-    for (int cz = c0[2]; cz <= c1[2]; ++cz)
+    for (int cz = c0[2]; cz <= c1[2]; ++cz) {
+        const double lz = g.o[2] + cz * g.cs;
+        const double ez = fmax(fmax(lz - hi[2], lo[2] - (lz + g.cs)), 0.0);
         for (int cy = c0[1]; cy <= c1[1]; ++cy) {
-            int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
-            int b = cs[row + c0[0]], e = cs[row + c1[0] + 1];
+            const double ly = g.o[1] + cy * g.cs;
+            const double ey = fmax(fmax(ly - hi[1], lo[1] - (ly + g.cs)), 0.0);
+            const double ryz = (rc2m - ez * ez) - ey * ey;
+            if (!(ryz >= 0.0)) continue;
+            const double hx =
+                ryz > 0.0 ? ryz * __builtin_amdgcn_rsq(ryz) * (1.0 + 0x1p-20) : 0.0;
+            const int x0 = max(c0[0], (int)floor(over_cs(g, lo[0] - hx - g.o[0])));
+            const int x1 = min(c1[0], (int)floor(over_cs(g, hi[0] + hx - g.o[0])));
+            if (x0 > x1) continue;
+            const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
+            const int b = cs[row + x0], e = cs[row + x1 + 1];
             for (int i = b; i < e; ++i) {
-                double x = ax[i], y = ay[i], z = az[i];
-                double dx = fmax(fmax(lo[0] - x, x - hi[0]), 0.0);
-                double dy = fmax(fmax(lo[1] - y, y - hi[1]), 0.0);
-                double dz = fmax(fmax(lo[2] - z, z - hi[2]), 0.0);
+                const double4 a = xw[i];
+                double dx = fmax(fmax(lo[0] - a.x, a.x - hi[0]), 0.0);
+                double dy = fmax(fmax(lo[1] - a.y, a.y - hi[1]), 0.0);
+                double dz = fmax(fmax(lo[2] - a.z, a.z - hi[2]), 0.0);
                 if (dx * dx + dy * dy + dz * dz <= rc2) {
                     if (EMIT) out[w++] = i;
                     else ++cnt;
                 }
             }
         }
+    }
     if (!EMIT) out[r] = cnt;
 }
 
@@ -273,20 +291,19 @@ hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *
 }
 
 hipError_t launch_root_count(const Grid *gt, int nconf, const int32_t *cell_start,
-                             const double *ax, const double *ay, const double *az, int64_t nroots,
-                             int32_t *cnt, hipStream_t s) {
+                             const double4 *xw, int64_t nroots, int32_t *cnt, hipStream_t s) {
     if (nroots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_root_lists<false>, dim3(nblk(nroots)), dim3(kBS), 0, s, gt, nconf,
-                       cell_start, ax, ay, az, nroots, nullptr, cnt);
+                       cell_start, xw, nroots, nullptr, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_root_fill(const Grid *gt, int nconf, const int32_t *cell_start, const double *ax,
-                            const double *ay, const double *az, int64_t nroots,
-                            const int32_t *start, int32_t *atoms, hipStream_t s) {
+hipError_t launch_root_fill(const Grid *gt, int nconf, const int32_t *cell_start,
+                            const double4 *xw, int64_t nroots, const int32_t *start,
+                            int32_t *atoms, hipStream_t s) {
     if (nroots <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_root_lists<true>, dim3(nblk(nroots)), dim3(kBS), 0, s, gt, nconf,
-                       cell_start, ax, ay, az, nroots, start, atoms);
+                       cell_start, xw, nroots, start, atoms);
     return hipGetLastError();
 }
 

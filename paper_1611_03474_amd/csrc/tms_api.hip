@@ -884,8 +884,8 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         CK(ctx->flags.ensure(4 * (size_t)(nr + 1)));
         int32_t *rc_cnt = ctx->flags.as<int32_t>();
         CK(launch_fill_u32(reinterpret_cast<uint32_t *>(rc_cnt), 0u, nr + 1, s));
-        CK(launch_root_count(gt, nconf, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
-                             cells->ay.as<double>(), cells->az.as<double>(), nr, rc_cnt, s));
+        CK(launch_root_count(gt, nconf, cells->cell_start.as<int32_t>(), cells->axw.as<double4>(),
+                             nr, rc_cnt, s));
         int64_t tot = 0;
         int32_t rc = scan_total(ctx, rc_cnt, cells->root_start.as<int32_t>(), nr + 1, &tot);
         if (rc) return bail(rc);
@@ -894,9 +894,9 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         // lists may grow a little) keeps the buffer, and with it a capture
         if (4 * (size_t)std::max<int64_t>(tot, 1) > cells->root_atoms.cap)
             CK(cells->root_atoms.ensure(5 * (size_t)std::max<int64_t>(tot, 1) + 4096));
-        CK(launch_root_fill(gt, nconf, cells->cell_start.as<int32_t>(), cells->ax.as<double>(),
-                            cells->ay.as<double>(), cells->az.as<double>(), nr,
-                            cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(), s));
+        CK(launch_root_fill(gt, nconf, cells->cell_start.as<int32_t>(), cells->axw.as<double4>(),
+                            nr, cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
+                            s));
     }
     CK(hipStreamSynchronize(s));
 #undef CK

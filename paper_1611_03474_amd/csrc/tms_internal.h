@@ -275,11 +275,10 @@ hipError_t launch_pack_atoms(const double *ax, const double *ay, const double *a
 hipError_t launch_sort_cells(const int32_t *cell_start, int64_t ncells, double *ax, double *ay,
                              double *az, double *aw, double *ar, int32_t *aidx, hipStream_t s);
 hipError_t launch_root_count(const Grid *gt, int nconf, const int32_t *cell_start,
-                             const double *ax, const double *ay, const double *az, int64_t nroots,
-                             int32_t *cnt, hipStream_t s);
-hipError_t launch_root_fill(const Grid *gt, int nconf, const int32_t *cell_start, const double *ax,
-                            const double *ay, const double *az, int64_t nroots,
-                            const int32_t *start, int32_t *atoms, hipStream_t s);
+                             const double4 *xw, int64_t nroots, int32_t *cnt, hipStream_t s);
+hipError_t launch_root_fill(const Grid *gt, int nconf, const int32_t *cell_start,
+                            const double4 *xw, int64_t nroots, const int32_t *start,
+                            int32_t *atoms, hipStream_t s);
 
 // k_adjoint.hip
 hipError_t launch_adjoint_fold(const Grid &g, const Lat &lat, const uint64_t *cbm,
