@@ -230,15 +230,9 @@ def run_batch(ctx, tms, confs, steps, warmup):
 def cpu_baseline(atoms, w, n_glob=4):
     """FP64 oracle on a bounded sample: the first n_glob globules of the
     assembly with their hydrogens (about n_glob/20 of the workload)."""
-    import numpy as np
     import oracle
-    sel = np.zeros(len(atoms), dtype=bool)
-    for k in range(n_glob):
-        heavy = atoms[5000 * k:5000 * (k + 1)]
-        cen = heavy[:, :3].mean(axis=0)
-        rho = np.max(np.linalg.norm(heavy[:, :3] - cen, axis=1))
-        sel |= np.linalg.norm(atoms[:, :3] - cen, axis=1) <= rho + 1.05
-    sample = atoms[sel]
+    from paper_1611_03474_amd import workloads
+    sample = workloads.assembly_slice(atoms, n_glob)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     t0 = time.perf_counter()
     r = oracle.partition(sample, w.D, c=w.c, tau=w.tau, h0=w.h0, h_min=w.h_min, pad=w.pad,

@@ -64,5 +64,20 @@ def atoms(w: Workload):
     raise KeyError(w.name)
 
 
+def assembly_slice(atoms, n_glob: int = 4):
+    """The first n_glob globules of the assembly with the hydrogens near
+    them (every atom within a globule's largest centre distance + 1.05 A of
+    its centroid): a bounded sample of the assembly workload that the FP64
+    oracle finishes in seconds to tens of seconds.  Selection only."""
+    import numpy as np
+    sel = np.zeros(len(atoms), dtype=bool)
+    for k in range(n_glob):
+        heavy = atoms[5000 * k:5000 * (k + 1)]
+        cen = heavy[:, :3].mean(axis=0)
+        rho = np.max(np.linalg.norm(heavy[:, :3] - cen, axis=1))
+        sel |= np.linalg.norm(atoms[:, :3] - cen, axis=1) <= rho + 1.05
+    return atoms[sel]
+
+
 ALL = {w.name: w for w in [GLOBULE200_UNIFORM, *GLOBULE5K.values(), GLOBULE20K_ADJOINT,
                            BATCH256, ASSEMBLY110K]}

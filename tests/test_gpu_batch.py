@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from paper_1611_03474_amd import synth, tms
+from parity_util import compare_lists
 
 pytestmark = pytest.mark.gpu
 
@@ -119,10 +120,10 @@ def test_batch_rejects_bad_offsets(ctx):
         ctx.build_cells_batch((a, [0, 5, 10]), pu)     # uniform grid: one conformation
 
 
-def test_batch_full_size_sampled(ctx):
-    # 256 conformations, sizes log-uniform in [500, 20000], FP32+guard: a
-    # sample of conformations must match their single-conformation passes
-    # bit for bit; two small ones also match the oracle
+@pytest.fixture(scope="module")
+def full_batch(ctx):
+    # 256 conformations, sizes log-uniform in [500, 20000], FP32+guard, the
+    # benchmark's batch configuration; results stay on the device
     confs = synth.batch(256)
     p = tms.make_params(D=0.9, tau=1e-3, precision=tms.PREC_FP32_GUARD)
     cells = ctx.build_cells_batch(confs, p)
@@ -131,26 +132,46 @@ def test_batch_full_size_sampled(ctx):
     lo, vo = ctx.batch_counts(cells)
     print("batch: %d atoms, %d leaves, %d vertices, %d cubes estimated"
           % (sum(len(x) for x in confs), lo[-1], vo[-1], sum(st["n_est"])))
+    ctx.free_cells(cells)
+    yield dict(confs=confs, p=p, leaves=leaves, cphi=cphi, verts=verts, lo=lo, vo=vo)
+
+
+def test_batch_full_size_sampled(ctx, full_batch):
+    # a sample of conformations must match their single-conformation passes
+    # bit for bit
+    fb = full_batch
+    confs, p, lo, vo = fb["confs"], fb["p"], fb["lo"], fb["vo"]
     rng = np.random.default_rng(11)
     sizes = np.array([len(x) for x in confs])
-    small = [int(i) for i in np.argsort(sizes)[:2]]
-    pick = sorted(set(small) | set(int(i) for i in rng.choice(256, 4, replace=False)))
+    pick = sorted(set(int(i) for i in np.argsort(sizes)[:2])
+                  | set(int(i) for i in rng.choice(256, 4, replace=False)))
     for b in pick:
         sel = slice(lo[b], lo[b + 1])
-        Lb = tms.leaves_to_numpy(leaves[sel])
-        Vb = tms.vertices_to_numpy(verts[vo[b]:vo[b + 1]])
+        Lb = tms.leaves_to_numpy(fb["leaves"][sel])
+        Vb = tms.vertices_to_numpy(fb["verts"][vo[b]:vo[b + 1]])
         Ls, CPs, Vs = _single(ctx, confs[b], p)
         for f in ("level", "ix", "iy", "iz", "reason", "mask", "cls"):
             assert np.array_equal(Lb[f], Ls[f]), (b, f)
-        assert np.array_equal(cphi[sel].cpu().numpy(), CPs), b
+        assert np.array_equal(fb["cphi"][sel].cpu().numpy(), CPs), b
         assert np.array_equal(Vb["edge_key"], Vs["edge_key"] | (np.uint64(b) << np.uint64(53)))
-        if b in small:
-            ref = oracle.partition(confs[b], 0.9, c=1.0, tau=1e-3, conf=b)
-            if ref.tie_cube == 0 and ref.tie_corner == 0:
-                assert np.array_equal(np.stack([Lb["ix"], Lb["iy"], Lb["iz"]], 1), ref.ijk)
-                assert np.array_equal(Lb["mask"], ref.mask)
-                assert np.array_equal(Vb["edge_key"], ref.vkey)
-    ctx.free_cells(cells)
+        assert np.array_equal(Vb["t"], Vs["t"]), b
+
+
+@pytest.mark.parametrize("b", list(range(0, 256, 16)))
+def test_batch_subset_oracle(full_batch, b):
+    # the fixed subset of 16 conformations b = 0 mod 16 (657 to 19,509 atoms),
+    # each compared element by element with the oracle run with its
+    # conformation id
+    fb = full_batch
+    lo, vo = fb["lo"], fb["vo"]
+    sel = slice(lo[b], lo[b + 1])
+    L = tms.leaves_to_numpy(fb["leaves"][sel])
+    CP = fb["cphi"][sel].cpu().numpy()
+    V = tms.vertices_to_numpy(fb["verts"][vo[b]:vo[b + 1]])
+    assert np.all(L["conf"] == b)
+    ref = oracle.partition(fb["confs"][b], 0.9, c=1.0, tau=1e-3, conf=b)
+    compare_lists(L, CP, V, ref, tms.PREC_FP32_GUARD, label="conformation %d (%d atoms)"
+                  % (b, len(fb["confs"][b])))
 
 
 def test_tuning_does_not_change_results(ctx):

@@ -18,11 +18,11 @@ import pytest
 
 import oracle
 from paper_1611_03474_amd import synth, tms
+from parity_util import compare as _compare, phi_tol as _phi_tol, run_gpu as _run_gpu
 
 pytestmark = pytest.mark.gpu
 
 PRECS = [tms.PREC_FP64, tms.PREC_FP32_GUARD]
-PNAME = {tms.PREC_FP64: "fp64", tms.PREC_FP32_GUARD: "fp32g"}
 
 
 @pytest.fixture(scope="module")
@@ -42,90 +42,6 @@ def g200():
 @pytest.fixture(scope="module")
 def g1000():
     return synth.globule(1000, 1006)
-
-
-def _phi_tol(prec):
-    return 1e-12 if prec == tms.PREC_FP64 else 1e-5
-
-
-def _taint(level, ijk, K, tie_cubes, tie_corner_keys):
-    """Boolean mask of leaves inside an oracle near-tie cube or touching a
-    near-tie corner."""
-    bad = np.zeros(len(level), dtype=bool)
-    if len(tie_cubes):
-        sh = K - level.astype(np.int64)
-        lo = ijk.astype(np.int64) << sh[:, None]
-        hi = (ijk.astype(np.int64) + 1) << sh[:, None]
-        for lev, x, y, z in tie_cubes:
-            s = K - int(lev)
-            tlo = np.array([x, y, z], dtype=np.int64) << s
-            thi = (np.array([x, y, z], dtype=np.int64) + 1) << s
-            bad |= np.all((lo < thi) & (hi > tlo), axis=1)
-    for key in tie_corner_keys:
-        X, Y, Z = (int(key) >> 32) & 0xFFFF, (int(key) >> 16) & 0xFFFF, int(key) & 0xFFFF
-        sh = K - level.astype(np.int64)
-        lo = ijk.astype(np.int64) << sh[:, None]
-        hi = (ijk.astype(np.int64) + 1) << sh[:, None]
-        p = np.array([X, Y, Z])
-        bad |= np.all((lo <= p) & (hi >= p), axis=1)
-    return bad
-
-
-def _run_gpu(ctx, atoms, prec, **kw):
-    p = tms.make_params(precision=prec, **kw)
-    cells = ctx.build_cells(atoms, p)
-    leaves, cphi, st = ctx.partition_estimate(cells)
-    verts = ctx.extract(cells, leaves, cphi)
-    out = dict(cells=cells, leaves=tms.leaves_to_numpy(leaves), cphi=cphi.cpu().numpy(),
-               verts=tms.vertices_to_numpy(verts), stats=st)
-    ctx.free_cells(cells)
-    return out
-
-
-def _compare(ctx, atoms, prec, D=0.9, **kw):
-    okw = {k: v for k, v in kw.items() if k in ("c", "tau", "h0", "h_min", "pad", "eps_cut")}
-    uniform = kw.get("mode", tms.MODE_ADAPTIVE) == tms.MODE_UNIFORM
-    ref = oracle.partition(atoms, D, uniform=uniform, **okw)
-    got = _run_gpu(ctx, atoms, prec, D=D, **kw)
-    L = got["leaves"]
-    assert np.allclose(got["cells"].origin, ref.origin, rtol=0, atol=0)
-    assert np.array_equal(got["cells"].dims, ref.dims)
-    ijk = np.stack([L["ix"], L["iy"], L["iz"]], axis=1)
-    bad_g = _taint(L["level"], ijk, ref.K, ref.tie_cubes, ref.tie_corner_keys)
-    bad_r = _taint(ref.level, ref.ijk, ref.K, ref.tie_cubes, ref.tie_corner_keys)
-    print("%s: leaves %d (oracle %d), excluded near-tie leaves %d/%d, guard cubes %d points %d"
-          % (PNAME[prec], len(L), ref.n_leaves, bad_g.sum(), bad_r.sum(),
-             got["stats"]["guard_cubes"], got["stats"]["guard_points"]))
-    if not len(ref.tie_cubes):
-        assert np.array_equal(got["stats"]["n_est"][:ref.K + 1], ref.n_est[:ref.K + 1])
-    g_keep, r_keep = ~bad_g, ~bad_r
-    assert g_keep.sum() == r_keep.sum()
-    for f_g, f_r in [(L["level"], ref.level), (L["ix"], ref.ijk[:, 0]), (L["iy"], ref.ijk[:, 1]),
-                     (L["iz"], ref.ijk[:, 2]), (L["reason"], ref.reason), (L["mask"], ref.mask),
-                     (L["cls"], ref.cls)]:
-        assert np.array_equal(np.asarray(f_g)[g_keep].astype(np.int64),
-                              np.asarray(f_r)[r_keep].astype(np.int64))
-    cg, cr = got["cphi"][g_keep], ref.corner_phi[r_keep]
-    tol = _phi_tol(prec)
-    assert np.all(np.abs(cg - cr) <= tol * np.maximum(np.abs(cr), 1e-300) + 1e-300)
-    # vertices: compare on edges whose owner leaf is outside the tainted set
-    V = got["verts"]
-    if bad_r.any() or bad_g.any():
-        # near ties present: compare t on the shared edge keys; the keys that
-        # differ must come from the excluded subtrees (a handful at most)
-        common, ig, ir = np.intersect1d(V["edge_key"], ref.vkey, return_indices=True)
-        tg, tr = V["t"][ig], ref.vt[ir]
-        assert len(V) - len(common) <= 12 * bad_g.sum()
-        assert ref.n_vert - len(common) <= 12 * bad_r.sum()
-    else:
-        assert np.array_equal(V["edge_key"], ref.vkey)
-        tg, tr = V["t"], ref.vt
-        assert np.allclose(np.stack([V["x"], V["y"], V["z"]], 1), ref.vxyz, rtol=0,
-                           atol=(1e-12 if prec == tms.PREC_FP64 else 1e-5) * 2.0)
-    ttol = 1e-11 if prec == tms.PREC_FP64 else 1e-5
-    print("max vertex t error %.3e" % np.max(np.abs(tg - tr), initial=0.0))
-    assert np.max(np.abs(tg - tr), initial=0.0) <= ttol
-    return got, ref
 
 
 @pytest.mark.parametrize("prec", PRECS)
