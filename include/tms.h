@@ -202,6 +202,24 @@ int32_t tms_free_cells(tms_ctx *ctx, tms_cells *cells);
 int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
                      double *phi, double *grad, int64_t *n_guard);
 
+/* tms_eval_phi for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results as tms_eval_phi (bit for bit; n_guard equal),
+ * but the FP32+guard path's per-point guard flags, guard list and count live
+ * in a static device array of the library (about 20 MB per device, held until
+ * the process ends) instead of context workspace.  This call allocates
+ * nothing: no hipMalloc, no hipFree, no allocating library routine.
+ *  m     0 .. 4194304 (2^22) points; larger m returns TMS_E_INVALID.
+ *  other arguments as tms_eval_phi.
+ * Every call on one device shares that array and keeps the last call's
+ * contents (the count is cleared at the start of each call): calls that
+ * overlap on one device -- from two contexts or two host threads -- race
+ * and must be serialised by the caller.
+ * Errors: TMS_E_INVALID, TMS_E_DEVICE (also when the context's device has no
+ * such array: device index 64 or above). */
+int32_t tms_eval_phi_noalloc(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                             double *phi, double *grad, int64_t *n_guard);
+
 /* The adaptive partition and estimation pass (Section 2.2, Steps 1-3), then
  * the classification of every leaf by the signs of phi - c at its corners
  * (the trilinear interpolant of eq. linear1 meets the closed cube iff the

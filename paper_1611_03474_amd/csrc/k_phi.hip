@@ -233,6 +233,25 @@ __global__ void k_list_emit2(const int32_t *__restrict__ f, const int32_t *__res
     if (i < n && f[i]) list[off[i]] = (int32_t)i;
 }
 
+// Indices of the flagged points appended to `list`, one device-scope atomic
+// per wavefront that holds any (the wave's lanes take consecutive slots in
+// lane order).  The list order depends on the wavefronts' timing; every listed
+// point is recomputed on its own, so results do not depend on it.
+__global__ __launch_bounds__(kBS) void k_guard_append(const uint8_t *__restrict__ gd, int64_t n,
+                                                      int32_t *__restrict__ list,
+                                                      unsigned *__restrict__ cnt) {
+    const int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    const bool f = i < n && gd[i];
+    const unsigned long long b = __ballot(f);
+    if (b == 0ull) return;  // uniform across the wavefront
+    const int lane = (int)(threadIdx.x & 63);
+    const int leader = __ffsll(b) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(cnt, (unsigned)__popcll(b));
+    base = __shfl(base, leader, 64);
+    if (f) list[base + (unsigned)__popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
 // number of SURFACE leaves: block partials, then one block
 __global__ void k_count_surface(const tms_leaf *__restrict__ leaves, int64_t n,
                                 const int64_t *__restrict__ nd,
@@ -570,6 +589,13 @@ hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_list_emit2, dim3(nblk(n)), dim3(kBS), 0, s, flags, off, n, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_append(const uint8_t *gd, int64_t n, int32_t *list, unsigned *cnt,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_guard_append, dim3(nblk(n)), dim3(kBS), 0, s, gd, n, list, cnt);
     return hipGetLastError();
 }
 

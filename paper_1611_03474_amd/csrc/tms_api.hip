@@ -9,12 +9,34 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "tms_internal.h"
 
 using namespace tms;
+
+// ---------------------------------------------------------------------------
+// Scratch of tms_eval_phi_noalloc, for callers that cannot allocate: a
+// file-scope device array that every GPU the library runs on holds until the
+// process ends.  Layout: a u32 guard count (first 256 bytes), the guard list
+// (int32 [kNoAllocMaxPoints]), the per-point guard bytes (u8
+// [kNoAllocMaxPoints]).  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address is taken once per device with
+// hipGetSymbolAddress (tms_create) and only that address is used.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNoAllocMaxPoints = (int64_t)1 << 22;
+constexpr size_t kNoAllocListOff = 256;
+constexpr size_t kNoAllocFlagOff = kNoAllocListOff + sizeof(int32_t) * (size_t)kNoAllocMaxPoints;
+constexpr size_t kNoAllocBytes = kNoAllocFlagOff + (size_t)kNoAllocMaxPoints;
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char *g_noalloc_addr[kNoAllocDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace tms {
 
@@ -603,9 +625,24 @@ int32_t tms_create(tms_ctx **out, int32_t device, void *stream) {
         return fail(nullptr, TMS_E_DEVICE, "device %d out of range (%d devices)", device, cnt);
     e = hipSetDevice(device);
     if (e != hipSuccess) return fail(nullptr, TMS_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    unsigned char *scr = nullptr;
+    if (device < kNoAllocDevices) {
+        // the device address of this device's copy of `scratch`, once per device
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (!g_noalloc_addr[device]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(nullptr, TMS_E_DEVICE, "hipGetSymbolAddress(scratch): %s",
+                            hipGetErrorString(e));
+            g_noalloc_addr[device] = static_cast<unsigned char *>(p);
+        }
+        scr = g_noalloc_addr[device];
+    }
     tms_ctx *ctx = new tms_ctx();
     ctx->device = device;
     ctx->stream = static_cast<hipStream_t>(stream);
+    ctx->noalloc_scratch = scr;
     e = ctx->counters.ensure(1 << 20);
     if (e != hipSuccess) {
         delete ctx;
@@ -1359,6 +1396,51 @@ int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, in
     if (rc) return rc;
     HIPCK(hipStreamSynchronize(ctx->stream));
     if (n_guard) *n_guard = ng;
+    return TMS_OK;
+}
+
+int32_t tms_eval_phi_noalloc(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                             double *phi, double *grad, int64_t *n_guard) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || m < 0 || (m > 0 && (!pts || !phi)))
+        return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_eval_phi_noalloc");
+    if (cells->nconf != 1)
+        return fail(ctx, TMS_E_INVALID, "tms_eval_phi_noalloc takes cells of one conformation");
+    if (m > kNoAllocMaxPoints)
+        return fail(ctx, TMS_E_INVALID,
+                    "tms_eval_phi_noalloc: %lld points exceed its maximum of %lld (use "
+                    "tms_eval_phi, or split the points)", (long long)m,
+                    (long long)kNoAllocMaxPoints);
+    if (!ctx->noalloc_scratch)
+        return fail(ctx, TMS_E_DEVICE, "no static scratch on device %d", ctx->device);
+    HIPCK(hipSetDevice(ctx->device));
+    if (n_guard) *n_guard = 0;
+    if (m == 0) return TMS_OK;
+    const int prec = cells->p.precision;
+    const Grid *gt = cells->gtab.as<Grid>();
+    hipStream_t s = ctx->stream;
+    unsigned *cnt = reinterpret_cast<unsigned *>(ctx->noalloc_scratch);
+    int32_t *list = reinterpret_cast<int32_t *>(ctx->noalloc_scratch + kNoAllocListOff);
+    uint8_t *gflag = ctx->noalloc_scratch + kNoAllocFlagOff;
+    if (prec != TMS_PREC_FP32_GUARD) {
+        HIPCK(launch_phi_points(gt, nullptr, prec, pts, m, cells->cell_start.as<int32_t>(),
+                                cells->axw.as<double4>(), 0.0, phi, grad, nullptr, s));
+        HIPCK(hipStreamSynchronize(s));
+        return TMS_OK;
+    }
+    // the count is cleared by a fill kernel (the array keeps the last call's
+    // contents); every guard byte of [0, m) is written by the phi kernel
+    HIPCK(launch_fill_u32(cnt, 0u, 1, s));
+    HIPCK(launch_phi_points(gt, nullptr, prec, pts, m, cells->cell_start.as<int32_t>(),
+                            cells->axw.as<double4>(), 0.0, phi, grad, gflag, s));
+    HIPCK(launch_guard_append(gflag, m, list, cnt, s));
+    HIPCK(launch_phi_points_subset(gt, nullptr, pts, list, m, cells->cell_start.as<int32_t>(),
+                                   cells->axw.as<double4>(), phi, grad, s,
+                                   reinterpret_cast<const int32_t *>(cnt)));
+    unsigned ng = 0;
+    HIPCK(hipMemcpyAsync(&ng, cnt, sizeof(ng), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (n_guard) *n_guard = (int64_t)ng;
     return TMS_OK;
 }
 

@@ -182,6 +182,9 @@ struct tms_graph_state {
 struct tms_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // device address of the library's static scratch array on this device
+    // (tms_eval_phi_noalloc); resolved once per device by tms_create
+    unsigned char *noalloc_scratch = nullptr;
     std::string err;
     std::vector<tms_cells *> cells;
     // last partition result
@@ -429,6 +432,10 @@ hipError_t launch_guard_flags_u8(const uint8_t *g, int64_t n, int32_t *flags, hi
                                  const int32_t *nd = nullptr);
 hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
                             hipStream_t s);
+// indices i < n with gd[i] != 0 appended to list at slots taken from *cnt
+// (which the caller zeroes); order arbitrary
+hipError_t launch_guard_append(const uint8_t *gd, int64_t n, int32_t *list, unsigned *cnt,
+                               hipStream_t s);
 hipError_t launch_count_surface(const tms_leaf *leaves, int64_t n, unsigned long long *count,
                                 unsigned long long *part, hipStream_t s,
                                 const int64_t *nd = nullptr);

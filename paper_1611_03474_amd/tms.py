@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
     L.tms_cells_info.argtypes = [_VP, dp, C.POINTER(i64), C.POINTER(i32), dp, C.POINTER(i64)]
     L.tms_free_cells.argtypes = [_VP, _VP]
     L.tms_eval_phi.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, C.POINTER(i64)]
+    L.tms_eval_phi_noalloc.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, C.POINTER(i64)]
     L.tms_partition_estimate.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64), _VP,
                                          C.POINTER(Stats)]
     L.tms_get_leaves.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
@@ -133,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     L.tms_debug_fast_exp.argtypes = [_VP, _VP, i64, _VP]
     for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
+              "tms_eval_phi_noalloc",
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
               "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
@@ -286,6 +288,16 @@ class Context:
         self._check(self.lib.tms_eval_phi(self.h, cells.handle, _VP(_ptr(p)), m, _VP(_ptr(phi)),
                                           _VP(_ptr(g)), C.byref(ng)))
         return phi, g, int(ng.value)
+
+    def eval_phi_noalloc(self, cells: Cells, pts, phi, grad=None):
+        """tms_eval_phi_noalloc: phi (and grad) at the points of a device
+        [m, 3] float64 tensor into the caller's tensors; the library allocates
+        nothing.  Returns the number of points recomputed in double precision."""
+        ng = C.c_int64()
+        self._check(self.lib.tms_eval_phi_noalloc(self.h, cells.handle, _VP(_ptr(pts)),
+                                                  pts.shape[0], _VP(_ptr(phi)), _VP(_ptr(grad)),
+                                                  C.byref(ng)))
+        return int(ng.value)
 
     # ------------------------------------------------------------ partition
     def partition_estimate(self, cells: Cells, cap: int | None = None):
