@@ -44,11 +44,15 @@ extern "C" {
 
 /* ---- precision of the per-pair arithmetic -------------------------------- */
 #define TMS_PREC_FP64 0       /* everything in double precision                 */
-#define TMS_PREC_FP32_GUARD 1 /* sums over atom pairs in single precision; any  */
-                              /* cube or point whose decision margin lies within */
-                              /* the single-precision error band is recomputed  */
-                              /* in double precision, so every discrete result  */
-                              /* equals the double-precision one               */
+#define TMS_PREC_FP32_GUARD 1 /* the per-pair exponentials that are not shared  */
+                              /* (phi at points and corners; 1-D projections    */
+                              /* computed in place) from the single-precision   */
+                              /* hardware exponential, relative error <= 1.5e-7; */
+                              /* every sum and product stays double precision.  */
+                              /* Any cube or point whose decision margin lies   */
+                              /* within that error band is recomputed with      */
+                              /* double-precision exponentials, so every        */
+                              /* discrete result equals the double-precision one */
 
 /* ---- partition mode ---------------------------------------------------- */
 #define TMS_MODE_ADAPTIVE 0 /* Section 2.2 Steps 1-3: estimate, bound, divide   */
@@ -180,8 +184,7 @@ int32_t tms_build_cells_batch(tms_ctx *ctx, const double *xyzr, const int64_t *o
 /* Per-conformation boundaries of the kept results of `cells`: leaf_offsets
  * [n_conf + 1] of the last partition pass, vertex_offsets [n_conf + 1] of
  * the last extraction (host arrays; either may be NULL).
- * Errors: TMS_E_INVALID (no kept result of these cells; vertex offsets of a
- * hashed extraction of more than one conformation). */
+ * Errors: TMS_E_INVALID (no kept result of these cells). */
 int32_t tms_batch_counts(tms_ctx *ctx, const tms_cells *cells, int64_t *leaf_offsets,
                          int64_t *vertex_offsets);
 
@@ -194,10 +197,12 @@ int32_t tms_free_cells(tms_ctx *ctx, tms_cells *cells);
 /* phi and its gradient at m points (eq. Gaussian1), summed over the atoms
  * within R_c of each point.
  *  pts   device [m][3] double;  phi device [m] double;  grad device [m][3]
- *  double or NULL.  In TMS_PREC_FP32_GUARD the sums run in single precision
- *  and every point with |phi - c| inside the single-precision error band is
- *  recomputed in double precision, so the sign of phi - c is the
- *  double-precision one; *n_guard (host, may be NULL) receives the count.
+ *  double or NULL.  In TMS_PREC_FP32_GUARD each term's exponential comes
+ *  from the single-precision hardware exponential (relative error <= 1.5e-7;
+ *  the sums stay double precision) and every point with |phi - c| inside
+ *  that error band is recomputed with double-precision exponentials, so the
+ *  sign of phi - c is the double-precision one; *n_guard (host, may be NULL)
+ *  receives the count.
  * Errors: TMS_E_INVALID, TMS_E_DEVICE. */
 int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
                      double *phi, double *grad, int64_t *n_guard);
@@ -239,6 +244,9 @@ int32_t tms_eval_phi_noalloc(tms_ctx *ctx, const tms_cells *cells, const double 
  * call; a too-small cap returns TMS_E_CAPACITY with *n_leaves set to the
  * required count and nothing copied -- then call tms_get_leaves with a
  * larger buffer.
+ * Corners are de-duplicated in a dense bitmap over the finest lattice; a
+ * lattice whose bitmap would exceed 8 GiB (a box of about 1,000 h_min per
+ * axis) is refused with TMS_E_INVALID.
  * Errors: TMS_E_CAPACITY, TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
 int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves, int64_t cap,
                                int64_t *n_leaves, double *corner_phi, tms_stats *stats);
@@ -260,14 +268,61 @@ int32_t tms_get_leaves(tms_ctx *ctx, tms_leaf *leaves, double *corner_phi, int64
  *  corner_phi device [n][8] double, or NULL to evaluate phi at the corners.
  *  out        device [cap] tms_vertex, or NULL to only count.
  *  n_out      host out: number of vertices.
- * When `out` holds the result (cap >= the count; dense edge bitmaps) the
- * vertices are written straight into it and ctx keeps no copy; otherwise
- * the result is kept in ctx until the next extract call (see
- * tms_get_vertices).  Errors: TMS_E_CAPACITY (*n_out = required),
- * TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
+ * When `out` holds the result (cap >= the count) the vertices are written
+ * straight into it and ctx keeps no copy; otherwise the result is kept in
+ * ctx until the next extract call (see tms_get_vertices).
+ * Edges are de-duplicated in dense bitmaps over each level's lattice; a
+ * lattice whose bitmaps would exceed 8 GiB (a box of about 1,000 h_min per
+ * axis) is refused with TMS_E_INVALID.  Errors: TMS_E_CAPACITY (*n_out =
+ * required), TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
 int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves,
                                   int64_t n, const double *corner_phi, tms_vertex *out,
                                   int64_t cap, int64_t *n_out);
+
+/* ---- stage-two points (Section 2.3) ----------------------------------------
+ * On a SURFACE leaf mapped to [-1,1]^3 with the trilinear interpolant g of
+ * eq. linear1:
+ *  - fold segments along axis a (eq. fold1: g = c and dg/da = 0): g is linear
+ *    in x_a, so wherever dg/da vanishes g does not depend on x_a and the fold
+ *    set is a set of full segments parallel to a; each joins an extreme point
+ *    on the face x_a = -1 to one on the face x_a = +1 (eq. curve: g = c,
+ *    x_a = +-1, dg/da = 0), at most two per axis;
+ *  - critical points (eq. critical: g = c, dg/da = 0, dg/db = 0, a != b), at
+ *    most two per pair of axes.
+ * Points on the boundary of the closed cube count.  A configuration with
+ * infinitely many solutions (g constant along a; the two equations sharing a
+ * factor) contributes no points and is counted as degenerate. */
+#define TMS_S2_FOLD 0     /* fold segment along `axis`                       */
+#define TMS_S2_CRITICAL 1 /* critical point of the two axes other than `axis` */
+
+/* One stage-two record.  leaf: index into the leaf list given.  FOLD: (x, y,
+ * z) is the segment's end on the face axis = lower (the extreme point there);
+ * its other end, on the face axis = upper, is that point moved by the leaf's
+ * edge along the axis.  CRITICAL: (x, y, z) is the point.  root numbers the
+ * solutions of one (leaf, kind, axis) from 0 in ascending order of their
+ * first free coordinate (FOLD: the lower of the two other axes; CRITICAL:
+ * the coordinate along `axis`).  32 bytes. */
+typedef struct {
+    int32_t leaf;
+    uint8_t kind, axis, root, pad;
+    double x, y, z;
+} tms_s2point;
+
+/* Stage-two points of every SURFACE leaf of a leaf list (Section 2.3, eqs.
+ * curve, fold1, critical), in double precision from the leaves' corner
+ * values.  Records come out by leaf; inside a leaf the folds along x, y, z,
+ * then the critical points of the pairs (y,z), (x,z), (x,y), each by root.
+ *  leaves      device [n] tms_leaf (from tms_partition_estimate, or any
+ *              leaves of the cells' lattice; conf indexes the batch).
+ *  corner_phi  device [n][8] double, corner v = dx + 2dy + 4dz (required).
+ *  out         device [cap] tms_s2point, or NULL to only count.
+ *  n_out       host out: number of records.
+ *  n_degenerate host out (or NULL): degenerate (leaf, kind, axis) cases.
+ * Errors: TMS_E_CAPACITY (cap below the count; *n_out = required, nothing
+ * written), TMS_E_INVALID, TMS_E_OOM, TMS_E_DEVICE. */
+int32_t tms_stage2_points(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
+                          const double *corner_phi, tms_s2point *out, int64_t cap,
+                          int64_t *n_out, int64_t *n_degenerate);
 
 /* Copy the vertices of the last extraction, as kept in ctx; with out NULL
  * only the count.  Errors: TMS_E_CAPACITY (*n_out = required),
@@ -309,8 +364,7 @@ int32_t tms_get_corners(tms_ctx *ctx, double *xyz, double *phi, int64_t cap, int
  *         kept leaves and corner values.
  *  dxyzr  device [n_atoms][4] double, written in the caller's atom order.
  * Errors: TMS_E_INVALID (no kept adaptive pass on these cells, count
- * mismatch, edge points that do not end on kept corners, or a pass too large
- * for the dense corner/edge bitmaps), TMS_E_DEVICE. */
+ * mismatch, edge points that do not end on kept corners), TMS_E_DEVICE. */
 int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, int64_t m,
                      const double *dt, int64_t nv, double *dxyzr);
 
@@ -322,7 +376,7 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
  * capacities (the counts of an eager pass of the same cells times `margin`)
  * and read their actual counts there, so a replay needs no host round trip
  * until its results are read.  Results are those of the eager pass, bit for
- * bit.  Needs the dense corner and edge bitmaps (not the hashed paths).
+ * bit.
  *
  * tms_graph_capture: requires an eager tms_partition_estimate and
  * tms_extract_cube_vertices of `cells` (the last ones on ctx); margin in
@@ -453,7 +507,8 @@ int32_t tms_autotune(tms_ctx *ctx, const tms_cells *cells, tms_tuning *best, dou
 #define TMS_T_TABLE 10   /* per-level projection tables                */
 #define TMS_T_GROUPED 11 /* tensor estimate, eight level-1 roots per
                             wavefront                                  */
-#define TMS_T_SLOTS 12
+#define TMS_T_STAGE2 12  /* stage-two points (tms_stage2_points)       */
+#define TMS_T_SLOTS 13
 
 typedef struct {
     double ms[TMS_T_SLOTS];       /* accumulated device milliseconds */

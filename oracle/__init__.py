@@ -64,6 +64,21 @@ class _Result(C.Structure):
                 ("tie_corner_keys", C.c_uint64 * 1024)]
 
 
+class _S2Pt(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("kind", C.c_uint8), ("axis", C.c_uint8),
+                ("root", C.c_uint8), ("pad", C.c_uint8), ("p", C.c_double * 3)]
+
+
+class _S2Result(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pts", C.POINTER(_S2Pt)),
+                ("leaf_margin", C.POINTER(C.c_double)), ("n_degenerate", C.c_int64),
+                ("n_mismatch", C.c_int64)]
+
+
+S2_DTYPE = np.dtype([("leaf", "<i4"), ("kind", "u1"), ("axis", "u1"), ("root", "u1"),
+                     ("pad", "u1"), ("x", "<f8"), ("y", "<f8"), ("z", "<f8")])
+S2_FOLD, S2_CRITICAL = 0, 1
+
 _lib = None
 _DP = C.POINTER(C.c_double)
 _FUN1 = C.CFUNCTYPE(C.c_double, C.c_double, C.c_void_p)
@@ -94,6 +109,14 @@ def lib():
         L.or_partition.argtypes = [_DP, C.c_int64, C.POINTER(Params)]
         L.or_partition.restype = C.POINTER(_Result)
         L.or_free.argtypes = [C.POINTER(_Result)]
+        _U8P = C.POINTER(C.c_uint8)
+        L.or_stage2_cube.argtypes = [_DP, C.c_double, _DP, _U8P, _U8P, _U8P, _DP,
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.or_stage2_cube.restype = C.c_int
+        L.or_stage2_points.argtypes = [C.POINTER(C.c_int32), _U8P, _U8P, _DP, C.c_int64,
+                                       C.c_double, _DP, C.c_double, C.c_int]
+        L.or_stage2_points.restype = C.POINTER(_S2Result)
+        L.or_stage2_free.argtypes = [C.POINTER(_S2Result)]
         _lib = L
     return _lib
 
@@ -349,3 +372,70 @@ def surface_loss_grad(xyzr, D, c, res: Result, eps_cut=1e-10, nthreads=0):
     grad = phi_adjoint(xyzr, D, pts, wbar, eps_cut=eps_cut, nthreads=nthreads)
     return surface_loss(ph, c, t, h), grad, dict(keys=keys, pts=pts, phi=ph, wbar=wbar, t=t,
                                                  k0=k0, k1=k1, h=h)
+
+
+# --------------------------------------------------------------------------
+# Stage 2 points of the trilinear surface (Section 2.3)
+# --------------------------------------------------------------------------
+
+def stage2_cube(f, c):
+    """Fold segments (eqs. curve, fold1) and critical points (eq. critical) of
+    g = c on one cube [-1,1]^3 whose trilinear interpolant (eq. linear1) has
+    corner values f[v], v = dx + 2 dy + 4 dz.  Returns (records in local
+    coordinates as a dict of arrays, margin, degenerate count, count of fold
+    segments whose two face extreme points disagree)."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(8)
+    loc = np.zeros((12, 3))
+    kind = np.zeros(12, dtype=np.uint8)
+    axis = np.zeros(12, dtype=np.uint8)
+    root = np.zeros(12, dtype=np.uint8)
+    margin = C.c_double(0)
+    nd = C.c_int(0)
+    mis = C.c_int(0)
+    U8 = C.POINTER(C.c_uint8)
+    n = lib().or_stage2_cube(_dp(f), float(c), _dp(loc), kind.ctypes.data_as(U8),
+                             axis.ctypes.data_as(U8), root.ctypes.data_as(U8), C.byref(margin),
+                             C.byref(nd), C.byref(mis))
+    return (dict(loc=loc[:n].copy(), kind=kind[:n].copy(), axis=axis[:n].copy(),
+                 root=root[:n].copy()), margin.value, nd.value, mis.value)
+
+
+class Stage2:
+    """Stage 2 points of every SURFACE leaf of a pass: ``pts`` (S2_DTYPE,
+    world coordinates, by leaf), ``leaf_margin`` per leaf, counts of
+    degenerate configurations and of face mismatches."""
+
+    def __init__(self, r):
+        n = r.n
+        raw = np.ctypeslib.as_array(C.cast(r.pts, C.POINTER(C.c_uint8)), (max(n, 1) * 32,))
+        self.pts = np.frombuffer(raw[:n * 32].tobytes(), dtype=S2_DTYPE).copy()
+        self.n_degenerate = r.n_degenerate
+        self.n_mismatch = r.n_mismatch
+
+
+def stage2_points(ijk, level, cls, corner_phi, c, origin, h0, nthreads=0):
+    """Stage 2 points (Section 2.3: eqs. curve, fold1, critical) of the
+    SURFACE leaves of a leaf list with its corner values."""
+    ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+    level = np.ascontiguousarray(level, dtype=np.uint8)
+    cls = np.ascontiguousarray(cls, dtype=np.uint8)
+    cp = np.ascontiguousarray(corner_phi, dtype=np.float64).reshape(-1, 8)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    n = ijk.shape[0]
+    assert level.shape[0] == n and cls.shape[0] == n and cp.shape[0] == n
+    U8 = C.POINTER(C.c_uint8)
+    rp = lib().or_stage2_points(ijk.ctypes.data_as(C.POINTER(C.c_int32)), level.ctypes.data_as(U8),
+                                cls.ctypes.data_as(U8), _dp(cp), n, float(c), _dp(o), float(h0),
+                                int(nthreads))
+    try:
+        out = Stage2(rp.contents)
+        out.leaf_margin = np.ctypeslib.as_array(rp.contents.leaf_margin, (max(n, 1),))[:n].copy()
+    finally:
+        lib().or_stage2_free(rp)
+    return out
+
+
+def stage2_of(res: Result, c, nthreads=0):
+    """Stage 2 points of a partition result."""
+    return stage2_points(res.ijk, res.level, res.cls, res.corner_phi, c, res.origin, res.h0,
+                         nthreads=nthreads)

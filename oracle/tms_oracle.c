@@ -1176,3 +1176,400 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
     return R;
 #undef PUSH_LEAF
 }
+
+/* ------------------------------------------------------------------------ */
+/* Stage 2 points of a leaf's trilinear surface g = c (Section 2.3).          */
+/*                                                                            */
+/* The leaf is mapped to [-1,1]^3 as in eq. linear1; corner v = dx + 2dy +    */
+/* 4dz sits at (2dx - 1, 2dy - 1, 2dz - 1) and holds the value f[v].          */
+/*                                                                            */
+/*  - extreme points on the face alpha = a (eq. curve): g = c, alpha = a and  */
+/*    dg/dalpha = 0, alpha in {x, y, z}, a in {-1, 1};                        */
+/*  - fold curves along alpha (eq. fold1): g = c and dg/dalpha = 0.  g is     */
+/*    linear in alpha, so dg/dalpha does not depend on alpha and, where it    */
+/*    vanishes, neither does g: the fold curve is a set of full segments      */
+/*    parallel to the alpha axis, each joining an extreme point of the face   */
+/*    alpha = -1 to one of the face alpha = +1 (the paper's remark that the   */
+/*    trilinear fold curves are straight segments ending at extreme points);  */
+/*  - critical points (eq. critical): g = c, dg/dalpha = 0, dg/dbeta = 0 for  */
+/*    a pair alpha != beta.                                                   */
+/*                                                                            */
+/* Reading: only SURFACE leaves are processed (the corner values straddle c,  */
+/* so g = c meets the closed cube); points on the boundary of the closed      */
+/* cube count.  A configuration with infinitely many solutions (g constant    */
+/* along alpha, or the two equations sharing a factor) is reported as         */
+/* degenerate and contributes no points.                                       */
+/*                                                                            */
+/* Each record: kind 0 = fold segment along `axis` (its lower end, the        */
+/* extreme point on the face axis = -1, is stored; the upper end, on the face */
+/* axis = +1, is the same point moved by the cube edge along the axis), kind  */
+/* 1 = critical point of the pair of axes other than `axis`.  Solutions of    */
+/* one (kind, axis) are numbered by `root` in ascending order of their first  */
+/* free coordinate (fold: the lower of the two other axes; critical: the      */
+/* coordinate along `axis`).                                                  */
+/* ------------------------------------------------------------------------ */
+
+#define OR_S2_MAX 12
+
+typedef struct {
+    int32_t leaf;
+    uint8_t kind, axis, root, pad;
+    double p[3];
+} or_s2pt;
+
+/* bilinear function on [-1,1]^2 from its corner values F[k] at
+ * (2(k&1) - 1, 2(k>>1) - 1): b[0] + b[1] u + b[2] v + b[3] u v */
+static void bilinear_coeffs(const double F[4], double b[4])
+{
+    b[0] = (F[0] + F[1] + F[2] + F[3]) / 4.0;
+    b[1] = (-F[0] + F[1] - F[2] + F[3]) / 4.0;
+    b[2] = (-F[0] - F[1] + F[2] + F[3]) / 4.0;
+    b[3] = (F[0] - F[1] - F[2] + F[3]) / 4.0;
+}
+
+/* Real roots of q0 + q1 t + q2 t^2 (ascending); returns their number, or -1
+ * when every coefficient is zero.  *dmargin receives the relative distance
+ * of the discriminant from zero (1 when linear or constant). */
+static int quad_roots(double q0, double q1, double q2, double t[2], double *dmargin)
+{
+    *dmargin = 1.0;
+    if (q2 == 0.0) {
+        if (q1 == 0.0) return (q0 == 0.0) ? -1 : 0;
+        t[0] = -q0 / q1;
+        return 1;
+    }
+    double disc = q1 * q1 - 4.0 * q2 * q0;
+    double den = q1 * q1 + 4.0 * fabs(q2 * q0);
+    if (den > 0.0) *dmargin = fabs(disc) / den;
+    if (disc < 0.0) return 0;
+    if (disc == 0.0) {
+        t[0] = -q1 / (2.0 * q2);
+        return 1;
+    }
+    double sq = sqrt(disc);
+    double q = -0.5 * (q1 + (q1 >= 0.0 ? sq : -sq));
+    double a = q / q2, b = (q != 0.0) ? q0 / q : a;
+    t[0] = a < b ? a : b;
+    t[1] = a < b ? b : a;
+    return 2;
+}
+
+static double range_margin(double u)
+{
+    return fmin(fabs(u - 1.0), fabs(u + 1.0));
+}
+
+/* Whether two linear functions p0 + p1 t and q0 + q1 t have a common real
+ * zero (both identically zero included). */
+static int linear_common_zero(double p0, double p1, double q0, double q1)
+{
+    if (p1 == 0.0 && q1 == 0.0) return p0 == 0.0 && q0 == 0.0;
+    return p0 * q1 - p1 * q0 == 0.0;
+}
+
+/* Extreme points of g = c on the face axis = a (eq. curve) in the local
+ * coordinates (u, v) of the two other axes (u the lower axis).  Returns the
+ * number of points (ascending u), or -1 when the equations have infinitely
+ * many real solutions (degenerate). */
+static int face_extremes(const double f[8], double c, int axis, int a, double uv[2][2],
+                         double *margin)
+{
+    int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+    int ax_u = o1 < o2 ? o1 : o2, ax_v = o1 < o2 ? o2 : o1;
+    double FG[4], FH[4];
+    for (int k = 0; k < 4; ++k) {
+        int d[3] = {0, 0, 0};
+        d[ax_u] = k & 1;
+        d[ax_v] = k >> 1;
+        d[axis] = (a > 0) ? 1 : 0;
+        int vf = d[0] + 2 * d[1] + 4 * d[2];
+        d[axis] = 0;
+        int v0 = d[0] + 2 * d[1] + 4 * d[2];
+        int v1 = v0 + (1 << axis);
+        FG[k] = f[vf] - c;             /* g - c restricted to the face (eq. linear1) */
+        FH[k] = (f[v1] - f[v0]) / 2.0; /* dg/dalpha: half the edge differences      */
+    }
+    double g[4], h[4];
+    bilinear_coeffs(FG, g);
+    bilinear_coeffs(FH, h);
+    /* dg/dalpha identically zero: g does not depend on alpha and every point
+     * of the surface (which meets a SURFACE leaf) solves the system */
+    if (FH[0] == 0.0 && FH[1] == 0.0 && FH[2] == 0.0 && FH[3] == 0.0) return -1;
+    /* G = (g0 + g1 u) + (g2 + g3 u) v,  H = (h0 + h1 u) + (h2 + h3 u) v: a
+     * common v exists iff the resultant in v vanishes */
+    double r0 = g[0] * h[2] - g[2] * h[0];
+    double r1 = g[0] * h[3] + g[1] * h[2] - g[2] * h[1] - g[3] * h[0];
+    double r2 = g[1] * h[3] - g[3] * h[1];
+    double sg = fabs(g[0]) + fabs(g[1]) + fabs(g[2]) + fabs(g[3]);
+    double sh = fabs(h[0]) + fabs(h[1]) + fabs(h[2]) + fabs(h[3]);
+    double sr = fabs(r0) + fabs(r1) + fabs(r2);
+    if (sg * sh > 0.0 && sr / (sg * sh) < *margin) *margin = sr / (sg * sh);
+    double t[2], dm;
+    int nr = quad_roots(r0, r1, r2, t, &dm);
+    if (nr < 0) {
+        /* resultant identically zero: if neither equation involves v, both
+         * are linear in u and share a zero (a whole line along v) or have no
+         * common solution; otherwise they share a factor (a curve) */
+        if (g[2] == 0.0 && g[3] == 0.0 && h[2] == 0.0 && h[3] == 0.0)
+            return linear_common_zero(g[0], g[1], h[0], h[1]) ? -1 : 0;
+        return -1;
+    }
+    if (dm < *margin) *margin = dm;
+    /* a root at which both equations vanish for every v: a line of solutions */
+    for (int i = 0; i < nr; ++i) {
+        double u = t[i];
+        double AG = g[0] + g[1] * u, BG = g[2] + g[3] * u;
+        double AH = h[0] + h[1] * u, BH = h[2] + h[3] * u;
+        if (BG == 0.0 && BH == 0.0 && AG == 0.0 && AH == 0.0) return -1;
+    }
+    int n = 0;
+    for (int i = 0; i < nr; ++i) {
+        double u = t[i];
+        double m = range_margin(u);
+        if (m < *margin) *margin = m;
+        if (u < -1.0 || u > 1.0) continue;
+        double AG = g[0] + g[1] * u, BG = g[2] + g[3] * u;
+        double AH = h[0] + h[1] * u, BH = h[2] + h[3] * u;
+        double bmax = fmax(fabs(BG), fabs(BH));
+        if (bmax == 0.0) {
+            /* no v solves both unless both constant terms vanish too */
+            double am = fmax(fabs(AG), fabs(AH)) / (sg + sh);
+            if (am < *margin) *margin = am;
+            continue;
+        }
+        double v = (fabs(BG) >= fabs(BH)) ? -AG / BG : -AH / BH;
+        m = range_margin(v);
+        if (m < *margin) *margin = m;
+        if (v < -1.0 || v > 1.0) continue;
+        uv[n][0] = u;
+        uv[n][1] = v;
+        ++n;
+    }
+    return n;
+}
+
+/* monomial coefficients of g (eq. linear1): g = sum_e m[e] prod_{i in e} x_i
+ * over the subsets e of {x, y, z} (bit 0 x, bit 1 y, bit 2 z) */
+static void trilinear_monomials(const double f[8], double m[8])
+{
+    for (int e = 0; e < 8; ++e) {
+        double s = 0.0;
+        for (int v = 0; v < 8; ++v) {
+            double sg = 1.0;
+            for (int i = 0; i < 3; ++i)
+                if ((e >> i) & 1) sg *= ((v >> i) & 1) ? 1.0 : -1.0;
+            s += sg * f[v];
+        }
+        m[e] = s / 8.0;
+    }
+}
+
+/* Critical points (eq. critical) of the pair of axes other than gamma, in
+ * local coordinates, ascending along gamma.  Returns their number, or -1
+ * when the equations have infinitely many real solutions (degenerate). */
+static int critical_points(const double f[8], double c, int gamma, double xyz[2][3],
+                           double *margin)
+{
+    int o1 = (gamma + 1) % 3, o2 = (gamma + 2) % 3;
+    int al = o1 < o2 ? o1 : o2, be = o1 < o2 ? o2 : o1;
+    int A = 1 << al, B = 1 << be, G = 1 << gamma;
+    double m[8];
+    trilinear_monomials(f, m);
+    /* at fixed gamma: g = k + P alpha + Q beta + S alpha beta, with k, P, Q, S
+     * linear in gamma; dg/dalpha = P + S beta, dg/dbeta = Q + S alpha; where
+     * both vanish (S != 0), g = k - P Q / S, so g = c iff (k - c) S - P Q = 0 */
+    double k0 = m[0] - c, k1 = m[G];
+    double P0 = m[A], P1 = m[A | G], Q0 = m[B], Q1 = m[B | G];
+    double S0 = m[A | B], S1 = m[A | B | G];
+    double w0 = k0 * S0 - P0 * Q0;
+    double w1 = k0 * S1 + k1 * S0 - P0 * Q1 - P1 * Q0;
+    double w2 = k1 * S1 - P1 * Q1;
+    double sc = 0.0;
+    for (int e = 0; e < 8; ++e)
+        sc += fabs(e == 0 ? m[0] - c : m[e]);
+    double sw = fabs(w0) + fabs(w1) + fabs(w2);
+    if (sc > 0.0 && sw / (sc * sc) < *margin) *margin = sw / (sc * sc);
+    double t[2], dm;
+    int nr = quad_roots(w0, w1, w2, t, &dm);
+    if (nr < 0) {
+        /* identically zero.  With S not identically zero every slice's
+         * stationary point lies on the surface: a curve.  With S = 0 the
+         * slices are g = k + P alpha + Q beta: a solution needs P = Q = 0 and
+         * k = c at one gamma (then the whole slice solves it) */
+        if (S0 != 0.0 || S1 != 0.0) return -1;
+        double a[3] = {P0, Q0, k0}, b[3] = {P1, Q1, k1};
+        int rank1 = 1, anyb = 0, anya = 0;
+        for (int i = 0; i < 3; ++i) {
+            if (b[i] != 0.0) anyb = 1;
+            if (a[i] != 0.0) anya = 1;
+            for (int j = i + 1; j < 3; ++j)
+                if (a[i] * b[j] - a[j] * b[i] != 0.0) rank1 = 0;
+        }
+        return (rank1 && (anyb || !anya)) ? -1 : 0;
+    }
+    if (dm < *margin) *margin = dm;
+    /* a root at which a whole slice solves the system */
+    for (int i = 0; i < nr; ++i) {
+        double gm = t[i];
+        if (S0 + S1 * gm == 0.0 && P0 + P1 * gm == 0.0 && Q0 + Q1 * gm == 0.0 &&
+            k0 + k1 * gm == 0.0)
+            return -1;
+    }
+    int n = 0;
+    for (int i = 0; i < nr; ++i) {
+        double gm = t[i];
+        double mg = range_margin(gm);
+        if (mg < *margin) *margin = mg;
+        if (gm < -1.0 || gm > 1.0) continue;
+        double S = S0 + S1 * gm, P = P0 + P1 * gm, Q = Q0 + Q1 * gm;
+        if (S == 0.0) {
+            /* the slice is g = k + P alpha + Q beta with P Q = 0: no isolated
+             * stationary point on it */
+            double pm = fmax(fabs(P), fabs(Q));
+            if (pm == 0.0) pm = fabs(k0 + k1 * gm);
+            if (sc > 0.0 && pm / sc < *margin) *margin = pm / sc;
+            continue;
+        }
+        double a = -Q / S, b = -P / S;
+        mg = fmin(range_margin(a), range_margin(b));
+        if (mg < *margin) *margin = mg;
+        if (a < -1.0 || a > 1.0 || b < -1.0 || b > 1.0) continue;
+        xyz[n][al] = a;
+        xyz[n][be] = b;
+        xyz[n][gamma] = gm;
+        ++n;
+    }
+    return n;
+}
+
+/* Every Stage 2 point of one cube (local coordinates).  Returns the number
+ * of records written (<= OR_S2_MAX); *margin receives the smallest relative
+ * distance of a discrete decision from a tie (1 if none), *ndeg the number
+ * of degenerate (kind, axis) configurations, *mismatch the number of fold
+ * segments whose extreme points on the faces -1 and +1 differ by more than
+ * 1e-9 (they coincide in exact arithmetic). */
+int or_stage2_cube(const double f[8], double c, double loc[OR_S2_MAX][3], uint8_t *kind,
+                   uint8_t *axis, uint8_t *root, double *margin, int *ndeg, int *mismatch)
+{
+    int n = 0;
+    *margin = 1.0;
+    *ndeg = 0;
+    *mismatch = 0;
+    for (int al = 0; al < 3; ++al) {
+        double lo[2][2], hi[2][2];
+        int nl = face_extremes(f, c, al, -1, lo, margin);
+        int nh = face_extremes(f, c, al, +1, hi, margin);
+        if (nl < 0 || nh < 0) {
+            ++*ndeg;
+            continue;
+        }
+        if (nl != nh) ++*mismatch;
+        for (int k = 0; k < nl; ++k) {
+            if (k < nh && (fabs(lo[k][0] - hi[k][0]) > 1e-9 || fabs(lo[k][1] - hi[k][1]) > 1e-9))
+                ++*mismatch;
+            int o1 = (al + 1) % 3, o2 = (al + 2) % 3;
+            int au = o1 < o2 ? o1 : o2, av = o1 < o2 ? o2 : o1;
+            loc[n][al] = -1.0;
+            loc[n][au] = lo[k][0];
+            loc[n][av] = lo[k][1];
+            kind[n] = 0;
+            axis[n] = (uint8_t)al;
+            root[n] = (uint8_t)k;
+            ++n;
+        }
+    }
+    for (int gm = 0; gm < 3; ++gm) {
+        double p[2][3];
+        int nc = critical_points(f, c, gm, p, margin);
+        if (nc < 0) {
+            ++*ndeg;
+            continue;
+        }
+        for (int k = 0; k < nc; ++k) {
+            for (int a = 0; a < 3; ++a)
+                loc[n][a] = p[k][a];
+            kind[n] = 1;
+            axis[n] = (uint8_t)gm;
+            root[n] = (uint8_t)k;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* Stage 2 points of every SURFACE leaf of a partition result, in world
+ * coordinates: leaf q's cube is origin + (ijk + [0,1]) h0 / 2^level, local
+ * u in [-1,1] maps to lo + (u + 1) h / 2.  Records come out by leaf, then
+ * in the order of or_stage2_cube.  leaf_margin[q] receives the cube's
+ * margin (1 for leaves that are not processed). */
+typedef struct {
+    int64_t n;
+    or_s2pt *pts;
+    double *leaf_margin;
+    int64_t n_degenerate;
+    int64_t n_mismatch;
+} or_s2result;
+
+or_s2result *or_stage2_points(const int32_t *ijk, const uint8_t *level, const uint8_t *cls,
+                              const double *corner_phi, int64_t nl, double c, const double origin[3],
+                              double h0, int nthreads)
+{
+    or_s2result *R = (or_s2result *)calloc(1, sizeof(or_s2result));
+    int32_t *cnt = (int32_t *)calloc((size_t)(nl ? nl : 1), sizeof(int32_t));
+    or_s2pt *tmp = (or_s2pt *)malloc(sizeof(or_s2pt) * OR_S2_MAX * (size_t)(nl ? nl : 1));
+    R->leaf_margin = (double *)malloc(sizeof(double) * (size_t)(nl ? nl : 1));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int64_t ndeg = 0, nmis = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : ndeg, nmis)
+#endif
+    for (int64_t q = 0; q < nl; ++q) {
+        R->leaf_margin[q] = 1.0;
+        if (cls[q] != OR_CLS_SURFACE) continue;
+        double loc[OR_S2_MAX][3], margin;
+        uint8_t kind[OR_S2_MAX], axis[OR_S2_MAX], root[OR_S2_MAX];
+        int nd, mis;
+        int n = or_stage2_cube(corner_phi + 8 * q, c, loc, kind, axis, root, &margin, &nd, &mis);
+        R->leaf_margin[q] = margin;
+        ndeg += nd;
+        nmis += mis;
+        double h = h0 / (double)(1 << level[q]);
+        for (int k = 0; k < n; ++k) {
+            or_s2pt *o = tmp + OR_S2_MAX * q + k;
+            o->leaf = (int32_t)q;
+            o->kind = kind[k];
+            o->axis = axis[k];
+            o->root = root[k];
+            o->pad = 0;
+            for (int a = 0; a < 3; ++a)
+                o->p[a] = origin[a] + (double)ijk[3 * q + a] * h + (loc[k][a] + 1.0) * h / 2.0;
+        }
+        cnt[q] = n;
+    }
+    int64_t tot = 0;
+    for (int64_t q = 0; q < nl; ++q)
+        tot += cnt[q];
+    R->pts = (or_s2pt *)malloc(sizeof(or_s2pt) * (size_t)(tot ? tot : 1));
+    int64_t w = 0;
+    for (int64_t q = 0; q < nl; ++q)
+        for (int k = 0; k < cnt[q]; ++k)
+            R->pts[w++] = tmp[OR_S2_MAX * q + k];
+    R->n = tot;
+    R->n_degenerate = ndeg;
+    R->n_mismatch = nmis;
+    free(tmp);
+    free(cnt);
+    return R;
+}
+
+void or_stage2_free(or_s2result *R)
+{
+    if (!R) return;
+    free(R->pts);
+    free(R->leaf_margin);
+    free(R);
+}

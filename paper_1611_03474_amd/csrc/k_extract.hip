@@ -3,10 +3,10 @@
 //
 // On a cube edge g is linear in the edge coordinate, so its root is
 // t = (c - phi0) / (phi1 - phi0) from the lower end.  Edges shared by leaves of
-// the same level carry the same key; the first candidate (leaf-major, then
-// edge order) owns it, which makes the output order independent of thread
-// timing: a hash table records the minimum candidate id per key, and a stable
-// scan over candidates writes the owners.
+// the same level are emitted once: each crossing edge is owned by one leaf
+// (found in a per-level leaf-lattice bitmap), which sets its bit in a dense
+// per-(conformation, level, axis) edge bitmap in key order; vertices are
+// written at their bits' ranks, so the list comes out in edge-key order.
 #include "tms_device.h"
 
 namespace tms {
@@ -15,16 +15,6 @@ namespace {
 
 constexpr int kBS = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
-constexpr uint64_t kEmpty = ~0ull;
-
-__device__ __forceinline__ uint64_t mix64(uint64_t k) {
-    k ^= k >> 33;
-    k *= 0xff51afd7ed558ccdull;
-    k ^= k >> 33;
-    k *= 0xc4ceb9fe1a85ec53ull;
-    k ^= k >> 33;
-    return k;
-}
 
 // Edge e of a leaf: axis = e / 4; the two other axes in ascending order take
 // offsets (e & 1, (e >> 1) & 1).  Returns corner indices v0 (lower end) and v1.
@@ -46,78 +36,6 @@ __device__ __forceinline__ uint64_t edge_key(const tms_leaf &L, int axis, const 
     const uint64_t Z = (uint64_t)((L.iz + off[2]) << sh);
     return ((uint64_t)(uint32_t)L.conf << 53) | ((uint64_t)L.level << 50) |
            ((uint64_t)axis << 48) | (X << 32) | (Y << 16) | Z;
-}
-
-__global__ void k_edge_insert(const tms_leaf *__restrict__ leaves, int64_t n, int K,
-                              uint64_t *__restrict__ hk, uint32_t *__restrict__ hown,
-                              uint64_t hmask, uint32_t *__restrict__ slot) {
-    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 12 * n) return;
-    const tms_leaf L = leaves[c / 12];
-    const int e = (int)(c % 12);
-    int axis, off[3], v0, v1;
-    edge_corners(e, axis, off, v0, v1);
-    const bool cross = L.cls == TMS_CLS_SURFACE && (((L.mask >> v0) ^ (L.mask >> v1)) & 1);
-    if (!cross) {
-        slot[c] = 0xFFFFFFFFu;
-        return;
-    }
-    const uint64_t key = edge_key(L, axis, off, K);
-    uint64_t s = mix64(key) & hmask;
-    while (true) {
-        const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long *>(hk + s),
-                                        (unsigned long long)kEmpty, (unsigned long long)key);
-        if (prev == kEmpty || prev == key) break;
-        s = (s + 1) & hmask;
-    }
-    slot[c] = (uint32_t)s;
-    atomicMin(&hown[s], (uint32_t)c);
-}
-
-__global__ void k_edge_emit(const Grid *__restrict__ gt, const tms_leaf *__restrict__ leaves,
-                            const double *__restrict__ cphi, int64_t ncand,
-                            const int32_t *__restrict__ f, const int32_t *__restrict__ off_,
-                            tms_vertex *__restrict__ out) {
-    const int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= ncand || !f[c]) return;
-    const int64_t q = c / 12;
-    const tms_leaf L = leaves[q];
-    const Grid &g = gt[L.conf];
-    int axis, off[3], v0, v1;
-    edge_corners((int)(c % 12), axis, off, v0, v1);
-    const double f0 = cphi[8 * q + v0], f1 = cphi[8 * q + v1];
-    const int sh = g.K - L.level;
-    const double h = ldexp(g.h0, -(int)L.level);
-    double p[3] = {g.o[0] + (double)((L.ix + off[0]) << sh) * g.hmin,
-                   g.o[1] + (double)((L.iy + off[1]) << sh) * g.hmin,
-                   g.o[2] + (double)((L.iz + off[2]) << sh) * g.hmin};
-    const double t = (g.c - f0) / (f1 - f0);
-    p[axis] += t * h;
-    tms_vertex V;
-    V.edge_key = edge_key(L, axis, off, g.K);
-    V.t = t;
-    V.x = p[0];
-    V.y = p[1];
-    V.z = p[2];
-    out[off_[c]] = V;
-}
-
-__global__ void k_edge_count(const tms_leaf *__restrict__ leaves, int64_t n,
-                             unsigned long long *__restrict__ cnt) {
-    const int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    unsigned long long c = 0;
-    if (q < n) {
-        const tms_leaf L = leaves[q];
-        if (L.cls == TMS_CLS_SURFACE)
-            for (int e = 0; e < 12; ++e) {
-                int axis, off[3], v0, v1;
-                edge_corners(e, axis, off, v0, v1);
-                c += ((L.mask >> v0) ^ (L.mask >> v1)) & 1;
-            }
-    }
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(cnt, c);
 }
 
 // ---- dense-bitmap edge de-duplication ------------------------------------
@@ -311,30 +229,6 @@ hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const doubl
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_edge_write, dim3(nblk(n)), dim3(kBS), 0, s, gt, leaves, cphi, n, et, bm,
                        woff, own, out, nd, vcap, ovf);
-    return hipGetLastError();
-}
-
-hipError_t launch_edge_count(const tms_leaf *leaves, int64_t n, unsigned long long *count,
-                             hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_count, dim3(nblk(n)), dim3(kBS), 0, s, leaves, n, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
-                              uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_insert, dim3(nblk(12 * n)), dim3(kBS), 0, s, leaves, n, K, hkeys, hown,
-                       (uint64_t)(hcap - 1), slot);
-    return hipGetLastError();
-}
-
-hipError_t launch_edge_emit(const Grid *gt, const tms_leaf *leaves, const double *corner_phi,
-                            int64_t ncand, const int32_t *flags, const int32_t *off,
-                            tms_vertex *out, hipStream_t s) {
-    if (ncand <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_emit, dim3(nblk(ncand)), dim3(kBS), 0, s, gt, leaves, corner_phi,
-                       ncand, flags, off, out);
     return hipGetLastError();
 }
 

@@ -13,7 +13,6 @@ namespace {
 
 constexpr int kBS = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBS - 1) / kBS); }
-constexpr uint64_t kEmpty = ~0ull;
 
 // FAST phi kernel: every term carries a relative error <= kFastExpErr, so
 // |dphi| <= kFastExpErr phi.  guard[k] = 1 when the sign of phi - c is not
@@ -71,74 +70,6 @@ __global__ __launch_bounds__(kBS) void k_phi_subset(const Grid *__restrict__ gt,
     }
 }
 
-// finest-lattice key of corner v of a leaf: conf(16) | X(16) | Y(16) | Z(16)
-__device__ __forceinline__ uint64_t corner_key(const tms_leaf &L, int v, int K) {
-    const int sh = K - L.level;
-    const uint64_t X = (uint64_t)((L.ix + (v & 1)) << sh);
-    const uint64_t Y = (uint64_t)((L.iy + ((v >> 1) & 1)) << sh);
-    const uint64_t Z = (uint64_t)((L.iz + ((v >> 2) & 1)) << sh);
-    return ((uint64_t)(uint32_t)L.conf << 48) | (X << 32) | (Y << 16) | Z;
-}
-
-__device__ __forceinline__ uint64_t mix64(uint64_t k) {
-    k ^= k >> 33;
-    k *= 0xff51afd7ed558ccdull;
-    k ^= k >> 33;
-    k *= 0xc4ceb9fe1a85ec53ull;
-    k ^= k >> 33;
-    return k;
-}
-
-// open addressing with linear probing; returns the slot that holds key
-__device__ __forceinline__ uint32_t hash_insert(uint64_t *__restrict__ hk, uint64_t hmask,
-                                                uint64_t key) {
-    uint64_t s = mix64(key) & hmask;
-    while (true) {
-        uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long *>(hk + s),
-                                  (unsigned long long)kEmpty, (unsigned long long)key);
-        if (prev == kEmpty || prev == key) return (uint32_t)s;
-        s = (s + 1) & hmask;
-    }
-}
-
-__global__ void k_corner_insert(const tms_leaf *__restrict__ leaves, int64_t n, int K,
-                                uint64_t *__restrict__ hk, uint32_t *__restrict__ hown,
-                                uint64_t hmask, uint32_t *__restrict__ slot) {
-    int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= 8 * n) return;
-    const tms_leaf L = leaves[c >> 3];
-    const uint64_t key = corner_key(L, (int)(c & 7), K);
-    const uint32_t s = hash_insert(hk, hmask, key);
-    slot[c] = s;
-    atomicMin(&hown[s], (uint32_t)c);
-}
-
-__global__ void k_owner_flags(const uint32_t *__restrict__ slot, const uint32_t *__restrict__ hown,
-                              int64_t ncand, int32_t *__restrict__ f) {
-    int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= ncand) return;
-    const uint32_t s = slot[c];
-    f[c] = (s != 0xFFFFFFFFu && hown[s] == (uint32_t)c) ? 1 : 0;
-}
-
-__global__ void k_corner_unique(const tms_leaf *__restrict__ leaves, int64_t ncand, int K,
-                                const Grid *__restrict__ gt, const int32_t *__restrict__ f,
-                                const int32_t *__restrict__ off, const uint32_t *__restrict__ slot,
-                                double *__restrict__ upts, int32_t *__restrict__ uconf,
-                                uint32_t *__restrict__ slot2u) {
-    int64_t c = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (c >= ncand || !f[c]) return;
-    const tms_leaf L = leaves[c >> 3];
-    const Grid &g = gt[L.conf];
-    const int v = (int)(c & 7), sh = K - L.level;
-    const int64_t u = off[c];
-    upts[3 * u] = g.o[0] + (double)((L.ix + (v & 1)) << sh) * g.hmin;
-    upts[3 * u + 1] = g.o[1] + (double)((L.iy + ((v >> 1) & 1)) << sh) * g.hmin;
-    upts[3 * u + 2] = g.o[2] + (double)((L.iz + ((v >> 2) & 1)) << sh) * g.hmin;
-    uconf[u] = L.conf;
-    slot2u[slot[c]] = (uint32_t)u;
-}
-
 __device__ __forceinline__ void classify(tms_leaf &L, const double f[8], double c) {
     uint8_t m = 0;
 #pragma unroll
@@ -146,24 +77,6 @@ __device__ __forceinline__ void classify(tms_leaf &L, const double f[8], double 
         if (f[v] >= c) m |= (uint8_t)(1u << v);
     L.mask = m;
     L.cls = (m == 0) ? TMS_CLS_OUTSIDE : (m == 0xFF ? TMS_CLS_INSIDE : TMS_CLS_SURFACE);
-}
-
-__global__ void k_corner_gather(const tms_leaf *__restrict__ lin, int64_t n,
-                                const uint32_t *__restrict__ slot, const uint32_t *__restrict__ s2u,
-                                const double *__restrict__ uphi, double c,
-                                tms_leaf *__restrict__ lout, double *__restrict__ cphi) {
-    int64_t q = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (q >= n) return;
-    double f[8];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) f[v] = uphi[s2u[slot[8 * q + v]]];
-    tms_leaf L = lin[q];
-    classify(L, f, c);
-    lout[q] = L;
-    if (cphi) {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) cphi[8 * q + v] = f[v];
-    }
 }
 
 __global__ void k_uniform_leaves(Grid g, tms_leaf *__restrict__ leaves, int64_t n) {
@@ -516,39 +429,6 @@ hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const 
     if (m <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_phi_subset, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, list, m, cs, xw,
                        phi, grad, nd);
-    return hipGetLastError();
-}
-
-hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
-                                uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_insert, dim3(nblk(8 * n)), dim3(kBS), 0, s, leaves, n, K, hkeys, hown,
-                       (uint64_t)(hcap - 1), slot);
-    return hipGetLastError();
-}
-
-hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_t ncand,
-                              int32_t *flags, hipStream_t s) {
-    if (ncand <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_owner_flags, dim3(nblk(ncand)), dim3(kBS), 0, s, slot, hown, ncand, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid *gt,
-                                const int32_t *flags, const int32_t *off, const uint32_t *slot,
-                                double *upts, int32_t *uconf, uint32_t *slot2u, hipStream_t s) {
-    if (ncand <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_unique, dim3(nblk(ncand)), dim3(kBS), 0, s, leaves, ncand, K, gt,
-                       flags, off, slot, upts, uconf, slot2u);
-    return hipGetLastError();
-}
-
-hipError_t launch_corner_gather(const tms_leaf *lin, int64_t n, const uint32_t *slot,
-                                const uint32_t *slot2u, const double *uphi, double c,
-                                tms_leaf *lout, double *cphi, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_gather, dim3(nblk(n)), dim3(kBS), 0, s, lin, n, slot, slot2u, uphi, c,
-                       lout, cphi);
     return hipGetLastError();
 }
 

@@ -129,7 +129,8 @@ size_t scan_tmp_bytes(int64_t n) {
 hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *total_dev, void *tmp,
                           hipStream_t s) {
     if (n <= 0) {
-        if (total_dev) return hipMemsetAsync(total_dev, 0, sizeof(int32_t), s);
+        // a fill kernel, not a memset: a captured pass holds no memset node
+        if (total_dev) return launch_fill_u32(reinterpret_cast<uint32_t *>(total_dev), 0u, 1, s);
         return hipSuccess;
     }
     int64_t nb = (n + kTile - 1) / kTile;

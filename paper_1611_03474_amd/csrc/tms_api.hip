@@ -82,9 +82,6 @@ void PinBuf::release() {
     cap = 0;
 }
 
-hipError_t launch_edge_count(const tms_leaf *leaves, int64_t n, unsigned long long *count,
-                             hipStream_t s);
-
 static hipEvent_t ev_get(tms_ctx *ctx) {
     if (!ctx->ev_pool.empty()) {
         hipEvent_t e = ctx->ev_pool.back();
@@ -351,8 +348,9 @@ constexpr int64_t kSliceCtr = 8192;
 
 std::atomic<uint64_t> g_cells_ids{0};
 
-// Largest dense bitmap (bits) used for corner and edge de-duplication; larger
-// lattices fall back to hashing.  8 GiB.
+// Largest dense bitmap (bits) used for corner and edge de-duplication, 8 GiB
+// (the finest lattice of a box about 1,000 h_min per axis); a pass on a larger
+// lattice is refused.
 constexpr double kMaxBitmapBits = 68719476736.0;
 
 // phi at m points of `pts` (with the FAST-exponential guard); returns the
@@ -408,7 +406,6 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
     ctx->corner_cells = cells->id;
     ctx->corner_dense = n <= 0;  // an empty pass has a (trivially) dense corner set
     if (n <= 0) return TMS_OK;
-    const int64_t ncand = 8 * n;
     {
         // dense bitmap over the finest lattice of every conformation (4x4x4
         // point blocks per word, one block of words per conformation) when
@@ -454,50 +451,9 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
             return TMS_OK;
         }
     }
-    // otherwise: open-addressing hash on the corner keys
-    if (ncand >= (int64_t)0x7FFFFFFF)
-        return fail(ctx, TMS_E_INVALID, "too many leaves for hashed corners (%lld)", (long long)n);
-    const int64_t hcap = next_pow2(2 * ncand);
-    HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
-    HIPCK(ctx->hown.ensure(sizeof(uint32_t) * (size_t)hcap));
-    HIPCK(ctx->slot.ensure(sizeof(uint32_t) * (size_t)ncand));
-    HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)ncand));
-    HIPCK(ctx->scan_a.ensure(sizeof(int32_t) * (size_t)ncand));
-    {
-        TimedScope ts_(ctx, TMS_T_CORNER);
-        HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
-        HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
-        HIPCK(launch_corner_insert(leaves, n, g.K, ctx->hkeys.as<uint64_t>(),
-                                   ctx->hown.as<uint32_t>(), hcap, ctx->slot.as<uint32_t>(), s));
-        HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
-                                 ctx->flags.as<int32_t>(), s));
-    }
-    int64_t nu = 0;
-    int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), ncand, &nu);
-    if (rc) return rc;
-    HIPCK(ctx->uniq.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(nu, 1)));
-    HIPCK(ctx->uphi.ensure(sizeof(double) * (size_t)std::max<int64_t>(nu, 1)));
-    HIPCK(ctx->uconf.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nu, 1)));
-    // slot -> unique index map
-    HIPCK(ctx->lc.ensure(sizeof(uint32_t) * (size_t)hcap));
-    uint32_t *slot2u = ctx->lc.as<uint32_t>();
-    {
-        TimedScope ts_(ctx, TMS_T_CORNER);
-        HIPCK(launch_corner_unique(leaves, ncand, g.K, gt, ctx->flags.as<int32_t>(),
-                                   ctx->scan_a.as<int32_t>(), ctx->slot.as<uint32_t>(),
-                                   ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), slot2u, s));
-    }
-    rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), nu,
-                        ctx->uphi.as<double>(), nullptr, n_guard, kCornerBand);
-    if (rc) return rc;
-    {
-        TimedScope ts_(ctx, TMS_T_CORNER);
-        HIPCK(launch_corner_gather(leaves, n, ctx->slot.as<uint32_t>(), slot2u,
-                                   ctx->uphi.as<double>(), g.c, leaves_out, cphi, s));
-    }
-    *n_corners = nu;
-    ctx->n_corners = nu;
-    return TMS_OK;
+    return fail(ctx, TMS_E_INVALID,
+                "the finest lattice needs %.4g bits of corner bitmap (limit %.4g): split the "
+                "atoms into smaller boxes", 64.0 * (double)cells->corner_words, kMaxBitmapBits);
 }
 
 // Chunks of <= 64 consecutive entries of one root over q (or over the
@@ -662,8 +618,8 @@ int32_t tms_destroy(tms_ctx *ctx) {
     }
     tms::DevBuf *bufs[] = {&ctx->leaves, &ctx->corner_phi, &ctx->verts, &ctx->q[0], &ctx->q[1],
                            &ctx->qmeta, &ctx->abuf, &ctx->ebuf, &ctx->dec, &ctx->scan_a,
-                           &ctx->scan_b, &ctx->scan_c, &ctx->flags, &ctx->idx, &ctx->hkeys,
-                           &ctx->hown, &ctx->slot, &ctx->uniq, &ctx->uphi, &ctx->uguard, &ctx->lc,
+                           &ctx->scan_b, &ctx->scan_c, &ctx->flags, &ctx->idx, &ctx->uniq,
+                           &ctx->uphi, &ctx->uguard,
                            &ctx->ctmp, &ctx->counters, &ctx->hidx, &ctx->chunks,
                            &ctx->chunks2, &ctx->runs};
     for (auto *b : bufs) b->release();
@@ -1869,42 +1825,9 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
         ctx->edge_dense = true;
         ctx->edge_lat = etab[0];
     } else if (n > 0) {
-        if (12 * n >= (int64_t)0x7FFFFFFF)
-            return fail(ctx, TMS_E_INVALID, "too many leaves for hashed edges");
-        unsigned long long *ctr = ctx->counters.as<unsigned long long>();
-        HIPCK(hipMemsetAsync(ctr, 0, 8, s));
-        {
-            TimedScope ts_(ctx, TMS_T_EXTRACT);
-            HIPCK(launch_edge_count(lv, n, ctr, s));
-        }
-        unsigned long long ncr = 0;
-        HIPCK(d2h(ctx, &ncr, ctr, 1));
-        const int64_t ncand = 12 * n;
-        const int64_t hcap = next_pow2(2 * (int64_t)ncr + 2);
-        HIPCK(ctx->hkeys.ensure(sizeof(uint64_t) * (size_t)hcap));
-        HIPCK(ctx->hown.ensure(sizeof(uint32_t) * (size_t)hcap));
-        HIPCK(ctx->slot.ensure(sizeof(uint32_t) * (size_t)ncand));
-        HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)ncand));
-        HIPCK(ctx->scan_b.ensure(sizeof(int32_t) * (size_t)ncand));
-        {
-            TimedScope ts_(ctx, TMS_T_EXTRACT);
-            HIPCK(launch_fill_u64(ctx->hkeys.as<uint64_t>(), ~0ull, hcap, s));
-            HIPCK(launch_fill_u32(ctx->hown.as<uint32_t>(), 0xFFFFFFFFu, hcap, s));
-            HIPCK(launch_edge_insert(lv, n, g.K, ctx->hkeys.as<uint64_t>(),
-                                     ctx->hown.as<uint32_t>(), hcap, ctx->slot.as<uint32_t>(), s));
-            HIPCK(launch_owner_flags(ctx->slot.as<uint32_t>(), ctx->hown.as<uint32_t>(), ncand,
-                                     ctx->flags.as<int32_t>(), s));
-        }
-        int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_b.as<int32_t>(), ncand, &nv);
-        if (rc) return rc;
-        HIPCK(ctx->verts.ensure(sizeof(tms_vertex) * (size_t)std::max<int64_t>(nv, 1)));
-        TimedScope ts_(ctx, TMS_T_EXTRACT);
-        HIPCK(launch_edge_emit(cells->gtab.as<Grid>(), lv, cphi, ncand, ctx->flags.as<int32_t>(),
-                               ctx->scan_b.as<int32_t>(), ctx->verts.as<tms_vertex>(), s));
-        // hashed edges come out in leaf order: per-conformation offsets only
-        // for a single conformation
-        if (nconf == 1) ctx->vert_off = {0, nv};
-        else ctx->vert_off.clear();
+        return fail(ctx, TMS_E_INVALID,
+                    "the edge lattices need %.4g bits of bitmap (limit %.4g): split the atoms "
+                    "into smaller boxes", std::max(ebits, 64.0 * (double)lwords), kMaxBitmapBits);
     }
     ctx->n_verts = nv;
     ctx->verts_kept = !vdirect;
@@ -1920,6 +1843,59 @@ int32_t tms_extract_cube_vertices(tms_ctx *ctx, const tms_cells *cells, const tm
     if (nv > 0 && !vdirect)
         HIPCK(hipMemcpyAsync(out, ctx->verts.p, sizeof(tms_vertex) * (size_t)nv,
                              hipMemcpyDeviceToDevice, s));
+    HIPCK(hipStreamSynchronize(s));
+    return TMS_OK;
+}
+
+int32_t tms_stage2_points(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
+                          const double *corner_phi, tms_s2point *out, int64_t cap,
+                          int64_t *n_out, int64_t *n_degenerate) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || n < 0 || !n_out || (n > 0 && (!leaves || !corner_phi)) || cap < 0)
+        return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_stage2_points");
+    HIPCK(hipSetDevice(ctx->device));
+    *n_out = 0;
+    if (n_degenerate) *n_degenerate = 0;
+    if (n == 0) return TMS_OK;
+    hipStream_t s = ctx->stream;
+    const Grid *gt = cells->gtab.as<Grid>();
+    // leaves in chunks whose record counts (<= 12 per leaf) fit int32 offsets
+    constexpr int64_t kChunk = (int64_t)1 << 27;
+    HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)n));
+    HIPCK(ctx->scan_a.ensure(sizeof(int32_t) * (size_t)n));
+    unsigned long long *ndeg = ctx->counters.as<unsigned long long>() + 112;
+    HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(ndeg), 0ull, 1, s));
+    std::vector<int64_t> base;
+    int64_t total = 0;
+    for (int64_t q0 = 0; q0 < n; q0 += kChunk) {
+        const int64_t nq = std::min(kChunk, n - q0);
+        {
+            TimedScope ts_(ctx, TMS_T_STAGE2);
+            HIPCK(launch_s2_count(gt, leaves + q0, corner_phi + 8 * q0, nq,
+                                  ctx->flags.as<int32_t>() + q0, ndeg, s));
+        }
+        int64_t t = 0;
+        int32_t rc = scan_total(ctx, ctx->flags.as<int32_t>() + q0, ctx->scan_a.as<int32_t>() + q0,
+                                nq, &t);
+        if (rc) return rc;
+        base.push_back(total);
+        total += t;
+    }
+    unsigned long long nd = 0;
+    HIPCK(d2h(ctx, &nd, ndeg, 1));
+    *n_out = total;
+    if (n_degenerate) *n_degenerate = (int64_t)nd;
+    if (!out) return TMS_OK;
+    if (cap < total)
+        return fail(ctx, TMS_E_CAPACITY, "stage-two output needs %lld records, capacity %lld",
+                    (long long)total, (long long)cap);
+    // leaf indices in the records count from the start of the whole list
+    for (size_t k = 0; k * kChunk < (size_t)n; ++k) {
+        const int64_t q0 = (int64_t)k * kChunk, nq = std::min(kChunk, n - q0);
+        TimedScope ts_(ctx, TMS_T_STAGE2);
+        HIPCK(launch_s2_emit(gt, leaves + q0, corner_phi + 8 * q0, nq,
+                             ctx->scan_a.as<int32_t>() + q0, out + base[k], q0, s));
+    }
     HIPCK(hipStreamSynchronize(s));
     return TMS_OK;
 }
@@ -1972,7 +1948,7 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
     if (ctx->corner_cells != cells->id || !ctx->corner_dense)
         return fail(ctx, TMS_E_INVALID,
                     "no kept corners of an adaptive pass on these cells (run "
-                    "tms_partition_estimate on them first; the hashed corner path has no adjoint)");
+                    "tms_partition_estimate on them first; the uniform grid has no adjoint)");
     if (dphi && m != ctx->n_corners)
         return fail(ctx, TMS_E_INVALID, "dphi holds %lld values, %lld corners are kept",
                     (long long)m, (long long)ctx->n_corners);
@@ -1980,7 +1956,7 @@ int32_t tms_backward(tms_ctx *ctx, const tms_cells *cells, const double *dphi, i
         if (ctx->edge_cells != cells->id || !ctx->edge_dense)
             return fail(ctx, TMS_E_INVALID,
                         "no kept edge points of these cells (run tms_extract_cube_vertices on the "
-                        "kept leaves first; the hashed edge path has no adjoint)");
+                        "kept leaves first)");
         if (nv != ctx->n_verts)
             return fail(ctx, TMS_E_INVALID, "dt holds %lld values, %lld edge points are kept",
                         (long long)nv, (long long)ctx->n_verts);
@@ -2105,6 +2081,8 @@ int32_t tms_graph_capture_into(tms_ctx *ctx, const tms_cells *cells, double marg
     }
     G.cells_id = cells->id;
     G.gh = cells->gh;
+    G.n_atoms = cells->n;
+    G.atom_off = cells->atom_off;
     cells_buffers(cells, G.cells_buf);
     return TMS_OK;
 }
@@ -2119,15 +2097,19 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
     if (!cells || std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
         return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
     if (cells->id != G.cells_id) {
-        // a rebuild keeps the graph valid when geometry and buffers are unchanged
+        // a rebuild keeps the graph valid when geometry, atom counts and
+        // buffers are unchanged (the captured launches and the projection
+        // table's rows are sized by the atom count)
         const void *p[kCellsBufs];
         cells_buffers(cells, p);
         bool same = cells->gh.size() == G.gh.size() &&
-                    memcmp(cells->gh.data(), G.gh.data(), sizeof(Grid) * G.gh.size()) == 0;
+                    memcmp(cells->gh.data(), G.gh.data(), sizeof(Grid) * G.gh.size()) == 0 &&
+                    cells->n == G.n_atoms && cells->atom_off == G.atom_off;
         for (int k = 0; k < kCellsBufs && same; ++k) same = p[k] == G.cells_buf[k];
         if (!same)
             return fail(ctx, TMS_E_INVALID,
-                        "cells changed geometry or buffers since the capture; capture again");
+                        "cells changed geometry, atom count or buffers since the capture; "
+                        "capture again");
     }
     HIPCK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;

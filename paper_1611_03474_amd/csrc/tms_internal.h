@@ -163,6 +163,8 @@ struct tms_graph_state {
     uint64_t cells_id = 0;          // cells build the graph was recorded for
     const void *cells_buf[kCellsBufs] = {};  // their device buffers (a rebuild must keep them)
     std::vector<tms::Grid> gh;      // and their geometry
+    int64_t n_atoms = 0;            // and atom count and per-conformation offsets
+    std::vector<int64_t> atom_off;  // (launch sizes and the projection table's rows)
     int nlev = 0, nconf = 1;
     int64_t qcap[TMS_MAX_LEVELS + 1] = {}, lcap = 0, ucap = 0, vcap = 0, ewords = 0, lwords = 0;
     int64_t nslices[TMS_MAX_LEVELS] = {}, slice[TMS_MAX_LEVELS] = {};
@@ -213,8 +215,8 @@ struct tms_ctx {
     tms::DevBuf chist;
     tms_graph_state graph;
     // workspace (grow-only)
-    tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, hkeys, hown,
-        slot, uniq, uphi, uguard, lc, ctmp, hidx, chunks, chunks2, runs, bmap, bmcnt, bmoff;
+    tms::DevBuf q[2], qmeta, abuf, ebuf, dec, scan_a, scan_b, scan_c, flags, idx, uniq, uphi,
+        uguard, ctmp, hidx, chunks, chunks2, runs, bmap, bmcnt, bmoff;
     // small device counters (u64 slots): [0,64) striped pair counts,
     // [72,77) decision histogram, 80 surface count, 96 adjoint consistency
     // flag, 100 scan total, 104 and 105 a level's leaf and child totals;
@@ -294,6 +296,13 @@ hipError_t launch_adjoint_atoms(const Grid &g, int precision, const Lat &lat, co
                                 int64_t n, const double *ax, const double *ay, const double *az,
                                 const double *aw, const double *ar, const int32_t *aidx,
                                 double *out, hipStream_t s);
+
+// k_stage2.hip -- per-leaf record counts (and the degenerate total, added
+// to *ndeg), then the records at the scanned offsets
+hipError_t launch_s2_count(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
+                           int32_t *cnt, unsigned long long *ndeg, hipStream_t s);
+hipError_t launch_s2_emit(const Grid *gt, const tms_leaf *leaves, const double *cphi, int64_t n,
+                          const int32_t *off, tms_s2point *out, int64_t leaf0, hipStream_t s);
 
 // k_graph.hip
 hipError_t launch_slice_counts(const int32_t *n, int64_t S, int nslices, int32_t *ns,
@@ -412,16 +421,6 @@ hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const 
                                     const int32_t *list, int64_t m, const int32_t *cell_start,
                                     const double4 *xw, double *phi, double *grad, hipStream_t s,
                                     const int32_t *nd = nullptr);
-hipError_t launch_corner_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
-                                uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
-hipError_t launch_owner_flags(const uint32_t *slot, const uint32_t *hown, int64_t ncand,
-                              int32_t *flags, hipStream_t s);
-hipError_t launch_corner_unique(const tms_leaf *leaves, int64_t ncand, int K, const Grid *gt,
-                                const int32_t *flags, const int32_t *off, const uint32_t *slot,
-                                double *upts, int32_t *uconf, uint32_t *slot2u, hipStream_t s);
-hipError_t launch_corner_gather(const tms_leaf *leaves_in, int64_t n, const uint32_t *slot,
-                                const uint32_t *slot2u, const double *uphi, double c,
-                                tms_leaf *leaves_out, double *corner_phi, hipStream_t s);
 hipError_t launch_uniform_leaves(const Grid &g, tms_leaf *leaves, int64_t n, hipStream_t s);
 hipError_t launch_uniform_points(const Grid &g, double *pts, int64_t m, hipStream_t s);
 hipError_t launch_uniform_gather(const Grid &g, const double *uphi, double c, tms_leaf *leaves,
@@ -471,10 +470,5 @@ hipError_t launch_edge_write(const Grid *gt, const tms_leaf *leaves, const doubl
                              const uint16_t *own, tms_vertex *out, hipStream_t s,
                              const int64_t *nd = nullptr, int64_t vcap = 0,
                              unsigned *ovf = nullptr);
-hipError_t launch_edge_insert(const tms_leaf *leaves, int64_t n, int K, uint64_t *hkeys,
-                              uint32_t *hown, int64_t hcap, uint32_t *slot, hipStream_t s);
-hipError_t launch_edge_emit(const Grid *gt, const tms_leaf *leaves, const double *corner_phi,
-                            int64_t ncand, const int32_t *flags, const int32_t *off,
-                            tms_vertex *out, hipStream_t s);
 
 }  // namespace tms

@@ -31,7 +31,7 @@ assert LEAF_DTYPE.itemsize == 20 and VERTEX_DTYPE.itemsize == 40
 
 
 T_SLOTS = ["build", "estimate", "decide", "guard", "compact", "corner", "phi", "extract",
-           "tiled", "backward", "table", "grouped"]
+           "tiled", "backward", "table", "grouped", "stage2"]
 
 
 class Timing(C.Structure):
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
     L.tms_free_cells.argtypes = [_VP, _VP]
     L.tms_eval_phi.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, C.POINTER(i64)]
     L.tms_eval_phi_noalloc.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, C.POINTER(i64)]
+    L.tms_stage2_points.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(i64),
+                                    C.POINTER(i64)]
     L.tms_partition_estimate.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64), _VP,
                                          C.POINTER(Stats)]
     L.tms_get_leaves.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
@@ -134,7 +136,7 @@ def load_library(path: str = LIB_PATH):
     L.tms_debug_fast_exp.argtypes = [_VP, _VP, i64, _VP]
     for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
-              "tms_eval_phi_noalloc",
+              "tms_eval_phi_noalloc", "tms_stage2_points",
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
               "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
@@ -367,6 +369,25 @@ class Context:
             self._check(rc)
         return out[:n.value]
 
+    def stage2_points(self, cells: Cells, leaves, corner_phi, cap: int | None = None):
+        """tms_stage2_points: fold segments and critical points (Section 2.3)
+        of the SURFACE leaves.  Returns (records uint8 tensor [P, 32],
+        degenerate count)."""
+        t = self._torch
+        n = leaves.shape[0]
+        cnt = C.c_int64()
+        nd = C.c_int64()
+        if cap is None:
+            self._check(self.lib.tms_stage2_points(self.h, cells.handle, _VP(_ptr(leaves)), n,
+                                                   _VP(_ptr(corner_phi)), None, 0,
+                                                   C.byref(cnt), C.byref(nd)))
+            cap = cnt.value
+        out = t.empty((max(cap, 1), 32), dtype=t.uint8, device=self.device)
+        self._check(self.lib.tms_stage2_points(self.h, cells.handle, _VP(_ptr(leaves)), n,
+                                               _VP(_ptr(corner_phi)), _VP(out.data_ptr()), cap,
+                                               C.byref(cnt), C.byref(nd)))
+        return out[:cnt.value], int(nd.value)
+
     def get_vertices(self):
         """Vertices [V, 40] of the last extraction."""
         t = self._torch
@@ -536,6 +557,15 @@ class Context:
 
 def leaves_to_numpy(leaves) -> np.ndarray:
     return leaves.cpu().numpy().reshape(-1).view(LEAF_DTYPE)
+
+
+S2_DTYPE = np.dtype([("leaf", "<i4"), ("kind", "u1"), ("axis", "u1"), ("root", "u1"),
+                     ("pad", "u1"), ("x", "<f8"), ("y", "<f8"), ("z", "<f8")])
+S2_FOLD, S2_CRITICAL = 0, 1
+
+
+def s2_to_numpy(recs) -> np.ndarray:
+    return np.frombuffer(recs.cpu().numpy().tobytes(), dtype=S2_DTYPE)
 
 
 def vertices_to_numpy(verts) -> np.ndarray:

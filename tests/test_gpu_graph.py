@@ -167,3 +167,27 @@ def test_graph_replay_on_rebuilt_cells(ctx):
         ctx.free_cells(cells)
     finally:
         ctx.set_tuning(**base)
+
+
+def test_graph_refuses_rebuild_with_other_atom_count(ctx):
+    # cells first built with one atom more, then rebuilt in place without it
+    # and captured: a rebuild back to the larger set keeps the geometry (the
+    # extra atom sits inside the box, with the smallest radius) and the
+    # buffers (they only grow), but the captured launches and the projection
+    # table's rows were sized by the smaller atom count, so the replay is
+    # refused; the captured set itself replays
+    atoms = synth.globule(400, 4100)
+    extra = np.concatenate([atoms, [[*atoms[:, :3].mean(axis=0), atoms[:, 3].min()]]], axis=0)
+    p = tms.make_params(D=0.9, tau=1e-3, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells(extra, p)
+    cells = ctx.build_cells(atoms, p, cells)
+    L0, _, V0, _ = _eager(ctx, cells)
+    ctx.graph_capture(cells, margin=1.25)
+    nl, nv, _ = ctx.graph_launch(cells)
+    assert nl == L0.shape[0] and nv == V0.shape[0]
+    big = ctx.build_cells(extra, p, cells)
+    assert np.array_equal(big.origin, cells.origin) and np.array_equal(big.dims, cells.dims)
+    with pytest.raises(tms.TmsError) as ei:
+        ctx.graph_launch(cells)
+    assert ei.value.code == tms.TMS_E_INVALID and "atom count" in str(ei.value)
+    ctx.free_cells(cells)
