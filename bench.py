@@ -40,11 +40,43 @@ TRAFFIC_TILED = 12.16e9
 
 # algorithmic work per unit
 FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
-FLOP_PER_PHI_PAIR = 14   # phi + grad per in-range (point, atom) pair, excl. exp
+# phi at a corner, per in-range (point, atom) pair: 8 VALU lane-ops (3 sub,
+# 3 FMA for the squared distance, 1 FMA for the scaled exponent, 1 add) plus
+# one single-precision exponential, which issues at a quarter of the VALU
+# rate (4 lane-op slots)
+OPS_PER_PHI_PAIR = 8 + 4
+# VALU lane-op issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 39.3
+# FP64 flops the nested-SVD bound executes per hard cube, from the
+# SQ_INSTS_VALU_FLOPS_FP64 counter over the pass's k_bound launches divided by
+# the hard cubes (profiles/bound_assembly110k_counters.md); None until counted
+FLOP_PER_HARD_CUBE = None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(fn, steps):
+    """Wall time of each of `steps` calls of fn (each ends synchronised);
+    returns (list of ms, the last result)."""
+    import torch
+    out, r = [], None
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) * 1e3)
+    return out, r
+
+
+def spread(ms):
+    import numpy as np
+    a = np.asarray(ms)
+    return {"mean": float(a.mean()), "median": float(np.median(a)), "min": float(a.min()),
+            "max": float(a.max()), "p10": float(np.percentile(a, 10)),
+            "p90": float(np.percentile(a, 90)), "n": int(len(a))}
 
 
 def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
@@ -70,17 +102,28 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
     torch.cuda.synchronize()
     ctx.set_timing(True)
     ctx.get_timing(reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        nl, nv, s = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    step_ms, (nl, nv, s) = timed_steps(step, steps)
     tm = ctx.get_timing(reset=True)
     ctx.set_timing(False)
     sd = s.as_dict()
-    ms = (t1 - t0) * 1e3 / steps
     per_step = {k: {"ms": v["ms"] / steps, "launches": v["launches"] / steps}
                 for k, v in tm.items()}
+    # algorithmic work of the corner values: the pairs phi sums over the
+    # pass's unique corners (kept in ctx)
+    cxyz, _ = ctx.get_corners()
+    phi_pairs = ctx.debug_phi_pairs(cells, cxyz)
+    del cxyz
+    # stage-two points (Section 2.3) of the pass's leaves, outside the step
+    ctx.set_timing(True)
+    ctx.get_timing(reset=True)
+    s2_ms, (s2rec, s2deg) = timed_steps(lambda: ctx.stage2_points(cells, lb[:nl], cb[:nl]), 3)
+    s2tm = ctx.get_timing(reset=True)
+    ctx.set_timing(False)
+    stage2 = {"records": int(s2rec.shape[0]), "degenerate": s2deg,
+              "ms_median": spread(s2_ms)["median"],
+              "device_ms": s2tm["stage2"]["ms"] / 3,
+              "leaves_per_s": nl / (spread(s2_ms)["median"] * 1e-3)}
+    del s2rec
     # the same pass replayed from a captured graph (build eager, rest one
     # graph) that writes its results into lb, cb, vb
     ctx.graph_capture(cells, margin=1.1, leaves=lb, cphi=cb, verts=vb)
@@ -91,16 +134,12 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
 
     for _ in range(warmup):
         gstep()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        gnl, gnv, _ = gstep()
-    torch.cuda.synchronize()
-    gms = (time.perf_counter() - t0) * 1e3 / steps
+    g_ms, (gnl, gnv, _) = timed_steps(gstep, steps)
     assert gnl == nl and gnv == nv
     ctx.free_cells(cells)
-    return dict(ms_per_step=ms, stats=sd, n_leaves=nl, n_vertices=nv, timing=per_step,
-                graph_ms_per_step=gms)
+    return dict(ms_per_step=spread(step_ms)["mean"], step_ms=spread(step_ms), stats=sd,
+                n_leaves=nl, n_vertices=nv, timing=per_step, phi_pairs=phi_pairs,
+                stage2=stage2, graph_ms_per_step=spread(g_ms)["mean"], graph_step_ms=spread(g_ms))
 
 
 def run_adjoint(ctx, tms, steps, warmup):
@@ -173,12 +212,8 @@ def run_batch(ctx, tms, confs, steps, warmup):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        nl, nv, s_ = step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    b_ms, (nl, nv, s_) = timed_steps(step, steps)
+    ms = spread(b_ms)["mean"]
     sd = s_.as_dict()
     # one captured graph for the whole batched pass, writing into lb, cb, vb
     ctx.graph_capture(cells, margin=1.1, leaves=lb, cphi=cb, verts=vb)
@@ -189,12 +224,8 @@ def run_batch(ctx, tms, confs, steps, warmup):
 
     for _ in range(warmup):
         gstep()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        gnl, gnv, _ = gstep()
-    torch.cuda.synchronize()
-    gms = (time.perf_counter() - t0) * 1e3 / steps
+    bg_ms, (gnl, gnv, _) = timed_steps(gstep, steps)
+    gms = spread(bg_ms)["mean"]
     assert gnl == nl and gnv == nv
     ctx.free_cells(cells)
 
@@ -220,35 +251,65 @@ def run_batch(ctx, tms, confs, steps, warmup):
     est = int(sum(sd["n_est"]))
     return {"workload": w.name, "conformations": len(confs), "atoms": int(off[-1]),
             "leaves": int(nl), "vertices": int(nv), "cubes_estimated": est,
-            "ms_per_pass": ms, "cubes_per_s": est / (ms * 1e-3),
-            "graph_ms_per_pass": gms, "graph_cubes_per_s": est / (gms * 1e-3),
+            "ms_per_pass": ms, "pass_ms": spread(b_ms), "cubes_per_s": est / (ms * 1e-3),
+            "graph_ms_per_pass": gms, "graph_pass_ms": spread(bg_ms),
+            "graph_cubes_per_s": est / (gms * 1e-3),
             "tuning": tuning, "autotune_best_ms": tune_ms, "autotune_passes": tune_n,
             "loop_fp32g_ms": loop32, "loop_fp64_ms": loop64,
             "speedup_vs_loop_fp32g": loop32 / ms, "speedup_vs_loop_fp64": loop64 / ms}
 
 
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_usable": affinity,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(atoms, w, n_glob=4):
     """FP64 oracle on a bounded sample: the first n_glob globules of the
-    assembly with their hydrogens (about n_glob/20 of the workload)."""
+    assembly with their hydrogens (about n_glob/20 of the workload), on every
+    thread the process may use; beside it one thread on a 1,000-atom globule
+    (context for the paper's serial CPU)."""
     import oracle
-    from paper_1611_03474_amd import workloads
+    from paper_1611_03474_amd import synth, workloads
     sample = workloads.assembly_slice(atoms, n_glob)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    kw = dict(c=w.c, tau=w.tau, h0=w.h0, h_min=w.h_min, pad=w.pad, eps_cut=w.eps_cut)
     t0 = time.perf_counter()
-    r = oracle.partition(sample, w.D, c=w.c, tau=w.tau, h0=w.h0, h_min=w.h_min, pad=w.pad,
-                         eps_cut=w.eps_cut, nthreads=threads)
+    r = oracle.partition(sample, w.D, nthreads=threads, **kw)
     dt = time.perf_counter() - t0
+    small = synth.globule(1000, 1006)
+    t0 = time.perf_counter()
+    r1 = oracle.partition(small, w.D, nthreads=1, **kw)
+    dt1 = time.perf_counter() - t0
     return {"value": r.cubes_estimated / dt, "unit": "cubes/s", "cores": threads,
             "kind": "oracle",
             "sample": "globules 0-%d of the assembly with their hydrogens (%d atoms, %d cubes "
-                      "estimated, %.1f s wall)" % (n_glob - 1, len(sample), r.cubes_estimated, dt)}
+                      "estimated, %.1f s wall on %d threads)"
+                      % (n_glob - 1, len(sample), r.cubes_estimated, dt, threads),
+            "host": host_info(),
+            "single_thread": {"sample": "1,000-atom globule (seed 1006), same parameters",
+                              "atoms": len(small), "cubes_estimated": r1.cubes_estimated,
+                              "s": dt1, "cubes_per_s": r1.cubes_estimated / dt1}}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
@@ -297,32 +358,57 @@ def main():
         log("  %.2f ms/step" % f64["ms_per_step"])
 
     def rates(r):
-        st = r["stats"]
+        st, tmr = r["stats"], r["timing"]
+        # phi at the corners: the kernel plus, in FP32+guard, the
+        # double-precision recompute of the guarded corners
+        phi_ms = tmr["phi"]["ms"] + tmr["guard"]["ms"]
         return {"cubes_per_s": st["cubes_estimated"] / (r["ms_per_step"] * 1e-3),
-                "phi_evals_per_s": st["n_corners"] / (r["timing"]["phi"]["ms"] * 1e-3)
-                if r["timing"]["phi"]["ms"] > 0 else None}
+                "phi_evals_per_s": st["n_corners"] / (phi_ms * 1e-3) if phi_ms > 0 else None,
+                "phi_pairs_per_s": r["phi_pairs"] / (phi_ms * 1e-3) if phi_ms > 0 else None}
 
     r32 = rates(f32)
     st = f32["stats"]
+    tm = f32["timing"]
+
+    def launch_avg(slot):
+        n = max(tm[slot]["launches"], 1)
+        return tm[slot]["ms"] / n, n
+
     # dominant kernel: the wave-per-chunk tensor estimate on the two deep
     # levels.  Its rank-one updates run in FP64 in both modes, so the FP64
     # vector peak applies; algorithmic work = in-range (cube, atom) pairs at
     # those levels x FLOP_PER_PAIR.
-    tm = f32["timing"]
     deep_pairs = sum(st["n_pairs_lvl"][2:4])
-    launches = tm["tiled"]["launches"]
-    avg_launch_s = tm["tiled"]["ms"] * 1e-3 / max(launches, 1)
-    work_per_launch = deep_pairs * FLOP_PER_PAIR / max(launches, 1)
-    achieved = work_per_launch / avg_launch_s / 1e12
+    t_ms, t_n = launch_avg("tiled")
+    achieved = deep_pairs / t_n * FLOP_PER_PAIR / (t_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_estimate_tiled (levels 2-3)",
                 "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": TRAFFIC_TILED if w.name == "assembly110k" else None,
                 "traffic_unit": "HBM bytes per launch",
                 "work_per_unit": "%d flop per in-range (cube, atom) pair" % FLOP_PER_PAIR,
-                "units_per_launch": deep_pairs / max(launches, 1),
-                "launches_per_step": launches,
-                "avg_launch_ms": avg_launch_s * 1e3}
+                "units_per_launch": deep_pairs / t_n, "launches_per_step": t_n,
+                "avg_launch_ms": t_ms}
+    # the other kernels with a large share of the pass
+    p_ms, p_n = launch_avg("phi")
+    phi_ach = f32["phi_pairs"] / p_n * OPS_PER_PHI_PAIR / (p_ms * 1e-3) / 1e12
+    rooflines = [roofline, {
+        "bound": "alu", "kernel": "k_phi_points<FAST> (corner values)",
+        "achieved": phi_ach, "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-op/s",
+        "frac": phi_ach / PEAK_VALU_TOPS, "traffic": None,
+        "work_per_unit": "%d lane-ops per in-range (point, atom) pair (8 VALU + one "
+                         "quarter-rate exponential)" % OPS_PER_PHI_PAIR,
+        "units_per_launch": f32["phi_pairs"] / p_n, "avg_launch_ms": p_ms}]
+    b_ms, b_n = launch_avg("decide")
+    if FLOP_PER_HARD_CUBE:
+        b_ach = st["n_bound"] * FLOP_PER_HARD_CUBE / (tm["decide"]["ms"] * 1e-3) / 1e12
+        rooflines.append({
+            "bound": "alu", "kernel": "k_bound (nested-SVD bound of the hard cubes)",
+            "achieved": b_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": b_ach / PEAK_FP64_TFLOPS, "traffic": None,
+            "work_per_unit": "%d FP64 flop per hard cube (executed, from counters)"
+                             % FLOP_PER_HARD_CUBE,
+            "units_per_launch": st["n_bound"] / b_n, "avg_launch_ms": b_ms})
 
     out = {
         "metric": "cubes estimated/sec and phi evals/sec at 100k atoms, FP32+guard vs FP64",
@@ -340,29 +426,38 @@ def main():
         "config": {"workload": w.name, "description": w.description, "atoms": int(len(atoms)),
                    "D": w.D, "c": w.c, "tau": w.tau, "h0": w.h0, "h_min": w.h_min,
                    "precision": "fp32+fp64 guard"},
+        "step_ms": f32["step_ms"],
         "phi_evals_per_s": r32["phi_evals_per_s"],
-        "graph_ms_per_step": f32["graph_ms_per_step"],
+        "phi_pairs": f32["phi_pairs"], "phi_pairs_per_s": r32["phi_pairs_per_s"],
+        "graph_ms_per_step": f32["graph_ms_per_step"], "graph_step_ms": f32["graph_step_ms"],
         "graph_cubes_per_s": st["cubes_estimated"] / (f32["graph_ms_per_step"] * 1e-3),
         "cubes_estimated": st["cubes_estimated"],
         "per_level_estimated": st["n_est"][:4],
         "leaves": f32["n_leaves"], "surface_leaves": st["n_surface"],
         "unique_corners": st["n_corners"], "vertices": f32["n_vertices"],
         "pairs": st["n_pairs"], "bound_cubes": st["n_bound"],
-        "guard_cubes": st["guard_cubes"], "guard_points": st["guard_points"],
-        "guard_cube_fraction": st["guard_cubes"] / max(1, st["cubes_estimated"]),
+        "guard_points": st["guard_points"],
+        "guard_point_fraction": st["guard_points"] / max(1, st["n_corners"]),
         "device_ms_per_step": {k: round(v["ms"], 4) for k, v in tm.items()},
         "pairs_per_level": st["n_pairs_lvl"][:4],
         "roofline": roofline,
+        "rooflines": rooflines,
+        "stage2": f32["stage2"],
     }
     if f64 is not None:
         r64 = rates(f64)
         out["fp64"] = {"value": r64["cubes_per_s"], "ms_per_step": f64["ms_per_step"],
+                       "step_ms": f64["step_ms"],
                        "graph_ms_per_step": f64["graph_ms_per_step"],
                        "phi_evals_per_s": r64["phi_evals_per_s"],
+                       "phi_pairs_per_s": r64["phi_pairs_per_s"],
                        "device_ms_per_step": {k: round(v["ms"], 4)
                                               for k, v in f64["timing"].items()},
                        "same_leaf_count": f64["n_leaves"] == f32["n_leaves"]}
         out["speedup_fp32guard_vs_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+        # where single-precision exponentials enter: phi at the corners
+        out["speedup_phi_fp32guard_vs_fp64"] = (
+            f64["timing"]["phi"]["ms"] / (tm["phi"]["ms"] + tm["guard"]["ms"]))
     if batch_confs is not None:
         log("batch run")
         out["batch"] = run_batch(ctx, tms, batch_confs, args.steps, args.warmup)

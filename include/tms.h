@@ -118,8 +118,9 @@ typedef struct {
     int64_t n_hmin[TMS_MAX_LEVELS];   /* leaves kept at the finest level */
     int64_t n_leaves, n_surface, n_corners;
     int64_t n_bound;        /* cubes that needed the full nested-SVD bound     */
-    int64_t guard_cubes;    /* cubes recomputed in double precision            */
-    int64_t guard_points;   /* corner points recomputed in double precision    */
+    int64_t guard_cubes;    /* always 0: every partition level runs with       */
+                            /* exact exponentials (kept for the layout)        */
+    int64_t guard_points;   /* corner points recomputed with exact exponentials */
     int64_t n_pairs;        /* cube-atom pairs inside R_c (algorithmic work)   */
     int64_t n_pairs_lvl[TMS_MAX_LEVELS]; /* the same, per level           */
 } tms_stats;
@@ -543,6 +544,14 @@ int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cu
  *        perturbation of A of size band can move L and U). */
 int32_t tms_debug_bound(tms_ctx *ctx, const double *A, const double *band, int64_t n,
                         double *out);
+
+/* Debug: the number of (point, atom) pairs within R_c that phi at m points
+ * sums (the terms of eq. Gaussian1 kept by the cut-off), i.e. the
+ * algorithmic work of tms_eval_phi and of the corner values on these points.
+ *  pts device [m][3] double; *pairs host out.  Cells of one conformation.
+ * Errors: TMS_E_INVALID, TMS_E_DEVICE. */
+int32_t tms_debug_phi_pairs(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                            int64_t *pairs);
 
 /* Debug: the exponential used by TMS_PREC_FP32_GUARD, y[i] = exp(x[i]) for
  * x[i] <= 0, computed as 2^n 2^f with n, f split in double precision and 2^f

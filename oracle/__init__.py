@@ -109,6 +109,9 @@ def lib():
         L.or_partition.argtypes = [_DP, C.c_int64, C.POINTER(Params)]
         L.or_partition.restype = C.POINTER(_Result)
         L.or_free.argtypes = [C.POINTER(_Result)]
+        L.or_extract.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_uint8), _DP, C.c_int64,
+                                 C.c_double, _DP, C.c_double, C.c_int, C.c_int]
+        L.or_extract.restype = C.POINTER(_Result)
         _U8P = C.POINTER(C.c_uint8)
         L.or_stage2_cube.argtypes = [_DP, C.c_double, _DP, _U8P, _U8P, _U8P, _DP,
                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -297,6 +300,25 @@ def partition(xyzr, D, c=1.0, tau=1e-3, h0=2.0, h_min=0.25, pad=3.0, eps_cut=1e-
         lib().or_free(rp)
     if res.status != 0:
         raise ValueError("oracle rejected the input (status %d)" % res.status)
+    res.h0 = float(h0)
+    return res
+
+
+def extract(ijk, level, corner_phi, c, origin, h0, K, conf=0) -> Result:
+    """Edge intersection points (eq. intersection) of a caller's leaves with
+    their corner values (masks and classes from eq. linear1); vertices in
+    ascending key order."""
+    ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+    level = np.ascontiguousarray(level, dtype=np.uint8)
+    cp = np.ascontiguousarray(corner_phi, dtype=np.float64).reshape(-1, 8)
+    o = np.ascontiguousarray(origin, dtype=np.float64)
+    rp = lib().or_extract(ijk.ctypes.data_as(C.POINTER(C.c_int32)),
+                          level.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(cp), ijk.shape[0],
+                          float(c), _dp(o), float(h0), int(K), int(conf))
+    try:
+        res = Result(rp.contents)
+    finally:
+        lib().or_free(rp)
     res.h0 = float(h0)
     return res
 

@@ -817,6 +817,103 @@ typedef struct {
     int32_t i[3];
 } cube3;
 
+/* Edge intersection points (eq. intersection) of the SURFACE leaves of R
+ * (ijk, level, mask, cls and corner values filled in), into R's vertex
+ * arrays.  hmin: the finest lattice spacing (the unit of the edge keys). */
+static void or_extract_edges(or_result *R, double c, double h0, double hmin, int conf)
+{
+    const int64_t nl = R->n_leaves;
+    /* ---- edge intersections (eq. intersection) ----------------------------
+     * g restricted to a cube edge is linear in the edge coordinate, so the
+     * root of g = c on an edge whose end signs differ is
+     * t = (c - phi0) / (phi1 - phi0), measured from the lower end.  Edges are
+     * visited leaf by leaf (leaf order), edge by edge (axis-major; inside an
+     * axis the two other offsets with the lower axis first); an edge key that
+     * was already emitted is skipped.  The list is finally sorted by key. */
+    int64_t vcap = 1024, nv = 0;
+    R->vkey = (uint64_t *)malloc(sizeof(uint64_t) * vcap);
+    R->vt = (double *)malloc(sizeof(double) * vcap);
+    R->vxyz = (double *)malloc(sizeof(double) * 3 * vcap);
+    /* seen-set: open addressing on the edge key */
+    int64_t hcap = 1024;
+    while (hcap < 24 * (nl + 1)) hcap *= 2;
+    uint64_t *hset = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)hcap);
+    for (int64_t i = 0; i < hcap; ++i)
+        hset[i] = ~(uint64_t)0;
+    for (int64_t q = 0; q < nl; ++q) {
+        if (R->cls[q] != OR_CLS_SURFACE) continue;
+        int lev = R->level[q], sh = R->K - lev;
+        double h = h0 / (double)(1 << lev);
+        for (int axis = 0; axis < 3; ++axis)
+            for (int ab = 0; ab < 4; ++ab) {
+                int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+                int lowo = o1 < o2 ? o1 : o2, higho = o1 < o2 ? o2 : o1;
+                int off[3] = {0, 0, 0};
+                off[lowo] = ab & 1;
+                off[higho] = (ab >> 1) & 1;
+                int v0 = off[0] + 2 * off[1] + 4 * off[2];
+                int v1 = v0 + (1 << axis);
+                int b0 = (R->mask[q] >> v0) & 1, b1 = (R->mask[q] >> v1) & 1;
+                if (b0 == b1) continue;
+                int64_t X = ((int64_t)R->ijk[3 * q + 0] + off[0]) << sh;
+                int64_t Y = ((int64_t)R->ijk[3 * q + 1] + off[1]) << sh;
+                int64_t Z = ((int64_t)R->ijk[3 * q + 2] + off[2]) << sh;
+                uint64_t key = edge_key(conf, lev, axis, X, Y, Z);
+                uint64_t hsh = key * 0x9E3779B97F4A7C15ull;
+                int64_t slot = (int64_t)(hsh >> 17) & (hcap - 1);
+                int found = 0;
+                while (hset[slot] != ~(uint64_t)0) {
+                    if (hset[slot] == key) { found = 1; break; }
+                    slot = (slot + 1) & (hcap - 1);
+                }
+                if (found) continue;
+                hset[slot] = key;
+                double f0 = R->corner_phi[8 * q + v0], f1 = R->corner_phi[8 * q + v1];
+                double t = (c - f0) / (f1 - f0);
+                if (nv == vcap) {
+                    vcap *= 2;
+                    R->vkey = (uint64_t *)realloc(R->vkey, sizeof(uint64_t) * vcap);
+                    R->vt = (double *)realloc(R->vt, sizeof(double) * vcap);
+                    R->vxyz = (double *)realloc(R->vxyz, sizeof(double) * 3 * vcap);
+                }
+                R->vkey[nv] = key;
+                R->vt[nv] = t;
+                double p0[3] = {R->origin[0] + (double)X * hmin, R->origin[1] + (double)Y * hmin,
+                                R->origin[2] + (double)Z * hmin};
+                p0[axis] += t * h;
+                for (int a = 0; a < 3; ++a)
+                    R->vxyz[3 * nv + a] = p0[a];
+                ++nv;
+            }
+    }
+    free(hset);
+    R->n_vert = nv;
+    /* canonical order of the vertex list: ascending edge key */
+    {
+        int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv ? nv : 1));
+        for (int64_t i = 0; i < nv; ++i)
+            ord[i] = i;
+        sort_keys_ctx = R->vkey;
+        qsort(ord, (size_t)nv, sizeof(int64_t), cmp_by_key);
+        uint64_t *k2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nv ? nv : 1));
+        double *t2 = (double *)malloc(sizeof(double) * (size_t)(nv ? nv : 1));
+        double *x2 = (double *)malloc(sizeof(double) * 3 * (size_t)(nv ? nv : 1));
+        for (int64_t i = 0; i < nv; ++i) {
+            k2[i] = R->vkey[ord[i]];
+            t2[i] = R->vt[ord[i]];
+            for (int a = 0; a < 3; ++a)
+                x2[3 * i + a] = R->vxyz[3 * ord[i] + a];
+        }
+        free(R->vkey);
+        free(R->vt);
+        free(R->vxyz);
+        R->vkey = k2;
+        R->vt = t2;
+        R->vxyz = x2;
+        free(ord);
+    }
+}
+
 or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
 {
     or_result *R = (or_result *)calloc(1, sizeof(or_result));
@@ -1083,95 +1180,7 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
     free(uk);
     free(keys);
 
-    /* ---- edge intersections (eq. intersection) ----------------------------
-     * g restricted to a cube edge is linear in the edge coordinate, so the
-     * root of g = c on an edge whose end signs differ is
-     * t = (c - phi0) / (phi1 - phi0), measured from the lower end.  Edges are
-     * visited leaf by leaf (leaf order), edge by edge (axis-major; inside an
-     * axis the two other offsets with the lower axis first); an edge key that
-     * was already emitted is skipped.  The list is finally sorted by key. */
-    int64_t vcap = 1024, nv = 0;
-    R->vkey = (uint64_t *)malloc(sizeof(uint64_t) * vcap);
-    R->vt = (double *)malloc(sizeof(double) * vcap);
-    R->vxyz = (double *)malloc(sizeof(double) * 3 * vcap);
-    /* seen-set: open addressing on the edge key */
-    int64_t hcap = 1024;
-    while (hcap < 24 * (nl + 1)) hcap *= 2;
-    uint64_t *hset = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)hcap);
-    for (int64_t i = 0; i < hcap; ++i)
-        hset[i] = ~(uint64_t)0;
-    for (int64_t q = 0; q < nl; ++q) {
-        if (R->cls[q] != OR_CLS_SURFACE) continue;
-        int lev = R->level[q], sh = K - lev;
-        double h = h0 / (double)(1 << lev);
-        for (int axis = 0; axis < 3; ++axis)
-            for (int ab = 0; ab < 4; ++ab) {
-                int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
-                int lowo = o1 < o2 ? o1 : o2, higho = o1 < o2 ? o2 : o1;
-                int off[3] = {0, 0, 0};
-                off[lowo] = ab & 1;
-                off[higho] = (ab >> 1) & 1;
-                int v0 = off[0] + 2 * off[1] + 4 * off[2];
-                int v1 = v0 + (1 << axis);
-                int b0 = (R->mask[q] >> v0) & 1, b1 = (R->mask[q] >> v1) & 1;
-                if (b0 == b1) continue;
-                int64_t X = ((int64_t)R->ijk[3 * q + 0] + off[0]) << sh;
-                int64_t Y = ((int64_t)R->ijk[3 * q + 1] + off[1]) << sh;
-                int64_t Z = ((int64_t)R->ijk[3 * q + 2] + off[2]) << sh;
-                uint64_t key = edge_key(P->conf, lev, axis, X, Y, Z);
-                uint64_t hsh = key * 0x9E3779B97F4A7C15ull;
-                int64_t slot = (int64_t)(hsh >> 17) & (hcap - 1);
-                int found = 0;
-                while (hset[slot] != ~(uint64_t)0) {
-                    if (hset[slot] == key) { found = 1; break; }
-                    slot = (slot + 1) & (hcap - 1);
-                }
-                if (found) continue;
-                hset[slot] = key;
-                double f0 = R->corner_phi[8 * q + v0], f1 = R->corner_phi[8 * q + v1];
-                double t = (c - f0) / (f1 - f0);
-                if (nv == vcap) {
-                    vcap *= 2;
-                    R->vkey = (uint64_t *)realloc(R->vkey, sizeof(uint64_t) * vcap);
-                    R->vt = (double *)realloc(R->vt, sizeof(double) * vcap);
-                    R->vxyz = (double *)realloc(R->vxyz, sizeof(double) * 3 * vcap);
-                }
-                R->vkey[nv] = key;
-                R->vt[nv] = t;
-                double p0[3] = {R->origin[0] + (double)X * hmin, R->origin[1] + (double)Y * hmin,
-                                R->origin[2] + (double)Z * hmin};
-                p0[axis] += t * h;
-                for (int a = 0; a < 3; ++a)
-                    R->vxyz[3 * nv + a] = p0[a];
-                ++nv;
-            }
-    }
-    free(hset);
-    R->n_vert = nv;
-    /* canonical order of the vertex list: ascending edge key */
-    {
-        int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv ? nv : 1));
-        for (int64_t i = 0; i < nv; ++i)
-            ord[i] = i;
-        sort_keys_ctx = R->vkey;
-        qsort(ord, (size_t)nv, sizeof(int64_t), cmp_by_key);
-        uint64_t *k2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nv ? nv : 1));
-        double *t2 = (double *)malloc(sizeof(double) * (size_t)(nv ? nv : 1));
-        double *x2 = (double *)malloc(sizeof(double) * 3 * (size_t)(nv ? nv : 1));
-        for (int64_t i = 0; i < nv; ++i) {
-            k2[i] = R->vkey[ord[i]];
-            t2[i] = R->vt[ord[i]];
-            for (int a = 0; a < 3; ++a)
-                x2[3 * i + a] = R->vxyz[3 * ord[i] + a];
-        }
-        free(R->vkey);
-        free(R->vt);
-        free(R->vxyz);
-        R->vkey = k2;
-        R->vt = t2;
-        R->vxyz = x2;
-        free(ord);
-    }
+    or_extract_edges(R, c, h0, hmin, P->conf);
     bins_free(&bins);
     return R;
 #undef PUSH_LEAF
@@ -1572,4 +1581,39 @@ void or_stage2_free(or_s2result *R)
     free(R->pts);
     free(R->leaf_margin);
     free(R);
+}
+
+/* Edge intersection points (eq. intersection) of a caller's leaf list: leaf
+ * q is the cube origin + (ijk + [0,1]) h0 / 2^level with corner values
+ * corner_phi[8 q + v]; its corner mask and class against c follow eq.
+ * linear1 (bit v set iff the value is >= c).  K: the finest level (edge keys
+ * count in units of h0 / 2^K).  Vertices come out in ascending key order, as
+ * in or_partition.  Free with or_free. */
+or_result *or_extract(const int32_t *ijk, const uint8_t *level, const double *corner_phi,
+                      int64_t nl, double c, const double origin[3], double h0, int K, int conf)
+{
+    or_result *R = (or_result *)calloc(1, sizeof(or_result));
+    R->n_leaves = nl;
+    R->K = K;
+    for (int a = 0; a < 3; ++a)
+        R->origin[a] = origin[a];
+    size_t m = (size_t)(nl ? nl : 1);
+    R->ijk = (int32_t *)malloc(sizeof(int32_t) * 3 * m);
+    R->level = (uint8_t *)malloc(m);
+    R->reason = (uint8_t *)calloc(m, 1);
+    R->mask = (uint8_t *)malloc(m);
+    R->cls = (uint8_t *)malloc(m);
+    R->corner_phi = (double *)malloc(sizeof(double) * 8 * m);
+    memcpy(R->ijk, ijk, sizeof(int32_t) * 3 * (size_t)nl);
+    memcpy(R->level, level, (size_t)nl);
+    memcpy(R->corner_phi, corner_phi, sizeof(double) * 8 * (size_t)nl);
+    for (int64_t q = 0; q < nl; ++q) {
+        uint8_t mk = 0;
+        for (int v = 0; v < 8; ++v)
+            if (corner_phi[8 * q + v] >= c) mk |= (uint8_t)(1u << v);
+        R->mask[q] = mk;
+        R->cls[q] = (mk == 0) ? OR_CLS_OUTSIDE : (mk == 0xFF ? OR_CLS_INSIDE : OR_CLS_SURFACE);
+    }
+    or_extract_edges(R, c, h0, h0 / (double)(1 << K), conf);
+    return R;
 }

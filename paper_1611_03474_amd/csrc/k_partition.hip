@@ -308,6 +308,16 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
 // projections computed here (same lattice points, same routine).
 // ---------------------------------------------------------------------------
 
+// The tiled kernels run one wavefront per workgroup: their lanes exchange data
+// through LDS with no workgroup barrier -- a wavefront's LDS accesses execute
+// in order, so only the compiler must not move them across this point.  (A
+// workgroup barrier's fence would also wait for the global-to-LDS copies
+// still in flight, which the pipelined tiles overlap with the updates.)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 constexpr int64_t kXcdBlock = 256;  // consecutive chunks per XCD turn
 
 // Bijection of [0, n): slot v = 8 j + x (x: the XCD the slot lands on) maps
@@ -336,11 +346,20 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     const int32_t *__restrict__ root_atoms, const double *__restrict__ ax,
     const double *__restrict__ ay, const double *__restrict__ az, const double *__restrict__ aw,
     EstOut o, unsigned long long *__restrict__ pairs, ProjTab P) {
-    constexpr int W = CH * 3 * kTileIv;  // projection items of a tile
-    constexpr int NB = CH + 64;          // atom buffer (a refill adds at most 64)
+    // Two sets of WS projection items: the table rows of the next tile are
+    // copied into one set while the rank-one updates of the current tile
+    // read the other.  A tile holds as many atoms as the chunk's items fit
+    // (WS / (intervals the chunk spans on the three axes)); the atom buffer
+    // holds a tile plus one refill of at most 64.
+    constexpr int WS = CH * 16;
+    constexpr int NA = WS / 3;  // most atoms in a tile
+    // the atom buffer is a ring of NB slots (a power of two >= NA + 64)
+    constexpr int NB = (NA + 64 <= 128) ? 128 : ((NA + 64 <= 256) ? 256 : 512);
     // item w = a * per_atom + (axis offset) + interval: {a0, a1}, {a2, a3},
-    // {err, squared 1-D distance}
-    __shared__ double2 t01[W], t23[W], ted[W];
+    // {err, squared 1-D distance}; a tile's atom weights alongside
+    __shared__ double2 s0_01[WS], s0_23[WS], s0_ed[WS];
+    __shared__ double2 s1_01[WS], s1_23[WS], s1_ed[WS];
+    __shared__ double s0_w[NA], s1_w[NA];
     __shared__ int b_i[NB];
     __shared__ int b_lo[NB][3];  // first table interval per axis
     __shared__ double b_w[NB];
@@ -353,7 +372,6 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
     // xcd_chunk(v): blocks of kXcdBlock consecutive chunks are dealt to the
     // XCDs in turn, so an XCD works through one block at a time while the
     // blocks of all XCDs interleave over the queue (balanced work).
-    //
     //
     // Slots: DYN = false, one per workgroup (the grid covers the chunks, or
     // with a device count their capacity); DYN = true, a fixed persistent
@@ -398,8 +416,9 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
             vlo = min(vlo, __shfl_xor(vlo, d, 64));
             vhi = max(vhi, __shfl_xor(vhi, d, 64));
         }
-        mn[a] = vlo;
-        mx[a] = vhi;
+        // wave-uniform: held in scalar registers, so the tile loops are too
+        mn[a] = __builtin_amdgcn_readfirstlane(vlo);
+        mx[a] = __builtin_amdgcn_readfirstlane(vhi);
     }
     const int nv[3] = {mx[0] - mn[0] + 1, mx[1] - mn[1] + 1, mx[2] - mn[2] + 1};
     double base[3], blo[3], bhi[3];
@@ -410,18 +429,21 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
         bhi[a] = base[a] + (mx[a] + 1) * h;
     }
     const int per_atom = nv[0] + nv[1] + nv[2];
+    const int tile = WS / per_atom;  // atoms per tile for this chunk
     // this lane's items in a tile: x, y, z interval of its cube
     const int ox = li[0] - mn[0], oy = nv[0] + li[1] - mn[1], oz = nv[0] + nv[1] + li[2] - mn[2];
     const int re = root_start[root + 1];
-    int head = root_start[root], nbuf = 0;
+    int head = root_start[root], nbuf = 0, bs = 0;  // ring: atoms [bs, bs + nbuf)
     double A[64];
 #pragma unroll
     for (int e = 0; e < 64; ++e) A[e] = 0.0;
     double EA = 0.0;
     unsigned long long np = 0;
-    for (;;) {
-        // refill: atoms of the list within R_c of the chunk's box, in order
-        while (nbuf < CH && head < re) {
+
+    // refill: atoms of the list within R_c of the chunk's box, in order,
+    // until a tile is buffered or the list ends
+    auto refill = [&]() {
+        while (nbuf < tile && head < re) {
             const int p = head + lane;
             bool use = false;
             int i = 0;
@@ -441,7 +463,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
             }
             const unsigned long long m = __ballot(use);
             if (use) {
-                const int at = nbuf + __popcll(m & ((1ull << lane) - 1ull));
+                const int at = (bs + nbuf + __popcll(m & ((1ull << lane) - 1ull))) & (NB - 1);
                 b_i[at] = i;
                 b_w[at] = aw[i];
 #pragma unroll
@@ -453,17 +475,21 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
             nbuf += __popcll(m);
             head += 64;
         }
-        __syncthreads();
-        const int na = min(CH, nbuf);
-        if (na == 0) break;
-        // projections of the tile's atoms on the chunk's intervals
+        wave_lds_sync();
+    };
+    // projections of the first na buffered atoms on the chunk's intervals
+    // into one item set: table rows by global-to-LDS copies (issued, not
+    // waited for), pruned and in-place items by LDS stores; the atoms then
+    // leave the ring
+    auto stage = [&](int na, double2 *t01, double2 *t23, double2 *ted, double *tw) {
         const int nw = na * per_atom;
         for (int k0 = 0; k0 < nw; k0 += 64) {
             const int w = k0 + lane;
             const double *src = nullptr;
             if (w < nw) {
-                const int a_idx = w / per_atom;
-                int r = w - a_idx * per_atom, axis = 0;
+                const int a_loc = w / per_atom;
+                const int a_idx = (bs + a_loc) & (NB - 1);
+                int r = w - a_loc * per_atom, axis = 0;
                 if (r >= nv[0]) {
                     r -= nv[0];
                     axis = 1;
@@ -503,65 +529,75 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
                 __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)(ted + k0), 16, 0, 0);
             }
         }
+        if (lane < na) tw[lane] = b_w[(bs + lane) & (NB - 1)];
+        // keep the copies issued here ahead of the update that follows
+        __builtin_amdgcn_sched_barrier(0);
+        bs = (bs + na) & (NB - 1);
+        nbuf -= na;
+        wave_lds_sync();
+    };
+    // the per-cube R_c test and the rank-one updates of a staged tile
+    auto update = [&](int na, const double2 *t01, const double2 *t23, const double2 *ted,
+                      const double *tw) {
+        if (!valid) return;
+        for (int a = 0; a < na; ++a) {
+            const int ba = a * per_atom;
+            const double2 ex = ted[ba + ox], ey = ted[ba + oy], ez = ted[ba + oz];
+            if (ex.y + ey.y + ez.y > rc2) continue;
+            ++np;
+            const double2 x01 = t01[ba + ox], x23 = t23[ba + ox];
+            const double2 y01 = t01[ba + oy], y23 = t23[ba + oy];
+            const double2 z01 = t01[ba + oz], z23 = t23[ba + oz];
+            const double px[4] = {x01.x, x01.y, x23.x, x23.y};
+            const double py[4] = {y01.x, y01.y, y23.x, y23.y};
+            const double pz[4] = {z01.x, z01.y, z23.x, z23.y};
+            const double wgt = tw[a];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double wx = wgt * px[j];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double wxy = wx * py[k];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) A[16 * j + 4 * k + l] += wxy * pz[l];
+                }
+            }
+            if (FAST) {
+                const double nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
+                const double ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
+                const double nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
+                EA += wgt * ((ex.x * ny + nx * ey.x) * nz + nx * ny * ez.x);
+            }
+        }
+    };
+
+    // software pipeline over tiles: while tile t is summed from one item set,
+    // the copies of tile t + 1 land in the other.  Before a set is refilled,
+    // every copy issued so far is waited for (those into it were issued a
+    // whole tile earlier)
+    refill();
+    int na_cur = min(tile, nbuf);
+    stage(na_cur, s0_01, s0_23, s0_ed, s0_w);
+    while (na_cur > 0) {
+        refill();
+        int na_nxt = min(tile, nbuf);
+        __builtin_amdgcn_s_waitcnt(0);  // the current set's copies have landed
+        wave_lds_sync();
+        stage(na_nxt, s1_01, s1_23, s1_ed, s1_w);
+        update(na_cur, s0_01, s0_23, s0_ed, s0_w);
+        wave_lds_sync();
+        na_cur = na_nxt;
+        if (na_cur == 0) break;
+        refill();
+        na_nxt = min(tile, nbuf);
         __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (valid) {
-            for (int a = 0; a < na; ++a) {
-                const int ba = a * per_atom;
-                const double2 ex = ted[ba + ox], ey = ted[ba + oy], ez = ted[ba + oz];
-                if (ex.y + ey.y + ez.y > rc2) continue;
-                ++np;
-                const double2 x01 = t01[ba + ox], x23 = t23[ba + ox];
-                const double2 y01 = t01[ba + oy], y23 = t23[ba + oy];
-                const double2 z01 = t01[ba + oz], z23 = t23[ba + oz];
-                const double px[4] = {x01.x, x01.y, x23.x, x23.y};
-                const double py[4] = {y01.x, y01.y, y23.x, y23.y};
-                const double pz[4] = {z01.x, z01.y, z23.x, z23.y};
-                const double wgt = b_w[a];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const double wx = wgt * px[j];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const double wxy = wx * py[k];
-#pragma unroll
-                        for (int l = 0; l < 4; ++l) A[16 * j + 4 * k + l] += wxy * pz[l];
-                    }
-                }
-                if (FAST) {
-                    const double nx = fabs(px[0]) + fabs(px[1]) + fabs(px[2]) + fabs(px[3]);
-                    const double ny = fabs(py[0]) + fabs(py[1]) + fabs(py[2]) + fabs(py[3]);
-                    const double nz = fabs(pz[0]) + fabs(pz[1]) + fabs(pz[2]) + fabs(pz[3]);
-                    EA += wgt * ((ex.x * ny + nx * ey.x) * nz + nx * ny * ez.x);
-                }
-            }
-        }
-        __syncthreads();
-        // move the atoms not yet staged (fewer than 64) to the buffer's front
-        const int rest = nbuf - na;
-        int mi = 0, ml[3] = {0, 0, 0};
-        double mw = 0.0, mx3[3] = {0.0, 0.0, 0.0};
-        if (lane < rest) {
-            mi = b_i[na + lane];
-            mw = b_w[na + lane];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                ml[a] = b_lo[na + lane][a];
-                mx3[a] = b_x[na + lane][a];
-            }
-        }
-        __syncthreads();
-        if (lane < rest) {
-            b_i[lane] = mi;
-            b_w[lane] = mw;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                b_lo[lane][a] = ml[a];
-                b_x[lane][a] = mx3[a];
-            }
-        }
-        nbuf = rest;
+        wave_lds_sync();
+        stage(na_nxt, s0_01, s0_23, s0_ed, s0_w);
+        update(na_cur, s1_01, s1_23, s1_ed, s1_w);
+        wave_lds_sync();
+        na_cur = na_nxt;
     }
+    __builtin_amdgcn_s_waitcnt(0);  // no copy outlives the chunk
     epilogue(g, level, FAST, A, EA, qi, valid, o);
     if (pairs) wave_add(pairs, np);
     if (!DYN) break;
@@ -1009,18 +1045,6 @@ __global__ void k_chunk_bins(const int2 *__restrict__ chunks, int64_t n, int64_t
         return a;
     };
     hist[j] += (int32_t)(lower(hi) - lower(lo));
-}
-
-__global__ void k_guard_flags(const uint8_t *__restrict__ dec, int64_t n,
-                              const int32_t *__restrict__ nd, int32_t *__restrict__ f) {
-    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i < n) f[i] = (!nd || i < (int64_t)*nd) && dec[i] == DEC_GUARD;
-}
-
-__global__ void k_list_emit(const int32_t *__restrict__ f, const int32_t *__restrict__ off,
-                            int64_t n, int32_t *__restrict__ list) {
-    int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
-    if (i < n && f[i]) list[off[i]] = (int32_t)i;
 }
 
 __global__ void k_level_counts(const uint8_t *__restrict__ dec, int64_t n,
@@ -1514,20 +1538,6 @@ hipError_t launch_chunks_by_length(const Grid *gt, int level, const int4 *q, con
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_chunk_len_scatter, dim3((unsigned)nb), dim3(kLenBuckets), 0, s, chunks, n,
                        ncount, bkt, boff, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s,
-                                   const int32_t *nd) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_guard_flags, dim3(nblk(n)), dim3(kBS), 0, s, dec, n, nd, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
-                                  hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_list_emit, dim3(nblk(n)), dim3(kBS), 0, s, flags, off, n, list);
     return hipGetLastError();
 }
 

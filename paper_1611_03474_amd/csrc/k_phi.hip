@@ -46,6 +46,26 @@ __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
     }
 }
 
+// number of (point, atom) pairs within R_c over the points (the terms phi
+// sums); one atomic add per wavefront
+__global__ __launch_bounds__(kBS) void k_phi_pairs(const Grid *__restrict__ gt,
+                                                   const double *__restrict__ pts, int64_t m,
+                                                   const int32_t *__restrict__ cs,
+                                                   const double4 *__restrict__ xw,
+                                                   unsigned long long *__restrict__ count) {
+    const int64_t k = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    unsigned long long c = 0;
+    if (k < m) {
+        const double p[3] = {pts[3 * k], pts[3 * k + 1], pts[3 * k + 2]};
+        double f, gr[3];
+        phi_at<false, false, true>(gt[0], p, cs, xw, f, gr);
+        c = (unsigned long long)f;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 __global__ __launch_bounds__(kBS) void k_phi_subset(const Grid *__restrict__ gt,
                                                     const int32_t *__restrict__ pconf,
                                                     const double *__restrict__ pts,
@@ -469,6 +489,13 @@ hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
                             hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_list_emit2, dim3(nblk(n)), dim3(kBS), 0, s, flags, off, n, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_pairs(const Grid *gt, const double *pts, int64_t m, const int32_t *cs,
+                            const double4 *xw, unsigned long long *count, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_phi_pairs, dim3(nblk(m)), dim3(kBS), 0, s, gt, pts, m, cs, xw, count);
     return hipGetLastError();
 }
 

@@ -1113,7 +1113,7 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     int32_t *nq = sz + kSzNq, *nl = sz + kSzNl;
     int32_t *nruns = sz + kSzRuns, *nchunks = sz + kSzChunks;
     int32_t *nu = sz + kSzNu, *ngp = sz + kSzNgp, *nv = sz + kSzNv;
-    int32_t *ns = sz + kSzSlices, *ngs = sz + kSzGSlices;
+    int32_t *ns = sz + kSzSlices;
     // result arrays: the caller's where the capture bound them; the level
     // loop emits a single conformation's leaves in final order, a batch's
     // are regrouped into the final array afterwards
@@ -1149,10 +1149,8 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
         const bool half = tiled && half_level(ctx, lev);
         const int cmax = half ? 32 : 64;
         ProjTab pt;
-        int lprec = prec;  // precision of this level's estimate
+        const int lprec = TMS_PREC_FP64;  // as the eager pass: exact estimate and bound
         if (G.proj_table) {
-            // tabulated projections are exact in either mode
-            lprec = TMS_PREC_FP64;
             const int pns = proj_table_slots(cells, lev);
             HIPCK(launch_proj_table(g, gt, nconf, lev, lprec, ax, ay, az, cells->n, pns,
                                     G.ptab.as<double>(), s));
@@ -1194,24 +1192,6 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                          percap ? ovf : nullptr));
             HIPCK(launch_bound(g, lev, lprec, cap, dec + off, G.abuf.as<double>(),
                                G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
-        }
-        if (lprec == TMS_PREC_FP32_GUARD) {
-            int32_t *ng = sz + kSzNg + lev;
-            HIPCK(launch_guard_list_flags(dec, QC, flags, s, nq + lev));
-            HIPCK(exclusive_scan(flags, sa, QC, ng, tmp, s));
-            HIPCK(launch_guard_list_emit(flags, sa, QC, idx, s));
-            HIPCK(launch_slice_counts(ng, S, nsl, ngs, s));
-            for (int k = 0; k < nsl; ++k) {
-                const int64_t off = (int64_t)k * S, cap = std::min(S, QC - off);
-                unsigned *hard = reinterpret_cast<unsigned *>(ctr + kCtHard + 2 * kMaxSlices * lev +
-                                                              kMaxSlices + k);
-                HIPCK(launch_estimate_decide(g, gt, lev, TMS_PREC_FP64, q, cap, idx + off, nullptr,
-                                             0, rs, ra, ax, ay, az, aw, dec, G.abuf.as<double>(),
-                                             G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
-                                             nullptr, ctx->tile_atoms, s, ngs + k));
-                HIPCK(launch_bound(g, lev, TMS_PREC_FP64, cap, dec, G.abuf.as<double>(),
-                                   G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
-            }
         }
         HIPCK(launch_level_histo(dec, QC, ctr + kCtHisto + 8 * lev, ctr + kCtPart, s, nq + lev));
         HIPCK(launch_level_counts(dec, QC, flags, idx, s, nq + lev));
@@ -1490,17 +1470,21 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const bool half = tiled && half_level(ctx, lev);
             int64_t level_chunks = 0;
             ProjTab pt;
-            int lprec = prec;  // precision of this level's estimate
+            // The estimate and the bound run with exact exponentials in both
+            // precision modes: with the table the exponentials are shared by
+            // every cube that reads an entry (no FP32 gain), and a bound
+            // decision taken on a tensor with single-precision exponentials
+            // could only be guarded by a perturbation estimate of the nested
+            // SVD, not a certified one (near clustered singular values its
+            // factors move arbitrarily), so classification would not be
+            // guaranteed to equal the double-precision one.
+            const int lprec = TMS_PREC_FP64;
             const int pns = proj_table_slots(cells, lev);
             // a table that does not fit in device memory leaves the level to
             // in-place projections
             if (ctx->proj_table &&
                 ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)pns) ==
                     hipSuccess) {
-                // the table amortises the exponentials over every cube that
-                // reads an entry, so its projections are exact in either mode
-                // (and the level needs no guard)
-                lprec = TMS_PREC_FP64;
                 const int ns = pns;
                 const int64_t na = cells->n;
                 {
@@ -1564,45 +1548,6 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             chunks_lvl[lev] = tiled && !half ? level_chunks : -1;
             ctx->last_chunk_bins[lev].clear();
             if (tiled && !half) ctx->last_chunk_bins[lev].resize((size_t)nbins);
-            if (lprec == TMS_PREC_FP32_GUARD) {
-                {
-                    TimedScope ts_(ctx, TMS_T_COMPACT);
-                    HIPCK(launch_guard_list_flags(ctx->dec.as<uint8_t>(), nq,
-                                                  ctx->flags.as<int32_t>(), s));
-                }
-                int64_t ng = 0;
-                rc = scan_total(ctx, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(), nq, &ng);
-                if (rc) return rc;
-                if (ng > 0) {
-                    {
-                        TimedScope ts_(ctx, TMS_T_GUARD);
-                        HIPCK(launch_guard_list_emit(ctx->flags.as<int32_t>(),
-                                                     ctx->scan_a.as<int32_t>(), nq,
-                                                     ctx->idx.as<int32_t>(), s));
-                    }
-                    // the guarded cubes are sparse (well under 1 %): one thread per
-                    // cube beats root chunks holding a handful of cubes each
-                    const int64_t gslices = (ng + S - 1) / S;
-                    if (gslices > kMaxSlices) return fail(ctx, TMS_E_INVALID, "guard list too large");
-                    for (int64_t k = 0; k < gslices; ++k) {
-                        const int64_t off = k * S, ns = std::min(S, ng - off);
-                        unsigned *hard =
-                            reinterpret_cast<unsigned *>(ctr + kSliceCtr + kMaxSlices + k);
-                        TimedScope ts_(ctx, TMS_T_GUARD);
-                        HIPCK(launch_estimate_decide(
-                            g, gt, lev, TMS_PREC_FP64, q, ns, ctx->idx.as<int32_t>() + off, nullptr,
-                            0, cells->root_start.as<int32_t>(), cells->root_atoms.as<int32_t>(),
-                            cells->ax.as<double>(), cells->ay.as<double>(), cells->az.as<double>(),
-                            cells->aw.as<double>(), ctx->dec.as<uint8_t>(), ctx->abuf.as<double>(),
-                            ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(), hard, nullptr,
-                            ctx->tile_atoms, s));
-                        HIPCK(launch_bound(g, lev, TMS_PREC_FP64, ns, ctx->dec.as<uint8_t>(),
-                                           ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
-                                           ctx->hidx.as<int32_t>(), hard, s));
-                    }
-                }
-                st.guard_cubes += ng;
-            }
             int32_t *lcnt = ctx->flags.as<int32_t>(), *ccnt = ctx->idx.as<int32_t>();
             {
                 TimedScope ts_(ctx, TMS_T_COMPACT);
@@ -2369,6 +2314,24 @@ int32_t tms_debug_tensor(tms_ctx *ctx, const tms_cells *cells, const int32_t *cu
     }
     if (S) HIPCK(hipMemcpyAsync(S, ctx->ebuf.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
     HIPCK(hipStreamSynchronize(s));
+    return TMS_OK;
+}
+
+int32_t tms_debug_phi_pairs(tms_ctx *ctx, const tms_cells *cells, const double *pts, int64_t m,
+                            int64_t *pairs) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!cells || m < 0 || !pairs || (m > 0 && !pts))
+        return fail(ctx, TMS_E_INVALID, "invalid arguments to tms_debug_phi_pairs");
+    if (cells->nconf != 1)
+        return fail(ctx, TMS_E_INVALID, "tms_debug_phi_pairs takes cells of one conformation");
+    HIPCK(hipSetDevice(ctx->device));
+    unsigned long long *ctr = ctx->counters.as<unsigned long long>() + 113;
+    HIPCK(launch_fill_u64(reinterpret_cast<uint64_t *>(ctr), 0ull, 1, ctx->stream));
+    HIPCK(launch_phi_pairs(cells->gtab.as<Grid>(), pts, m, cells->cell_start.as<int32_t>(),
+                           cells->axw.as<double4>(), ctr, ctx->stream));
+    unsigned long long h = 0;
+    HIPCK(d2h(ctx, &h, ctr, 1));
+    *pairs = (int64_t)h;
     return TMS_OK;
 }
 

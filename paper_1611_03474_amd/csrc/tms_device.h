@@ -506,8 +506,9 @@ constexpr int kPhiBatch = 2;
 // phi and grad phi at one point (eq. Gaussian1).
 // ---------------------------------------------------------------------------
 // Sum over atoms within R_c of p, in canonical atom order (cell rows of the
-// stencil, atoms in cell order); xw holds the atoms as (x, y, z, w).
-template <bool FAST, bool GRAD = true>
+// stencil, atoms in cell order); xw holds the atoms as (x, y, z, w).  COUNT:
+// phi receives the number of terms instead (the sum's algorithmic work).
+template <bool FAST, bool GRAD = true, bool COUNT = false>
 __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
                                        const int32_t *__restrict__ cs,
                                        const double4 *__restrict__ xw, double &phi, double gr[3]) {
@@ -515,6 +516,10 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
     phi = 0.0;
     gr[0] = gr[1] = gr[2] = 0.0;
     auto add = [&](double w, double dx, double dy, double dz, double d2) {
+        if (COUNT) {
+            phi += 1.0;
+            return;
+        }
         const double term = w * expn<FAST>(-D * d2);
         phi += term;
         if (GRAD) {

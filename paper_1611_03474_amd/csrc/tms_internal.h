@@ -219,7 +219,8 @@ struct tms_ctx {
         uguard, ctmp, hidx, chunks, chunks2, runs, bmap, bmcnt, bmoff;
     // small device counters (u64 slots): [0,64) striped pair counts,
     // [72,77) decision histogram, 80 surface count, 96 adjoint consistency
-    // flag, 100 scan total, 104 and 105 a level's leaf and child totals;
+    // flag, 100 scan total, 104 and 105 a level's leaf and child totals,
+    // 112 stage-two degenerate count, 113 phi pair count;
     // [256, 256 + 5*1024) reduction partials;
     // [8192, 8192 + 512) hard-list lengths of the queue slices
     // tuning (results do not depend on it): queue entries per estimate
@@ -387,10 +388,6 @@ hipError_t launch_chunks_by_length(const Grid *gt, int level, const int4 *q, con
                                    int64_t n, const int32_t *ncount, const int32_t *root_start,
                                    int32_t *bkt, int32_t *bcnt, int32_t *boff, void *tmp,
                                    int2 *out, hipStream_t s);
-hipError_t launch_guard_list_flags(const uint8_t *dec, int64_t n, int32_t *flags, hipStream_t s,
-                                   const int32_t *nd = nullptr);
-hipError_t launch_guard_list_emit(const int32_t *flags, const int32_t *off, int64_t n,
-                                  int32_t *list, hipStream_t s);
 hipError_t launch_level_counts(const uint8_t *dec, int64_t n, int32_t *leaf_cnt,
                                int32_t *child_cnt, hipStream_t s, const int32_t *nd = nullptr);
 hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int level,
@@ -431,6 +428,9 @@ hipError_t launch_guard_flags_u8(const uint8_t *g, int64_t n, int32_t *flags, hi
                                  const int32_t *nd = nullptr);
 hipError_t launch_list_emit(const int32_t *flags, const int32_t *off, int64_t n, int32_t *list,
                             hipStream_t s);
+// *count += the (point, atom) pairs within R_c over m points (conformation 0)
+hipError_t launch_phi_pairs(const Grid *gt, const double *pts, int64_t m, const int32_t *cs,
+                            const double4 *xw, unsigned long long *count, hipStream_t s);
 // indices i < n with gd[i] != 0 appended to list at slots taken from *cnt
 // (which the caller zeroes); order arbitrary
 hipError_t launch_guard_append(const uint8_t *gd, int64_t n, int32_t *list, unsigned *cnt,

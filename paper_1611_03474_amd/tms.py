@@ -134,9 +134,10 @@ def load_library(path: str = LIB_PATH):
     L.tms_debug_tensor.argtypes = [_VP, _VP, _VP, i64, i32, _VP, _VP]
     L.tms_debug_bound.argtypes = [_VP, _VP, _VP, i64, _VP]
     L.tms_debug_fast_exp.argtypes = [_VP, _VP, i64, _VP]
+    L.tms_debug_phi_pairs.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
     for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
-              "tms_eval_phi_noalloc", "tms_stage2_points",
+              "tms_eval_phi_noalloc", "tms_stage2_points", "tms_debug_phi_pairs",
               "tms_partition_estimate", "tms_get_leaves", "tms_extract_cube_vertices",
               "tms_get_vertices", "tms_debug_tensor", "tms_debug_bound", "tms_set_timing",
               "tms_get_timing", "tms_debug_fast_exp", "tms_get_corners", "tms_backward",
@@ -540,6 +541,16 @@ class Context:
         self._check(self.lib.tms_debug_fast_exp(self.h, _VP(_ptr(xx)), xx.shape[0],
                                                 _VP(_ptr(y))))
         return y
+
+    def debug_phi_pairs(self, cells: Cells, pts) -> int:
+        """(point, atom) pairs within R_c over the points (phi's terms)."""
+        t = self._torch
+        p = pts if isinstance(pts, t.Tensor) else t.as_tensor(np.asarray(pts))
+        p = p.to(device=self.device, dtype=t.float64).contiguous()
+        n = C.c_int64()
+        self._check(self.lib.tms_debug_phi_pairs(self.h, cells.handle, _VP(_ptr(p)), p.shape[0],
+                                                 C.byref(n)))
+        return int(n.value)
 
     def debug_bound(self, A, band=None):
         """Returns [n, 6]: L, U, rho, r, jump, amp."""

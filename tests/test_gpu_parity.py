@@ -279,3 +279,43 @@ def test_extract_recomputes_corners(ctx, g200):
     b = tms.vertices_to_numpy(ctx.extract(cells, leaves, None))
     assert a.tobytes() == b.tobytes()
     ctx.free_cells(cells)
+
+
+def test_phi_pair_count(ctx, g200):
+    # the pairs phi sums: (point, atom) with |p - x_i|^2 <= R_c^2, counted by
+    # brute force over every pair
+    rng = np.random.default_rng(23)
+    pts = g200[rng.integers(0, len(g200), 3000), :3] + rng.normal(scale=3.0, size=(3000, 3))
+    p = tms.make_params(D=0.9)
+    cells = ctx.build_cells(g200, p)
+    rc2 = oracle.cutoff2(g200, 0.9)
+    d2 = ((pts[:, None, :] - g200[None, :, :3]) ** 2).sum(-1)
+    assert ctx.debug_phi_pairs(cells, pts) == int((d2 <= rc2).sum())
+    ctx.free_cells(cells)
+
+
+def test_extract_exact_on_trilinear_field(ctx):
+    # corner values of a trilinear field (dyadic coefficients: exact inputs)
+    # on leaves of two levels, fed to tms_extract_cube_vertices and to the
+    # oracle's edge step: the same edges, t equal to the last bits
+    import torch
+    from test_oracle_extract import leaves_and_values
+    c = 0.883
+    atoms = np.array([[-5.0, -3.0, -1.0, 1.5], [1.0, 3.0, 5.0, 1.5]])
+    cells = ctx.build_cells(atoms, tms.make_params(D=0.9, c=c))
+    origin, h0, K = np.array([-8.0, -6.0, -4.0]), 2.0, 3
+    assert np.array_equal(cells.origin, origin) and cells.K == K  # reading R9
+    coef = [3 / 4, 1 / 8, -1 / 16, 1 / 32, 3 / 64, -1 / 64, 1 / 128, 1 / 256]
+    _, ijk, level, cp = leaves_and_values(coef, origin, h0, K)
+    ref = oracle.extract(ijk, level, cp, c, origin, h0, K, conf=0)
+    L = np.zeros(len(ijk), dtype=tms.LEAF_DTYPE)
+    L["ix"], L["iy"], L["iz"], L["level"] = ijk[:, 0], ijk[:, 1], ijk[:, 2], level
+    L["mask"], L["cls"] = ref.mask, ref.cls
+    lt = torch.as_tensor(np.frombuffer(L.tobytes(), dtype=np.uint8).reshape(-1, 20)).to(ctx.device)
+    V = tms.vertices_to_numpy(ctx.extract(cells, lt, torch.as_tensor(cp).to(ctx.device)))
+    assert ref.n_vert > 100
+    assert np.array_equal(V["edge_key"], ref.vkey)
+    ulp = np.spacing(np.maximum(np.abs(ref.vt), 1e-300))
+    assert np.all(np.abs(V["t"] - ref.vt) <= ulp)
+    assert np.allclose(np.stack([V["x"], V["y"], V["z"]], 1), ref.vxyz, rtol=0, atol=1e-14)
+    ctx.free_cells(cells)
