@@ -433,7 +433,8 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time
  * does.  Defaults: slice_cubes 2^26, tiled_min_level 1, tile_atoms 8,
- * proj_table 1, tiled_persistent 0, tiled_half 0.  A captured pass takes
+ * proj_table 1, tiled_persistent 0, tiled_half 0, corner_groups 2,
+ * corner_reach 48.  A captured pass takes
  * them as they are at capture, except that its whole-wave tiled launches are
  * always one workgroup per chunk (sized from the eager pass's chunk count). */
 typedef struct {
@@ -468,6 +469,16 @@ typedef struct {
                                 its own atom stream); 2: level 2 so, level 3
                                 whole-wave; 0: one chunk of <= 64 cubes per
                                 wavefront                                   */
+    int32_t corner_groups;   /* phi at the unique leaf corners: 0 one thread
+                                per point; 1..8: a wavefront stages the
+                                atoms near its 64 points in LDS once per
+                                spatial group of them, for up to this many
+                                groups (a wavefront needing more sums its
+                                points one by one).  Values are
+                                bit-identical under every setting          */
+    int32_t corner_reach;    /* a group holds the points within
+                                corner_reach / 16 R_c of its first point
+                                along each axis (1..64)                     */
     int32_t reserved;        /* 0                                          */
 } tms_tuning;
 

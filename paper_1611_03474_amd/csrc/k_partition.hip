@@ -309,14 +309,9 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
 // ---------------------------------------------------------------------------
 
 // The tiled kernels run one wavefront per workgroup: their lanes exchange data
-// through LDS with no workgroup barrier -- a wavefront's LDS accesses execute
-// in order, so only the compiler must not move them across this point.  (A
-// workgroup barrier's fence would also wait for the global-to-LDS copies
-// still in flight, which the pipelined tiles overlap with the updates.)
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
+// through LDS with no workgroup barrier (wave_lds_sync).  A workgroup
+// barrier's fence would also wait for the global-to-LDS copies still in
+// flight, which the pipelined tiles overlap with the updates.
 
 constexpr int64_t kXcdBlock = 256;  // consecutive chunks per XCD turn
 

@@ -2,8 +2,8 @@
 // unique finest-lattice corners, phi once per corner, 8-bit sign masks and
 // classes against c (eq. linear1).  gfx950.
 //
-// Every phi value at a point is a pure function of the point: its cell, the
-// 5x5x5 cell stencil (cells of edge >= R_c/2), atoms in canonical order.  So
+// Every phi value at a point is a pure function of the point: the atoms
+// within R_c of it, summed in ascending atom order (cells row by row).  So
 // corners shared by neighbouring leaves get bit-identical values and signs.
 #include "tms_device.h"
 
@@ -43,6 +43,207 @@ __global__ __launch_bounds__(kBS) void k_phi_points(const Grid *__restrict__ gt,
     if (guard) {
         const double m_ = fabs(f - g.c);
         guard[k] = (m_ <= 2.0 * kFastExpErr * f + 1e-300 || m_ <= band_rel * g.c) ? 1 : 0;
+    }
+}
+
+// ---- phi at the unique leaf corners, atoms staged per wavefront ------------
+// The unique corners come in bitmap-rank order: 64 consecutive ones mostly lie
+// in a few neighbouring 4x4x4 lattice blocks.  A wavefront splits its 64
+// points into spatial groups (the first point left and every point left of
+// its conformation within `reach` R_c of it along each axis; at most `gmax`
+// groups, else every lane runs phi_at on its own).  For each group it loads,
+// coalesced, the atoms of the cell rows around the group's bounding box, keeps
+// those within R_c of the box and packs them, in atom order, into LDS; every
+// lane of the group then sums its own point over the packed atoms with the
+// same operations and the same distance test as phi_at.  phi_at takes exactly
+// the atoms within R_c of its point (the packed set holds them all), in
+// ascending atom order (cells are stored row by row), so each value is
+// bit-identical to phi_at's: only the loads are shared.
+constexpr int kCW = kBS / 64;   // wavefronts per workgroup
+constexpr int kCCap = 256;      // packed atoms per wavefront before a sum
+
+template <bool FAST>
+__global__ __launch_bounds__(kBS) void k_phi_corners(
+    const Grid *__restrict__ gt, const int32_t *__restrict__ pconf,
+    const double *__restrict__ pts, int64_t m, const int32_t *__restrict__ cs,
+    const double4 *__restrict__ xw, double band_rel, int gmax, double reach,
+    double *__restrict__ phi, uint8_t *__restrict__ guard, const int32_t *__restrict__ nd) {
+    __shared__ double4 s_at[kCW][kCCap + 4];
+    __shared__ int s_rb[kCW][64];  // first atom of each row of a row group
+    __shared__ int s_rp[kCW][64];  // exclusive prefix of the rows' atom counts
+    const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    int64_t mm = m;
+    if (nd) mm = min(mm, (int64_t)*nd);
+    const int64_t k0 = blockIdx.x * (int64_t)kBS + (int64_t)(threadIdx.x - lane);
+    if (k0 >= mm) return;  // uniform across the wavefront
+    const int64_t k = k0 + lane;
+    const bool valid = k < mm;
+    const int64_t kk = valid ? k : k0;
+    const int b = pconf ? pconf[kk] : 0;
+    const double p0 = pts[3 * kk], p1 = pts[3 * kk + 1], p2 = pts[3 * kk + 2];
+
+    // the group of the first point in `left` (every lane takes part: the
+    // shuffles read the leader's registers)
+    auto group_of = [&](unsigned long long left) -> unsigned long long {
+        const int ld = __ffsll(left) - 1;
+        const int lb = __shfl(b, ld, 64);
+        const double r = reach * sqrt(gt[lb].rc2);
+        const double lx = __shfl(p0, ld, 64), ly = __shfl(p1, ld, 64), lz = __shfl(p2, ld, 64);
+        const bool mine = ((left >> lane) & 1ull) && b == lb && fabs(p0 - lx) <= r &&
+                          fabs(p1 - ly) <= r && fabs(p2 - lz) <= r;
+        // the leader always joins its own group, so every round takes a point
+        return __ballot(mine) | (1ull << ld);
+    };
+    const unsigned long long all = __ballot(valid);
+    unsigned long long left = all;
+    for (int ng = 0; left != 0ull && ng <= gmax; ++ng) left &= ~group_of(left);
+
+    double f = 0.0;
+    if (left != 0ull) {  // more than gmax groups
+        if (valid) {
+            const double p[3] = {p0, p1, p2};
+            double gr[3];
+            phi_at<FAST, false>(gt[b], p, cs, xw, f, gr);
+        }
+    } else {
+        double4 *at = s_at[wv];
+        left = all;
+        while (left != 0ull) {
+            const unsigned long long gm = group_of(left);
+            left &= ~gm;
+            const bool ing = (gm >> lane) & 1ull;
+            const int ld = __ffsll(gm) - 1;
+            const int lb = __builtin_amdgcn_readfirstlane(__shfl(b, ld, 64));
+            const Grid &g = gt[lb];
+            const double rc2 = g.rc2, D = g.D;
+            // the group's bounding box (lanes outside it take the leader's
+            // point; the shuffles run on every lane)
+            const double q0 = __shfl(p0, ld, 64), q1 = __shfl(p1, ld, 64),
+                         q2 = __shfl(p2, ld, 64);
+            double lo0 = ing ? p0 : q0, lo1 = ing ? p1 : q1, lo2 = ing ? p2 : q2;
+            double hi0 = lo0, hi1 = lo1, hi2 = lo2;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) {
+                lo0 = fmin(lo0, __shfl_xor(lo0, d, 64));
+                lo1 = fmin(lo1, __shfl_xor(lo1, d, 64));
+                lo2 = fmin(lo2, __shfl_xor(lo2, d, 64));
+                hi0 = fmax(hi0, __shfl_xor(hi0, d, 64));
+                hi1 = fmax(hi1, __shfl_xor(hi1, d, 64));
+                hi2 = fmax(hi2, __shfl_xor(hi2, d, 64));
+            }
+            // cells within the stencil of some point of the box (cell
+            // indices clamped to +-1e8 before conversion; corners are lattice
+            // points inside the grid)
+            int c0[3], c1[3];
+            {
+                const double lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double fl = fmin(fmax(floor(over_cs(g, lo[a] - g.o[a])), -1.0e8), 1.0e8);
+                    const double fh = fmin(fmax(floor(over_cs(g, hi[a] - g.o[a])), -1.0e8), 1.0e8);
+                    c0[a] = max((int)fl - g.span, 0);
+                    c1[a] = min((int)fh + g.span, g.nc[a] - 1);
+                }
+            }
+            const int ny = c1[1] - c0[1] + 1;
+            const int nrow = (ny > 0 && c1[2] >= c0[2] && c1[0] >= c0[0])
+                                 ? (c1[2] - c0[2] + 1) * ny : 0;
+            // atoms kept: within R_c of the box (a margin of 2^-40 relative
+            // covers the rounding of either squared distance)
+            const double keep2 = rc2 * (1.0 + 0x1p-40);
+            int n = 0;  // packed atoms (uniform)
+            // sum the packed atoms over the group's points: pad to a multiple
+            // of four with atoms that no point takes, then four per step
+            auto flush = [&]() {
+                const int np = (n + 3) & ~3;
+                if (lane < np - n) at[n + lane] = make_double4(1e300, 1e300, 1e300, 0.0);
+                wave_lds_sync();
+                if (ing) {
+                    for (int j = 0; j < np; j += 4) {
+                        double4 a[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) a[u] = at[j + u];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double dx = p0 - a[u].x, dy = p1 - a[u].y, dz = p2 - a[u].z;
+                            const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                            if (!(d2 > rc2)) f = fma(a[u].w, expn<FAST>(-D * d2), f);
+                        }
+                    }
+                }
+                wave_lds_sync();
+                n = 0;
+            };
+            for (int r0 = 0; r0 < nrow; r0 += 64) {
+                // lane r: row r0 + r (z outer, y inner), its x range clipped
+                // to the chord of the R_c neighbourhood of the box (enlarged
+                // by 2^-16 relative: a row may keep a cell more than needed,
+                // never one less)
+                const int r = r0 + lane;
+                int rb = 0, len = 0;
+                if (r < nrow) {
+                    const int cz = c0[2] + r / ny, cy = c0[1] + r % ny;
+                    const double lz = g.o[2] + cz * g.cs, ly = g.o[1] + cy * g.cs;
+                    const double ez = fmax(fmax(lz - hi2, lo2 - (lz + g.cs)), 0.0);
+                    const double ey = fmax(fmax(ly - hi1, lo1 - (ly + g.cs)), 0.0);
+                    const double ryz = (rc2 - ez * ez) - ey * ey;
+                    if (ryz >= 0.0) {
+                        const double hx = sqrt(ryz) * (1.0 + 0x1p-16);
+                        const int x0 = max(c0[0], (int)floor(over_cs(g, lo0 - hx - g.o[0])));
+                        const int x1 = min(c1[0], (int)floor(over_cs(g, hi0 + hx - g.o[0])));
+                        if (x0 <= x1) {
+                            const int row = (int)g.cell_base + (cz * g.nc[1] + cy) * g.nc[0];
+                            rb = cs[row + x0];
+                            len = cs[row + x1 + 1] - rb;
+                        }
+                    }
+                }
+                int inc = len;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int t = __shfl_up(inc, d, 64);
+                    if (lane >= d) inc += t;
+                }
+                const int tot = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
+                const int nr = min(64, nrow - r0);
+                s_rb[wv][lane] = rb;
+                s_rp[wv][lane] = inc - len;
+                wave_lds_sync();
+                for (int t = 0; t < tot; t += 64) {
+                    const int fi = t + lane;
+                    bool keep = false;
+                    double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
+                    if (fi < tot) {
+                        // the row holding flattened atom fi: the last row whose
+                        // prefix is <= fi
+                        int lo = 0, hi = nr - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (s_rp[wv][mid] <= fi) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        a = xw[s_rb[wv][lo] + (fi - s_rp[wv][lo])];
+                        const double ex = fmax(fmax(lo0 - a.x, a.x - hi0), 0.0);
+                        const double ey = fmax(fmax(lo1 - a.y, a.y - hi1), 0.0);
+                        const double ez = fmax(fmax(lo2 - a.z, a.z - hi2), 0.0);
+                        keep = fma(ez, ez, fma(ey, ey, ex * ex)) <= keep2;
+                    }
+                    const unsigned long long bk = __ballot(keep);
+                    if (keep) at[n + __popcll(bk & ((1ull << lane) - 1ull))] = a;
+                    n += __popcll(bk);
+                    if (n > kCCap - 64) flush();
+                }
+                wave_lds_sync();  // the row tables are rewritten next
+            }
+            flush();
+        }
+    }
+    if (valid) {
+        phi[k] = f;
+        if (guard) {
+            const double m_ = fabs(f - gt[b].c);
+            guard[k] = (m_ <= 2.0 * kFastExpErr * f + 1e-300 || m_ <= band_rel * gt[b].c) ? 1 : 0;
+        }
     }
 }
 
@@ -439,6 +640,23 @@ hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision
             hipLaunchKernelGGL((k_phi_points<false, false>), dim3(nblk(m)), dim3(kBS), 0, s, gt,
                                pconf, pts, m, cs, xw, 0.0, phi, grad, nullptr, nd);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_corners(const Grid *gt, const int32_t *pconf, int precision,
+                              const double *pts, int64_t m, const int32_t *cs, const double4 *xw,
+                              double band_rel, int groups, double reach, double *phi,
+                              uint8_t *guard, hipStream_t s, const int32_t *nd) {
+    if (m <= 0) return hipSuccess;
+    if (groups <= 0)
+        return launch_phi_points(gt, pconf, precision, pts, m, cs, xw, band_rel, phi, nullptr,
+                                 guard, s, nd);
+    if (precision == TMS_PREC_FP32_GUARD)
+        hipLaunchKernelGGL(k_phi_corners<true>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
+                           cs, xw, band_rel, groups, reach, phi, guard, nd);
+    else
+        hipLaunchKernelGGL(k_phi_corners<false>, dim3(nblk(m)), dim3(kBS), 0, s, gt, pconf, pts, m,
+                           cs, xw, 0.0, groups, reach, phi, nullptr, nd);
     return hipGetLastError();
 }
 

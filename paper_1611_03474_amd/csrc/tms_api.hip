@@ -354,10 +354,11 @@ std::atomic<uint64_t> g_cells_ids{0};
 constexpr double kMaxBitmapBits = 68719476736.0;
 
 // phi at m points of `pts` (with the FAST-exponential guard); returns the
-// number of points recomputed with exact exponentials
+// number of points recomputed with exact exponentials.  corners: the points
+// are unique leaf corners in bitmap-rank order (the staged corner kernel).
 int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts,
                        const int32_t *pconf, int64_t m, double *phi, double *grad,
-                       int64_t *n_guard, double band_rel) {
+                       int64_t *n_guard, double band_rel, bool corners) {
     const int prec = cells->p.precision;
     const Grid *gt = cells->gtab.as<Grid>();
     *n_guard = 0;
@@ -369,8 +370,14 @@ int32_t phi_with_guard(tms_ctx *ctx, const tms_cells *cells, const double *pts,
     }
     {
         TimedScope ts_(ctx, TMS_T_PHI);
-        HIPCK(launch_phi_points(gt, pconf, prec, pts, m, cells->cell_start.as<int32_t>(),
-                                cells->axw.as<double4>(), band_rel, phi, grad, gbuf, ctx->stream));
+        if (corners && !grad)
+            HIPCK(launch_phi_corners(gt, pconf, prec, pts, m, cells->cell_start.as<int32_t>(),
+                                     cells->axw.as<double4>(), band_rel, ctx->corner_groups,
+                                     ctx->corner_reach / 16.0, phi, gbuf, ctx->stream));
+        else
+            HIPCK(launch_phi_points(gt, pconf, prec, pts, m, cells->cell_start.as<int32_t>(),
+                                    cells->axw.as<double4>(), band_rel, phi, grad, gbuf,
+                                    ctx->stream));
     }
     if (prec == TMS_PREC_FP32_GUARD) {
         HIPCK(ctx->flags.ensure(sizeof(int32_t) * (size_t)m));
@@ -437,7 +444,7 @@ int32_t corner_stage(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leave
                                          ctx->uconf.as<int32_t>(), s));
             }
             rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), ctx->uconf.as<int32_t>(), nu,
-                                ctx->uphi.as<double>(), nullptr, n_guard, kCornerBand);
+                                ctx->uphi.as<double>(), nullptr, n_guard, kCornerBand, true);
             if (rc) return rc;
             {
                 TimedScope ts_(ctx, TMS_T_CORNER);
@@ -1226,10 +1233,10 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
     HIPCK(launch_corner_enum(gt, nconf, G.bmap.as<uint64_t>(), G.bmoff.as<int32_t>(), cw,
                              G.uniq.as<double>(), G.uconf.as<int32_t>(), s, G.ucap, ovf));
     const bool fast = prec == TMS_PREC_FP32_GUARD;
-    HIPCK(launch_phi_points(gt, G.uconf.as<int32_t>(), prec, G.uniq.as<double>(), G.ucap,
-                            cells->cell_start.as<int32_t>(), cells->axw.as<double4>(), kCornerBand,
-                            G.uphi.as<double>(), nullptr, fast ? G.uguard.as<uint8_t>() : nullptr, s,
-                            nu));
+    HIPCK(launch_phi_corners(gt, G.uconf.as<int32_t>(), prec, G.uniq.as<double>(), G.ucap,
+                             cells->cell_start.as<int32_t>(), cells->axw.as<double4>(), kCornerBand,
+                             ctx->corner_groups, ctx->corner_reach / 16.0, G.uphi.as<double>(),
+                             fast ? G.uguard.as<uint8_t>() : nullptr, s, nu));
     if (fast) {
         HIPCK(launch_guard_flags_u8(G.uguard.as<uint8_t>(), G.ucap, flags, s, nu));
         HIPCK(exclusive_scan(flags, sa, G.ucap, ngp, tmp, s));
@@ -1328,7 +1335,7 @@ int32_t tms_eval_phi(tms_ctx *ctx, const tms_cells *cells, const double *pts, in
         return fail(ctx, TMS_E_INVALID, "tms_eval_phi takes cells of one conformation");
     HIPCK(hipSetDevice(ctx->device));
     int64_t ng = 0;
-    int32_t rc = phi_with_guard(ctx, cells, pts, nullptr, m, phi, grad, &ng, 0.0);
+    int32_t rc = phi_with_guard(ctx, cells, pts, nullptr, m, phi, grad, &ng, 0.0, false);
     if (rc) return rc;
     HIPCK(hipStreamSynchronize(ctx->stream));
     if (n_guard) *n_guard = ng;
@@ -1413,7 +1420,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         HIPCK(launch_uniform_points(g, ctx->uniq.as<double>(), m, s));
         int64_t ng = 0;
         int32_t rc = phi_with_guard(ctx, cells, ctx->uniq.as<double>(), nullptr, m, ctx->uphi.as<double>(),
-                                    nullptr, &ng, kCornerBand);
+                                    nullptr, &ng, kCornerBand, false);
         if (rc) return rc;
         HIPCK(launch_uniform_gather(g, ctx->uphi.as<double>(), g.c, ctx->leaves.as<tms_leaf>(), L,
                                     ctx->corner_phi.as<double>(), s));
@@ -2136,12 +2143,18 @@ int32_t tms_set_tuning(tms_ctx *ctx, const tms_tuning *t) {
         return fail(ctx, TMS_E_INVALID, "tiled_persistent must be 0 or 1");
     if (t->tiled_half < 0 || t->tiled_half > 2)
         return fail(ctx, TMS_E_INVALID, "tiled_half must be 0, 1 or 2");
+    if (t->corner_groups < 0 || t->corner_groups > 8)
+        return fail(ctx, TMS_E_INVALID, "corner_groups outside 0..8");
+    if (t->corner_reach < 1 || t->corner_reach > 64)
+        return fail(ctx, TMS_E_INVALID, "corner_reach outside 1..64");
     ctx->slice_cubes = t->slice_cubes;
     ctx->tiled_min_level = t->tiled_min_level;
     ctx->tile_atoms = t->tile_atoms;
     ctx->proj_table = t->proj_table;
     ctx->tiled_dyn = t->tiled_persistent != 0;
     ctx->tiled_half = t->tiled_half;
+    ctx->corner_groups = t->corner_groups;
+    ctx->corner_reach = t->corner_reach;
     return TMS_OK;
 }
 
@@ -2153,6 +2166,8 @@ int32_t tms_get_tuning(tms_ctx *ctx, tms_tuning *t) {
     t->proj_table = ctx->proj_table;
     t->tiled_persistent = ctx->tiled_dyn ? 1 : 0;
     t->tiled_half = ctx->tiled_half;
+    t->corner_groups = ctx->corner_groups;
+    t->corner_reach = ctx->corner_reach;
     t->reserved = 0;
     return TMS_OK;
 }

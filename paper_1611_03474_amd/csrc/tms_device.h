@@ -494,6 +494,15 @@ __device__ __forceinline__ void sample_range(const double *A, double &lo, double
     hi = fmax(hi, ctr);
 }
 
+// Lanes of one wavefront exchanging data through LDS: a wavefront's LDS
+// accesses execute in order, so only the compiler must not move them across
+// this point (no workgroup barrier, which would also wait for outstanding
+// global-to-LDS copies).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // x / cs, as a multiplication when that is exact
 __device__ __forceinline__ double over_cs(const Grid &g, double x) {
     return g.inv_cs != 0.0 ? x * g.inv_cs : x / g.cs;
@@ -520,10 +529,12 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
             phi += 1.0;
             return;
         }
-        const double term = w * expn<FAST>(-D * d2);
-        phi += term;
+        // explicit fused forms: every kernel that sums phi over atoms uses
+        // these same operations, so their values agree bit for bit
+        const double e = expn<FAST>(-D * d2);
+        phi = fma(w, e, phi);
         if (GRAD) {
-            const double f = m2D * term;
+            const double f = m2D * (w * e);
             gr[0] += f * dx;
             gr[1] += f * dy;
             gr[2] += f * dz;
@@ -585,7 +596,7 @@ __device__ __forceinline__ void phi_at(const Grid &g, const double p[3],
 #pragma unroll
             for (int k = 0; k < kPhiBatch; ++k) {
                 const double dx = p[0] - a[k].x, dy = p[1] - a[k].y, dz = p[2] - a[k].z;
-                const double d2 = dx * dx + dy * dy + dz * dz;
+                const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 const bool in = i + k < re && !(d2 > g.rc2);
                 // the weight selected here keeps its load beside the
                 // coordinates'

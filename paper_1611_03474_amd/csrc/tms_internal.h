@@ -229,6 +229,8 @@ struct tms_ctx {
     int tiled_min_level = 1;
     int tile_atoms = 8;
     int tiled_half = 0;  // half-wave chunks of <= 32 cubes: 1 levels 2-3, 2 level 2
+    int corner_groups = 2;  // spatial groups per wavefront of the corner phi kernel
+    int corner_reach = 48;  // their reach, in R_c / 16
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
     tms::DevBuf ptab;       // that table
     tms::DevBuf tick;       // [8] chunk slot counters of the tiled estimate
@@ -414,6 +416,15 @@ hipError_t launch_phi_points(const Grid *gt, const int32_t *pconf, int precision
                              int64_t m, const int32_t *cell_start, const double4 *xw,
                              double band_rel, double *phi, double *grad, uint8_t *guard,
                              hipStream_t s, const int32_t *nd = nullptr);
+// phi at unique corner points in bitmap-rank order (no gradient): up to
+// `groups` (<= 8) spatial groups per wavefront sum over atoms staged in LDS (points
+// within reach R_c of a group's first point per axis); 0: launch_phi_points.
+// Values bit-identical to launch_phi_points'.
+hipError_t launch_phi_corners(const Grid *gt, const int32_t *pconf, int precision,
+                              const double *pts, int64_t m, const int32_t *cell_start,
+                              const double4 *xw, double band_rel, int groups, double reach,
+                              double *phi, uint8_t *guard, hipStream_t s,
+                              const int32_t *nd = nullptr);
 hipError_t launch_phi_points_subset(const Grid *gt, const int32_t *pconf, const double *pts,
                                     const int32_t *list, int64_t m, const int32_t *cell_start,
                                     const double4 *xw, double *phi, double *grad, hipStream_t s,

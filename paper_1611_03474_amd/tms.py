@@ -46,6 +46,7 @@ class Tuning(C.Structure):
     _fields_ = [("slice_cubes", C.c_int64), ("tiled_min_level", C.c_int32),
                 ("tile_atoms", C.c_int32), ("proj_table", C.c_int32),
                 ("tiled_persistent", C.c_int32), ("tiled_half", C.c_int32),
+                ("corner_groups", C.c_int32), ("corner_reach", C.c_int32),
                 ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
@@ -485,7 +486,8 @@ class Context:
 
     # ---------------------------------------------------------------- tuning
     def set_tuning(self, slice_cubes=None, tiled_min_level=None, tile_atoms=None,
-                   proj_table=None, tiled_persistent=None, tiled_half=None):
+                   proj_table=None, tiled_persistent=None, tiled_half=None,
+                   corner_groups=None, corner_reach=None):
         t = self.get_tuning()
         if slice_cubes is not None:
             t.slice_cubes = int(slice_cubes)
@@ -499,6 +501,10 @@ class Context:
             t.tiled_persistent = int(tiled_persistent)
         if tiled_half is not None:
             t.tiled_half = int(tiled_half)
+        if corner_groups is not None:
+            t.corner_groups = int(corner_groups)
+        if corner_reach is not None:
+            t.corner_reach = int(corner_reach)
         self._check(self.lib.tms_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self) -> Tuning:
