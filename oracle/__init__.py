@@ -42,7 +42,8 @@ class Params(C.Structure):
     _fields_ = [("D", C.c_double), ("c", C.c_double), ("tau", C.c_double),
                 ("h0", C.c_double), ("h_min", C.c_double), ("pad", C.c_double),
                 ("eps_cut", C.c_double), ("uniform", C.c_int32),
-                ("nthreads", C.c_int32), ("conf", C.c_int32), ("gl_nodes", C.c_int32)]
+                ("nthreads", C.c_int32), ("conf", C.c_int32), ("gl_nodes", C.c_int32),
+                ("degree", C.c_int32), ("reexpand", C.c_int32)]
 
 
 _I64A = C.c_int64 * OR_MAXLEV
@@ -91,6 +92,10 @@ def lib():
         L.or_gauss_legendre.argtypes = [C.c_int, _DP, _DP]
         L.or_project_fn.argtypes = [_FUN1, C.c_void_p, C.c_int, _DP]
         L.or_project.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _DP]
+        L.or_project_deg.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                     C.c_int, _DP]
+        L.or_project_fn_deg.argtypes = [_FUN1, C.c_void_p, C.c_int, C.c_int, _DP]
+        L.or_child_tensor.argtypes = [_DP, C.c_int, _DP]
         L.or_cutoff2.argtypes = [_DP, C.c_int64, C.c_double, C.c_double]
         L.or_cutoff2.restype = C.c_double
         L.or_phi.argtypes = [_DP, C.c_int64, C.c_double, C.c_double, _DP, C.c_int64, _DP, _DP,
@@ -144,21 +149,33 @@ def gauss_legendre(n: int):
     return t, w
 
 
-def project(D, lo, hi, xi, nodes=0):
-    """Degree-3 Legendre projection with C0 endpoint correction of the factor
-    exp(-D (x - xi)^2) on [lo, hi] (Section 2.2.1, eqs. poly2_1, poly3,
-    condition1, alpha)."""
+def project(D, lo, hi, xi, nodes=0, degree=3):
+    """Degree-n Legendre projection (n = 1..3; the paper uses 3) with C0
+    endpoint correction of the factor exp(-D (x - xi)^2) on [lo, hi]
+    (Section 2.2.1, eqs. poly2_1, poly3, condition1, alpha); coefficients
+    above n are zero."""
     a = np.zeros(4)
-    lib().or_project(float(D), float(lo), float(hi), float(xi), int(nodes), _dp(a))
+    lib().or_project_deg(float(D), float(lo), float(hi), float(xi), int(nodes), int(degree),
+                         _dp(a))
     return a
 
 
-def project_fn(f, nodes=0):
+def project_fn(f, nodes=0, degree=3):
     """The same projection applied to an arbitrary function f on [-1, 1]."""
     cb = _FUN1(lambda t, _ctx: float(f(t)))
     a = np.zeros(4)
-    lib().or_project_fn(cb, None, int(nodes), _dp(a))
+    lib().or_project_fn_deg(cb, None, int(nodes), int(degree), _dp(a))
     return a
+
+
+def child_tensor(A, octant):
+    """The polynomial of tensor A written in the Legendre basis of child
+    `octant` (bit 0: x, 1: y, 2: z; set = upper half) of its cube
+    (Section 2.2.3, eq. childtensor)."""
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(64)
+    out = np.zeros(64)
+    lib().or_child_tensor(_dp(A), int(octant), _dp(out))
+    return out.reshape(4, 4, 4)
 
 
 def cutoff2(xyzr, D, eps_cut=1e-10):
@@ -286,13 +303,18 @@ class Result:
 
 
 def partition(xyzr, D, c=1.0, tau=1e-3, h0=2.0, h_min=0.25, pad=3.0, eps_cut=1e-10,
-              uniform=False, nthreads=0, conf=0, gl_nodes=0) -> Result:
+              uniform=False, nthreads=0, conf=0, gl_nodes=0, degree=3,
+              reexpand=False) -> Result:
     """Adaptive partition and estimation (Section 2.2, Steps 1-3) followed by
-    leaf classification (eq. linear1) and edge intersections (eq. intersection)."""
+    leaf classification (eq. linear1) and edge intersections (eq. intersection).
+    degree: the 1-D series degree n (1..3); reexpand: child tensors are the
+    parent's polynomial in the child's basis (eq. childtensor) instead of new
+    projections from the atoms."""
     a = _atoms(xyzr)
     P = Params(D=float(D), c=float(c), tau=float(tau), h0=float(h0), h_min=float(h_min),
                pad=float(pad), eps_cut=float(eps_cut), uniform=int(bool(uniform)),
-               nthreads=int(nthreads), conf=int(conf), gl_nodes=int(gl_nodes))
+               nthreads=int(nthreads), conf=int(conf), gl_nodes=int(gl_nodes),
+               degree=int(degree), reexpand=int(bool(reexpand)))
     rp = lib().or_partition(_dp(a), a.shape[0], C.byref(P))
     try:
         res = Result(rp.contents)

@@ -44,6 +44,12 @@ typedef struct {
     int32_t nthreads;/* OpenMP threads (0: library default) */
     int32_t conf;    /* conformation id written into edge keys */
     int32_t gl_nodes;/* Gauss-Legendre nodes for the 1-D projections (0: 32) */
+    int32_t degree;  /* degree n of the 1-D Legendre series, 1..3 (0: 3, the
+                        paper's choice; Section 2.2.1) */
+    int32_t reexpand;/* 0: a child's tensor is projected from the atoms again;
+                        1: it is the parent's polynomial written in the child's
+                        Legendre basis (eq. childtensor), no atom loop below the
+                        roots */
 } or_params;
 
 enum { OR_REASON_UNIFORM = 0, OR_REASON_CONVERGED = 1, OR_REASON_HMIN = 2 };
@@ -138,34 +144,55 @@ static void gl_nodes(int n, const double **t, const double **w)
     *w = gl_w[n];
 }
 
-void or_project_fn(or_fun1 f, void *ctx, int nodes, double alpha[4])
+/* Degree-n series (n = 1..3) of f on [-1,1] with the endpoint correction of
+ * eqs. poly3, condition1 and alpha; coefficients above n are zero. */
+void or_project_fn_deg(or_fun1 f, void *ctx, int nodes, int degree, double alpha[4])
 {
     const double *t, *w;
     if (nodes <= 0 || nodes > 64)
         nodes = 32;
+    const int n = (degree >= 1 && degree <= 3) ? degree : 3;
     gl_nodes(nodes, &t, &w);
     double a[4] = {0, 0, 0, 0};
     for (int q = 0; q < nodes; ++q) {
         double L[4];
         legendre4(t[q], L);
         double fq = f(t[q], ctx);
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j <= n; ++j)
             a[j] += w[q] * fq * L[j];
     }
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j <= n; ++j)
         a[j] *= (2.0 * j + 1.0) / 2.0;
     /* eq. condition1: the corrected polynomial must equal f at both ends.
-     * P(1) = sum_j a_j, P(-1) = sum_j (-1)^j a_j; adding e0 L2 + e1 L3 with
-     * L2(+-1) = 1 and L3(+-1) = +-1 gives e0 + e1 = f(1) - P(1) and
-     * e0 - e1 = f(-1) - P(-1). */
+     * With P(1) = sum_j a_j and P(-1) = sum_j (-1)^j a_j, the corrections
+     * e0 (on L_{n-1}) and e1 (on L_n) satisfy, since L_j(+-1) = (+-1)^j,
+     *   e0 + e1 = f(1) - P(1) =: ep,
+     *   (-1)^(n-1) e0 + (-1)^n e1 = f(-1) - P(-1) =: em.
+     * n odd: e0 - e1 = em; n even: -e0 + e1 = em. */
     double fp = f(1.0, ctx), fm = f(-1.0, ctx);
-    double ep = fp - (a[0] + a[1] + a[2] + a[3]);
-    double em = fm - (a[0] - a[1] + a[2] - a[3]);
-    double e0 = 0.5 * (ep + em), e1 = 0.5 * (ep - em);
-    alpha[0] = a[0];
-    alpha[1] = a[1];
-    alpha[2] = a[2] + e0; /* eq. alpha, j = n-1 */
-    alpha[3] = a[3] + e1; /* eq. alpha, j = n */
+    double Pp = 0.0, Pm = 0.0;
+    for (int j = 0; j <= n; ++j) {
+        Pp += a[j];
+        Pm += (j & 1) ? -a[j] : a[j];
+    }
+    double ep = fp - Pp, em = fm - Pm;
+    double e0, e1;
+    if (n & 1) {
+        e0 = 0.5 * (ep + em);
+        e1 = 0.5 * (ep - em);
+    } else {
+        e0 = 0.5 * (ep - em);
+        e1 = 0.5 * (ep + em);
+    }
+    for (int j = 0; j < 4; ++j)
+        alpha[j] = j <= n ? a[j] : 0.0;
+    alpha[n - 1] += e0; /* eq. alpha, j = n-1 */
+    alpha[n] += e1;     /* eq. alpha, j = n */
+}
+
+void or_project_fn(or_fun1 f, void *ctx, int nodes, double alpha[4])
+{
+    or_project_fn_deg(f, ctx, nodes, 3, alpha);
 }
 
 typedef struct {
@@ -181,14 +208,21 @@ static double gauss1(double t, void *vctx)
     return exp(-g->D * u * u);
 }
 
-/* Projection of the factor of atom coordinate xi on the interval [lo,hi]. */
-void or_project(double D, double lo, double hi, double xi, int nodes, double alpha[4])
+/* Projection of the factor of atom coordinate xi on the interval [lo,hi],
+ * series of degree n (1..3). */
+void or_project_deg(double D, double lo, double hi, double xi, int nodes, int degree,
+                    double alpha[4])
 {
     gauss1_ctx g;
     g.D = D;
     g.s = 0.5 * (hi - lo);
     g.delta = 0.5 * (lo + hi) - xi;
-    or_project_fn(gauss1, &g, nodes, alpha);
+    or_project_fn_deg(gauss1, &g, nodes, degree, alpha);
+}
+
+void or_project(double D, double lo, double hi, double xi, int nodes, double alpha[4])
+{
+    or_project_deg(D, lo, hi, xi, nodes, 3, alpha);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -407,7 +441,7 @@ void or_phi_adjoint(const double *xyzr, int64_t n, double D, double eps_cut, con
 /* j: x-degree, k: y-degree, l: z-degree; flat index 16 j + 4 k + l.          */
 /* ------------------------------------------------------------------------ */
 
-static int64_t cube_tensor(const or_bins *b, double D, double rc2, int nodes,
+static int64_t cube_tensor(const or_bins *b, double D, double rc2, int nodes, int degree,
                            const double lo[3], const double hi[3], double A[64])
 {
     const double *xyzr = b->xyzr;
@@ -419,9 +453,9 @@ static int64_t cube_tensor(const or_bins *b, double D, double rc2, int nodes,
         const double *x = xyzr + 4 * i;
         if (box_dist2(x, lo, hi) <= rc2) {
             double ax[4], ay[4], az[4];
-            or_project(D, lo[0], hi[0], x[0], nodes, ax);
-            or_project(D, lo[1], hi[1], x[1], nodes, ay);
-            or_project(D, lo[2], hi[2], x[2], nodes, az);
+            or_project_deg(D, lo[0], hi[0], x[0], nodes, degree, ax);
+            or_project_deg(D, lo[1], hi[1], x[1], nodes, degree, ay);
+            or_project_deg(D, lo[2], hi[2], x[2], nodes, degree, az);
             double w = exp(D * x[3] * x[3]);
             for (int j = 0; j < 4; ++j)
                 for (int k = 0; k < 4; ++k)
@@ -439,7 +473,7 @@ void or_cube_tensor(const double *xyzr, int64_t n, double D, double eps_cut, int
     double rc2 = or_cutoff2(xyzr, n, D, eps_cut);
     or_bins b;
     bins_build(&b, xyzr, n, sqrt(rc2));
-    int64_t c = cube_tensor(&b, D, rc2, nodes, lo, hi, A);
+    int64_t c = cube_tensor(&b, D, rc2, nodes, 3, lo, hi, A);
     if (n_nb) *n_nb = c;
     bins_free(&b);
 }
@@ -458,9 +492,52 @@ double or_tensor_eval(const double A[64], double x, double y, double z)
     return s;
 }
 
-/* Reading of Step 3's stopping rule ("coefficients of higher order terms
- * (higher than the linear order) ... under some user-specified bound"): the
- * absolute l1 mass of the 56 entries with max(j,k,l) >= 2. */
+/* The parent's polynomial written in the Legendre basis of one of its eight
+ * children (eq. childtensor).  Child `octant` (bit 0: x, 1: y, 2: z; a set
+ * bit is the upper half) covers parent coordinates u = (t + s) / 2 with
+ * t in [-1,1] the child's coordinate and s = -1 or +1.  Along one axis the
+ * child coefficients of a parent basis polynomial L_i are its Legendre
+ * projection on the child,
+ *   M[j][i] = (2j+1)/2 int_{-1}^{1} L_i((t + s)/2) L_j(t) dt,
+ * computed by Gauss-Legendre quadrature with 8 nodes (exact: the integrand
+ * has degree <= 6); then A'[j][k][l] = sum over (i, i', i'') of
+ * Mx[j][i] My[k][i'] Mz[l][i''] A[i][i'][i''].  The child polynomial equals
+ * the parent's on the child exactly (degree <= 3 both). */
+void or_child_tensor(const double Ap[64], int octant, double Ac[64])
+{
+    const double *t, *w;
+    gl_nodes(8, &t, &w);
+    double M[3][4][4];
+    for (int a = 0; a < 3; ++a) {
+        const double s = ((octant >> a) & 1) ? 1.0 : -1.0;
+        for (int j = 0; j < 4; ++j)
+            for (int i = 0; i < 4; ++i) {
+                double acc = 0.0;
+                for (int q = 0; q < 8; ++q) {
+                    double Lu[4], Lt[4];
+                    legendre4(0.5 * (t[q] + s), Lu);
+                    legendre4(t[q], Lt);
+                    acc += w[q] * Lu[i] * Lt[j];
+                }
+                M[a][j][i] = 0.5 * (2.0 * j + 1.0) * acc;
+            }
+    }
+    for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l) {
+                double acc = 0.0;
+                for (int i = 0; i < 4; ++i)
+                    for (int i2 = 0; i2 < 4; ++i2)
+                        for (int i3 = 0; i3 < 4; ++i3)
+                            acc += M[0][j][i] * M[1][k][i2] * M[2][l][i3] *
+                                   Ap[16 * i + 4 * i2 + i3];
+                Ac[16 * j + 4 * k + l] = acc;
+            }
+}
+
+/* Reading of Step 3's stopping rule (the coefficients beyond the linear
+ * terms must fall under a user bound): the absolute l1 mass of the 56
+ * entries with max(j,k,l) >= 2. */
 double or_higher_mass(const double A[64])
 {
     double e = 0.0;
@@ -919,7 +996,8 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
     or_result *R = (or_result *)calloc(1, sizeof(or_result));
     int K = 0;
     if (!(P->D > 0) || !(P->c > 0) || !(P->h0 > 0) || !(P->h_min > 0) || !(P->eps_cut > 0) ||
-        !(P->eps_cut < 1) || !(P->pad >= 0) || n < 0 ||
+        !(P->eps_cut < 1) || !(P->pad >= 0) || n < 0 || P->degree < 0 || P->degree > 3 ||
+        (P->reexpand != 0 && P->reexpand != 1) ||
         (!P->uniform && (!(P->tau > 0) || !is_pow2_ratio(P->h0, P->h_min, &K)))) {
         R->status = -1;
         return R;
@@ -937,6 +1015,8 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
     R->K = K;
     const double D = P->D, c = P->c, h0 = P->h0;
     const int nodes = P->gl_nodes > 0 ? P->gl_nodes : 32;
+    const int degree = P->degree > 0 ? P->degree : 3;
+    const int reexpand = P->reexpand;
 
     /* Initial coarse grid (Section 2.2): reading -- the origin is snapped to
      * a multiple of h0 below the padded atom box, and the grid covers the
@@ -1025,11 +1105,18 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
             }
         free(occ);
 
+        /* with re-expansion: the tensors of the previous level's queue, and
+         * for each cube of the current queue its parent and octant */
+        double *Aprev = NULL;
+        int64_t *par = NULL;
+        uint8_t *oct = NULL;
         for (int lev = 0; lev <= K; ++lev) {
             double h = h0 / (double)(1 << lev);
             R->n_est[lev] = nq;
             /* decision per cube: 0 discard, 1 refine, 2 converged leaf, 3 h_min leaf */
             uint8_t *dec = (uint8_t *)malloc((size_t)(nq ? nq : 1));
+            double *Acur = reexpand ? (double *)malloc(sizeof(double) * 64 * (size_t)(nq ? nq : 1))
+                                    : NULL;
             int64_t pairs = 0, ties = 0;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : pairs, ties)
@@ -1040,8 +1127,14 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
                     lo[a] = R->origin[a] + Q[q].i[a] * h;
                     hi[a] = lo[a] + h;
                 }
-                /* Step 1: the degree-3 tensor polynomial of the cube */
-                pairs += cube_tensor(&bins, D, rc2, nodes, lo, hi, A);
+                /* Step 1: the tensor polynomial of the cube -- projected from
+                 * the atoms, or (re-expansion, below the roots) the parent's
+                 * polynomial in the child's basis (eq. childtensor) */
+                if (reexpand && lev >= 1)
+                    or_child_tensor(Aprev + 64 * par[q], oct[q], A);
+                else
+                    pairs += cube_tensor(&bins, D, rc2, nodes, degree, lo, hi, A);
+                if (Acur) memcpy(Acur + 64 * q, A, sizeof(double) * 64);
                 double E = or_higher_mass(A);
                 double tie = 1.0;
                 /* Step 3 for a child cube: higher-order mass under the
@@ -1096,6 +1189,8 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
                 else { R->n_hmin[lev]++; PUSH_LEAF(Q[q].i[0], Q[q].i[1], Q[q].i[2], lev, OR_REASON_HMIN); }
             }
             cube3 *Qn = (cube3 *)malloc(sizeof(cube3) * (size_t)(nn ? nn : 1));
+            int64_t *parn = reexpand ? (int64_t *)malloc(sizeof(int64_t) * (size_t)(nn ? nn : 1)) : NULL;
+            uint8_t *octn = reexpand ? (uint8_t *)malloc((size_t)(nn ? nn : 1)) : NULL;
             int64_t w = 0;
             for (int64_t q = 0; q < nq; ++q)
                 if (dec[q] == 1)
@@ -1103,13 +1198,26 @@ or_result *or_partition(const double *xyzr, int64_t n, const or_params *P)
                         Qn[w].i[0] = 2 * Q[q].i[0] + (o & 1);
                         Qn[w].i[1] = 2 * Q[q].i[1] + ((o >> 1) & 1);
                         Qn[w].i[2] = 2 * Q[q].i[2] + ((o >> 2) & 1);
+                        if (reexpand) {
+                            parn[w] = q;
+                            octn[w] = (uint8_t)o;
+                        }
                         ++w;
                     }
             free(dec);
             free(Q);
+            free(Aprev);
+            free(par);
+            free(oct);
+            Aprev = Acur;
+            par = parn;
+            oct = octn;
             Q = Qn;
             nq = nn;
         }
+        free(Aprev);
+        free(par);
+        free(oct);
         free(Q);
     }
 
