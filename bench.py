@@ -47,10 +47,14 @@ FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
 OPS_PER_PHI_PAIR = 8 + 4
 # VALU lane-op issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 39.3
-# FP64 flops the nested-SVD bound executes per hard cube, from the
-# SQ_INSTS_VALU_FLOPS_FP64 counter over the pass's k_bound launches divided by
-# the hard cubes (profiles/bound_assembly110k_counters.md); None until counted
-FLOP_PER_HARD_CUBE = None
+# FP64 flop slots the nested-SVD bound issues per hard cube: the
+# SQ_INSTS_VALU_FLOPS_FP64 counter over five passes' k_bound launches (it
+# counts per wavefront instruction, FMA as two), times 64 lanes, divided by
+# the hard cubes of those passes (profiles/bound_assembly110k_counters.md).
+# Lanes masked off by divergence are included, so it is an upper bound on the
+# flops the bound needs; the number of Jacobi sweeps and of inner problems
+# varies per cube, so there is no fixed algorithmic count.
+FLOP_PER_HARD_CUBE = 9256
 
 
 def log(*a):
@@ -393,7 +397,7 @@ def main():
     p_ms, p_n = launch_avg("phi")
     phi_ach = f32["phi_pairs"] / p_n * OPS_PER_PHI_PAIR / (p_ms * 1e-3) / 1e12
     rooflines = [roofline, {
-        "bound": "alu", "kernel": "k_phi_points<FAST> (corner values)",
+        "bound": "alu", "kernel": "k_phi_corners<FAST> (corner values)",
         "achieved": phi_ach, "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-op/s",
         "frac": phi_ach / PEAK_VALU_TOPS, "traffic": None,
         "work_per_unit": "%d lane-ops per in-range (point, atom) pair (8 VALU + one "
@@ -406,7 +410,7 @@ def main():
             "bound": "alu", "kernel": "k_bound (nested-SVD bound of the hard cubes)",
             "achieved": b_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": b_ach / PEAK_FP64_TFLOPS, "traffic": None,
-            "work_per_unit": "%d FP64 flop per hard cube (executed, from counters)"
+            "work_per_unit": "%d FP64 flop slots issued per hard cube (from counters)"
                              % FLOP_PER_HARD_CUBE,
             "units_per_launch": st["n_bound"] / b_n, "avg_launch_ms": b_ms})
 

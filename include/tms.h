@@ -58,6 +58,15 @@ extern "C" {
 #define TMS_MODE_ADAPTIVE 0 /* Section 2.2 Steps 1-3: estimate, bound, divide   */
 #define TMS_MODE_UNIFORM 1  /* plain method: every cube of the h0 grid is a leaf */
 
+/* ---- tensors of the cubes below the roots (Section 2.2.3) ---------------- */
+#define TMS_CHILD_PROJECT 0  /* projected from the atoms again on every child    */
+                             /* (the default; Step 3 computes the expression of  */
+                             /* P in each child)                                  */
+#define TMS_CHILD_REEXPAND 1 /* the parent's polynomial written in the child's   */
+                             /* Legendre basis (eq. childtensor): only the roots  */
+                             /* loop over atoms.  The root-level approximation    */
+                             /* error is carried down unchanged                   */
+
 /* ---- leaf reasons and classes ------------------------------------------ */
 #define TMS_REASON_UNIFORM 0   /* uniform mode                                   */
 #define TMS_REASON_CONVERGED 1 /* higher-order mass 2E <= tau (Step 3)          */
@@ -83,11 +92,18 @@ typedef struct tms_cells tms_cells;
  *  pad     margin added around the atom bounding box (>= 0)
  *  eps_cut every Gaussian term below eps_cut is dropped: the sums run over
  *          atoms within R_c, R_c^2 = max r_i^2 + ln(1/eps_cut)/D (0 < eps_cut < 1)
- *  precision TMS_PREC_*;  mode TMS_MODE_*                                    */
+ *  precision TMS_PREC_*;  mode TMS_MODE_*
+ *  degree  degree n of the 1-D Legendre series of each Gaussian factor
+ *          (Section 2.2.1, eqs. poly2_1 to alpha): 1, 2 or 3 (0 means 3, the
+ *          paper's choice); the endpoint corrections go on L_{n-1} and L_n
+ *          and the tensor entries above n are zero
+ *  child_tensor TMS_CHILD_* (adaptive mode)                                  */
 typedef struct {
     double D, c, tau, h0, h_min, pad, eps_cut;
     int32_t precision;
     int32_t mode;
+    int32_t degree;
+    int32_t child_tensor;
 } tms_params;
 
 /* One leaf cube: the closed box origin + [i, i+1] * h0 / 2^level per axis.

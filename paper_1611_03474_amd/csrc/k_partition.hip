@@ -62,6 +62,8 @@ struct EstOut {
                             // launch is sized by a capacity; null: the launch size
     unsigned *tick = nullptr;  // [8] zeroed slot counters (persistent tiled grid)
     unsigned *ovf = nullptr;   // set when a capacity-sized tiled grid is short of chunks
+    double *allA = nullptr;    // [n][64]: every entry's tensor (children re-expanded
+                               // from their parents' next level), or null
 };
 
 constexpr uint8_t DEC_HARD = 255;
@@ -126,6 +128,11 @@ __device__ __forceinline__ uint8_t easy_decision(const Grid &g, int level, bool 
 __device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, const double *A,
                                          double EA, int64_t qi, bool valid, const EstOut &o) {
     const uint8_t d = valid ? easy_decision(g, level, fast, A, EA) : (uint8_t)0;
+    if (o.allA && valid) {
+        double *dst = o.allA + 64 * qi;
+#pragma unroll
+        for (int e = 0; e < 64; ++e) dst[e] = A[e];
+    }
     const bool hard = valid && d == DEC_HARD;
     const unsigned slot = wave_append(o.hardCount, hard);
     if (hard) {
@@ -251,11 +258,11 @@ __global__ __launch_bounds__(kBS) void k_estimate_thread(
             ++np;
             double px[4], py[4], pz[4], ex, ey, ez;
             if (!P.t || !tab_proj(P, 0, i, c.x, proj_first(g, 0, x, rc, h, level), px, ex))
-                project<FAST, QH>(R, g.D, s, mid[0] - x, px, ex);
+                project<FAST, QH>(R, g.D, s, mid[0] - x, g.deg, px, ex);
             if (!P.t || !tab_proj(P, 1, i, c.y, proj_first(g, 1, y, rc, h, level), py, ey))
-                project<FAST, QH>(R, g.D, s, mid[1] - y, py, ey);
+                project<FAST, QH>(R, g.D, s, mid[1] - y, g.deg, py, ey);
             if (!P.t || !tab_proj(P, 2, i, c.z, proj_first(g, 2, z, rc, h, level), pz, ez))
-                project<FAST, QH>(R, g.D, s, mid[2] - z, pz, ez);
+                project<FAST, QH>(R, g.D, s, mid[2] - z, g.deg, pz, ez);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const double wx = w * px[j];
@@ -512,7 +519,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
                     src = P.t + 6 * (((int64_t)axis * P.n + b_i[a_idx]) * P.ns + slot);
                 } else {
                     double pr[4], err;
-                    project<FAST, QH>(R, D, s, (lo + s) - xa, pr, err);
+                    project<FAST, QH>(R, D, s, (lo + s) - xa, g.deg, pr, err);
                     t01[w] = make_double2(pr[0], pr[1]);
                     t23[w] = make_double2(pr[2], pr[3]);
                     ted[w] = make_double2(err, dd);
@@ -761,7 +768,7 @@ __global__ __launch_bounds__(64, 2) void k_estimate_groups(
                     src = P.t + 6 * (((int64_t)axis * P.n + b_i[gr][a_idx]) * P.ns + slot);
                 } else {
                     double pr[4], err;
-                    project<FAST, QH>(R, D, s, (lo + s) - xa, pr, err);
+                    project<FAST, QH>(R, D, s, (lo + s) - xa, g.deg, pr, err);
                     t01[slot_lds] = make_double2(pr[0], pr[1]);
                     t23[slot_lds] = make_double2(pr[2], pr[3]);
                     ted[slot_lds] = make_double2(err, dd);
@@ -871,7 +878,7 @@ __global__ void k_proj_table(const Grid *__restrict__ gt, int nconf, int level, 
     const double lo = g.o[axis] + (double)(first + slot) * h, hi = lo + h;
     const double d = fmax(fmax(lo - x, x - hi), 0.0);
     double pr[4] = {0.0, 0.0, 0.0, 0.0}, err = 0.0;
-    if (d * d <= g.rc2) project<FAST, QH>(R, g.D, s, (lo + s) - x, pr, err);
+    if (d * d <= g.rc2) project<FAST, QH>(R, g.D, s, (lo + s) - x, g.deg, pr, err);
     double2 *dst = reinterpret_cast<double2 *>(T + 6 * t);
     dst[0] = make_double2(pr[0], pr[1]);
     dst[1] = make_double2(pr[2], pr[3]);
@@ -1064,7 +1071,7 @@ __global__ void k_level_emit(const int4 *__restrict__ q, const uint8_t *__restri
                              const int32_t *__restrict__ coff, tms_leaf *__restrict__ leaves,
                              int64_t leaf_base, int4 *__restrict__ qn, const int32_t *__restrict__ nd,
                              const int64_t *__restrict__ lbd, int64_t lcap, int64_t qcap,
-                             unsigned *__restrict__ ovf) {
+                             unsigned *__restrict__ ovf, int32_t *__restrict__ qpar) {
     int64_t i = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (i >= n || (nd && i >= (int64_t)*nd)) return;
     const uint8_t d = dec[i];
@@ -1094,7 +1101,75 @@ __global__ void k_level_emit(const int4 *__restrict__ q, const uint8_t *__restri
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             o[k] = make_int4(2 * c.x + (k & 1), 2 * c.y + ((k >> 1) & 1), 2 * c.z + ((k >> 2) & 1), c.w);
+        // the children's parent: next-level entries 8 j .. 8 j + 7 come from
+        // this entry
+        if (qpar) qpar[coff[i] >> 3] = (int32_t)i;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Child tensors by re-expansion (Section 2.2.3, eq. childtensor): the parent's
+// polynomial written in the Legendre basis of the child.  Along one axis the
+// child covers parent coordinates u = (t + s)/2, t in [-1,1], s = -1 (lower
+// half) or +1 (upper half), and
+//   L0(u) = L0,  L1(u) = s/2 L0 + 1/2 L1,  L2(u) = 3s/4 L1 + 1/4 L2,
+//   L3(u) = -s/8 L0 + 3/8 L1 + 5s/8 L2 + 1/8 L3
+// (from (t + s)^2 = t^2 + 2 s t + 1, (t + s)^3 = t^3 + 3 s t^2 + 3 t + s and
+// t^2 = (2 L2 + L0)/3, t^3 = (2 L3 + 3 L1)/5), so a series p becomes
+//   x0 = p0 + s/2 p1 - s/8 p3,  x1 = 1/2 p1 + 3s/4 p2 + 3/8 p3,
+//   x2 = 1/4 p2 + 5s/8 p3,      x3 = 1/8 p3
+// along each axis in turn.  Then the decisions of the estimate epilogue.
+// One thread per child; entries 8 j .. 8 j + 7 of the level (the children of
+// parent qpar[j]) are consecutive, its octant the low bits of its coordinates.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void half_series(double p0, double p1, double p2, double p3, double s,
+                                            double x[4]) {
+    x[0] = p0 + (0.5 * s) * p1 - (0.125 * s) * p3;
+    x[1] = 0.5 * p1 + (0.75 * s) * p2 + 0.375 * p3;
+    x[2] = 0.25 * p2 + (0.625 * s) * p3;
+    x[3] = 0.125 * p3;
+}
+
+__global__ __launch_bounds__(kBS) void k_reexpand(Grid g, int level, const int4 *__restrict__ q,
+                                                  int64_t n, int64_t off,
+                                                  const double *__restrict__ Apar,
+                                                  const int32_t *__restrict__ qpar, EstOut o) {
+    const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
+    const bool valid = t < n;  // every lane reaches the epilogue (wave append)
+    double A[64];
+#pragma unroll
+    for (int e = 0; e < 64; ++e) A[e] = 0.0;
+    if (valid) {
+        const int4 c = q[t];
+        const double *src = Apar + 64 * (int64_t)qpar[(off + t) >> 3];
+#pragma unroll
+        for (int e = 0; e < 64; ++e) A[e] = src[e];
+        const double sx = (c.x & 1) ? 1.0 : -1.0, sy = (c.y & 1) ? 1.0 : -1.0,
+                     sz = (c.z & 1) ? 1.0 : -1.0;
+        double x[4];
+#pragma unroll
+        for (int kl = 0; kl < 16; ++kl) {  // along x: index 16 j + kl
+            half_series(A[kl], A[16 + kl], A[32 + kl], A[48 + kl], sx, x);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) A[16 * j + kl] = x[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {  // along y: index 16 j + 4 k + l
+                const int b = 16 * j + l;
+                half_series(A[b], A[b + 4], A[b + 8], A[b + 12], sy, x);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) A[b + 4 * k] = x[k];
+            }
+#pragma unroll
+        for (int jk = 0; jk < 16; ++jk) {  // along z: index 4 jk + l
+            half_series(A[4 * jk], A[4 * jk + 1], A[4 * jk + 2], A[4 * jk + 3], sz, x);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) A[4 * jk + l] = x[l];
+        }
+    }
+    epilogue(g, level, false, A, 0.0, t, valid, o);
 }
 
 // A batch's leaves come out level by level, conformations in order inside a
@@ -1425,12 +1500,13 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   const double *aw, uint8_t *dec, double *hardA, double *hardE,
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount,
-                                  const ProjTab &pt, unsigned *tick, bool half, unsigned *ovf) {
+                                  const ProjTab &pt, unsigned *tick, bool half, unsigned *ovf,
+                                  double *allA) {
     if (n <= 0) return hipSuccess;
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf, allA};
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
@@ -1462,6 +1538,18 @@ hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level
     if (precision == TMS_PREC_FP32_GUARD)
         return proj_table_dispatch<true>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
     return proj_table_dispatch<false>(qh, gt, nconf, level, ax, ay, az, n, ns, t, s);
+}
+
+hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, int64_t off,
+                          const double *Apar, const int32_t *qpar, uint8_t *dec, double *hardA,
+                          double *hardE, int32_t *hardIdx, unsigned *hardCount, double *allA,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, nullptr};
+    o.allA = allA;
+    hipLaunchKernelGGL(k_reexpand, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, n, off, Apar, qpar,
+                       o);
+    return hipGetLastError();
 }
 
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
@@ -1546,10 +1634,11 @@ hipError_t launch_level_counts(const uint8_t *dec, int64_t n, int32_t *lc, int32
 hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int level,
                              const int32_t *loff, const int32_t *coff, tms_leaf *leaves,
                              int64_t leaf_base, int4 *qn, hipStream_t s, const int32_t *nd,
-                             const int64_t *lbd, int64_t lcap, int64_t qcap, unsigned *ovf) {
+                             const int64_t *lbd, int64_t lcap, int64_t qcap, unsigned *ovf,
+                             int32_t *qpar) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_level_emit, dim3(nblk(n)), dim3(kBS), 0, s, q, dec, n, level, loff, coff,
-                       leaves, leaf_base, qn, nd, lbd, lcap, qcap, ovf);
+                       leaves, leaf_base, qn, nd, lbd, lcap, qcap, ovf, qpar);
     return hipGetLastError();
 }
 

@@ -220,6 +220,11 @@ bool check_params(const tms_params *p, std::string &why, int *Kout) {
         why = "mode must be TMS_MODE_ADAPTIVE or TMS_MODE_UNIFORM";
         return false;
     }
+    if (p->degree < 0 || p->degree > 3) { why = "degree must be 1, 2 or 3 (0: 3)"; return false; }
+    if (p->child_tensor != TMS_CHILD_PROJECT && p->child_tensor != TMS_CHILD_REEXPAND) {
+        why = "child_tensor must be TMS_CHILD_PROJECT or TMS_CHILD_REEXPAND";
+        return false;
+    }
     int K = 0;
     if (p->mode == TMS_MODE_ADAPTIVE) {
         if (!pos(p->tau)) { why = "tau must be finite and > 0"; return false; }
@@ -782,6 +787,7 @@ int32_t build_cells_impl(tms_ctx *ctx, const double *xyzr, const std::vector<int
         g.c = p->c;
         g.tau = p->tau;
         g.K = K;
+        g.deg = p->degree > 0 ? p->degree : 3;
         const double rmax = has ? sb[6] : 0.0;
         cells->rmax = std::max(cells->rmax, rmax);
         g.rc2 = rmax * rmax + std::log(1.0 / p->eps_cut) / p->D;
@@ -1273,6 +1279,8 @@ int32_t capture_args(tms_ctx *ctx, const tms_cells *cells, double margin) {
         return fail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
     if (cells->p.mode != TMS_MODE_ADAPTIVE)
         return fail(ctx, TMS_E_INVALID, "capture takes cells built in adaptive mode");
+    if (cells->p.child_tensor != TMS_CHILD_PROJECT)
+        return fail(ctx, TMS_E_INVALID, "capture takes cells whose child tensors are projected");
     if (!(margin >= 1.0 && margin <= 64.0))
         return fail(ctx, TMS_E_INVALID, "margin must lie in [1, 64]");
     if (ctx->last_stats_cells != cells->id || ctx->edge_cells != cells->id)
@@ -1450,9 +1458,21 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             HIPCK(launch_roots_emit(gt, nconf, ctx->flags.as<int32_t>(), ctx->scan_a.as<int32_t>(),
                                     nr, ctx->q[0].as<int4>(), s));
         }
+        // re-expanded child tensors (eq. childtensor): every level below K
+        // keeps its entries' tensors for its children, which take them from
+        // there instead of projecting the atoms
+        const bool reex = cells->p.child_tensor == TMS_CHILD_REEXPAND;
         for (int lev = 0; lev <= g.K && nq > 0; ++lev) {
             if (nq >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "queue too large");
             st.n_est[lev] = nq;
+            const bool reex_lev = reex && lev >= 1;
+            double *allA = nullptr;
+            if (reex && lev < g.K) {
+                if (ctx->asave[lev & 1].ensure(sizeof(double) * 64 * (size_t)nq) != hipSuccess)
+                    return fail(ctx, TMS_E_OOM, "re-expansion needs %.3g GB for the tensors of level %d",
+                                64.0 * 8.0 * (double)nq * 1e-9, lev);
+                allA = ctx->asave[lev & 1].as<double>();
+            }
             // the tensors of the cubes that need the bound are staged in
             // slices of at most slice_cubes queue entries
             // (equal slices: ceil(nq / slice_cubes) of them)
@@ -1473,7 +1493,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             HIPCK(hipMemsetAsync(ctr + kSliceCtr, 0, 2 * kMaxSlices * sizeof(unsigned long long), s));
             const int4 *q = ctx->q[cur].as<int4>();
             // deep levels: chunks of <= 64 consecutive cubes of one root
-            const bool tiled = lev >= ctx->tiled_min_level && lev <= 3;
+            const bool tiled = !reex_lev && lev >= ctx->tiled_min_level && lev <= 3;
             const bool half = tiled && half_level(ctx, lev);
             int64_t level_chunks = 0;
             ProjTab pt;
@@ -1489,7 +1509,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
             const int pns = proj_table_slots(cells, lev);
             // a table that does not fit in device memory leaves the level to
             // in-place projections
-            if (ctx->proj_table &&
+            if (!reex_lev && ctx->proj_table &&
                 ctx->ptab.ensure(sizeof(double) * 6 * 3 * (size_t)cells->n * (size_t)pns) ==
                     hipSuccess) {
                 const int ns = pns;
@@ -1533,7 +1553,15 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                     tick = ctx->tick.as<unsigned>();
                     HIPCK(launch_fill_u32(ctx->tick.as<uint32_t>(), 0u, 8, s));
                 }
-                {  // Step 1 (tensor) and the decisions that need no bound
+                if (reex_lev) {  // Step 1 by re-expansion, and the easy decisions
+                    TimedScope ts_(ctx, TMS_T_ESTIMATE);
+                    HIPCK(launch_reexpand(g, lev, q + off, ns, off,
+                                          ctx->asave[(lev - 1) & 1].as<double>(),
+                                          ctx->qpar.as<int32_t>(), ctx->dec.as<uint8_t>() + off,
+                                          ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
+                                          ctx->hidx.as<int32_t>(), hard,
+                                          allA ? allA + 64 * off : nullptr, s));
+                } else {  // Step 1 (tensor) and the decisions that need no bound
                     TimedScope ts_(ctx, !tiled ? TMS_T_ESTIMATE
                                                : (lev <= 1 ? TMS_T_GROUPED : TMS_T_TILED));
                     HIPCK(launch_estimate_decide(
@@ -1543,7 +1571,8 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         cells->aw.as<double>(), ctx->dec.as<uint8_t>() + off,
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
                         hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s, nullptr,
-                        pt, half ? nullptr : tick, half));
+                        pt, half ? nullptr : tick, half, nullptr,
+                        allA ? allA + 64 * off : nullptr));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
@@ -1591,11 +1620,13 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 return fail(ctx, TMS_E_INVALID, "level %d too large (32-bit offsets)", lev);
             HIPCK(grow_keep(ctx->leaves, sizeof(tms_leaf) * (size_t)(L + nl), sizeof(tms_leaf) * (size_t)L, s));
             HIPCK(ctx->q[cur ^ 1].ensure(sizeof(int4) * (size_t)std::max<int64_t>(nc, 1)));
+            if (reex) HIPCK(ctx->qpar.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nc / 8, 1)));
             {
                 TimedScope ts_(ctx, TMS_T_COMPACT);
                 HIPCK(launch_level_emit(q, ctx->dec.as<uint8_t>(), nq, lev, ctx->scan_a.as<int32_t>(),
                                         ctx->scan_b.as<int32_t>(), ctx->leaves.as<tms_leaf>(), L,
-                                        ctx->q[cur ^ 1].as<int4>(), s));
+                                        ctx->q[cur ^ 1].as<int4>(), s, nullptr, nullptr, 0, 0,
+                                        nullptr, reex ? ctx->qpar.as<int32_t>() : nullptr));
             }
             L += nl;
             nq = nc;

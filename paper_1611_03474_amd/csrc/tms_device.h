@@ -54,10 +54,17 @@ __device__ __forceinline__ double expn(double x) {
 // and with c0, c1 >= 0 at the positive nodes and f > 0,
 //   |da0| <= eps a0,  |da1| <= eps b1,  b1 = sum_q c1_q (f(t_q) + f(-t_q)),
 // so sum_j |da~_j| <= eps (2 a0 + 2 b1 + f(1) + f(-1)).
+//
+// deg < 3 (Section 2.2.1 with n = deg): the series stops at L_deg (higher
+// coefficients 0) and the endpoint corrections go on L_{n-1} and L_n, solved
+// from eq. condition1 with L_j(+-1) = (+-1)^j: for odd n, e0 = (ep + em)/2
+// on L_{n-1} and e1 = (ep - em)/2 on L_n; for even n the two swap.  The same
+// cancellation leaves an error of at most eps (2 a0 + f(1) + f(-1)) (n = 2)
+// or eps (f(1) + f(-1)) (n = 1), below the bound above.
 // ---------------------------------------------------------------------------
 template <bool FAST, int QH>
 __device__ __forceinline__ void project(const GLRule<double> &R, double D, double s, double d,
-                                        double a[4], double &err) {
+                                        int deg, double a[4], double &err) {
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0, sf = 0;
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
@@ -71,16 +78,23 @@ __device__ __forceinline__ void project(const GLRule<double> &R, double D, doubl
         a3 += R.c3[q] * od;
         if (FAST) sf += R.c1[q] * ev;
     }
-    // eq. condition1: match f at t = +-1 by adding e0 L2 + e1 L3
+    // eq. condition1: match f at t = +-1 by adding e0 L_{n-1} + e1 L_n
     const double f1 = expn<FAST>(-D * (s + d) * (s + d));
     const double fm1 = expn<FAST>(-D * (d - s) * (d - s));
+    err = FAST ? kFastExpErr * (2.0 * (a0 + sf) + f1 + fm1) : 0.0;
+    // the series stops at L_deg; the even-index correction goes on L2 (on L0
+    // when deg = 1), the odd one on L_deg's odd neighbour (L3 when deg = 3,
+    // else L1).  Selects, not branches: with deg = 3 the operations are those
+    // of the degree-3 formula
+    a2 = deg >= 2 ? a2 : 0.0;
+    a3 = deg >= 3 ? a3 : 0.0;
     const double ep = f1 - (a0 + a1 + a2 + a3);
     const double em = fm1 - (a0 - a1 + a2 - a3);
-    a[0] = a0;
-    a[1] = a1;
-    a[2] = a2 + 0.5 * (ep + em);
-    a[3] = a3 + 0.5 * (ep - em);
-    err = FAST ? kFastExpErr * (2.0 * (a0 + sf) + f1 + fm1) : 0.0;
+    const double ee = 0.5 * (ep + em), eo = 0.5 * (ep - em);
+    a[0] = deg == 1 ? a0 + ee : a0;
+    a[1] = deg <= 2 ? a1 + eo : a1;
+    a[2] = deg >= 2 ? a2 + ee : 0.0;
+    a[3] = deg >= 3 ? a3 + eo : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -48,6 +48,7 @@ struct Grid {
     int32_t nr[3];   // root cubes per axis
     int32_t nc[3];   // atom cells per axis
     int32_t K;       // finest level
+    int32_t deg;     // degree n of the 1-D series (1..3; entries above n are 0)
     int32_t span;    // cell stencil half-width, ceil(R_c / cs)
     int64_t root_base;  // first root / cell / atom of this conformation in the
     int64_t cell_base;  // batch-wide root, cell and atom arrays
@@ -99,9 +100,29 @@ enum : uint8_t {
 // ---------------------------------------------------------------------------
 // Device buffer that only grows.
 // ---------------------------------------------------------------------------
+// Device buffer, grow-only; freed by release() or when its owner (a context,
+// cells or graph state) is deleted, with the owner's device current.
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), cap(o.cap) {
+        o.p = nullptr;
+        o.cap = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            cap = o.cap;
+            o.p = nullptr;
+            o.cap = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
     hipError_t ensure(size_t bytes);
     void release();
     template <typename T>
@@ -233,6 +254,9 @@ struct tms_ctx {
     int corner_reach = 48;  // their reach, in R_c / 16
     int proj_table = 1;     // tiled levels gather 1-D projections from a table
     tms::DevBuf ptab;       // that table
+    tms::DevBuf asave[2];   // re-expanded child tensors: every entry's tensor of
+                            // the last two levels (by queue index)
+    tms::DevBuf qpar;       // parent queue index of each group of 8 children
     tms::DevBuf tick;       // [8] chunk slot counters of the tiled estimate
     bool tiled_dyn = false; // eager tiled launches draw chunks from them
     tms::DevBuf counters;
@@ -350,7 +374,8 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
                                   const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr,
-                                  bool half = false, unsigned *ovf = nullptr);
+                                  bool half = false, unsigned *ovf = nullptr,
+                                  double *allA = nullptr);
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
 // fill the projection table (t: [3 n ns][6] doubles)
@@ -396,7 +421,16 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
                              const int32_t *leaf_off, const int32_t *child_off, tms_leaf *leaves,
                              int64_t leaf_base, int4 *qnext, hipStream_t s,
                              const int32_t *nd = nullptr, const int64_t *leaf_base_dev = nullptr,
-                             int64_t leaf_cap = 0, int64_t queue_cap = 0, unsigned *ovf = nullptr);
+                             int64_t leaf_cap = 0, int64_t queue_cap = 0, unsigned *ovf = nullptr,
+                             int32_t *qpar = nullptr);
+// child tensors re-expanded from their parents' (eq. childtensor) for n
+// entries of a level starting at off (q, dec, hard list as for the estimate);
+// Apar: the previous level's tensors by queue index, qpar[j]: the parent of
+// entries 8 j .. 8 j + 7; allA: where the children's tensors go (or null)
+hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, int64_t off,
+                          const double *Apar, const int32_t *qpar, uint8_t *dec, double *hardA,
+                          double *hardE, int32_t *hardIdx, unsigned *hardCount, double *allA,
+                          hipStream_t s);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
                               unsigned long long *part, hipStream_t s, const int32_t *nd = nullptr);
 // regrouping of a batch's leaves by conformation (segments level * nconf + conf)

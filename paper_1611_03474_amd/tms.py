@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libtms.so")
 TMS_OK, TMS_E_INVALID, TMS_E_CAPACITY, TMS_E_DEVICE, TMS_E_OOM = 0, -1, -2, -3, -4
 PREC_FP64, PREC_FP32_GUARD = 0, 1
 MODE_ADAPTIVE, MODE_UNIFORM = 0, 1
+CHILD_PROJECT, CHILD_REEXPAND = 0, 1
 REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN = 0, 1, 2
 CLS_OUTSIDE, CLS_SURFACE, CLS_INSIDE = 0, 1, 2
 MAX_LEVELS = 8
@@ -62,7 +63,8 @@ class TmsError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("D", C.c_double), ("c", C.c_double), ("tau", C.c_double), ("h0", C.c_double),
                 ("h_min", C.c_double), ("pad", C.c_double), ("eps_cut", C.c_double),
-                ("precision", C.c_int32), ("mode", C.c_int32)]
+                ("precision", C.c_int32), ("mode", C.c_int32), ("degree", C.c_int32),
+                ("child_tensor", C.c_int32)]
 
 
 _I64L = C.c_int64 * MAX_LEVELS
@@ -151,10 +153,11 @@ def load_library(path: str = LIB_PATH):
 
 
 def make_params(D=0.9, c=1.0, tau=1e-3, h0=2.0, h_min=0.25, pad=3.0, eps_cut=1e-10,
-                precision=PREC_FP64, mode=MODE_ADAPTIVE) -> Params:
+                precision=PREC_FP64, mode=MODE_ADAPTIVE, degree=3,
+                child_tensor=CHILD_PROJECT) -> Params:
     return Params(D=float(D), c=float(c), tau=float(tau), h0=float(h0), h_min=float(h_min),
                   pad=float(pad), eps_cut=float(eps_cut), precision=int(precision),
-                  mode=int(mode))
+                  mode=int(mode), degree=int(degree), child_tensor=int(child_tensor))
 
 
 def check_params(p: Params):

@@ -41,7 +41,8 @@ def test_library_loads_and_binds():
 def test_struct_layouts():
     assert tms.LEAF_DTYPE.itemsize == 20
     assert tms.VERTEX_DTYPE.itemsize == 40
-    assert C_sizeof(tms.Params) == 7 * 8 + 2 * 4
+    assert C_sizeof(tms.Params) == 7 * 8 + 4 * 4
+    assert C_sizeof(tms.Tuning) == 8 + 8 * 4
 
 
 def C_sizeof(t):
@@ -52,7 +53,7 @@ def C_sizeof(t):
 @pytest.mark.parametrize("field,value", [
     ("D", 0.0), ("D", -1.0), ("D", math.nan), ("c", 0.0), ("tau", 0.0), ("h0", 0.0),
     ("h_min", -0.25), ("pad", -1.0), ("eps_cut", 0.0), ("eps_cut", 1.0), ("precision", 7),
-    ("mode", 3)])
+    ("mode", 3), ("degree", 4), ("degree", -1), ("child_tensor", 2)])
 def test_check_params_rejects(field, value):
     p = tms.make_params()
     setattr(p, field, value)
