@@ -146,6 +146,39 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
                 stage2=stage2, graph_ms_per_step=spread(g_ms)["mean"], graph_step_ms=spread(g_ms))
 
 
+def run_variants(ctx, tms, atoms_dev, w, steps, warmup):
+    """The estimator variants (Section 2.2) on the benchmark's workload,
+    FP32+guard: child tensors re-expanded from the parent (eq. childtensor)
+    and the degree-2 series; partition with corner classification, cubes
+    estimated per second."""
+    import torch
+    out = {}
+    for name, kw in (("reexpand", dict(child_tensor=tms.CHILD_REEXPAND)),
+                     ("degree2", dict(degree=2))):
+        p = w.params(tms.PREC_FP32_GUARD)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        cells = ctx.build_cells(atoms_dev, p)
+        leaves, cphi, st = ctx.partition_estimate(cells)
+        lb = torch.empty((leaves.shape[0] + 1024, 20), dtype=torch.uint8, device=ctx.device)
+        cb = torch.empty((leaves.shape[0] + 1024, 8), dtype=torch.float64, device=ctx.device)
+        del leaves, cphi
+        step = lambda: ctx.partition_into(cells, lb, cb)
+        for _ in range(warmup):
+            step()
+        ms, (nl, s) = timed_steps(step, steps)
+        sd = s.as_dict()
+        est = int(sum(sd["n_est"]))
+        med = spread(ms)["median"]
+        out[name] = {"ms_median": med, "step_ms": spread(ms), "cubes_estimated": est,
+                     "cubes_per_s": est / (med * 1e-3), "leaves": int(nl),
+                     "surface_leaves": int(sd["n_surface"]), "pairs": int(sd["n_pairs"]),
+                     "bound_cubes": int(sd["n_bound"])}
+        ctx.free_cells(cells)
+        del lb, cb
+    return out
+
+
 def run_adjoint(ctx, tms, steps, warmup):
     """Differentiation workload: forward pass (partition, corners, edge
     points) and the adjoint of the surface loss on a 20,000-atom globule."""
@@ -318,6 +351,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the estimator variants (re-expanded children, degree 2)")
     ap.add_argument("--workload", default="assembly110k")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device-to-device copy first (counter scale for HBM traffic)")
@@ -468,6 +503,10 @@ def main():
         log("  %.1f ms per batched pass, %.1f ms looped FP32+guard, %.1f ms looped FP64"
             % (out["batch"]["ms_per_pass"], out["batch"]["loop_fp32g_ms"],
                out["batch"]["loop_fp64_ms"]))
+    if not args.no_variants:
+        log("estimator variants")
+        out["variants"] = run_variants(ctx, tms, atoms_dev, w, args.steps, args.warmup)
+        log("  %s" % {k: round(v["ms_median"], 2) for k, v in out["variants"].items()})
     if not args.no_adjoint:
         log("adjoint run")
         out["adjoint"] = run_adjoint(ctx, tms, args.steps, args.warmup)

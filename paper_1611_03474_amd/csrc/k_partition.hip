@@ -531,7 +531,8 @@ __global__ __launch_bounds__(64, 2) void k_estimate_tiled(
                 __builtin_amdgcn_global_load_lds(src + 4, (lds_ptr)(ted + k0), 16, 0, 0);
             }
         }
-        if (lane < na) tw[lane] = b_w[(bs + lane) & (NB - 1)];
+        // a tile holds up to NA atoms (more than 64 with 32-atom tiles)
+        for (int a = lane; a < na; a += 64) tw[a] = b_w[(bs + a) & (NB - 1)];
         // keep the copies issued here ahead of the update that follows
         __builtin_amdgcn_sched_barrier(0);
         bs = (bs + na) & (NB - 1);

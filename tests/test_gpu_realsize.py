@@ -58,3 +58,27 @@ def test_assembly_slice_parity(ctx):
     got, _ = compare(ctx, atoms, tms.PREC_FP32_GUARD, D=w.D, ref=ref, label="assembly slice",
                      **_wkw(w))
     assert len(got["leaves"]) > 2_000_000
+
+
+@pytest.mark.parametrize("prec", [tms.PREC_FP64, tms.PREC_FP32_GUARD], ids=["fp64", "fp32g"])
+def test_tile_sizes_bit_identical_globule5k_D05(ctx, prec):
+    # 32-atom tiles hold up to 85 atoms for a chunk of one 2 x 2 x 2 block
+    # (six intervals in all); at D = 0.5 (R_c = 7 A) such chunks see more
+    # than 64 atoms, so a tile's weights must be staged beyond one wavefront
+    w = workloads.GLOBULE5K[0.5]
+    atoms = workloads.atoms(w)
+    cells = ctx.build_cells(atoms, w.params(prec))
+    base = ctx.get_tuning().as_dict()
+    try:
+        ref = None
+        for ch in (8, 16, 32):
+            ctx.set_tuning(tile_atoms=ch)
+            leaves, cphi, st = ctx.partition_estimate(cells)
+            got = (leaves.cpu().numpy().tobytes(), cphi.cpu().numpy().tobytes(),
+                   list(st["n_est"]), st["n_bound"])
+            if ref is None:
+                ref = got
+            assert got == ref, ch
+    finally:
+        ctx.set_tuning(**base)
+        ctx.free_cells(cells)
