@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # known size (FETCH x2.0, WRITE x1.0), mean of the level-2 and level-3
 # launches on the 110,000-atom assembly (profiles/estimate_tiled_assembly110k_traffic.md);
 # None when the kernel changed since the counters were taken
-TRAFFIC_TILED = 12.16e9
+TRAFFIC_TILED = 12.23e9
 
 # algorithmic work per unit
 FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
@@ -50,7 +50,7 @@ PEAK_VALU_TOPS = 39.3
 # FP64 flop slots the nested-SVD bound issues per hard cube: the
 # SQ_INSTS_VALU_FLOPS_FP64 counter over five passes' k_bound launches (it
 # counts per wavefront instruction, FMA as two), times 64 lanes, divided by
-# the hard cubes of those passes (profiles/bound_assembly110k_counters.md).
+# the hard cubes of those passes (profiles/counters_assembly110k_fp32guard.md).
 # Lanes masked off by divergence are included, so it is an upper bound on the
 # flops the bound needs; the number of Jacobi sweeps and of inner problems
 # varies per cube, so there is no fixed algorithmic count.
