@@ -445,6 +445,75 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
                          tms_vertex *verts, int64_t vert_cap, int64_t *n_verts,
                          int64_t *leaf_offsets, int64_t *vertex_offsets, tms_stats *stats);
 
+/* ---- host Stage 2: the mesh (Section 2.3, manifold checks of Section 3.2) ---
+ * The trilinear surface g = c (eq. linear1) of every SURFACE leaf as
+ * triangles on the leaves' edge points (eq. intersection).  On each face of a
+ * leaf the curve g = c is a hyperbola branch joining the face's edge points in
+ * pairs (two points: joined; four: by the value of g at the face's saddle
+ * point, the same on both leaves sharing the face); the face segments link
+ * into closed loops on the cube's boundary, and each loop's patch is
+ * triangulated by ear clipping in the plane normal to an axis along which it
+ * projects to a simple polygon (the single-valued direction of the patch),
+ * else fanned from its first point (counted).  Triangles point along -grad g
+ * (outward, phi >= c inside).  Host code (threads); the inputs are copied
+ * from the device.
+ *
+ * tms_mesh_build: cells of one conformation; leaves [n] and corner_phi [n][8]
+ *   as tms_partition_estimate wrote them, verts [nv] as
+ *   tms_extract_cube_vertices wrote them for those leaves (device pointers).
+ *   The mesh's vertices are the nv edge points in that (key) order.  Every
+ *   SURFACE leaf must have the same level (faces between cubes of different
+ *   sizes are not meshed).  *out receives a mesh owned by the caller (free it
+ *   with tms_mesh_free).  An edge point within 1e-6 of its edge from a corner
+ *   (a corner value equal to c puts three points on the corner) is moved to
+ *   1e-6 of the edge from it, in the triangulation and in xyz.
+ *   Errors: TMS_E_INVALID (arguments, several levels,
+ *   an edge point missing from verts), TMS_E_DEVICE.
+ * tms_mesh_info: vertex and triangle counts, loops, fanned loops, and the
+ *   faces of SURFACE leaves whose corner values cross c but that have no
+ *   SURFACE leaf across (there the bound discarded the neighbouring cube, so
+ *   the surface is open).
+ * tms_mesh_get: host copies: xyz [nv][3], tri [nt][3] (vertex indices),
+ *   tri_leaf [nt] (index of the triangle's leaf in the caller's list); any
+ *   pointer may be NULL.
+ * tms_mesh_check: the three conditions of a manifold mesh (Section 3.2):
+ *   (a) every edge shared by exactly two triangles (and traversed in opposite
+ *   directions), (b) the neighbourhood of every vertex a single loop, (c) no
+ *   intersecting pair of triangles that share no vertex (tested among the
+ *   triangles of the same or touching leaves; skipped, reported -1, when
+ *   intersections = 0).  Non-manifold vertices are those failing (a) or (b).
+ *   Also connected components, Euler characteristic V - E + F, area, enclosed
+ *   volume and vertices per unit area.
+ * tms_mesh_write_off: the mesh as an OFF file. */
+typedef struct tms_mesh tms_mesh;
+typedef struct {
+    int64_t n_vertices, n_triangles, n_loops, n_fallback, open_faces;
+    int64_t boundary_edges;       /* (a): sides in one triangle            */
+    int64_t nonmanifold_edges;    /* (a): sides in more than two triangles */
+    int64_t misoriented_edges;    /* (a): two triangles, same direction    */
+    int64_t nonmanifold_vertices; /* vertices failing (a) or (b)           */
+    int64_t intersecting_pairs;   /* (c), or -1 when not tested           */
+    int64_t components, euler, unused_vertices;
+    double area, volume, density; /* A^2, A^3, vertices per A^2           */
+} tms_mesh_report;
+
+int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
+                       const double *corner_phi, const tms_vertex *verts, int64_t nv,
+                       tms_mesh **out);
+/* The same from host arrays (leaves [n], corner_phi [n][8], verts [nv] in
+ * ascending key order), with the isovalue c, the finest level K and the root
+ * edge h0 of the cells they came from; errors as above, with the message in
+ * msg. */
+int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *corner_phi,
+                            const tms_vertex *verts, int64_t nv, double c, int32_t K, double h0,
+                            tms_mesh **out, char *msg, int64_t msg_len);
+int32_t tms_mesh_info(const tms_mesh *m, int64_t *n_vertices, int64_t *n_triangles,
+                      int64_t *n_loops, int64_t *n_fallback, int64_t *open_faces);
+int32_t tms_mesh_get(const tms_mesh *m, double *xyz, int32_t *tri, int32_t *tri_leaf);
+int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report *report);
+int32_t tms_mesh_write_off(const tms_mesh *m, const char *path);
+int32_t tms_mesh_free(tms_mesh *m);
+
 /* ---- tuning ---------------------------------------------------------------
  * Launch-shape knobs of the partition pass.  Results do not depend on them
  * (every cube's arithmetic is the same under any setting); only the time

@@ -1,0 +1,298 @@
+"""Oracle for the host Stage 2 (Section 2.3) and the manifold conditions
+(Section 3.2).  TEST INFRASTRUCTURE ONLY: nothing in the product path may
+import it; only the test-suite uses it.  Plain numpy/scipy, slow, written
+from the definitions:
+
+* face segments of a leaf -- on a face the trilinear g is bilinear, and the
+  curve g = c joins the face's edge points (eq. intersection) in pairs; with
+  four of them (corners alternating about c) the pairing follows which
+  corners the region g >= c connects, found here by brute force: the face is
+  sampled on a fine grid and the connected components of {g >= c} labelled;
+* the loops those segments form on the cube's boundary;
+* a mesh checker: (a) every edge in exactly two triangles, traversed in
+  opposite directions; (b) the triangles around every vertex form a single
+  loop; (c) no two triangles without a shared vertex intersect (brute force
+  over all pairs, segment-triangle tests); plus components, Euler
+  characteristic, area and enclosed volume.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import ndimage
+
+
+# ---- cube numbering (corner v = dx + 2 dy + 4 dz; edge e along axis e // 4,
+# the other two axes in ascending order at offsets (e & 1, (e >> 1) & 1)) ----
+
+def edge_offsets(e):
+    axis = e >> 2
+    others = sorted({0, 1, 2} - {axis})
+    off = [0, 0, 0]
+    off[others[0]] = e & 1
+    off[others[1]] = (e >> 1) & 1
+    return axis, off
+
+
+def edge_corners(e):
+    axis, off = edge_offsets(e)
+    v0 = off[0] + 2 * off[1] + 4 * off[2]
+    return v0, v0 + (1 << axis)
+
+
+def edge_key(conf, level, K, ijk, e):
+    """Key of a leaf's edge e: conf | level | axis | finest-lattice lower end
+    (the vertex order of the edge-point list)."""
+    axis, off = edge_offsets(e)
+    sh = K - level
+    X, Y, Z = [(int(ijk[a]) + off[a]) << sh for a in range(3)]
+    return (conf << 53) | (level << 50) | (axis << 48) | (X << 32) | (Y << 16) | Z
+
+
+def face_edges(a, s):
+    """Edges of the face u_a = s with their two corners."""
+    out = []
+    for e in range(12):
+        axis, off = edge_offsets(e)
+        if axis != a and off[a] == s:
+            out.append(e)
+    return out
+
+
+# ---- face pairing by brute force ----------------------------------------------
+
+def high_corners_joined(F, c, n=401):
+    """F[p][q]: a face's corner values (p, q in {0,1}), corners alternating
+    about c.  True if the two corners with value >= c lie in one connected
+    component of {bilinear >= c} (sampled on an n x n grid)."""
+    t = np.linspace(0.0, 1.0, n)
+    P, Q = np.meshgrid(t, t, indexing="ij")
+    h = (F[0][0] * (1 - P) * (1 - Q) + F[1][0] * P * (1 - Q) + F[0][1] * (1 - P) * Q
+         + F[1][1] * P * Q)
+    lab, _ = ndimage.label(h >= c)
+    hi = [(p, q) for p in (0, 1) for q in (0, 1) if F[p][q] >= c]
+    assert len(hi) == 2
+    (p0, q0), (p1, q1) = hi
+    return lab[p0 * (n - 1), q0 * (n - 1)] == lab[p1 * (n - 1), q1 * (n - 1)]
+
+
+def leaf_face_segments(f, c):
+    """The face segments of a leaf with corner values f[8]: a set of
+    frozensets {e1, e2} of cube edge indices."""
+    segs = set()
+    for a in range(3):
+        p_ax, q_ax = sorted({0, 1, 2} - {a})
+        for s in (0, 1):
+            def corner(p, q):
+                off = [0, 0, 0]
+                off[a], off[p_ax], off[q_ax] = s, p, q
+                return off[0] + 2 * off[1] + 4 * off[2]
+            cuts = []
+            for e in face_edges(a, s):
+                v0, v1 = edge_corners(e)
+                if (f[v0] >= c) != (f[v1] >= c):
+                    cuts.append(e)
+            if len(cuts) == 2:
+                segs.add(frozenset(cuts))
+            elif len(cuts) == 4:
+                F = [[f[corner(p, q)] for q in (0, 1)] for p in (0, 1)]
+                joined = high_corners_joined(F, c)
+                # cut off each corner of the separated kind: pair its edges
+                for p in (0, 1):
+                    for q in (0, 1):
+                        v = corner(p, q)
+                        if (f[v] >= c) == joined:
+                            continue
+                        mine = [e for e in cuts if v in edge_corners(e)]
+                        assert len(mine) == 2
+                        segs.add(frozenset(mine))
+    return segs
+
+
+def loops_from_segments(segs):
+    """Cycles (lists of edge indices) formed by the segments."""
+    nb = {}
+    for sg in segs:
+        a, b = tuple(sg)
+        nb.setdefault(a, []).append(b)
+        nb.setdefault(b, []).append(a)
+    assert all(len(v) == 2 for v in nb.values())
+    seen, loops = set(), []
+    for start in sorted(nb):
+        if start in seen:
+            continue
+        loop, prev, cur = [start], None, start
+        seen.add(start)
+        while True:
+            nxt = nb[cur][0] if nb[cur][0] != prev else nb[cur][1]
+            prev, cur = cur, nxt
+            if cur == start:
+                break
+            loop.append(cur)
+            seen.add(cur)
+        loops.append(loop)
+    return loops
+
+
+# ---- mesh checker ---------------------------------------------------------------
+
+def _seg_tri(p, q, A, B, C, eps=1e-12):
+    """Does the closed segment pq meet the closed triangle ABC (not coplanar)?"""
+    n = np.cross(B - A, C - A)
+    dp, dq = np.dot(n, p - A), np.dot(n, q - A)
+    scale = np.linalg.norm(n) * max(np.linalg.norm(q - p), 1e-300)
+    if dp * dq > 0 or (abs(dp) <= eps * scale and abs(dq) <= eps * scale):
+        return False
+    t = dp / (dp - dq)
+    x = p + t * (q - p)
+    # barycentric test
+    v0, v1, v2 = C - A, B - A, x - A
+    d00, d01, d11 = np.dot(v0, v0), np.dot(v0, v1), np.dot(v1, v1)
+    d20, d21 = np.dot(v2, v0), np.dot(v2, v1)
+    den = d00 * d11 - d01 * d01
+    if den == 0:
+        return False
+    u = (d11 * d20 - d01 * d21) / den
+    v = (d00 * d21 - d01 * d20) / den
+    return u >= -1e-12 and v >= -1e-12 and u + v <= 1 + 1e-12
+
+
+def _seg_tri_vec(p, q, A, B, C, eps=1e-12):
+    """_seg_tri over arrays of segments and triangles (rows)."""
+    n = np.cross(B - A, C - A)
+    dp = np.einsum("ij,ij->i", n, p - A)
+    dq = np.einsum("ij,ij->i", n, q - A)
+    scale = np.linalg.norm(n, axis=1) * np.maximum(np.linalg.norm(q - p, axis=1), 1e-300)
+    flat = (np.abs(dp) <= eps * scale) & (np.abs(dq) <= eps * scale)
+    ok = ~((dp * dq > 0) | flat)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(ok, dp / (dp - dq), 0.0)
+    x = p + t[:, None] * (q - p)
+    v0, v1, v2 = C - A, B - A, x - A
+    d00 = np.einsum("ij,ij->i", v0, v0)
+    d01 = np.einsum("ij,ij->i", v0, v1)
+    d11 = np.einsum("ij,ij->i", v1, v1)
+    d20 = np.einsum("ij,ij->i", v2, v0)
+    d21 = np.einsum("ij,ij->i", v2, v1)
+    den = d00 * d11 - d01 * d01
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = (d11 * d20 - d01 * d21) / den
+        v = (d00 * d21 - d01 * d20) / den
+    return ok & (den != 0) & (u >= -1e-12) & (v >= -1e-12) & (u + v <= 1 + 1e-12)
+
+
+def tris_intersect(T1, T2):
+    """Two triangles (3 x 3 arrays) sharing no vertex intersect iff a side of
+    one meets the other (for non-coplanar triangles)."""
+    for a in range(3):
+        if _seg_tri(T1[a], T1[(a + 1) % 3], *T2) or _seg_tri(T2[a], T2[(a + 1) % 3], *T1):
+            return True
+    return False
+
+
+def check_mesh(xyz, tri, intersections=True, cell=None):
+    """Manifold conditions and invariants of a triangle mesh (Section 3.2).
+    cell: optional edge length of a bucket grid that limits the pairs tested
+    for (c) to triangles in touching buckets (all pairs when None)."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    tri = np.asarray(tri, dtype=np.int64)
+    nv, nt = len(xyz), len(tri)
+    rep = {}
+    # (a)
+    edges = {}
+    for t, (a, b, c) in enumerate(tri):
+        for u, v in ((a, b), (b, c), (c, a)):
+            edges.setdefault((min(u, v), max(u, v)), []).append(1 if u < v else -1)
+    bnd = [e for e, d in edges.items() if len(d) == 1]
+    nonman = [e for e, d in edges.items() if len(d) > 2]
+    misor = [e for e, d in edges.items() if len(d) == 2 and sum(d) != 0]
+    rep["boundary_edges"], rep["nonmanifold_edges"] = len(bnd), len(nonman)
+    rep["misoriented_edges"] = len(misor)
+    bad = set()
+    for e in bnd + nonman + misor:
+        bad.update(e)
+    # (b): the sides opposite v in its triangles form one cycle
+    opp = {}
+    for a, b, c in tri:
+        opp.setdefault(a, []).append((b, c))
+        opp.setdefault(b, []).append((c, a))
+        opp.setdefault(c, []).append((a, b))
+    for v, link in opp.items():
+        deg = {}
+        for s in link:
+            for w in s:
+                deg[w] = deg.get(w, 0) + 1
+        ok = all(d == 2 for d in deg.values())
+        if ok:
+            # walk one cycle and require it to use every side
+            nb = {}
+            for x, y in link:
+                nb.setdefault(x, []).append(y)
+                nb.setdefault(y, []).append(x)
+            start = link[0][0]
+            prev, cur, n = None, start, 0
+            while True:
+                nxt = nb[cur][0] if nb[cur][0] != prev else nb[cur][1]
+                prev, cur = cur, nxt
+                n += 1
+                if cur == start or n > len(link):
+                    break
+            ok = cur == start and n == len(link)
+        if not ok:
+            bad.add(v)
+    rep["nonmanifold_vertices"] = len(bad)
+    # components, Euler characteristic
+    parent = list(range(nv))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+    used = np.zeros(nv, dtype=bool)
+    for a, b, c in tri:
+        used[[a, b, c]] = True
+        for u, v in ((a, b), (b, c)):
+            ru, rv = find(u), find(v)
+            if ru != rv:
+                parent[ru] = rv
+    rep["components"] = len({find(v) for v in range(nv) if used[v]})
+    rep["euler"] = int(used.sum()) - len(edges) + nt
+    P = xyz[tri]
+    cr = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    rep["area"] = float(0.5 * np.linalg.norm(cr, axis=1).sum())
+    rep["volume"] = float(np.einsum("ij,ij->i", P[:, 0], np.cross(P[:, 1], P[:, 2])).sum() / 6.0)
+    # (c)
+    if intersections:
+        if cell is None:
+            I, J = np.triu_indices(nt, 1)
+        else:
+            cen = P.mean(axis=1)
+            key = np.floor(cen / cell).astype(np.int64)
+            buckets = {}
+            for i, k in enumerate(map(tuple, key)):
+                buckets.setdefault(k, []).append(i)
+            Is, Js = [], []
+            for k, lst in buckets.items():
+                a = np.array(lst)
+                for d in np.ndindex(3, 3, 3):
+                    k2 = (k[0] + d[0] - 1, k[1] + d[1] - 1, k[2] + d[2] - 1)
+                    b = buckets.get(k2)
+                    if b is None:
+                        continue
+                    ii, jj = np.meshgrid(a, np.array(b), indexing="ij")
+                    m = ii < jj
+                    Is.append(ii[m])
+                    Js.append(jj[m])
+            I = np.concatenate(Is) if Is else np.zeros(0, np.int64)
+            J = np.concatenate(Js) if Js else np.zeros(0, np.int64)
+        share = np.zeros(len(I), dtype=bool)
+        for a in range(3):
+            for b in range(3):
+                share |= tri[I, a] == tri[J, b]
+        I, J = I[~share], J[~share]
+        hit = np.zeros(len(I), dtype=bool)
+        for a in range(3):
+            hit |= _seg_tri_vec(P[I, a], P[I, (a + 1) % 3], P[J, 0], P[J, 1], P[J, 2])
+            hit |= _seg_tri_vec(P[J, a], P[J, (a + 1) % 3], P[I, 0], P[I, 1], P[I, 2])
+        rep["intersecting_pairs"] = int(hit.sum())
+    return rep

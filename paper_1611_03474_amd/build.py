@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libtms.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["tms_api.hip", "k_cells.hip", "k_scan.hip", "k_partition.hip", "k_phi.hip",
-           "k_extract.hip", "k_adjoint.hip", "k_graph.hip", "k_stage2.hip"]
+           "k_extract.hip", "k_adjoint.hip", "k_graph.hip", "k_stage2.hip", "mesh.cpp"]
 HEADERS = ["tms_internal.h", "tms_device.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,988 @@
+// Host Stage 2 (Section 2.3): the trilinear surface g = c of every SURFACE
+// leaf (eq. linear1) as triangles, and the manifold conditions of Section
+// 3.2.  Host C++ over std::thread; the device results of the partition
+// (leaves, corner values) and of the extraction (edge points) are copied in.
+//
+// Per leaf, the surface meets the cube's boundary in curves on its faces.  On
+// a face g is bilinear, so g = c there is a hyperbola (or a pair of lines)
+// whose branches join the face's edge points (eq. intersection) in pairs: two
+// edge points on a face are joined directly; four (the corners alternate
+// around the face) are paired by the value of g at the face's saddle point --
+// at or above c the two corners at or above c are joined through the face and
+// each corner below c is cut off, else the reverse.  Both leaves that share a
+// face see the same four values and pair the same way, so neighbouring
+// leaves' curves agree.  Each edge point lies on two faces of the cube, so
+// the face segments link into closed loops on the cube's boundary, each
+// enclosing one patch of the surface.
+//
+// A patch is triangulated by ear clipping (Section 2.3) in the plane normal
+// to an axis along which it is single valued: the axis of the loop's largest
+// projected area, else the next, as long as the loop projects to a simple
+// polygon there.  A loop that projects simply along no axis is fanned from
+// its first point and counted.  Triangles are oriented so that their normal
+// points along -grad g (outward: phi >= c is inside).
+//
+// The checks: (a) every edge shared by exactly two triangles, traversed in
+// opposite directions; (b) the neighbourhood of every vertex one single loop;
+// (c) no two triangles without a shared vertex intersecting.  Vertices that
+// fail (a) or (b) are the paper's non-manifold defects.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tms_internal.h"
+
+struct tms_mesh {
+    std::vector<double> xyz;        // [nv][3]
+    std::vector<int32_t> tri;       // [nt][3]
+    std::vector<int32_t> tri_leaf;  // [nt] index of the leaf in the caller's list
+    std::vector<int32_t> leaf_ijk;  // [n][3] of the caller's leaves (for the checks)
+    int level = 0;
+    int64_t n_surface = 0, n_loops = 0, n_fallback = 0, open_faces = 0;
+};
+
+namespace {
+
+using tms::Grid;
+
+int32_t mfail(tms_ctx *ctx, int32_t code, const char *msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+// ---- cube topology ----------------------------------------------------------
+// corner v = dx + 2 dy + 4 dz; edge e: axis = e / 4, the other two axes in
+// ascending order take offsets (e & 1, (e >> 1) & 1) (the extraction's edge
+// numbering).
+struct EdgeInfo {
+    int axis, off[3], v0, v1;
+};
+
+EdgeInfo edge_info(int e) {
+    EdgeInfo E;
+    E.axis = e >> 2;
+    const int o1 = (E.axis + 1) % 3, o2 = (E.axis + 2) % 3;
+    const int lo = std::min(o1, o2), hi = std::max(o1, o2);
+    E.off[0] = E.off[1] = E.off[2] = 0;
+    E.off[lo] = e & 1;
+    E.off[hi] = (e >> 1) & 1;
+    E.v0 = E.off[0] + 2 * E.off[1] + 4 * E.off[2];
+    E.v1 = E.v0 + (1 << E.axis);
+    return E;
+}
+
+// edge along axis b with offsets ob[] on the other axes
+int edge_index(int b, const int off[3]) {
+    const int o1 = (b + 1) % 3, o2 = (b + 2) % 3;
+    const int lo = std::min(o1, o2), hi = std::max(o1, o2);
+    return 4 * b + off[lo] + 2 * off[hi];
+}
+
+// Face (a, s): the plane u_a = s.  Its corners in cyclic order K0..K3 =
+// (p, q) = (0,0), (1,0), (1,1), (0,1) with p, q the other two axes in
+// ascending order, and its edges E_k between K_k and K_{k+1}.
+struct FaceInfo {
+    int corner[4];
+    int edge[4];
+};
+
+FaceInfo face_info(int a, int s) {
+    const int o1 = (a + 1) % 3, o2 = (a + 2) % 3;
+    const int p = std::min(o1, o2), q = std::max(o1, o2);
+    const int pq[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+    FaceInfo F;
+    for (int k = 0; k < 4; ++k) {
+        int off[3];
+        off[a] = s;
+        off[p] = pq[k][0];
+        off[q] = pq[k][1];
+        F.corner[k] = off[0] + 2 * off[1] + 4 * off[2];
+    }
+    for (int k = 0; k < 4; ++k) {
+        const int k1 = (k + 1) & 3;
+        // the axis along which K_k and K_k1 differ
+        const int b = (pq[k][0] != pq[k1][0]) ? p : q;
+        int off[3];
+        off[a] = s;
+        off[p] = std::min(pq[k][0], pq[k1][0]);
+        off[q] = std::min(pq[k][1], pq[k1][1]);
+        off[b] = 0;
+        F.edge[k] = edge_index(b, off);
+    }
+    return F;
+}
+
+struct Topo {
+    EdgeInfo E[12];
+    FaceInfo F[6];  // face 2 a + s
+    int edge_face[12][2];
+    Topo() {
+        for (int e = 0; e < 12; ++e) E[e] = edge_info(e);
+        int cnt[12] = {0};
+        for (int a = 0; a < 3; ++a)
+            for (int s = 0; s < 2; ++s) {
+                F[2 * a + s] = face_info(a, s);
+                for (int k = 0; k < 4; ++k) {
+                    const int e = F[2 * a + s].edge[k];
+                    edge_face[e][cnt[e]++] = 2 * a + s;
+                }
+            }
+    }
+};
+
+const Topo &topo() {
+    static const Topo t;
+    return t;
+}
+
+// ---- one leaf ---------------------------------------------------------------
+struct LeafOut {
+    // corners: cube edge indices 0..11, or 12 + k for the k-th interior point
+    std::vector<std::array<int, 3>> tri;
+    std::vector<std::array<double, 3>> inner;  // interior points (local)
+    int loops = 0, fallback = 0;
+};
+
+// face segments of a leaf: partner[e][j] = the edge joined to edge e on the
+// j-th face containing e (-1: none)
+void face_segments(const double f[8], double c, int partner[12][2]) {
+    const Topo &T = topo();
+    for (int e = 0; e < 12; ++e) partner[e][0] = partner[e][1] = -1;
+    auto link = [&](int e1, int e2, int face) {
+        const int j1 = T.edge_face[e1][0] == face ? 0 : 1;
+        const int j2 = T.edge_face[e2][0] == face ? 0 : 1;
+        partner[e1][j1] = e2;
+        partner[e2][j2] = e1;
+    };
+    for (int fi = 0; fi < 6; ++fi) {
+        const FaceInfo &F = T.F[fi];
+        bool hi[4];
+        for (int k = 0; k < 4; ++k) hi[k] = f[F.corner[k]] >= c;
+        int cut[4], n = 0;
+        for (int k = 0; k < 4; ++k)
+            if (hi[k] != hi[(k + 1) & 3]) cut[n++] = k;
+        if (n == 2) {
+            link(F.edge[cut[0]], F.edge[cut[1]], fi);
+        } else if (n == 4) {
+            // corners alternate; bilinear h(p,q) on the face, saddle value
+            // (h00 h11 - h10 h01) / (h00 + h11 - h10 - h01)
+            const double h00 = f[F.corner[0]], h10 = f[F.corner[1]], h11 = f[F.corner[2]],
+                         h01 = f[F.corner[3]];
+            const double sad = (h00 * h11 - h10 * h01) / (h00 + h11 - h10 - h01);
+            const bool join_high = sad >= c;
+            // corner k is cut off by the segment joining its two edges
+            // (E_{k-1}, E_k); cut the low corners when the high ones join
+            for (int k = 0; k < 4; ++k)
+                if (hi[k] != join_high) link(F.edge[(k + 3) & 3], F.edge[k], fi);
+        }
+    }
+}
+
+// An edge point closer than kTmin (of the edge) to a corner is moved to
+// kTmin from it: a corner value equal to c (inside, phi >= c) would otherwise
+// put the points of its three edges on the corner itself, and the polygon
+// of the loop would repeat a point.  The move is at most kTmin h.
+constexpr double kTmin = 1e-6;
+
+double clamp_t(double t) { return std::min(std::max(t, kTmin), 1.0 - kTmin); }
+
+// local position of the edge point of edge e
+void edge_point(const double f[8], double c, int e, double P[3]) {
+    const EdgeInfo &E = topo().E[e];
+    const double t = clamp_t((c - f[E.v0]) / (f[E.v1] - f[E.v0]));
+    for (int a = 0; a < 3; ++a) P[a] = (double)E.off[a];
+    P[E.axis] = t;
+}
+
+// the trilinear interpolant at local point u
+double g_at(const double f[8], const double u[3]) {
+    double s = 0.0;
+    for (int v = 0; v < 8; ++v) {
+        double w = 1.0;
+        for (int b = 0; b < 3; ++b) w *= ((v >> b) & 1) ? u[b] : 1.0 - u[b];
+        s += w * f[v];
+    }
+    return s;
+}
+
+// gradient of the trilinear interpolant at local point u
+void grad_g(const double f[8], const double u[3], double G[3]);
+
+// a point of g = c near u: Newton steps along grad g, kept in the cube;
+// false if the gradient vanishes or the steps do not converge
+bool onto_surface(const double f[8], double c, double u[3]) {
+    for (int it = 0; it < 50; ++it) {
+        double G[3];
+        grad_g(f, u, G);
+        const double gg = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+        const double r = g_at(f, u) - c;
+        if (std::fabs(r) <= 1e-13 * (std::fabs(c) + 1.0)) return true;
+        if (!(gg > 0.0)) return false;
+        for (int a = 0; a < 3; ++a) u[a] = std::min(1.0, std::max(0.0, u[a] - r * G[a] / gg));
+    }
+    return false;
+}
+
+void grad_g(const double f[8], const double u[3], double G[3]) {
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int v = 0; v < 8; ++v) {
+            double w = 1.0;
+            for (int b = 0; b < 3; ++b) {
+                if (b == a) continue;
+                const int o = (v >> b) & 1;
+                w *= o ? u[b] : 1.0 - u[b];
+            }
+            s += (((v >> a) & 1) ? 1.0 : -1.0) * w * f[v];
+        }
+        G[a] = s;
+    }
+}
+
+double cross2(const double a[2], const double b[2], const double c[2]) {
+    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+}
+
+// do segments ab and cd meet (including touching)?
+bool seg_meet(const double a[2], const double b[2], const double c[2], const double d[2]) {
+    const double d1 = cross2(a, b, c), d2 = cross2(a, b, d), d3 = cross2(c, d, a),
+                 d4 = cross2(c, d, b);
+    if (((d1 > 0 && d2 < 0) || (d1 < 0 && d2 > 0)) && ((d3 > 0 && d4 < 0) || (d3 < 0 && d4 > 0)))
+        return true;
+    auto on = [](const double p[2], const double q[2], const double r[2], double cr) {
+        return cr == 0.0 && std::min(p[0], q[0]) <= r[0] && r[0] <= std::max(p[0], q[0]) &&
+               std::min(p[1], q[1]) <= r[1] && r[1] <= std::max(p[1], q[1]);
+    };
+    return on(a, b, c, d1) || on(a, b, d, d2) || on(c, d, a, d3) || on(c, d, b, d4);
+}
+
+// ear clipping of a simple polygon (counter-clockwise or clockwise) of m
+// points; emits index triples with the polygon's winding.  Returns false if
+// the polygon is not simple or has no ear left.
+bool ear_clip(const std::vector<std::array<double, 2>> &Q, std::vector<std::array<int, 3>> &out) {
+    const int m = (int)Q.size();
+    // simple: non-adjacent sides do not meet, no repeated point
+    for (int i = 0; i < m; ++i)
+        for (int j = i + 1; j < m; ++j) {
+            if (Q[i][0] == Q[j][0] && Q[i][1] == Q[j][1]) return false;
+            if (j == i + 1 || (i == 0 && j == m - 1)) continue;
+            if (seg_meet(Q[i].data(), Q[(i + 1) % m].data(), Q[j].data(), Q[(j + 1) % m].data()))
+                return false;
+        }
+    double area = 0.0;
+    for (int i = 0; i < m; ++i)
+        area += Q[i][0] * Q[(i + 1) % m][1] - Q[(i + 1) % m][0] * Q[i][1];
+    if (area == 0.0) return false;
+    const double sg = area > 0 ? 1.0 : -1.0;
+    std::vector<int> idx(m);
+    std::iota(idx.begin(), idx.end(), 0);
+    while (idx.size() > 3) {
+        const int k = (int)idx.size();
+        bool found = false;
+        for (int i = 0; i < k && !found; ++i) {
+            const int ia = idx[(i + k - 1) % k], ib = idx[i], ic = idx[(i + 1) % k];
+            const double cr = cross2(Q[ia].data(), Q[ib].data(), Q[ic].data()) * sg;
+            if (!(cr > 0.0)) continue;
+            bool inside = false;
+            for (int j = 0; j < k && !inside; ++j) {
+                const int ij = idx[j];
+                if (ij == ia || ij == ib || ij == ic) continue;
+                const double *p = Q[ij].data();
+                const double c1 = cross2(Q[ia].data(), Q[ib].data(), p) * sg,
+                             c2 = cross2(Q[ib].data(), Q[ic].data(), p) * sg,
+                             c3 = cross2(Q[ic].data(), Q[ia].data(), p) * sg;
+                if (c1 >= 0 && c2 >= 0 && c3 >= 0) inside = true;
+            }
+            if (inside) continue;
+            out.push_back({ia, ib, ic});
+            idx.erase(idx.begin() + i);
+            found = true;
+        }
+        if (!found) return false;
+    }
+    out.push_back({idx[0], idx[1], idx[2]});
+    return true;
+}
+
+void leaf_triangles(const double f[8], double c, LeafOut &L) {
+    const Topo &T = topo();
+    int partner[12][2];
+    face_segments(f, c, partner);
+    bool used[12] = {false};
+    for (int e0 = 0; e0 < 12; ++e0) {
+        if (used[e0] || partner[e0][0] < 0) continue;
+        // walk the loop through e0
+        std::vector<int> loop;
+        int prev = -1, cur = e0;
+        while (true) {
+            loop.push_back(cur);
+            used[cur] = true;
+            const int nx = (partner[cur][0] != prev) ? partner[cur][0] : partner[cur][1];
+            prev = cur;
+            cur = nx;
+            if (cur == e0 || cur < 0 || loop.size() > 12) break;
+        }
+        if (cur != e0 || loop.size() < 3) continue;  // not closed (cannot happen)
+        ++L.loops;
+        const int m = (int)loop.size();
+        std::vector<std::array<double, 3>> P(m);
+        for (int i = 0; i < m; ++i) edge_point(f, c, loop[i], P[i].data());
+        // vector area of the loop and the outward direction -grad g at its
+        // centroid decide the orientation
+        double A[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
+        for (int i = 0; i < m; ++i) {
+            const double *p = P[i].data(), *q = P[(i + 1) % m].data();
+            A[0] += 0.5 * (p[1] * q[2] - p[2] * q[1]);
+            A[1] += 0.5 * (p[2] * q[0] - p[0] * q[2]);
+            A[2] += 0.5 * (p[0] * q[1] - p[1] * q[0]);
+            for (int a = 0; a < 3; ++a) ctr[a] += p[a] / m;
+        }
+        int order[3] = {0, 1, 2};
+        std::sort(order, order + 3, [&](int x, int y) { return std::fabs(A[x]) > std::fabs(A[y]); });
+        std::vector<std::array<int, 3>> tl;
+        bool ok = false;
+        for (int oi = 0; oi < 3 && !ok; ++oi) {
+            const int a = order[oi], b = (a + 1) % 3, cc = (a + 2) % 3;
+            std::vector<std::array<double, 2>> Q(m);
+            for (int i = 0; i < m; ++i) Q[i] = {P[i][b], P[i][cc]};
+            tl.clear();
+            ok = ear_clip(Q, tl);
+        }
+        int inner = -1;
+        if (!ok) {
+            // single valued along no axis (folds along all three): a fan
+            // from a point of the patch inside the cube, the loop's centroid
+            // moved onto g = c (else from the loop's first point)
+            tl.clear();
+            double u[3] = {ctr[0], ctr[1], ctr[2]};
+            if (onto_surface(f, c, u)) {
+                inner = (int)L.inner.size();
+                L.inner.push_back({u[0], u[1], u[2]});
+                P.push_back({u[0], u[1], u[2]});
+                for (int i = 0; i < m; ++i) tl.push_back({m, i, (i + 1) % m});
+            } else {
+                for (int i = 1; i + 1 < m; ++i) tl.push_back({0, i, i + 1});
+            }
+            ++L.fallback;
+        }
+        // orientation: sum over the triangles of n . (-grad g) at their centroids
+        double score = 0.0;
+        for (const auto &t : tl) {
+            const double *p = P[t[0]].data(), *q = P[t[1]].data(), *r = P[t[2]].data();
+            const double u1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+            const double u2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+            const double n[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
+                                 u1[0] * u2[1] - u1[1] * u2[0]};
+            const double cen[3] = {(p[0] + q[0] + r[0]) / 3, (p[1] + q[1] + r[1]) / 3,
+                                   (p[2] + q[2] + r[2]) / 3};
+            double G[3];
+            grad_g(f, cen, G);
+            score -= n[0] * G[0] + n[1] * G[1] + n[2] * G[2];
+        }
+        const bool flip = score < 0.0;
+        auto id = [&](int k) { return k < m ? loop[k] : 12 + inner; };
+        for (const auto &t : tl) {
+            if (flip) L.tri.push_back({id(t[0]), id(t[2]), id(t[1])});
+            else L.tri.push_back({id(t[0]), id(t[1]), id(t[2])});
+        }
+    }
+}
+
+uint64_t edge_key(int conf, int level, int K, int32_t ix, int32_t iy, int32_t iz, int e) {
+    const EdgeInfo &E = topo().E[e];
+    const int sh = K - level;
+    const uint64_t X = (uint64_t)((int64_t)(ix + E.off[0]) << sh);
+    const uint64_t Y = (uint64_t)((int64_t)(iy + E.off[1]) << sh);
+    const uint64_t Z = (uint64_t)((int64_t)(iz + E.off[2]) << sh);
+    return ((uint64_t)(uint32_t)conf << 53) | ((uint64_t)level << 50) | ((uint64_t)E.axis << 48) |
+           (X << 32) | (Y << 16) | Z;
+}
+
+template <typename F>
+void parallel_for(int64_t n, F fn) {
+    unsigned nt = std::max(1u, std::thread::hardware_concurrency());
+    nt = (unsigned)std::min<int64_t>(nt, std::max<int64_t>(1, n / 1024));
+    if (nt <= 1) {
+        fn(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) {
+        const int64_t b = n * t / nt, e = n * (t + 1) / nt;
+        th.emplace_back([=, &fn] { fn(b, e, (int)t); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// ---- triangle-triangle intersection (Moller's interval overlap test) -------
+void sub3(const double *a, const double *b, double *r) {
+    r[0] = a[0] - b[0];
+    r[1] = a[1] - b[1];
+    r[2] = a[2] - b[2];
+}
+void crs3(const double *a, const double *b, double *r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+bool coplanar_tri_tri(const double *N, const double *V0, const double *V1, const double *V2,
+                      const double *U0, const double *U1, const double *U2) {
+    // project onto the plane where the normal is largest, then 2-D tests
+    const double A[3] = {std::fabs(N[0]), std::fabs(N[1]), std::fabs(N[2])};
+    int i0, i1;
+    if (A[0] > A[1]) {
+        if (A[0] > A[2]) { i0 = 1; i1 = 2; }
+        else { i0 = 0; i1 = 1; }
+    } else {
+        if (A[2] > A[1]) { i0 = 0; i1 = 1; }
+        else { i0 = 0; i1 = 2; }
+    }
+    const double *V[3] = {V0, V1, V2}, *U[3] = {U0, U1, U2};
+    double v[3][2], u[3][2];
+    for (int k = 0; k < 3; ++k) {
+        v[k][0] = V[k][i0]; v[k][1] = V[k][i1];
+        u[k][0] = U[k][i0]; u[k][1] = U[k][i1];
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (seg_meet(v[i], v[(i + 1) % 3], u[j], u[(j + 1) % 3])) return true;
+    auto inside = [](const double p[2], double t[3][2]) {
+        const double c1 = cross2(t[0], t[1], p), c2 = cross2(t[1], t[2], p), c3 = cross2(t[2], t[0], p);
+        return (c1 >= 0 && c2 >= 0 && c3 >= 0) || (c1 <= 0 && c2 <= 0 && c3 <= 0);
+    };
+    return inside(v[0], u) || inside(u[0], v);
+}
+
+bool tri_tri(const double *V0, const double *V1, const double *V2, const double *U0,
+             const double *U1, const double *U2) {
+    double E1[3], E2[3], N1[3], N2[3];
+    sub3(V1, V0, E1);
+    sub3(V2, V0, E2);
+    crs3(E1, E2, N1);
+    const double d1 = -dot3(N1, V0);
+    double du0 = dot3(N1, U0) + d1, du1 = dot3(N1, U1) + d1, du2 = dot3(N1, U2) + d1;
+    const double eps = 1e-14 * (dot3(N1, N1) > 0 ? std::sqrt(dot3(N1, N1)) : 1.0);
+    if (std::fabs(du0) < eps) du0 = 0;
+    if (std::fabs(du1) < eps) du1 = 0;
+    if (std::fabs(du2) < eps) du2 = 0;
+    if ((du0 > 0 && du1 > 0 && du2 > 0) || (du0 < 0 && du1 < 0 && du2 < 0)) return false;
+    sub3(U1, U0, E1);
+    sub3(U2, U0, E2);
+    crs3(E1, E2, N2);
+    const double d2 = -dot3(N2, U0);
+    double dv0 = dot3(N2, V0) + d2, dv1 = dot3(N2, V1) + d2, dv2 = dot3(N2, V2) + d2;
+    const double eps2 = 1e-14 * (dot3(N2, N2) > 0 ? std::sqrt(dot3(N2, N2)) : 1.0);
+    if (std::fabs(dv0) < eps2) dv0 = 0;
+    if (std::fabs(dv1) < eps2) dv1 = 0;
+    if (std::fabs(dv2) < eps2) dv2 = 0;
+    if ((dv0 > 0 && dv1 > 0 && dv2 > 0) || (dv0 < 0 && dv1 < 0 && dv2 < 0)) return false;
+    double D[3];
+    crs3(N1, N2, D);
+    if ((du0 == 0 && du1 == 0 && du2 == 0) || (dv0 == 0 && dv1 == 0 && dv2 == 0))
+        return coplanar_tri_tri(N1, V0, V1, V2, U0, U1, U2);
+    // interval of each triangle on the line of intersection
+    auto interval = [&](const double *P0, const double *P1, const double *P2, double d0, double dd1,
+                        double dd2, double &lo, double &hi) {
+        int ax = 0;
+        if (std::fabs(D[1]) > std::fabs(D[ax])) ax = 1;
+        if (std::fabs(D[2]) > std::fabs(D[ax])) ax = 2;
+        const double p0 = P0[ax], p1 = P1[ax], p2 = P2[ax];
+        // the vertex alone on its side
+        double a, b, c, da, db, dc;
+        if (d0 * dd1 > 0) { a = p2; b = p0; c = p1; da = dd2; db = d0; dc = dd1; }
+        else if (d0 * dd2 > 0) { a = p1; b = p0; c = p2; da = dd1; db = d0; dc = dd2; }
+        else if (dd1 * dd2 > 0 || d0 != 0) { a = p0; b = p1; c = p2; da = d0; db = dd1; dc = dd2; }
+        else if (dd1 != 0) { a = p1; b = p0; c = p2; da = dd1; db = d0; dc = dd2; }
+        else { a = p2; b = p0; c = p1; da = dd2; db = d0; dc = dd1; }
+        const double t1 = a + (b - a) * da / (da - db), t2 = a + (c - a) * da / (da - dc);
+        lo = std::min(t1, t2);
+        hi = std::max(t1, t2);
+    };
+    double a0, a1, b0, b1;
+    interval(V0, V1, V2, dv0, dv1, dv2, a0, a1);
+    interval(U0, U1, U2, du0, du1, du2, b0, b1);
+    return !(a1 < b0 || b1 < a0);
+}
+
+
+// the mesh of host copies of the leaves, corner values and vertices; returns
+// a message (empty: success) and the mesh
+std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+                       const std::vector<tms_vertex> &V, double c, int K, double h0,
+                       tms_mesh **out) {
+    *out = nullptr;
+    const int64_t n = (int64_t)L.size(), nv = (int64_t)V.size();
+    if (n >= (int64_t)0x7FFFFFFF || nv >= (int64_t)0x7FFFFFFF)
+        return "too many leaves or vertices for 32-bit indices";
+    for (int64_t k = 1; k < nv; ++k)
+        if (!(V[(size_t)k - 1].edge_key < V[(size_t)k].edge_key))
+            return "vertices must come in ascending edge-key order";
+    auto *M = new tms_mesh();
+    std::vector<int64_t> surf;
+    for (int64_t i = 0; i < n; ++i)
+        if (L[(size_t)i].cls == TMS_CLS_SURFACE) surf.push_back(i);
+    M->n_surface = (int64_t)surf.size();
+    M->level = surf.empty() ? K : L[(size_t)surf[0]].level;
+    for (int64_t i : surf)
+        if (L[(size_t)i].level != M->level || L[(size_t)i].level > K) {
+            delete M;
+            return "SURFACE leaves of different levels: faces between cubes of different sizes "
+                   "(T-junctions) are not meshed";
+        }
+    M->leaf_ijk.resize((size_t)n * 3);
+    for (int64_t i = 0; i < n; ++i) {
+        M->leaf_ijk[3 * i] = L[(size_t)i].ix;
+        M->leaf_ijk[3 * i + 1] = L[(size_t)i].iy;
+        M->leaf_ijk[3 * i + 2] = L[(size_t)i].iz;
+    }
+    M->xyz.resize((size_t)nv * 3);
+    for (int64_t k = 0; k < nv; ++k) {
+        const tms_vertex &v = V[(size_t)k];
+        double p[3] = {v.x, v.y, v.z};
+        // an edge point on (or within kTmin of) a corner moves along its edge
+        const double tc = clamp_t(v.t);
+        if (tc != v.t) {
+            const int level = (int)((v.edge_key >> 50) & 7), axis = (int)((v.edge_key >> 48) & 3);
+            p[axis] += (tc - v.t) * std::ldexp(h0, -level);
+        }
+        M->xyz[3 * k] = p[0];
+        M->xyz[3 * k + 1] = p[1];
+        M->xyz[3 * k + 2] = p[2];
+    }
+    // vertex of an edge key: the extraction's list is in ascending key order
+    auto vid = [&](uint64_t key) -> int64_t {
+        auto it = std::lower_bound(V.begin(), V.end(), key,
+                                   [](const tms_vertex &a, uint64_t k) { return a.edge_key < k; });
+        return (it != V.end() && it->edge_key == key) ? (int64_t)(it - V.begin()) : -1;
+    };
+    const int64_t ns = (int64_t)surf.size();
+    const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+    std::vector<std::vector<int32_t>> ptri(nth), pleaf(nth);
+    std::vector<std::vector<double>> pxyz(nth);  // interior points of fanned loops
+    std::vector<int64_t> loops(nth, 0), fb(nth, 0), missing(nth, 0);
+    // per-thread chunks of the surface list, merged in order afterwards
+    std::vector<int64_t> first(nth, -1);
+    parallel_for(ns, [&](int64_t b, int64_t e, int t) {
+        first[(size_t)t] = b;
+        LeafOut out;
+        for (int64_t s = b; s < e; ++s) {
+            const int64_t i = surf[(size_t)s];
+            const tms_leaf &lf = L[(size_t)i];
+            const double *f = &cp[(size_t)i * 8];
+            out.tri.clear();
+            out.inner.clear();
+            out.loops = out.fallback = 0;
+            leaf_triangles(f, c, out);
+            loops[(size_t)t] += out.loops;
+            fb[(size_t)t] += out.fallback;
+            // interior points: placed from a corner of an edge point of the
+            // leaf (its global position minus its local one) -- numbered
+            // -1 - k in the thread, renumbered after the merge
+            std::vector<int32_t> inner_id(out.inner.size(), 0);
+            if (!out.inner.empty()) {
+                int e0 = -1;
+                for (const auto &tr : out.tri)
+                    for (int k = 0; k < 3 && e0 < 0; ++k)
+                        if (tr[k] < 12) e0 = tr[k];
+                const int64_t v0 = e0 < 0 ? -1 : vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, e0));
+                if (v0 < 0) {
+                    ++missing[(size_t)t];
+                    continue;
+                }
+                double P0[3];
+                edge_point(f, c, e0, P0);
+                const double h = std::ldexp(h0, -(int)lf.level);
+                for (size_t k = 0; k < out.inner.size(); ++k) {
+                    inner_id[k] = -1 - (int32_t)(pxyz[(size_t)t].size() / 3);
+                    for (int a = 0; a < 3; ++a)
+                        pxyz[(size_t)t].push_back(M->xyz[3 * v0 + a] + (out.inner[k][a] - P0[a]) * h);
+                }
+            }
+            for (const auto &tr : out.tri) {
+                int32_t id[3];
+                bool ok = true;
+                for (int k = 0; k < 3; ++k) {
+                    if (tr[k] >= 12) {
+                        id[k] = inner_id[(size_t)(tr[k] - 12)];
+                        continue;
+                    }
+                    const int64_t v = vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, tr[k]));
+                    if (v < 0) ok = false;
+                    id[k] = (int32_t)v;
+                }
+                if (!ok) {
+                    ++missing[(size_t)t];
+                    continue;
+                }
+                ptri[(size_t)t].insert(ptri[(size_t)t].end(), id, id + 3);
+                pleaf[(size_t)t].push_back((int32_t)i);
+            }
+        }
+    });
+    std::vector<int> order;
+    for (unsigned t = 0; t < nth; ++t)
+        if (first[t] >= 0) order.push_back((int)t);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return first[a] < first[b]; });
+    int64_t miss = 0;
+    for (int t : order) {
+        // interior points of this thread's leaves follow the edge points
+        const int32_t base = (int32_t)(M->xyz.size() / 3);
+        for (int32_t &v : ptri[(size_t)t])
+            if (v < 0) v = base + (-1 - v);
+        M->xyz.insert(M->xyz.end(), pxyz[(size_t)t].begin(), pxyz[(size_t)t].end());
+        M->tri.insert(M->tri.end(), ptri[(size_t)t].begin(), ptri[(size_t)t].end());
+        M->tri_leaf.insert(M->tri_leaf.end(), pleaf[(size_t)t].begin(), pleaf[(size_t)t].end());
+        M->n_loops += loops[(size_t)t];
+        M->n_fallback += fb[(size_t)t];
+        miss += missing[(size_t)t];
+    }
+    if (miss > 0) {
+        delete M;
+        return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
+    }
+    // faces of SURFACE leaves that cross c with no SURFACE leaf of the level
+    // across: the mesh is open there (the bound discarded that cube)
+    {
+        std::unordered_map<uint64_t, int64_t> at;
+        at.reserve((size_t)ns * 2);
+        auto ck = [](int64_t x, int64_t y, int64_t z) {
+            return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
+                   (uint64_t)(z & 0x1FFFFF);
+        };
+        for (int64_t i : surf) {
+            const tms_leaf &lf = L[(size_t)i];
+            at[ck(lf.ix, lf.iy, lf.iz)] = i;
+        }
+        const Topo &T = topo();
+        int64_t open = 0;
+        for (int64_t i : surf) {
+            const tms_leaf &lf = L[(size_t)i];
+            for (int fi = 0; fi < 6; ++fi) {
+                bool hi = false, lo = false;
+                for (int k = 0; k < 4; ++k) {
+                    if ((lf.mask >> T.F[fi].corner[k]) & 1) hi = true;
+                    else lo = true;
+                }
+                if (!(hi && lo)) continue;
+                int64_t q[3] = {lf.ix, lf.iy, lf.iz};
+                q[fi >> 1] += (fi & 1) ? 1 : -1;
+                if (!at.count(ck(q[0], q[1], q[2]))) ++open;
+            }
+        }
+        M->open_faces = open;
+    }
+    *out = M;
+    return std::string();
+}
+
+void set_msg(char *msg, int64_t len, const std::string &s) {
+    if (!msg || len <= 0) return;
+    const size_t k = std::min<size_t>((size_t)len - 1, s.size());
+    std::memcpy(msg, s.data(), k);
+    msg[k] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
+                       const double *corner_phi, const tms_vertex *verts, int64_t nv,
+                       tms_mesh **out) {
+    if (!ctx) return TMS_E_INVALID;
+    if (!out || !cells || n < 0 || nv < 0 || (n > 0 && (!leaves || !corner_phi)) ||
+        (nv > 0 && !verts))
+        return mfail(ctx, TMS_E_INVALID, "invalid arguments to tms_mesh_build");
+    *out = nullptr;
+    if (std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
+        return mfail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
+    if (cells->nconf != 1)
+        return mfail(ctx, TMS_E_INVALID, "tms_mesh_build takes cells of one conformation");
+    const Grid &g = cells->g;
+    std::vector<tms_leaf> L((size_t)n);
+    std::vector<double> cp((size_t)n * 8);
+    std::vector<tms_vertex> V((size_t)nv);
+    if (hipSetDevice(ctx->device) != hipSuccess ||
+        (n > 0 && hipMemcpyAsync(L.data(), leaves, sizeof(tms_leaf) * n, hipMemcpyDeviceToHost,
+                                 ctx->stream) != hipSuccess) ||
+        (n > 0 && hipMemcpyAsync(cp.data(), corner_phi, sizeof(double) * 8 * n,
+                                 hipMemcpyDeviceToHost, ctx->stream) != hipSuccess) ||
+        (nv > 0 && hipMemcpyAsync(V.data(), verts, sizeof(tms_vertex) * nv, hipMemcpyDeviceToHost,
+                                  ctx->stream) != hipSuccess) ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return mfail(ctx, TMS_E_DEVICE, "copying leaves, corner values or vertices to the host");
+    }
+    const std::string why = build_mesh(L, cp, V, g.c, g.K, g.h0, out);
+    if (!why.empty()) return mfail(ctx, TMS_E_INVALID, why.c_str());
+    return TMS_OK;
+}
+
+int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *corner_phi,
+                            const tms_vertex *verts, int64_t nv, double c, int32_t K, double h0,
+                            tms_mesh **out, char *msg, int64_t msg_len) {
+    set_msg(msg, msg_len, "");
+    if (!out || n < 0 || nv < 0 || (n > 0 && (!leaves || !corner_phi)) || (nv > 0 && !verts) ||
+        !(c > 0) || K < 0 || K >= TMS_MAX_LEVELS || !(h0 > 0)) {
+        set_msg(msg, msg_len, "invalid arguments to tms_mesh_build_host");
+        return TMS_E_INVALID;
+    }
+    std::vector<tms_leaf> L(leaves, leaves + n);
+    std::vector<double> cp(corner_phi, corner_phi + 8 * n);
+    std::vector<tms_vertex> V(verts, verts + nv);
+    const std::string why = build_mesh(L, cp, V, c, K, h0, out);
+    if (!why.empty()) {
+        set_msg(msg, msg_len, why);
+        return TMS_E_INVALID;
+    }
+    return TMS_OK;
+}
+
+int32_t tms_mesh_info(const tms_mesh *m, int64_t *n_vertices, int64_t *n_triangles,
+                      int64_t *n_loops, int64_t *n_fallback, int64_t *open_faces) {
+    if (!m) return TMS_E_INVALID;
+    if (n_vertices) *n_vertices = (int64_t)(m->xyz.size() / 3);
+    if (n_triangles) *n_triangles = (int64_t)(m->tri.size() / 3);
+    if (n_loops) *n_loops = m->n_loops;
+    if (n_fallback) *n_fallback = m->n_fallback;
+    if (open_faces) *open_faces = m->open_faces;
+    return TMS_OK;
+}
+
+int32_t tms_mesh_get(const tms_mesh *m, double *xyz, int32_t *tri, int32_t *tri_leaf) {
+    if (!m) return TMS_E_INVALID;
+    if (xyz) std::memcpy(xyz, m->xyz.data(), sizeof(double) * m->xyz.size());
+    if (tri) std::memcpy(tri, m->tri.data(), sizeof(int32_t) * m->tri.size());
+    if (tri_leaf) std::memcpy(tri_leaf, m->tri_leaf.data(), sizeof(int32_t) * m->tri_leaf.size());
+    return TMS_OK;
+}
+
+int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report *r) {
+    if (!m || !r) return TMS_E_INVALID;
+    std::memset(r, 0, sizeof *r);
+    const int64_t nv = (int64_t)(m->xyz.size() / 3), nt = (int64_t)(m->tri.size() / 3);
+    const int32_t *T = m->tri.data();
+    const double *X = m->xyz.data();
+    r->n_vertices = nv;
+    r->n_triangles = nt;
+    r->n_loops = m->n_loops;
+    r->n_fallback = m->n_fallback;
+    r->open_faces = m->open_faces;
+    // (a) edges: (min, max, direction) of every triangle side, sorted
+    struct HE {
+        int32_t a, b;
+        int8_t dir;
+    };
+    std::vector<HE> he((size_t)nt * 3);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const int32_t u = T[3 * t + k], v = T[3 * t + (k + 1) % 3];
+            he[(size_t)(3 * t + k)] = {std::min(u, v), std::max(u, v), (int8_t)(u < v ? 1 : -1)};
+        }
+    std::sort(he.begin(), he.end(), [](const HE &x, const HE &y) {
+        return x.a != y.a ? x.a < y.a : x.b < y.b;
+    });
+    std::vector<uint8_t> bad((size_t)nv, 0);
+    int64_t nedges = 0;
+    for (size_t i = 0; i < he.size();) {
+        size_t j = i;
+        int s = 0;
+        while (j < he.size() && he[j].a == he[i].a && he[j].b == he[i].b) s += he[j++].dir;
+        const size_t k = j - i;
+        ++nedges;
+        if (k == 1) ++r->boundary_edges;
+        else if (k > 2) ++r->nonmanifold_edges;
+        else if (s != 0) ++r->misoriented_edges;
+        if (k != 2 || s != 0) bad[(size_t)he[i].a] = bad[(size_t)he[i].b] = 1;
+        i = j;
+    }
+    // (b) vertex neighbourhoods: the sides opposite a vertex in its triangles
+    // must form one cycle
+    std::vector<int64_t> off((size_t)nv + 1, 0);
+    for (int64_t t = 0; t < 3 * nt; ++t) ++off[(size_t)T[t] + 1];
+    for (int64_t v = 0; v < nv; ++v) off[(size_t)v + 1] += off[(size_t)v];
+    std::vector<int32_t> inc((size_t)(3 * nt));
+    {
+        std::vector<int64_t> pos(off.begin(), off.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int k = 0; k < 3; ++k) inc[(size_t)pos[(size_t)T[3 * t + k]]++] = (int32_t)t;
+    }
+    std::atomic<int64_t> badv{0};
+    parallel_for(nv, [&](int64_t b, int64_t e, int) {
+        std::vector<std::pair<int32_t, int32_t>> link;
+        for (int64_t v = b; v < e; ++v) {
+            link.clear();
+            for (int64_t p = off[(size_t)v]; p < off[(size_t)v + 1]; ++p) {
+                const int32_t t = inc[(size_t)p];
+                int32_t o[2], c = 0;
+                for (int k = 0; k < 3; ++k)
+                    if (T[3 * t + k] != v) o[c++] = T[3 * t + k];
+                if (c == 2) link.push_back({o[0], o[1]});
+            }
+            bool ok = !link.empty();
+            if (ok) {
+                // every link vertex twice, and one cycle through all sides
+                std::unordered_map<int32_t, int> deg;
+                for (auto &s : link) {
+                    ++deg[s.first];
+                    ++deg[s.second];
+                }
+                for (auto &d : deg)
+                    if (d.second != 2) ok = false;
+                if (ok) {
+                    std::vector<char> seen(link.size(), 0);
+                    size_t cnt = 1;
+                    seen[0] = 1;
+                    int32_t cur = link[0].second;
+                    const int32_t start = link[0].first;
+                    while (cur != start && cnt <= link.size()) {
+                        size_t nx = link.size();
+                        for (size_t q = 0; q < link.size(); ++q)
+                            if (!seen[q] && (link[q].first == cur || link[q].second == cur)) {
+                                nx = q;
+                                break;
+                            }
+                        if (nx == link.size()) break;
+                        seen[nx] = 1;
+                        ++cnt;
+                        cur = link[nx].first == cur ? link[nx].second : link[nx].first;
+                    }
+                    ok = cur == start && cnt == link.size();
+                }
+            }
+            if (!ok || bad[(size_t)v]) badv.fetch_add(1);
+        }
+    });
+    r->nonmanifold_vertices = badv.load();
+    // components (union-find over triangle sides) and Euler characteristic
+    {
+        std::vector<int32_t> par((size_t)nv);
+        std::iota(par.begin(), par.end(), 0);
+        std::function<int32_t(int32_t)> find = [&](int32_t x) {
+            while (par[(size_t)x] != x) {
+                par[(size_t)x] = par[(size_t)par[(size_t)x]];
+                x = par[(size_t)x];
+            }
+            return x;
+        };
+        std::vector<char> usedv((size_t)nv, 0);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int k = 0; k < 3; ++k) {
+                usedv[(size_t)T[3 * t + k]] = 1;
+                const int32_t a = find(T[3 * t + k]), b = find(T[3 * t + (k + 1) % 3]);
+                if (a != b) par[(size_t)a] = b;
+            }
+        int64_t comps = 0, nvu = 0;
+        for (int64_t v = 0; v < nv; ++v)
+            if (usedv[(size_t)v]) {
+                ++nvu;
+                if (find((int32_t)v) == v) ++comps;
+            }
+        r->components = comps;
+        r->euler = nvu - nedges + nt;
+        r->unused_vertices = nv - nvu;
+    }
+    // area, enclosed volume (outward orientation gives a positive volume)
+    double area = 0.0, vol = 0.0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const double *p = X + 3 * T[3 * t], *q = X + 3 * T[3 * t + 1], *s = X + 3 * T[3 * t + 2];
+        double u[3], w[3], n[3];
+        sub3(q, p, u);
+        sub3(s, p, w);
+        crs3(u, w, n);
+        area += 0.5 * std::sqrt(dot3(n, n));
+        double qs[3];
+        crs3(q, s, qs);
+        vol += dot3(p, qs) / 6.0;
+    }
+    r->area = area;
+    r->volume = vol;
+    r->density = area > 0 ? (double)nv / area : 0.0;
+    // (c) intersecting pairs among triangles of the same or touching leaves
+    if (intersections) {
+        const int64_t nl = (int64_t)(m->leaf_ijk.size() / 3);
+        std::unordered_map<uint64_t, std::vector<int32_t>> by;
+        auto ck = [](int64_t x, int64_t y, int64_t z) {
+            return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
+                   (uint64_t)(z & 0x1FFFFF);
+        };
+        for (int64_t t = 0; t < nt; ++t) {
+            const int32_t li = m->tri_leaf[(size_t)t];
+            if (li < 0 || li >= nl) continue;
+            const int32_t *c = &m->leaf_ijk[3 * (size_t)li];
+            by[ck(c[0], c[1], c[2])].push_back((int32_t)t);
+        }
+        std::vector<uint64_t> keys;
+        keys.reserve(by.size());
+        for (auto &kv : by) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end());
+        std::atomic<int64_t> hits{0};
+        parallel_for((int64_t)keys.size(), [&](int64_t b, int64_t e, int) {
+            for (int64_t ki = b; ki < e; ++ki) {
+                const uint64_t k0 = keys[(size_t)ki];
+                const int64_t x = (int64_t)(k0 >> 42), y = (int64_t)((k0 >> 21) & 0x1FFFFF),
+                              z = (int64_t)(k0 & 0x1FFFFF);
+                const auto &A = by.find(k0)->second;
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const uint64_t k1 = ck(x + dx, y + dy, z + dz);
+                            if (k1 < k0) continue;  // each leaf pair once
+                            auto it = by.find(k1);
+                            if (it == by.end()) continue;
+                            const auto &B = it->second;
+                            for (size_t i = 0; i < A.size(); ++i)
+                                for (size_t j = (k1 == k0 ? i + 1 : 0); j < B.size(); ++j) {
+                                    const int32_t s = A[i], t = B[j];
+                                    bool share = false;
+                                    for (int p = 0; p < 3; ++p)
+                                        for (int q = 0; q < 3; ++q)
+                                            if (T[3 * s + p] == T[3 * t + q]) share = true;
+                                    if (share) continue;
+                                    if (tri_tri(X + 3 * T[3 * s], X + 3 * T[3 * s + 1],
+                                                X + 3 * T[3 * s + 2], X + 3 * T[3 * t],
+                                                X + 3 * T[3 * t + 1], X + 3 * T[3 * t + 2]))
+                                        hits.fetch_add(1);
+                                }
+                        }
+            }
+        });
+        r->intersecting_pairs = hits.load();
+    } else {
+        r->intersecting_pairs = -1;
+    }
+    return TMS_OK;
+}
+
+int32_t tms_mesh_write_off(const tms_mesh *m, const char *path) {
+    if (!m || !path) return TMS_E_INVALID;
+    FILE *fp = std::fopen(path, "w");
+    if (!fp) return TMS_E_INVALID;
+    const int64_t nv = (int64_t)(m->xyz.size() / 3), nt = (int64_t)(m->tri.size() / 3);
+    std::fprintf(fp, "OFF\n%lld %lld 0\n", (long long)nv, (long long)nt);
+    for (int64_t v = 0; v < nv; ++v)
+        std::fprintf(fp, "%.17g %.17g %.17g\n", m->xyz[3 * v], m->xyz[3 * v + 1], m->xyz[3 * v + 2]);
+    for (int64_t t = 0; t < nt; ++t)
+        std::fprintf(fp, "3 %d %d %d\n", m->tri[3 * t], m->tri[3 * t + 1], m->tri[3 * t + 2]);
+    const bool ok = std::fclose(fp) == 0;
+    return ok ? TMS_OK : TMS_E_INVALID;
+}
+
+int32_t tms_mesh_free(tms_mesh *m) {
+    delete m;
+    return TMS_OK;
+}
+
+}  // extern "C"

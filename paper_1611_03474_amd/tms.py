@@ -43,6 +43,79 @@ class Timing(C.Structure):
                 for i, k in enumerate(T_SLOTS)}
 
 
+class MeshReport(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "n_vertices", "n_triangles", "n_loops", "n_fallback", "open_faces", "boundary_edges",
+        "nonmanifold_edges", "misoriented_edges", "nonmanifold_vertices", "intersecting_pairs",
+        "components", "euler", "unused_vertices")] + [
+        ("area", C.c_double), ("volume", C.c_double), ("density", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Mesh:
+    """A host mesh of tms_mesh_build (Section 2.3): .xyz [nv, 3], .tri [nt, 3],
+    .tri_leaf [nt] (numpy), counts in .info."""
+
+    def __init__(self, lib, handle):
+        self.lib, self.h = lib, handle
+        i64 = C.c_int64
+        v = [i64() for _ in range(5)]
+        lib.tms_mesh_info(handle, *[C.byref(x) for x in v])
+        nv, nt = v[0].value, v[1].value
+        self.info = dict(n_vertices=nv, n_triangles=nt, n_loops=v[2].value,
+                         n_fallback=v[3].value, open_faces=v[4].value)
+        self.xyz = np.zeros((nv, 3))
+        self.tri = np.zeros((nt, 3), dtype=np.int32)
+        self.tri_leaf = np.zeros(nt, dtype=np.int32)
+        lib.tms_mesh_get(handle, self.xyz.ctypes.data_as(_VP), self.tri.ctypes.data_as(_VP),
+                         self.tri_leaf.ctypes.data_as(_VP))
+
+    def check(self, intersections: bool = True) -> dict:
+        r = MeshReport()
+        rc = self.lib.tms_mesh_check(self.h, int(bool(intersections)), C.byref(r))
+        if rc != TMS_OK:
+            raise TmsError(rc, "tms_mesh_check")
+        return r.as_dict()
+
+    def write_off(self, path: str):
+        rc = self.lib.tms_mesh_write_off(self.h, str(path).encode())
+        if rc != TMS_OK:
+            raise TmsError(rc, "cannot write %s" % path)
+
+    def free(self):
+        if self.h:
+            self.lib.tms_mesh_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def mesh_build_host(leaves: np.ndarray, corner_phi: np.ndarray, verts: np.ndarray, c: float,
+                    K: int, h0: float) -> Mesh:
+    """tms_mesh_build_host on host arrays: leaves (LEAF_DTYPE), corner values
+    [n, 8], vertices (VERTEX_DTYPE, ascending keys)."""
+    L = load_library()
+    lv = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    cp = np.ascontiguousarray(corner_phi, dtype=np.float64).reshape(-1, 8)
+    vv = np.ascontiguousarray(verts, dtype=VERTEX_DTYPE)
+    assert len(lv) == len(cp)
+    h = _VP()
+    msg = C.create_string_buffer(256)
+    rc = L.tms_mesh_build_host(lv.ctypes.data_as(_VP), len(lv), cp.ctypes.data_as(_VP),
+                               vv.ctypes.data_as(_VP), len(vv), float(c), int(K), float(h0),
+                               C.byref(h),
+                               msg, 256)
+    if rc != TMS_OK:
+        raise TmsError(rc, msg.value.decode())
+    return Mesh(L, h)
+
+
 class Tuning(C.Structure):
     _fields_ = [("slice_cubes", C.c_int64), ("tiled_min_level", C.c_int32),
                 ("tile_atoms", C.c_int32), ("proj_table", C.c_int32),
@@ -138,6 +211,17 @@ def load_library(path: str = LIB_PATH):
     L.tms_debug_bound.argtypes = [_VP, _VP, _VP, i64, _VP]
     L.tms_debug_fast_exp.argtypes = [_VP, _VP, i64, _VP]
     L.tms_debug_phi_pairs.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
+    L.tms_mesh_build.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(_VP)]
+    L.tms_mesh_build_host.argtypes = [_VP, i64, _VP, _VP, i64, C.c_double, i32, C.c_double,
+                                      C.POINTER(_VP), C.c_char_p, i64]
+    L.tms_mesh_info.argtypes = [_VP] + [C.POINTER(i64)] * 5
+    L.tms_mesh_get.argtypes = [_VP, _VP, _VP, _VP]
+    L.tms_mesh_check.argtypes = [_VP, i32, C.POINTER(MeshReport)]
+    L.tms_mesh_write_off.argtypes = [_VP, C.c_char_p]
+    L.tms_mesh_free.argtypes = [_VP]
+    for f in ("tms_mesh_build", "tms_mesh_build_host", "tms_mesh_info", "tms_mesh_get", "tms_mesh_check",
+              "tms_mesh_write_off", "tms_mesh_free"):
+        getattr(L, f).restype = i32
     for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
               "tms_build_cells", "tms_cells_info", "tms_free_cells", "tms_eval_phi",
               "tms_eval_phi_noalloc", "tms_stage2_points", "tms_debug_phi_pairs",
@@ -307,6 +391,14 @@ class Context:
         return int(ng.value)
 
     # ------------------------------------------------------------ partition
+    def mesh_build(self, cells: Cells, leaves, cphi, verts) -> "Mesh":
+        """tms_mesh_build on device tensors from partition_estimate / extract."""
+        h = _VP()
+        self._check(self.lib.tms_mesh_build(self.h, cells.handle, _VP(_ptr(leaves)),
+                                            leaves.shape[0], _VP(_ptr(cphi)), _VP(_ptr(verts)),
+                                            verts.shape[0], C.byref(h)))
+        return Mesh(self.lib, h)
+
     def partition_estimate(self, cells: Cells, cap: int | None = None):
         """Returns (leaves uint8 tensor [L, 20], corner_phi [L, 8], stats dict)."""
         t = self._torch

@@ -1,0 +1,159 @@
+"""The host Stage 2 of the library (tms_mesh_build_host: loops, ear clipping,
+the manifold checks of Section 3.2) against the oracle, on the oracle's own
+partitions.  CPU only: the host entry point takes host arrays.
+
+* Face segments: in every SURFACE leaf the sides used once by the leaf's
+  triangles are the face segments of the leaf (as pairs of edge keys), and
+  they equal the oracle's segments, which pair ambiguous faces by brute-force
+  connectivity of {g >= c}.
+* Checks: the library's report equals the oracle checker's on the same mesh
+  ((a), (b), (c), components, Euler characteristic, area, volume).
+* Closed forms: one atom gives a sphere of radius R, R^2 = r^2 - ln(c)/D
+  (Euler characteristic 2, area and volume within 1 %); two distant atoms two
+  spheres; a ring of atoms a torus (Euler characteristic 0); a 200-atom
+  globule a closed manifold with no defect.
+* Open faces (a crossing face of a SURFACE leaf with no SURFACE leaf across)
+  are counted, and the holes' rims are the only defects.
+* An OFF file reads back; SURFACE leaves of two levels are refused.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mesh as om
+from paper_1611_03474_amd import synth, tms
+
+
+def _leaves(r):
+    L = np.zeros(r.n_leaves, dtype=tms.LEAF_DTYPE)
+    L["ix"], L["iy"], L["iz"] = r.ijk[:, 0], r.ijk[:, 1], r.ijk[:, 2]
+    L["level"], L["reason"], L["mask"], L["cls"] = r.level, r.reason, r.mask, r.cls
+    return L
+
+
+def _verts(r):
+    V = np.zeros(r.n_vert, dtype=tms.VERTEX_DTYPE)
+    V["edge_key"], V["t"] = r.vkey, r.vt
+    V["x"], V["y"], V["z"] = r.vxyz[:, 0], r.vxyz[:, 1], r.vxyz[:, 2]
+    return V
+
+
+def _mesh(atoms, D=0.9, tau=1e-3, c=1.0, h0=2.0, h_min=0.25):
+    r = oracle.partition(atoms, D, c=c, tau=tau, h0=h0, h_min=h_min)
+    m = tms.mesh_build_host(_leaves(r), r.corner_phi, _verts(r), c, r.K, h0)
+    return r, m
+
+
+@pytest.fixture(scope="module")
+def glob200():
+    return _mesh(synth.globule(200, 1001))
+
+
+def test_face_segments_equal_oracle(glob200):
+    r, m = glob200
+    nvk = r.n_vert
+    # sides used once within each leaf's triangles (interior points excluded)
+    got = {}
+    for t, leaf in zip(m.tri, m.tri_leaf):
+        for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
+            k = (int(leaf), min(a, b), max(a, b))
+            got[k] = got.get(k, 0) + 1
+    g_segs = {(lf, int(r.vkey[a]), int(r.vkey[b])) if r.vkey[a] < r.vkey[b]
+              else (lf, int(r.vkey[b]), int(r.vkey[a]))
+              for (lf, a, b), cnt in got.items() if cnt == 1 and a < nvk and b < nvk}
+    o_segs = set()
+    for i in np.flatnonzero(r.cls == oracle.CLS_SURFACE):
+        for s in om.leaf_face_segments(r.corner_phi[i], 1.0):
+            e1, e2 = sorted(s)
+            k1 = om.edge_key(0, int(r.level[i]), r.K, r.ijk[i], e1)
+            k2 = om.edge_key(0, int(r.level[i]), r.K, r.ijk[i], e2)
+            o_segs.add((int(i), min(k1, k2), max(k1, k2)))
+    print("segments: library %d, oracle %d, fanned loops %d" % (len(g_segs), len(o_segs),
+                                                                m.info["n_fallback"]))
+    assert g_segs == o_segs
+
+
+def test_checks_equal_oracle(glob200):
+    r, m = glob200
+    got = m.check()
+    ref = om.check_mesh(m.xyz, m.tri, cell=0.5)
+    print(got)
+    for k in ("boundary_edges", "nonmanifold_edges", "misoriented_edges", "nonmanifold_vertices",
+              "intersecting_pairs", "components", "euler"):
+        assert got[k] == ref[k], k
+    assert abs(got["area"] - ref["area"]) <= 1e-9 * ref["area"]
+    assert abs(got["volume"] - ref["volume"]) <= 1e-9 * abs(ref["volume"])
+    # a closed manifold: no defect of (a), (b) or (c), every vertex used
+    assert got["boundary_edges"] == got["nonmanifold_vertices"] == got["intersecting_pairs"] == 0
+    assert got["misoriented_edges"] == 0 and got["unused_vertices"] == 0
+    assert got["euler"] % 2 == 0 and got["volume"] > 0
+    assert got["density"] > 0
+
+
+@pytest.mark.parametrize("center", [(0.3, -0.2, 0.1), (0.0, 0.0, 0.0), (0.61, 0.17, -0.33)])
+def test_sphere(center):
+    D, r0 = 0.9, 1.7
+    _, m = _mesh(np.array([[*center, r0]]), D=D)
+    rep = m.check()
+    R = np.sqrt(r0 * r0 - np.log(1.0) / D)
+    print(rep)
+    assert rep["euler"] == 2 and rep["components"] == 1
+    assert rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    assert abs(rep["area"] / (4 * np.pi * R * R) - 1) < 0.01
+    assert abs(rep["volume"] / (4 / 3 * np.pi * R ** 3) - 1) < 0.01
+    d = np.linalg.norm(m.xyz - np.array(center), axis=1)
+    assert np.max(np.abs(d - R)) < 0.05
+
+
+def test_two_spheres_and_torus():
+    _, m = _mesh(np.array([[0, 0, 0, 1.6], [8.3, 0.4, 0.2, 1.5]]))
+    rep = m.check()
+    assert m.info["open_faces"] == 0
+    assert rep["components"] == 2 and rep["euler"] == 4 and rep["nonmanifold_vertices"] == 0
+    # a ring of 16 atoms of radius 1.5 on a circle of radius 5: a torus
+    a = np.array([[5 * np.cos(k * np.pi / 8), 5 * np.sin(k * np.pi / 8), 0.0, 1.5]
+                  for k in range(16)])
+    _, m = _mesh(a)
+    rep = m.check()
+    print(rep)
+    assert m.info["open_faces"] == 0
+    assert rep["components"] == 1 and rep["euler"] == 0
+    assert rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+
+
+def test_open_faces_counted():
+    # here the bound discards a coarse cube next to the sphere although the
+    # finest lattice values inside it cross c: the host mesh has holes there,
+    # each crossing face of a SURFACE leaf with nothing across is one open
+    # face, and the only defects are the holes' rims
+    _, m = _mesh(np.array([[9.0, 1.0, -0.5, 1.5]]))
+    rep = m.check()
+    nopen = m.info["open_faces"]
+    assert nopen > 0
+    assert nopen <= rep["boundary_edges"] <= 2 * nopen
+    assert rep["nonmanifold_edges"] == rep["misoriented_edges"] == 0
+    assert rep["nonmanifold_vertices"] == rep["boundary_edges"]
+    assert rep["intersecting_pairs"] == 0
+
+
+def test_off_roundtrip(glob200, tmp_path):
+    _, m = glob200
+    p = tmp_path / "s.off"
+    m.write_off(str(p))
+    lines = p.read_text().split("\n")
+    assert lines[0] == "OFF"
+    nv, nt, _ = map(int, lines[1].split())
+    assert nv == len(m.xyz) and nt == len(m.tri)
+    X = np.array([list(map(float, ln.split())) for ln in lines[2:2 + nv]])
+    T = np.array([list(map(int, ln.split()))[1:] for ln in lines[2 + nv:2 + nv + nt]])
+    assert np.array_equal(X, m.xyz) and np.array_equal(T, m.tri)
+
+
+def test_mixed_levels_refused():
+    r = oracle.partition(synth.globule(120, 1003), 0.9, tau=1e-3)
+    L = _leaves(r)
+    s = np.flatnonzero(L["cls"] == tms.CLS_SURFACE)
+    L["level"][s[0]] -= 1
+    with pytest.raises(tms.TmsError) as ei:
+        tms.mesh_build_host(L, r.corner_phi, _verts(r), 1.0, r.K, 2.0)
+    assert ei.value.code == tms.TMS_E_INVALID and "levels" in str(ei.value)

@@ -1,0 +1,131 @@
+"""Pins for the oracle's Stage-2 mesh functions (oracle/mesh.py) against
+closed forms and hand-built meshes.  CPU only.
+
+* Face pairing: the brute-force connectivity of {g >= c} on a bilinear face
+  agrees with the classical saddle-value criterion (the two corners at or
+  above c are connected through the face iff the bilinear's value at its
+  saddle point is >= c), away from ties.
+* Loops: a planar field crossing four parallel edges gives one loop of four;
+  every crossing edge lies in exactly two face segments.
+* The mesh checker on meshes whose answers are known: a tetrahedron, an
+  octahedron and a torus (closed, Euler characteristic 2, 2 and 0, exact
+  volumes), a tetrahedron with a face missing (three boundary edges), a
+  flipped face (misoriented edges), two tetrahedra sharing one vertex (one
+  vertex whose neighbourhood is two loops), two crossing triangles.
+"""
+import numpy as np
+import pytest
+
+from oracle import mesh as om
+
+
+def test_face_pairing_matches_saddle_criterion():
+    rng = np.random.default_rng(5)
+    c, n = 1.0, 0
+    while n < 60:
+        hi = c + rng.uniform(0.05, 1.0, 2)
+        lo = c - rng.uniform(0.05, 1.0, 2)
+        if rng.random() < 0.5:
+            F = [[hi[0], lo[0]], [lo[1], hi[1]]]   # (0,0), (1,1) high
+        else:
+            F = [[lo[0], hi[0]], [hi[1], lo[1]]]   # (0,1), (1,0) high
+        h00, h01, h10, h11 = F[0][0], F[0][1], F[1][0], F[1][1]
+        sad = (h00 * h11 - h10 * h01) / (h00 + h11 - h10 - h01)
+        if abs(sad - c) < 0.05:
+            continue
+        assert om.high_corners_joined(F, c) == (sad >= c), (F, sad)
+        n += 1
+
+
+def test_planar_field_one_loop_of_four():
+    # g = c + (x - 0.4): the four edges along x cross, one loop around them
+    f = [1.0 + ((v & 1) - 0.4) for v in range(8)]
+    segs = om.leaf_face_segments(f, 1.0)
+    loops = om.loops_from_segments(segs)
+    assert len(loops) == 1 and sorted(loops[0]) == [0, 1, 2, 3]
+
+
+def test_every_crossing_edge_in_two_segments():
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        f = 1.0 + rng.normal(size=8)
+        segs = om.leaf_face_segments(f, 1.0)
+        cross = [e for e in range(12)
+                 if (f[om.edge_corners(e)[0]] >= 1.0) != (f[om.edge_corners(e)[1]] >= 1.0)]
+        cnt = {}
+        for s in segs:
+            for e in s:
+                cnt[e] = cnt.get(e, 0) + 1
+        assert sorted(cnt) == sorted(cross) and all(v == 2 for v in cnt.values())
+        assert sum(len(L) for L in om.loops_from_segments(segs)) == len(cross)
+
+
+TET = (np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float),
+       np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]]))
+
+
+def test_tetrahedron():
+    r = om.check_mesh(*TET)
+    assert r["boundary_edges"] == r["nonmanifold_edges"] == r["misoriented_edges"] == 0
+    assert r["nonmanifold_vertices"] == 0 and r["intersecting_pairs"] == 0
+    assert r["euler"] == 2 and r["components"] == 1
+    assert abs(r["volume"] - 1 / 6) < 1e-15  # outward orientation
+
+
+def test_octahedron_volume_and_area():
+    X = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    T = []
+    for a in (0, 1):
+        for b in (2, 3):
+            for c in (4, 5):
+                t = [a, b, c]
+                n = np.cross(X[b] - X[a], X[c] - X[a])
+                if np.dot(n, X[a] + X[b] + X[c]) < 0:
+                    t = [a, c, b]
+                T.append(t)
+    r = om.check_mesh(X, np.array(T))
+    assert r["euler"] == 2 and r["nonmanifold_vertices"] == 0 and r["misoriented_edges"] == 0
+    assert abs(r["volume"] - 4 / 3) < 1e-14
+    assert abs(r["area"] - 8 * np.sqrt(3) / 2) < 1e-13
+
+
+def test_torus_euler_zero():
+    n, m, R, a = 12, 8, 3.0, 1.0
+    X = np.array([[(R + a * np.cos(v * 2 * np.pi / m)) * np.cos(u * 2 * np.pi / n),
+                   (R + a * np.cos(v * 2 * np.pi / m)) * np.sin(u * 2 * np.pi / n),
+                   a * np.sin(v * 2 * np.pi / m)] for u in range(n) for v in range(m)])
+    T = []
+    for u in range(n):
+        for v in range(m):
+            p, q = u * m + v, ((u + 1) % n) * m + v
+            p1, q1 = u * m + (v + 1) % m, ((u + 1) % n) * m + (v + 1) % m
+            T += [[p, q, q1], [p, q1, p1]]
+    r = om.check_mesh(X, np.array(T), cell=1.5)
+    assert r["euler"] == 0 and r["components"] == 1
+    assert r["nonmanifold_vertices"] == 0 and r["intersecting_pairs"] == 0
+    assert r["misoriented_edges"] == 0
+
+
+def test_defects_counted():
+    X, T = TET
+    r = om.check_mesh(X, T[:3])          # a face missing
+    assert r["boundary_edges"] == 3 and r["nonmanifold_vertices"] == 3
+    T2 = T.copy()
+    T2[3] = T2[3][::-1]                    # one face flipped
+    r = om.check_mesh(X, T2)
+    assert r["misoriented_edges"] == 3 and r["boundary_edges"] == 0
+    # two tetrahedra sharing vertex 0: its neighbourhood is two loops
+    Y = np.vstack([X, -X[1:]])
+    T3 = np.vstack([T, np.array([[0, 6, 5], [0, 5, 4], [0, 4, 6], [4, 5, 6]])])
+    r = om.check_mesh(Y, T3)
+    assert r["nonmanifold_vertices"] == 1 and r["boundary_edges"] == 0
+    assert r["euler"] == 3
+
+
+def test_crossing_triangles():
+    X = np.array([[0, 0, 0], [2, 0, 0], [0, 2, 0], [0.5, 0.5, -1], [0.5, 0.5, 1], [3, 3, 0]], float)
+    r = om.check_mesh(X, np.array([[0, 1, 2], [3, 4, 5]]))
+    assert r["intersecting_pairs"] == 1
+    Z = X.copy()
+    Z[3:, 2] += 5.0
+    assert om.check_mesh(Z, np.array([[0, 1, 2], [3, 4, 5]]))["intersecting_pairs"] == 0
