@@ -83,7 +83,7 @@ def spread(ms):
             "p90": float(np.percentile(a, 90)), "n": int(len(a))}
 
 
-def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
+def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup, with_mesh=False):
     import torch
     p = w.params(precision)
     cells = ctx.build_cells(atoms_dev, p)
@@ -128,6 +128,23 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
               "device_ms": s2tm["stage2"]["ms"] / 3,
               "leaves_per_s": nl / (spread(s2_ms)["median"] * 1e-3)}
     del s2rec
+    # the Stage-2 mesh (host, Section 2.3) of the pass's leaves with open
+    # faces closed, and its manifold checks (a), (b) (no intersection test at
+    # this size), outside the step
+    mesh = None
+    if with_mesh:
+        m_ms, m = timed_steps(lambda: ctx.mesh_build(cells, lb[:nl], cb[:nl], vb[:nv]), 1)
+        t0 = time.perf_counter()
+        rep = m.check(intersections=False)
+        c_ms = (time.perf_counter() - t0) * 1e3
+        mesh = {"build_ms": m_ms[0], "check_ms": c_ms, "threads": os.cpu_count(),
+                "surface_leaves_per_s": sd["n_surface"] / (m_ms[0] * 1e-3),
+                **{k: rep[k] for k in ("n_vertices", "n_triangles", "n_loops", "n_fallback",
+                                       "open_faces", "added_cubes", "boundary_edges",
+                                       "nonmanifold_edges", "misoriented_edges",
+                                       "nonmanifold_vertices", "components", "euler",
+                                       "unused_vertices", "area", "volume", "density")}}
+        del m
     # the same pass replayed from a captured graph (build eager, rest one
     # graph) that writes its results into lb, cb, vb
     ctx.graph_capture(cells, margin=1.1, leaves=lb, cphi=cb, verts=vb)
@@ -143,7 +160,8 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup):
     ctx.free_cells(cells)
     return dict(ms_per_step=spread(step_ms)["mean"], step_ms=spread(step_ms), stats=sd,
                 n_leaves=nl, n_vertices=nv, timing=per_step, phi_pairs=phi_pairs,
-                stage2=stage2, graph_ms_per_step=spread(g_ms)["mean"], graph_step_ms=spread(g_ms))
+                stage2=stage2, mesh=mesh, graph_ms_per_step=spread(g_ms)["mean"],
+                graph_step_ms=spread(g_ms))
 
 
 def run_variants(ctx, tms, atoms_dev, w, steps, warmup):
@@ -351,6 +369,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the Stage-2 mesh leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the estimator variants (re-expanded children, degree 2)")
     ap.add_argument("--workload", default="assembly110k")
@@ -388,7 +407,11 @@ def main():
     ctx = tms.Context(0)
 
     log("FP32+guard run")
-    f32 = run_mode(ctx, tms, atoms_dev, w, tms.PREC_FP32_GUARD, args.steps, args.warmup)
+    f32 = run_mode(ctx, tms, atoms_dev, w, tms.PREC_FP32_GUARD, args.steps, args.warmup,
+                   with_mesh=not args.no_mesh)
+    if f32["mesh"]:
+        log("  mesh %s" % {k: f32["mesh"][k] for k in ("build_ms", "n_triangles", "added_cubes",
+                                                      "boundary_edges", "nonmanifold_vertices")})
     log("  %.2f ms/step" % f32["ms_per_step"])
     f64 = None
     if not args.no_fp64:
@@ -482,6 +505,7 @@ def main():
         "roofline": roofline,
         "rooflines": rooflines,
         "stage2": f32["stage2"],
+        "mesh": f32["mesh"],
     }
     if f64 is not None:
         r64 = rates(f64)

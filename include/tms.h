@@ -71,6 +71,7 @@ extern "C" {
 #define TMS_REASON_UNIFORM 0   /* uniform mode                                   */
 #define TMS_REASON_CONVERGED 1 /* higher-order mass 2E <= tau (Step 3)          */
 #define TMS_REASON_HMIN 2      /* kept by the bound at the finest level          */
+#define TMS_REASON_CLOSED 3    /* added by tms_mesh_build across an open face    */
 #define TMS_CLS_OUTSIDE 0      /* every corner value below c                     */
 #define TMS_CLS_SURFACE 1      /* corner values on both sides of c               */
 #define TMS_CLS_INSIDE 2       /* every corner value >= c                        */
@@ -454,28 +455,42 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * into closed loops on the cube's boundary, and each loop's patch is
  * triangulated by ear clipping in the plane normal to an axis along which it
  * projects to a simple polygon (the single-valued direction of the patch),
- * else fanned from its first point (counted).  Triangles point along -grad g
- * (outward, phi >= c inside).  Host code (threads); the inputs are copied
- * from the device.
+ * with no triangle side between two points of one cube face other than the
+ * face's curve segments, else fanned from a point of the patch inside the
+ * cube (counted).  Triangles
+ * point along -grad g (outward, phi >= c inside).  Host code (threads); the
+ * inputs are copied from the device.
  *
  * tms_mesh_build: cells of one conformation; leaves [n] and corner_phi [n][8]
  *   as tms_partition_estimate wrote them, verts [nv] as
  *   tms_extract_cube_vertices wrote them for those leaves (device pointers).
- *   The mesh's vertices are the nv edge points in that (key) order.  Every
+ *   The mesh's vertices are the nv edge points in that (key) order, then
+ *   those of added cubes and interior points of fanned patches.  Every
  *   SURFACE leaf must have the same level (faces between cubes of different
  *   sizes are not meshed).  *out receives a mesh owned by the caller (free it
  *   with tms_mesh_free).  An edge point within 1e-6 of its edge from a corner
  *   (a corner value equal to c puts three points on the corner) is moved to
  *   1e-6 of the edge from it, in the triangulation and in xyz.
- *   Errors: TMS_E_INVALID (arguments, several levels,
- *   an edge point missing from verts), TMS_E_DEVICE.
+ *   flags TMS_MESH_CLOSE: close open faces (below).  Where the bound of a
+ *   coarse cube stayed clear of c although phi at the finest lattice points
+ *   inside it crosses c, the surface leaves a SURFACE leaf through a face
+ *   with nothing across; with the flag, every cube of the leaves' level
+ *   across such a face (inside the root grid) is added as a SURFACE leaf
+ *   (reason TMS_REASON_CLOSED), again for the added cubes' own open faces,
+ *   up to 64 rounds.  An added cube takes the value of each corner from a
+ *   SURFACE leaf with the same corner where one exists, else phi of the
+ *   library at that point (as tms_eval_phi); its new edge points are placed
+ *   as the extraction places them.
+ *   Errors: TMS_E_INVALID (arguments, unknown flags, several levels, an edge
+ *   point missing from verts), TMS_E_OOM, TMS_E_DEVICE.
  * tms_mesh_info: vertex and triangle counts, loops, fanned loops, and the
  *   faces of SURFACE leaves whose corner values cross c but that have no
- *   SURFACE leaf across (there the bound discarded the neighbouring cube, so
- *   the surface is open).
+ *   SURFACE leaf across (the surface is open there).
  * tms_mesh_get: host copies: xyz [nv][3], tri [nt][3] (vertex indices),
- *   tri_leaf [nt] (index of the triangle's leaf in the caller's list); any
- *   pointer may be NULL.
+ *   tri_leaf [nt] (index of the triangle's leaf in the caller's list, n + k
+ *   for the k-th added cube); any pointer may be NULL.
+ * tms_mesh_added: host copies of the added cubes (leaves [k], corner_phi
+ *   [k][8]); *n_out = k; both NULL: only count; TMS_E_CAPACITY if cap < k.
  * tms_mesh_check: the three conditions of a manifold mesh (Section 3.2):
  *   (a) every edge shared by exactly two triangles (and traversed in opposite
  *   directions), (b) the neighbourhood of every vertex a single loop, (c) no
@@ -485,9 +500,11 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  *   Also connected components, Euler characteristic V - E + F, area, enclosed
  *   volume and vertices per unit area.
  * tms_mesh_write_off: the mesh as an OFF file. */
+#define TMS_MESH_CLOSE 1
 typedef struct tms_mesh tms_mesh;
 typedef struct {
     int64_t n_vertices, n_triangles, n_loops, n_fallback, open_faces;
+    int64_t added_cubes;          /* cubes added across open faces         */
     int64_t boundary_edges;       /* (a): sides in one triangle            */
     int64_t nonmanifold_edges;    /* (a): sides in more than two triangles */
     int64_t misoriented_edges;    /* (a): two triangles, same direction    */
@@ -499,7 +516,7 @@ typedef struct {
 
 int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
                        const double *corner_phi, const tms_vertex *verts, int64_t nv,
-                       tms_mesh **out);
+                       int32_t flags, tms_mesh **out);
 /* The same from host arrays (leaves [n], corner_phi [n][8], verts [nv] in
  * ascending key order), with the isovalue c, the finest level K and the root
  * edge h0 of the cells they came from; errors as above, with the message in
@@ -510,6 +527,8 @@ int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *cor
 int32_t tms_mesh_info(const tms_mesh *m, int64_t *n_vertices, int64_t *n_triangles,
                       int64_t *n_loops, int64_t *n_fallback, int64_t *open_faces);
 int32_t tms_mesh_get(const tms_mesh *m, double *xyz, int32_t *tri, int32_t *tri_leaf);
+int32_t tms_mesh_added(const tms_mesh *m, tms_leaf *leaves, double *corner_phi, int64_t cap,
+                       int64_t *n_out);
 int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report *report);
 int32_t tms_mesh_write_off(const tms_mesh *m, const char *path);
 int32_t tms_mesh_free(tms_mesh *m);

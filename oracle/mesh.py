@@ -9,6 +9,8 @@ from the definitions:
   corners the region g >= c connects, found here by brute force: the face is
   sampled on a fine grid and the connected components of {g >= c} labelled;
 * the loops those segments form on the cube's boundary;
+* closing open faces (the cubes across crossing faces with no SURFACE leaf
+  across, added until none is left);
 * a mesh checker: (a) every edge in exactly two triangles, traversed in
   opposite directions; (b) the triangles around every vertex form a single
   loop; (c) no two triangles without a shared vertex intersect (brute force
@@ -296,3 +298,64 @@ def check_mesh(xyz, tri, intersections=True, cell=None):
             hit |= _seg_tri_vec(P[J, a], P[J, (a + 1) % 3], P[I, 0], P[I, 1], P[I, 2])
         rep["intersecting_pairs"] = int(hit.sum())
     return rep
+
+
+# ---- closing open faces -----------------------------------------------------
+# Reading (the paper is silent here): a crossing face of a SURFACE leaf with
+# no SURFACE leaf across is open, because the bound discarded a coarse cube
+# although phi at finest lattice points inside it crosses c.  The cube of the
+# leaves' level across each such face is added as a SURFACE leaf, again for
+# the added cubes, until no open face is left (or the cube lies outside the
+# root grid).  Corner values of a lattice point that is a corner of a SURFACE
+# leaf are that leaf's; other points are evaluated by `phi_at`.
+
+FACE_CORNERS = [[v for v in range(8) if ((v >> (f >> 1)) & 1) == (f & 1)] for f in range(6)]
+
+
+def open_faces(front, cubes, c):
+    """Open faces of the cubes `front` {ijk: corner values [8]} with respect
+    to the SURFACE cubes `cubes` (same form): a list of (ijk, face, ijk
+    across)."""
+    out = []
+    for q, f in front.items():
+        for fc in range(6):
+            hi = [f[v] >= c for v in FACE_CORNERS[fc]]
+            if all(hi) or not any(hi):
+                continue
+            r = list(q)
+            r[fc >> 1] += 1 if (fc & 1) else -1
+            if tuple(r) not in cubes:
+                out.append((q, fc, tuple(r)))
+    return out
+
+
+def close_open_faces(ijk, corner_phi, surface, c, dims, phi_at, rounds=64):
+    """The cubes added across open faces (sorted list of ijk) and their
+    corner values.  ijk, corner_phi: the leaves of one level; surface: their
+    SURFACE flags; dims: cubes per axis at that level; phi_at(P): phi at
+    lattice points P [m, 3] (integer coordinates at that level)."""
+    cubes = {tuple(int(x) for x in q): np.asarray(f, float)
+             for q, f, s in zip(ijk, corner_phi, surface) if s}
+    known = {}
+    for q, f in cubes.items():
+        for v in range(8):
+            known[(q[0] + (v & 1), q[1] + ((v >> 1) & 1), q[2] + ((v >> 2) & 1))] = f[v]
+    added = {}
+    front = dict(cubes)
+    for _ in range(rounds):
+        new = sorted({r for _, _, r in open_faces(front, cubes, c)
+                      if all(0 <= r[a] < dims[a] for a in range(3))})
+        if not new:
+            break
+        pts = sorted({(r[0] + (v & 1), r[1] + ((v >> 1) & 1), r[2] + ((v >> 2) & 1))
+                      for r in new for v in range(8)} - set(known))
+        if pts:
+            vals = phi_at(np.array(pts, dtype=np.int64))
+            known.update(zip(pts, (float(x) for x in vals)))
+        front = {}
+        for r in new:
+            f = np.array([known[(r[0] + (v & 1), r[1] + ((v >> 1) & 1), r[2] + ((v >> 2) & 1))]
+                          for v in range(8)])
+            cubes[r] = front[r] = added[r] = f
+    keys = sorted(added)
+    return keys, np.array([added[k] for k in keys]).reshape(-1, 8)

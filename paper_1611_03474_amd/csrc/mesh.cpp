@@ -18,8 +18,10 @@
 // A patch is triangulated by ear clipping (Section 2.3) in the plane normal
 // to an axis along which it is single valued: the axis of the loop's largest
 // projected area, else the next, as long as the loop projects to a simple
-// polygon there.  A loop that projects simply along no axis is fanned from
-// its first point and counted.  Triangles are oriented so that their normal
+// polygon there, with no diagonal between two points of one cube face (that
+// side would lie in the face, where the leaf across has its own triangles).
+// A loop that cannot be clipped so along any axis is fanned from a point of
+// its patch inside the cube and counted.  Triangles are oriented so that their normal
 // points along -grad g (outward: phi >= c is inside).
 //
 // The checks: (a) every edge shared by exactly two triangles, traversed in
@@ -47,12 +49,15 @@ struct tms_mesh {
     std::vector<int32_t> tri;       // [nt][3]
     std::vector<int32_t> tri_leaf;  // [nt] index of the leaf in the caller's list
     std::vector<int32_t> leaf_ijk;  // [n][3] of the caller's leaves (for the checks)
+    std::vector<tms_leaf> added;    // cubes added across open faces
+    std::vector<double> added_phi;  // [n_added][8] their corner values
     int level = 0;
     int64_t n_surface = 0, n_loops = 0, n_fallback = 0, open_faces = 0;
 };
 
 namespace {
 
+using tms::DevBuf;
 using tms::Grid;
 
 int32_t mfail(tms_ctx *ctx, int32_t code, const char *msg) {
@@ -267,9 +272,14 @@ bool seg_meet(const double a[2], const double b[2], const double c[2], const dou
 }
 
 // ear clipping of a simple polygon (counter-clockwise or clockwise) of m
-// points; emits index triples with the polygon's winding.  Returns false if
-// the polygon is not simple or has no ear left.
-bool ear_clip(const std::vector<std::array<double, 2>> &Q, std::vector<std::array<int, 3>> &out) {
+// points; emits index triples with the polygon's winding.  fm[i]: the cube
+// faces point i lies on (bit 2 a + s); no diagonal joins two points of one
+// face -- such a side would lie in the face, where the leaf across puts its
+// own triangles (a loop that crosses a face twice, through both branches of
+// its hyperbola, would otherwise be capped in the face from both sides).
+// Returns false if the polygon is not simple or has no ear left.
+bool ear_clip(const std::vector<std::array<double, 2>> &Q, const std::vector<unsigned> &fm,
+              std::vector<std::array<int, 3>> &out) {
     const int m = (int)Q.size();
     // simple: non-adjacent sides do not meet, no repeated point
     for (int i = 0; i < m; ++i)
@@ -291,6 +301,7 @@ bool ear_clip(const std::vector<std::array<double, 2>> &Q, std::vector<std::arra
         bool found = false;
         for (int i = 0; i < k && !found; ++i) {
             const int ia = idx[(i + k - 1) % k], ib = idx[i], ic = idx[(i + 1) % k];
+            if (fm[(size_t)ia] & fm[(size_t)ic]) continue;
             const double cr = cross2(Q[ia].data(), Q[ib].data(), Q[ic].data()) * sg;
             if (!(cr > 0.0)) continue;
             bool inside = false;
@@ -336,7 +347,11 @@ void leaf_triangles(const double f[8], double c, LeafOut &L) {
         ++L.loops;
         const int m = (int)loop.size();
         std::vector<std::array<double, 3>> P(m);
-        for (int i = 0; i < m; ++i) edge_point(f, c, loop[i], P[i].data());
+        std::vector<unsigned> fm(m);
+        for (int i = 0; i < m; ++i) {
+            edge_point(f, c, loop[i], P[i].data());
+            fm[(size_t)i] = (1u << T.edge_face[loop[i]][0]) | (1u << T.edge_face[loop[i]][1]);
+        }
         // vector area of the loop and the outward direction -grad g at its
         // centroid decide the orientation
         double A[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
@@ -356,7 +371,7 @@ void leaf_triangles(const double f[8], double c, LeafOut &L) {
             std::vector<std::array<double, 2>> Q(m);
             for (int i = 0; i < m; ++i) Q[i] = {P[i][b], P[i][cc]};
             tl.clear();
-            ok = ear_clip(Q, tl);
+            ok = ear_clip(Q, fm, tl);
         }
         int inner = -1;
         if (!ok) {
@@ -517,6 +532,204 @@ bool tri_tri(const double *V0, const double *V1, const double *V2, const double 
 }
 
 
+// ---- open faces ---------------------------------------------------------------
+// A face of a SURFACE leaf whose corners lie on both sides of c carries a
+// curve of the surface; with no SURFACE leaf across it the surface is open
+// there.
+
+using CubeIndex = std::unordered_map<uint64_t, int64_t>;
+
+uint64_t cube_key(int64_t x, int64_t y, int64_t z) {
+    return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
+           (uint64_t)(z & 0x1FFFFF);
+}
+
+// the open faces of the leaves `idx` (SURFACE leaves of one level, indexed by
+// `at`); `across`, when given, receives the cube across each
+int64_t open_faces(const std::vector<tms_leaf> &L, const std::vector<int64_t> &idx,
+                   const CubeIndex &at, std::vector<std::array<int32_t, 3>> *across) {
+    const Topo &T = topo();
+    int64_t open = 0;
+    for (int64_t i : idx) {
+        const tms_leaf &lf = L[(size_t)i];
+        for (int fi = 0; fi < 6; ++fi) {
+            bool hi = false, lo = false;
+            for (int k = 0; k < 4; ++k) {
+                if ((lf.mask >> T.F[fi].corner[k]) & 1) hi = true;
+                else lo = true;
+            }
+            if (!(hi && lo)) continue;
+            int32_t q[3] = {lf.ix, lf.iy, lf.iz};
+            q[fi >> 1] += (fi & 1) ? 1 : -1;
+            if (at.count(cube_key(q[0], q[1], q[2]))) continue;
+            ++open;
+            if (across) across->push_back({q[0], q[1], q[2]});
+        }
+    }
+    return open;
+}
+
+// Closing open faces (device entry point).  The partition keeps a cube when
+// the bound of its polynomial reaches c; where the bound is not met on a
+// coarse cube although phi at the finest lattice points inside it crosses c,
+// the surface leaves a kept cube through a face with nothing across.  Each
+// finest cube across such a face is added as a SURFACE leaf, repeatedly (an
+// added cube may itself have open faces), until none is left or `rounds`
+// passes.  Its corner values come from a SURFACE leaf that has the same
+// lattice point as a corner wherever there is one (so both sides of a shared
+// face pair its edge points alike), else from phi of the library
+// (tms_eval_phi, the precision of `cells`); its new edge points are placed as
+// the extraction places them.  Cubes outside the root grid are not added.
+constexpr int kCloseRounds = 64;
+
+std::string close_open_faces(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
+                             std::vector<double> &cp, std::vector<tms_vertex> &V, int rounds,
+                             int32_t *rc) {
+    *rc = TMS_OK;
+    const Grid &g = cells->g;
+    std::vector<int64_t> surf;
+    for (int64_t i = 0; i < (int64_t)L.size(); ++i)
+        if (L[(size_t)i].cls == TMS_CLS_SURFACE) surf.push_back(i);
+    if (surf.empty()) return std::string();
+    const int level = L[(size_t)surf[0]].level;
+    for (int64_t i : surf)
+        if (L[(size_t)i].level != level || level > g.K) return std::string();  // refused later
+    const int sh = g.K - level;
+    const double h = std::ldexp(g.h0, -level);
+    CubeIndex at;
+    at.reserve(surf.size() * 2);
+    for (int64_t i : surf) at.emplace(cube_key(L[(size_t)i].ix, L[(size_t)i].iy, L[(size_t)i].iz), i);
+    const Topo &T = topo();
+    std::vector<int64_t> front = surf;
+    DevBuf dpts, dphi;
+    for (int r = 0; r < rounds && !front.empty(); ++r) {
+        std::vector<std::array<int32_t, 3>> q;
+        open_faces(L, front, at, &q);
+        std::sort(q.begin(), q.end());
+        q.erase(std::unique(q.begin(), q.end()), q.end());
+        q.erase(std::remove_if(q.begin(), q.end(),
+                               [&](const std::array<int32_t, 3> &c) {
+                                   for (int a = 0; a < 3; ++a)
+                                       if (c[a] < 0 || (int64_t)c[a] >= ((int64_t)g.nr[a] << level))
+                                           return true;
+                                   return false;
+                               }),
+                q.end());
+        if (q.empty()) break;
+        // corner values: from a SURFACE leaf at the same lattice point, else phi
+        const size_t nq = q.size();
+        std::vector<double> f(nq * 8, 0.0);
+        std::vector<int64_t> slot(nq * 8, -1);
+        std::unordered_map<uint64_t, int64_t> need;
+        std::vector<double> pts;
+        for (size_t k = 0; k < nq; ++k)
+            for (int v = 0; v < 8; ++v) {
+                const int64_t P[3] = {q[k][0] + (v & 1), q[k][1] + ((v >> 1) & 1),
+                                      q[k][2] + ((v >> 2) & 1)};
+                bool found = false;
+                for (int w = 0; w < 8 && !found; ++w) {
+                    auto it = at.find(cube_key(P[0] - (w & 1), P[1] - ((w >> 1) & 1),
+                                               P[2] - ((w >> 2) & 1)));
+                    if (it == at.end()) continue;
+                    f[k * 8 + v] = cp[(size_t)it->second * 8 + (size_t)w];
+                    found = true;
+                }
+                if (found) continue;
+                const uint64_t pk = cube_key(P[0], P[1], P[2]);
+                auto ins = need.emplace(pk, (int64_t)(pts.size() / 3));
+                if (ins.second)
+                    for (int a = 0; a < 3; ++a)
+                        pts.push_back(g.o[a] + (double)(P[a] << sh) * g.hmin);
+                slot[k * 8 + v] = ins.first->second;
+            }
+        const int64_t m = (int64_t)(pts.size() / 3);
+        if (m > 0) {
+            std::vector<double> phi((size_t)m);
+            int64_t ng = 0;
+            if (dpts.ensure(sizeof(double) * pts.size()) != hipSuccess ||
+                dphi.ensure(sizeof(double) * (size_t)m) != hipSuccess) {
+                (void)hipGetLastError();
+                *rc = TMS_E_OOM;
+                return "device memory for the corner values of cubes added across open faces";
+            }
+            if (hipMemcpyAsync(dpts.p, pts.data(), sizeof(double) * pts.size(),
+                               hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                *rc = TMS_E_DEVICE;
+                return "copying the corners of cubes added across open faces to the device";
+            }
+            const int32_t e = tms_eval_phi(ctx, cells, dpts.as<double>(), m, dphi.as<double>(),
+                                           nullptr, &ng);
+            if (e != TMS_OK) {
+                *rc = e;
+                return ctx->err;
+            }
+            if (hipMemcpyAsync(phi.data(), dphi.p, sizeof(double) * (size_t)m,
+                               hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess) {
+                (void)hipGetLastError();
+                *rc = TMS_E_DEVICE;
+                return "copying the corner values of cubes added across open faces to the host";
+            }
+            for (size_t k = 0; k < nq * 8; ++k)
+                if (slot[k] >= 0) f[k] = phi[(size_t)slot[k]];
+        }
+        // the new leaves and the edge points of their edges not yet listed
+        front.clear();
+        std::vector<tms_vertex> nv;
+        std::unordered_map<uint64_t, int> seen;
+        for (size_t k = 0; k < nq; ++k) {
+            tms_leaf lf{};
+            lf.ix = q[k][0];
+            lf.iy = q[k][1];
+            lf.iz = q[k][2];
+            lf.conf = 0;
+            lf.level = (uint8_t)level;
+            lf.reason = TMS_REASON_CLOSED;
+            unsigned mask = 0;
+            for (int v = 0; v < 8; ++v)
+                if (f[k * 8 + v] >= g.c) mask |= 1u << v;
+            lf.mask = (uint8_t)mask;
+            lf.cls = mask == 0 ? TMS_CLS_OUTSIDE : mask == 0xFF ? TMS_CLS_INSIDE : TMS_CLS_SURFACE;
+            const int64_t i = (int64_t)L.size();
+            L.push_back(lf);
+            cp.insert(cp.end(), f.begin() + (ptrdiff_t)(k * 8), f.begin() + (ptrdiff_t)(k * 8 + 8));
+            if (lf.cls != TMS_CLS_SURFACE) continue;  // cannot happen: a face of it crosses c
+            at.emplace(cube_key(lf.ix, lf.iy, lf.iz), i);
+            front.push_back(i);
+            for (int e = 0; e < 12; ++e) {
+                const EdgeInfo &E = T.E[e];
+                const double f0 = f[k * 8 + E.v0], f1 = f[k * 8 + E.v1];
+                if ((f0 >= g.c) == (f1 >= g.c)) continue;
+                const uint64_t key = edge_key(0, level, g.K, lf.ix, lf.iy, lf.iz, e);
+                auto it = std::lower_bound(V.begin(), V.end(), key,
+                                           [](const tms_vertex &a, uint64_t kk) { return a.edge_key < kk; });
+                if ((it != V.end() && it->edge_key == key) || !seen.emplace(key, 1).second) continue;
+                tms_vertex x;
+                x.edge_key = key;
+                x.t = (g.c - f0) / (f1 - f0);
+                const int64_t I[3] = {lf.ix + E.off[0], lf.iy + E.off[1], lf.iz + E.off[2]};
+                double p[3];
+                for (int a = 0; a < 3; ++a) p[a] = g.o[a] + (double)(I[a] << sh) * g.hmin;
+                p[E.axis] += x.t * h;
+                x.x = p[0];
+                x.y = p[1];
+                x.z = p[2];
+                nv.push_back(x);
+            }
+        }
+        if (!nv.empty()) {
+            std::sort(nv.begin(), nv.end(),
+                      [](const tms_vertex &a, const tms_vertex &b) { return a.edge_key < b.edge_key; });
+            const size_t mid = V.size();
+            V.insert(V.end(), nv.begin(), nv.end());
+            std::inplace_merge(V.begin(), V.begin() + (ptrdiff_t)mid, V.end(),
+                               [](const tms_vertex &a, const tms_vertex &b) { return a.edge_key < b.edge_key; });
+        }
+    }
+    return std::string();
+}
+
 // the mesh of host copies of the leaves, corner values and vertices; returns
 // a message (empty: success) and the mesh
 std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
@@ -652,36 +865,10 @@ std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double>
         delete M;
         return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
     }
-    // faces of SURFACE leaves that cross c with no SURFACE leaf of the level
-    // across: the mesh is open there (the bound discarded that cube)
     {
-        std::unordered_map<uint64_t, int64_t> at;
-        at.reserve((size_t)ns * 2);
-        auto ck = [](int64_t x, int64_t y, int64_t z) {
-            return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
-                   (uint64_t)(z & 0x1FFFFF);
-        };
-        for (int64_t i : surf) {
-            const tms_leaf &lf = L[(size_t)i];
-            at[ck(lf.ix, lf.iy, lf.iz)] = i;
-        }
-        const Topo &T = topo();
-        int64_t open = 0;
-        for (int64_t i : surf) {
-            const tms_leaf &lf = L[(size_t)i];
-            for (int fi = 0; fi < 6; ++fi) {
-                bool hi = false, lo = false;
-                for (int k = 0; k < 4; ++k) {
-                    if ((lf.mask >> T.F[fi].corner[k]) & 1) hi = true;
-                    else lo = true;
-                }
-                if (!(hi && lo)) continue;
-                int64_t q[3] = {lf.ix, lf.iy, lf.iz};
-                q[fi >> 1] += (fi & 1) ? 1 : -1;
-                if (!at.count(ck(q[0], q[1], q[2]))) ++open;
-            }
-        }
-        M->open_faces = open;
+        CubeIndex at;
+        for (int64_t i : surf) at.emplace(cube_key(L[(size_t)i].ix, L[(size_t)i].iy, L[(size_t)i].iz), i);
+        M->open_faces = open_faces(L, surf, at, nullptr);
     }
     *out = M;
     return std::string();
@@ -700,10 +887,10 @@ extern "C" {
 
 int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,
                        const double *corner_phi, const tms_vertex *verts, int64_t nv,
-                       tms_mesh **out) {
+                       int32_t flags, tms_mesh **out) {
     if (!ctx) return TMS_E_INVALID;
     if (!out || !cells || n < 0 || nv < 0 || (n > 0 && (!leaves || !corner_phi)) ||
-        (nv > 0 && !verts))
+        (nv > 0 && !verts) || (flags & ~TMS_MESH_CLOSE))
         return mfail(ctx, TMS_E_INVALID, "invalid arguments to tms_mesh_build");
     *out = nullptr;
     if (std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
@@ -725,8 +912,15 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
         (void)hipGetLastError();
         return mfail(ctx, TMS_E_DEVICE, "copying leaves, corner values or vertices to the host");
     }
+    if (flags & TMS_MESH_CLOSE) {
+        int32_t rc = TMS_OK;
+        const std::string why = close_open_faces(ctx, cells, L, cp, V, kCloseRounds, &rc);
+        if (rc != TMS_OK) return mfail(ctx, rc, why.c_str());
+    }
     const std::string why = build_mesh(L, cp, V, g.c, g.K, g.h0, out);
     if (!why.empty()) return mfail(ctx, TMS_E_INVALID, why.c_str());
+    (*out)->added.assign(L.begin() + n, L.end());
+    (*out)->added_phi.assign(cp.begin() + 8 * n, cp.end());
     return TMS_OK;
 }
 
@@ -769,6 +963,18 @@ int32_t tms_mesh_get(const tms_mesh *m, double *xyz, int32_t *tri, int32_t *tri_
     return TMS_OK;
 }
 
+int32_t tms_mesh_added(const tms_mesh *m, tms_leaf *leaves, double *corner_phi, int64_t cap,
+                       int64_t *n_out) {
+    if (!m || cap < 0) return TMS_E_INVALID;
+    const int64_t k = (int64_t)m->added.size();
+    if (n_out) *n_out = k;
+    if (!leaves && !corner_phi) return TMS_OK;
+    if (cap < k) return TMS_E_CAPACITY;
+    if (leaves) std::copy(m->added.begin(), m->added.end(), leaves);
+    if (corner_phi) std::copy(m->added_phi.begin(), m->added_phi.end(), corner_phi);
+    return TMS_OK;
+}
+
 int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report *r) {
     if (!m || !r) return TMS_E_INVALID;
     std::memset(r, 0, sizeof *r);
@@ -780,6 +986,7 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
     r->n_loops = m->n_loops;
     r->n_fallback = m->n_fallback;
     r->open_faces = m->open_faces;
+    r->added_cubes = (int64_t)m->added.size();
     // (a) edges: (min, max, direction) of every triangle side, sorted
     struct HE {
         int32_t a, b;

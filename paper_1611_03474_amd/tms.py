@@ -20,7 +20,8 @@ TMS_OK, TMS_E_INVALID, TMS_E_CAPACITY, TMS_E_DEVICE, TMS_E_OOM = 0, -1, -2, -3, 
 PREC_FP64, PREC_FP32_GUARD = 0, 1
 MODE_ADAPTIVE, MODE_UNIFORM = 0, 1
 CHILD_PROJECT, CHILD_REEXPAND = 0, 1
-REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN = 0, 1, 2
+REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN, REASON_CLOSED = 0, 1, 2, 3
+MESH_CLOSE = 1
 CLS_OUTSIDE, CLS_SURFACE, CLS_INSIDE = 0, 1, 2
 MAX_LEVELS = 8
 
@@ -45,7 +46,8 @@ class Timing(C.Structure):
 
 class MeshReport(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
-        "n_vertices", "n_triangles", "n_loops", "n_fallback", "open_faces", "boundary_edges",
+        "n_vertices", "n_triangles", "n_loops", "n_fallback", "open_faces", "added_cubes",
+        "boundary_edges",
         "nonmanifold_edges", "misoriented_edges", "nonmanifold_vertices", "intersecting_pairs",
         "components", "euler", "unused_vertices")] + [
         ("area", C.c_double), ("volume", C.c_double), ("density", C.c_double)]
@@ -56,7 +58,8 @@ class MeshReport(C.Structure):
 
 class Mesh:
     """A host mesh of tms_mesh_build (Section 2.3): .xyz [nv, 3], .tri [nt, 3],
-    .tri_leaf [nt] (numpy), counts in .info."""
+    .tri_leaf [nt] (numpy), counts in .info; .added (LEAF_DTYPE) and
+    .added_phi [k, 8]: the cubes added across open faces."""
 
     def __init__(self, lib, handle):
         self.lib, self.h = lib, handle
@@ -71,6 +74,15 @@ class Mesh:
         self.tri_leaf = np.zeros(nt, dtype=np.int32)
         lib.tms_mesh_get(handle, self.xyz.ctypes.data_as(_VP), self.tri.ctypes.data_as(_VP),
                          self.tri_leaf.ctypes.data_as(_VP))
+        k = i64()
+        lib.tms_mesh_added(handle, None, None, 0, C.byref(k))
+        self.added = np.zeros(k.value, dtype=LEAF_DTYPE)
+        self.added_phi = np.zeros((k.value, 8))
+        rc = lib.tms_mesh_added(handle, self.added.ctypes.data_as(_VP),
+                                self.added_phi.ctypes.data_as(_VP), k.value, C.byref(k))
+        if rc != TMS_OK:
+            raise TmsError(rc, "tms_mesh_added")
+        self.info["added_cubes"] = len(self.added)
 
     def check(self, intersections: bool = True) -> dict:
         r = MeshReport()
@@ -211,15 +223,17 @@ def load_library(path: str = LIB_PATH):
     L.tms_debug_bound.argtypes = [_VP, _VP, _VP, i64, _VP]
     L.tms_debug_fast_exp.argtypes = [_VP, _VP, i64, _VP]
     L.tms_debug_phi_pairs.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
-    L.tms_mesh_build.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, C.POINTER(_VP)]
+    L.tms_mesh_build.argtypes = [_VP, _VP, _VP, i64, _VP, _VP, i64, i32, C.POINTER(_VP)]
     L.tms_mesh_build_host.argtypes = [_VP, i64, _VP, _VP, i64, C.c_double, i32, C.c_double,
                                       C.POINTER(_VP), C.c_char_p, i64]
     L.tms_mesh_info.argtypes = [_VP] + [C.POINTER(i64)] * 5
     L.tms_mesh_get.argtypes = [_VP, _VP, _VP, _VP]
+    L.tms_mesh_added.argtypes = [_VP, _VP, _VP, i64, C.POINTER(i64)]
     L.tms_mesh_check.argtypes = [_VP, i32, C.POINTER(MeshReport)]
     L.tms_mesh_write_off.argtypes = [_VP, C.c_char_p]
     L.tms_mesh_free.argtypes = [_VP]
-    for f in ("tms_mesh_build", "tms_mesh_build_host", "tms_mesh_info", "tms_mesh_get", "tms_mesh_check",
+    for f in ("tms_mesh_build", "tms_mesh_build_host", "tms_mesh_info", "tms_mesh_get",
+              "tms_mesh_added", "tms_mesh_check",
               "tms_mesh_write_off", "tms_mesh_free"):
         getattr(L, f).restype = i32
     for f in ("tms_create", "tms_destroy", "tms_check_params", "tms_check_atoms_host",
@@ -391,12 +405,14 @@ class Context:
         return int(ng.value)
 
     # ------------------------------------------------------------ partition
-    def mesh_build(self, cells: Cells, leaves, cphi, verts) -> "Mesh":
-        """tms_mesh_build on device tensors from partition_estimate / extract."""
+    def mesh_build(self, cells: Cells, leaves, cphi, verts, close: bool = True) -> "Mesh":
+        """tms_mesh_build on device tensors from partition_estimate / extract;
+        close: add the cubes across open faces (TMS_MESH_CLOSE)."""
         h = _VP()
         self._check(self.lib.tms_mesh_build(self.h, cells.handle, _VP(_ptr(leaves)),
                                             leaves.shape[0], _VP(_ptr(cphi)), _VP(_ptr(verts)),
-                                            verts.shape[0], C.byref(h)))
+                                            verts.shape[0], MESH_CLOSE if close else 0,
+                                            C.byref(h)))
         return Mesh(self.lib, h)
 
     def partition_estimate(self, cells: Cells, cap: int | None = None):

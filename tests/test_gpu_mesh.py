@@ -1,0 +1,141 @@
+"""The Stage-2 mesh (Section 2.3) of the HIP path's partitions, with and
+without closing open faces, against the oracle.
+
+* Unclosed: tms_mesh_build on the device partition gives the same triangles
+  (vertex indices, leaf of each triangle) as tms_mesh_build_host on the
+  oracle's partition of the same atoms (FP64: identical leaf lists and
+  vertex keys), and positions within 2e-12.
+* Closed: the cubes the library adds across open faces are exactly the
+  oracle's (oracle/mesh.close_open_faces over the oracle's partition, phi of
+  the oracle at the new corners), their corner values within the parity bar;
+  the closed mesh has no open face, and the library's check report equals
+  the oracle checker's on it with no defect of (a), (b) or (c).
+* A sphere whose unclosed mesh has holes closes into a sphere (Euler
+  characteristic 2, area within 1 % of the closed form); the 5,000-atom
+  globule in FP32+guard closes into a manifold with no defect.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mesh as om
+from paper_1611_03474_amd import synth, tms, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = tms.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_meshes(ctx, atoms, prec, **kw):
+    p = tms.make_params(precision=prec, **kw)
+    cells = ctx.build_cells(atoms, p)
+    try:
+        leaves, cphi, _ = ctx.partition_estimate(cells)
+        verts = ctx.extract(cells, leaves, cphi)
+        open_m = ctx.mesh_build(cells, leaves, cphi, verts, close=False)
+        closed = ctx.mesh_build(cells, leaves, cphi, verts, close=True)
+        L = tms.leaves_to_numpy(leaves)
+    finally:
+        ctx.free_cells(cells)
+    return L, open_m, closed
+
+
+def _oracle_host_mesh(r, c, h0):
+    L = np.zeros(r.n_leaves, dtype=tms.LEAF_DTYPE)
+    L["ix"], L["iy"], L["iz"] = r.ijk[:, 0], r.ijk[:, 1], r.ijk[:, 2]
+    L["level"], L["reason"], L["mask"], L["cls"] = r.level, r.reason, r.mask, r.cls
+    V = np.zeros(r.n_vert, dtype=tms.VERTEX_DTYPE)
+    V["edge_key"], V["t"] = r.vkey, r.vt
+    V["x"], V["y"], V["z"] = r.vxyz[:, 0], r.vxyz[:, 1], r.vxyz[:, 2]
+    return tms.mesh_build_host(L, r.corner_phi, V, c, r.K, h0)
+
+
+def _oracle_closure(r, atoms, D, c, h0):
+    surf = r.cls == oracle.CLS_SURFACE
+    lev = int(r.level[surf][0]) if surf.any() else r.K
+    h = h0 / (1 << lev)
+    dims = tuple(int(d) << lev for d in r.dims)
+
+    def phi_at(P):
+        return oracle.phi(atoms, D, r.origin + P * h)
+
+    same = r.level == lev
+    return om.close_open_faces(r.ijk[same], r.corner_phi[same], surf[same], c, dims, phi_at)
+
+
+# atoms and seeds whose oracle partition has no near tie; the first two and
+# the 200-atom globule of seed 1002 have open faces before closing
+CASES = {
+    "sphere_with_holes": (np.array([[-2.8735, -1.1366, 2.6300, 1.6307]]), 0.9),
+    "sphere_with_holes2": (np.array([[2.8824, 0.0931, 0.1270, 1.9172]]), 0.9),
+    "globule200_open": (synth.globule(200, 1002), 0.9),
+    "globule200": (synth.globule(200, 1001), 0.9),
+    "globule1000": (synth.globule(1000, 1006), 0.9),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mesh_parity_fp64(ctx, name):
+    atoms, D = CASES[name]
+    c, h0 = 1.0, 2.0
+    print("case", name, flush=True)
+    L, mo, mc = _gpu_meshes(ctx, atoms, tms.PREC_FP64, D=D)
+    r = oracle.partition(atoms, D, c=c, tau=1e-3, h0=h0, h_min=0.25)
+    assert r.tie_cube == 0 and r.tie_corner == 0, "near ties: pick another seed"
+    ref = _oracle_host_mesh(r, c, h0)
+    # unclosed: same triangles as the host mesher on the oracle's partition
+    assert np.array_equal(mo.tri, ref.tri) and np.array_equal(mo.tri_leaf, ref.tri_leaf)
+    assert np.max(np.abs(mo.xyz - ref.xyz), initial=0.0) < 2e-12
+    assert mo.info["open_faces"] == ref.info["open_faces"] and len(mo.added) == 0
+    # closed: the oracle's closure of its own partition
+    keys, aphi = _oracle_closure(r, atoms, D, c, h0)
+    got = sorted(zip(mc.added["ix"].tolist(), mc.added["iy"].tolist(), mc.added["iz"].tolist()))
+    print("open faces %d, added cubes: library %d, oracle %d"
+          % (mo.info["open_faces"], len(got), len(keys)))
+    assert got == keys
+    order = np.lexsort((mc.added["iz"], mc.added["iy"], mc.added["ix"]))
+    if len(keys):
+        assert np.max(np.abs(mc.added_phi[order] - aphi) / np.abs(aphi)) < 1e-12
+        assert np.all(mc.added["reason"] == tms.REASON_CLOSED)
+        assert np.all(mc.added["cls"] == tms.CLS_SURFACE)
+    if name in ("sphere_with_holes", "sphere_with_holes2", "globule200_open"):
+        assert mo.info["open_faces"] > 0 and len(keys) > 0
+    assert mc.info["open_faces"] == 0
+    assert np.all(mc.tri_leaf < len(L) + len(mc.added))
+    rep = mc.check()
+    oref = om.check_mesh(mc.xyz, mc.tri, cell=0.5)
+    print(rep)
+    for k in ("boundary_edges", "nonmanifold_edges", "misoriented_edges", "nonmanifold_vertices",
+              "intersecting_pairs", "components", "euler"):
+        assert rep[k] == oref[k], k
+    assert rep["boundary_edges"] == rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    assert rep["misoriented_edges"] == rep["nonmanifold_edges"] == 0
+    assert rep["euler"] % 2 == 0 and rep["volume"] > 0
+    if name.startswith("sphere"):
+        R = atoms[0, 3]  # c = 1: phi = 1 on the sphere of radius r_i
+        assert rep["euler"] == 2 and rep["components"] == 1
+        assert abs(rep["area"] / (4 * np.pi * R * R) - 1) < 0.01
+
+
+def test_closed_mesh_globule5k_fp32g(ctx):
+    w = workloads.GLOBULE5K[0.9]
+    atoms = workloads.atoms(w)
+    print("case globule5k fp32g", flush=True)
+    L, mo, mc = _gpu_meshes(ctx, atoms, tms.PREC_FP32_GUARD, D=w.D, tau=1e-3)
+    rep = mc.check()
+    print(mo.info, rep)
+    assert mc.info["open_faces"] == 0
+    assert rep["boundary_edges"] == rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    assert rep["misoriented_edges"] == rep["nonmanifold_edges"] == 0
+    assert rep["unused_vertices"] == 0 and rep["euler"] % 2 == 0 and rep["volume"] > 0
+    # the added cubes straddle c and touch the surface through a crossing face
+    a = mc.added
+    assert np.all(a["cls"] == tms.CLS_SURFACE)
+    assert np.all((mc.added_phi >= 1.0).any(1) & (mc.added_phi < 1.0).any(1))

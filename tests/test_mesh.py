@@ -12,6 +12,10 @@ partitions.  CPU only: the host entry point takes host arrays.
   (Euler characteristic 2, area and volume within 1 %); two distant atoms two
   spheres; a ring of atoms a torus (Euler characteristic 0); a 200-atom
   globule a closed manifold with no defect.
+* A loop through both branches of a shared face's hyperbola: no triangle
+  lies in the face (no side in more than two triangles).
+* The oracle's closure of its own partition, meshed here: no open face, no
+  defect.
 * Open faces (a crossing face of a SURFACE leaf with no SURFACE leaf across)
   are counted, and the holes' rims are the only defects.
 * An OFF file reads back; SURFACE leaves of two levels are refused.
@@ -157,3 +161,68 @@ def test_mixed_levels_refused():
     with pytest.raises(tms.TmsError) as ei:
         tms.mesh_build_host(L, r.corner_phi, _verts(r), 1.0, r.K, 2.0)
     assert ei.value.code == tms.TMS_E_INVALID and "levels" in str(ei.value)
+
+
+@pytest.mark.parametrize("atoms", [np.array([[-2.8735, -1.1366, 2.6300, 1.6307]]),
+                                   synth.globule(200, 1002)], ids=["sphere", "globule200"])
+def test_oracle_closure_closes_host_mesh(atoms):
+    # the oracle's closure of its own partition (cubes across open faces, phi
+    # of the oracle at new corners), extracted by the oracle and meshed by
+    # the host mesher: no open face and no defect left
+    D, c, h0 = 0.9, 1.0, 2.0
+    r = oracle.partition(atoms, D, c=c, tau=1e-3, h0=h0, h_min=0.25)
+    m0 = tms.mesh_build_host(_leaves(r), r.corner_phi, _verts(r), c, r.K, h0)
+    surf = r.cls == oracle.CLS_SURFACE
+    lev = int(r.level[surf][0])
+    h = h0 / (1 << lev)
+    same = r.level == lev
+    keys, aphi = om.close_open_faces(r.ijk[same], r.corner_phi[same], surf[same], c,
+                                     tuple(int(d) << lev for d in r.dims),
+                                     lambda P: oracle.phi(atoms, D, r.origin + P * h))
+    assert m0.info["open_faces"] > 0 and len(keys) > 0
+    e = oracle.extract(np.vstack([r.ijk, np.array(keys)]),
+                       np.concatenate([r.level, np.full(len(keys), lev, np.uint8)]),
+                       np.vstack([r.corner_phi, aphi]), c, r.origin, h0, r.K)
+    e.reason = np.zeros(e.n_leaves, np.uint8)
+    m = tms.mesh_build_host(_leaves(e), e.corner_phi, _verts(e), c, e.K, h0)
+    rep = m.check()
+    print(m0.info["open_faces"], len(keys), rep)
+    assert m.info["open_faces"] == 0
+    assert rep["boundary_edges"] == rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    assert rep["misoriented_edges"] == rep["nonmanifold_edges"] == 0
+    assert rep["euler"] % 2 == 0
+    if len(atoms) == 1:
+        R = atoms[0, 3]
+        assert rep["euler"] == 2 and abs(rep["area"] / (4 * np.pi * R * R) - 1) < 0.01
+
+
+def test_loop_crossing_a_face_twice():
+    # two leaves stacked along z share a face whose corners alternate about
+    # c with the saddle value below c: on each side one loop runs through both
+    # branches of the face's hyperbola.  A diagonal between two points of that
+    # face would lie in it, and the leaf across would put its own triangles
+    # there too (sides in four triangles); none may.
+    top = np.array([1.01, 0.99, 0.96, 1.01])  # face corners v = dx + 2 dy
+    sad = (top[0] * top[3] - top[1] * top[2]) / (top[0] + top[3] - top[1] - top[2])
+    assert sad < 1.0
+    cpA = np.concatenate([np.full(4, 1.2), top])
+    cpB = np.concatenate([top, np.full(4, 1.2)])
+    origin, h0, K = np.zeros(3), 2.0, 0
+    e = oracle.extract(np.array([[3, 4, 5], [3, 4, 6]]), np.zeros(2, np.uint8),
+                       np.vstack([cpA, cpB]), 1.0, origin, h0, K)
+    e.reason = np.zeros(2, np.uint8)
+    m = tms.mesh_build_host(_leaves(e), e.corner_phi, _verts(e), 1.0, K, h0)
+    rep = m.check()
+    ref = om.check_mesh(m.xyz, m.tri)
+    assert m.info["n_loops"] == 2
+    assert rep["nonmanifold_edges"] == ref["nonmanifold_edges"] == 0
+    assert rep["misoriented_edges"] == ref["misoriented_edges"] == 0
+    assert rep["intersecting_pairs"] == ref["intersecting_pairs"] == 0
+    # no triangle side between two points of the shared face z = 12 except
+    # the face's two curve segments
+    zf = 6 * h0
+    on = np.abs(m.xyz[:, 2] - zf) < 1e-12
+    sides = {tuple(sorted((int(t[a]), int(t[(a + 1) % 3])))) for t in m.tri for a in range(3)
+             if on[t[a]] and on[t[(a + 1) % 3]]}
+    assert len(sides) == 2
+    assert not any(on[t].all() for t in m.tri)

@@ -12,6 +12,9 @@ closed forms and hand-built meshes.  CPU only.
   volumes), a tetrahedron with a face missing (three boundary edges), a
   flipped face (misoriented edges), two tetrahedra sharing one vertex (one
   vertex whose neighbourhood is two loops), two crossing triangles.
+* Closing open faces: on a sampled field whose crossing cubes form one
+  face-connected set, dropping most of them and closing gives back exactly
+  the dropped cubes with their values.
 """
 import numpy as np
 import pytest
@@ -129,3 +132,38 @@ def test_crossing_triangles():
     Z = X.copy()
     Z[3:, 2] += 5.0
     assert om.check_mesh(Z, np.array([[0, 1, 2], [3, 4, 5]]))["intersecting_pairs"] == 0
+
+
+def test_closure_restores_dropped_surface_cubes():
+    # phi of two overlapping spheres sampled on a lattice: the cubes whose
+    # corners straddle c are face-connected through crossing faces (one
+    # connected surface, no corner value equal to c), so dropping any of them
+    # but one and closing the open faces must give back exactly the full set
+    # -- and nothing outside it, since only crossing faces are followed
+    n, h, c = 24, 0.35, 1.0
+    X = np.stack(np.meshgrid(*[np.arange(n + 1) * h - 4.0] * 3, indexing="ij"), -1)
+    f = np.exp(-((X - [0.3, 0.1, -0.2]) ** 2).sum(-1) + 4.0) + \
+        np.exp(-((X - [1.6, 0.4, 0.3]) ** 2).sum(-1) + 3.0)
+    cubes, vals = [], []
+    for q in np.ndindex(n, n, n):
+        v = np.array([f[q[0] + (k & 1), q[1] + ((k >> 1) & 1), q[2] + ((k >> 2) & 1)]
+                      for k in range(8)])
+        if (v >= c).any() and (v < c).any():
+            cubes.append(q)
+            vals.append(v)
+    assert len(cubes) > 300
+    rng = np.random.default_rng(3)
+    keep = rng.random(len(cubes)) < 0.3
+    keep[0] = True
+    ijk = np.array(cubes)[keep]
+    cp = np.array(vals)[keep]
+    added, aphi = om.close_open_faces(ijk, cp, np.ones(len(ijk), bool), c, (n, n, n),
+                                      lambda P: f[P[:, 0], P[:, 1], P[:, 2]])
+    want = sorted(tuple(q) for q, k in zip(cubes, keep) if not k)
+    assert added == want
+    for q, v in zip(added, aphi):
+        assert np.array_equal(v, vals[cubes.index(q)])
+    # nothing to add on the full set
+    added, _ = om.close_open_faces(np.array(cubes), np.array(vals), np.ones(len(cubes), bool),
+                                   c, (n, n, n), lambda P: f[P[:, 0], P[:, 1], P[:, 2]])
+    assert added == []
