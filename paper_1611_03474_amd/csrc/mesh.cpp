@@ -40,6 +40,7 @@
 #include <numeric>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "tms_internal.h"
@@ -532,87 +533,320 @@ bool tri_tri(const double *V0, const double *V1, const double *V2, const double 
 }
 
 
-// ---- open faces ---------------------------------------------------------------
-// A face of a SURFACE leaf whose corners lie on both sides of c carries a
-// curve of the surface; with no SURFACE leaf across it the surface is open
-// there.
+// ---- building the mesh ------------------------------------------------------
+// Vertex ids: the caller's edge points in key order (0 .. nv-1), then points
+// appended later (interior points of fanned patches, edge points of added
+// cubes).  Every SURFACE leaf ORs its position around each of its crossing
+// edges into that edge point's ring bits: around an edge, the cube at offsets
+// (u, v) along the edge's two other axes (ascending) is bit u + 2 v (the
+// edge's index & 3 within that cube).  A crossing edge crosses every face
+// that contains it, so a present cube whose ring neighbour across such a face
+// is absent has an open face there; with no open face every ring is full.
 
-using CubeIndex = std::unordered_map<uint64_t, int64_t>;
+using VidFn = std::function<int64_t(uint64_t)>;
+using KeyFn = std::function<uint64_t(int64_t)>;
 
 uint64_t cube_key(int64_t x, int64_t y, int64_t z) {
     return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
            (uint64_t)(z & 0x1FFFFF);
 }
 
-// the open faces of the leaves `idx` (SURFACE leaves of one level, indexed by
-// `at`); `across`, when given, receives the cube across each
-int64_t open_faces(const std::vector<tms_leaf> &L, const std::vector<int64_t> &idx,
-                   const CubeIndex &at, std::vector<std::array<int32_t, 3>> *across) {
+// Triangulates the leaves idx into M (triangles, interior points appended in
+// the order of idx) and ORs their ring bits into em (one byte per vertex id).
+// Returns false if an edge point of a leaf is missing (vid < 0).
+bool triangulate(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+                 const std::vector<int64_t> &idx, double c, int K, double h0, const VidFn &vid,
+                 tms_mesh *M, std::vector<uint8_t> &em) {
     const Topo &T = topo();
-    int64_t open = 0;
-    for (int64_t i : idx) {
-        const tms_leaf &lf = L[(size_t)i];
-        for (int fi = 0; fi < 6; ++fi) {
-            bool hi = false, lo = false;
-            for (int k = 0; k < 4; ++k) {
-                if ((lf.mask >> T.F[fi].corner[k]) & 1) hi = true;
-                else lo = true;
+    const int64_t ns = (int64_t)idx.size();
+    const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+    std::vector<std::vector<int32_t>> ptri(nth), pleaf(nth);
+    std::vector<std::vector<double>> pxyz(nth);  // interior points of fanned loops
+    std::vector<int64_t> loops(nth, 0), fb(nth, 0), missing(nth, 0);
+    std::vector<int64_t> first(nth, -1);  // chunk starts, merged in order afterwards
+    parallel_for(ns, [&](int64_t b, int64_t e, int t) {
+        first[(size_t)t] = b;
+        LeafOut out;
+        for (int64_t s = b; s < e; ++s) {
+            const int64_t i = idx[(size_t)s];
+            const tms_leaf &lf = L[(size_t)i];
+            const double *f = &cp[(size_t)i * 8];
+            // the leaf's crossing edges: vertex ids and ring bits
+            int64_t id[12];
+            bool ok = true;
+            for (int ed = 0; ed < 12; ++ed) {
+                id[ed] = -1;
+                if ((f[T.E[ed].v0] >= c) == (f[T.E[ed].v1] >= c)) continue;
+                id[ed] = vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, ed));
+                if (id[ed] < 0) ok = false;
             }
-            if (!(hi && lo)) continue;
-            int32_t q[3] = {lf.ix, lf.iy, lf.iz};
-            q[fi >> 1] += (fi & 1) ? 1 : -1;
-            if (at.count(cube_key(q[0], q[1], q[2]))) continue;
-            ++open;
-            if (across) across->push_back({q[0], q[1], q[2]});
+            if (!ok) {
+                ++missing[(size_t)t];
+                continue;
+            }
+            for (int ed = 0; ed < 12; ++ed)
+                if (id[ed] >= 0)
+                    __atomic_fetch_or(&em[(size_t)id[ed]], (uint8_t)(1u << (ed & 3)),
+                                      __ATOMIC_RELAXED);
+            out.tri.clear();
+            out.inner.clear();
+            out.loops = out.fallback = 0;
+            leaf_triangles(f, c, out);
+            loops[(size_t)t] += out.loops;
+            fb[(size_t)t] += out.fallback;
+            // interior points: placed from an edge point of the leaf (its
+            // global position minus its local one) -- numbered -1 - k in the
+            // thread, renumbered after the merge
+            std::vector<int32_t> inner_id(out.inner.size(), 0);
+            if (!out.inner.empty()) {
+                int e0 = -1;
+                for (const auto &tr : out.tri)
+                    for (int k = 0; k < 3 && e0 < 0; ++k)
+                        if (tr[k] < 12) e0 = tr[k];
+                if (e0 < 0) {
+                    ++missing[(size_t)t];
+                    continue;
+                }
+                double P0[3];
+                edge_point(f, c, e0, P0);
+                const double h = std::ldexp(h0, -(int)lf.level);
+                for (size_t k = 0; k < out.inner.size(); ++k) {
+                    inner_id[k] = -1 - (int32_t)(pxyz[(size_t)t].size() / 3);
+                    for (int a = 0; a < 3; ++a)
+                        pxyz[(size_t)t].push_back(M->xyz[3 * (size_t)id[e0] + a] +
+                                                  (out.inner[k][a] - P0[a]) * h);
+                }
+            }
+            for (const auto &tr : out.tri) {
+                int32_t v[3];
+                for (int k = 0; k < 3; ++k)
+                    v[k] = tr[k] >= 12 ? inner_id[(size_t)(tr[k] - 12)] : (int32_t)id[tr[k]];
+                ptri[(size_t)t].insert(ptri[(size_t)t].end(), v, v + 3);
+                pleaf[(size_t)t].push_back((int32_t)i);
+            }
         }
+    });
+    std::vector<int> order;
+    for (unsigned t = 0; t < nth; ++t)
+        if (first[t] >= 0) order.push_back((int)t);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return first[a] < first[b]; });
+    int64_t miss = 0;
+    for (int t : order) {
+        // interior points of this thread's leaves follow the points so far
+        const int32_t base = (int32_t)(M->xyz.size() / 3);
+        for (int32_t &v : ptri[(size_t)t])
+            if (v < 0) v = base + (-1 - v);
+        M->xyz.insert(M->xyz.end(), pxyz[(size_t)t].begin(), pxyz[(size_t)t].end());
+        M->tri.insert(M->tri.end(), ptri[(size_t)t].begin(), ptri[(size_t)t].end());
+        M->tri_leaf.insert(M->tri_leaf.end(), pleaf[(size_t)t].begin(), pleaf[(size_t)t].end());
+        M->n_loops += loops[(size_t)t];
+        M->n_fallback += fb[(size_t)t];
+        miss += missing[(size_t)t];
     }
-    return open;
+    em.resize(M->xyz.size() / 3, 0);
+    return miss == 0;
+}
+
+// Open faces seen from the rings of the vertex ids `ids` (all ids when
+// null): the number of distinct (cube, face) pairs, and the cubes across
+// them (sorted, distinct) when `across` is given.
+int64_t open_faces(const std::vector<uint8_t> &em, const std::vector<int64_t> *ids, int64_t nall,
+                   const KeyFn &key_of, int K, std::vector<std::array<int32_t, 3>> *across) {
+    const int64_t n = ids ? (int64_t)ids->size() : nall;
+    const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+    std::vector<std::vector<std::array<int32_t, 4>>> part(nth);  // cube, face
+    parallel_for(n, [&](int64_t b, int64_t e, int t) {
+        for (int64_t s = b; s < e; ++s) {
+            const int64_t v = ids ? (*ids)[(size_t)s] : s;
+            const unsigned m = em[(size_t)v];
+            if (m == 0 || m == 0xF) continue;
+            const uint64_t key = key_of(v);
+            const int level = (int)((key >> 50) & 7), axis = (int)((key >> 48) & 3),
+                      sh = K - level;
+            const int32_t E[3] = {(int32_t)(((key >> 32) & 0xFFFF) >> sh),
+                                  (int32_t)(((key >> 16) & 0xFFFF) >> sh),
+                                  (int32_t)((key & 0xFFFF) >> sh)};
+            const int o1 = (axis + 1) % 3, o2 = (axis + 2) % 3;
+            const int lo = std::min(o1, o2), hi = std::max(o1, o2);
+            for (int p = 0; p < 4; ++p) {
+                if (!((m >> p) & 1)) continue;
+                const int u = p & 1, w = p >> 1;
+                std::array<int32_t, 4> q = {E[0], E[1], E[2], 0};
+                q[lo] -= u;
+                q[hi] -= w;
+                if (!((m >> (p ^ 1)) & 1)) {  // across the face normal to lo
+                    q[3] = 2 * lo + u;
+                    part[(size_t)t].push_back(q);
+                }
+                if (!((m >> (p ^ 2)) & 1)) {  // across the face normal to hi
+                    q[3] = 2 * hi + w;
+                    part[(size_t)t].push_back(q);
+                }
+            }
+        }
+    });
+    std::vector<std::array<int32_t, 4>> all;
+    for (auto &p : part) all.insert(all.end(), p.begin(), p.end());
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    if (across) {
+        across->clear();
+        for (const auto &q : all) {
+            std::array<int32_t, 3> r = {q[0], q[1], q[2]};
+            r[q[3] >> 1] += (q[3] & 1) ? 1 : -1;
+            across->push_back(r);
+        }
+        std::sort(across->begin(), across->end());
+        across->erase(std::unique(across->begin(), across->end()), across->end());
+    }
+    return (int64_t)all.size();
+}
+
+// the edge point of key `key` on a leaf's edge, moved off a corner as the
+// caller's points are (t clamped to [kTmin, 1 - kTmin])
+void place_vertex(uint64_t key, double t, double px, double py, double pz, double h0,
+                  double out[3]) {
+    out[0] = px;
+    out[1] = py;
+    out[2] = pz;
+    const double tc = clamp_t(t);
+    if (tc != t) {
+        const int level = (int)((key >> 50) & 7), axis = (int)((key >> 48) & 3);
+        out[axis] += (tc - t) * std::ldexp(h0, -level);
+    }
+}
+
+// the mesh of host copies of the leaves, corner values and vertices; returns
+// a message (empty: success) and the mesh; em receives the ring bits
+std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+                       const std::vector<tms_vertex> &V, double c, int K, double h0,
+                       tms_mesh **out, std::vector<uint8_t> &em) {
+    *out = nullptr;
+    const int64_t n = (int64_t)L.size(), nv = (int64_t)V.size();
+    if (n >= (int64_t)0x7FFFFFFF || nv >= (int64_t)0x7FFFFFFF)
+        return "too many leaves or vertices for 32-bit indices";
+    std::atomic<bool> sorted{true};
+    parallel_for(nv - 1, [&](int64_t b, int64_t e, int) {
+        for (int64_t k = b; k < e; ++k)
+            if (!(V[(size_t)k].edge_key < V[(size_t)k + 1].edge_key)) sorted = false;
+    });
+    if (!sorted) return "vertices must come in ascending edge-key order";
+    auto *M = new tms_mesh();
+    std::vector<int64_t> surf;
+    for (int64_t i = 0; i < n; ++i)
+        if (L[(size_t)i].cls == TMS_CLS_SURFACE) surf.push_back(i);
+    M->n_surface = (int64_t)surf.size();
+    M->level = surf.empty() ? K : L[(size_t)surf[0]].level;
+    for (int64_t i : surf)
+        if (L[(size_t)i].level != M->level || L[(size_t)i].level > K) {
+            delete M;
+            return "SURFACE leaves of different levels: faces between cubes of different sizes "
+                   "(T-junctions) are not meshed";
+        }
+    M->leaf_ijk.resize((size_t)n * 3);
+    M->xyz.resize((size_t)nv * 3);
+    parallel_for(n, [&](int64_t b, int64_t e, int) {
+        for (int64_t i = b; i < e; ++i) {
+            M->leaf_ijk[3 * i] = L[(size_t)i].ix;
+            M->leaf_ijk[3 * i + 1] = L[(size_t)i].iy;
+            M->leaf_ijk[3 * i + 2] = L[(size_t)i].iz;
+        }
+    });
+    parallel_for(nv, [&](int64_t b, int64_t e, int) {
+        for (int64_t k = b; k < e; ++k) {
+            const tms_vertex &v = V[(size_t)k];
+            place_vertex(v.edge_key, v.t, v.x, v.y, v.z, h0, &M->xyz[3 * (size_t)k]);
+        }
+    });
+    // vertex of an edge key: the caller's list is in ascending key order
+    const VidFn vid = [&](uint64_t key) -> int64_t {
+        auto it = std::lower_bound(V.begin(), V.end(), key,
+                                   [](const tms_vertex &a, uint64_t k) { return a.edge_key < k; });
+        return (it != V.end() && it->edge_key == key) ? (int64_t)(it - V.begin()) : -1;
+    };
+    em.assign((size_t)nv, 0);
+    if (!triangulate(L, cp, surf, c, K, h0, vid, M, em)) {
+        delete M;
+        return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
+    }
+    M->open_faces = open_faces(em, nullptr, nv, [&](int64_t v) { return V[(size_t)v].edge_key; },
+                               K, nullptr);
+    *out = M;
+    return std::string();
 }
 
 // Closing open faces (device entry point).  The partition keeps a cube when
 // the bound of its polynomial reaches c; where the bound is not met on a
 // coarse cube although phi at the finest lattice points inside it crosses c,
 // the surface leaves a kept cube through a face with nothing across.  Each
-// finest cube across such a face is added as a SURFACE leaf, repeatedly (an
-// added cube may itself have open faces), until none is left or `rounds`
-// passes.  Its corner values come from a SURFACE leaf that has the same
-// lattice point as a corner wherever there is one (so both sides of a shared
-// face pair its edge points alike), else from phi of the library
-// (tms_eval_phi, the precision of `cells`); its new edge points are placed as
-// the extraction places them.  Cubes outside the root grid are not added.
+// cube of the leaves' level across such a face is added as a SURFACE leaf,
+// repeatedly (an added cube may itself have open faces), until none is left
+// or `rounds` passes, and triangulated like the others.  Its corner values
+// come from a SURFACE leaf that has the same lattice point as a corner
+// wherever there is one (so both sides of a shared face pair its edge points
+// alike), else from phi of the library (tms_eval_phi, the precision of
+// `cells`); its new edge points are placed as the extraction places them and
+// appended to the mesh's points.  Cubes outside the root grid are not added.
 constexpr int kCloseRounds = 64;
 
-std::string close_open_faces(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
-                             std::vector<double> &cp, std::vector<tms_vertex> &V, int rounds,
-                             int32_t *rc) {
+std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
+                       std::vector<double> &cp, const std::vector<tms_vertex> &V,
+                       std::vector<uint8_t> &em, tms_mesh *M, int32_t *rc) {
     *rc = TMS_OK;
     const Grid &g = cells->g;
-    std::vector<int64_t> surf;
-    for (int64_t i = 0; i < (int64_t)L.size(); ++i)
-        if (L[(size_t)i].cls == TMS_CLS_SURFACE) surf.push_back(i);
-    if (surf.empty()) return std::string();
-    const int level = L[(size_t)surf[0]].level;
-    for (int64_t i : surf)
-        if (L[(size_t)i].level != level || level > g.K) return std::string();  // refused later
-    const int sh = g.K - level;
+    const int level = M->level, sh = g.K - level;
     const double h = std::ldexp(g.h0, -level);
-    CubeIndex at;
-    at.reserve(surf.size() * 2);
-    for (int64_t i : surf) at.emplace(cube_key(L[(size_t)i].ix, L[(size_t)i].iy, L[(size_t)i].iz), i);
+    const int64_t n0 = (int64_t)L.size(), nv = (int64_t)V.size();
     const Topo &T = topo();
-    std::vector<int64_t> front = surf;
+    std::unordered_map<uint64_t, int64_t> nmap;   // key -> id of added edge points
+    std::unordered_map<int64_t, uint64_t> nkey;   // and back
+    const VidFn vid = [&](uint64_t key) -> int64_t {
+        auto it = std::lower_bound(V.begin(), V.end(), key,
+                                   [](const tms_vertex &a, uint64_t k) { return a.edge_key < k; });
+        if (it != V.end() && it->edge_key == key) return (int64_t)(it - V.begin());
+        auto jt = nmap.find(key);
+        return jt == nmap.end() ? -1 : jt->second;
+    };
+    const KeyFn key_of = [&](int64_t v) -> uint64_t {
+        return v < nv ? V[(size_t)v].edge_key : nkey.at(v);
+    };
+    std::vector<std::array<int32_t, 3>> q;
+    open_faces(em, nullptr, nv, key_of, g.K, &q);
     DevBuf dpts, dphi;
-    for (int r = 0; r < rounds && !front.empty(); ++r) {
-        std::vector<std::array<int32_t, 3>> q;
-        open_faces(L, front, at, &q);
-        std::sort(q.begin(), q.end());
-        q.erase(std::unique(q.begin(), q.end()), q.end());
+    for (int r = 0; r < kCloseRounds; ++r) {
         q.erase(std::remove_if(q.begin(), q.end(),
-                               [&](const std::array<int32_t, 3> &c) {
+                               [&](const std::array<int32_t, 3> &x) {
                                    for (int a = 0; a < 3; ++a)
-                                       if (c[a] < 0 || (int64_t)c[a] >= ((int64_t)g.nr[a] << level))
+                                       if (x[a] < 0 || (int64_t)x[a] >= ((int64_t)g.nr[a] << level))
                                            return true;
                                    return false;
+                               }),
+                q.end());
+        if (q.empty()) break;
+        // SURFACE leaves within one cube of the new cubes (their corners and
+        // faces are the only ones the new cubes share)
+        std::unordered_map<uint64_t, int64_t> at;
+        {
+            std::unordered_set<uint64_t> nb;
+            for (const auto &x : q)
+                for (int d = 0; d < 27; ++d)
+                    nb.insert(cube_key(x[0] + d % 3 - 1, x[1] + (d / 3) % 3 - 1, x[2] + d / 9 - 1));
+            const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+            std::vector<std::vector<std::pair<uint64_t, int64_t>>> part(nth);
+            parallel_for((int64_t)L.size(), [&](int64_t b, int64_t e, int t) {
+                for (int64_t i = b; i < e; ++i) {
+                    const tms_leaf &lf = L[(size_t)i];
+                    if (lf.cls != TMS_CLS_SURFACE || lf.level != level) continue;
+                    const uint64_t k = cube_key(lf.ix, lf.iy, lf.iz);
+                    if (nb.count(k)) part[(size_t)t].push_back({k, i});
+                }
+            });
+            for (auto &p : part)
+                for (auto &kv : p) at.emplace(kv.first, kv.second);
+        }
+        q.erase(std::remove_if(q.begin(), q.end(),
+                               [&](const std::array<int32_t, 3> &x) {
+                                   return at.count(cube_key(x[0], x[1], x[2])) > 0;
                                }),
                 q.end());
         if (q.empty()) break;
@@ -635,8 +869,7 @@ std::string close_open_faces(tms_ctx *ctx, const tms_cells *cells, std::vector<t
                     found = true;
                 }
                 if (found) continue;
-                const uint64_t pk = cube_key(P[0], P[1], P[2]);
-                auto ins = need.emplace(pk, (int64_t)(pts.size() / 3));
+                auto ins = need.emplace(cube_key(P[0], P[1], P[2]), (int64_t)(pts.size() / 3));
                 if (ins.second)
                     for (int a = 0; a < 3; ++a)
                         pts.push_back(g.o[a] + (double)(P[a] << sh) * g.hmin);
@@ -674,10 +907,8 @@ std::string close_open_faces(tms_ctx *ctx, const tms_cells *cells, std::vector<t
             for (size_t k = 0; k < nq * 8; ++k)
                 if (slot[k] >= 0) f[k] = phi[(size_t)slot[k]];
         }
-        // the new leaves and the edge points of their edges not yet listed
-        front.clear();
-        std::vector<tms_vertex> nv;
-        std::unordered_map<uint64_t, int> seen;
+        // the new leaves, the edge points of their edges not yet in the mesh
+        std::vector<int64_t> idx, touched;
         for (size_t k = 0; k < nq; ++k) {
             tms_leaf lf{};
             lf.ix = q[k][0];
@@ -690,187 +921,45 @@ std::string close_open_faces(tms_ctx *ctx, const tms_cells *cells, std::vector<t
             for (int v = 0; v < 8; ++v)
                 if (f[k * 8 + v] >= g.c) mask |= 1u << v;
             lf.mask = (uint8_t)mask;
+            // a face of it crosses c, so it is a SURFACE cube
             lf.cls = mask == 0 ? TMS_CLS_OUTSIDE : mask == 0xFF ? TMS_CLS_INSIDE : TMS_CLS_SURFACE;
-            const int64_t i = (int64_t)L.size();
+            idx.push_back((int64_t)L.size());
             L.push_back(lf);
             cp.insert(cp.end(), f.begin() + (ptrdiff_t)(k * 8), f.begin() + (ptrdiff_t)(k * 8 + 8));
-            if (lf.cls != TMS_CLS_SURFACE) continue;  // cannot happen: a face of it crosses c
-            at.emplace(cube_key(lf.ix, lf.iy, lf.iz), i);
-            front.push_back(i);
-            for (int e = 0; e < 12; ++e) {
-                const EdgeInfo &E = T.E[e];
+            M->leaf_ijk.insert(M->leaf_ijk.end(), {lf.ix, lf.iy, lf.iz});
+            for (int ed = 0; ed < 12; ++ed) {
+                const EdgeInfo &E = T.E[ed];
                 const double f0 = f[k * 8 + E.v0], f1 = f[k * 8 + E.v1];
                 if ((f0 >= g.c) == (f1 >= g.c)) continue;
-                const uint64_t key = edge_key(0, level, g.K, lf.ix, lf.iy, lf.iz, e);
-                auto it = std::lower_bound(V.begin(), V.end(), key,
-                                           [](const tms_vertex &a, uint64_t kk) { return a.edge_key < kk; });
-                if ((it != V.end() && it->edge_key == key) || !seen.emplace(key, 1).second) continue;
-                tms_vertex x;
-                x.edge_key = key;
-                x.t = (g.c - f0) / (f1 - f0);
-                const int64_t I[3] = {lf.ix + E.off[0], lf.iy + E.off[1], lf.iz + E.off[2]};
-                double p[3];
-                for (int a = 0; a < 3; ++a) p[a] = g.o[a] + (double)(I[a] << sh) * g.hmin;
-                p[E.axis] += x.t * h;
-                x.x = p[0];
-                x.y = p[1];
-                x.z = p[2];
-                nv.push_back(x);
+                const uint64_t key = edge_key(0, level, g.K, lf.ix, lf.iy, lf.iz, ed);
+                int64_t id = vid(key);
+                if (id < 0) {
+                    id = (int64_t)(M->xyz.size() / 3);
+                    nmap.emplace(key, id);
+                    nkey.emplace(id, key);
+                    const double t = (g.c - f0) / (f1 - f0);
+                    const int64_t I[3] = {lf.ix + E.off[0], lf.iy + E.off[1], lf.iz + E.off[2]};
+                    double p[3], x[3];
+                    for (int a = 0; a < 3; ++a) p[a] = g.o[a] + (double)(I[a] << sh) * g.hmin;
+                    p[E.axis] += t * h;
+                    place_vertex(key, t, p[0], p[1], p[2], g.h0, x);
+                    M->xyz.insert(M->xyz.end(), x, x + 3);
+                    em.push_back(0);
+                }
+                touched.push_back(id);
             }
         }
-        if (!nv.empty()) {
-            std::sort(nv.begin(), nv.end(),
-                      [](const tms_vertex &a, const tms_vertex &b) { return a.edge_key < b.edge_key; });
-            const size_t mid = V.size();
-            V.insert(V.end(), nv.begin(), nv.end());
-            std::inplace_merge(V.begin(), V.begin() + (ptrdiff_t)mid, V.end(),
-                               [](const tms_vertex &a, const tms_vertex &b) { return a.edge_key < b.edge_key; });
+        if (!triangulate(L, cp, idx, g.c, g.K, g.h0, vid, M, em)) {
+            *rc = TMS_E_INVALID;
+            return "an edge point of a cube added across an open face is missing";
         }
+        std::sort(touched.begin(), touched.end());
+        touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+        open_faces(em, &touched, 0, key_of, g.K, &q);
     }
-    return std::string();
-}
-
-// the mesh of host copies of the leaves, corner values and vertices; returns
-// a message (empty: success) and the mesh
-std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
-                       const std::vector<tms_vertex> &V, double c, int K, double h0,
-                       tms_mesh **out) {
-    *out = nullptr;
-    const int64_t n = (int64_t)L.size(), nv = (int64_t)V.size();
-    if (n >= (int64_t)0x7FFFFFFF || nv >= (int64_t)0x7FFFFFFF)
-        return "too many leaves or vertices for 32-bit indices";
-    for (int64_t k = 1; k < nv; ++k)
-        if (!(V[(size_t)k - 1].edge_key < V[(size_t)k].edge_key))
-            return "vertices must come in ascending edge-key order";
-    auto *M = new tms_mesh();
-    std::vector<int64_t> surf;
-    for (int64_t i = 0; i < n; ++i)
-        if (L[(size_t)i].cls == TMS_CLS_SURFACE) surf.push_back(i);
-    M->n_surface = (int64_t)surf.size();
-    M->level = surf.empty() ? K : L[(size_t)surf[0]].level;
-    for (int64_t i : surf)
-        if (L[(size_t)i].level != M->level || L[(size_t)i].level > K) {
-            delete M;
-            return "SURFACE leaves of different levels: faces between cubes of different sizes "
-                   "(T-junctions) are not meshed";
-        }
-    M->leaf_ijk.resize((size_t)n * 3);
-    for (int64_t i = 0; i < n; ++i) {
-        M->leaf_ijk[3 * i] = L[(size_t)i].ix;
-        M->leaf_ijk[3 * i + 1] = L[(size_t)i].iy;
-        M->leaf_ijk[3 * i + 2] = L[(size_t)i].iz;
-    }
-    M->xyz.resize((size_t)nv * 3);
-    for (int64_t k = 0; k < nv; ++k) {
-        const tms_vertex &v = V[(size_t)k];
-        double p[3] = {v.x, v.y, v.z};
-        // an edge point on (or within kTmin of) a corner moves along its edge
-        const double tc = clamp_t(v.t);
-        if (tc != v.t) {
-            const int level = (int)((v.edge_key >> 50) & 7), axis = (int)((v.edge_key >> 48) & 3);
-            p[axis] += (tc - v.t) * std::ldexp(h0, -level);
-        }
-        M->xyz[3 * k] = p[0];
-        M->xyz[3 * k + 1] = p[1];
-        M->xyz[3 * k + 2] = p[2];
-    }
-    // vertex of an edge key: the extraction's list is in ascending key order
-    auto vid = [&](uint64_t key) -> int64_t {
-        auto it = std::lower_bound(V.begin(), V.end(), key,
-                                   [](const tms_vertex &a, uint64_t k) { return a.edge_key < k; });
-        return (it != V.end() && it->edge_key == key) ? (int64_t)(it - V.begin()) : -1;
-    };
-    const int64_t ns = (int64_t)surf.size();
-    const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
-    std::vector<std::vector<int32_t>> ptri(nth), pleaf(nth);
-    std::vector<std::vector<double>> pxyz(nth);  // interior points of fanned loops
-    std::vector<int64_t> loops(nth, 0), fb(nth, 0), missing(nth, 0);
-    // per-thread chunks of the surface list, merged in order afterwards
-    std::vector<int64_t> first(nth, -1);
-    parallel_for(ns, [&](int64_t b, int64_t e, int t) {
-        first[(size_t)t] = b;
-        LeafOut out;
-        for (int64_t s = b; s < e; ++s) {
-            const int64_t i = surf[(size_t)s];
-            const tms_leaf &lf = L[(size_t)i];
-            const double *f = &cp[(size_t)i * 8];
-            out.tri.clear();
-            out.inner.clear();
-            out.loops = out.fallback = 0;
-            leaf_triangles(f, c, out);
-            loops[(size_t)t] += out.loops;
-            fb[(size_t)t] += out.fallback;
-            // interior points: placed from a corner of an edge point of the
-            // leaf (its global position minus its local one) -- numbered
-            // -1 - k in the thread, renumbered after the merge
-            std::vector<int32_t> inner_id(out.inner.size(), 0);
-            if (!out.inner.empty()) {
-                int e0 = -1;
-                for (const auto &tr : out.tri)
-                    for (int k = 0; k < 3 && e0 < 0; ++k)
-                        if (tr[k] < 12) e0 = tr[k];
-                const int64_t v0 = e0 < 0 ? -1 : vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, e0));
-                if (v0 < 0) {
-                    ++missing[(size_t)t];
-                    continue;
-                }
-                double P0[3];
-                edge_point(f, c, e0, P0);
-                const double h = std::ldexp(h0, -(int)lf.level);
-                for (size_t k = 0; k < out.inner.size(); ++k) {
-                    inner_id[k] = -1 - (int32_t)(pxyz[(size_t)t].size() / 3);
-                    for (int a = 0; a < 3; ++a)
-                        pxyz[(size_t)t].push_back(M->xyz[3 * v0 + a] + (out.inner[k][a] - P0[a]) * h);
-                }
-            }
-            for (const auto &tr : out.tri) {
-                int32_t id[3];
-                bool ok = true;
-                for (int k = 0; k < 3; ++k) {
-                    if (tr[k] >= 12) {
-                        id[k] = inner_id[(size_t)(tr[k] - 12)];
-                        continue;
-                    }
-                    const int64_t v = vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, tr[k]));
-                    if (v < 0) ok = false;
-                    id[k] = (int32_t)v;
-                }
-                if (!ok) {
-                    ++missing[(size_t)t];
-                    continue;
-                }
-                ptri[(size_t)t].insert(ptri[(size_t)t].end(), id, id + 3);
-                pleaf[(size_t)t].push_back((int32_t)i);
-            }
-        }
-    });
-    std::vector<int> order;
-    for (unsigned t = 0; t < nth; ++t)
-        if (first[t] >= 0) order.push_back((int)t);
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return first[a] < first[b]; });
-    int64_t miss = 0;
-    for (int t : order) {
-        // interior points of this thread's leaves follow the edge points
-        const int32_t base = (int32_t)(M->xyz.size() / 3);
-        for (int32_t &v : ptri[(size_t)t])
-            if (v < 0) v = base + (-1 - v);
-        M->xyz.insert(M->xyz.end(), pxyz[(size_t)t].begin(), pxyz[(size_t)t].end());
-        M->tri.insert(M->tri.end(), ptri[(size_t)t].begin(), ptri[(size_t)t].end());
-        M->tri_leaf.insert(M->tri_leaf.end(), pleaf[(size_t)t].begin(), pleaf[(size_t)t].end());
-        M->n_loops += loops[(size_t)t];
-        M->n_fallback += fb[(size_t)t];
-        miss += missing[(size_t)t];
-    }
-    if (miss > 0) {
-        delete M;
-        return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
-    }
-    {
-        CubeIndex at;
-        for (int64_t i : surf) at.emplace(cube_key(L[(size_t)i].ix, L[(size_t)i].iy, L[(size_t)i].iz), i);
-        M->open_faces = open_faces(L, surf, at, nullptr);
-    }
-    *out = M;
+    M->added.assign(L.begin() + n0, L.end());
+    M->added_phi.assign(cp.begin() + 8 * n0, cp.end());
+    M->open_faces = open_faces(em, nullptr, (int64_t)em.size(), key_of, g.K, nullptr);
     return std::string();
 }
 
@@ -912,15 +1001,18 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
         (void)hipGetLastError();
         return mfail(ctx, TMS_E_DEVICE, "copying leaves, corner values or vertices to the host");
     }
-    if (flags & TMS_MESH_CLOSE) {
-        int32_t rc = TMS_OK;
-        const std::string why = close_open_faces(ctx, cells, L, cp, V, kCloseRounds, &rc);
-        if (rc != TMS_OK) return mfail(ctx, rc, why.c_str());
-    }
-    const std::string why = build_mesh(L, cp, V, g.c, g.K, g.h0, out);
+    std::vector<uint8_t> em;
+    const std::string why = build_mesh(L, cp, V, g.c, g.K, g.h0, out, em);
     if (!why.empty()) return mfail(ctx, TMS_E_INVALID, why.c_str());
-    (*out)->added.assign(L.begin() + n, L.end());
-    (*out)->added_phi.assign(cp.begin() + 8 * n, cp.end());
+    if ((flags & TMS_MESH_CLOSE) && (*out)->open_faces > 0) {
+        int32_t rc = TMS_OK;
+        const std::string w = close_mesh(ctx, cells, L, cp, V, em, *out, &rc);
+        if (rc != TMS_OK) {
+            delete *out;
+            *out = nullptr;
+            return mfail(ctx, rc, w.c_str());
+        }
+    }
     return TMS_OK;
 }
 
@@ -936,7 +1028,8 @@ int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *cor
     std::vector<tms_leaf> L(leaves, leaves + n);
     std::vector<double> cp(corner_phi, corner_phi + 8 * n);
     std::vector<tms_vertex> V(verts, verts + nv);
-    const std::string why = build_mesh(L, cp, V, c, K, h0, out);
+    std::vector<uint8_t> em;
+    const std::string why = build_mesh(L, cp, V, c, K, h0, out, em);
     if (!why.empty()) {
         set_msg(msg, msg_len, why);
         return TMS_E_INVALID;
@@ -987,92 +1080,92 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
     r->n_fallback = m->n_fallback;
     r->open_faces = m->open_faces;
     r->added_cubes = (int64_t)m->added.size();
-    // (a) edges: (min, max, direction) of every triangle side, sorted
-    struct HE {
-        int32_t a, b;
-        int8_t dir;
-    };
-    std::vector<HE> he((size_t)nt * 3);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int k = 0; k < 3; ++k) {
-            const int32_t u = T[3 * t + k], v = T[3 * t + (k + 1) % 3];
-            he[(size_t)(3 * t + k)] = {std::min(u, v), std::max(u, v), (int8_t)(u < v ? 1 : -1)};
-        }
-    std::sort(he.begin(), he.end(), [](const HE &x, const HE &y) {
-        return x.a != y.a ? x.a < y.a : x.b < y.b;
-    });
-    std::vector<uint8_t> bad((size_t)nv, 0);
-    int64_t nedges = 0;
-    for (size_t i = 0; i < he.size();) {
-        size_t j = i;
-        int s = 0;
-        while (j < he.size() && he[j].a == he[i].a && he[j].b == he[i].b) s += he[j++].dir;
-        const size_t k = j - i;
-        ++nedges;
-        if (k == 1) ++r->boundary_edges;
-        else if (k > 2) ++r->nonmanifold_edges;
-        else if (s != 0) ++r->misoriented_edges;
-        if (k != 2 || s != 0) bad[(size_t)he[i].a] = bad[(size_t)he[i].b] = 1;
-        i = j;
-    }
-    // (b) vertex neighbourhoods: the sides opposite a vertex in its triangles
-    // must form one cycle
+    // incident triangles of every vertex (CSR)
     std::vector<int64_t> off((size_t)nv + 1, 0);
-    for (int64_t t = 0; t < 3 * nt; ++t) ++off[(size_t)T[t] + 1];
+    parallel_for(3 * nt, [&](int64_t b, int64_t e, int) {
+        for (int64_t t = b; t < e; ++t) __atomic_fetch_add(&off[(size_t)T[t] + 1], 1, __ATOMIC_RELAXED);
+    });
     for (int64_t v = 0; v < nv; ++v) off[(size_t)v + 1] += off[(size_t)v];
     std::vector<int32_t> inc((size_t)(3 * nt));
     {
         std::vector<int64_t> pos(off.begin(), off.end() - 1);
-        for (int64_t t = 0; t < nt; ++t)
-            for (int k = 0; k < 3; ++k) inc[(size_t)pos[(size_t)T[3 * t + k]]++] = (int32_t)t;
+        parallel_for(nt, [&](int64_t b, int64_t e, int) {
+            for (int64_t t = b; t < e; ++t)
+                for (int k = 0; k < 3; ++k)
+                    inc[(size_t)__atomic_fetch_add(&pos[(size_t)T[3 * t + k]], 1, __ATOMIC_RELAXED)] =
+                        (int32_t)t;
+        });
     }
-    std::atomic<int64_t> badv{0};
-    parallel_for(nv, [&](int64_t b, int64_t e, int) {
-        std::vector<std::pair<int32_t, int32_t>> link;
+    // per vertex: (a) the sides at it -- each neighbour joined through
+    // exactly two triangles, once in each direction (sides counted at their
+    // smaller end); (b) the sides opposite it in its triangles form a single
+    // cycle
+    const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+    std::vector<std::array<int64_t, 5>> acc(nth, {0, 0, 0, 0, 0});
+    parallel_for(nv, [&](int64_t b, int64_t e, int th) {
+        std::array<int64_t, 5> &A = acc[(size_t)th];  // edges, boundary, >2, misoriented, bad v
+        std::vector<std::pair<int32_t, int32_t>> nbr, link;
         for (int64_t v = b; v < e; ++v) {
+            nbr.clear();
             link.clear();
             for (int64_t p = off[(size_t)v]; p < off[(size_t)v + 1]; ++p) {
                 const int32_t t = inc[(size_t)p];
-                int32_t o[2], c = 0;
-                for (int k = 0; k < 3; ++k)
-                    if (T[3 * t + k] != v) o[c++] = T[3 * t + k];
-                if (c == 2) link.push_back({o[0], o[1]});
+                int k = 0;
+                while (k < 3 && T[3 * t + k] != v) ++k;
+                const int32_t nx = T[3 * t + (k + 1) % 3], pv = T[3 * t + (k + 2) % 3];
+                nbr.push_back({nx, 1});
+                nbr.push_back({pv, -1});
+                if (nx != v && pv != v) link.push_back({nx, pv});
             }
+            std::sort(nbr.begin(), nbr.end());
             bool ok = !link.empty();
-            if (ok) {
-                // every link vertex twice, and one cycle through all sides
-                std::unordered_map<int32_t, int> deg;
-                for (auto &s : link) {
-                    ++deg[s.first];
-                    ++deg[s.second];
+            for (size_t i = 0; i < nbr.size();) {
+                size_t j = i;
+                int sdir = 0;
+                while (j < nbr.size() && nbr[j].first == nbr[i].first) sdir += nbr[j++].second;
+                const size_t k = j - i;
+                if (k != 2 || sdir != 0) ok = false;
+                if (nbr[i].first > v) {
+                    ++A[0];
+                    if (k == 1) ++A[1];
+                    else if (k > 2) ++A[2];
+                    else if (sdir != 0) ++A[3];
                 }
-                for (auto &d : deg)
-                    if (d.second != 2) ok = false;
-                if (ok) {
-                    std::vector<char> seen(link.size(), 0);
-                    size_t cnt = 1;
-                    seen[0] = 1;
-                    int32_t cur = link[0].second;
-                    const int32_t start = link[0].first;
-                    while (cur != start && cnt <= link.size()) {
-                        size_t nx = link.size();
-                        for (size_t q = 0; q < link.size(); ++q)
-                            if (!seen[q] && (link[q].first == cur || link[q].second == cur)) {
-                                nx = q;
-                                break;
-                            }
-                        if (nx == link.size()) break;
-                        seen[nx] = 1;
-                        ++cnt;
-                        cur = link[nx].first == cur ? link[nx].second : link[nx].first;
-                    }
-                    ok = cur == start && cnt == link.size();
-                }
+                i = j;
             }
-            if (!ok || bad[(size_t)v]) badv.fetch_add(1);
+            if (ok) {
+                // every link vertex is in two link sides (each neighbour is in
+                // two triangles); walk the cycle from the first side
+                std::vector<char> seen(link.size(), 0);
+                size_t cnt = 1;
+                seen[0] = 1;
+                int32_t cur = link[0].second;
+                const int32_t start = link[0].first;
+                while (cur != start && cnt <= link.size()) {
+                    size_t nx = link.size();
+                    for (size_t q = 0; q < link.size(); ++q)
+                        if (!seen[q] && (link[q].first == cur || link[q].second == cur)) {
+                            nx = q;
+                            break;
+                        }
+                    if (nx == link.size()) break;
+                    seen[nx] = 1;
+                    ++cnt;
+                    cur = link[nx].first == cur ? link[nx].second : link[nx].first;
+                }
+                ok = cur == start && cnt == link.size();
+            }
+            if (!ok && off[(size_t)v + 1] > off[(size_t)v]) ++A[4];
         }
     });
-    r->nonmanifold_vertices = badv.load();
+    int64_t nedges = 0;
+    for (const auto &A : acc) {
+        nedges += A[0];
+        r->boundary_edges += A[1];
+        r->nonmanifold_edges += A[2];
+        r->misoriented_edges += A[3];
+        r->nonmanifold_vertices += A[4];
+    }
     // components (union-find over triangle sides) and Euler characteristic
     {
         std::vector<int32_t> par((size_t)nv);
@@ -1088,7 +1181,8 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
         for (int64_t t = 0; t < nt; ++t)
             for (int k = 0; k < 3; ++k) {
                 usedv[(size_t)T[3 * t + k]] = 1;
-                const int32_t a = find(T[3 * t + k]), b = find(T[3 * t + (k + 1) % 3]);
+                if (k == 2) break;  // two sides join all three corners
+                const int32_t a = find(T[3 * t + k]), b = find(T[3 * t + k + 1]);
                 if (a != b) par[(size_t)a] = b;
             }
         int64_t comps = 0, nvu = 0;
@@ -1102,17 +1196,27 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
         r->unused_vertices = nv - nvu;
     }
     // area, enclosed volume (outward orientation gives a positive volume)
+    std::vector<std::array<double, 2>> av(nth, {0.0, 0.0});
+    parallel_for(nt, [&](int64_t b, int64_t e, int th) {
+        double area = 0.0, vol = 0.0;
+        for (int64_t t = b; t < e; ++t) {
+            const double *p = X + 3 * T[3 * t], *q = X + 3 * T[3 * t + 1],
+                         *s = X + 3 * T[3 * t + 2];
+            double u[3], w[3], n[3];
+            sub3(q, p, u);
+            sub3(s, p, w);
+            crs3(u, w, n);
+            area += 0.5 * std::sqrt(dot3(n, n));
+            double qs[3];
+            crs3(q, s, qs);
+            vol += dot3(p, qs) / 6.0;
+        }
+        av[(size_t)th] = {area, vol};
+    });
     double area = 0.0, vol = 0.0;
-    for (int64_t t = 0; t < nt; ++t) {
-        const double *p = X + 3 * T[3 * t], *q = X + 3 * T[3 * t + 1], *s = X + 3 * T[3 * t + 2];
-        double u[3], w[3], n[3];
-        sub3(q, p, u);
-        sub3(s, p, w);
-        crs3(u, w, n);
-        area += 0.5 * std::sqrt(dot3(n, n));
-        double qs[3];
-        crs3(q, s, qs);
-        vol += dot3(p, qs) / 6.0;
+    for (const auto &x : av) {
+        area += x[0];
+        vol += x[1];
     }
     r->area = area;
     r->volume = vol;
