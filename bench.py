@@ -47,6 +47,8 @@ FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
 OPS_PER_PHI_PAIR = 8 + 4
 # VALU lane-op issue peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 PEAK_VALU_TOPS = 39.3
+# single-precision exponentials (v_exp_f32, quarter rate): 39.3 / 4 T/s
+PEAK_TRANS_TOPS = PEAK_VALU_TOPS / 4
 # FP64 flop slots the nested-SVD bound issues per hard cube: the
 # SQ_INSTS_VALU_FLOPS_FP64 counter over five passes' k_bound launches (it
 # counts per wavefront instruction, FMA as two), times 64 lanes, divided by
@@ -460,7 +462,11 @@ def main():
         "frac": phi_ach / PEAK_VALU_TOPS, "traffic": None,
         "work_per_unit": "%d lane-ops per in-range (point, atom) pair (8 VALU + one "
                          "quarter-rate exponential)" % OPS_PER_PHI_PAIR,
-        "units_per_launch": f32["phi_pairs"] / p_n, "avg_launch_ms": p_ms}]
+        "units_per_launch": f32["phi_pairs"] / p_n, "avg_launch_ms": p_ms,
+        # the same launches against the transcendental unit alone: one
+        # single-precision exponential per in-range pair
+        "exp_per_s": f32["phi_pairs"] / p_n / (p_ms * 1e-3),
+        "exp_frac": f32["phi_pairs"] / p_n / (p_ms * 1e-3) / (PEAK_TRANS_TOPS * 1e12)}]
     b_ms, b_n = launch_avg("decide")
     if FLOP_PER_HARD_CUBE:
         b_ach = st["n_bound"] * FLOP_PER_HARD_CUBE / (tm["decide"]["ms"] * 1e-3) / 1e12
