@@ -440,6 +440,36 @@ void parallel_for(int64_t n, F fn) {
     for (auto &x : th) x.join();
 }
 
+
+// sorts v with cmp: chunks sorted on threads, then merged pairwise
+template <typename T, typename C>
+void parallel_sort(std::vector<T> &v, C cmp) {
+    const int64_t n = (int64_t)v.size();
+    unsigned nt = std::max(1u, std::thread::hardware_concurrency());
+    nt = (unsigned)std::min<int64_t>(nt, std::max<int64_t>(1, n / 65536));
+    if (nt <= 1) {
+        std::sort(v.begin(), v.end(), cmp);
+        return;
+    }
+    std::vector<int64_t> cut(nt + 1);
+    for (unsigned t = 0; t <= nt; ++t) cut[t] = n * t / nt;
+    {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([&, t] { std::sort(v.begin() + cut[t], v.begin() + cut[t + 1], cmp); });
+        for (auto &x : th) x.join();
+    }
+    for (unsigned w = 1; w < nt; w *= 2) {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t + w < nt; t += 2 * w) {
+            const int64_t b = cut[t], mid = cut[t + w], e = cut[std::min(t + 2 * w, nt)];
+            th.emplace_back([&, b, mid, e] {
+                std::inplace_merge(v.begin() + b, v.begin() + mid, v.begin() + e, cmp);
+            });
+        }
+        for (auto &x : th) x.join();
+    }
+}
 // ---- triangle-triangle intersection (Moller's interval overlap test) -------
 void sub3(const double *a, const double *b, double *r) {
     r[0] = a[0] - b[0];
@@ -1221,54 +1251,65 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
     r->area = area;
     r->volume = vol;
     r->density = area > 0 ? (double)nv / area : 0.0;
-    // (c) intersecting pairs among triangles of the same or touching leaves
+    // (c) intersecting pairs among triangles of the same or touching leaves:
+    // the triangles of a leaf are contiguous (emitted leaf by leaf), so each
+    // leaf is a run of triangles; runs sorted by the leaf's cube key, and
+    // the neighbours of a leaf found by binary search
     if (intersections) {
         const int64_t nl = (int64_t)(m->leaf_ijk.size() / 3);
-        std::unordered_map<uint64_t, std::vector<int32_t>> by;
-        auto ck = [](int64_t x, int64_t y, int64_t z) {
-            return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
-                   (uint64_t)(z & 0x1FFFFF);
+        struct Run {
+            uint64_t key;
+            int64_t b, e;
         };
-        for (int64_t t = 0; t < nt; ++t) {
+        std::vector<Run> runs;
+        for (int64_t t = 0; t < nt;) {
+            int64_t e = t + 1;
+            while (e < nt && m->tri_leaf[(size_t)e] == m->tri_leaf[(size_t)t]) ++e;
             const int32_t li = m->tri_leaf[(size_t)t];
-            if (li < 0 || li >= nl) continue;
-            const int32_t *c = &m->leaf_ijk[3 * (size_t)li];
-            by[ck(c[0], c[1], c[2])].push_back((int32_t)t);
-        }
-        std::vector<uint64_t> keys;
-        keys.reserve(by.size());
-        for (auto &kv : by) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end());
-        std::atomic<int64_t> hits{0};
-        parallel_for((int64_t)keys.size(), [&](int64_t b, int64_t e, int) {
-            for (int64_t ki = b; ki < e; ++ki) {
-                const uint64_t k0 = keys[(size_t)ki];
-                const int64_t x = (int64_t)(k0 >> 42), y = (int64_t)((k0 >> 21) & 0x1FFFFF),
-                              z = (int64_t)(k0 & 0x1FFFFF);
-                const auto &A = by.find(k0)->second;
-                for (int dz = -1; dz <= 1; ++dz)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            const uint64_t k1 = ck(x + dx, y + dy, z + dz);
-                            if (k1 < k0) continue;  // each leaf pair once
-                            auto it = by.find(k1);
-                            if (it == by.end()) continue;
-                            const auto &B = it->second;
-                            for (size_t i = 0; i < A.size(); ++i)
-                                for (size_t j = (k1 == k0 ? i + 1 : 0); j < B.size(); ++j) {
-                                    const int32_t s = A[i], t = B[j];
-                                    bool share = false;
-                                    for (int p = 0; p < 3; ++p)
-                                        for (int q = 0; q < 3; ++q)
-                                            if (T[3 * s + p] == T[3 * t + q]) share = true;
-                                    if (share) continue;
-                                    if (tri_tri(X + 3 * T[3 * s], X + 3 * T[3 * s + 1],
-                                                X + 3 * T[3 * s + 2], X + 3 * T[3 * t],
-                                                X + 3 * T[3 * t + 1], X + 3 * T[3 * t + 2]))
-                                        hits.fetch_add(1);
-                                }
-                        }
+            if (li >= 0 && li < nl) {
+                const int32_t *c = &m->leaf_ijk[3 * (size_t)li];
+                runs.push_back({cube_key(c[0], c[1], c[2]), t, e});
             }
+            t = e;
+        }
+        parallel_sort(runs, [](const Run &x, const Run &y) {
+            return x.key != y.key ? x.key < y.key : x.b < y.b;
+        });
+        auto first_run = [&](uint64_t k) {
+            return std::lower_bound(runs.begin(), runs.end(), k,
+                                    [](const Run &x, uint64_t kk) { return x.key < kk; }) -
+                   runs.begin();
+        };
+        std::atomic<int64_t> hits{0};
+        parallel_for((int64_t)runs.size(), [&](int64_t rb, int64_t re, int) {
+            int64_t local = 0;
+            for (int64_t ri = rb; ri < re; ++ri) {
+                const Run &A = runs[(size_t)ri];
+                const int64_t x = (int64_t)(A.key >> 42), y = (int64_t)((A.key >> 21) & 0x1FFFFF),
+                              z = (int64_t)(A.key & 0x1FFFFF);
+                for (int d = 0; d < 27; ++d) {
+                    const uint64_t k1 = cube_key(x + d % 3 - 1, y + (d / 3) % 3 - 1, z + d / 9 - 1);
+                    if (k1 < A.key) continue;  // each pair of leaves once
+                    for (int64_t rj = first_run(k1);
+                         rj < (int64_t)runs.size() && runs[(size_t)rj].key == k1; ++rj) {
+                        const Run &B = runs[(size_t)rj];
+                        if (k1 == A.key && rj < ri) continue;
+                        for (int64_t s = A.b; s < A.e; ++s)
+                            for (int64_t t = (rj == ri ? s + 1 : B.b); t < B.e; ++t) {
+                                bool share = false;
+                                for (int p = 0; p < 3; ++p)
+                                    for (int q = 0; q < 3; ++q)
+                                        if (T[3 * s + p] == T[3 * t + q]) share = true;
+                                if (share) continue;
+                                if (tri_tri(X + 3 * T[3 * s], X + 3 * T[3 * s + 1],
+                                            X + 3 * T[3 * s + 2], X + 3 * T[3 * t],
+                                            X + 3 * T[3 * t + 1], X + 3 * T[3 * t + 2]))
+                                    ++local;
+                            }
+                    }
+                }
+            }
+            hits.fetch_add(local);
         });
         r->intersecting_pairs = hits.load();
     } else {

@@ -12,7 +12,9 @@ without closing open faces, against the oracle.
   the oracle checker's on it with no defect of (a), (b) or (c).
 * A sphere whose unclosed mesh has holes closes into a sphere (Euler
   characteristic 2, area within 1 % of the closed form); the 5,000-atom
-  globule in FP32+guard closes into a manifold with no defect.
+  globule and the 110,000-atom assembly in FP32+guard close into manifolds
+  with no defect of (a), (b) or (c); the added cubes' corner values are the
+  oracle's phi (1e-5 relative, the FP32+guard bar).
 """
 import numpy as np
 import pytest
@@ -139,3 +141,37 @@ def test_closed_mesh_globule5k_fp32g(ctx):
     a = mc.added
     assert np.all(a["cls"] == tms.CLS_SURFACE)
     assert np.all((mc.added_phi >= 1.0).any(1) & (mc.added_phi < 1.0).any(1))
+
+
+def test_closed_mesh_assembly110k(ctx):
+    # the benchmark's workload at full size (FP32+guard, default launch
+    # shapes): the closed mesh meets all three conditions, including (c)
+    # over every pair of triangles of touching leaves; the corner values of
+    # a sample of the added cubes are phi of the oracle at those points
+    w = workloads.ASSEMBLY110K
+    atoms = workloads.atoms(w)
+    print("case assembly110k fp32g", flush=True)
+    cells = ctx.build_cells(atoms, w.params(tms.PREC_FP32_GUARD))
+    try:
+        leaves, cphi, _ = ctx.partition_estimate(cells)
+        verts = ctx.extract(cells, leaves, cphi)
+        m = ctx.mesh_build(cells, leaves, cphi, verts, close=True)
+        origin, K = np.array(cells.origin), cells.K
+    finally:
+        ctx.free_cells(cells)
+    rep = m.check(intersections=True)
+    print(rep)
+    assert rep["n_triangles"] > 10_000_000 and rep["open_faces"] == 0
+    assert rep["boundary_edges"] == rep["nonmanifold_edges"] == rep["misoriented_edges"] == 0
+    assert rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    assert rep["unused_vertices"] == 0 and rep["euler"] % 2 == 0 and rep["volume"] > 0
+    a, ap = m.added, m.added_phi
+    assert np.all(a["reason"] == tms.REASON_CLOSED) and np.all(a["level"] == K)
+    rng = np.random.default_rng(12)
+    pick = rng.choice(len(a), min(50, len(a)), replace=False)
+    h = w.h0 / (1 << K)
+    off = np.array([[v & 1, (v >> 1) & 1, (v >> 2) & 1] for v in range(8)])
+    ijk = np.stack([a["ix"], a["iy"], a["iz"]], 1)[pick]
+    pts = origin + ((ijk[:, None, :] + off[None]) * h).reshape(-1, 3)
+    ref = oracle.phi(atoms, w.D, pts).reshape(-1, 8)
+    assert np.max(np.abs(ap[pick] - ref) / ref) < 1e-5
