@@ -54,7 +54,8 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long 
 // ---------------------------------------------------------------------------
 struct EstOut {
     uint8_t *dec;        // [n] decision per queue entry (255: in the hard list)
-    double *hardA;       // [cap][64] tensors of hard cubes
+    double *hardA;       // tensors of hard cubes, entry pairs outermost: the
+                         // pair (A[2 e], A[2 e + 1]) of slot k at double2 e * hs + k
     double *hardE;       // [cap] their error bounds (0 for exact exponentials)
     int32_t *hardIdx;    // [cap] their queue indices
     unsigned *hardCount; // device counter (reset by the host per pass)
@@ -64,6 +65,7 @@ struct EstOut {
     unsigned *ovf = nullptr;   // set when a capacity-sized tiled grid is short of chunks
     double *allA = nullptr;    // [n][64]: every entry's tensor (children re-expanded
                                // from their parents' next level), or null
+    int64_t hs = 0;            // slots of the hard list (its stride)
 };
 
 constexpr uint8_t DEC_HARD = 255;
@@ -136,9 +138,11 @@ __device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, co
     const bool hard = valid && d == DEC_HARD;
     const unsigned slot = wave_append(o.hardCount, hard);
     if (hard) {
-        double *dst = o.hardA + 64 * (int64_t)slot;
+        // a wavefront's slots are consecutive: each pair is one contiguous
+        // run of stores across its lanes
+        double2 *dst = reinterpret_cast<double2 *>(o.hardA) + slot;
 #pragma unroll
-        for (int e = 0; e < 64; ++e) dst[e] = A[e];
+        for (int e = 0; e < 32; ++e) dst[e * o.hs] = make_double2(A[2 * e], A[2 * e + 1]);
         o.hardE[slot] = EA;
         o.hardIdx[slot] = (int32_t)qi;
     }
@@ -905,9 +909,13 @@ __global__ __launch_bounds__(kBS, 2) void k_bound(Grid g, int level, EstOut o) {
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= (int64_t)*o.hardCount) return;
     double A[64];
-    const double *src = o.hardA + 64 * t;
+    const double2 *src = reinterpret_cast<const double2 *>(o.hardA) + t;
 #pragma unroll
-    for (int e = 0; e < 64; ++e) A[e] = src[e];
+    for (int e = 0; e < 32; ++e) {
+        const double2 v = src[e * o.hs];
+        A[2 * e] = v.x;
+        A[2 * e + 1] = v.y;
+    }
     double E, asum;
     masses(A, E, asum);
     const double band = error_band(FAST, o.hardE[t], asum);
@@ -1502,12 +1510,13 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount,
                                   const ProjTab &pt, unsigned *tick, bool half, unsigned *ovf,
-                                  double *allA) {
+                                  double *allA, int64_t hs) {
     if (n <= 0) return hipSuccess;
+    if (hs < n) return hipErrorInvalidValue;  // the hard list holds every entry
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf, allA};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf, allA, hs};
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
@@ -1544,10 +1553,12 @@ hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level
 hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, int64_t off,
                           const double *Apar, const int32_t *qpar, uint8_t *dec, double *hardA,
                           double *hardE, int32_t *hardIdx, unsigned *hardCount, double *allA,
-                          hipStream_t s) {
+                          hipStream_t s, int64_t hs) {
     if (n <= 0) return hipSuccess;
+    if (hs < n) return hipErrorInvalidValue;
     EstOut o{dec, hardA, hardE, hardIdx, hardCount, nullptr};
     o.allA = allA;
+    o.hs = hs;
     hipLaunchKernelGGL(k_reexpand, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, n, off, Apar, qpar,
                        o);
     return hipGetLastError();
@@ -1555,9 +1566,11 @@ hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, i
 
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
-                        hipStream_t s) {
+                        hipStream_t s, int64_t hs) {
     if (max_n <= 0) return hipSuccess;
+    if (hs < max_n) return hipErrorInvalidValue;
     EstOut o{dec, hardA, hardE, hardIdx, hardCount, nullptr};
+    o.hs = hs;
     if (precision == TMS_PREC_FP32_GUARD)
         hipLaunchKernelGGL(k_bound<true>, dim3(nblk(max_n)), dim3(kBS), 0, s, g, level, o);
     else

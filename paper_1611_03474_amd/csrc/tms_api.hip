@@ -1202,9 +1202,9 @@ int32_t record_pass(tms_ctx *ctx, const tms_cells *cells, hipStream_t s) {
                                          G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard,
                                          reinterpret_cast<int64_t *>(ctr + kCtPairs + 64 * lev),
                                          ctx->tile_atoms, s, ncount, pt, nullptr, half,
-                                         percap ? ovf : nullptr));
+                                         percap ? ovf : nullptr, nullptr, S));
             HIPCK(launch_bound(g, lev, lprec, cap, dec + off, G.abuf.as<double>(),
-                               G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s));
+                               G.ebuf.as<double>(), G.hidx.as<int32_t>(), hard, s, S));
         }
         HIPCK(launch_level_histo(dec, QC, ctr + kCtHisto + 8 * lev, ctr + kCtPart, s, nq + lev));
         HIPCK(launch_level_counts(dec, QC, flags, idx, s, nq + lev));
@@ -1560,7 +1560,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                                           ctx->qpar.as<int32_t>(), ctx->dec.as<uint8_t>() + off,
                                           ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
                                           ctx->hidx.as<int32_t>(), hard,
-                                          allA ? allA + 64 * off : nullptr, s));
+                                          allA ? allA + 64 * off : nullptr, s, cap));
                 } else {  // Step 1 (tensor) and the decisions that need no bound
                     TimedScope ts_(ctx, !tiled ? TMS_T_ESTIMATE
                                                : (lev <= 1 ? TMS_T_GROUPED : TMS_T_TILED));
@@ -1572,13 +1572,13 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
                         hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s, nullptr,
                         pt, half ? nullptr : tick, half, nullptr,
-                        allA ? allA + 64 * off : nullptr));
+                        allA ? allA + 64 * off : nullptr, cap));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
                     HIPCK(launch_bound(g, lev, lprec, ns, ctx->dec.as<uint8_t>() + off,
                                        ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
-                                       ctx->hidx.as<int32_t>(), hard, s));
+                                       ctx->hidx.as<int32_t>(), hard, s, cap));
                 }
             }
             chunks_lvl[lev] = tiled && !half ? level_chunks : -1;

@@ -375,16 +375,18 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
                                   const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr,
                                   bool half = false, unsigned *ovf = nullptr,
-                                  double *allA = nullptr);
+                                  double *allA = nullptr, int64_t hs = 0);
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
 // fill the projection table (t: [3 n ns][6] doubles)
 hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level, int precision,
                              const double *ax, const double *ay, const double *az, int64_t n,
                              int ns, double *t, hipStream_t s);
+// The hard list (hardA, hardE, hardIdx) has hs slots: hardA holds the
+// tensors with entry pairs outermost, pair e of slot k at double2 e * hs + k.
 hipError_t launch_bound(const Grid &g, int level, int precision, int64_t max_n, uint8_t *dec,
                         double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
-                        hipStream_t s);
+                        hipStream_t s, int64_t hs);
 // Trailing device-count arguments (nd: count on the device, n then a
 // capacity that sizes the launch) are for the capture path; null elsewhere.
 hipError_t launch_run_flags(const Grid *gt, int level, const int4 *q, const int32_t *subset,
@@ -430,7 +432,7 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
 hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, int64_t off,
                           const double *Apar, const int32_t *qpar, uint8_t *dec, double *hardA,
                           double *hardE, int32_t *hardIdx, unsigned *hardCount, double *allA,
-                          hipStream_t s);
+                          hipStream_t s, int64_t hs);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
                               unsigned long long *part, hipStream_t s, const int32_t *nd = nullptr);
 // regrouping of a batch's leaves by conformation (segments level * nconf + conf)
