@@ -63,9 +63,11 @@ struct EstOut {
                             // launch is sized by a capacity; null: the launch size
     unsigned *tick = nullptr;  // [8] zeroed slot counters (persistent tiled grid)
     unsigned *ovf = nullptr;   // set when a capacity-sized tiled grid is short of chunks
-    double *allA = nullptr;    // [n][64]: every entry's tensor (children re-expanded
-                               // from their parents' next level), or null
+    double *allA = nullptr;    // every entry's tensor (children re-expanded from
+                               // their parents' next level), or null: pair e
+                               // of entry k at double2 e * as + k
     int64_t hs = 0;            // slots of the hard list (its stride)
+    int64_t as = 0;            // entries of allA (its stride)
 };
 
 constexpr uint8_t DEC_HARD = 255;
@@ -131,9 +133,9 @@ __device__ __forceinline__ void epilogue(const Grid &g, int level, bool fast, co
                                          double EA, int64_t qi, bool valid, const EstOut &o) {
     const uint8_t d = valid ? easy_decision(g, level, fast, A, EA) : (uint8_t)0;
     if (o.allA && valid) {
-        double *dst = o.allA + 64 * qi;
+        double2 *dst = reinterpret_cast<double2 *>(o.allA) + qi;
 #pragma unroll
-        for (int e = 0; e < 64; ++e) dst[e] = A[e];
+        for (int e = 0; e < 32; ++e) dst[e * o.as] = make_double2(A[2 * e], A[2 * e + 1]);
     }
     const bool hard = valid && d == DEC_HARD;
     const unsigned slot = wave_append(o.hardCount, hard);
@@ -1141,7 +1143,7 @@ __device__ __forceinline__ void half_series(double p0, double p1, double p2, dou
 
 __global__ __launch_bounds__(kBS) void k_reexpand(Grid g, int level, const int4 *__restrict__ q,
                                                   int64_t n, int64_t off,
-                                                  const double *__restrict__ Apar,
+                                                  const double *__restrict__ Apar, int64_t aps,
                                                   const int32_t *__restrict__ qpar, EstOut o) {
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     const bool valid = t < n;  // every lane reaches the epilogue (wave append)
@@ -1150,9 +1152,13 @@ __global__ __launch_bounds__(kBS) void k_reexpand(Grid g, int level, const int4 
     for (int e = 0; e < 64; ++e) A[e] = 0.0;
     if (valid) {
         const int4 c = q[t];
-        const double *src = Apar + 64 * (int64_t)qpar[(off + t) >> 3];
+        const double2 *src = reinterpret_cast<const double2 *>(Apar) + qpar[(off + t) >> 3];
 #pragma unroll
-        for (int e = 0; e < 64; ++e) A[e] = src[e];
+        for (int e = 0; e < 32; ++e) {
+            const double2 v = src[e * aps];
+            A[2 * e] = v.x;
+            A[2 * e + 1] = v.y;
+        }
         const double sx = (c.x & 1) ? 1.0 : -1.0, sy = (c.y & 1) ? 1.0 : -1.0,
                      sz = (c.z & 1) ? 1.0 : -1.0;
         double x[4];
@@ -1510,13 +1516,13 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   int32_t *hardIdx, unsigned *hardCount, int64_t *pairs,
                                   int tile_atoms, hipStream_t s, const int32_t *ncount,
                                   const ProjTab &pt, unsigned *tick, bool half, unsigned *ovf,
-                                  double *allA, int64_t hs) {
+                                  double *allA, int64_t hs, int64_t as) {
     if (n <= 0) return hipSuccess;
     if (hs < n) return hipErrorInvalidValue;  // the hard list holds every entry
     const int qh = qh_for(g, level);
     const bool fast = precision == TMS_PREC_FP32_GUARD;
     auto *pc = reinterpret_cast<unsigned long long *>(pairs);
-    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf, allA, hs};
+    EstOut o{dec, hardA, hardE, hardIdx, hardCount, ncount, tick, ovf, allA, hs, as};
     if (chunks) {
         if (nchunks <= 0) return hipSuccess;
         if (fast)
@@ -1551,16 +1557,17 @@ hipError_t launch_proj_table(const Grid &g, const Grid *gt, int nconf, int level
 }
 
 hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, int64_t off,
-                          const double *Apar, const int32_t *qpar, uint8_t *dec, double *hardA,
-                          double *hardE, int32_t *hardIdx, unsigned *hardCount, double *allA,
-                          hipStream_t s, int64_t hs) {
+                          const double *Apar, int64_t aps, const int32_t *qpar, uint8_t *dec,
+                          double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
+                          double *allA, hipStream_t s, int64_t hs, int64_t as) {
     if (n <= 0) return hipSuccess;
     if (hs < n) return hipErrorInvalidValue;
     EstOut o{dec, hardA, hardE, hardIdx, hardCount, nullptr};
     o.allA = allA;
     o.hs = hs;
-    hipLaunchKernelGGL(k_reexpand, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, n, off, Apar, qpar,
-                       o);
+    o.as = as;
+    hipLaunchKernelGGL(k_reexpand, dim3(nblk(n)), dim3(kBS), 0, s, g, level, q, n, off, Apar, aps,
+                       qpar, o);
     return hipGetLastError();
 }
 

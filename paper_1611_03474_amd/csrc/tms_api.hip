@@ -1462,6 +1462,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
         // keeps its entries' tensors for its children, which take them from
         // there instead of projecting the atoms
         const bool reex = cells->p.child_tensor == TMS_CHILD_REEXPAND;
+        int64_t nq_prev = 0;  // the previous level's entries (its saved tensors' stride)
         for (int lev = 0; lev <= g.K && nq > 0; ++lev) {
             if (nq >= (int64_t)0x7FFFFFFF) return fail(ctx, TMS_E_INVALID, "queue too large");
             st.n_est[lev] = nq;
@@ -1556,11 +1557,11 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                 if (reex_lev) {  // Step 1 by re-expansion, and the easy decisions
                     TimedScope ts_(ctx, TMS_T_ESTIMATE);
                     HIPCK(launch_reexpand(g, lev, q + off, ns, off,
-                                          ctx->asave[(lev - 1) & 1].as<double>(),
+                                          ctx->asave[(lev - 1) & 1].as<double>(), nq_prev,
                                           ctx->qpar.as<int32_t>(), ctx->dec.as<uint8_t>() + off,
                                           ctx->abuf.as<double>(), ctx->ebuf.as<double>(),
                                           ctx->hidx.as<int32_t>(), hard,
-                                          allA ? allA + 64 * off : nullptr, s, cap));
+                                          allA ? allA + 2 * off : nullptr, s, cap, nq));
                 } else {  // Step 1 (tensor) and the decisions that need no bound
                     TimedScope ts_(ctx, !tiled ? TMS_T_ESTIMATE
                                                : (lev <= 1 ? TMS_T_GROUPED : TMS_T_TILED));
@@ -1572,7 +1573,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                         ctx->abuf.as<double>(), ctx->ebuf.as<double>(), ctx->hidx.as<int32_t>(),
                         hard, reinterpret_cast<int64_t *>(ctr + 0), ctx->tile_atoms, s, nullptr,
                         pt, half ? nullptr : tick, half, nullptr,
-                        allA ? allA + 64 * off : nullptr, cap));
+                        allA ? allA + 2 * off : nullptr, cap, nq));
                 }
                 {  // Step 2: nested-SVD bound on the cubes that need it
                     TimedScope ts_(ctx, TMS_T_DECIDE);
@@ -1629,6 +1630,7 @@ int32_t tms_partition_estimate(tms_ctx *ctx, const tms_cells *cells, tms_leaf *l
                                         nullptr, reex ? ctx->qpar.as<int32_t>() : nullptr));
             }
             L += nl;
+            nq_prev = nq;
             nq = nc;
             cur ^= 1;
         }

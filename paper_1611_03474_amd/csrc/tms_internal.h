@@ -375,7 +375,7 @@ hipError_t launch_estimate_decide(const Grid &g, const Grid *gt, int level, int 
                                   int tile_atoms, hipStream_t s, const int32_t *ncount = nullptr,
                                   const ProjTab &pt = ProjTab{}, unsigned *tick = nullptr,
                                   bool half = false, unsigned *ovf = nullptr,
-                                  double *allA = nullptr, int64_t hs = 0);
+                                  double *allA = nullptr, int64_t hs = 0, int64_t as = 0);
 // intervals per (axis, atom) of the projection table of a level
 int proj_table_slots(const tms_cells *cells, int level);
 // fill the projection table (t: [3 n ns][6] doubles)
@@ -427,12 +427,14 @@ hipError_t launch_level_emit(const int4 *q, const uint8_t *dec, int64_t n, int l
                              int32_t *qpar = nullptr);
 // child tensors re-expanded from their parents' (eq. childtensor) for n
 // entries of a level starting at off (q, dec, hard list as for the estimate);
-// Apar: the previous level's tensors by queue index, qpar[j]: the parent of
-// entries 8 j .. 8 j + 7; allA: where the children's tensors go (or null)
+// Apar: the previous level's tensors by queue index (aps entries, pair e of
+// entry k at double2 e * aps + k), qpar[j]: the parent of entries
+// 8 j .. 8 j + 7; allA: where this level's tensors go (as entries, the same
+// layout; offset to the slice), or null
 hipError_t launch_reexpand(const Grid &g, int level, const int4 *q, int64_t n, int64_t off,
-                          const double *Apar, const int32_t *qpar, uint8_t *dec, double *hardA,
-                          double *hardE, int32_t *hardIdx, unsigned *hardCount, double *allA,
-                          hipStream_t s, int64_t hs);
+                          const double *Apar, int64_t aps, const int32_t *qpar, uint8_t *dec,
+                          double *hardA, double *hardE, int32_t *hardIdx, unsigned *hardCount,
+                          double *allA, hipStream_t s, int64_t hs, int64_t as);
 hipError_t launch_level_histo(const uint8_t *dec, int64_t n, unsigned long long *h5,
                               unsigned long long *part, hipStream_t s, const int32_t *nd = nullptr);
 // regrouping of a batch's leaves by conformation (segments level * nconf + conf)
