@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # known size (FETCH x2.0, WRITE x1.0), mean of the level-2 and level-3
 # launches on the 110,000-atom assembly (profiles/estimate_tiled_assembly110k_traffic.md);
 # None when the kernel changed since the counters were taken
-TRAFFIC_TILED = 12.23e9
+TRAFFIC_TILED = 12.55e9
 
 # algorithmic work per unit
 FLOP_PER_PAIR = 148      # rank-one update of a 4x4x4 tensor: 64 FMA + 20 MUL
