@@ -130,23 +130,6 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup, with_mesh=False):
               "device_ms": s2tm["stage2"]["ms"] / 3,
               "leaves_per_s": nl / (spread(s2_ms)["median"] * 1e-3)}
     del s2rec
-    # the Stage-2 mesh (host, Section 2.3) of the pass's leaves with open
-    # faces closed, and its manifold checks (a), (b) (no intersection test at
-    # this size), outside the step
-    mesh = None
-    if with_mesh:
-        m_ms, m = timed_steps(lambda: ctx.mesh_build(cells, lb[:nl], cb[:nl], vb[:nv]), 1)
-        t0 = time.perf_counter()
-        rep = m.check(intersections=False)
-        c_ms = (time.perf_counter() - t0) * 1e3
-        mesh = {"build_ms": m_ms[0], "check_ms": c_ms, "threads": os.cpu_count(),
-                "surface_leaves_per_s": sd["n_surface"] / (m_ms[0] * 1e-3),
-                **{k: rep[k] for k in ("n_vertices", "n_triangles", "n_loops", "n_fallback",
-                                       "open_faces", "added_cubes", "boundary_edges",
-                                       "nonmanifold_edges", "misoriented_edges",
-                                       "nonmanifold_vertices", "components", "euler",
-                                       "unused_vertices", "area", "volume", "density")}}
-        del m
     # the same pass replayed from a captured graph (build eager, rest one
     # graph) that writes its results into lb, cb, vb
     ctx.graph_capture(cells, margin=1.1, leaves=lb, cphi=cb, verts=vb)
@@ -159,6 +142,41 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup, with_mesh=False):
         gstep()
     g_ms, (gnl, gnv, _) = timed_steps(gstep, steps)
     assert gnl == nl and gnv == nv
+    # the Stage-2 mesh (host, Section 2.3) of the pass's leaves (the
+    # replays wrote the same ones into lb, cb, vb) with open
+    # faces closed, and its manifold checks (a), (b) (no intersection test at
+    # this size), outside the step
+    mesh = None
+    if with_mesh:
+        m_ms, m = timed_steps(lambda: ctx.mesh_build(cells, lb[:nl], cb[:nl], vb[:nv]), 1)
+        t0 = time.perf_counter()
+        rep = m.check(intersections=False)
+        c_ms = (time.perf_counter() - t0) * 1e3
+        # vertex density against h_min (Section 3.1 meshes at 1 and 2
+        # vertices per square angstrom): coarser lattices of the same atoms
+        dens = {}
+        for h_min in (1.0, 0.5):
+            pc = tms.make_params(D=w.D, c=w.c, tau=w.tau, h0=w.h0, h_min=h_min,
+                                 precision=precision)
+            cc = ctx.build_cells(atoms_dev, pc)
+            lc, cpc, _ = ctx.partition_estimate(cc)
+            vc = ctx.extract(cc, lc, cpc)
+            mc = ctx.mesh_build(cc, lc, cpc, vc)
+            ctx.free_cells(cc)
+            rc = mc.check(intersections=False)
+            dens[str(h_min)] = {k: rc[k] for k in ("density", "n_vertices", "n_triangles",
+                                                   "added_cubes", "boundary_edges",
+                                                   "nonmanifold_vertices")}
+            del mc
+        mesh = {"build_ms": m_ms[0], "check_ms": c_ms, "threads": os.cpu_count(),
+                "by_h_min": dens,
+                "surface_leaves_per_s": sd["n_surface"] / (m_ms[0] * 1e-3),
+                **{k: rep[k] for k in ("n_vertices", "n_triangles", "n_loops", "n_fallback",
+                                       "open_faces", "added_cubes", "boundary_edges",
+                                       "nonmanifold_edges", "misoriented_edges",
+                                       "nonmanifold_vertices", "components", "euler",
+                                       "unused_vertices", "area", "volume", "density")}}
+        del m
     ctx.free_cells(cells)
     return dict(ms_per_step=spread(step_ms)["mean"], step_ms=spread(step_ms), stats=sd,
                 n_leaves=nl, n_vertices=nv, timing=per_step, phi_pairs=phi_pairs,

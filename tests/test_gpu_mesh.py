@@ -175,3 +175,33 @@ def test_closed_mesh_assembly110k(ctx):
     pts = origin + ((ijk[:, None, :] + off[None]) * h).reshape(-1, 3)
     ref = oracle.phi(atoms, w.D, pts).reshape(-1, 8)
     assert np.max(np.abs(ap[pick] - ref) / ref) < 1e-5
+
+
+def test_vertex_density_follows_h_min(ctx):
+    # the mesh's vertices are edge points of the finest lattice, so the
+    # density per unit area scales as 1 / h_min^2 (Section 3.1 tunes it to
+    # 1 and 2 vertices per square angstrom; h_min = 1 gives about 1.5); every
+    # level's closed mesh has no defect
+    w = workloads.GLOBULE5K[0.9]
+    atoms = workloads.atoms(w)
+    dens = {}
+    for h_min in (1.0, 0.5, 0.25):
+        print("case globule5k h_min %g" % h_min, flush=True)
+        p = tms.make_params(D=w.D, tau=1e-3, h0=2.0, h_min=h_min,
+                            precision=tms.PREC_FP32_GUARD)
+        cells = ctx.build_cells(atoms, p)
+        try:
+            leaves, cphi, _ = ctx.partition_estimate(cells)
+            verts = ctx.extract(cells, leaves, cphi)
+            m = ctx.mesh_build(cells, leaves, cphi, verts, close=True)
+        finally:
+            ctx.free_cells(cells)
+        rep = m.check(intersections=True)
+        print(h_min, rep)
+        assert rep["open_faces"] == 0 and rep["boundary_edges"] == 0
+        assert rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+        assert rep["misoriented_edges"] == rep["nonmanifold_edges"] == 0
+        dens[h_min] = rep["density"]
+    assert 1.0 < dens[1.0] < 2.0
+    for a, b in ((1.0, 0.5), (0.5, 0.25)):
+        assert 3.0 < dens[b] / dens[a] < 5.0
