@@ -72,6 +72,7 @@ extern "C" {
 #define TMS_REASON_CONVERGED 1 /* higher-order mass 2E <= tau (Step 3)          */
 #define TMS_REASON_HMIN 2      /* kept by the bound at the finest level          */
 #define TMS_REASON_CLOSED 3    /* added by tms_mesh_build across an open face    */
+#define TMS_REASON_SPLIT 4     /* finest cube of a coarser SURFACE leaf (mesh)   */
 #define TMS_CLS_OUTSIDE 0      /* every corner value below c                     */
 #define TMS_CLS_SURFACE 1      /* corner values on both sides of c               */
 #define TMS_CLS_INSIDE 2       /* every corner value >= c                        */
@@ -465,10 +466,13 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  *   as tms_partition_estimate wrote them, verts [nv] as
  *   tms_extract_cube_vertices wrote them for those leaves (device pointers).
  *   The mesh's vertices are the nv edge points in that (key) order, then
- *   those of added cubes and interior points of fanned patches.  Every
- *   SURFACE leaf must have the same level (faces between cubes of different
- *   sizes are not meshed).  *out receives a mesh owned by the caller (free it
- *   with tms_mesh_free).  An edge point within 1e-6 of its edge from a corner
+ *   those of added cubes and interior points of fanned patches.  A SURFACE
+ *   leaf above the finest level (a loose tau can stop a straddling cube
+ *   early) is meshed through the cubes of the finest level inside it whose
+ *   corner values straddle c, added as SURFACE leaves (reason
+ *   TMS_REASON_SPLIT; corner values as for TMS_MESH_CLOSE below); its own
+ *   edge points stay in the vertex list, unused.  *out receives a mesh owned
+ *   by the caller (free it with tms_mesh_free).  An edge point within 1e-6 of its edge from a corner
  *   (a corner value equal to c puts three points on the corner) is moved to
  *   1e-6 of the edge from it, in the triangulation and in xyz.
  *   flags TMS_MESH_CLOSE: close open faces (below).  Where the bound of a
@@ -489,8 +493,9 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * tms_mesh_get: host copies: xyz [nv][3], tri [nt][3] (vertex indices),
  *   tri_leaf [nt] (index of the triangle's leaf in the caller's list, n + k
  *   for the k-th added cube); any pointer may be NULL.
- * tms_mesh_added: host copies of the added cubes (leaves [k], corner_phi
- *   [k][8]); *n_out = k; both NULL: only count; TMS_E_CAPACITY if cap < k.
+ * tms_mesh_added: host copies of the added cubes, split and closing ones
+ *   (leaves [k], corner_phi [k][8]); *n_out = k; both NULL: only count;
+ *   TMS_E_CAPACITY if cap < k.
  * tms_mesh_check: the three conditions of a manifold mesh (Section 3.2):
  *   (a) every edge shared by exactly two triangles (and traversed in opposite
  *   directions), (b) the neighbourhood of every vertex a single loop, (c) no
@@ -519,8 +524,9 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
                        int32_t flags, tms_mesh **out);
 /* The same from host arrays (leaves [n], corner_phi [n][8], verts [nv] in
  * ascending key order), with the isovalue c, the finest level K and the root
- * edge h0 of the cells they came from; errors as above, with the message in
- * msg. */
+ * edge h0 of the cells they came from, without phi: no closing, and every
+ * SURFACE leaf must have the same level (TMS_E_INVALID otherwise); errors as
+ * above, with the message in msg. */
 int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *corner_phi,
                             const tms_vertex *verts, int64_t nv, double c, int32_t K, double h0,
                             tms_mesh **out, char *msg, int64_t msg_len);

@@ -10,7 +10,8 @@ from the definitions:
   sampled on a fine grid and the connected components of {g >= c} labelled;
 * the loops those segments form on the cube's boundary;
 * closing open faces (the cubes across crossing faces with no SURFACE leaf
-  across, added until none is left);
+  across, added until none is left), and the cubes of the finest level that
+  replace coarser SURFACE leaves;
 * a mesh checker: (a) every edge in exactly two triangles, traversed in
   opposite directions; (b) the triangles around every vertex form a single
   loop; (c) no two triangles without a shared vertex intersect (brute force
@@ -359,3 +360,50 @@ def close_open_faces(ijk, corner_phi, surface, c, dims, phi_at, rounds=64):
             cubes[r] = front[r] = added[r] = f
     keys = sorted(added)
     return keys, np.array([added[k] for k in keys]).reshape(-1, 8)
+
+
+# ---- coarser SURFACE leaves -------------------------------------------------
+# Reading (the paper meshes cubes of different sizes against each other): a
+# SURFACE leaf above the finest level K is meshed through the cubes of level
+# K inside it whose corner values straddle c.  Values at lattice points that
+# are corners of the coarse leaf, or of a SURFACE leaf of level K, are those
+# leaves' values; other points are evaluated by `phi_at`.
+
+def split_coarse(ijk, level, corner_phi, surface, K, phi_at):
+    """Every level-K cube inside the SURFACE leaves above level K, as
+    {ijk: corner values [8]} (`straddling` keeps those whose values lie on
+    both sides of c).  ijk, level, corner_phi, surface: the leaves;
+    phi_at(P): phi at level-K lattice points P [m, 3]."""
+    known = {}
+    coarse = []
+    for q, l, f, s in zip(ijk, level, corner_phi, surface):
+        if not s:
+            continue
+        sh = K - int(l)
+        b = tuple(int(x) << sh for x in q)
+        n = 1 << sh
+        for v in range(8):
+            known[(b[0] + (v & 1) * n, b[1] + ((v >> 1) & 1) * n, b[2] + ((v >> 2) & 1) * n)] = \
+                float(f[v])
+        if sh > 0:
+            coarse.append((b, n))
+    pts = sorted({(b[0] + x, b[1] + y, b[2] + z) for b, n in coarse
+                  for x in range(n + 1) for y in range(n + 1) for z in range(n + 1)} - set(known))
+    if pts:
+        known.update(zip(pts, (float(v) for v in phi_at(np.array(pts, dtype=np.int64)))))
+    out = {}
+    for b, n in coarse:
+        for x in range(n):
+            for y in range(n):
+                for z in range(n):
+                    f = np.array([known[(b[0] + x + (v & 1), b[1] + y + ((v >> 1) & 1),
+                                         b[2] + z + ((v >> 2) & 1))] for v in range(8)])
+                    out[(b[0] + x, b[1] + y, b[2] + z)] = f
+    return out
+
+
+def straddling(cubes, c):
+    """The cubes of {ijk: corner values} whose values lie on both sides of c
+    (sorted list of ijk, values [k, 8])."""
+    keys = sorted(k for k, f in cubes.items() if (f >= c).any() and (f < c).any())
+    return keys, np.array([cubes[k] for k in keys]).reshape(-1, 8)

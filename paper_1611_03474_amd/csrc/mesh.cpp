@@ -576,6 +576,31 @@ bool tri_tri(const double *V0, const double *V1, const double *V2, const double 
 using VidFn = std::function<int64_t(uint64_t)>;
 using KeyFn = std::function<uint64_t(int64_t)>;
 
+// Vertex ids by edge key: the caller's points in ascending key order (ids
+// 0 .. nv-1), then points appended later (edge points of added cubes), found
+// through a map.
+struct VIndex {
+    const std::vector<tms_vertex> *V = nullptr;
+    std::unordered_map<uint64_t, int64_t> id;   // appended points: key -> id
+    std::unordered_map<int64_t, uint64_t> key;  // and id -> key
+    int64_t nv() const { return (int64_t)V->size(); }
+    int64_t find(uint64_t k) const {
+        auto it = std::lower_bound(V->begin(), V->end(), k,
+                                   [](const tms_vertex &a, uint64_t kk) { return a.edge_key < kk; });
+        if (it != V->end() && it->edge_key == k) return (int64_t)(it - V->begin());
+        auto jt = id.find(k);
+        return jt == id.end() ? -1 : jt->second;
+    }
+    uint64_t key_of(int64_t v) const { return v < nv() ? (*V)[(size_t)v].edge_key : key.at(v); }
+    void add(uint64_t k, int64_t v) {
+        id.emplace(k, v);
+        key.emplace(v, k);
+    }
+};
+
+// host copy only: a coarser SURFACE leaf meshed through its finest sub-cubes
+constexpr uint8_t kClsSplit = 0xFE;
+
 uint64_t cube_key(int64_t x, int64_t y, int64_t z) {
     return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
            (uint64_t)(z & 0x1FFFFF);
@@ -749,10 +774,12 @@ void place_vertex(uint64_t key, double t, double px, double py, double pz, doubl
 // the mesh of host copies of the leaves, corner values and vertices; returns
 // a message (empty: success) and the mesh; em receives the ring bits
 std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
-                       const std::vector<tms_vertex> &V, double c, int K, double h0,
-                       tms_mesh **out, std::vector<uint8_t> &em) {
+                       const std::vector<tms_vertex> &V, const std::vector<tms_vertex> &X,
+                       VIndex &VI, double c, int K, double h0, tms_mesh **out,
+                       std::vector<uint8_t> &em) {
     *out = nullptr;
     const int64_t n = (int64_t)L.size(), nv = (int64_t)V.size();
+    VI.V = &V;
     if (n >= (int64_t)0x7FFFFFFF || nv >= (int64_t)0x7FFFFFFF)
         return "too many leaves or vertices for 32-bit indices";
     std::atomic<bool> sorted{true};
@@ -774,7 +801,7 @@ std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double>
                    "(T-junctions) are not meshed";
         }
     M->leaf_ijk.resize((size_t)n * 3);
-    M->xyz.resize((size_t)nv * 3);
+    M->xyz.resize((size_t)(nv + (int64_t)X.size()) * 3);
     parallel_for(n, [&](int64_t b, int64_t e, int) {
         for (int64_t i = b; i < e; ++i) {
             M->leaf_ijk[3 * i] = L[(size_t)i].ix;
@@ -788,20 +815,206 @@ std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double>
             place_vertex(v.edge_key, v.t, v.x, v.y, v.z, h0, &M->xyz[3 * (size_t)k]);
         }
     });
-    // vertex of an edge key: the caller's list is in ascending key order
-    const VidFn vid = [&](uint64_t key) -> int64_t {
-        auto it = std::lower_bound(V.begin(), V.end(), key,
-                                   [](const tms_vertex &a, uint64_t k) { return a.edge_key < k; });
-        return (it != V.end() && it->edge_key == key) ? (int64_t)(it - V.begin()) : -1;
-    };
-    em.assign((size_t)nv, 0);
+    // appended points (edge points of cubes that replace coarser leaves)
+    for (size_t k = 0; k < X.size(); ++k) {
+        const tms_vertex &v = X[k];
+        place_vertex(v.edge_key, v.t, v.x, v.y, v.z, h0, &M->xyz[3 * ((size_t)nv + k)]);
+        VI.add(v.edge_key, nv + (int64_t)k);
+    }
+    const VidFn vid = [&](uint64_t key) { return VI.find(key); };
+    em.assign((size_t)(nv + (int64_t)X.size()), 0);
     if (!triangulate(L, cp, surf, c, K, h0, vid, M, em)) {
         delete M;
         return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
     }
-    M->open_faces = open_faces(em, nullptr, nv, [&](int64_t v) { return V[(size_t)v].edge_key; },
-                               K, nullptr);
+    M->open_faces = open_faces(em, nullptr, (int64_t)em.size(),
+                               [&](int64_t v) { return VI.key_of(v); }, K, nullptr);
     *out = M;
+    return std::string();
+}
+
+// phi of the library (tms_eval_phi, the precision of `cells`) at host points
+// pts [m][3]; on failure *rc and a message
+std::string eval_points(tms_ctx *ctx, const tms_cells *cells, const std::vector<double> &pts,
+                        std::vector<double> &phi, DevBuf &dpts, DevBuf &dphi, int32_t *rc) {
+    const int64_t m = (int64_t)(pts.size() / 3);
+    phi.assign((size_t)m, 0.0);
+    if (m == 0) return std::string();
+    int64_t ng = 0;
+    if (dpts.ensure(sizeof(double) * pts.size()) != hipSuccess ||
+        dphi.ensure(sizeof(double) * (size_t)m) != hipSuccess) {
+        (void)hipGetLastError();
+        *rc = TMS_E_OOM;
+        return "device memory for the corner values of cubes added to the mesh";
+    }
+    if (hipMemcpyAsync(dpts.p, pts.data(), sizeof(double) * pts.size(), hipMemcpyHostToDevice,
+                       ctx->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        *rc = TMS_E_DEVICE;
+        return "copying the corners of cubes added to the mesh to the device";
+    }
+    const int32_t e = tms_eval_phi(ctx, cells, dpts.as<double>(), m, dphi.as<double>(), nullptr,
+                                   &ng);
+    if (e != TMS_OK) {
+        *rc = e;
+        return ctx->err;
+    }
+    if (hipMemcpyAsync(phi.data(), dphi.p, sizeof(double) * (size_t)m, hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        *rc = TMS_E_DEVICE;
+        return "copying the corner values of cubes added to the mesh to the host";
+    }
+    return std::string();
+}
+
+// the edge point of a crossing edge e of the cube (ix, iy, iz) at `level`
+// with corner values f, placed as the extraction places its points
+tms_vertex new_vertex(const Grid &g, int level, int32_t ix, int32_t iy, int32_t iz, int e,
+                      const double f[8]) {
+    const EdgeInfo &E = topo().E[e];
+    const int sh = g.K - level;
+    const double h = std::ldexp(g.h0, -level);
+    const double f0 = f[E.v0], f1 = f[E.v1];
+    tms_vertex x;
+    x.edge_key = edge_key(0, level, g.K, ix, iy, iz, e);
+    x.t = (g.c - f0) / (f1 - f0);
+    const int64_t I[3] = {(int64_t)ix + E.off[0], (int64_t)iy + E.off[1], (int64_t)iz + E.off[2]};
+    double p[3];
+    for (int a = 0; a < 3; ++a) p[a] = g.o[a] + (double)(I[a] << sh) * g.hmin;
+    p[E.axis] += x.t * h;
+    x.x = p[0];
+    x.y = p[1];
+    x.z = p[2];
+    return x;
+}
+
+// Coarser SURFACE leaves (device entry point).  With a loose tolerance a
+// cube can meet the stopping rule (2E <= tau) above the finest level while
+// its corner values straddle c; its faces would meet smaller cubes.  Each
+// such leaf is meshed through the cubes of the finest level inside it whose
+// corner values straddle c, added as SURFACE leaves (reason
+// TMS_REASON_SPLIT): corner values from a SURFACE leaf of the finest level
+// or from the coarse leaf itself wherever they have the same lattice point,
+// else phi of the library; their edge points as the extraction places them
+// (appended to X).  The coarse leaf is marked kClsSplit in the host copy;
+// its own edge points stay in the vertex list, unused.
+std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
+                         std::vector<double> &cp, const std::vector<tms_vertex> &V,
+                         std::vector<tms_vertex> &X, int32_t *rc) {
+    *rc = TMS_OK;
+    const Grid &g = cells->g;
+    const int K = g.K;
+    std::vector<int64_t> coarse;
+    for (int64_t i = 0; i < (int64_t)L.size(); ++i)
+        if (L[(size_t)i].cls == TMS_CLS_SURFACE && L[(size_t)i].level < K) coarse.push_back(i);
+    if (coarse.empty()) return std::string();
+    // lattice points of the finest level with a known value: the coarse
+    // leaves' corners, and the corners of finest SURFACE leaves next to them
+    std::unordered_map<uint64_t, double> val;
+    std::unordered_set<uint64_t> halo;  // finest cubes within one cube of a coarse leaf
+    for (int64_t i : coarse) {
+        const tms_leaf &lf = L[(size_t)i];
+        const int s = K - lf.level;
+        const int64_t n = (int64_t)1 << s;
+        const int64_t b[3] = {(int64_t)lf.ix << s, (int64_t)lf.iy << s, (int64_t)lf.iz << s};
+        for (int v = 0; v < 8; ++v)
+            val[cube_key(b[0] + (v & 1) * n, b[1] + ((v >> 1) & 1) * n, b[2] + ((v >> 2) & 1) * n)] =
+                cp[(size_t)i * 8 + (size_t)v];
+        for (int64_t z = -1; z <= n; ++z)
+            for (int64_t y = -1; y <= n; ++y)
+                for (int64_t x = -1; x <= n; ++x)
+                    if (x < 0 || y < 0 || z < 0 || x == n || y == n || z == n)
+                        halo.insert(cube_key(b[0] + x, b[1] + y, b[2] + z));
+    }
+    {
+        const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+        std::vector<std::vector<int64_t>> part(nth);
+        parallel_for((int64_t)L.size(), [&](int64_t b, int64_t e, int t) {
+            for (int64_t i = b; i < e; ++i) {
+                const tms_leaf &lf = L[(size_t)i];
+                if (lf.cls == TMS_CLS_SURFACE && lf.level == K &&
+                    halo.count(cube_key(lf.ix, lf.iy, lf.iz)))
+                    part[(size_t)t].push_back(i);
+            }
+        });
+        for (auto &pp : part)
+            for (int64_t i : pp) {
+                const tms_leaf &lf = L[(size_t)i];
+                for (int v = 0; v < 8; ++v)
+                    val.emplace(cube_key(lf.ix + (v & 1), lf.iy + ((v >> 1) & 1), lf.iz + ((v >> 2) & 1)),
+                                cp[(size_t)i * 8 + (size_t)v]);
+            }
+    }
+    // every other lattice point inside the coarse leaves: phi
+    std::vector<uint64_t> need;
+    std::vector<double> pts;
+    for (int64_t i : coarse) {
+        const tms_leaf &lf = L[(size_t)i];
+        const int s = K - lf.level;
+        const int64_t n = (int64_t)1 << s;
+        const int64_t b[3] = {(int64_t)lf.ix << s, (int64_t)lf.iy << s, (int64_t)lf.iz << s};
+        for (int64_t z = 0; z <= n; ++z)
+            for (int64_t y = 0; y <= n; ++y)
+                for (int64_t x = 0; x <= n; ++x) {
+                    const uint64_t k = cube_key(b[0] + x, b[1] + y, b[2] + z);
+                    if (val.count(k)) continue;
+                    val.emplace(k, 0.0);
+                    need.push_back(k);
+                    pts.push_back(g.o[0] + (double)(b[0] + x) * g.hmin);
+                    pts.push_back(g.o[1] + (double)(b[1] + y) * g.hmin);
+                    pts.push_back(g.o[2] + (double)(b[2] + z) * g.hmin);
+                }
+    }
+    DevBuf dpts, dphi;
+    std::vector<double> phi;
+    const std::string why = eval_points(ctx, cells, pts, phi, dpts, dphi, rc);
+    if (*rc != TMS_OK) return why;
+    for (size_t k = 0; k < need.size(); ++k) val[need[k]] = phi[k];
+    // the straddling cubes of the finest level inside each coarse leaf
+    const Topo &T = topo();
+    std::unordered_set<uint64_t> seen;
+    for (int64_t i : coarse) {
+        const tms_leaf lc = L[(size_t)i];
+        L[(size_t)i].cls = kClsSplit;
+        const int s = K - lc.level;
+        const int64_t n = (int64_t)1 << s;
+        const int64_t b[3] = {(int64_t)lc.ix << s, (int64_t)lc.iy << s, (int64_t)lc.iz << s};
+        for (int64_t z = 0; z < n; ++z)
+            for (int64_t y = 0; y < n; ++y)
+                for (int64_t x = 0; x < n; ++x) {
+                    double f[8];
+                    unsigned mask = 0;
+                    for (int v = 0; v < 8; ++v) {
+                        f[v] = val.at(cube_key(b[0] + x + (v & 1), b[1] + y + ((v >> 1) & 1),
+                                               b[2] + z + ((v >> 2) & 1)));
+                        if (f[v] >= g.c) mask |= 1u << v;
+                    }
+                    if (mask == 0 || mask == 0xFF) continue;
+                    tms_leaf lf{};
+                    lf.ix = (int32_t)(b[0] + x);
+                    lf.iy = (int32_t)(b[1] + y);
+                    lf.iz = (int32_t)(b[2] + z);
+                    lf.conf = 0;
+                    lf.level = (uint8_t)K;
+                    lf.reason = TMS_REASON_SPLIT;
+                    lf.mask = (uint8_t)mask;
+                    lf.cls = TMS_CLS_SURFACE;
+                    L.push_back(lf);
+                    cp.insert(cp.end(), f, f + 8);
+                    for (int e = 0; e < 12; ++e) {
+                        if ((f[T.E[e].v0] >= g.c) == (f[T.E[e].v1] >= g.c)) continue;
+                        const uint64_t key = edge_key(0, K, K, lf.ix, lf.iy, lf.iz, e);
+                        auto it = std::lower_bound(
+                            V.begin(), V.end(), key,
+                            [](const tms_vertex &a, uint64_t kk) { return a.edge_key < kk; });
+                        if ((it != V.end() && it->edge_key == key) || !seen.insert(key).second)
+                            continue;
+                        X.push_back(new_vertex(g, K, lf.ix, lf.iy, lf.iz, e, f));
+                    }
+                }
+    }
     return std::string();
 }
 
@@ -820,28 +1033,16 @@ std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double>
 constexpr int kCloseRounds = 64;
 
 std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
-                       std::vector<double> &cp, const std::vector<tms_vertex> &V,
-                       std::vector<uint8_t> &em, tms_mesh *M, int32_t *rc) {
+                       std::vector<double> &cp, VIndex &VI, std::vector<uint8_t> &em,
+                       tms_mesh *M, int32_t *rc) {
     *rc = TMS_OK;
     const Grid &g = cells->g;
     const int level = M->level, sh = g.K - level;
-    const double h = std::ldexp(g.h0, -level);
-    const int64_t n0 = (int64_t)L.size(), nv = (int64_t)V.size();
     const Topo &T = topo();
-    std::unordered_map<uint64_t, int64_t> nmap;   // key -> id of added edge points
-    std::unordered_map<int64_t, uint64_t> nkey;   // and back
-    const VidFn vid = [&](uint64_t key) -> int64_t {
-        auto it = std::lower_bound(V.begin(), V.end(), key,
-                                   [](const tms_vertex &a, uint64_t k) { return a.edge_key < k; });
-        if (it != V.end() && it->edge_key == key) return (int64_t)(it - V.begin());
-        auto jt = nmap.find(key);
-        return jt == nmap.end() ? -1 : jt->second;
-    };
-    const KeyFn key_of = [&](int64_t v) -> uint64_t {
-        return v < nv ? V[(size_t)v].edge_key : nkey.at(v);
-    };
+    const VidFn vid = [&](uint64_t key) { return VI.find(key); };
+    const KeyFn key_of = [&](int64_t v) { return VI.key_of(v); };
     std::vector<std::array<int32_t, 3>> q;
-    open_faces(em, nullptr, nv, key_of, g.K, &q);
+    open_faces(em, nullptr, (int64_t)em.size(), key_of, g.K, &q);
     DevBuf dpts, dphi;
     for (int r = 0; r < kCloseRounds; ++r) {
         q.erase(std::remove_if(q.begin(), q.end(),
@@ -905,35 +1106,10 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_lea
                         pts.push_back(g.o[a] + (double)(P[a] << sh) * g.hmin);
                 slot[k * 8 + v] = ins.first->second;
             }
-        const int64_t m = (int64_t)(pts.size() / 3);
-        if (m > 0) {
-            std::vector<double> phi((size_t)m);
-            int64_t ng = 0;
-            if (dpts.ensure(sizeof(double) * pts.size()) != hipSuccess ||
-                dphi.ensure(sizeof(double) * (size_t)m) != hipSuccess) {
-                (void)hipGetLastError();
-                *rc = TMS_E_OOM;
-                return "device memory for the corner values of cubes added across open faces";
-            }
-            if (hipMemcpyAsync(dpts.p, pts.data(), sizeof(double) * pts.size(),
-                               hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
-                (void)hipGetLastError();
-                *rc = TMS_E_DEVICE;
-                return "copying the corners of cubes added across open faces to the device";
-            }
-            const int32_t e = tms_eval_phi(ctx, cells, dpts.as<double>(), m, dphi.as<double>(),
-                                           nullptr, &ng);
-            if (e != TMS_OK) {
-                *rc = e;
-                return ctx->err;
-            }
-            if (hipMemcpyAsync(phi.data(), dphi.p, sizeof(double) * (size_t)m,
-                               hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-                hipStreamSynchronize(ctx->stream) != hipSuccess) {
-                (void)hipGetLastError();
-                *rc = TMS_E_DEVICE;
-                return "copying the corner values of cubes added across open faces to the host";
-            }
+        {
+            std::vector<double> phi;
+            const std::string why = eval_points(ctx, cells, pts, phi, dpts, dphi, rc);
+            if (*rc != TMS_OK) return why;
             for (size_t k = 0; k < nq * 8; ++k)
                 if (slot[k] >= 0) f[k] = phi[(size_t)slot[k]];
         }
@@ -965,14 +1141,10 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_lea
                 int64_t id = vid(key);
                 if (id < 0) {
                     id = (int64_t)(M->xyz.size() / 3);
-                    nmap.emplace(key, id);
-                    nkey.emplace(id, key);
-                    const double t = (g.c - f0) / (f1 - f0);
-                    const int64_t I[3] = {lf.ix + E.off[0], lf.iy + E.off[1], lf.iz + E.off[2]};
-                    double p[3], x[3];
-                    for (int a = 0; a < 3; ++a) p[a] = g.o[a] + (double)(I[a] << sh) * g.hmin;
-                    p[E.axis] += t * h;
-                    place_vertex(key, t, p[0], p[1], p[2], g.h0, x);
+                    VI.add(key, id);
+                    const tms_vertex nvx = new_vertex(g, level, lf.ix, lf.iy, lf.iz, ed, &f[k * 8]);
+                    double x[3];
+                    place_vertex(key, nvx.t, nvx.x, nvx.y, nvx.z, g.h0, x);
                     M->xyz.insert(M->xyz.end(), x, x + 3);
                     em.push_back(0);
                 }
@@ -987,8 +1159,6 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_lea
         touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
         open_faces(em, &touched, 0, key_of, g.K, &q);
     }
-    M->added.assign(L.begin() + n0, L.end());
-    M->added_phi.assign(cp.begin() + 8 * n0, cp.end());
     M->open_faces = open_faces(em, nullptr, (int64_t)em.size(), key_of, g.K, nullptr);
     return std::string();
 }
@@ -1031,18 +1201,29 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
         (void)hipGetLastError();
         return mfail(ctx, TMS_E_DEVICE, "copying leaves, corner values or vertices to the host");
     }
+    // SURFACE leaves above the finest level are meshed through their finest
+    // sub-cubes; then the mesh, then the cubes across open faces
+    std::vector<tms_vertex> X;
+    {
+        int32_t rc = TMS_OK;
+        const std::string w = split_coarse(ctx, cells, L, cp, V, X, &rc);
+        if (rc != TMS_OK) return mfail(ctx, rc, w.c_str());
+    }
     std::vector<uint8_t> em;
-    const std::string why = build_mesh(L, cp, V, g.c, g.K, g.h0, out, em);
+    VIndex VI;
+    const std::string why = build_mesh(L, cp, V, X, VI, g.c, g.K, g.h0, out, em);
     if (!why.empty()) return mfail(ctx, TMS_E_INVALID, why.c_str());
     if ((flags & TMS_MESH_CLOSE) && (*out)->open_faces > 0) {
         int32_t rc = TMS_OK;
-        const std::string w = close_mesh(ctx, cells, L, cp, V, em, *out, &rc);
+        const std::string w = close_mesh(ctx, cells, L, cp, VI, em, *out, &rc);
         if (rc != TMS_OK) {
             delete *out;
             *out = nullptr;
             return mfail(ctx, rc, w.c_str());
         }
     }
+    (*out)->added.assign(L.begin() + n, L.end());
+    (*out)->added_phi.assign(cp.begin() + 8 * n, cp.end());
     return TMS_OK;
 }
 
@@ -1059,7 +1240,8 @@ int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *cor
     std::vector<double> cp(corner_phi, corner_phi + 8 * n);
     std::vector<tms_vertex> V(verts, verts + nv);
     std::vector<uint8_t> em;
-    const std::string why = build_mesh(L, cp, V, c, K, h0, out, em);
+    VIndex VI;
+    const std::string why = build_mesh(L, cp, V, std::vector<tms_vertex>(), VI, c, K, h0, out, em);
     if (!why.empty()) {
         set_msg(msg, msg_len, why);
         return TMS_E_INVALID;

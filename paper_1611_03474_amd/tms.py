@@ -20,7 +20,7 @@ TMS_OK, TMS_E_INVALID, TMS_E_CAPACITY, TMS_E_DEVICE, TMS_E_OOM = 0, -1, -2, -3, 
 PREC_FP64, PREC_FP32_GUARD = 0, 1
 MODE_ADAPTIVE, MODE_UNIFORM = 0, 1
 CHILD_PROJECT, CHILD_REEXPAND = 0, 1
-REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN, REASON_CLOSED = 0, 1, 2, 3
+REASON_UNIFORM, REASON_CONVERGED, REASON_HMIN, REASON_CLOSED, REASON_SPLIT = 0, 1, 2, 3, 4
 MESH_CLOSE = 1
 CLS_OUTSIDE, CLS_SURFACE, CLS_INSIDE = 0, 1, 2
 MAX_LEVELS = 8

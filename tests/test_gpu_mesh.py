@@ -15,6 +15,11 @@ without closing open faces, against the oracle.
   globule and the 110,000-atom assembly in FP32+guard close into manifolds
   with no defect of (a), (b) or (c); the added cubes' corner values are the
   oracle's phi (1e-5 relative, the FP32+guard bar).
+* SURFACE leaves of two levels (loose tolerances): the finest cubes that
+  replace the coarser leaves, and the closing cubes after them, equal the
+  oracle's; the mesh has no defect.
+* Vertex density scales as 1 / h_min^2 (about 1.5 per square angstrom at
+  h_min = 1).
 """
 import numpy as np
 import pytest
@@ -205,3 +210,64 @@ def test_vertex_density_follows_h_min(ctx):
     assert 1.0 < dens[1.0] < 2.0
     for a, b in ((1.0, 0.5), (0.5, 0.25)):
         assert 3.0 < dens[b] / dens[a] < 5.0
+
+
+SPLIT_CASES = {
+    # loose tolerances stop some straddling cubes above the finest level
+    "globule600_D0.5_tau0.1": (synth.globule(600, 1011), 0.5, 0.1),
+    "globule600_D0.9_tau0.3": (synth.globule(600, 1012), 0.9, 0.3),
+}
+
+
+@pytest.mark.parametrize("name", list(SPLIT_CASES))
+def test_mixed_levels_fp64(ctx, name):
+    # SURFACE leaves of two levels: the library meshes the coarser ones
+    # through their straddling cubes of the finest level; those cubes, and
+    # then the cubes added across open faces, equal the oracle's (from its
+    # own partition and phi), and the mesh has no defect
+    atoms, D, tau = SPLIT_CASES[name]
+    c, h0 = 1.0, 2.0
+    print("case", name, flush=True)
+    p = tms.make_params(D=D, tau=tau, precision=tms.PREC_FP64)
+    cells = ctx.build_cells(atoms, p)
+    try:
+        leaves, cphi, _ = ctx.partition_estimate(cells)
+        verts = ctx.extract(cells, leaves, cphi)
+        m = ctx.mesh_build(cells, leaves, cphi, verts, close=True)
+        V = tms.vertices_to_numpy(verts)
+    finally:
+        ctx.free_cells(cells)
+    r = oracle.partition(atoms, D, c=c, tau=tau, h0=h0, h_min=0.25)
+    assert r.tie_cube == 0 and r.tie_corner == 0
+    K = r.K
+    surf = r.cls == oracle.CLS_SURFACE
+    assert (r.level[surf] < K).any()
+    h = h0 / (1 << K)
+
+    def phi_at(P):
+        return oracle.phi(atoms, D, r.origin + P * h)
+
+    sk, sv = om.straddling(om.split_coarse(r.ijk, r.level, r.corner_phi, surf, K, phi_at), c)
+    a = m.added
+    ijk = np.stack([a["ix"], a["iy"], a["iz"]], 1)
+    sp = a["reason"] == tms.REASON_SPLIT
+    got = sorted(map(tuple, ijk[sp].tolist()))
+    print("split cubes: library %d, oracle %d" % (len(got), len(sk)))
+    assert got == sk
+    o = np.lexsort((ijk[sp, 2], ijk[sp, 1], ijk[sp, 0]))
+    assert np.max(np.abs(m.added_phi[sp][o] - sv) / np.abs(sv)) < 1e-12
+    # closing over the finest SURFACE leaves and the split cubes
+    fine = surf & (r.level == K)
+    keys, _ = om.close_open_faces(np.vstack([r.ijk[fine], np.array(sk)]),
+                                  np.vstack([r.corner_phi[fine], sv]),
+                                  np.ones(int(fine.sum()) + len(sk), bool), c,
+                                  tuple(int(d) << K for d in r.dims), phi_at)
+    cl = a["reason"] == tms.REASON_CLOSED
+    assert sorted(map(tuple, ijk[cl].tolist())) == keys
+    rep = m.check(intersections=True)
+    print(rep)
+    assert rep["open_faces"] == 0 and rep["boundary_edges"] == 0
+    assert rep["nonmanifold_edges"] == rep["misoriented_edges"] == 0
+    assert rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    # the coarse leaves' own edge points are the only unused vertices
+    assert rep["unused_vertices"] == int((((V["edge_key"] >> 50) & 7) < K).sum())

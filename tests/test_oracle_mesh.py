@@ -167,3 +167,48 @@ def test_closure_restores_dropped_surface_cubes():
     added, _ = om.close_open_faces(np.array(cubes), np.array(vals), np.ones(len(cubes), bool),
                                    c, (n, n, n), lambda P: f[P[:, 0], P[:, 1], P[:, 2]])
     assert added == []
+
+
+def test_split_coarse_equals_direct_enumeration():
+    # a sampled field on the finest lattice; leaves of level K - 1 (2x2x2
+    # blocks) and K - 2 (4x4x4) taken over parts of it: the cubes that
+    # replace the coarse SURFACE leaves are exactly the straddling finest
+    # cubes inside them, with the sampled values
+    n, h, c, K = 16, 0.5, 1.0, 3
+    X = np.stack(np.meshgrid(*[np.arange(n + 1) * h - 4.0] * 3, indexing="ij"), -1)
+    f = np.exp(-((X - [0.3, 0.1, -0.2]) ** 2).sum(-1) + 4.0)
+    ijk, level, cp = [], [], []
+    for q in np.ndindex(n // 4, n // 4, n // 4):  # level K - 2 blocks over x < n/2
+        if q[0] >= n // 8:
+            continue
+        b = np.array(q) * 4
+        ijk.append(q); level.append(K - 2)
+        cp.append([f[b[0] + 4 * (v & 1), b[1] + 4 * ((v >> 1) & 1), b[2] + 4 * ((v >> 2) & 1)]
+                   for v in range(8)])
+    for q in np.ndindex(n // 2, n // 2, n // 2):  # level K - 1 blocks over x >= n/2
+        if q[0] < n // 4:
+            continue
+        b = np.array(q) * 2
+        ijk.append(q); level.append(K - 1)
+        cp.append([f[b[0] + 2 * (v & 1), b[1] + 2 * ((v >> 1) & 1), b[2] + 2 * ((v >> 2) & 1)]
+                   for v in range(8)])
+    ijk, level, cp = np.array(ijk), np.array(level), np.array(cp)
+    surf = (cp >= c).any(1) & (cp < c).any(1)
+    cubes = om.split_coarse(ijk, level, cp, surf, K, lambda P: f[P[:, 0], P[:, 1], P[:, 2]])
+    got, vals = om.straddling(cubes, c)
+    want = []
+    for q, l, s in zip(ijk, level, surf):
+        if not s:
+            continue
+        sh = K - int(l)
+        for d in np.ndindex(1 << sh, 1 << sh, 1 << sh):
+            p = (int(q[0] << sh) + d[0], int(q[1] << sh) + d[1], int(q[2] << sh) + d[2])
+            v = np.array([f[p[0] + (k & 1), p[1] + ((k >> 1) & 1), p[2] + ((k >> 2) & 1)]
+                          for k in range(8)])
+            if (v >= c).any() and (v < c).any():
+                want.append(p)
+    assert surf.sum() > 10 and len(want) > 50
+    assert got == sorted(want)
+    for p, v in zip(got, vals):
+        assert np.array_equal(v, [f[p[0] + (k & 1), p[1] + ((k >> 1) & 1), p[2] + ((k >> 2) & 1)]
+                                  for k in range(8)])
