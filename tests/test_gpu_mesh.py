@@ -271,3 +271,22 @@ def test_mixed_levels_fp64(ctx, name):
     assert rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
     # the coarse leaves' own edge points are the only unused vertices
     assert rep["unused_vertices"] == int((((V["edge_key"] >> 50) & 7) < K).sum())
+
+
+def test_empty_partition_and_bad_flags(ctx):
+    # no atoms: no leaves, an empty mesh; unknown flags are refused
+    p = tms.make_params(precision=tms.PREC_FP64)
+    cells = ctx.build_cells(np.zeros((0, 4)), p)
+    try:
+        leaves, cphi, _ = ctx.partition_estimate(cells)
+        verts = ctx.extract(cells, leaves, cphi)
+        assert leaves.shape[0] == 0 and verts.shape[0] == 0
+        m = ctx.mesh_build(cells, leaves, cphi, verts)
+        rep = m.check()
+        assert rep["n_triangles"] == rep["n_vertices"] == 0 and len(m.added) == 0
+        import ctypes as C
+        h = C.c_void_p()
+        rc = ctx.lib.tms_mesh_build(ctx.h, cells.handle, None, 0, None, None, 0, 2, C.byref(h))
+        assert rc == tms.TMS_E_INVALID
+    finally:
+        ctx.free_cells(cells)

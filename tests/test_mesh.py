@@ -226,3 +226,28 @@ def test_loop_crossing_a_face_twice():
              if on[t[a]] and on[t[(a + 1) % 3]]}
     assert len(sides) == 2
     assert not any(on[t].all() for t in m.tri)
+
+
+def test_empty_and_invalid_inputs(tmp_path):
+    # no leaves: an empty mesh whose checks are all zero
+    m = tms.mesh_build_host(np.zeros(0, dtype=tms.LEAF_DTYPE), np.zeros((0, 8)),
+                            np.zeros(0, dtype=tms.VERTEX_DTYPE), 1.0, 3, 2.0)
+    rep = m.check()
+    assert rep["n_vertices"] == rep["n_triangles"] == rep["open_faces"] == 0
+    assert rep["boundary_edges"] == rep["nonmanifold_vertices"] == rep["intersecting_pairs"] == 0
+    assert rep["components"] == rep["euler"] == 0 and rep["area"] == 0.0
+    m.write_off(str(tmp_path / "e.off"))
+    assert (tmp_path / "e.off").read_text().split("\n")[:2] == ["OFF", "0 0 0"]
+    # vertices out of key order, and an edge point missing: refused
+    r = oracle.partition(np.array([[0.3, -0.2, 0.1, 1.7]]), 0.9, tau=1e-3)
+    L, V = _leaves(r), _verts(r)
+    with pytest.raises(tms.TmsError) as ei:
+        tms.mesh_build_host(L, r.corner_phi, V[::-1].copy(), 1.0, r.K, 2.0)
+    assert ei.value.code == tms.TMS_E_INVALID and "order" in str(ei.value)
+    with pytest.raises(tms.TmsError) as ei:
+        tms.mesh_build_host(L, r.corner_phi, np.delete(V, len(V) // 2), 1.0, r.K, 2.0)
+    assert ei.value.code == tms.TMS_E_INVALID and "missing" in str(ei.value)
+    # bad isovalue, level or root edge
+    for c, K, h0 in ((0.0, r.K, 2.0), (1.0, -1, 2.0), (1.0, r.K, 0.0)):
+        with pytest.raises(tms.TmsError):
+            tms.mesh_build_host(L, r.corner_phi, V, c, K, h0)
