@@ -152,6 +152,7 @@ const Topo &topo() {
 }
 
 // ---- one leaf ---------------------------------------------------------------
+constexpr int kLoopMax = 12;  // a loop visits each of the cube's edges at most once
 struct LeafOut {
     // corners: cube edge indices 0..11, or 12 + k for the k-th interior point
     std::vector<std::array<int, 3>> tri;
@@ -279,50 +280,47 @@ bool seg_meet(const double a[2], const double b[2], const double c[2], const dou
 // own triangles (a loop that crosses a face twice, through both branches of
 // its hyperbola, would otherwise be capped in the face from both sides).
 // Returns false if the polygon is not simple or has no ear left.
-bool ear_clip(const std::vector<std::array<double, 2>> &Q, const std::vector<unsigned> &fm,
-              std::vector<std::array<int, 3>> &out) {
-    const int m = (int)Q.size();
+bool ear_clip(const double (*Q)[2], int m, const unsigned *fm, std::array<int, 3> *out,
+              int *nout) {
+    *nout = 0;
     // simple: non-adjacent sides do not meet, no repeated point
     for (int i = 0; i < m; ++i)
         for (int j = i + 1; j < m; ++j) {
             if (Q[i][0] == Q[j][0] && Q[i][1] == Q[j][1]) return false;
             if (j == i + 1 || (i == 0 && j == m - 1)) continue;
-            if (seg_meet(Q[i].data(), Q[(i + 1) % m].data(), Q[j].data(), Q[(j + 1) % m].data()))
-                return false;
+            if (seg_meet(Q[i], Q[(i + 1) % m], Q[j], Q[(j + 1) % m])) return false;
         }
     double area = 0.0;
-    for (int i = 0; i < m; ++i)
-        area += Q[i][0] * Q[(i + 1) % m][1] - Q[(i + 1) % m][0] * Q[i][1];
+    for (int i = 0; i < m; ++i) area += Q[i][0] * Q[(i + 1) % m][1] - Q[(i + 1) % m][0] * Q[i][1];
     if (area == 0.0) return false;
     const double sg = area > 0 ? 1.0 : -1.0;
-    std::vector<int> idx(m);
-    std::iota(idx.begin(), idx.end(), 0);
-    while (idx.size() > 3) {
-        const int k = (int)idx.size();
+    int idx[kLoopMax], k = m;
+    for (int i = 0; i < m; ++i) idx[i] = i;
+    while (k > 3) {
         bool found = false;
         for (int i = 0; i < k && !found; ++i) {
             const int ia = idx[(i + k - 1) % k], ib = idx[i], ic = idx[(i + 1) % k];
-            if (fm[(size_t)ia] & fm[(size_t)ic]) continue;
-            const double cr = cross2(Q[ia].data(), Q[ib].data(), Q[ic].data()) * sg;
+            if (fm[ia] & fm[ic]) continue;
+            const double cr = cross2(Q[ia], Q[ib], Q[ic]) * sg;
             if (!(cr > 0.0)) continue;
             bool inside = false;
             for (int j = 0; j < k && !inside; ++j) {
                 const int ij = idx[j];
                 if (ij == ia || ij == ib || ij == ic) continue;
-                const double *p = Q[ij].data();
-                const double c1 = cross2(Q[ia].data(), Q[ib].data(), p) * sg,
-                             c2 = cross2(Q[ib].data(), Q[ic].data(), p) * sg,
-                             c3 = cross2(Q[ic].data(), Q[ia].data(), p) * sg;
+                const double c1 = cross2(Q[ia], Q[ib], Q[ij]) * sg,
+                             c2 = cross2(Q[ib], Q[ic], Q[ij]) * sg,
+                             c3 = cross2(Q[ic], Q[ia], Q[ij]) * sg;
                 if (c1 >= 0 && c2 >= 0 && c3 >= 0) inside = true;
             }
             if (inside) continue;
-            out.push_back({ia, ib, ic});
-            idx.erase(idx.begin() + i);
+            out[(*nout)++] = {ia, ib, ic};
+            for (int j = i; j + 1 < k; ++j) idx[j] = idx[j + 1];
+            --k;
             found = true;
         }
         if (!found) return false;
     }
-    out.push_back({idx[0], idx[1], idx[2]});
+    out[(*nout)++] = {idx[0], idx[1], idx[2]};
     return true;
 }
 
@@ -334,30 +332,29 @@ void leaf_triangles(const double f[8], double c, LeafOut &L) {
     for (int e0 = 0; e0 < 12; ++e0) {
         if (used[e0] || partner[e0][0] < 0) continue;
         // walk the loop through e0
-        std::vector<int> loop;
+        int loop[kLoopMax], m = 0;
         int prev = -1, cur = e0;
         while (true) {
-            loop.push_back(cur);
+            loop[m++] = cur;
             used[cur] = true;
             const int nx = (partner[cur][0] != prev) ? partner[cur][0] : partner[cur][1];
             prev = cur;
             cur = nx;
-            if (cur == e0 || cur < 0 || loop.size() > 12) break;
+            if (cur == e0 || cur < 0 || m == kLoopMax) break;
         }
-        if (cur != e0 || loop.size() < 3) continue;  // not closed (cannot happen)
+        if (cur != e0 || m < 3) continue;  // not closed (cannot happen)
         ++L.loops;
-        const int m = (int)loop.size();
-        std::vector<std::array<double, 3>> P(m);
-        std::vector<unsigned> fm(m);
+        double P[kLoopMax + 1][3];  // the loop's points, then an interior point
+        unsigned fm[kLoopMax];
         for (int i = 0; i < m; ++i) {
-            edge_point(f, c, loop[i], P[i].data());
-            fm[(size_t)i] = (1u << T.edge_face[loop[i]][0]) | (1u << T.edge_face[loop[i]][1]);
+            edge_point(f, c, loop[i], P[i]);
+            fm[i] = (1u << T.edge_face[loop[i]][0]) | (1u << T.edge_face[loop[i]][1]);
         }
         // vector area of the loop and the outward direction -grad g at its
         // centroid decide the orientation
         double A[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
         for (int i = 0; i < m; ++i) {
-            const double *p = P[i].data(), *q = P[(i + 1) % m].data();
+            const double *p = P[i], *q = P[(i + 1) % m];
             A[0] += 0.5 * (p[1] * q[2] - p[2] * q[1]);
             A[1] += 0.5 * (p[2] * q[0] - p[0] * q[2]);
             A[2] += 0.5 * (p[0] * q[1] - p[1] * q[0]);
@@ -365,36 +362,40 @@ void leaf_triangles(const double f[8], double c, LeafOut &L) {
         }
         int order[3] = {0, 1, 2};
         std::sort(order, order + 3, [&](int x, int y) { return std::fabs(A[x]) > std::fabs(A[y]); });
-        std::vector<std::array<int, 3>> tl;
+        std::array<int, 3> tl[kLoopMax];
+        int ntl = 0;
         bool ok = false;
         for (int oi = 0; oi < 3 && !ok; ++oi) {
             const int a = order[oi], b = (a + 1) % 3, cc = (a + 2) % 3;
-            std::vector<std::array<double, 2>> Q(m);
-            for (int i = 0; i < m; ++i) Q[i] = {P[i][b], P[i][cc]};
-            tl.clear();
-            ok = ear_clip(Q, fm, tl);
+            double Q[kLoopMax][2];
+            for (int i = 0; i < m; ++i) {
+                Q[i][0] = P[i][b];
+                Q[i][1] = P[i][cc];
+            }
+            ok = ear_clip(Q, m, fm, tl, &ntl);
         }
         int inner = -1;
         if (!ok) {
             // single valued along no axis (folds along all three): a fan
             // from a point of the patch inside the cube, the loop's centroid
             // moved onto g = c (else from the loop's first point)
-            tl.clear();
+            ntl = 0;
             double u[3] = {ctr[0], ctr[1], ctr[2]};
             if (onto_surface(f, c, u)) {
                 inner = (int)L.inner.size();
                 L.inner.push_back({u[0], u[1], u[2]});
-                P.push_back({u[0], u[1], u[2]});
-                for (int i = 0; i < m; ++i) tl.push_back({m, i, (i + 1) % m});
+                for (int a = 0; a < 3; ++a) P[m][a] = u[a];
+                for (int i = 0; i < m; ++i) tl[ntl++] = {m, i, (i + 1) % m};
             } else {
-                for (int i = 1; i + 1 < m; ++i) tl.push_back({0, i, i + 1});
+                for (int i = 1; i + 1 < m; ++i) tl[ntl++] = {0, i, i + 1};
             }
             ++L.fallback;
         }
         // orientation: sum over the triangles of n . (-grad g) at their centroids
         double score = 0.0;
-        for (const auto &t : tl) {
-            const double *p = P[t[0]].data(), *q = P[t[1]].data(), *r = P[t[2]].data();
+        for (int k = 0; k < ntl; ++k) {
+            const auto &t = tl[k];
+            const double *p = P[t[0]], *q = P[t[1]], *r = P[t[2]];
             const double u1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
             const double u2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
             const double n[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
@@ -407,7 +408,8 @@ void leaf_triangles(const double f[8], double c, LeafOut &L) {
         }
         const bool flip = score < 0.0;
         auto id = [&](int k) { return k < m ? loop[k] : 12 + inner; };
-        for (const auto &t : tl) {
+        for (int k = 0; k < ntl; ++k) {
+            const auto &t = tl[k];
             if (flip) L.tri.push_back({id(t[0]), id(t[2]), id(t[1])});
             else L.tri.push_back({id(t[0]), id(t[1]), id(t[2])});
         }
