@@ -175,7 +175,8 @@ def run_mode(ctx, tms, atoms_dev, w, precision, steps, warmup, with_mesh=False):
                                        "open_faces", "added_cubes", "boundary_edges",
                                        "nonmanifold_edges", "misoriented_edges",
                                        "nonmanifold_vertices", "components", "euler",
-                                       "unused_vertices", "area", "volume", "density")}}
+                                       "unused_vertices", "area", "volume", "density",
+                                       "min_angle", "small_angles", "zero_area")}}
         del m
     ctx.free_cells(cells)
     return dict(ms_per_step=spread(step_ms)["mean"], step_ms=spread(step_ms), stats=sd,

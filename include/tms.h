@@ -503,7 +503,11 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  *   triangles of the same or touching leaves; skipped, reported -1, when
  *   intersections = 0).  Non-manifold vertices are those failing (a) or (b).
  *   Also connected components, Euler characteristic V - E + F, area, enclosed
- *   volume and vertices per unit area.
+ *   volume, vertices per unit area, and the uniformness of the triangles
+ *   (Section 1 lists sharp angles and zero-area elements among the defects
+ *   of a mesh): the smallest angle, the triangles with an angle below 5
+ *   degrees, and those whose area is at most 1e-12 of their longest side
+ *   squared.
  * tms_mesh_write_off: the mesh as an OFF file. */
 #define TMS_MESH_CLOSE 1
 typedef struct tms_mesh tms_mesh;
@@ -517,6 +521,9 @@ typedef struct {
     int64_t intersecting_pairs;   /* (c), or -1 when not tested           */
     int64_t components, euler, unused_vertices;
     double area, volume, density; /* A^2, A^3, vertices per A^2           */
+    double min_angle;             /* smallest triangle angle, degrees      */
+    int64_t small_angles;         /* triangles with an angle below 5 deg   */
+    int64_t zero_area;            /* triangles of area <= 1e-12 side^2     */
 } tms_mesh_report;
 
 int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *leaves, int64_t n,

@@ -1409,28 +1409,51 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
         r->euler = nvu - nedges + nt;
         r->unused_vertices = nv - nvu;
     }
-    // area, enclosed volume (outward orientation gives a positive volume)
-    std::vector<std::array<double, 2>> av(nth, {0.0, 0.0});
+    // area, enclosed volume (outward orientation gives a positive volume),
+    // angles and degenerate triangles
+    struct Acc {
+        double area = 0.0, vol = 0.0, amin = 180.0;
+        int64_t small = 0, zero = 0;
+    };
+    std::vector<Acc> av(nth);
     parallel_for(nt, [&](int64_t b, int64_t e, int th) {
-        double area = 0.0, vol = 0.0;
+        Acc a;
         for (int64_t t = b; t < e; ++t) {
-            const double *p = X + 3 * T[3 * t], *q = X + 3 * T[3 * t + 1],
-                         *s = X + 3 * T[3 * t + 2];
+            const double *P[3] = {X + 3 * T[3 * t], X + 3 * T[3 * t + 1], X + 3 * T[3 * t + 2]};
             double u[3], w[3], n[3];
-            sub3(q, p, u);
-            sub3(s, p, w);
+            sub3(P[1], P[0], u);
+            sub3(P[2], P[0], w);
             crs3(u, w, n);
-            area += 0.5 * std::sqrt(dot3(n, n));
+            const double n2 = std::sqrt(dot3(n, n));
+            a.area += 0.5 * n2;
             double qs[3];
-            crs3(q, s, qs);
-            vol += dot3(p, qs) / 6.0;
+            crs3(P[1], P[2], qs);
+            a.vol += dot3(P[0], qs) / 6.0;
+            // the angle at each corner: atan2(|x y|, x . y) of its two sides
+            double tmin = 180.0, side2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double x[3], y[3], xy[3];
+                sub3(P[(k + 1) % 3], P[k], x);
+                sub3(P[(k + 2) % 3], P[k], y);
+                crs3(x, y, xy);
+                side2 = std::max(side2, dot3(x, x));
+                tmin = std::min(tmin, std::atan2(std::sqrt(dot3(xy, xy)), dot3(x, y)) *
+                                          (180.0 / 3.14159265358979323846));
+            }
+            a.amin = std::min(a.amin, tmin);
+            if (tmin < 5.0) ++a.small;
+            if (0.5 * n2 <= 1e-12 * side2) ++a.zero;
         }
-        av[(size_t)th] = {area, vol};
+        av[(size_t)th] = a;
     });
     double area = 0.0, vol = 0.0;
+    r->min_angle = nt > 0 ? 180.0 : 0.0;
     for (const auto &x : av) {
-        area += x[0];
-        vol += x[1];
+        area += x.area;
+        vol += x.vol;
+        r->min_angle = std::min(r->min_angle, x.amin);
+        r->small_angles += x.small;
+        r->zero_area += x.zero;
     }
     r->area = area;
     r->volume = vol;

@@ -50,7 +50,8 @@ class MeshReport(C.Structure):
         "boundary_edges",
         "nonmanifold_edges", "misoriented_edges", "nonmanifold_vertices", "intersecting_pairs",
         "components", "euler", "unused_vertices")] + [
-        ("area", C.c_double), ("volume", C.c_double), ("density", C.c_double)]
+        ("area", C.c_double), ("volume", C.c_double), ("density", C.c_double),
+        ("min_angle", C.c_double), ("small_angles", C.c_int64), ("zero_area", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

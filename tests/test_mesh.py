@@ -251,3 +251,25 @@ def test_empty_and_invalid_inputs(tmp_path):
     for c, K, h0 in ((0.0, r.K, 2.0), (1.0, -1, 2.0), (1.0, r.K, 0.0)):
         with pytest.raises(tms.TmsError):
             tms.mesh_build_host(L, r.corner_phi, V, c, K, h0)
+
+
+def test_triangle_uniformness(glob200):
+    # the smallest angle, the triangles with an angle below 5 degrees and
+    # the degenerate ones, against a direct computation on the mesh's arrays
+    _, m = glob200
+    rep = m.check(intersections=False)
+    P = m.xyz[m.tri]                                   # [nt, 3, 3]
+    ang = []
+    for k in range(3):
+        x = P[:, (k + 1) % 3] - P[:, k]
+        y = P[:, (k + 2) % 3] - P[:, k]
+        ang.append(np.degrees(np.arctan2(np.linalg.norm(np.cross(x, y), axis=1),
+                                         (x * y).sum(1))))
+    tmin = np.min(ang, axis=0)
+    assert abs(rep["min_angle"] - tmin.min()) < 1e-9
+    assert rep["small_angles"] == int((tmin < 5.0).sum())
+    side2 = np.max([((P[:, (k + 1) % 3] - P[:, k]) ** 2).sum(1) for k in range(3)], axis=0)
+    area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+    assert rep["zero_area"] == int((area <= 1e-12 * side2).sum())
+    print("min angle %.3f deg, %d of %d triangles below 5 deg, %d degenerate"
+          % (rep["min_angle"], rep["small_angles"], len(m.tri), rep["zero_area"]))
