@@ -462,9 +462,11 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * point along -grad g (outward, phi >= c inside).  Host code (threads); the
  * inputs are copied from the device.
  *
- * tms_mesh_build: cells of one conformation; leaves [n] and corner_phi [n][8]
- *   as tms_partition_estimate wrote them, verts [nv] as
- *   tms_extract_cube_vertices wrote them for those leaves (device pointers).
+ * tms_mesh_build: leaves [n] and corner_phi [n][8] as tms_partition_estimate
+ *   wrote them, verts [nv] as tms_extract_cube_vertices wrote them for those
+ *   leaves (device pointers), of one conformation: the cells' only one, or
+ *   one of a batch's (its ranges of the leaves and the vertices, from
+ *   tms_batch_counts); leaves of several conformations are refused.
  *   The mesh's vertices are the nv edge points in that (key) order, then
  *   those of added cubes and interior points of fanned patches.  A SURFACE
  *   leaf above the finest level (a loose tau can stop a straddling cube

@@ -835,14 +835,14 @@ std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double>
     return std::string();
 }
 
-// phi of the library (tms_eval_phi, the precision of `cells`) at host points
-// pts [m][3]; on failure *rc and a message
-std::string eval_points(tms_ctx *ctx, const tms_cells *cells, const std::vector<double> &pts,
-                        std::vector<double> &phi, DevBuf &dpts, DevBuf &dphi, int32_t *rc) {
+// phi of the library (as tms_eval_phi, the precision of `cells`) of
+// conformation conf at host points pts [m][3]; on failure *rc and a message
+std::string eval_points(tms_ctx *ctx, const tms_cells *cells, int conf,
+                        const std::vector<double> &pts, std::vector<double> &phi, DevBuf &dpts,
+                        DevBuf &dphi, int32_t *rc) {
     const int64_t m = (int64_t)(pts.size() / 3);
     phi.assign((size_t)m, 0.0);
     if (m == 0) return std::string();
-    int64_t ng = 0;
     if (dpts.ensure(sizeof(double) * pts.size()) != hipSuccess ||
         dphi.ensure(sizeof(double) * (size_t)m) != hipSuccess) {
         (void)hipGetLastError();
@@ -855,8 +855,7 @@ std::string eval_points(tms_ctx *ctx, const tms_cells *cells, const std::vector<
         *rc = TMS_E_DEVICE;
         return "copying the corners of cubes added to the mesh to the device";
     }
-    const int32_t e = tms_eval_phi(ctx, cells, dpts.as<double>(), m, dphi.as<double>(), nullptr,
-                                   &ng);
+    const int32_t e = tms::eval_phi_conf(ctx, cells, conf, dpts.as<double>(), m, dphi.as<double>());
     if (e != TMS_OK) {
         *rc = e;
         return ctx->err;
@@ -873,14 +872,14 @@ std::string eval_points(tms_ctx *ctx, const tms_cells *cells, const std::vector<
 
 // the edge point of a crossing edge e of the cube (ix, iy, iz) at `level`
 // with corner values f, placed as the extraction places its points
-tms_vertex new_vertex(const Grid &g, int level, int32_t ix, int32_t iy, int32_t iz, int e,
-                      const double f[8]) {
+tms_vertex new_vertex(const Grid &g, int conf, int level, int32_t ix, int32_t iy, int32_t iz,
+                      int e, const double f[8]) {
     const EdgeInfo &E = topo().E[e];
     const int sh = g.K - level;
     const double h = std::ldexp(g.h0, -level);
     const double f0 = f[E.v0], f1 = f[E.v1];
     tms_vertex x;
-    x.edge_key = edge_key(0, level, g.K, ix, iy, iz, e);
+    x.edge_key = edge_key(conf, level, g.K, ix, iy, iz, e);
     x.t = (g.c - f0) / (f1 - f0);
     const int64_t I[3] = {(int64_t)ix + E.off[0], (int64_t)iy + E.off[1], (int64_t)iz + E.off[2]};
     double p[3];
@@ -902,11 +901,11 @@ tms_vertex new_vertex(const Grid &g, int level, int32_t ix, int32_t iy, int32_t 
 // else phi of the library; their edge points as the extraction places them
 // (appended to X).  The coarse leaf is marked kClsSplit in the host copy;
 // its own edge points stay in the vertex list, unused.
-std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
+std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, int conf, std::vector<tms_leaf> &L,
                          std::vector<double> &cp, const std::vector<tms_vertex> &V,
                          std::vector<tms_vertex> &X, int32_t *rc) {
     *rc = TMS_OK;
-    const Grid &g = cells->g;
+    const Grid &g = cells->gh[(size_t)conf];
     const int K = g.K;
     std::vector<int64_t> coarse;
     for (int64_t i = 0; i < (int64_t)L.size(); ++i)
@@ -971,7 +970,7 @@ std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_l
     }
     DevBuf dpts, dphi;
     std::vector<double> phi;
-    const std::string why = eval_points(ctx, cells, pts, phi, dpts, dphi, rc);
+    const std::string why = eval_points(ctx, cells, conf, pts, phi, dpts, dphi, rc);
     if (*rc != TMS_OK) return why;
     for (size_t k = 0; k < need.size(); ++k) val[need[k]] = phi[k];
     // the straddling cubes of the finest level inside each coarse leaf
@@ -998,7 +997,7 @@ std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_l
                     lf.ix = (int32_t)(b[0] + x);
                     lf.iy = (int32_t)(b[1] + y);
                     lf.iz = (int32_t)(b[2] + z);
-                    lf.conf = 0;
+                    lf.conf = conf;
                     lf.level = (uint8_t)K;
                     lf.reason = TMS_REASON_SPLIT;
                     lf.mask = (uint8_t)mask;
@@ -1007,13 +1006,13 @@ std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_l
                     cp.insert(cp.end(), f, f + 8);
                     for (int e = 0; e < 12; ++e) {
                         if ((f[T.E[e].v0] >= g.c) == (f[T.E[e].v1] >= g.c)) continue;
-                        const uint64_t key = edge_key(0, K, K, lf.ix, lf.iy, lf.iz, e);
+                        const uint64_t key = edge_key(conf, K, K, lf.ix, lf.iy, lf.iz, e);
                         auto it = std::lower_bound(
                             V.begin(), V.end(), key,
                             [](const tms_vertex &a, uint64_t kk) { return a.edge_key < kk; });
                         if ((it != V.end() && it->edge_key == key) || !seen.insert(key).second)
                             continue;
-                        X.push_back(new_vertex(g, K, lf.ix, lf.iy, lf.iz, e, f));
+                        X.push_back(new_vertex(g, conf, K, lf.ix, lf.iy, lf.iz, e, f));
                     }
                 }
     }
@@ -1034,11 +1033,11 @@ std::string split_coarse(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_l
 // appended to the mesh's points.  Cubes outside the root grid are not added.
 constexpr int kCloseRounds = 64;
 
-std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_leaf> &L,
+std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, int conf, std::vector<tms_leaf> &L,
                        std::vector<double> &cp, VIndex &VI, std::vector<uint8_t> &em,
                        tms_mesh *M, int32_t *rc) {
     *rc = TMS_OK;
-    const Grid &g = cells->g;
+    const Grid &g = cells->gh[(size_t)conf];
     const int level = M->level, sh = g.K - level;
     const Topo &T = topo();
     const VidFn vid = [&](uint64_t key) { return VI.find(key); };
@@ -1110,7 +1109,7 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_lea
             }
         {
             std::vector<double> phi;
-            const std::string why = eval_points(ctx, cells, pts, phi, dpts, dphi, rc);
+            const std::string why = eval_points(ctx, cells, conf, pts, phi, dpts, dphi, rc);
             if (*rc != TMS_OK) return why;
             for (size_t k = 0; k < nq * 8; ++k)
                 if (slot[k] >= 0) f[k] = phi[(size_t)slot[k]];
@@ -1122,7 +1121,7 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_lea
             lf.ix = q[k][0];
             lf.iy = q[k][1];
             lf.iz = q[k][2];
-            lf.conf = 0;
+            lf.conf = conf;
             lf.level = (uint8_t)level;
             lf.reason = TMS_REASON_CLOSED;
             unsigned mask = 0;
@@ -1139,12 +1138,13 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, std::vector<tms_lea
                 const EdgeInfo &E = T.E[ed];
                 const double f0 = f[k * 8 + E.v0], f1 = f[k * 8 + E.v1];
                 if ((f0 >= g.c) == (f1 >= g.c)) continue;
-                const uint64_t key = edge_key(0, level, g.K, lf.ix, lf.iy, lf.iz, ed);
+                const uint64_t key = edge_key(conf, level, g.K, lf.ix, lf.iy, lf.iz, ed);
                 int64_t id = vid(key);
                 if (id < 0) {
                     id = (int64_t)(M->xyz.size() / 3);
                     VI.add(key, id);
-                    const tms_vertex nvx = new_vertex(g, level, lf.ix, lf.iy, lf.iz, ed, &f[k * 8]);
+                    const tms_vertex nvx =
+                        new_vertex(g, conf, level, lf.ix, lf.iy, lf.iz, ed, &f[k * 8]);
                     double x[3];
                     place_vertex(key, nvx.t, nvx.x, nvx.y, nvx.z, g.h0, x);
                     M->xyz.insert(M->xyz.end(), x, x + 3);
@@ -1186,9 +1186,6 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
     *out = nullptr;
     if (std::find(ctx->cells.begin(), ctx->cells.end(), cells) == ctx->cells.end())
         return mfail(ctx, TMS_E_INVALID, "cells handle does not belong to this context");
-    if (cells->nconf != 1)
-        return mfail(ctx, TMS_E_INVALID, "tms_mesh_build takes cells of one conformation");
-    const Grid &g = cells->g;
     std::vector<tms_leaf> L((size_t)n);
     std::vector<double> cp((size_t)n * 8);
     std::vector<tms_vertex> V((size_t)nv);
@@ -1203,12 +1200,24 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
         (void)hipGetLastError();
         return mfail(ctx, TMS_E_DEVICE, "copying leaves, corner values or vertices to the host");
     }
+    // one conformation: the cells' only one, or one of a batch's (its range
+    // of the leaves and of the vertices)
+    const int conf = n > 0 ? L[0].conf : 0;
+    if (conf < 0 || conf >= cells->nconf)
+        return mfail(ctx, TMS_E_INVALID, "leaves of a conformation the cells do not have");
+    for (const tms_leaf &lf : L)
+        if (lf.conf != conf)
+            return mfail(ctx, TMS_E_INVALID, "leaves of several conformations: mesh one at a time");
+    for (const tms_vertex &v : V)
+        if ((int)(v.edge_key >> 53) != conf)
+            return mfail(ctx, TMS_E_INVALID, "vertices of another conformation than the leaves");
+    const Grid &g = cells->gh[(size_t)conf];
     // SURFACE leaves above the finest level are meshed through their finest
     // sub-cubes; then the mesh, then the cubes across open faces
     std::vector<tms_vertex> X;
     {
         int32_t rc = TMS_OK;
-        const std::string w = split_coarse(ctx, cells, L, cp, V, X, &rc);
+        const std::string w = split_coarse(ctx, cells, conf, L, cp, V, X, &rc);
         if (rc != TMS_OK) return mfail(ctx, rc, w.c_str());
     }
     std::vector<uint8_t> em;
@@ -1217,7 +1226,7 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
     if (!why.empty()) return mfail(ctx, TMS_E_INVALID, why.c_str());
     if ((flags & TMS_MESH_CLOSE) && (*out)->open_faces > 0) {
         int32_t rc = TMS_OK;
-        const std::string w = close_mesh(ctx, cells, L, cp, VI, em, *out, &rc);
+        const std::string w = close_mesh(ctx, cells, conf, L, cp, VI, em, *out, &rc);
         if (rc != TMS_OK) {
             delete *out;
             *out = nullptr;

@@ -575,6 +575,32 @@ int32_t regroup_by_conf(tms_ctx *ctx, const tms_cells *cells, int64_t L) {
 
 }  // namespace
 
+namespace tms {
+
+// phi of conformation `conf` of `cells` at m device points, the path of
+// tms_eval_phi (with the FP32 guard of the cells' precision); the context's
+// error is set on failure
+int32_t eval_phi_conf(tms_ctx *ctx, const tms_cells *cells, int conf, const double *pts,
+                      int64_t m, double *phi) {
+    if (conf < 0 || conf >= cells->nconf)
+        return fail(ctx, TMS_E_INVALID, "conformation %d out of range", conf);
+    HIPCK(hipSetDevice(ctx->device));
+    const int32_t *pconf = nullptr;
+    DevBuf pc;
+    if (cells->nconf > 1 && m > 0) {
+        HIPCK(pc.ensure(sizeof(int32_t) * (size_t)m));
+        HIPCK(launch_fill_u32(pc.as<uint32_t>(), (uint32_t)conf, m, ctx->stream));
+        pconf = pc.as<int32_t>();
+    }
+    int64_t ng = 0;
+    const int32_t rc = phi_with_guard(ctx, cells, pts, pconf, m, phi, nullptr, &ng, 0.0, false);
+    if (rc) return rc;
+    HIPCK(hipStreamSynchronize(ctx->stream));  // pc is released on return
+    return TMS_OK;
+}
+
+}  // namespace tms
+
 // ---------------------------------------------------------------------------
 // public API
 // ---------------------------------------------------------------------------

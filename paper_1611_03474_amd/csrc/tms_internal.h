@@ -346,6 +346,10 @@ hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *t
                           void *tmp, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// phi of conformation conf of cells at m device points (as tms_eval_phi;
+// batch cells allowed); synchronizes the context's stream
+int32_t eval_phi_conf(tms_ctx *ctx, const tms_cells *cells, int conf, const double *pts,
+                      int64_t m, double *phi);
 // out[i] = src[idx[i]]
 hipError_t launch_gather_i32(const int32_t *src, const int64_t *idx, int n, int64_t *out,
                              hipStream_t s);

@@ -290,3 +290,36 @@ def test_empty_partition_and_bad_flags(ctx):
         assert rc == tms.TMS_E_INVALID
     finally:
         ctx.free_cells(cells)
+
+
+def test_batch_conformations_mesh_as_single_passes(ctx):
+    # each conformation of a batch meshed from its ranges of the batch's
+    # leaves and vertices (the closing cubes evaluated for that conformation)
+    # equals the mesh of its own single pass; a range spanning two
+    # conformations is refused
+    confs = [synth.globule(200, 1002), synth.globule(300, 1013), synth.globule(200, 1001)]
+    p = tms.make_params(D=0.9, tau=1e-3, precision=tms.PREC_FP32_GUARD)
+    cells = ctx.build_cells_batch(confs, p)
+    try:
+        leaves, cphi, _ = ctx.partition_estimate(cells)
+        verts = ctx.extract(cells, leaves, cphi)
+        lo, vo = ctx.batch_counts(cells)
+        meshes = [ctx.mesh_build(cells, leaves[lo[b]:lo[b + 1]], cphi[lo[b]:lo[b + 1]],
+                                 verts[vo[b]:vo[b + 1]]) for b in range(len(confs))]
+        with pytest.raises(tms.TmsError):
+            ctx.mesh_build(cells, leaves[lo[0]:lo[2]], cphi[lo[0]:lo[2]], verts[vo[0]:vo[2]])
+    finally:
+        ctx.free_cells(cells)
+    n_added = 0
+    for b, atoms in enumerate(confs):
+        L, mo, ms = _gpu_meshes(ctx, atoms, tms.PREC_FP32_GUARD, D=0.9, tau=1e-3)
+        mb = meshes[b]
+        assert np.array_equal(mb.tri, ms.tri) and np.array_equal(mb.tri_leaf, ms.tri_leaf)
+        assert np.array_equal(mb.xyz, ms.xyz)
+        assert np.array_equal(mb.added_phi, ms.added_phi)
+        for f in ("ix", "iy", "iz", "level", "reason", "mask", "cls"):
+            assert np.array_equal(mb.added[f], ms.added[f])
+        assert np.all(mb.added["conf"] == b)
+        assert mb.check() == ms.check()
+        n_added += len(mb.added)
+    assert n_added > 0  # the first globule has open faces
