@@ -449,18 +449,26 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
 
 /* ---- host Stage 2: the mesh (Section 2.3, manifold checks of Section 3.2) ---
  * The trilinear surface g = c (eq. linear1) of every SURFACE leaf as
- * triangles on the leaves' edge points (eq. intersection).  On each face of a
- * leaf the curve g = c is a hyperbola branch joining the face's edge points in
- * pairs (two points: joined; four: by the value of g at the face's saddle
- * point, the same on both leaves sharing the face); the face segments link
- * into closed loops on the cube's boundary, and each loop's patch is
- * triangulated by ear clipping in the plane normal to an axis along which it
- * projects to a simple polygon (the single-valued direction of the patch),
- * with no triangle side between two points of one cube face other than the
- * face's curve segments, else fanned from a point of the patch inside the
- * cube (counted).  Triangles
- * point along -grad g (outward, phi >= c inside).  Host code (threads); the
- * inputs are copied from the device.
+ * triangles on the leaves' edge points (eq. intersection) and the extreme
+ * points on their faces (eq. curve).  On each face of a leaf the curve g = c
+ * is a hyperbola branch joining the face's edge points in pairs (two points:
+ * joined; four: by the value of g at the face's saddle point, the same on
+ * both leaves sharing the face).  The extreme points of both leaves beside a
+ * face (where g = c and the derivative of g normal to the face vanishes; g
+ * is trilinear, so each is an end of a straight fold segment, eq. fold1,
+ * across a leaf) lie on its curve and are vertices of it in both leaves
+ * (two within 1e-9 leaf edges of each other are one point; those within
+ * 1e-9 leaf edges of the face's rim are left out).
+ * The face segments link into closed loops on the cube's boundary.  Each
+ * loop's patch is cut along the leaf's fold segments along one axis whose
+ * two ends are on the loop (Section 2.3: pieces single-valued along that
+ * axis) and every piece is triangulated by ear clipping in the plane normal
+ * to that axis, the axes tried in order of the loop's projected area; no
+ * triangle side joins two points of one cube face other than the face's
+ * curve segments.  A loop that no axis admits is fanned from a point of the
+ * patch inside the cube (counted).  Triangles point along -grad g (outward,
+ * phi >= c inside).  Host code (threads); the inputs are copied from the
+ * device.
  *
  * tms_mesh_build: leaves [n] and corner_phi [n][8] as tms_partition_estimate
  *   wrote them, verts [nv] as tms_extract_cube_vertices wrote them for those
@@ -468,7 +476,8 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  *   one of a batch's (its ranges of the leaves and the vertices, from
  *   tms_batch_counts); leaves of several conformations are refused.
  *   The mesh's vertices are the nv edge points in that (key) order, then
- *   those of added cubes and interior points of fanned patches.  A SURFACE
+ *   those of added cubes, the extreme points on leaf faces (by face, then
+ *   face coordinates) and one interior point per fanned loop.  A SURFACE
  *   leaf above the finest level (a loose tau can stop a straddling cube
  *   early) is meshed through the cubes of the finest level inside it whose
  *   corner values straddle c, added as SURFACE leaves (reason

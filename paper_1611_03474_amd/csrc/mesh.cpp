@@ -53,7 +53,7 @@ struct tms_mesh {
     std::vector<tms_leaf> added;    // cubes added across open faces
     std::vector<double> added_phi;  // [n_added][8] their corner values
     int level = 0;
-    int64_t n_surface = 0, n_loops = 0, n_fallback = 0, open_faces = 0;
+    int64_t n_surface = 0, n_loops = 0, n_fallback = 0, open_faces = 0, n_face_points = 0;
 };
 
 namespace {
@@ -152,11 +152,16 @@ const Topo &topo() {
 }
 
 // ---- one leaf ---------------------------------------------------------------
-constexpr int kLoopMax = 12;  // a loop visits each of the cube's edges at most once
+// a loop visits each of the cube's 12 edges at most once; with up to 4
+// points on each face it has at most 36 points
+constexpr int kPolyMax = 48;
 struct LeafOut {
-    // corners: cube edge indices 0..11, or 12 + k for the k-th interior point
+    // corners: cube edge indices 0..11, 12 + k the k-th interior point, or
+    // 64 + j the j-th face point (fpid[j] its mesh vertex id)
     std::vector<std::array<int, 3>> tri;
     std::vector<std::array<double, 3>> inner;  // interior points (local)
+    std::vector<int64_t> fpid;
+    std::vector<std::array<double, 3>> fpxyz;  // face points (local)
     int loops = 0, fallback = 0;
 };
 
@@ -273,15 +278,31 @@ bool seg_meet(const double a[2], const double b[2], const double c[2], const dou
     return on(a, b, c, d1) || on(a, b, d, d2) || on(c, d, a, d3) || on(c, d, b, d4);
 }
 
+// sine of a triangle's smallest angle (the angle at the vertex opposite its
+// shortest side: twice the area over the two longer sides), 0 if degenerate
+double shape(const double *p, const double *q, const double *r) {
+    const double u[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+    const double v[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+    const double w[3] = {r[0] - q[0], r[1] - q[1], r[2] - q[2]};
+    const double n[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+    double l[3] = {u[0] * u[0] + u[1] * u[1] + u[2] * u[2], v[0] * v[0] + v[1] * v[1] + v[2] * v[2],
+                   w[0] * w[0] + w[1] * w[1] + w[2] * w[2]};
+    std::sort(l, l + 3);
+    const double d = std::sqrt(l[1] * l[2]);
+    return d > 0.0 ? std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]) / d : 0.0;
+}
+
 // ear clipping of a simple polygon (counter-clockwise or clockwise) of m
 // points; emits index triples with the polygon's winding.  fm[i]: the cube
 // faces point i lies on (bit 2 a + s); no diagonal joins two points of one
 // face -- such a side would lie in the face, where the leaf across puts its
 // own triangles (a loop that crosses a face twice, through both branches of
 // its hyperbola, would otherwise be capped in the face from both sides).
-// Returns false if the polygon is not simple or has no ear left.
-bool ear_clip(const double (*Q)[2], int m, const unsigned *fm, std::array<int, 3> *out,
-              int *nout) {
+// Of the ears at each step the one whose triangle in space (X) is best
+// shaped is cut.  Returns false if the polygon is not simple or has no ear
+// left.
+bool ear_clip(const double (*Q)[2], const double (*X)[3], int m, const unsigned *fm,
+              std::array<int, 3> *out, int *nout) {
     *nout = 0;
     // simple: non-adjacent sides do not meet, no repeated point
     for (int i = 0; i < m; ++i)
@@ -294,11 +315,14 @@ bool ear_clip(const double (*Q)[2], int m, const unsigned *fm, std::array<int, 3
     for (int i = 0; i < m; ++i) area += Q[i][0] * Q[(i + 1) % m][1] - Q[(i + 1) % m][0] * Q[i][1];
     if (area == 0.0) return false;
     const double sg = area > 0 ? 1.0 : -1.0;
-    int idx[kLoopMax], k = m;
+    if (m > kPolyMax) return false;
+    int idx[kPolyMax], k = m;
     for (int i = 0; i < m; ++i) idx[i] = i;
     while (k > 3) {
-        bool found = false;
-        for (int i = 0; i < k && !found; ++i) {
+        // of the ears, the one whose triangle in space is best shaped
+        int best = -1;
+        double bq = -1.0;
+        for (int i = 0; i < k; ++i) {
             const int ia = idx[(i + k - 1) % k], ib = idx[i], ic = idx[(i + 1) % k];
             if (fm[ia] & fm[ic]) continue;
             const double cr = cross2(Q[ia], Q[ib], Q[ic]) * sg;
@@ -313,72 +337,418 @@ bool ear_clip(const double (*Q)[2], int m, const unsigned *fm, std::array<int, 3
                 if (c1 >= 0 && c2 >= 0 && c3 >= 0) inside = true;
             }
             if (inside) continue;
-            out[(*nout)++] = {ia, ib, ic};
-            for (int j = i; j + 1 < k; ++j) idx[j] = idx[j + 1];
-            --k;
-            found = true;
+            const double q = shape(X[ia], X[ib], X[ic]);
+            if (q > bq) {
+                bq = q;
+                best = i;
+            }
         }
-        if (!found) return false;
+        if (best < 0) return false;
+        out[(*nout)++] = {idx[(best + k - 1) % k], idx[best], idx[(best + 1) % k]};
+        for (int j = best; j + 1 < k; ++j) idx[j] = idx[j + 1];
+        --k;
     }
     out[(*nout)++] = {idx[0], idx[1], idx[2]};
     return true;
 }
 
-void leaf_triangles(const double f[8], double c, LeafOut &L) {
+// ---- folds and face points (Section 2.3: eqs. curve, fold1) -----------------
+// On a leaf's local cube [0,1]^3 the trilinear g = sum_S m_S prod_{i in S} x_i
+// (S a set of axes; bit 0 x, bit 1 y, bit 2 z).  Along axis a, dg/da does
+// not depend on x_a, and where it vanishes neither does g: the fold set along
+// a (g = c, dg/da = 0) is a set of full segments parallel to a, over the
+// points (u, v) of the two other axes (u the lower) where dg/da = 0 and
+// g(x_a = 0) = c -- at most two -- and each ends at an extreme point (eq.
+// curve) on the faces x_a = 0 and x_a = 1.  Folds on the cube's boundary (u
+// or v within 1e-9 of 0 or 1) lie in a face curve and are left out.
+struct Fold {
+    double u, v;
+};
+
+constexpr double kFoldIn = 1e-9;
+// face points closer than this (in face coordinates) are one point
+constexpr double kFaceMerge = 1e-9;
+
+void monomials01(const double f[8], double m[8]) {
+    for (int v = 0; v < 8; ++v) m[v] = f[v];
+    for (int b = 1; b < 8; b <<= 1)
+        for (int v = 0; v < 8; ++v)
+            if (v & b) m[v] -= m[v ^ b];
+}
+
+// real roots of r0 + r1 t + r2 t^2, ascending; -1 when every coefficient is 0
+int quad_roots(double r0, double r1, double r2, double t[2]) {
+    if (r2 == 0.0) {
+        if (r1 == 0.0) return r0 == 0.0 ? -1 : 0;
+        t[0] = -r0 / r1;
+        return 1;
+    }
+    const double d = r1 * r1 - 4.0 * r2 * r0;
+    if (d < 0.0) return 0;
+    if (d == 0.0) {
+        t[0] = -r1 / (2.0 * r2);
+        return 1;
+    }
+    const double sq = std::sqrt(d);
+    const double big = (r1 >= 0.0) ? (-r1 - sq) / (2.0 * r2) : (-r1 + sq) / (2.0 * r2);
+    const double small = (big != 0.0) ? r0 / (r2 * big) : big;
+    t[0] = std::min(big, small);
+    t[1] = std::max(big, small);
+    return 2;
+}
+
+int folds_along(const double m[8], double c, int a, Fold out[2]) {
+    const int U = (a == 0) ? 2 : 1, V = (a == 2) ? 2 : 4, A = 1 << a;
+    const double h0 = m[A], hu = m[A | U], hv = m[A | V], huv = m[A | U | V];
+    if (h0 == 0.0 && hu == 0.0 && hv == 0.0 && huv == 0.0) return 0;  // g free of x_a
+    const double g0 = m[0] - c, gu = m[U], gv = m[V], guv = m[U | V];
+    // both equations as alpha(v) + beta(v) u; their resultant in u
+    const double r0 = g0 * hu - gu * h0;
+    const double r1 = g0 * huv + gv * hu - gu * hv - guv * h0;
+    const double r2 = gv * huv - guv * hv;
+    double t[2];
+    const int nr = quad_roots(r0, r1, r2, t);
+    if (nr <= 0) return 0;  // none, or infinitely many (a curve: not split)
+    int n = 0;
+    for (int i = 0; i < nr; ++i) {
+        const double v = t[i];
+        if (!(v > kFoldIn && v < 1.0 - kFoldIn)) continue;
+        const double aG = g0 + gv * v, bG = gu + guv * v;
+        const double aH = h0 + hv * v, bH = hu + huv * v;
+        if (bG == 0.0 && bH == 0.0) continue;  // a line of solutions, or none
+        const double u = (std::fabs(bG) >= std::fabs(bH)) ? -aG / bG : -aH / bH;
+        if (!(u > kFoldIn && u < 1.0 - kFoldIn)) continue;
+        out[n++] = {u, v};
+    }
+    if (n == 2 && out[1].u < out[0].u) std::swap(out[0], out[1]);
+    return n;
+}
+
+// a point on a face of the leaf: face coordinates (u along the face's lower
+// other axis, v along the higher) and its mesh vertex id
+struct FacePt {
+    double u, v;
+    int64_t id;
+};
+
+// what the triangulation of a leaf knows besides its corner values: the
+// points on each face (its own extreme points and the neighbour's, from
+// both cubes sharing the face), and its own folds with the ids of their ends
+struct LeafFolds {
+    const FacePt *fp[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int nfp[6] = {0, 0, 0, 0, 0, 0};
+    Fold fold[3][2];
+    int64_t end_id[3][2][2];  // [axis][fold][side]
+    int nfold[3] = {0, 0, 0};
+};
+
+
+// Corner codes of LeafOut triangles: 0..11 edge points, 12 + k the k-th
+// interior point, 64 + j the j-th face point of the leaf (LeafOut::fpid).
+constexpr int kCodeFace = 64;
+
+// Ear clipping of one piece of a patch (loop indices pc, in loop order) in
+// the plane normal to axis a.  A fold along a on the piece's boundary (two
+// consecutive points of pc that are the two ends of one chord) projects to a
+// single point W: the projected polygon takes W once, and after clipping the
+// fan of triangles around W is lifted back, the triangles from W's neighbour
+// after the fold up to the fan vertex u nearest the fold's middle along a on
+// the fold's second end, the rest on its first end, with the triangle
+// (first end, second end, u) spanning the fold.  Triangles keep the order of
+// the loop.  False if the projection is not a simple polygon.
+bool clip_piece(const double (*P)[3], const unsigned *fm, const std::vector<int> &pc,
+                const int (*chord)[2], int nch, int a, std::array<int, 3> *tl, int *ntl) {
+    const int b = (a + 1) % 3, cc = (a + 2) % 3;
+    const int pm = (int)pc.size();
+    auto is_chord = [&](int x, int y) {
+        for (int k = 0; k < nch; ++k)
+            if ((chord[k][0] == x && chord[k][1] == y) || (chord[k][0] == y && chord[k][1] == x))
+                return true;
+        return false;
+    };
+    // rotate so that no fold pair wraps around the end of the list
+    int r0 = 0;
+    if (pm > 1 && is_chord(pc[(size_t)(pm - 1)], pc[0])) r0 = pm - 1;
+    int first[kPolyMax], second[kPolyMax], nk = 0;
+    for (int t = 0; t < pm;) {
+        const int x = pc[(size_t)((r0 + t) % pm)];
+        if (t + 1 < pm && is_chord(x, pc[(size_t)((r0 + t + 1) % pm)])) {
+            first[nk] = x;
+            second[nk++] = pc[(size_t)((r0 + t + 1) % pm)];
+            t += 2;
+        } else {
+            first[nk] = x;
+            second[nk++] = -1;
+            ++t;
+        }
+    }
+    if (nk < 3) return false;
+    double Q[kPolyMax][2], X[kPolyMax][3];
+    unsigned qfm[kPolyMax];
+    for (int i = 0; i < nk; ++i) {
+        Q[i][0] = P[first[i]][b];
+        Q[i][1] = P[first[i]][cc];
+        for (int d = 0; d < 3; ++d)
+            X[i][d] = second[i] < 0 ? P[first[i]][d] : 0.5 * (P[first[i]][d] + P[second[i]][d]);
+        qfm[i] = fm[first[i]] | (second[i] >= 0 ? fm[second[i]] : 0u);
+    }
+    std::array<int, 3> rt[kPolyMax];
+    int nrt = 0;
+    if (!ear_clip(Q, X, nk, qfm, rt, &nrt)) return false;
+    // per reduced triangle and corner: the loop index it stands for
+    std::array<int, 3> out[kPolyMax];
+    for (int k = 0; k < nrt; ++k)
+        for (int z = 0; z < 3; ++z) out[k][(size_t)z] = first[rt[k][(size_t)z]];
+    std::array<int, 3> bridge[kPolyMax];
+    int nb = 0;
+    for (int w = 0; w < nk; ++w) {
+        if (second[w] < 0) continue;
+        // the fan around w: triangles rotated to (w, x, y), chained from
+        // x = the next vertex to y = the previous one
+        const int nxt = (w + 1) % nk, prv = (w + nk - 1) % nk;
+        int fan[kPolyMax], fu[kPolyMax + 1], nf = 0;
+        int x = nxt;
+        while (true) {
+            int hit = -1, y = -1;
+            for (int k = 0; k < nrt && hit < 0; ++k)
+                for (int z = 0; z < 3; ++z)
+                    if (rt[k][(size_t)z] == w && rt[k][(size_t)((z + 1) % 3)] == x) {
+                        hit = k;
+                        y = rt[k][(size_t)((z + 2) % 3)];
+                    }
+            if (hit < 0 || nf >= kPolyMax) return false;
+            fu[nf] = x;
+            fan[nf++] = hit;
+            x = y;
+            if (x == prv) break;
+        }
+        fu[nf] = prv;
+        // the fan vertex where the triangles pass from the second end to
+        // the first: nearest the fold's middle along a, not itself a fold
+        const double mid = 0.5 * (P[first[w]][a] + P[second[w]][a]);
+        int j = -1;
+        double bd = 1e300;
+        for (int t = 0; t <= nf; ++t) {
+            if (second[fu[t]] >= 0) continue;
+            const double d = std::fabs(P[first[fu[t]]][a] - mid);
+            if (d < bd) {
+                bd = d;
+                j = t;
+            }
+        }
+        if (j < 0) return false;
+        for (int t = 0; t < nf; ++t)
+            for (int z = 0; z < 3; ++z)
+                if (rt[fan[t]][(size_t)z] == w) out[fan[t]][(size_t)z] = t < j ? second[w] : first[w];
+        bridge[nb++] = {first[w], second[w], first[fu[j]]};
+    }
+    for (int k = 0; k < nrt; ++k) tl[(*ntl)++] = out[k];
+    for (int k = 0; k < nb; ++k) tl[(*ntl)++] = bridge[k];
+    return true;
+}
+
+void leaf_triangles(const double f[8], double c, const LeafFolds &lfo, LeafOut &L) {
     const Topo &T = topo();
     int partner[12][2];
     face_segments(f, c, partner);
+    L.fpid.clear();
+    L.fpxyz.clear();
+    // the face points of each face on each of its branches (a face curve
+    // has one or two branches, each joining two edge points, each monotone
+    // in both face coordinates): a point goes to the branch whose bounding
+    // box is nearest (contains it, barring rounding)
+    struct Branch {
+        int e1, e2;
+        int pts[8];
+        int np;
+    };
+    Branch br[6][2];
+    int nbr[6] = {0, 0, 0, 0, 0, 0};
+    double Pe[12][3];
+    bool have[12] = {false};
+    for (int e = 0; e < 12; ++e)
+        if (partner[e][0] >= 0) {
+            edge_point(f, c, e, Pe[e]);
+            have[e] = true;
+        }
+    for (int fi = 0; fi < 6; ++fi) {
+        for (int e = 0; e < 12; ++e)
+            for (int j = 0; j < 2; ++j)
+                if (partner[e][j] > e && T.edge_face[e][j] == fi && nbr[fi] < 2)
+                    br[fi][nbr[fi]++] = {e, partner[e][j], {0}, 0};
+        if (lfo.nfp[fi] == 0 || nbr[fi] == 0) continue;
+        const int a = fi >> 1, p = (a == 0) ? 1 : 0, q = (a == 2) ? 1 : 2;
+        for (int k = 0; k < lfo.nfp[fi]; ++k) {
+            const FacePt &x = lfo.fp[fi][k];
+            int best = 0;
+            double bd = 1e300;
+            for (int b = 0; b < nbr[fi]; ++b) {
+                const double *P1 = Pe[br[fi][b].e1], *P2 = Pe[br[fi][b].e2];
+                const double du = std::max({0.0, std::min(P1[p], P2[p]) - x.u, x.u - std::max(P1[p], P2[p])});
+                const double dv = std::max({0.0, std::min(P1[q], P2[q]) - x.v, x.v - std::max(P1[q], P2[q])});
+                const double d = du * du + dv * dv;
+                if (d < bd) {
+                    bd = d;
+                    best = b;
+                }
+            }
+            Branch &B = br[fi][best];
+            if (B.np < 8) B.pts[B.np++] = k;
+        }
+    }
     bool used[12] = {false};
     for (int e0 = 0; e0 < 12; ++e0) {
         if (used[e0] || partner[e0][0] < 0) continue;
-        // walk the loop through e0
-        int loop[kLoopMax], m = 0;
+        // walk the loop through e0, with the face points of each branch crossed
+        int code[kPolyMax], m = 0, ne = 0;
         int prev = -1, cur = e0;
+        bool bad = false;
         while (true) {
-            loop[m++] = cur;
+            if (m >= kPolyMax) {
+                bad = true;
+                break;
+            }
+            code[m++] = cur;
+            ++ne;
             used[cur] = true;
-            const int nx = (partner[cur][0] != prev) ? partner[cur][0] : partner[cur][1];
+            const int j = (partner[cur][0] != prev) ? 0 : 1;
+            const int nx = partner[cur][j], fi = T.edge_face[cur][j];
+            if (nx < 0) break;
+            // the branch (cur, nx) of face fi and its points, from cur to nx
+            for (int b = 0; b < nbr[fi]; ++b) {
+                const Branch &B = br[fi][b];
+                if (!((B.e1 == cur && B.e2 == nx) || (B.e1 == nx && B.e2 == cur)) || B.np == 0)
+                    continue;
+                const int a = fi >> 1, p = (a == 0) ? 1 : 0, q = (a == 2) ? 1 : 2;
+                const double d0 = Pe[nx][p] - Pe[cur][p], d1 = Pe[nx][q] - Pe[cur][q];
+                int ord[8];
+                double key[8];
+                for (int k = 0; k < B.np; ++k) {
+                    const FacePt &x = lfo.fp[fi][B.pts[k]];
+                    ord[k] = B.pts[k];
+                    key[k] = (x.u - Pe[cur][p]) * d0 + (x.v - Pe[cur][q]) * d1;
+                }
+                for (int k = 1; k < B.np; ++k)  // insertion sort along the branch
+                    for (int l = k; l > 0 && key[l] < key[l - 1]; --l) {
+                        std::swap(key[l], key[l - 1]);
+                        std::swap(ord[l], ord[l - 1]);
+                    }
+                for (int k = 0; k < B.np && m < kPolyMax; ++k) {
+                    const int64_t id = lfo.fp[fi][ord[k]].id;
+                    int slot = -1;
+                    for (int z = 0; z < (int)L.fpid.size(); ++z)
+                        if (L.fpid[(size_t)z] == id) slot = z;
+                    if (slot < 0) {
+                        slot = (int)L.fpid.size();
+                        L.fpid.push_back(id);
+                        L.fpxyz.push_back({0.0, 0.0, 0.0});
+                        double *X = L.fpxyz.back().data();
+                        X[a] = (double)(fi & 1);
+                        X[p] = lfo.fp[fi][ord[k]].u;
+                        X[q] = lfo.fp[fi][ord[k]].v;
+                    }
+                    code[m++] = kCodeFace + slot;
+                }
+                break;
+            }
             prev = cur;
             cur = nx;
-            if (cur == e0 || cur < 0 || m == kLoopMax) break;
+            if (cur == e0 || ne > 12) break;
         }
-        if (cur != e0 || m < 3) continue;  // not closed (cannot happen)
+        if (bad || cur != e0 || ne < 3) continue;  // not closed (cannot happen)
         ++L.loops;
-        double P[kLoopMax + 1][3];  // the loop's points, then an interior point
-        unsigned fm[kLoopMax];
+        double P[kPolyMax + 1][3];  // the loop's points, then an interior point
+        unsigned fm[kPolyMax];
         for (int i = 0; i < m; ++i) {
-            edge_point(f, c, loop[i], P[i]);
-            fm[i] = (1u << T.edge_face[loop[i]][0]) | (1u << T.edge_face[loop[i]][1]);
+            if (code[i] < 12) {
+                for (int a = 0; a < 3; ++a) P[i][a] = Pe[code[i]][a];
+                fm[i] = (1u << T.edge_face[code[i]][0]) | (1u << T.edge_face[code[i]][1]);
+            } else {
+                const double *X = L.fpxyz[(size_t)(code[i] - kCodeFace)].data();
+                for (int a = 0; a < 3; ++a) P[i][a] = X[a];
+                unsigned mk = 0;
+                for (int a = 0; a < 3; ++a)
+                    if (X[a] == 0.0 || X[a] == 1.0) mk |= 1u << (2 * a + (X[a] == 1.0 ? 1 : 0));
+                fm[i] = mk;
+            }
         }
-        // vector area of the loop and the outward direction -grad g at its
-        // centroid decide the orientation
+        // vector area of the loop and the outward direction -grad g decide
+        // the projection order and the orientation
         double A[3] = {0, 0, 0}, ctr[3] = {0, 0, 0};
         for (int i = 0; i < m; ++i) {
-            const double *p = P[i], *q = P[(i + 1) % m];
-            A[0] += 0.5 * (p[1] * q[2] - p[2] * q[1]);
-            A[1] += 0.5 * (p[2] * q[0] - p[0] * q[2]);
-            A[2] += 0.5 * (p[0] * q[1] - p[1] * q[0]);
-            for (int a = 0; a < 3; ++a) ctr[a] += p[a] / m;
+            const double *pp = P[i], *qq = P[(i + 1) % m];
+            A[0] += 0.5 * (pp[1] * qq[2] - pp[2] * qq[1]);
+            A[1] += 0.5 * (pp[2] * qq[0] - pp[0] * qq[2]);
+            A[2] += 0.5 * (pp[0] * qq[1] - pp[1] * qq[0]);
+            for (int a = 0; a < 3; ++a) ctr[a] += pp[a] / m;
         }
         int order[3] = {0, 1, 2};
         std::sort(order, order + 3, [&](int x, int y) { return std::fabs(A[x]) > std::fabs(A[y]); });
-        std::array<int, 3> tl[kLoopMax];
+        std::array<int, 3> tl[3 * kPolyMax];
         int ntl = 0;
         bool ok = false;
         for (int oi = 0; oi < 3 && !ok; ++oi) {
+            // split the patch along its folds of this axis (each piece is a
+            // single-valued graph over the other two axes), then clip every
+            // piece in that projection
             const int a = order[oi], b = (a + 1) % 3, cc = (a + 2) % 3;
-            double Q[kLoopMax][2];
-            for (int i = 0; i < m; ++i) {
-                Q[i][0] = P[i][b];
-                Q[i][1] = P[i][cc];
+            int chord[2][2], nch = 0;
+            for (int k = 0; k < lfo.nfold[a]; ++k) {
+                int i0 = -1, i1 = -1;
+                for (int i = 0; i < m; ++i)
+                    if (code[i] >= kCodeFace) {
+                        const int64_t id = L.fpid[(size_t)(code[i] - kCodeFace)];
+                        if (id == lfo.end_id[a][k][0]) i0 = i;
+                        if (id == lfo.end_id[a][k][1]) i1 = i;
+                    }
+                if (i0 >= 0 && i1 >= 0) {
+                    chord[nch][0] = i0;
+                    chord[nch][1] = i1;
+                    ++nch;
+                }
             }
-            ok = ear_clip(Q, m, fm, tl, &ntl);
+            // pieces as index lists; a chord splits the piece holding both ends
+            std::vector<std::vector<int>> pieces(1);
+            for (int i = 0; i < m; ++i) pieces[0].push_back(i);
+            bool split_ok = true;
+            for (int k = 0; k < nch && split_ok; ++k) {
+                bool done = false;
+                for (size_t pi = 0; pi < pieces.size() && !done; ++pi) {
+                    std::vector<int> &pc = pieces[pi];
+                    int x0 = -1, x1 = -1;
+                    for (int i = 0; i < (int)pc.size(); ++i) {
+                        if (pc[(size_t)i] == chord[k][0]) x0 = i;
+                        if (pc[(size_t)i] == chord[k][1]) x1 = i;
+                    }
+                    if (x0 < 0 || x1 < 0) continue;
+                    if (x1 < x0) std::swap(x0, x1);
+                    if (x1 - x0 < 2 || (x0 == 0 && x1 == (int)pc.size() - 1)) {
+                        split_ok = false;  // the ends are neighbours: nothing to split
+                        break;
+                    }
+                    std::vector<int> p1(pc.begin() + x0, pc.begin() + x1 + 1), p2;
+                    for (int i = x1; i != x0; i = (i + 1) % (int)pc.size()) p2.push_back(pc[(size_t)i]);
+                    p2.push_back(pc[(size_t)x0]);
+                    pc = p1;
+                    pieces.push_back(p2);
+                    done = true;
+                }
+            }
+            if (!split_ok) continue;
+            ntl = 0;
+            ok = true;
+            for (const auto &pc : pieces) {
+                if (!clip_piece(P, fm, pc, chord, nch, a, tl, &ntl)) {
+                    ok = false;
+                    break;
+                }
+            }
         }
         int inner = -1;
         if (!ok) {
-            // single valued along no axis (folds along all three): a fan
-            // from a point of the patch inside the cube, the loop's centroid
-            // moved onto g = c (else from the loop's first point)
+            // single valued along no axis even between folds: a fan from a
+            // point of the patch inside the cube, the loop's centroid moved
+            // onto g = c (else from the loop's first point)
             ntl = 0;
             double u[3] = {ctr[0], ctr[1], ctr[2]};
             if (onto_surface(f, c, u)) {
@@ -395,19 +765,19 @@ void leaf_triangles(const double f[8], double c, LeafOut &L) {
         double score = 0.0;
         for (int k = 0; k < ntl; ++k) {
             const auto &t = tl[k];
-            const double *p = P[t[0]], *q = P[t[1]], *r = P[t[2]];
-            const double u1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
-            const double u2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+            const double *pp = P[t[0]], *qq = P[t[1]], *rr = P[t[2]];
+            const double u1[3] = {qq[0] - pp[0], qq[1] - pp[1], qq[2] - pp[2]};
+            const double u2[3] = {rr[0] - pp[0], rr[1] - pp[1], rr[2] - pp[2]};
             const double n[3] = {u1[1] * u2[2] - u1[2] * u2[1], u1[2] * u2[0] - u1[0] * u2[2],
                                  u1[0] * u2[1] - u1[1] * u2[0]};
-            const double cen[3] = {(p[0] + q[0] + r[0]) / 3, (p[1] + q[1] + r[1]) / 3,
-                                   (p[2] + q[2] + r[2]) / 3};
+            const double cen[3] = {(pp[0] + qq[0] + rr[0]) / 3, (pp[1] + qq[1] + rr[1]) / 3,
+                                   (pp[2] + qq[2] + rr[2]) / 3};
             double G[3];
             grad_g(f, cen, G);
             score -= n[0] * G[0] + n[1] * G[1] + n[2] * G[2];
         }
         const bool flip = score < 0.0;
-        auto id = [&](int k) { return k < m ? loop[k] : 12 + inner; };
+        auto id = [&](int k) { return k < m ? code[k] : 12 + inner; };
         for (int k = 0; k < ntl; ++k) {
             const auto &t = tl[k];
             if (flip) L.tri.push_back({id(t[0]), id(t[2]), id(t[1])});
@@ -608,12 +978,144 @@ uint64_t cube_key(int64_t x, int64_t y, int64_t z) {
            (uint64_t)(z & 0x1FFFFF);
 }
 
-// Triangulates the leaves idx into M (triangles, interior points appended in
-// the order of idx) and ORs their ring bits into em (one byte per vertex id).
-// Returns false if an edge point of a leaf is missing (vid < 0).
+// Face points (eq. curve): the ends of every SURFACE leaf's folds, on its two
+// faces normal to the fold's axis.  Both leaves that share a face put the
+// points of both into their loops (Section 2.3 joins a cube's points with
+// those of its neighbours on the shared faces), so their face curves have
+// the same vertices.  Sorted by face, then (u, v); ids follow the points so
+// far, positions placed from an edge point of the leaf that made them.
+struct FaceRec {
+    uint64_t key;  // face: normal axis, lattice coordinates of its lower corner
+    double u, v;
+    int64_t id;
+};
+
+uint64_t face_key(int a, int64_t x, int64_t y, int64_t z) {
+    return ((uint64_t)a << 62) | ((uint64_t)(x & 0xFFFFF) << 40) | ((uint64_t)(y & 0xFFFFF) << 20) |
+           (uint64_t)(z & 0xFFFFF);
+}
+
+uint64_t leaf_face_key(const tms_leaf &lf, int fi) {
+    const int a = fi >> 1;
+    int64_t q[3] = {lf.ix, lf.iy, lf.iz};
+    q[a] += fi & 1;
+    return face_key(a, q[0], q[1], q[2]);
+}
+
+bool face_points(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+                 const std::vector<int64_t> &idx, double c, int K, double h0, const VidFn &vid,
+                 tms_mesh *M, std::vector<FaceRec> &FR) {
+    const Topo &T = topo();
+    const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
+    struct Rec {
+        uint64_t key;
+        double u, v, x[3];
+    };
+    std::vector<std::vector<Rec>> part(nth);
+    std::atomic<int64_t> missing{0};
+    parallel_for((int64_t)idx.size(), [&](int64_t b, int64_t e, int t) {
+        for (int64_t s2 = b; s2 < e; ++s2) {
+            const int64_t i = idx[(size_t)s2];
+            const tms_leaf &lf = L[(size_t)i];
+            const double *f = &cp[(size_t)i * 8];
+            double m[8];
+            monomials01(f, m);
+            Fold fo[3][2];
+            int nf[3], tot = 0;
+            for (int a = 0; a < 3; ++a) tot += nf[a] = folds_along(m, c, a, fo[a]);
+            if (!tot) continue;
+            int e0 = -1;
+            for (int ed = 0; ed < 12 && e0 < 0; ++ed)
+                if ((f[T.E[ed].v0] >= c) != (f[T.E[ed].v1] >= c)) e0 = ed;
+            const int64_t v0 = e0 < 0 ? -1 : vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, e0));
+            if (v0 < 0) {
+                ++missing;
+                continue;
+            }
+            double P0[3];
+            edge_point(f, c, e0, P0);
+            const double h = std::ldexp(h0, -(int)lf.level);
+            for (int a = 0; a < 3; ++a) {
+                const int p = (a == 0) ? 1 : 0, q = (a == 2) ? 1 : 2;
+                for (int k = 0; k < nf[a]; ++k)
+                    for (int sd = 0; sd < 2; ++sd) {
+                        Rec r;
+                        r.key = leaf_face_key(lf, 2 * a + sd);
+                        r.u = fo[a][k].u;
+                        r.v = fo[a][k].v;
+                        double loc[3];
+                        loc[a] = (double)sd;
+                        loc[p] = r.u;
+                        loc[q] = r.v;
+                        for (int d = 0; d < 3; ++d)
+                            r.x[d] = M->xyz[3 * (size_t)v0 + d] + (loc[d] - P0[d]) * h;
+                        part[(size_t)t].push_back(r);
+                    }
+            }
+        }
+    });
+    if (missing.load()) return false;
+    std::vector<Rec> all;
+    for (auto &pp : part) all.insert(all.end(), pp.begin(), pp.end());
+    std::sort(all.begin(), all.end(), [](const Rec &x, const Rec &y) {
+        return x.key != y.key ? x.key < y.key : (x.u != y.u ? x.u < y.u : x.v < y.v);
+    });
+    FR.clear();
+    for (const Rec &r : all) {
+        // the same point made by both leaves of the face: their corner
+        // orders differ, so the two solutions can differ in the last bits
+        bool dup = false;
+        for (size_t k = FR.size(); k-- > 0 && FR[k].key == r.key && r.u - FR[k].u <= kFaceMerge;)
+            if (std::fabs(r.v - FR[k].v) <= kFaceMerge) dup = true;
+        if (dup) continue;
+        FR.push_back({r.key, r.u, r.v, (int64_t)(M->xyz.size() / 3)});
+        M->xyz.insert(M->xyz.end(), r.x, r.x + 3);
+    }
+    return true;
+}
+
+// the face points of face fi of a leaf (a range of FR)
+void face_range(const std::vector<FaceRec> &FR, uint64_t key, const FaceRec **b, int *n) {
+    auto lo = std::lower_bound(FR.begin(), FR.end(), key,
+                               [](const FaceRec &r, uint64_t k) { return r.key < k; });
+    auto hi = lo;
+    while (hi != FR.end() && hi->key == key) ++hi;
+    *b = lo == hi ? nullptr : &*lo;
+    *n = (int)(hi - lo);
+}
+
+// Ring bits of the leaves idx (their crossing edges); false if an edge point
+// is missing.
+bool ring_pass(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+               const std::vector<int64_t> &idx, double c, int K, const VidFn &vid,
+               std::vector<uint8_t> &em) {
+    const Topo &T = topo();
+    std::atomic<int64_t> missing{0};
+    parallel_for((int64_t)idx.size(), [&](int64_t b, int64_t e, int) {
+        for (int64_t s2 = b; s2 < e; ++s2) {
+            const int64_t i = idx[(size_t)s2];
+            const tms_leaf &lf = L[(size_t)i];
+            const double *f = &cp[(size_t)i * 8];
+            for (int ed = 0; ed < 12; ++ed) {
+                if ((f[T.E[ed].v0] >= c) == (f[T.E[ed].v1] >= c)) continue;
+                const int64_t id = vid(edge_key(lf.conf, lf.level, K, lf.ix, lf.iy, lf.iz, ed));
+                if (id < 0) {
+                    ++missing;
+                    continue;
+                }
+                __atomic_fetch_or(&em[(size_t)id], (uint8_t)(1u << (ed & 3)), __ATOMIC_RELAXED);
+            }
+        }
+    });
+    return missing.load() == 0;
+}
+
+// Triangulates the leaves idx into M (triangles, then interior points
+// appended in the order of idx), each with the face points of FR on its
+// faces and its own folds.  Returns false if an edge point is missing.
 bool triangulate(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
                  const std::vector<int64_t> &idx, double c, int K, double h0, const VidFn &vid,
-                 tms_mesh *M, std::vector<uint8_t> &em) {
+                 const std::vector<FaceRec> &FR, tms_mesh *M) {
     const Topo &T = topo();
     const int64_t ns = (int64_t)idx.size();
     const unsigned nth = std::max(1u, std::thread::hardware_concurrency());
@@ -624,11 +1126,11 @@ bool triangulate(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
     parallel_for(ns, [&](int64_t b, int64_t e, int t) {
         first[(size_t)t] = b;
         LeafOut out;
-        for (int64_t s = b; s < e; ++s) {
-            const int64_t i = idx[(size_t)s];
+        std::vector<FacePt> fpbuf;
+        for (int64_t s2 = b; s2 < e; ++s2) {
+            const int64_t i = idx[(size_t)s2];
             const tms_leaf &lf = L[(size_t)i];
             const double *f = &cp[(size_t)i * 8];
-            // the leaf's crossing edges: vertex ids and ring bits
             int64_t id[12];
             bool ok = true;
             for (int ed = 0; ed < 12; ++ed) {
@@ -641,14 +1143,39 @@ bool triangulate(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
                 ++missing[(size_t)t];
                 continue;
             }
-            for (int ed = 0; ed < 12; ++ed)
-                if (id[ed] >= 0)
-                    __atomic_fetch_or(&em[(size_t)id[ed]], (uint8_t)(1u << (ed & 3)),
-                                      __ATOMIC_RELAXED);
+            // the points on its faces and its own folds with their ends' ids
+            LeafFolds lfo;
+            fpbuf.clear();
+            if (!FR.empty()) {
+                int start[6];
+                for (int fi = 0; fi < 6; ++fi) {
+                    const FaceRec *r;
+                    int n;
+                    face_range(FR, leaf_face_key(lf, fi), &r, &n);
+                    start[fi] = (int)fpbuf.size();
+                    for (int k = 0; k < n; ++k) fpbuf.push_back({r[k].u, r[k].v, r[k].id});
+                    lfo.nfp[fi] = n;
+                }
+                for (int fi = 0; fi < 6; ++fi) lfo.fp[fi] = fpbuf.data() + start[fi];
+                double m[8];
+                monomials01(f, m);
+                for (int a = 0; a < 3; ++a) {
+                    lfo.nfold[a] = folds_along(m, c, a, lfo.fold[a]);
+                    for (int k = 0; k < lfo.nfold[a]; ++k)
+                        for (int sd = 0; sd < 2; ++sd) {
+                            lfo.end_id[a][k][sd] = -1;
+                            const int fi = 2 * a + sd;
+                            for (int z = 0; z < lfo.nfp[fi]; ++z)
+                                if (std::fabs(lfo.fp[fi][z].u - lfo.fold[a][k].u) <= kFaceMerge &&
+                                    std::fabs(lfo.fp[fi][z].v - lfo.fold[a][k].v) <= kFaceMerge)
+                                    lfo.end_id[a][k][sd] = lfo.fp[fi][z].id;
+                        }
+                }
+            }
             out.tri.clear();
             out.inner.clear();
             out.loops = out.fallback = 0;
-            leaf_triangles(f, c, out);
+            leaf_triangles(f, c, lfo, out);
             loops[(size_t)t] += out.loops;
             fb[(size_t)t] += out.fallback;
             // interior points: placed from an edge point of the leaf (its
@@ -676,8 +1203,12 @@ bool triangulate(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
             }
             for (const auto &tr : out.tri) {
                 int32_t v[3];
-                for (int k = 0; k < 3; ++k)
-                    v[k] = tr[k] >= 12 ? inner_id[(size_t)(tr[k] - 12)] : (int32_t)id[tr[k]];
+                for (int k = 0; k < 3; ++k) {
+                    const int cd = tr[k];
+                    v[k] = cd < 12 ? (int32_t)id[cd]
+                           : cd < kCodeFace ? inner_id[(size_t)(cd - 12)]
+                                            : (int32_t)out.fpid[(size_t)(cd - kCodeFace)];
+                }
                 ptri[(size_t)t].insert(ptri[(size_t)t].end(), v, v + 3);
                 pleaf[(size_t)t].push_back((int32_t)i);
             }
@@ -700,7 +1231,6 @@ bool triangulate(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
         M->n_fallback += fb[(size_t)t];
         miss += missing[(size_t)t];
     }
-    em.resize(M->xyz.size() / 3, 0);
     return miss == 0;
 }
 
@@ -773,12 +1303,15 @@ void place_vertex(uint64_t key, double t, double px, double py, double pz, doubl
     }
 }
 
-// the mesh of host copies of the leaves, corner values and vertices; returns
-// a message (empty: success) and the mesh; em receives the ring bits
-std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
-                       const std::vector<tms_vertex> &V, const std::vector<tms_vertex> &X,
-                       VIndex &VI, double c, int K, double h0, tms_mesh **out,
-                       std::vector<uint8_t> &em) {
+// The mesh of host copies of the leaves, corner values and vertices, in two
+// steps around the closing of open faces: prepare_mesh checks the inputs,
+// places the points (the caller's, then X) and sets the ring bits of the
+// SURFACE leaves; finish_mesh adds the face points of every SURFACE leaf
+// and triangulates them all.  Each returns a message (empty: success).
+std::string prepare_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+                         const std::vector<tms_vertex> &V, const std::vector<tms_vertex> &X,
+                         VIndex &VI, double c, int K, double h0, tms_mesh **out,
+                         std::vector<uint8_t> &em) {
     *out = nullptr;
     const int64_t n = (int64_t)L.size(), nv = (int64_t)V.size();
     VI.V = &V;
@@ -823,15 +1356,28 @@ std::string build_mesh(const std::vector<tms_leaf> &L, const std::vector<double>
         place_vertex(v.edge_key, v.t, v.x, v.y, v.z, h0, &M->xyz[3 * ((size_t)nv + k)]);
         VI.add(v.edge_key, nv + (int64_t)k);
     }
-    const VidFn vid = [&](uint64_t key) { return VI.find(key); };
     em.assign((size_t)(nv + (int64_t)X.size()), 0);
-    if (!triangulate(L, cp, surf, c, K, h0, vid, M, em)) {
+    if (!ring_pass(L, cp, surf, c, K, [&](uint64_t key) { return VI.find(key); }, em)) {
         delete M;
         return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
     }
     M->open_faces = open_faces(em, nullptr, (int64_t)em.size(),
                                [&](int64_t v) { return VI.key_of(v); }, K, nullptr);
     *out = M;
+    return std::string();
+}
+
+std::string finish_mesh(const std::vector<tms_leaf> &L, const std::vector<double> &cp,
+                        const VIndex &VI, double c, int K, double h0, tms_mesh *M) {
+    std::vector<int64_t> surf;
+    for (int64_t i = 0; i < (int64_t)L.size(); ++i)
+        if (L[(size_t)i].cls == TMS_CLS_SURFACE) surf.push_back(i);
+    const VidFn vid = [&](uint64_t key) { return VI.find(key); };
+    std::vector<FaceRec> FR;
+    if (!face_points(L, cp, surf, c, K, h0, vid, M, FR) ||
+        !triangulate(L, cp, surf, c, K, h0, vid, FR, M))
+        return "a leaf's edge point is missing from the vertex list (vertices of other leaves?)";
+    M->n_face_points = (int64_t)FR.size();
     return std::string();
 }
 
@@ -1153,7 +1699,7 @@ std::string close_mesh(tms_ctx *ctx, const tms_cells *cells, int conf, std::vect
                 touched.push_back(id);
             }
         }
-        if (!triangulate(L, cp, idx, g.c, g.K, g.h0, vid, M, em)) {
+        if (!ring_pass(L, cp, idx, g.c, g.K, vid, em)) {
             *rc = TMS_E_INVALID;
             return "an edge point of a cube added across an open face is missing";
         }
@@ -1222,7 +1768,7 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
     }
     std::vector<uint8_t> em;
     VIndex VI;
-    const std::string why = build_mesh(L, cp, V, X, VI, g.c, g.K, g.h0, out, em);
+    const std::string why = prepare_mesh(L, cp, V, X, VI, g.c, g.K, g.h0, out, em);
     if (!why.empty()) return mfail(ctx, TMS_E_INVALID, why.c_str());
     if ((flags & TMS_MESH_CLOSE) && (*out)->open_faces > 0) {
         int32_t rc = TMS_OK;
@@ -1232,6 +1778,12 @@ int32_t tms_mesh_build(tms_ctx *ctx, const tms_cells *cells, const tms_leaf *lea
             *out = nullptr;
             return mfail(ctx, rc, w.c_str());
         }
+    }
+    const std::string w2 = finish_mesh(L, cp, VI, g.c, g.K, g.h0, *out);
+    if (!w2.empty()) {
+        delete *out;
+        *out = nullptr;
+        return mfail(ctx, TMS_E_INVALID, w2.c_str());
     }
     (*out)->added.assign(L.begin() + n, L.end());
     (*out)->added_phi.assign(cp.begin() + 8 * n, cp.end());
@@ -1252,7 +1804,14 @@ int32_t tms_mesh_build_host(const tms_leaf *leaves, int64_t n, const double *cor
     std::vector<tms_vertex> V(verts, verts + nv);
     std::vector<uint8_t> em;
     VIndex VI;
-    const std::string why = build_mesh(L, cp, V, std::vector<tms_vertex>(), VI, c, K, h0, out, em);
+    std::string why = prepare_mesh(L, cp, V, std::vector<tms_vertex>(), VI, c, K, h0, out, em);
+    if (why.empty()) {
+        why = finish_mesh(L, cp, VI, c, K, h0, *out);
+        if (!why.empty()) {
+            delete *out;
+            *out = nullptr;
+        }
+    }
     if (!why.empty()) {
         set_msg(msg, msg_len, why);
         return TMS_E_INVALID;

@@ -3,9 +3,15 @@ the manifold checks of Section 3.2) against the oracle, on the oracle's own
 partitions.  CPU only: the host entry point takes host arrays.
 
 * Face segments: in every SURFACE leaf the sides used once by the leaf's
-  triangles are the face segments of the leaf (as pairs of edge keys), and
-  they equal the oracle's segments, which pair ambiguous faces by brute-force
-  connectivity of {g >= c}.
+  triangles, from edge point through face points to edge point, are the
+  face segments of the leaf (as pairs of edge keys), and they equal the
+  oracle's segments, which pair ambiguous faces by brute-force connectivity
+  of {g >= c}.
+* Face points: the extreme points on the leaves' faces (eq. curve) are the
+  ends of the oracle's fold segments (eq. fold1), one point where both
+  leaves beside a face find it (a plane of symmetry of the torus).
+* Cuts along folds: every fold side is in two triangles of its leaf, and
+  no loop of the 200-atom globule is fanned.
 * Checks: the library's report equals the oracle checker's on the same mesh
   ((a), (b), (c), components, Euler characteristic, area, volume).
 * Closed forms: one atom gives a sphere of radius R, R^2 = r^2 - ln(c)/D
@@ -22,6 +28,7 @@ partitions.  CPU only: the host entry point takes host arrays.
 """
 import numpy as np
 import pytest
+from scipy.spatial import cKDTree
 
 import oracle
 from oracle import mesh as om
@@ -56,15 +63,34 @@ def glob200():
 def test_face_segments_equal_oracle(glob200):
     r, m = glob200
     nvk = r.n_vert
-    # sides used once within each leaf's triangles (interior points excluded)
+    # sides used once within each leaf's triangles form its boundary; face
+    # points (ids past the edge points) sit on it between edge points, so
+    # each chain from an edge point through face points to the next edge
+    # point is one face segment of the leaf
     got = {}
     for t, leaf in zip(m.tri, m.tri_leaf):
         for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
             k = (int(leaf), min(a, b), max(a, b))
             got[k] = got.get(k, 0) + 1
-    g_segs = {(lf, int(r.vkey[a]), int(r.vkey[b])) if r.vkey[a] < r.vkey[b]
-              else (lf, int(r.vkey[b]), int(r.vkey[a]))
-              for (lf, a, b), cnt in got.items() if cnt == 1 and a < nvk and b < nvk}
+    once = [k for k, cnt in got.items() if cnt == 1]
+    adj = {}
+    for lf, a, b in once:
+        adj.setdefault((lf, a), []).append(b)
+        adj.setdefault((lf, b), []).append(a)
+    g_segs = set()
+    n_face = 0
+    for lf, a, b in once:
+        for s0, s1 in ((a, b), (b, a)):
+            if s0 >= nvk:
+                continue
+            prev, cur = s0, s1
+            while cur >= nvk:
+                n_face += 1
+                nxt = [x for x in adj[(lf, cur)] if x != prev]
+                assert len(nxt) == 1
+                prev, cur = cur, nxt[0]
+            k1, k2 = int(r.vkey[s0]), int(r.vkey[cur])
+            g_segs.add((lf, min(k1, k2), max(k1, k2)))
     o_segs = set()
     for i in np.flatnonzero(r.cls == oracle.CLS_SURFACE):
         for s in om.leaf_face_segments(r.corner_phi[i], 1.0):
@@ -72,9 +98,67 @@ def test_face_segments_equal_oracle(glob200):
             k1 = om.edge_key(0, int(r.level[i]), r.K, r.ijk[i], e1)
             k2 = om.edge_key(0, int(r.level[i]), r.K, r.ijk[i], e2)
             o_segs.add((int(i), min(k1, k2), max(k1, k2)))
-    print("segments: library %d, oracle %d, fanned loops %d" % (len(g_segs), len(o_segs),
-                                                                m.info["n_fallback"]))
+    print("segments: library %d, oracle %d, fanned loops %d, face points on them %d"
+          % (len(g_segs), len(o_segs), m.info["n_fallback"], n_face))
     assert g_segs == o_segs
+
+
+def _torus():
+    # a ring of 16 atoms of radius 1.5 on a circle of radius 5
+    return np.array([[5 * np.cos(k * np.pi / 8), 5 * np.sin(k * np.pi / 8), 0.0, 1.5]
+                     for k in range(16)])
+
+
+@pytest.mark.parametrize("case", ["globule200", "torus"])
+def test_face_points_equal_oracle_fold_ends(case, glob200):
+    # the vertices after the edge points and before the fanned loops' interior
+    # points are the extreme points on the leaves' faces (eq. curve); each is
+    # an end of a fold (eq. fold1) of a leaf beside the face, which the
+    # oracle computes from its own bilinear face coefficients.  On the torus
+    # the plane z = 0 and the planes through the axis and an atom are planes
+    # of symmetry, so both leaves beside such a face find the same point:
+    # it is one vertex
+    r, m = glob200 if case == "globule200" else _mesh(_torus())
+    F = m.xyz[r.n_vert:len(m.xyz) - m.info["n_fallback"]]
+    s2 = oracle.stage2_of(r, 1.0)
+    assert s2.n_degenerate == 0 and s2.n_mismatch == 0
+    p = s2.pts[s2.pts["kind"] == oracle.S2_FOLD]
+    lo = np.stack([p["x"], p["y"], p["z"]], 1)
+    hi = lo.copy()
+    hi[np.arange(len(p)), p["axis"]] += r.h0 * 2.0 ** (-r.level[p["leaf"]].astype(np.float64))
+    O = np.concatenate([lo, hi])
+    keep = np.ones(len(O), dtype=bool)
+    for i, j in cKDTree(O).query_pairs(1e-9):
+        keep[max(i, j)] = False  # the later of two coincident points
+    O = O[keep]
+    print("%s: face points %d, oracle fold ends %d" % (case, len(F), len(O)))
+    assert len(F) == len(O) and len(F) > 0
+    assert cKDTree(O).query(F)[0].max() < 1e-9
+    assert cKDTree(F).query(O)[0].max() < 1e-9
+
+
+def test_patches_cut_along_folds(glob200):
+    # a fold (eq. fold1) joins two face points of a leaf along an axis, the
+    # length of the leaf edge; a patch cut along it has the fold as a side of
+    # one triangle of each piece, so every such side is in exactly two
+    # triangles of its leaf; and with the cuts no loop of this globule needs
+    # the fan from an interior point
+    r, m = glob200
+    nvk = r.n_vert
+    h = r.h0 / 2.0 ** r.K
+    sides = {}
+    for t, leaf in zip(m.tri, m.tri_leaf):
+        for a, b in ((t[0], t[1]), (t[1], t[2]), (t[2], t[0])):
+            if a < nvk or b < nvk:
+                continue
+            d = np.abs(m.xyz[a] - m.xyz[b])
+            if np.sum(d < 1e-12) == 2 and abs(d.max() - h) < 1e-12:
+                k = (int(leaf), min(a, b), max(a, b))
+                sides[k] = sides.get(k, 0) + 1
+    print("fold sides %d" % len(sides))
+    assert len(sides) > 100
+    assert all(v == 2 for v in sides.values())
+    assert m.info["n_fallback"] == 0
 
 
 def test_checks_equal_oracle(glob200):
