@@ -278,6 +278,12 @@ bool seg_meet(const double a[2], const double b[2], const double c[2], const dou
     return on(a, b, c, d1) || on(a, b, d, d2) || on(c, d, a, d3) || on(c, d, b, d4);
 }
 
+// Choices between candidates (ears, axes, the vertex spanning a fold) take
+// a later candidate only if it is better by more than this, so that inputs
+// equal up to rounding (a symmetric cube, corner values that differ in their
+// last bits) give the same triangles.
+constexpr double kTie = 1e-9;
+
 // sine of a triangle's smallest angle (the angle at the vertex opposite its
 // shortest side: twice the area over the two longer sides), 0 if degenerate
 double shape(const double *p, const double *q, const double *r) {
@@ -338,7 +344,7 @@ bool ear_clip(const double (*Q)[2], const double (*X)[3], int m, const unsigned 
             }
             if (inside) continue;
             const double q = shape(X[ia], X[ib], X[ic]);
-            if (q > bq) {
+            if (q > bq + kTie) {
                 bq = q;
                 best = i;
             }
@@ -531,7 +537,7 @@ bool clip_piece(const double (*P)[3], const unsigned *fm, const std::vector<int>
         for (int t = 0; t <= nf; ++t) {
             if (second[fu[t]] >= 0) continue;
             const double d = std::fabs(P[first[fu[t]]][a] - mid);
-            if (d < bd) {
+            if (d < bd - kTie) {
                 bd = d;
                 j = t;
             }
@@ -683,7 +689,9 @@ void leaf_triangles(const double f[8], double c, const LeafFolds &lfo, LeafOut &
             for (int a = 0; a < 3; ++a) ctr[a] += pp[a] / m;
         }
         int order[3] = {0, 1, 2};
-        std::sort(order, order + 3, [&](int x, int y) { return std::fabs(A[x]) > std::fabs(A[y]); });
+        for (int i = 1; i < 3; ++i)  // by |A| descending; near-equal keep axis order
+            for (int j = i; j > 0 && std::fabs(A[order[j]]) > std::fabs(A[order[j - 1]]) + kTie; --j)
+                std::swap(order[j], order[j - 1]);
         std::array<int, 3> tl[3 * kPolyMax];
         int ntl = 0;
         bool ok = false;

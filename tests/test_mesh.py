@@ -12,6 +12,9 @@ partitions.  CPU only: the host entry point takes host arrays.
   leaves beside a face find it (a plane of symmetry of the torus).
 * Cuts along folds: every fold side is in two triangles of its leaf, and
   no loop of the 200-atom globule is fanned.
+* The triangles of a sphere and of the torus do not change under relative
+  noise of 1e-15 on the corner values (ties between ears, axes and fold
+  vertices are not decided by rounding).
 * Checks: the library's report equals the oracle checker's on the same mesh
   ((a), (b), (c), components, Euler characteristic, area, volume).
 * Closed forms: one atom gives a sphere of radius R, R^2 = r^2 - ln(c)/D
@@ -159,6 +162,23 @@ def test_patches_cut_along_folds(glob200):
     assert len(sides) > 100
     assert all(v == 2 for v in sides.values())
     assert m.info["n_fallback"] == 0
+
+
+@pytest.mark.parametrize("case", ["sphere", "torus"])
+def test_triangles_stable_under_last_bit_noise(case):
+    # the device partition's corner values equal the oracle's up to their
+    # last bits; on symmetric surfaces ears, projection axes and the vertex
+    # spanning a fold tie exactly, so the choices among them must not follow
+    # rounding: the triangles stay the same under relative noise of 1e-15
+    atoms = (np.array([[-2.8735, -1.1366, 2.6300, 1.6307]]) if case == "sphere" else _torus())
+    r = oracle.partition(atoms, 0.9, c=1.0, tau=1e-3, h0=2.0, h_min=0.25)
+    L, V = _leaves(r), _verts(r)
+    m0 = tms.mesh_build_host(L, r.corner_phi, V, 1.0, r.K, 2.0)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        cp = r.corner_phi * (1 + 1e-15 * rng.uniform(-1, 1, r.corner_phi.shape))
+        m1 = tms.mesh_build_host(L, cp, V, 1.0, r.K, 2.0)
+        assert np.array_equal(m0.tri, m1.tri) and np.array_equal(m0.tri_leaf, m1.tri_leaf)
 
 
 def test_checks_equal_oracle(glob200):
