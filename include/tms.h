@@ -463,7 +463,9 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * loop's patch is cut along the leaf's fold segments along one axis whose
  * two ends are on the loop (Section 2.3: pieces single-valued along that
  * axis) and every piece is triangulated by ear clipping in the plane normal
- * to that axis, the axes tried in order of the loop's projected area; no
+ * to that axis (the ear with the largest smallest angle first; candidates
+ * within 1e-9 of each other keep their order, so rounding decides no
+ * choice), the axes tried in order of the loop's projected area; no
  * triangle side joins two points of one cube face other than the face's
  * curve segments.  A loop that no axis admits is fanned from a point of the
  * patch inside the cube (counted).  Triangles point along -grad g (outward,
