@@ -333,6 +333,8 @@ bool ear_clip(const double (*Q)[2], const double (*X)[3], int m, const unsigned 
             if (fm[ia] & fm[ic]) continue;
             const double cr = cross2(Q[ia], Q[ib], Q[ic]) * sg;
             if (!(cr > 0.0)) continue;
+            const double q = shape(X[ia], X[ib], X[ic]);
+            if (!(q > bq + kTie)) continue;  // cannot replace the best ear so far
             bool inside = false;
             for (int j = 0; j < k && !inside; ++j) {
                 const int ij = idx[j];
@@ -343,11 +345,8 @@ bool ear_clip(const double (*Q)[2], const double (*X)[3], int m, const unsigned 
                 if (c1 >= 0 && c2 >= 0 && c3 >= 0) inside = true;
             }
             if (inside) continue;
-            const double q = shape(X[ia], X[ib], X[ic]);
-            if (q > bq + kTie) {
-                bq = q;
-                best = i;
-            }
+            bq = q;
+            best = i;
         }
         if (best < 0) return false;
         out[(*nout)++] = {idx[(best + k - 1) % k], idx[best], idx[(best + 1) % k]};
@@ -462,10 +461,14 @@ constexpr int kCodeFace = 64;
 // the fold's second end, the rest on its first end, with the triangle
 // (first end, second end, u) spanning the fold.  Triangles keep the order of
 // the loop.  False if the projection is not a simple polygon.
-bool clip_piece(const double (*P)[3], const unsigned *fm, const std::vector<int> &pc,
+struct Piece {
+    int v[kPolyMax];
+    int n;
+};
+
+bool clip_piece(const double (*P)[3], const unsigned *fm, const int *pc, int pm,
                 const int (*chord)[2], int nch, int a, std::array<int, 3> *tl, int *ntl) {
     const int b = (a + 1) % 3, cc = (a + 2) % 3;
-    const int pm = (int)pc.size();
     auto is_chord = [&](int x, int y) {
         for (int k = 0; k < nch; ++k)
             if ((chord[k][0] == x && chord[k][1] == y) || (chord[k][0] == y && chord[k][1] == x))
@@ -474,13 +477,13 @@ bool clip_piece(const double (*P)[3], const unsigned *fm, const std::vector<int>
     };
     // rotate so that no fold pair wraps around the end of the list
     int r0 = 0;
-    if (pm > 1 && is_chord(pc[(size_t)(pm - 1)], pc[0])) r0 = pm - 1;
+    if (pm > 1 && is_chord(pc[pm - 1], pc[0])) r0 = pm - 1;
     int first[kPolyMax], second[kPolyMax], nk = 0;
     for (int t = 0; t < pm;) {
-        const int x = pc[(size_t)((r0 + t) % pm)];
-        if (t + 1 < pm && is_chord(x, pc[(size_t)((r0 + t + 1) % pm)])) {
+        const int x = pc[(r0 + t) % pm];
+        if (t + 1 < pm && is_chord(x, pc[(r0 + t + 1) % pm])) {
             first[nk] = x;
-            second[nk++] = pc[(size_t)((r0 + t + 1) % pm)];
+            second[nk++] = pc[(r0 + t + 1) % pm];
             t += 2;
         } else {
             first[nk] = x;
@@ -716,37 +719,42 @@ void leaf_triangles(const double f[8], double c, const LeafFolds &lfo, LeafOut &
                 }
             }
             // pieces as index lists; a chord splits the piece holding both ends
-            std::vector<std::vector<int>> pieces(1);
-            for (int i = 0; i < m; ++i) pieces[0].push_back(i);
+            // (at most two folds per axis: at most three pieces, each no longer
+            // than the loop)
+            Piece pieces[3];
+            int npc = 1;
+            pieces[0].n = m;
+            for (int i = 0; i < m; ++i) pieces[0].v[i] = i;
             bool split_ok = true;
             for (int k = 0; k < nch && split_ok; ++k) {
                 bool done = false;
-                for (size_t pi = 0; pi < pieces.size() && !done; ++pi) {
-                    std::vector<int> &pc = pieces[pi];
+                for (int pi = 0; pi < npc && !done; ++pi) {
+                    Piece &pc = pieces[pi];
                     int x0 = -1, x1 = -1;
-                    for (int i = 0; i < (int)pc.size(); ++i) {
-                        if (pc[(size_t)i] == chord[k][0]) x0 = i;
-                        if (pc[(size_t)i] == chord[k][1]) x1 = i;
+                    for (int i = 0; i < pc.n; ++i) {
+                        if (pc.v[i] == chord[k][0]) x0 = i;
+                        if (pc.v[i] == chord[k][1]) x1 = i;
                     }
                     if (x0 < 0 || x1 < 0) continue;
                     if (x1 < x0) std::swap(x0, x1);
-                    if (x1 - x0 < 2 || (x0 == 0 && x1 == (int)pc.size() - 1)) {
+                    if (x1 - x0 < 2 || (x0 == 0 && x1 == pc.n - 1)) {
                         split_ok = false;  // the ends are neighbours: nothing to split
                         break;
                     }
-                    std::vector<int> p1(pc.begin() + x0, pc.begin() + x1 + 1), p2;
-                    for (int i = x1; i != x0; i = (i + 1) % (int)pc.size()) p2.push_back(pc[(size_t)i]);
-                    p2.push_back(pc[(size_t)x0]);
-                    pc = p1;
-                    pieces.push_back(p2);
+                    Piece &p2 = pieces[npc++];
+                    p2.n = 0;
+                    for (int i = x1; i != x0; i = (i + 1) % pc.n) p2.v[p2.n++] = pc.v[i];
+                    p2.v[p2.n++] = pc.v[x0];
+                    for (int i = x0; i <= x1; ++i) pc.v[i - x0] = pc.v[i];
+                    pc.n = x1 - x0 + 1;
                     done = true;
                 }
             }
             if (!split_ok) continue;
             ntl = 0;
             ok = true;
-            for (const auto &pc : pieces) {
-                if (!clip_piece(P, fm, pc, chord, nch, a, tl, &ntl)) {
+            for (int pi = 0; pi < npc; ++pi) {
+                if (!clip_piece(P, fm, pieces[pi].v, pieces[pi].n, chord, nch, a, tl, &ntl)) {
                     ok = false;
                     break;
                 }
