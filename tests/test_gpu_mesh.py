@@ -18,11 +18,14 @@ without closing open faces, against the oracle.
 * SURFACE leaves of two levels (loose tolerances): the finest cubes that
   replace the coarser leaves, and the closing cubes after them, equal the
   oracle's; the mesh has no defect.
+* The mesh's extreme points on leaf faces are the ends of the fold segments
+  the GPU's Stage-2 kernel writes for the same partition.
 * Vertex density scales as 1 / h_min^2 (about 2.3 per square angstrom at
   h_min = 1, 1.5 of them edge points).
 """
 import numpy as np
 import pytest
+from scipy.spatial import cKDTree
 
 import oracle
 from oracle import mesh as om
@@ -129,6 +132,36 @@ def test_mesh_parity_fp64(ctx, name):
         R = atoms[0, 3]  # c = 1: phi = 1 on the sphere of radius r_i
         assert rep["euler"] == 2 and rep["components"] == 1
         assert abs(rep["area"] / (4 * np.pi * R * R) - 1) < 0.01
+
+
+def test_face_points_equal_gpu_stage2_fold_ends(ctx):
+    # two implementations of eq. curve on one device partition: the host
+    # mesher's extreme points on the leaves' faces, and the ends of the fold
+    # segments tms_stage2_points writes on the GPU (the stored lower end on
+    # the face axis = -1, the upper end one leaf edge along the axis)
+    atoms, D = CASES["globule200"]
+    cells = ctx.build_cells(atoms, tms.make_params(precision=tms.PREC_FP64, D=D))
+    try:
+        leaves, cphi, _ = ctx.partition_estimate(cells)
+        verts = ctx.extract(cells, leaves, cphi)
+        m = ctx.mesh_build(cells, leaves, cphi, verts, close=False)
+        recs, ndeg = ctx.stage2_points(cells, leaves, cphi)
+        R = tms.s2_to_numpy(recs)
+        L = tms.leaves_to_numpy(leaves)
+        nv, h0 = verts.shape[0], cells.params.h0
+    finally:
+        ctx.free_cells(cells)
+    assert ndeg == 0 and len(m.added) == 0
+    F = m.xyz[nv:len(m.xyz) - m.info["n_fallback"]]
+    f = R[R["kind"] == tms.S2_FOLD]
+    lo = np.stack([f["x"], f["y"], f["z"]], 1)
+    hi = lo.copy()
+    hi[np.arange(len(f)), f["axis"]] += h0 * 2.0 ** (-L["level"][f["leaf"]].astype(np.float64))
+    O = np.concatenate([lo, hi])
+    print("face points %d, GPU fold ends %d" % (len(F), len(O)))
+    assert len(F) == len(O) > 0
+    assert cKDTree(O).query(F)[0].max() < 1e-9
+    assert cKDTree(F).query(O)[0].max() < 1e-9
 
 
 def test_closed_mesh_globule5k_fp32g(ctx):
