@@ -907,7 +907,7 @@ constexpr double kKappa = 8.0;
 
 template <bool FAST>
 __global__ __launch_bounds__(kBS, 2) void k_bound(Grid g, int level, EstOut o) {
-    __shared__ double wsh[20 * kBS];
+    __shared__ double wsh[36 * kBS];
     const int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= (int64_t)*o.hardCount) return;
     double A[64];
@@ -1255,7 +1255,7 @@ __global__ void k_level_histo_final(const unsigned long long *__restrict__ part,
 __global__ __launch_bounds__(kBS) void k_bound_debug(const double *__restrict__ Ain,
                                                      const double *__restrict__ band, int64_t n,
                                                      double *__restrict__ out) {
-    __shared__ double wsh[20 * kBS];
+    __shared__ double wsh[36 * kBS];
     int64_t t = blockIdx.x * (int64_t)kBS + threadIdx.x;
     if (t >= n) return;
     double A[64];

@@ -329,9 +329,10 @@ __device__ __forceinline__ double sgap(const double s[4], int i) {
 // adding or dropping inner term k of outer term i moves L and U by at most
 // 16 sigma_i d_k, and an outer term i by at most 32 sigma_i.
 // BAND = false: exact tensors (band is 0 and the perturbation terms are not
-// formed).  The outer singular vectors and values are parked in LDS (ws:
-// this thread's 20 doubles at stride wstride) while the inner problems run,
-// which keeps the register footprint within two waves per SIMD.
+// formed).  The outer singular vectors and values, and each inner problem's
+// eigenvectors, are parked in LDS (ws: this thread's 36 doubles at stride
+// wstride) while the inner problems run, which keeps the register footprint
+// within two waves per SIMD.
 template <bool BAND = true>
 __device__ inline BoundResult nested_bound(double *A, double band, double *ws, int wstride) {
     BoundResult R;
@@ -388,6 +389,12 @@ __device__ inline BoundResult nested_bound(double *A, double band, double *ws, i
                 H[k2][k] = g;
             }
         eig4_sorted(H, mu, Z);
+        // Z goes to the workspace too: the residual loop below reads one
+        // column per rank, and holding all 16 would spill there
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) ws[(20 + 4 * a + b) * wstride] = Z[a][b];
         // v again, from A (unchanged so far) -- the same operations, hence the
         // same bits; the empty asm hides the equality from the optimiser so v
         // is not held in registers across the eigen-solve
@@ -423,7 +430,8 @@ __device__ inline BoundResult nested_bound(double *A, double band, double *ws, i
         leg3_range(u, ux0, ux1);
         double Myz = 0.0, myz = 0.0;
         for (int k = 0; k < ri; ++k) {
-            double w[4] = {Z[0][k], Z[1][k], Z[2][k], Z[3][k]};
+            double w[4] = {ws[(20 + k) * wstride], ws[(24 + k) * wstride], ws[(28 + k) * wstride],
+                           ws[(32 + k) * wstride]};
             double iz = 1.0 / d[k];
             double z[4];
 #pragma unroll
