@@ -512,8 +512,9 @@ int32_t tms_graph_launch(tms_ctx *ctx, const tms_cells *cells, tms_leaf *leaves,
  * tms_mesh_check: the three conditions of a manifold mesh (Section 3.2):
  *   (a) every edge shared by exactly two triangles (and traversed in opposite
  *   directions), (b) the neighbourhood of every vertex a single loop, (c) no
- *   intersecting pair of triangles that share no vertex (tested among the
- *   triangles of the same or touching leaves; skipped, reported -1, when
+ *   pair of closed triangles that share no vertex and meet (tested among the
+ *   triangles of the same or touching leaves, decided by exact orientation
+ *   signs after a quick test in doubles; skipped, reported -1, when
  *   intersections = 0).  Non-manifold vertices are those failing (a) or (b).
  *   Also connected components, Euler characteristic V - E + F, area, enclosed
  *   volume, vertices per unit area, and the uniformness of the triangles

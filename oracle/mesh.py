@@ -14,9 +14,9 @@ from the definitions:
   replace coarser SURFACE leaves;
 * a mesh checker: (a) every edge in exactly two triangles, traversed in
   opposite directions; (b) the triangles around every vertex form a single
-  loop; (c) no two triangles without a shared vertex intersect (brute force
-  over all pairs, segment-triangle tests); plus components, Euler
-  characteristic, area and enclosed volume.
+  loop; (c) no two closed triangles without a shared vertex meet (brute
+  force over all pairs, segment-triangle tests decided by exact orientation
+  signs); plus components, Euler characteristic, area and enclosed volume.
 """
 from __future__ import annotations
 
@@ -138,58 +138,129 @@ def loops_from_segments(segs):
 
 # ---- mesh checker ---------------------------------------------------------------
 
-def _seg_tri(p, q, A, B, C, eps=1e-12):
-    """Does the closed segment pq meet the closed triangle ABC (not coplanar)?"""
-    n = np.cross(B - A, C - A)
-    dp, dq = np.dot(n, p - A), np.dot(n, q - A)
-    scale = np.linalg.norm(n) * max(np.linalg.norm(q - p), 1e-300)
-    if dp * dq > 0 or (abs(dp) <= eps * scale and abs(dq) <= eps * scale):
-        return False
-    t = dp / (dp - dq)
-    x = p + t * (q - p)
-    # barycentric test
-    v0, v1, v2 = C - A, B - A, x - A
-    d00, d01, d11 = np.dot(v0, v0), np.dot(v0, v1), np.dot(v1, v1)
-    d20, d21 = np.dot(v2, v0), np.dot(v2, v1)
-    den = d00 * d11 - d01 * d01
-    if den == 0:
-        return False
-    u = (d11 * d20 - d01 * d21) / den
-    v = (d00 * d21 - d01 * d20) / den
-    return u >= -1e-12 and v >= -1e-12 and u + v <= 1 + 1e-12
+# ---- condition (c): exact intersection of closed triangles ---------------
+# Every decision is the sign of an orientation determinant.  The coordinates
+# are doubles, hence dyadic rationals, so integers give the exact sign; the
+# vectorised pass uses a sign computed in doubles only where it clears an
+# error bound (1e-14 of the sum of the magnitudes of the determinant's terms;
+# the rounding error of this evaluation is below 8e-16 of it, Shewchuk,
+# "Adaptive precision floating-point arithmetic and fast robust geometric
+# predicates", 1997) and leaves the other pairs to the exact test.
+
+def _exact_ints(*pts):
+    """The coordinates of the points as integers over one common denominator:
+    a double is n / 2^k exactly, so scaling every coordinate by the largest
+    2^k keeps every sign and ratio."""
+    rat = [float(x).as_integer_ratio() for pt in pts for x in pt]
+    den = max(d for _, d in rat)
+    v = [n * (den // d) for n, d in rat]
+    k = len(pts[0])
+    return [v[i * k:(i + 1) * k] for i in range(len(pts))]
 
 
-def _seg_tri_vec(p, q, A, B, C, eps=1e-12):
-    """_seg_tri over arrays of segments and triangles (rows)."""
-    n = np.cross(B - A, C - A)
-    dp = np.einsum("ij,ij->i", n, p - A)
-    dq = np.einsum("ij,ij->i", n, q - A)
-    scale = np.linalg.norm(n, axis=1) * np.maximum(np.linalg.norm(q - p, axis=1), 1e-300)
-    flat = (np.abs(dp) <= eps * scale) & (np.abs(dq) <= eps * scale)
-    ok = ~((dp * dq > 0) | flat)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        t = np.where(ok, dp / (dp - dq), 0.0)
-    x = p + t[:, None] * (q - p)
-    v0, v1, v2 = C - A, B - A, x - A
-    d00 = np.einsum("ij,ij->i", v0, v0)
-    d01 = np.einsum("ij,ij->i", v0, v1)
-    d11 = np.einsum("ij,ij->i", v1, v1)
-    d20 = np.einsum("ij,ij->i", v2, v0)
-    d21 = np.einsum("ij,ij->i", v2, v1)
-    den = d00 * d11 - d01 * d01
-    with np.errstate(divide="ignore", invalid="ignore"):
-        u = (d11 * d20 - d01 * d21) / den
-        v = (d00 * d21 - d01 * d20) / den
-    return ok & (den != 0) & (u >= -1e-12) & (v >= -1e-12) & (u + v <= 1 + 1e-12)
+def _orient3d_exact(a, b, c, d):
+    """Sign of det[a - d; b - d; c - d], exactly (integer arithmetic)."""
+    a, b, c, d = _exact_ints(a[:3], b[:3], c[:3], d[:3])
+    A = [a[i] - d[i] for i in range(3)]
+    B = [b[i] - d[i] for i in range(3)]
+    C = [c[i] - d[i] for i in range(3)]
+    det = (A[0] * (B[1] * C[2] - B[2] * C[1]) - A[1] * (B[0] * C[2] - B[2] * C[0])
+           + A[2] * (B[0] * C[1] - B[1] * C[0]))
+    return (det > 0) - (det < 0)
+
+
+def _orient2d_exact(a, b, c):
+    """Sign of det[a - c; b - c] in the plane, exactly."""
+    a, b, c = _exact_ints(a[:2], b[:2], c[:2])
+    det = (a[0] - c[0]) * (b[1] - c[1]) - (a[1] - c[1]) * (b[0] - c[0])
+    return (det > 0) - (det < 0)
+
+
+def _on_segment2(p, q, r):
+    """r on the closed segment pq, given that the three are collinear."""
+    return (min(p[0], q[0]) <= r[0] <= max(p[0], q[0])
+            and min(p[1], q[1]) <= r[1] <= max(p[1], q[1]))
+
+
+def _segments_meet2(p, q, r, s):
+    o1, o2 = _orient2d_exact(p, q, r), _orient2d_exact(p, q, s)
+    o3, o4 = _orient2d_exact(r, s, p), _orient2d_exact(r, s, q)
+    if o1 * o2 < 0 and o3 * o4 < 0:
+        return True
+    return ((o1 == 0 and _on_segment2(p, q, r)) or (o2 == 0 and _on_segment2(p, q, s))
+            or (o3 == 0 and _on_segment2(r, s, p)) or (o4 == 0 and _on_segment2(r, s, q)))
+
+
+def _in_triangle2(p, a, b, c):
+    s = (_orient2d_exact(a, b, p), _orient2d_exact(b, c, p), _orient2d_exact(c, a, p))
+    return all(x >= 0 for x in s) or all(x <= 0 for x in s)
+
+
+def segment_meets_triangle(p, q, a, b, c):
+    """Does the closed segment pq meet the closed triangle abc?  Exact."""
+    op, oq = _orient3d_exact(a, b, c, p), _orient3d_exact(a, b, c, q)
+    if op * oq > 0:
+        return False
+    if op == 0 and oq == 0:
+        # in the triangle's plane: project out the axis along which its
+        # normal is largest (orientations are kept)
+        n = np.cross(np.asarray(b, float) - a, np.asarray(c, float) - a)
+        keep = [i for i in range(3) if i != int(np.argmax(np.abs(n)))]
+        P, Q, A, B, C = ([float(x[i]) for i in keep] for x in (p, q, a, b, c))
+        return (_in_triangle2(P, A, B, C) or _in_triangle2(Q, A, B, C)
+                or _segments_meet2(P, Q, A, B) or _segments_meet2(P, Q, B, C)
+                or _segments_meet2(P, Q, C, A))
+    # pq crosses the plane (or ends on it): the crossing is in the triangle
+    # iff pq passes every directed edge on the same side
+    s = (_orient3d_exact(p, q, a, b), _orient3d_exact(p, q, b, c), _orient3d_exact(p, q, c, a))
+    return all(x >= 0 for x in s) or all(x <= 0 for x in s)
 
 
 def tris_intersect(T1, T2):
-    """Two triangles (3 x 3 arrays) sharing no vertex intersect iff a side of
-    one meets the other (for non-coplanar triangles)."""
+    """Do two closed triangles (3 x 3 arrays) meet?  They do iff an edge of
+    one meets the other.  Exact."""
     for a in range(3):
-        if _seg_tri(T1[a], T1[(a + 1) % 3], *T2) or _seg_tri(T2[a], T2[(a + 1) % 3], *T1):
+        if (segment_meets_triangle(T1[a], T1[(a + 1) % 3], *T2)
+                or segment_meets_triangle(T2[a], T2[(a + 1) % 3], *T1)):
             return True
     return False
+
+
+def _orient3d_vec(a, b, c, d):
+    """Signs of det[a - d; b - d; c - d] over rows, in doubles, and whether
+    each is certain (clears the error bound)."""
+    A, B, C = a - d, b - d, c - d
+    t0 = B[:, 1] * C[:, 2] - B[:, 2] * C[:, 1]
+    t1 = B[:, 2] * C[:, 0] - B[:, 0] * C[:, 2]
+    t2 = B[:, 0] * C[:, 1] - B[:, 1] * C[:, 0]
+    det = A[:, 0] * t0 + A[:, 1] * t1 + A[:, 2] * t2
+    mag = (np.abs(A[:, 0]) * (np.abs(B[:, 1] * C[:, 2]) + np.abs(B[:, 2] * C[:, 1]))
+           + np.abs(A[:, 1]) * (np.abs(B[:, 2] * C[:, 0]) + np.abs(B[:, 0] * C[:, 2]))
+           + np.abs(A[:, 2]) * (np.abs(B[:, 0] * C[:, 1]) + np.abs(B[:, 1] * C[:, 0])))
+    sure = np.abs(det) > 1e-14 * mag
+    # four points with one coordinate exactly equal lie in a lattice plane:
+    # the determinant is exactly zero (common for sides on a cube face)
+    flat = np.zeros(len(det), dtype=bool)
+    for k in range(3):
+        flat |= (a[:, k] == b[:, k]) & (b[:, k] == c[:, k]) & (c[:, k] == d[:, k])
+    return np.where(sure & ~flat, np.sign(det), 0).astype(np.int8), sure | flat
+
+
+def _seg_tri_vec(p, q, A, B, C):
+    """segment_meets_triangle over rows in doubles: (meets, certain).  Rows
+    where a sign needed is uncertain, or the segment lies in the plane, are
+    not certain."""
+    op, sp = _orient3d_vec(A, B, C, p)
+    oq, sq = _orient3d_vec(A, B, C, q)
+    apart = sp & sq & (op * oq > 0)
+    s1, u1 = _orient3d_vec(p, q, A, B)
+    s2, u2 = _orient3d_vec(p, q, B, C)
+    s3, u3 = _orient3d_vec(p, q, C, A)
+    inside = ((s1 >= 0) & (s2 >= 0) & (s3 >= 0)) | ((s1 <= 0) & (s2 <= 0) & (s3 <= 0))
+    # the segment in the triangle's plane is left to the exact test
+    crossing = sp & sq & ~apart & ~((op == 0) & (oq == 0))
+    certain = apart | (crossing & u1 & u2 & u3)
+    return crossing & u1 & u2 & u3 & inside, certain
 
 
 def check_mesh(xyz, tri, intersections=True, cell=None):
@@ -293,10 +364,21 @@ def check_mesh(xyz, tri, intersections=True, cell=None):
             for b in range(3):
                 share |= tri[I, a] == tri[J, b]
         I, J = I[~share], J[~share]
+        # closed triangles can meet only if their bounding boxes overlap (an
+        # exact comparison of doubles)
+        lo, hi = P.min(axis=1), P.max(axis=1)
+        box = np.all(lo[I] <= hi[J], axis=1) & np.all(lo[J] <= hi[I], axis=1)
+        I, J = I[box], J[box]
         hit = np.zeros(len(I), dtype=bool)
+        sure = np.ones(len(I), dtype=bool)
         for a in range(3):
-            hit |= _seg_tri_vec(P[I, a], P[I, (a + 1) % 3], P[J, 0], P[J, 1], P[J, 2])
-            hit |= _seg_tri_vec(P[J, a], P[J, (a + 1) % 3], P[I, 0], P[I, 1], P[I, 2])
+            for U, V in ((I, J), (J, I)):
+                h, c = _seg_tri_vec(P[U, a], P[U, (a + 1) % 3], P[V, 0], P[V, 1], P[V, 2])
+                hit |= h
+                sure &= c
+        # pairs no certain sign decided: exactly
+        for k in np.flatnonzero(~hit & ~sure):
+            hit[k] = tris_intersect(P[I[k]], P[J[k]])
         rep["intersecting_pairs"] = int(hit.sum())
     return rep
 

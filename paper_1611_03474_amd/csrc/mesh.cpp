@@ -871,69 +871,215 @@ void crs3(const double *a, const double *b, double *r) {
 }
 double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
-bool coplanar_tri_tri(const double *N, const double *V0, const double *V1, const double *V2,
-                      const double *U0, const double *U1, const double *U2) {
-    // project onto the plane where the normal is largest, then 2-D tests
-    const double A[3] = {std::fabs(N[0]), std::fabs(N[1]), std::fabs(N[2])};
-    int i0, i1;
-    if (A[0] > A[1]) {
-        if (A[0] > A[2]) { i0 = 1; i1 = 2; }
-        else { i0 = 0; i1 = 1; }
-    } else {
-        if (A[2] > A[1]) { i0 = 0; i1 = 1; }
-        else { i0 = 0; i1 = 2; }
-    }
-    const double *V[3] = {V0, V1, V2}, *U[3] = {U0, U1, U2};
-    double v[3][2], u[3][2];
-    for (int k = 0; k < 3; ++k) {
-        v[k][0] = V[k][i0]; v[k][1] = V[k][i1];
-        u[k][0] = U[k][i0]; u[k][1] = U[k][i1];
-    }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            if (seg_meet(v[i], v[(i + 1) % 3], u[j], u[(j + 1) % 3])) return true;
-    auto inside = [](const double p[2], double t[3][2]) {
-        const double c1 = cross2(t[0], t[1], p), c2 = cross2(t[1], t[2], p), c3 = cross2(t[2], t[0], p);
-        return (c1 >= 0 && c2 >= 0 && c3 >= 0) || (c1 <= 0 && c2 <= 0 && c3 <= 0);
-    };
-    return inside(v[0], u) || inside(u[0], v);
+// ---- exact orientation signs -------------------------------------------------
+// Knuth's two-sum and the two-product by FMA are error-free; an expansion, a
+// sum of nonoverlapping doubles kept smallest first (Shewchuk, "Adaptive
+// precision floating-point arithmetic and fast robust geometric predicates",
+// 1997), holds a sum or product of doubles exactly, and its sign is that of
+// its last component.  A determinant is evaluated in doubles first; when its
+// magnitude does not clear a generous bound on the rounding error (1e-14 of
+// the sum of the magnitudes of its terms; the error is below 2e-15 of it),
+// it is evaluated exactly.
+
+inline void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bv = s - a;
+    e = (a - (s - bv)) + (b - bv);
 }
 
-bool tri_tri(const double *V0, const double *V1, const double *V2, const double *U0,
-             const double *U1, const double *U2) {
+inline void two_prod(double a, double b, double &p, double &e) {
+    p = a * b;
+    e = std::fma(a, b, -p);
+}
+
+// h += b exactly (h nonoverlapping, smallest first, no zero components)
+void grow(std::vector<double> &h, double b) {
+    double q = b;
+    size_t k = 0;
+    for (size_t i = 0; i < h.size(); ++i) {
+        double sum, err;
+        two_sum(q, h[i], sum, err);
+        if (err != 0.0) h[k++] = err;
+        q = sum;
+    }
+    h.resize(k);
+    if (q != 0.0) h.push_back(q);
+}
+
+int expansion_sign(const std::vector<double> &h) {
+    return h.empty() ? 0 : (h.back() > 0.0 ? 1 : -1);
+}
+
+// h += sg x y z exactly (sg = +-1)
+void add_prod3(std::vector<double> &h, double x, double y, double z, double sg) {
+    if (x == 0.0 || y == 0.0 || z == 0.0) return;
+    double p, e, p1, e1;
+    two_prod(x, y, p, e);
+    two_prod(p, z, p1, e1);
+    grow(h, sg * p1);
+    grow(h, sg * e1);
+    if (e != 0.0) {
+        two_prod(e, z, p1, e1);
+        grow(h, sg * p1);
+        grow(h, sg * e1);
+    }
+}
+
+// sign of det[a - d; b - d; c - d] (positive when d lies below the plane of a,
+// b, c seen with a, b, c counter-clockwise), exactly
+int orient3d_exact(const double *a, const double *b, const double *c, const double *d) {
+    double A[3][2], B[3][2], C[3][2];  // the differences, each as two doubles
+    for (int i = 0; i < 3; ++i) {
+        two_sum(a[i], -d[i], A[i][0], A[i][1]);
+        two_sum(b[i], -d[i], B[i][0], B[i][1]);
+        two_sum(c[i], -d[i], C[i][0], C[i][1]);
+    }
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 2, 0}, {1, 0, 2}, {2, 0, 1}, {2, 1, 0}};
+    static const double sgn[6] = {1.0, -1.0, 1.0, -1.0, 1.0, -1.0};
+    std::vector<double> h;
+    h.reserve(64);
+    for (int t = 0; t < 6; ++t)
+        for (int u = 0; u < 2; ++u)
+            for (int v = 0; v < 2; ++v)
+                for (int w = 0; w < 2; ++w)
+                    add_prod3(h, A[perm[t][0]][u], B[perm[t][1]][v], C[perm[t][2]][w], sgn[t]);
+    return expansion_sign(h);
+}
+
+int orient3d(const double *a, const double *b, const double *c, const double *d) {
+    const double ax = a[0] - d[0], ay = a[1] - d[1], az = a[2] - d[2];
+    const double bx = b[0] - d[0], by = b[1] - d[1], bz = b[2] - d[2];
+    const double cx = c[0] - d[0], cy = c[1] - d[1], cz = c[2] - d[2];
+    const double det = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+    const double mag = std::fabs(ax) * (std::fabs(by * cz) + std::fabs(bz * cy)) +
+                       std::fabs(ay) * (std::fabs(bz * cx) + std::fabs(bx * cz)) +
+                       std::fabs(az) * (std::fabs(bx * cy) + std::fabs(by * cx));
+    if (det > 1e-14 * mag) return 1;
+    if (det < -1e-14 * mag) return -1;
+    return orient3d_exact(a, b, c, d);
+}
+
+// sign of det[a - c; b - c] in the plane, exactly
+int orient2d(const double *a, const double *b, const double *c) {
+    const double det = (a[0] - c[0]) * (b[1] - c[1]) - (a[1] - c[1]) * (b[0] - c[0]);
+    const double mag = std::fabs((a[0] - c[0]) * (b[1] - c[1])) + std::fabs((a[1] - c[1]) * (b[0] - c[0]));
+    if (det > 1e-14 * mag) return 1;
+    if (det < -1e-14 * mag) return -1;
+    double A[2][2], B[2][2];
+    for (int i = 0; i < 2; ++i) {
+        two_sum(a[i], -c[i], A[i][0], A[i][1]);
+        two_sum(b[i], -c[i], B[i][0], B[i][1]);
+    }
+    std::vector<double> h;
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+            add_prod3(h, A[0][u], B[1][v], 1.0, 1.0);
+            add_prod3(h, A[1][u], B[0][v], 1.0, -1.0);
+        }
+    return expansion_sign(h);
+}
+
+// ---- triangle pairs for condition (c) ----------------------------------------
+// Closed triangles and segments; every decision is an exact orientation sign.
+
+// r on the closed segment pq, given that the three are collinear
+bool on_segment2(const double *p, const double *q, const double *r) {
+    return std::min(p[0], q[0]) <= r[0] && r[0] <= std::max(p[0], q[0]) &&
+           std::min(p[1], q[1]) <= r[1] && r[1] <= std::max(p[1], q[1]);
+}
+
+bool segments_meet2(const double *p, const double *q, const double *r, const double *s) {
+    const int o1 = orient2d(p, q, r), o2 = orient2d(p, q, s), o3 = orient2d(r, s, p),
+              o4 = orient2d(r, s, q);
+    if (o1 * o2 < 0 && o3 * o4 < 0) return true;
+    return (o1 == 0 && on_segment2(p, q, r)) || (o2 == 0 && on_segment2(p, q, s)) ||
+           (o3 == 0 && on_segment2(r, s, p)) || (o4 == 0 && on_segment2(r, s, q));
+}
+
+bool in_triangle2(const double *p, const double *a, const double *b, const double *c) {
+    const int c1 = orient2d(a, b, p), c2 = orient2d(b, c, p), c3 = orient2d(c, a, p);
+    return (c1 >= 0 && c2 >= 0 && c3 >= 0) || (c1 <= 0 && c2 <= 0 && c3 <= 0);
+}
+
+// does the closed segment pq meet the closed triangle abc?
+bool segment_meets_triangle(const double *p, const double *q, const double *a, const double *b,
+                            const double *c) {
+    const int op = orient3d(a, b, c, p), oq = orient3d(a, b, c, q);
+    if (op * oq > 0) return false;
+    if (op == 0 && oq == 0) {
+        // in the triangle's plane: in the coordinate plane where its normal
+        // is largest (the projection keeps every orientation)
+        double E1[3], E2[3], N[3];
+        sub3(b, a, E1);
+        sub3(c, a, E2);
+        crs3(E1, E2, N);
+        const int drop = (std::fabs(N[0]) >= std::fabs(N[1]) && std::fabs(N[0]) >= std::fabs(N[2]))
+                             ? 0 : (std::fabs(N[1]) >= std::fabs(N[2]) ? 1 : 2);
+        const int i0 = drop == 0 ? 1 : 0, i1 = drop == 2 ? 1 : 2;
+        const double P[2] = {p[i0], p[i1]}, Q[2] = {q[i0], q[i1]}, A[2] = {a[i0], a[i1]},
+                     B[2] = {b[i0], b[i1]}, C[2] = {c[i0], c[i1]};
+        return in_triangle2(P, A, B, C) || in_triangle2(Q, A, B, C) ||
+               segments_meet2(P, Q, A, B) || segments_meet2(P, Q, B, C) ||
+               segments_meet2(P, Q, C, A);
+    }
+    // pq crosses the plane (or ends on it): the crossing is in the triangle
+    // iff pq passes every directed edge on the same side
+    const int s1 = orient3d(p, q, a, b), s2 = orient3d(p, q, b, c), s3 = orient3d(p, q, c, a);
+    return (s1 >= 0 && s2 >= 0 && s3 >= 0) || (s1 <= 0 && s2 <= 0 && s3 <= 0);
+}
+
+// two closed triangles meet iff an edge of one meets the other
+bool triangles_meet(const double *V0, const double *V1, const double *V2, const double *U0,
+                    const double *U1, const double *U2) {
+    const double *V[3] = {V0, V1, V2}, *U[3] = {U0, U1, U2};
+    for (int k = 0; k < 3; ++k)
+        if (segment_meets_triangle(V[k], V[(k + 1) % 3], U0, U1, U2) ||
+            segment_meets_triangle(U[k], U[(k + 1) % 3], V0, V1, V2))
+            return true;
+    return false;
+}
+
+// A quick test in doubles that can only err towards "meet" (distances to the
+// planes within 1e-9 of the coordinate scale count as on the plane, the
+// intervals on the line of the planes' intersection get the same slack, and
+// coplanar pairs pass); what it passes, triangles_meet decides.
+bool may_meet(const double *V0, const double *V1, const double *V2, const double *U0,
+              const double *U1, const double *U2) {
+    double scale = 1.0;
+    for (const double *P : {V0, V1, V2, U0, U1, U2})
+        for (int i = 0; i < 3; ++i) scale = std::max(scale, std::fabs(P[i]));
     double E1[3], E2[3], N1[3], N2[3];
     sub3(V1, V0, E1);
     sub3(V2, V0, E2);
     crs3(E1, E2, N1);
     const double d1 = -dot3(N1, V0);
     double du0 = dot3(N1, U0) + d1, du1 = dot3(N1, U1) + d1, du2 = dot3(N1, U2) + d1;
-    const double eps = 1e-14 * (dot3(N1, N1) > 0 ? std::sqrt(dot3(N1, N1)) : 1.0);
-    if (std::fabs(du0) < eps) du0 = 0;
-    if (std::fabs(du1) < eps) du1 = 0;
-    if (std::fabs(du2) < eps) du2 = 0;
+    const double eps = 1e-9 * scale * std::sqrt(dot3(N1, N1));
+    if (std::fabs(du0) <= eps) du0 = 0;
+    if (std::fabs(du1) <= eps) du1 = 0;
+    if (std::fabs(du2) <= eps) du2 = 0;
     if ((du0 > 0 && du1 > 0 && du2 > 0) || (du0 < 0 && du1 < 0 && du2 < 0)) return false;
     sub3(U1, U0, E1);
     sub3(U2, U0, E2);
     crs3(E1, E2, N2);
     const double d2 = -dot3(N2, U0);
     double dv0 = dot3(N2, V0) + d2, dv1 = dot3(N2, V1) + d2, dv2 = dot3(N2, V2) + d2;
-    const double eps2 = 1e-14 * (dot3(N2, N2) > 0 ? std::sqrt(dot3(N2, N2)) : 1.0);
-    if (std::fabs(dv0) < eps2) dv0 = 0;
-    if (std::fabs(dv1) < eps2) dv1 = 0;
-    if (std::fabs(dv2) < eps2) dv2 = 0;
+    const double eps2 = 1e-9 * scale * std::sqrt(dot3(N2, N2));
+    if (std::fabs(dv0) <= eps2) dv0 = 0;
+    if (std::fabs(dv1) <= eps2) dv1 = 0;
+    if (std::fabs(dv2) <= eps2) dv2 = 0;
     if ((dv0 > 0 && dv1 > 0 && dv2 > 0) || (dv0 < 0 && dv1 < 0 && dv2 < 0)) return false;
+    if ((du0 == 0 && du1 == 0 && du2 == 0) || (dv0 == 0 && dv1 == 0 && dv2 == 0)) return true;
     double D[3];
     crs3(N1, N2, D);
-    if ((du0 == 0 && du1 == 0 && du2 == 0) || (dv0 == 0 && dv1 == 0 && dv2 == 0))
-        return coplanar_tri_tri(N1, V0, V1, V2, U0, U1, U2);
-    // interval of each triangle on the line of intersection
+    int ax = 0;
+    if (std::fabs(D[1]) > std::fabs(D[ax])) ax = 1;
+    if (std::fabs(D[2]) > std::fabs(D[ax])) ax = 2;
+    // interval of a triangle on the line: the vertex alone on its side and
+    // the two crossings of its edges to the others
     auto interval = [&](const double *P0, const double *P1, const double *P2, double d0, double dd1,
                         double dd2, double &lo, double &hi) {
-        int ax = 0;
-        if (std::fabs(D[1]) > std::fabs(D[ax])) ax = 1;
-        if (std::fabs(D[2]) > std::fabs(D[ax])) ax = 2;
         const double p0 = P0[ax], p1 = P1[ax], p2 = P2[ax];
-        // the vertex alone on its side
         double a, b, c, da, db, dc;
         if (d0 * dd1 > 0) { a = p2; b = p0; c = p1; da = dd2; db = d0; dc = dd1; }
         else if (d0 * dd2 > 0) { a = p1; b = p0; c = p2; da = dd1; db = d0; dc = dd2; }
@@ -947,9 +1093,9 @@ bool tri_tri(const double *V0, const double *V1, const double *V2, const double 
     double a0, a1, b0, b1;
     interval(V0, V1, V2, dv0, dv1, dv2, a0, a1);
     interval(U0, U1, U2, du0, du1, du2, b0, b1);
-    return !(a1 < b0 || b1 < a0);
+    const double slack = 1e-9 * scale;
+    return !(a1 < b0 - slack || b1 < a0 - slack);
 }
-
 
 // ---- building the mesh ------------------------------------------------------
 // Vertex ids: the caller's edge points in key order (0 .. nv-1), then points
@@ -2092,9 +2238,11 @@ int32_t tms_mesh_check(const tms_mesh *m, int32_t intersections, tms_mesh_report
                                     for (int q = 0; q < 3; ++q)
                                         if (T[3 * s + p] == T[3 * t + q]) share = true;
                                 if (share) continue;
-                                if (tri_tri(X + 3 * T[3 * s], X + 3 * T[3 * s + 1],
-                                            X + 3 * T[3 * s + 2], X + 3 * T[3 * t],
-                                            X + 3 * T[3 * t + 1], X + 3 * T[3 * t + 2]))
+                                const double *V0 = X + 3 * T[3 * s], *V1 = X + 3 * T[3 * s + 1],
+                                             *V2 = X + 3 * T[3 * s + 2], *U0 = X + 3 * T[3 * t],
+                                             *U1 = X + 3 * T[3 * t + 1], *U2 = X + 3 * T[3 * t + 2];
+                                if (may_meet(V0, V1, V2, U0, U1, U2) &&
+                                    triangles_meet(V0, V1, V2, U0, U1, U2))
                                     ++local;
                             }
                     }

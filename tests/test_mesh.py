@@ -12,6 +12,9 @@ partitions.  CPU only: the host entry point takes host arrays.
   leaves beside a face find it (a plane of symmetry of the torus).
 * Cuts along folds: every fold side is in two triangles of its leaf, and
   no loop of the 200-atom globule is fanned.
+* A mirror-symmetric molecule on the lattice (phi = c at lattice corners,
+  slivers around them): no intersecting pair, by the library's exact test
+  and the oracle's.
 * The triangles of a sphere and of the torus do not change under relative
   noise of 1e-15 on the corner values (ties between ears, axes and fold
   vertices are not decided by rounding).
@@ -179,6 +182,27 @@ def test_triangles_stable_under_last_bit_noise(case):
         cp = r.corner_phi * (1 + 1e-15 * rng.uniform(-1, 1, r.corner_phi.shape))
         m1 = tms.mesh_build_host(L, cp, V, 1.0, r.K, 2.0)
         assert np.array_equal(m0.tri, m1.tri) and np.array_equal(m0.tri_leaf, m1.tri_leaf)
+
+
+def test_symmetric_molecule_no_false_intersections():
+    # lattice-aligned atoms of one radius, mirrored in x = 0: phi = c exactly
+    # at lattice corners, where three edge points sit within 1e-6 of a leaf
+    # edge of the corner and the triangles around it are slivers; condition
+    # (c) is decided by exact orientation signs, so near misses between them
+    # are not counted (library and oracle agree)
+    a = np.array([[-3.0, -1.5, 3.0], [-3.0, -1.25, -1.75], [-2.5, -1.5, -1.25],
+                  [-1.5, -1.0, -2.5], [-0.75, 2.5, 2.25], [-0.25, -0.25, 2.0],
+                  [0.0, -0.5, -2.25], [0.25, -0.25, 2.0], [0.75, 2.5, 2.25],
+                  [1.5, -1.0, -2.5], [2.5, -1.5, -1.25], [3.0, -1.5, 3.0],
+                  [3.0, -1.25, -1.75]])
+    atoms = np.concatenate([a, np.full((len(a), 1), 1.5)], 1)
+    _, m = _mesh(atoms, D=0.9, h_min=0.5)
+    got = m.check()
+    ref = om.check_mesh(m.xyz, m.tri, cell=0.5)
+    print(got)
+    assert got["intersecting_pairs"] == ref["intersecting_pairs"] == 0
+    assert got["boundary_edges"] == got["nonmanifold_vertices"] == got["open_faces"] == 0
+    assert got["nonmanifold_edges"] == got["misoriented_edges"] == 0
 
 
 def test_checks_equal_oracle(glob200):

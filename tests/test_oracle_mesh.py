@@ -12,6 +12,11 @@ closed forms and hand-built meshes.  CPU only.
   volumes), a tetrahedron with a face missing (three boundary edges), a
   flipped face (misoriented edges), two tetrahedra sharing one vertex (one
   vertex whose neighbourhood is two loops), two crossing triangles.
+* Condition (c) is decided exactly: a vertex on a face or an edge meets it,
+  one smallest double off the plane it does not (or crosses), coplanar
+  pairs overlap, touch or stay apart as built, and two slivers separated by
+  a lattice plane, which tolerance-based tests report as crossing, do not
+  meet.
 * Closing open faces: on a sampled field whose crossing cubes form one
   face-connected set, dropping most of them and closing gives back exactly
   the dropped cubes with their values.
@@ -132,6 +137,39 @@ def test_crossing_triangles():
     Z = X.copy()
     Z[3:, 2] += 5.0
     assert om.check_mesh(Z, np.array([[0, 1, 2], [3, 4, 5]]))["intersecting_pairs"] == 0
+
+
+def test_intersection_is_exact_at_contact():
+    # closed triangles: a vertex exactly on the other's face meets it; moved
+    # off the plane by the smallest double, the pair is apart on that side
+    # and crossing on the other
+    T = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], float)
+    for z, meets in ((0.0, True), (5e-324, False), (-5e-324, True)):
+        U = np.array([[0.25, 0.25, z], [0.25, 0.5, 1.0], [0.5, 0.25, 1.0]])
+        assert om.tris_intersect(T, U) == meets, z
+        assert om.tris_intersect(U, T) == meets, z
+    # a vertex exactly on an edge (x + y = 1 on the hypotenuse) meets it
+    U = np.array([[0.5, 0.5, 0.0], [0.5, 0.5, 1.0], [1.0, 1.0, 1.0]])
+    assert om.tris_intersect(T, U)
+    # coplanar: overlapping, touching at a vertex, and apart
+    assert om.tris_intersect(T, np.array([[0.2, 0.2, 0], [2, 0.2, 0], [0.2, 2, 0]]))
+    assert om.tris_intersect(T, np.array([[1, 0, 0], [2, 0, 0], [2, 1, 0]]))
+    assert not om.tris_intersect(T, np.array([[1 + 1e-15, 0, 0], [2, 0, 0], [2, 1, 0]]))
+
+
+def test_sliver_near_miss_is_not_an_intersection():
+    # two slivers around a lattice corner (4, -1, 4) where the surface passes
+    # through it: every vertex of the first has x > 4 and every vertex of the
+    # second x <= 4, so the plane x = 4 separates them; tolerance-based tests
+    # report this pair as crossing
+    T1 = np.array([[4.0000005, -1.0, 4.0], [4.149170512684766, -1.5, 4.0],
+                   [4.363400953262453, -1.0, 3.5]])
+    T2 = np.array([[3.5, -0.5, 4.000011358053928], [4.0, -1.0, 4.000000500000001],
+                   [4.0, -0.9999995, 4.0]])
+    assert T1[:, 0].min() > 4.0 >= T2[:, 0].max()
+    assert not om.tris_intersect(T1, T2)
+    X = np.concatenate([T1, T2])
+    assert om.check_mesh(X, np.array([[0, 1, 2], [3, 4, 5]]))["intersecting_pairs"] == 0
 
 
 def test_closure_restores_dropped_surface_cubes():
