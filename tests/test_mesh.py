@@ -12,6 +12,8 @@ partitions.  CPU only: the host entry point takes host arrays.
   leaves beside a face find it (a plane of symmetry of the torus).
 * Cuts along folds: every fold side is in two triangles of its leaf, and
   no loop of the 200-atom globule is fanned.
+* Vertices moved by the caller make triangles cross: the library counts
+  the same intersecting pairs as the oracle.
 * A mirror-symmetric molecule on the lattice (phi = c at lattice corners,
   slivers around them): no intersecting pair, by the library's exact test
   and the oracle's.
@@ -182,6 +184,24 @@ def test_triangles_stable_under_last_bit_noise(case):
         cp = r.corner_phi * (1 + 1e-15 * rng.uniform(-1, 1, r.corner_phi.shape))
         m1 = tms.mesh_build_host(L, cp, V, 1.0, r.K, 2.0)
         assert np.array_equal(m0.tri, m1.tri) and np.array_equal(m0.tri_leaf, m1.tri_leaf)
+
+
+def test_intersections_counted_like_the_oracle(glob200):
+    # the mesh takes the caller's vertex positions: 200 edge points moved by
+    # up to 0.15 A make triangles cross (within touching leaves, the pairs
+    # both checkers examine); the library's exact test counts the same pairs
+    # as the oracle's
+    r, _ = glob200
+    V = _verts(r)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(len(V), 200, replace=False)
+    for c in ("x", "y", "z"):
+        V[c][idx] += rng.uniform(-0.15, 0.15, len(idx))
+    m = tms.mesh_build_host(_leaves(r), r.corner_phi, V, 1.0, r.K, 2.0)
+    got = m.check()["intersecting_pairs"]
+    ref = om.check_mesh(m.xyz, m.tri, cell=1.0)["intersecting_pairs"]
+    print("intersecting pairs: library %d, oracle %d" % (got, ref))
+    assert got == ref > 10
 
 
 def test_symmetric_molecule_no_false_intersections():
